@@ -1,0 +1,142 @@
+"""ctypes wrappers around the oracle's C library (test infrastructure only).
+
+Every function takes and returns numpy float64 arrays.  The C sources cite the
+paper passages each step follows (Sec. 2.1 eq. BrV; Appendix eqs. EFB, curva,
+EFT; forward Euler).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    """Load liboracle.so, building it with gcc if it is missing."""
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build
+            build.build()
+        L = ctypes.CDLL(path)
+        L.oracle_bessel.argtypes = [ctypes.c_int64, _D, _D, _D, _D]
+        L.oracle_kernel.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int64, _D, _D, _D]
+        L.oracle_velocity.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double,
+                                      ctypes.c_double, _D, _D]
+        L.oracle_velocity_at.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int64, _I64, _D, _D]
+        L.oracle_energy.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D, ctypes.c_double,
+                                    ctypes.c_double, _D]
+        L.oracle_energy.restype = ctypes.c_double
+        L.oracle_forces.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D, ctypes.c_double,
+                                    ctypes.c_double, _D, _D, _D]
+        L.oracle_kappa0.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, _D]
+        L.oracle_forward.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _I32]
+        L.oracle_forward.restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _p(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def bessel(z):
+    """K0(z), K1(z) and q(z) = z K1(z) - 1 (integral representation, A&S 9.6.24;
+    ascending series A&S 9.6.11 for q at z <= 2)."""
+    z = _f64(z).ravel()
+    k0, k1, q = (np.empty_like(z) for _ in range(3))
+    lib().oracle_bessel(z.size, _p(z), _p(k0), _p(k1), _p(q))
+    return k0, k1, q
+
+
+def kernel(alpha, eps, t):
+    """H1(r), H2(r) of eq. (BrV) at squared distances t = r^2 (blob reading in
+    swim_oracle.c)."""
+    t = _f64(t)
+    shape = t.shape
+    t = t.ravel()
+    H1, H2 = np.empty_like(t), np.empty_like(t)
+    lib().oracle_kernel(float(alpha), float(eps), t.size, _p(t), _p(H1), _p(H2))
+    return H1.reshape(shape), H2.reshape(shape)
+
+
+def velocity(x, y, fx, fy, alpha, eps):
+    """Dense sum of eq. (BrV) over all points of one system: u_i = sum_j
+    [H1 F_j + H2 (F_j . x_ij) x_ij], x_ij = X_i - X_j, j ascending."""
+    x, y, fx, fy = map(_f64, (x, y, fx, fy))
+    ux, uy = np.empty_like(x), np.empty_like(x)
+    lib().oracle_velocity(x.size, _p(x), _p(y), _p(fx), _p(fy), float(alpha), float(eps),
+                          _p(ux), _p(uy))
+    return ux, uy
+
+
+def velocity_at(x, y, fx, fy, alpha, eps, idx):
+    """Same sum as velocity(), at the targets idx only."""
+    x, y, fx, fy = map(_f64, (x, y, fx, fy))
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    ux, uy = np.empty(idx.size), np.empty(idx.size)
+    lib().oracle_velocity_at(x.size, _p(x), _p(y), _p(fx), _p(fy), float(alpha), float(eps),
+                             idx.size, idx.ctypes.data_as(_I64), _p(ux), _p(uy))
+    return ux, uy
+
+
+def kappa0(N, b, k, omega, phase, t):
+    """Preferred curvature -k^2 b sin(k s - omega t + phase) at s_i = i/(N-1)."""
+    out = np.empty(N)
+    lib().oracle_kappa0(N, 1.0 / (N - 1), float(b), float(k), float(omega), float(phase),
+                        float(t), _p(out))
+    return out
+
+
+def energy(x, y, Sb, Ss, kap0):
+    """Discrete E_tens + E_bend of one filament (Appendix EFT, EFB, curva)."""
+    x, y, kap0 = map(_f64, (x, y, kap0))
+    N = x.size
+    return lib().oracle_energy(N, 1.0 / (N - 1), _p(x), _p(y), float(Sb), float(Ss), _p(kap0))
+
+
+def forces(x, y, Sb, Ss, kap0):
+    """F = -dE/dX of energy() (eq. Fenergy)."""
+    x, y, kap0 = map(_f64, (x, y, kap0))
+    N = x.size
+    fx, fy = np.empty(N), np.empty(N)
+    lib().oracle_forces(N, 1.0 / (N - 1), _p(x), _p(y), float(Sb), float(Ss), _p(kap0),
+                        _p(fx), _p(fy))
+    return fx, fy
+
+
+PARAM_FIELDS = ("alpha", "Sb", "Ss", "b", "omega", "k", "phase", "x0", "y0")
+
+
+def forward(params, N, steps, dt, obs_every, eps_over_ds=1.5):
+    """Forward-Euler run of one system.
+
+    params: array (n_swim, 9) with columns PARAM_FIELDS (alpha from row 0).
+    Returns dict(obs=(n_swim, steps//obs_every, 2), speed=(n_swim,),
+    x=(n_swim*N,), y=(n_swim*N,), status=int).
+    """
+    P = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64)
+    n_swim = P.shape[0]
+    n_obs = steps // obs_every if obs_every > 0 else 0
+    obs = np.full((n_swim, max(n_obs, 1), 2), np.nan)
+    speed = np.empty(n_swim)
+    xo, yo = np.empty(n_swim * N), np.empty(n_swim * N)
+    st = ctypes.c_int32(0)
+    lib().oracle_forward(n_swim, N, _p(P), float(eps_over_ds), int(steps), float(dt),
+                         int(obs_every), _p(obs), _p(speed), _p(xo), _p(yo), ctypes.byref(st))
+    return dict(obs=obs[:, :n_obs], speed=speed, x=xo, y=yo, status=int(st.value))

@@ -1,0 +1,469 @@
+/*
+ * swim_oracle.c -- plain, slow FP64 CPU oracle for the regularized-Brinkmanlet
+ * filament swimmer (Larson, Olson & Matzavinos, "Bayesian uncertainty
+ * quantification for micro-swimmers with fully resolved hydrodynamics").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  The product library
+ * (libswim) never links, loads or calls it, and shares no code with it.
+ *
+ * What it computes, step by step, in the paper's order:
+ *   - regularized Brinkmanlet velocity of point forces, eq. (BrV) of Sec. 2.1,
+ *     v(x) = sum_i [ -F_i B''(r) + (F_i . x_i)(x_i) (r B'' - B')/r^3 ],
+ *     with (Delta - alpha^2) B = G and Delta G = phi (Sec. 2.1).
+ *     The paper defers the closed forms of G and B to its references; the
+ *     reading used here (blob phi_K, see kernel_init) is written out below.
+ *   - forces F = -dE/dX of the discrete flagellum energy, eq. (Fenergy), with
+ *     the bending energy (EFB), the signed curvature (curva) and the
+ *     tensile energy (EFT) of the Appendix, second-order centred differences
+ *     and the trapezoid rule (Appendix, numerical algorithm paragraph).
+ *   - no-slip update dX/dt = v(X) by forward Euler (Sec. 2.1, Appendix).
+ *
+ * Floating point: positions, forces and sums are FP64.  The kernel functions
+ * are evaluated in x87 extended precision (long double, 64-bit mantissa) and
+ * rounded to double, so the cancellations inside the closed forms cost no
+ * FP64 digits.  Velocity sums use Neumaier compensated summation in index
+ * order j = 0, 1, ...
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef long double ld;
+
+static const ld PI_L = 3.14159265358979323846264338327950288L;
+static const ld EULER_GAMMA_L = 0.57721566490153286060651209008240243L;
+
+/* ------------------------------------------------------------------------ */
+/* Modified Bessel functions of the second kind, orders 0 and 1.            */
+/*                                                                          */
+/* Integral representation K_nu(z) = int_0^inf exp(-z cosh u) cosh(nu u) du */
+/* (Abramowitz & Stegun 9.6.24).  The integrand is even and analytic in the */
+/* strip |Im u| < pi/2, so the trapezoid rule with step h converges like    */
+/* exp(-pi^2/h); h = 0.2 gives ~e^-49 relative error, below long double     */
+/* rounding.  For large z the integrand is a Gaussian of width 1/sqrt(z)    */
+/* near u = 0, whose trapezoid error is ~exp(-2 pi^2/(z h^2)); h is capped  */
+/* at 0.6/sqrt(z) to keep that below e^-54.  The factor exp(-z) is pulled   */
+/* out.                                                                     */
+/* ------------------------------------------------------------------------ */
+static void bessel_k01_scaled(ld z, ld *k0e, ld *k1e)
+{
+    /* returns exp(z) K0(z), exp(z) K1(z) */
+    ld h = 0.2L;
+    if (z > 9.0L) h = 0.6L / sqrtl(z);
+    ld umax = acoshl(1.0L + 70.0L / z); /* exp(-z (cosh u - 1)) < e^-70 beyond */
+    int n = (int)(umax / h) + 2;
+    ld s0 = 0.5L, s1 = 0.5L;            /* u = 0 node carries weight 1/2      */
+    for (int k = 1; k <= n; ++k) {
+        ld u = h * (ld)k;
+        ld c = coshl(u);
+        ld e = expl(-z * (c - 1.0L));
+        s0 += e;
+        s1 += e * c;
+    }
+    *k0e = h * s0;
+    *k1e = h * s1;
+}
+
+static void bessel_k01(ld z, ld *k0, ld *k1)
+{
+    ld a, b;
+    bessel_k01_scaled(z, &a, &b);
+    ld ez = expl(-z);
+    *k0 = a * ez;
+    *k1 = b * ez;
+}
+
+/* q(z) = z K1(z) - 1.  For z <= 2 the ascending series of A&S 9.6.11 (n = 1):
+ *   z K1(z) = 1 + z ln(z/2) I1(z)
+ *               - (z^2/4) sum_k [psi(k+1) + psi(k+2)] (z^2/4)^k / (k! (k+1)!),
+ *   z I1(z) = (z^2/2) sum_k (z^2/4)^k / (k! (k+1)!),
+ * which never forms "1 - 1" for small z.  Above that, z K1(z) - 1 directly. */
+static ld q_of(ld z)
+{
+    if (z > 2.0L) {
+        ld k0, k1;
+        bessel_k01(z, &k0, &k1);
+        return z * k1 - 1.0L;
+    }
+    ld y = 0.25L * z * z;
+    ld lg = logl(0.5L * z);
+    ld term = 1.0L;                /* y^k / (k! (k+1)!) */
+    ld psi1 = -EULER_GAMMA_L;      /* psi(k+1) */
+    ld psi2 = 1.0L - EULER_GAMMA_L;/* psi(k+2) */
+    ld sI = 0.0L, sP = 0.0L;
+    for (int k = 0; k < 60; ++k) {
+        sI += term;
+        sP += (psi1 + psi2) * term;
+        term *= y / ((ld)(k + 1) * (ld)(k + 2));
+        psi1 += 1.0L / (ld)(k + 1);
+        psi2 += 1.0L / (ld)(k + 2);
+        if (term < 1e-30L * sI) break;
+    }
+    return 2.0L * y * lg * sI - y * sP;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kernel of eq. (BrV): v = sum_j [ H1(r) F_j + H2(r) (F_j . x) x ],       */
+/* H1 = -B'',  H2 = (r B'' - B')/r^3,  x = x_i - X_j, r = |x|.              */
+/*                                                                          */
+/* Reading of the blob (the paper defers G and B to its references):        */
+/*   g(r) = -c K0(alpha R) / (2 pi),  R = sqrt(r^2 + eps^2),               */
+/*   c = 1 / (alpha eps K1(alpha eps)),                                     */
+/* solves (Delta - alpha^2) g = phi with the positive, unit-mass blob       */
+/*   phi = c eps^2/(2 pi) [alpha^2 K0(alpha R)/R^2 + 2 alpha K1(alpha R)/R^3]*/
+/* which tends to eps^2/(pi R^4) as alpha -> 0.  With B = (g - G)/alpha^2   */
+/* one has Delta B = g, so B' = M/r with M(r) = int_0^r s g(s) ds and       */
+/* B'' = g - M/r^2:                                                         */
+/*   M  = c [q(alpha R) - q(alpha eps)] / (2 pi alpha^2)                   */
+/*   H1 = M/r^2 - g,   H2 = (g - 2 M/r^2)/r^2.                              */
+/* At alpha = 0 (Stokes limit, same blob), with delta = r^2/eps^2:         */
+/*   H1 = (1/4pi)[-ln R + log1p(delta)/(2 delta) - 1/2],                    */
+/*   H2 = (1/2pi)[1/(2 r^2) - log1p(delta)/(2 r^2 delta)].                  */
+/* Near contact (delta < 0.25) both use the Taylor series of g in delta,    */
+/* g = sum_n gam_n delta^n, for which                                       */
+/*   H1 = -sum_{n>=0} gam_n delta^n (2n+1)/(2(n+1)),                        */
+/*   H2 = (1/eps^2) sum_{n>=1} gam_n delta^(n-1) n/(n+1).                   */
+/* Brinkman: gam_n = -(c/2pi)(-1)^n kap_n, kap_n = (z0/2)^n K_n(z0)/n!,     */
+/* z0 = alpha eps, from the recurrence K_{n+1} = K_{n-1} + (2n/z) K_n.      */
+/* Stokes:   gam_0 = ln(eps^2)/(4pi), gam_n = (-1)^(n+1)/(4 pi n).          */
+/* ------------------------------------------------------------------------ */
+#define NGAM 32
+#define DELTA_TAYLOR 0.25L
+
+typedef struct {
+    ld alpha, eps, e2;
+    int stokes;
+    ld c, q0;
+    ld gam[NGAM];
+} okern;
+
+static void kernel_init(okern *k, double alpha, double eps)
+{
+    memset(k, 0, sizeof(*k));
+    k->alpha = alpha;
+    k->eps = eps;
+    k->e2 = (ld)eps * (ld)eps;
+    k->stokes = (alpha == 0.0);
+    if (k->stokes) {
+        k->c = 1.0L;
+        k->gam[0] = logl(k->e2) / (4.0L * PI_L);
+        for (int n = 1; n < NGAM; ++n)
+            k->gam[n] = ((n % 2) ? 1.0L : -1.0L) / (4.0L * PI_L * (ld)n);
+        return;
+    }
+    ld z0 = (ld)alpha * (ld)eps;
+    ld K0, K1;
+    bessel_k01(z0, &K0, &K1);
+    k->c = 1.0L / (z0 * K1);
+    k->q0 = q_of(z0);
+    ld kap[NGAM];
+    kap[0] = K0;
+    kap[1] = 0.5L * z0 * K1;
+    for (int n = 1; n + 1 < NGAM; ++n)
+        kap[n + 1] = 0.25L * z0 * z0 * kap[n - 1] / ((ld)n * (ld)(n + 1))
+                   + (ld)n * kap[n] / (ld)(n + 1);
+    for (int n = 0; n < NGAM; ++n)
+        k->gam[n] = -(k->c / (2.0L * PI_L)) * ((n % 2) ? -1.0L : 1.0L) * kap[n];
+}
+
+static void kernel_eval(const okern *k, double t_d, ld *H1, ld *H2)
+{
+    ld t = t_d;
+    ld delta = t / k->e2;
+    if (delta < DELTA_TAYLOR) {
+        ld p = 1.0L, h1 = 0.0L, h2 = 0.0L;
+        for (int n = 0; n < NGAM; ++n) {
+            h1 -= k->gam[n] * p * (ld)(2 * n + 1) / (ld)(2 * (n + 1));
+            if (n + 1 < NGAM)
+                h2 += k->gam[n + 1] * p * (ld)(n + 1) / (ld)(n + 2);
+            p *= delta;
+        }
+        *H1 = h1;
+        *H2 = h2 / k->e2;
+        return;
+    }
+    if (k->stokes) {
+        ld R2 = t + k->e2;
+        ld L1 = log1pl(delta);
+        *H1 = (1.0L / (4.0L * PI_L)) * (-0.5L * logl(R2) + L1 / (2.0L * delta) - 0.5L);
+        *H2 = (1.0L / (2.0L * PI_L)) * (1.0L / (2.0L * t) - L1 / (2.0L * t * delta));
+        return;
+    }
+    ld R = sqrtl(t + k->e2);
+    ld z = k->alpha * R;
+    ld K0, K1;
+    bessel_k01(z, &K0, &K1);
+    ld qz = (z > 2.0L) ? z * K1 - 1.0L : q_of(z);
+    ld g = -k->c * K0 / (2.0L * PI_L);
+    ld M = k->c * (qz - k->q0) / (2.0L * PI_L * k->alpha * k->alpha);
+    *H1 = M / t - g;
+    *H2 = (g - 2.0L * M / t) / t;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported: kernel and special-function values (for the pins).             */
+/* ------------------------------------------------------------------------ */
+void oracle_bessel(int64_t n, const double *z, double *k0, double *k1, double *q)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        ld a, b;
+        bessel_k01((ld)z[i], &a, &b);
+        k0[i] = (double)a;
+        k1[i] = (double)b;
+        q[i] = (double)q_of((ld)z[i]);
+    }
+}
+
+void oracle_kernel(double alpha, double eps, int64_t n, const double *t, double *H1, double *H2)
+{
+    okern k;
+    kernel_init(&k, alpha, eps);
+    for (int64_t i = 0; i < n; ++i) {
+        ld a, b;
+        kernel_eval(&k, t[i], &a, &b);
+        H1[i] = (double)a;
+        H2[i] = (double)b;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense velocity sum, eq. (BrV), over all n points of one system.          */
+/* ------------------------------------------------------------------------ */
+static void velocity_sum(const okern *k, int64_t n, const double *x, const double *y,
+                         const double *fx, const double *fy, double *ux, double *uy)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i) {
+        double sx = 0.0, cx = 0.0, sy = 0.0, cy = 0.0; /* Neumaier sums */
+        for (int64_t j = 0; j < n; ++j) {
+            double dx = x[i] - x[j], dy = y[i] - y[j];
+            double t = dx * dx + dy * dy;
+            ld H1, H2;
+            kernel_eval(k, t, &H1, &H2);
+            double h1 = (double)H1, h2 = (double)H2;
+            double fd = fx[j] * dx + fy[j] * dy;
+            double vx = h1 * fx[j] + h2 * fd * dx;
+            double vy = h1 * fy[j] + h2 * fd * dy;
+            double s;
+            s = sx + vx;
+            cx += (fabs(sx) >= fabs(vx)) ? (sx - s) + vx : (vx - s) + sx;
+            sx = s;
+            s = sy + vy;
+            cy += (fabs(sy) >= fabs(vy)) ? (sy - s) + vy : (vy - s) + sy;
+            sy = s;
+        }
+        ux[i] = sx + cx;
+        uy[i] = sy + cy;
+    }
+}
+
+void oracle_velocity(int64_t n, const double *x, const double *y, const double *fx,
+                     const double *fy, double alpha, double eps, double *ux, double *uy)
+{
+    okern k;
+    kernel_init(&k, alpha, eps);
+    velocity_sum(&k, n, x, y, fx, fy, ux, uy);
+}
+
+/* Velocity at a subset of targets only (targets idx[0..m-1]), for sampled
+ * checks of systems too large to sum in full. */
+void oracle_velocity_at(int64_t n, const double *x, const double *y, const double *fx,
+                        const double *fy, double alpha, double eps, int64_t m,
+                        const int64_t *idx, double *ux, double *uy)
+{
+    okern k;
+    kernel_init(&k, alpha, eps);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t a = 0; a < m; ++a) {
+        int64_t i = idx[a];
+        double sx = 0.0, cx = 0.0, sy = 0.0, cy = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double dx = x[i] - x[j], dy = y[i] - y[j];
+            double t = dx * dx + dy * dy;
+            ld H1, H2;
+            kernel_eval(&k, t, &H1, &H2);
+            double h1 = (double)H1, h2 = (double)H2;
+            double fd = fx[j] * dx + fy[j] * dy;
+            double vx = h1 * fx[j] + h2 * fd * dx;
+            double vy = h1 * fy[j] + h2 * fd * dy;
+            double s;
+            s = sx + vx;
+            cx += (fabs(sx) >= fabs(vx)) ? (sx - s) + vx : (vx - s) + sx;
+            sx = s;
+            s = sy + vy;
+            cy += (fabs(sy) >= fabs(vy)) ? (sy - s) + vy : (vy - s) + sy;
+            sy = s;
+        }
+        ux[a] = sx + cx;
+        uy[a] = sy + cy;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Flagellum energy and forces, Appendix eqs. (EFB), (curva), (EFT).        */
+/*   E_tens = S_s sum_{k=0}^{N-2} (l_k/ds - 1)^2 ds,  l_k = |X_{k+1}-X_k|   */
+/*   (Hookean springs between neighbouring points; the derivative inside    */
+/*    the norm is the first one, the printed second derivative is read as   */
+/*    a typo since the text calls the discrete form springs).               */
+/*   E_bend = S_b sum_{k=1}^{N-2} (kappa_k - kappa0_k)^2 ds                 */
+/*   kappa = (y'' x' - x'' y') / (x'^2 + y'^2)^(3/2), centred differences.  */
+/*   Only interior nodes carry curvature (end nodes contribute nothing).    */
+/*   F = -dE/dX (eq. Fenergy), the exact gradient of the discrete energy.   */
+/* ------------------------------------------------------------------------ */
+double oracle_energy(int N, double ds, const double *x, const double *y, double Sb,
+                     double Ss, const double *kappa0)
+{
+    double E = 0.0;
+    for (int k = 0; k + 1 < N; ++k) {
+        double dx = x[k + 1] - x[k], dy = y[k + 1] - y[k];
+        double l = sqrt(dx * dx + dy * dy);
+        double e = l / ds - 1.0;
+        E += Ss * e * e * ds;
+    }
+    for (int k = 1; k + 1 < N; ++k) {
+        double xp = (x[k + 1] - x[k - 1]) / (2.0 * ds);
+        double yp = (y[k + 1] - y[k - 1]) / (2.0 * ds);
+        double xpp = (x[k + 1] - 2.0 * x[k] + x[k - 1]) / (ds * ds);
+        double ypp = (y[k + 1] - 2.0 * y[k] + y[k - 1]) / (ds * ds);
+        double S = xp * xp + yp * yp;
+        double kap = (ypp * xp - xpp * yp) / pow(S, 1.5);
+        double d = kap - kappa0[k];
+        E += Sb * d * d * ds;
+    }
+    return E;
+}
+
+void oracle_forces(int N, double ds, const double *x, const double *y, double Sb, double Ss,
+                   const double *kappa0, double *fx, double *fy)
+{
+    for (int k = 0; k < N; ++k) {
+        fx[k] = 0.0;
+        fy[k] = 0.0;
+    }
+    /* stretching: dE/dX_{k+1} = 2 S_s (l/ds - 1) d/l from segment k */
+    for (int k = 0; k + 1 < N; ++k) {
+        double dx = x[k + 1] - x[k], dy = y[k + 1] - y[k];
+        double l = sqrt(dx * dx + dy * dy);
+        double e = l / ds - 1.0;
+        double gx = 2.0 * Ss * e * dx / l;
+        double gy = 2.0 * Ss * e * dy / l;
+        fx[k + 1] -= gx;
+        fy[k + 1] -= gy;
+        fx[k] += gx;
+        fy[k] += gy;
+    }
+    /* bending: chain rule through kappa_k(X_{k-1}, X_k, X_{k+1}) */
+    for (int k = 1; k + 1 < N; ++k) {
+        double a = (x[k + 1] - x[k - 1]) / (2.0 * ds);        /* x'  */
+        double b = (y[k + 1] - y[k - 1]) / (2.0 * ds);        /* y'  */
+        double p = (x[k + 1] - 2.0 * x[k] + x[k - 1]) / (ds * ds); /* x'' */
+        double q = (y[k + 1] - 2.0 * y[k] + y[k - 1]) / (ds * ds); /* y'' */
+        double S = a * a + b * b;
+        double S32 = pow(S, 1.5);
+        double num = q * a - p * b;
+        double kap = num / S32;
+        double co = 2.0 * Sb * (kap - kappa0[k]) * ds;       /* dE/dkappa_k */
+        double dk_da = q / S32 - 3.0 * a * num / (S32 * S);
+        double dk_db = -p / S32 - 3.0 * b * num / (S32 * S);
+        double dk_dp = -b / S32;
+        double dk_dq = a / S32;
+        /* da/dx_{k-1} = -1/(2ds), da/dx_{k+1} = 1/(2ds);
+           dp/dx_{k-1} = dp/dx_{k+1} = 1/ds^2, dp/dx_k = -2/ds^2 (same for y) */
+        double i2 = 1.0 / (2.0 * ds), i1 = 1.0 / (ds * ds);
+        fx[k - 1] -= co * (-dk_da * i2 + dk_dp * i1);
+        fy[k - 1] -= co * (-dk_db * i2 + dk_dq * i1);
+        fx[k] -= co * (-2.0 * dk_dp * i1);
+        fy[k] -= co * (-2.0 * dk_dq * i1);
+        fx[k + 1] -= co * (dk_da * i2 + dk_dp * i1);
+        fy[k + 1] -= co * (dk_db * i2 + dk_dq * i1);
+    }
+}
+
+/* preferred curvature kappa0(s, t) = -k^2 b sin(k s - omega t + phase), the
+ * untapered case of the Appendix beat with zeta_hat = d^2 y_hat / ds^2. */
+static void preferred_curvature(int N, double ds, double b, double kw, double omega,
+                                double phase, double t, double *kappa0)
+{
+    for (int k = 0; k < N; ++k)
+        kappa0[k] = -kw * kw * b * sin(kw * (double)k * ds - omega * t + phase);
+}
+
+void oracle_kappa0(int N, double ds, double b, double kw, double omega, double phase,
+                   double t, double *kappa0)
+{
+    preferred_curvature(N, ds, b, kw, omega, phase, t, kappa0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward model: one system of n_swim filaments of N points each.          */
+/* params: n_swim rows of 9 doubles (alpha, Sb, Ss, b, omega, k, phase,     */
+/* x0, y0); alpha is taken from row 0 (one fluid per system).               */
+/* Filament m starts straight along x: X_k = (x0 + k ds, y0), ds = 1/(N-1), */
+/* eps = eps_over_ds * ds.  Each step n (t = n dt): kappa0, forces of each  */
+/* filament, velocity sum over all n_swim*N points, Euler update; after the */
+/* update, if (n+1) % obs_every == 0, store the head X_{N-1} of every       */
+/* filament.  Status 1 = non-finite, 2 = |X| > 1e3 (run stops there).       */
+/* speed[m] = |X_h(T) - X_h(0)| / T.                                        */
+/* ------------------------------------------------------------------------ */
+int oracle_forward(int n_swim, int N, const double *params, double eps_over_ds, int steps,
+                   double dt, int obs_every, double *obs, double *speed, double *xout,
+                   double *yout, int *status)
+{
+    int64_t n = (int64_t)n_swim * N;
+    double ds = 1.0 / (double)(N - 1);
+    double eps = eps_over_ds * ds;
+    double *x = malloc(sizeof(double) * n), *y = malloc(sizeof(double) * n);
+    double *fx = malloc(sizeof(double) * n), *fy = malloc(sizeof(double) * n);
+    double *ux = malloc(sizeof(double) * n), *uy = malloc(sizeof(double) * n);
+    double *k0 = malloc(sizeof(double) * N);
+    double *h0 = malloc(sizeof(double) * 2 * n_swim);
+    okern k;
+    kernel_init(&k, params[0], eps);
+    for (int m = 0; m < n_swim; ++m) {
+        const double *P = params + 9 * m;
+        for (int i = 0; i < N; ++i) {
+            x[m * N + i] = P[7] + (double)i * ds;
+            y[m * N + i] = P[8];
+        }
+        h0[2 * m] = x[m * N + N - 1];
+        h0[2 * m + 1] = y[m * N + N - 1];
+    }
+    int st = 0;
+    int n_obs = obs_every > 0 ? steps / obs_every : 0;
+    for (int s = 0; s < steps && st == 0; ++s) {
+        double t = (double)s * dt;
+        for (int m = 0; m < n_swim; ++m) {
+            const double *P = params + 9 * m;
+            preferred_curvature(N, ds, P[3], P[5], P[4], P[6], t, k0);
+            oracle_forces(N, ds, x + m * N, y + m * N, P[1], P[2], k0, fx + m * N, fy + m * N);
+        }
+        velocity_sum(&k, n, x, y, fx, fy, ux, uy);
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] += dt * ux[i];
+            y[i] += dt * uy[i];
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            if (!isfinite(x[i]) || !isfinite(y[i])) { st = 1; break; }
+            if (fabs(x[i]) > 1e3 || fabs(y[i]) > 1e3) { st = 2; break; }
+        }
+        if (st == 0 && obs_every > 0 && (s + 1) % obs_every == 0) {
+            int o = (s + 1) / obs_every - 1;
+            for (int m = 0; m < n_swim; ++m) {
+                obs[((int64_t)m * n_obs + o) * 2] = x[m * N + N - 1];
+                obs[((int64_t)m * n_obs + o) * 2 + 1] = y[m * N + N - 1];
+            }
+        }
+    }
+    double T = (double)steps * dt;
+    for (int m = 0; m < n_swim; ++m) {
+        double dx = x[m * N + N - 1] - h0[2 * m], dy = y[m * N + N - 1] - h0[2 * m + 1];
+        speed[m] = st ? NAN : sqrt(dx * dx + dy * dy) / T;
+    }
+    if (xout) memcpy(xout, x, sizeof(double) * n);
+    if (yout) memcpy(yout, y, sizeof(double) * n);
+    *status = st;
+    free(x); free(y); free(fx); free(fy); free(ux); free(uy); free(k0); free(h0);
+    return 0;
+}

@@ -1,0 +1,121 @@
+"""Seeded synthetic inputs for the workloads (numpy PCG64).
+
+This module holds none of the method's arithmetic: it only draws parameter
+sets, filament sizes, phases and test geometries.  Random numbers that the
+ABC method itself draws (prior draws, PMC resampling and perturbation) are
+not made here; they come from the Philox4x32-10 generator that the library
+and the test oracle each implement.
+
+Workloads (the forward model runs on a filament of length 1 with N points,
+ds = 1/(N-1), blob width eps = 1.5 ds, initially straight along x):
+  single   N=64, FP64, alpha in {1, 0}, S_b=0.1, S_s=1e3, b=0.1, k=omega=2 pi,
+           dt=1e-4, 2000 steps.
+  batch    4096 parameter sets, alpha~U[0,10], S_b~U[0.01,1], S_s~U[1e2,1e4],
+           N=128, 5000 steps at dt=5e-5, head observed every 100 steps.
+  uneven   16384 particles, N~U{64,96,...,512}, same priors, 3 PMC generations.
+  dense    64 samples x 8 swimmers x N=512 on a 2x4 grid (spacing 1.5),
+           phases~U[0,2pi), alpha~U[0,10].
+  surrogate 65536 training runs (N=128) and 1M prescreened proposals.
+"""
+import numpy as np
+
+TWO_PI = 2.0 * np.pi
+
+# default swimmer constants of the single-filament workload
+DEFAULTS = dict(alpha=1.0, Sb=0.1, Ss=1e3, b=0.1, omega=TWO_PI, k=TWO_PI, phase=0.0, x0=0.0, y0=0.0)
+PARAM_FIELDS = ("alpha", "Sb", "Ss", "b", "omega", "k", "phase", "x0", "y0")
+
+# uniform prior box on (alpha, S_b, S_s)
+PRIOR_LO = np.array([0.0, 0.01, 1e2])
+PRIOR_HI = np.array([10.0, 1.0, 1e4])
+TRUE_THETA = np.array([2.0, 0.1, 1e3])
+
+UNEVEN_N_CHOICES = np.arange(64, 513, 32)
+
+
+def param_rows(n, **overrides):
+    """(n, 9) array of swimmer parameter rows (columns PARAM_FIELDS)."""
+    P = np.empty((n, len(PARAM_FIELDS)))
+    for i, f in enumerate(PARAM_FIELDS):
+        P[:, i] = overrides.get(f, DEFAULTS[f])
+    return P
+
+
+def theta_rows(theta, **overrides):
+    """Parameter rows from an (n, 3) array of (alpha, S_b, S_s)."""
+    theta = np.atleast_2d(np.asarray(theta, dtype=np.float64))
+    P = param_rows(theta.shape[0], **overrides)
+    P[:, 0:3] = theta
+    return P
+
+
+def uneven_sizes(n, seed=2):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.choice(UNEVEN_N_CHOICES, size=n).astype(np.int32)
+
+
+def dense_layout(n_samples=64, seed=3, n_cols=4, n_rows=2, spacing=1.5):
+    """Swimmer rows for the multi-swimmer workload: (n_samples, 8, 9)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    alpha = rng.uniform(0.0, 10.0, size=n_samples)
+    phase = rng.uniform(0.0, TWO_PI, size=(n_samples, n_cols * n_rows))
+    P = np.empty((n_samples, n_cols * n_rows, len(PARAM_FIELDS)))
+    for s in range(n_samples):
+        rows = param_rows(n_cols * n_rows, alpha=alpha[s])
+        m = 0
+        for r in range(n_rows):
+            for c in range(n_cols):
+                rows[m, 6] = phase[s, m]
+                rows[m, 7] = spacing * c
+                rows[m, 8] = spacing * r
+                m += 1
+        P[s] = rows
+    return P
+
+
+def filament_geometry(N, seed, n_swim=1, amp=0.08, spacing=1.5, jitter=1e-3):
+    """Bent filaments of length ~1 (a travelling-wave shape plus jitter) for
+    single-evaluation tests.  Returns x, y of shape (n_swim*N,)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = np.linspace(0.0, 1.0, N)
+    xs, ys = [], []
+    for m in range(n_swim):
+        ph = rng.uniform(0.0, TWO_PI)
+        x = s + jitter * rng.standard_normal(N) / N
+        y = amp * np.sin(TWO_PI * s + ph) + jitter * rng.standard_normal(N) / N
+        xs.append(x + spacing * (m % 4))
+        ys.append(y + spacing * (m // 4))
+    return np.concatenate(xs), np.concatenate(ys)
+
+
+def force_pattern(N, seed, n_swim=1, tension=50.0, smooth=5.0):
+    """Point forces shaped like a filament's: a large alternating tension part
+    T_k - T_{k-1} along x plus a smooth part, with zero sum per filament."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fxs, fys = [], []
+    for _ in range(n_swim):
+        T = tension * rng.standard_normal(N + 1)
+        T[0] = T[-1] = 0.0
+        fx = T[1:] - T[:-1] + smooth * rng.standard_normal(N)
+        fy = smooth * np.sin(np.linspace(0, 3 * np.pi, N)) * rng.uniform(0.5, 1.5) + \
+            0.2 * smooth * rng.standard_normal(N)
+        fx -= fx.mean()
+        fy -= fy.mean()
+        fxs.append(fx)
+        fys.append(fy)
+    return np.concatenate(fxs), np.concatenate(fys)
+
+
+def surrogate_inputs(n, seed):
+    """(alpha, log S_b, log S_s, b, omega) rows drawn from the prior box with b
+    and omega at their defaults."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.uniform(PRIOR_LO[0], PRIOR_HI[0], n)
+    sb = rng.uniform(PRIOR_LO[1], PRIOR_HI[1], n)
+    ss = rng.uniform(PRIOR_LO[2], PRIOR_HI[2], n)
+    return np.stack([a, sb, ss], axis=1)
+
+
+def observation_noise(n_obs, sigma=1e-3, seed=20191027):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return sigma * rng.standard_normal((n_obs, 2))
