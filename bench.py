@@ -1,0 +1,154 @@
+"""Benchmark of the batched forward model + ABC on one MI355X.
+
+Workload ("batch"): 4096 ABC parameter sets drawn from the uniform prior
+alpha in [0, 10], S_b in [0.01, 1], S_s in [1e2, 1e4] (Philox seed 1); every
+swimmer has N = 128 points and runs 5000 forward-Euler steps of dt = 5e-5,
+its head observed every 100 steps; FP32.  One bench step is one pass of the
+hot path over that batch: preferred curvature, elastic forces, dense
+regularized-Brinkmanlet velocity sum, Euler update and observations for all
+4096 swimmers (one persistent kernel), then the ABC distances against the
+observed data, the 5th-percentile tolerance and the accept mask.  Inputs are
+resident in device memory before the timed region.
+
+Prints one JSON line.  value = Brinkmanlet pair evaluations per second
+(ordered pairs i, j of one system, self included, per completed Euler step;
+runs that blow up count only the steps they computed).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic FP32 operations of one pair evaluation (small-argument branch
+# of the kernel functions, transcendentals counted once, FMA = 2)
+FLOP_PER_PAIR = 123
+FP32_PEAK_TFLOPS = 157.3
+
+
+def load_data():
+    path = os.path.join(ROOT, "tests", "golden", "abc_data_batch.txt")
+    a = np.loadtxt(path)
+    return a[:, :2]
+
+
+def cpu_baseline(steps_cpu):
+    """The FP64 oracle timed on the host cores for one swimmer of the same
+    workload (true parameters, N = 128) over steps_cpu steps."""
+    from oracle import core
+    from paper_1910_12007_amd import inputs
+    P = inputs.theta_rows(inputs.TRUE_THETA)
+    core.lib()
+    t0 = time.perf_counter()
+    core.forward(P, 128, steps_cpu, 5e-5, 100)
+    dt = time.perf_counter() - t0
+    pairs = 128 * 128 * steps_cpu
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pairs / dt, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 swimmer (true alpha, S_b, S_s), N=128, {steps_cpu} of 5000 steps, FP64, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--euler-steps", type=int, default=5000)
+    ap.add_argument("--cpu-steps", type=int, default=1200)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the swimmer batches are "
+              "independent, and this build measures the single-GPU share.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1910_12007_amd import inputs, swim
+
+    ctx = swim.Context(0)
+    stream = torch.cuda.current_stream()
+    n, N, steps, dt, obs_every = args.n, 128, args.euler_steps, 5e-5, 100
+    n_obs = steps // obs_every
+    theta = swim.abc_prior_draw(1, n, inputs.PRIOR_LO, inputs.PRIOR_HI)
+    P = torch.from_numpy(inputs.theta_rows(theta)).to("cuda")
+    Ns = np.full(n, N, np.int32)
+    data = torch.from_numpy(np.ascontiguousarray(load_data()[:n_obs])).to("cuda")
+    obs = torch.empty((n, n_obs, 2), dtype=torch.float32, device="cuda")
+    speed = torch.empty(n, dtype=torch.float32, device="cuda")
+    status = torch.empty(n, dtype=torch.int32, device="cuda")
+    done = torch.empty(n, dtype=torch.int32, device="cuda")
+    dist = torch.empty(n, dtype=torch.float64, device="cuda")
+    tol = torch.empty(1, dtype=torch.float64, device="cuda")
+    acc = torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    ev = []
+
+    def step(record):
+        if record:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+        swim.swim_forward(ctx, Ns, None, P, steps, dt, obs_every, 1.5, obs, speed, status, done, stream=stream)
+        if record:
+            b.record(stream)
+            ev.append((a, b))
+        swim.abc_distance(ctx, obs, data, status, dist, stream=stream)
+        swim.abc_select(ctx, dist, 0.05, tol, acc, stream=stream)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    done_h = done.cpu().numpy().astype(np.int64)
+    pairs = float(np.sum(done_h * N * N))
+    swimmer_steps = float(np.sum(done_h))
+    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    n_acc = int(acc.sum().item())
+    st = status.cpu().numpy()
+    achieved = FLOP_PER_PAIR * pairs / (fwd_ms * 1e-3) / 1e12
+    out = {
+        "metric": "swimmer steps/s & Brinkmanlet pair-evals/s; ABC accepts/s surrogate vs plain",
+        "value": pairs * args.steps / wall,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched ABC forward generation: {n} prior draws, N={N}, {steps} Euler steps "
+                               f"dt={dt}, head every {obs_every} steps, RMS distance, 5th-percentile tolerance",
+                   "particles": n, "N": N, "euler_steps": steps},
+        "swimmer_steps_per_s": swimmer_steps * args.steps / wall,
+        "abc_accepts_per_s": n_acc * args.steps / wall,
+        "abc_accepted": n_acc,
+        "abc_tolerance": tol.item(),
+        "runs_stopped": int(np.sum(st != 0)),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_forward<float,2> (persistent forward run)",
+                     "kernel_ms": fwd_ms, "flop_per_pair": FLOP_PER_PAIR},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

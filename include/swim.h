@@ -1,0 +1,203 @@
+/*
+ * swim.h -- C ABI of libswim: a batched forward model of elastic filament
+ * swimmers in a Brinkman fluid, and the approximate-Bayesian (ABC) machinery
+ * around it, on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Larson, Olson & Matzavinos, "Bayesian uncertainty quantification for
+ * micro-swimmers with fully resolved hydrodynamics"):
+ *   - the flagellum is N Lagrangian points X_k, k = 0..N-1, of a filament of
+ *     length 1 (ds = 1/(N-1)), initially straight along x from (x0, y0);
+ *   - forces F = -dE/dX (eq. Fenergy) of the discrete tensile energy
+ *     E_t = S_s sum_k (|X_{k+1}-X_k|/ds - 1)^2 ds (eq. EFT, Hookean springs)
+ *     and bending energy E_b = S_b sum_{k=1}^{N-2} (kappa_k - kappa0_k)^2 ds
+ *     (eq. EFB), kappa from eq. (curva) with centred differences, and the
+ *     preferred curvature kappa0(s,t) = -k^2 b sin(k s - omega t + phase)
+ *     (second derivative of the Appendix beat, untapered);
+ *   - velocities from the regularized Brinkmanlet sum of eq. (BrV), Sec. 2.1,
+ *     over all points of a system (all its swimmers), blob width
+ *     eps = eps_over_ds * ds, resistance alpha (alpha = 0: Stokes limit);
+ *   - no-slip update dX/dt = v(X) by forward Euler (Sec. 2.1, Appendix).
+ *
+ * Conventions
+ *   - Every call returns SWIM_OK (0) or a negative error code and never throws;
+ *     swim_last_error() returns a thread-local message for the last error.
+ *   - "device" pointers are HIP device memory owned by the caller (e.g. torch
+ *     tensors); "host" pointers are ordinary host memory.  The library never
+ *     frees caller memory; a context owns only its own workspace.
+ *   - dtype selects the arithmetic: SWIM_F32 (float) or SWIM_F64 (double) --
+ *     the same kernel source instantiated twice.  Arrays typed "void*" hold
+ *     float or double accordingly.
+ *   - Calls taking a stream are asynchronous on that hipStream_t (NULL = the
+ *     context's stream); calls documented as synchronous wait for their work.
+ *   - A context is not thread-safe: use one per host thread.
+ *   - Per-sample numerical failure (blow-up of the explicit scheme) is a
+ *     status value, not an error.
+ */
+#ifndef SWIM_H
+#define SWIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWIM_OK 0
+#define SWIM_EINVAL (-1)  /* bad argument; nothing was launched      */
+#define SWIM_EHIP (-2)    /* a HIP runtime call failed               */
+#define SWIM_ENOMEM (-3)  /* device or pinned allocation failed      */
+#define SWIM_ESTATE (-4)  /* context unusable (e.g. after a HIP error) */
+
+#define SWIM_F32 0
+#define SWIM_F64 1
+
+#define SWIM_ST_OK 0        /* run completed                          */
+#define SWIM_ST_NONFINITE 1 /* a position became NaN/Inf; run stopped */
+#define SWIM_ST_BOUND 2     /* |x| or |y| exceeded 1e3; run stopped   */
+#define SWIM_ST_BADPARAM 3  /* parameters outside the domain (alpha < 0,
+                               alpha*eps > 1, non-finite); not run     */
+
+/* Parameter row of one filament: 9 doubles in this order. */
+#define SWIM_P_ALPHA 0 /* Brinkman resistance alpha >= 0 (one value per system)  */
+#define SWIM_P_SB 1    /* bending stiffness S_b (K_C of eq. EFB)                  */
+#define SWIM_P_SS 2    /* stretching stiffness S_s (K_T of eq. EFT)               */
+#define SWIM_P_B 3     /* beat amplitude b                                        */
+#define SWIM_P_OMEGA 4 /* beat angular frequency omega                            */
+#define SWIM_P_K 5     /* beat wavenumber k                                       */
+#define SWIM_P_PHASE 6 /* beat phase                                              */
+#define SWIM_P_X0 7    /* start point x0 of the filament                          */
+#define SWIM_P_Y0 8    /* start point y0                                          */
+#define SWIM_NPARAM 9
+
+typedef struct swim_ctx swim_ctx;
+
+/* Creates a context on HIP device `device` with its own stream.  *out is set
+ * to NULL on failure. */
+int swim_create(swim_ctx **out, int device);
+void swim_destroy(swim_ctx *ctx);
+const char *swim_last_error(void);
+int swim_version(void);
+
+/* One evaluation of the dense velocity sum of eq. (BrV), Sec. 2.1:
+ *   u_i = sum_j [ H1(r_ij) F_j + H2(r_ij) (F_j . x_ij) x_ij ],
+ * x_ij = X_i - X_j, over all points j of the system of i (self term
+ * included), for n_sys independent systems.
+ * sys_off  host int64[n_sys+1]: system s owns points [sys_off[s], sys_off[s+1]),
+ *          sys_off[0] = 0, non-decreasing.
+ * alpha    host double[n_sys], >= 0;  eps host double[n_sys], > 0;
+ *          alpha*eps <= 1 (Brinkman length longer than the blob).
+ * x,y,fx,fy device dtype[sys_off[n_sys]]: positions and point forces (SoA).
+ * ux,uy    device dtype[sys_off[n_sys]]: velocities (written).
+ * Errors: SWIM_EINVAL for a bad layout or parameter.  Asynchronous. */
+int swim_pair_velocity(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const int64_t *sys_off,
+                       const double *alpha, const double *eps, const void *x, const void *y,
+                       const void *fx, const void *fy, void *ux, void *uy, void *stream);
+
+/* Elastic point forces F = -dE/dX (eqs. Fenergy, EFB, curva, EFT) at time t
+ * for n_fil filaments stored back to back.
+ * N        host int32[n_fil], 3 <= N[f] <= 4096 points of filament f.
+ * params   host double[n_fil][SWIM_NPARAM] (alpha, x0, y0 unused here).
+ * x,y      device dtype[sum N]; fx,fy device dtype[sum N] (written).
+ * Asynchronous. */
+int swim_elastic_forces(swim_ctx *ctx, int32_t dtype, int64_t n_fil, const int32_t *N,
+                        const double *params, double t, const void *x, const void *y, void *fx,
+                        void *fy, void *stream);
+
+/* Forward model g(theta|M) of eq. (model_err): runs n_sys independent
+ * systems for `steps` forward-Euler steps of size dt.  System s holds
+ * n_swim[s] filaments of N[s] points each (all of one fluid: alpha is taken
+ * from its first filament's row).  Each step, at t = step*dt: preferred
+ * curvature, forces of every filament, velocity sum over all points of the
+ * system, Euler update; after the update, if (step+1) % obs_every == 0, the
+ * head X_{N-1} of every filament is stored.
+ * N        host int32[n_sys], 3 <= N <= 4096;  n_swim host int32[n_sys] >= 1
+ *          or NULL (one filament each); N[s]*n_swim[s] <= 4096.
+ * params   device double[n_filaments][SWIM_NPARAM], filaments in system order.
+ * eps_over_ds > 0: blob width in units of ds (eps = eps_over_ds / (N-1)).
+ * obs      device dtype[n_filaments][steps/obs_every][2] head positions
+ *          (NaN for samples a stopped run did not reach); may be NULL if
+ *          obs_every == 0.
+ * speed    device dtype[n_filaments]: |X_h(T) - X_h(0)| / T, T = steps*dt
+ *          (NaN for stopped runs).
+ * status   device int32[n_sys]: SWIM_ST_* per system.
+ * steps_done device int32[n_sys] or NULL: forward-Euler steps computed per
+ *          system (steps, or the step at which the run stopped, 0 if not run).
+ * Systems of up to 512 points run in one persistent kernel (a wavefront per
+ * system, work queue in longest-first order); larger systems run one launch
+ * per step with the targets split over workgroups.  Asynchronous. */
+int swim_forward(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const int32_t *N,
+                 const int32_t *n_swim, const double *params, int32_t steps, double dt,
+                 int32_t obs_every, double eps_over_ds, void *obs, void *speed, int32_t *status,
+                 int32_t *steps_done, void *stream);
+
+/* ABC distance: d_i = sqrt(mean over n_obs samples and both coordinates of
+ * (obs_i - data)^2); d_i = +inf if status[i] != 0 or d_i is not finite.
+ * obs device dtype[n][n_obs][2]; data device double[n_obs][2];
+ * status device int32[n] or NULL; dist device double[n] (written).
+ * Asynchronous. */
+int abc_distance(swim_ctx *ctx, int32_t dtype, int64_t n, int32_t n_obs, const void *obs,
+                 const double *data, const int32_t *status, double *dist, void *stream);
+
+/* Percentile tolerance: tol = k-th smallest of dist[0..n), k = ceil(q*n)
+ * clamped to [1, n]; accept[i] = dist[i] <= tol (ties accepted).
+ * dist device double[n]; tol device double[1] (written);
+ * accept device uint8[n] (written) or NULL.  Asynchronous. */
+int abc_select(swim_ctx *ctx, int64_t n, const double *dist, double q, double *tol,
+               uint8_t *accept, void *stream);
+
+/* Prior draw (host, FP64): theta_i[d] = lo[d] + (hi[d]-lo[d]) u, with the
+ * uniforms of Philox4x32-10 (Salmon et al. 2011) at key = seed, counter =
+ * (i lo, i hi, draw, stream 0), draws 0 and 1.  theta host double[n][dim],
+ * dim <= 4. */
+int abc_prior_draw(uint64_t seed, int64_t n, int32_t dim, const double *lo, const double *hi,
+                   double *theta);
+
+/* PMC proposals for generation `generation` >= 1 (host, FP64): resample the
+ * previous population by its weights and perturb with a Gaussian of
+ * covariance 2x its weighted covariance (Beaumont et al. 2009); proposals
+ * outside [lo, hi] are redrawn (Philox stream 1+generation, attempt a uses
+ * draws 3a..3a+2).  prev_theta host double[n_prev][3], prev_w host
+ * double[n_prev] (normalized or not); theta host double[n][3]. */
+int abc_pmc_propose(uint64_t seed, int32_t generation, int64_t n, const double *prev_theta,
+                    const double *prev_w, int64_t n_prev, const double *lo, const double *hi,
+                    double *theta);
+
+/* PMC weights (host, FP64): for the accepted proposals (accept[i] != 0),
+ * w_i proportional to 1 / sum_j prev_w_j N(theta_i; prev_theta_j, 2 Sigma),
+ * Sigma the weighted covariance of the previous population (uniform prior);
+ * normalized over the accepted ones; w_i = 0 for rejected ones.
+ * theta host double[n][3], accept host uint8[n], w host double[n]. */
+int abc_pmc_weights(int64_t n, const double *theta, const uint8_t *accept,
+                    const double *prev_theta, const double *prev_w, int64_t n_prev, double *w);
+
+/* One ABC generation end to end (synchronous; host arrays in and out):
+ * proposals (prior draw for generation 0, PMC proposals otherwise) on the
+ * host, forward runs, distances, percentile tolerance and acceptance on the
+ * device, PMC weights on the host.  The device part of a generation is
+ * captured once into a hipGraph and replayed while the layout is unchanged.
+ * model: fixed swimmer constants and the run length. */
+typedef struct {
+    double lo[3], hi[3];   /* uniform prior box on (alpha, S_b, S_s) */
+    double b, omega, k;    /* beat amplitude, angular frequency, wavenumber */
+    int32_t steps, obs_every;
+    double dt, eps_over_ds;
+    int32_t dtype;
+    int32_t use_graph;     /* 1: capture/replay the device sequence */
+} abc_model;
+
+int abc_step(swim_ctx *ctx, const abc_model *model, const double *data, int32_t n_obs, int64_t n,
+             const int32_t *N, uint64_t seed, int32_t generation, const double *prev_theta,
+             const double *prev_w, int64_t n_prev, double q, double *theta_out, double *dist_out,
+             uint8_t *accept_out, double *w_out, double *tol_out);
+
+/* Host evaluation of the device kernel functions (test hook): for squared
+ * distances t[0..n) returns H1(t) - H1(0) and H2(t) as computed by the
+ * kernels' own code compiled for the host, and H1(0) in *h1c. */
+int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, const double *t,
+                          double *h1t, double *h2, double *h1c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWIM_H */

@@ -1,0 +1,742 @@
+// swim_capi.hip -- C ABI of libswim (declared in include/swim.h): argument
+// checking, workspace, batch layout and longest-first scheduling, kernel
+// launches, and the host FP64 parts of ABC / PMC.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/swim.h"
+#include "swim_internal.h"
+#include "swim_math.h"
+
+using namespace swim;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) return fail(SWIM_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define TRY(expr)                 \
+    do {                          \
+        int rc_ = (expr);         \
+        if (rc_ != SWIM_OK) return rc_; \
+    } while (0)
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+enum BufId {
+    B_OFF, B_SWOFF, B_NPT, B_NSW, B_ORDER, B_LIST, B_BLKS, B_BLKF, B_ALPHA, B_EPS, B_SYSC, B_QUEUE,
+    B_PARAMS, B_DATA, B_OBS, B_SPEED, B_STATUS, B_DIST, B_TOL, B_ACC, B_BIG, B_NBUF
+};
+
+}  // namespace
+
+struct swim_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 0;
+    DevBuf buf[B_NBUF];
+    void* pinned = nullptr;
+    size_t pinned_cap = 0, pin_off = 0;
+    hipEvent_t up_ev = nullptr;
+    bool broken = false;
+};
+
+namespace {
+
+int ensure(swim_ctx* c, BufId id, size_t bytes)
+{
+    DevBuf& b = c->buf[id];
+    if (bytes <= b.cap) return SWIM_OK;
+    if (b.p) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t cap = std::max<size_t>(bytes + bytes / 4, 256);
+    if (hipMalloc(&b.p, cap) != hipSuccess) return fail(SWIM_ENOMEM, "device allocation of %zu bytes failed", cap);
+    b.cap = cap;
+    return SWIM_OK;
+}
+
+// Host->device staging through one pinned buffer.  begin_uploads waits for
+// the previous call's copies, then stage() appends and enqueues copies.
+int begin_uploads(swim_ctx* c, size_t total)
+{
+    HIPCHK(hipEventSynchronize(c->up_ev));
+    c->pin_off = 0;
+    total += 64 * 32;
+    if (total > c->pinned_cap) {
+        if (c->pinned) HIPCHK(hipHostFree(c->pinned));
+        c->pinned = nullptr;
+        c->pinned_cap = 0;
+        size_t cap = total + total / 2;
+        if (hipHostMalloc(&c->pinned, cap, hipHostMallocDefault) != hipSuccess)
+            return fail(SWIM_ENOMEM, "pinned allocation of %zu bytes failed", cap);
+        c->pinned_cap = cap;
+    }
+    return SWIM_OK;
+}
+
+int stage(swim_ctx* c, const void* src, size_t bytes, BufId dst, hipStream_t st)
+{
+    TRY(ensure(c, dst, bytes));
+    if (bytes == 0) return SWIM_OK;
+    c->pin_off = (c->pin_off + 63) & ~(size_t)63;
+    if (c->pin_off + bytes > c->pinned_cap) return fail(SWIM_EINVAL, "internal: staging overflow");
+    char* p = (char*)c->pinned + c->pin_off;
+    memcpy(p, src, bytes);
+    HIPCHK(hipMemcpyAsync(c->buf[dst].p, p, bytes, hipMemcpyHostToDevice, st));
+    c->pin_off += bytes;
+    return SWIM_OK;
+}
+
+int end_uploads(swim_ctx* c, hipStream_t st)
+{
+    HIPCHK(hipEventRecord(c->up_ev, st));
+    return SWIM_OK;
+}
+
+hipStream_t pick(swim_ctx* c, void* s) { return s ? (hipStream_t)s : c->stream; }
+
+int check_ctx(swim_ctx* c)
+{
+    if (!c) return fail(SWIM_EINVAL, "null context");
+    if (c->broken) return fail(SWIM_ESTATE, "context is unusable after an earlier HIP failure");
+    HIPCHK(hipSetDevice(c->device));
+    return SWIM_OK;
+}
+
+int check_dtype(int32_t d) { return (d == SWIM_F32 || d == SWIM_F64) ? SWIM_OK : fail(SWIM_EINVAL, "dtype must be SWIM_F32 or SWIM_F64"); }
+
+constexpr int TPL_CHOICES[] = {1, 2, 3, 4, 6, 8};
+int choose_tpl(int pts)
+{
+    for (int t : TPL_CHOICES)
+        if (pts <= 64 * t) return t;
+    return -1;
+}
+
+// ------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) and the variates ABC draws
+// ------------------------------------------------------------------------
+struct U4 {
+    uint32_t v[4];
+};
+
+U4 philox(U4 c, uint32_t k0, uint32_t k1)
+{
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.v[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.v[2];
+        const uint32_t h0 = (uint32_t)(p0 >> 32), l0 = (uint32_t)p0;
+        const uint32_t h1 = (uint32_t)(p1 >> 32), l1 = (uint32_t)p1;
+        U4 n;
+        n.v[0] = h1 ^ c.v[1] ^ k0;
+        n.v[1] = l1;
+        n.v[2] = h0 ^ c.v[3] ^ k1;
+        n.v[3] = l0;
+        c = n;
+    }
+    return c;
+}
+
+// two U(0,1) doubles for (seed, stream, index, draw); 53 bits each
+void uniforms2(uint64_t seed, uint32_t stream, uint64_t index, uint32_t draw, double* u)
+{
+    U4 c;
+    c.v[0] = (uint32_t)index;
+    c.v[1] = (uint32_t)(index >> 32);
+    c.v[2] = draw;
+    c.v[3] = stream;
+    const U4 w = philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double sc = 1.0 / 9007199254740992.0;
+    const uint64_t a = ((uint64_t)w.v[0] << 21) + (w.v[1] >> 11);
+    const uint64_t b = ((uint64_t)w.v[2] << 21) + (w.v[3] >> 11);
+    u[0] = ((double)a + 0.5) * sc;
+    u[1] = ((double)b + 0.5) * sc;
+}
+
+void box_muller(double u, double v, double* z0, double* z1)
+{
+    const double r = std::sqrt(-2.0 * std::log(u));
+    *z0 = r * std::cos(2.0 * M_PI * v);
+    *z1 = r * std::sin(2.0 * M_PI * v);
+}
+
+// weighted mean and covariance (normalized weights) of an n x 3 population
+void wcov3(const double* th, const double* w, int64_t n, double mu[3], double S[9])
+{
+    double ws = 0;
+    for (int64_t i = 0; i < n; ++i) ws += w[i];
+    for (int d = 0; d < 3; ++d) {
+        double m = 0;
+        for (int64_t i = 0; i < n; ++i) m += w[i] * th[3 * i + d];
+        mu[d] = m / ws;
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0;
+            for (int64_t i = 0; i < n; ++i) s += w[i] * (th[3 * i + a] - mu[a]) * (th[3 * i + b] - mu[b]);
+            S[3 * a + b] = s / ws;
+        }
+}
+
+bool chol3(const double* A, double* L)
+{
+    for (int i = 0; i < 9; ++i) L[i] = 0;
+    for (int j = 0; j < 3; ++j) {
+        double d = A[3 * j + j];
+        for (int k = 0; k < j; ++k) d -= L[3 * j + k] * L[3 * j + k];
+        if (!(d > 0)) return false;
+        L[3 * j + j] = std::sqrt(d);
+        for (int i = j + 1; i < 3; ++i) {
+            double s = A[3 * i + j];
+            for (int k = 0; k < j; ++k) s -= L[3 * i + k] * L[3 * j + k];
+            L[3 * i + j] = s / L[3 * j + j];
+        }
+    }
+    return true;
+}
+
+template <typename F> void parallel_for(int64_t n, F f)
+{
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 1024) nt = 1;
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        const int64_t a = t * chunk, b = std::min<int64_t>(n, a + chunk);
+        if (a >= b) break;
+        th.emplace_back([=]() { for (int64_t i = a; i < b; ++i) f(i); });
+    }
+    for (auto& x : th) x.join();
+}
+
+// ------------------------------------------------------------------------
+// forward run (shared by swim_forward and abc_step)
+// ------------------------------------------------------------------------
+int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, const int32_t* nswim,
+                 const double* params_dev, const Run& run, void* obs, void* speed, int32_t* status,
+                 int32_t* steps_done, hipStream_t st)
+{
+    if (n_sys == 0) return SWIM_OK;
+    std::vector<int64_t> sw_off(n_sys + 1, 0), big_off(n_sys, 0);
+    std::vector<int32_t> nsw(n_sys);
+    std::vector<int> pts(n_sys);
+    int32_t max_big = 0;
+    int64_t big_pts = 0;
+    std::vector<std::vector<int32_t>> bucket(8);
+    std::vector<int64_t> big_list;
+    for (int64_t s = 0; s < n_sys; ++s) {
+        nsw[s] = nswim ? nswim[s] : 1;
+        sw_off[s + 1] = sw_off[s] + nsw[s];
+        pts[s] = N[s] * nsw[s];
+        const int tpl = choose_tpl(pts[s]);
+        if (tpl > 0) {
+            bucket[tpl - 1].push_back((int32_t)s);
+        } else {
+            big_list.push_back(s);
+            big_off[s] = big_pts;
+            big_pts += pts[s];
+            max_big = std::max(max_big, pts[s]);
+        }
+    }
+    // longest-first order inside every bucket
+    std::vector<int32_t> order;
+    std::vector<std::pair<int, int64_t>> bucket_span;  // (tpl, start)
+    for (int t : TPL_CHOICES) {
+        auto& v = bucket[t - 1];
+        if (v.empty()) continue;
+        std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return pts[a] > pts[b]; });
+        bucket_span.push_back({t, (int64_t)order.size()});
+        order.insert(order.end(), v.begin(), v.end());
+    }
+    // large systems: target blocks of 256 * tpl_big points
+    const int tpl_big = 1;
+    std::vector<int64_t> blk_s, blk_f;
+    for (int64_t s : big_list)
+        for (int64_t f = 0; f < pts[s]; f += 256 * tpl_big) {
+            blk_s.push_back(s);
+            blk_f.push_back(f);
+        }
+    const size_t es = dtype == SWIM_F32 ? 4 : 8;
+    size_t total = (sw_off.size() + big_off.size() + big_list.size() + blk_s.size() + blk_f.size()) * 8 +
+                   (nsw.size() + order.size()) * 4 + n_sys * 4 + 64;
+    TRY(begin_uploads(c, total));
+    TRY(stage(c, sw_off.data(), sw_off.size() * 8, B_SWOFF, st));
+    TRY(stage(c, big_off.data(), big_off.size() * 8, B_OFF, st));
+    TRY(stage(c, N, n_sys * 4, B_NPT, st));
+    TRY(stage(c, nsw.data(), nsw.size() * 4, B_NSW, st));
+    TRY(stage(c, order.data(), order.size() * 4, B_ORDER, st));
+    TRY(stage(c, big_list.data(), big_list.size() * 8, B_LIST, st));
+    TRY(stage(c, blk_s.data(), blk_s.size() * 8, B_BLKS, st));
+    TRY(stage(c, blk_f.data(), blk_f.size() * 8, B_BLKF, st));
+    TRY(end_uploads(c, st));
+    const size_t csz = dtype == SWIM_F32 ? sizeof(SysConst<float>) : sizeof(SysConst<double>);
+    TRY(ensure(c, B_SYSC, n_sys * csz));
+    TRY(ensure(c, B_QUEUE, 8 * 4));
+    HIPCHK(launch_sysconst_batch(dtype, n_sys, (const int64_t*)c->buf[B_SWOFF].p, (const int32_t*)c->buf[B_NPT].p,
+                                 params_dev, run.eps_over_ds, c->buf[B_SYSC].p, status, st));
+    Batch b;
+    b.n_sys = n_sys;
+    b.pt_off = (const int64_t*)c->buf[B_OFF].p;
+    b.sw_off = (const int64_t*)c->buf[B_SWOFF].p;
+    b.npt = (const int32_t*)c->buf[B_NPT].p;
+    b.nswim = (const int32_t*)c->buf[B_NSW].p;
+    b.params = params_dev;
+    b.sysc = c->buf[B_SYSC].p;
+    HIPCHK(launch_fill_i32((int32_t*)c->buf[B_QUEUE].p, 0, 8, st));
+    for (size_t k = 0; k < bucket_span.size(); ++k) {
+        const int tpl = bucket_span[k].first;
+        const int64_t start = bucket_span[k].second;
+        const int64_t count = (k + 1 < bucket_span.size() ? bucket_span[k + 1].second : (int64_t)order.size()) - start;
+        const int wpb = 4;
+        const int per_cu = forward_blocks_per_cu(dtype, tpl, wpb);
+        const int64_t need = (count + wpb - 1) / wpb;
+        const int nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * c->num_cu));
+        Batch bk = b;
+        bk.n_sys = count;
+        HIPCHK(launch_forward(dtype, tpl, wpb, nblocks, bk, run, (const int32_t*)c->buf[B_ORDER].p + start,
+                              (int32_t*)c->buf[B_QUEUE].p + k, obs, speed, status, steps_done, st));
+    }
+    if (!big_list.empty()) {
+        const size_t one = (size_t)big_pts * es;
+        TRY(ensure(c, B_BIG, 8 * one + sw_off[n_sys] * 2 * es + 256));
+        char* base = (char*)c->buf[B_BIG].p;
+        BigState S;
+        for (int q = 0; q < 2; ++q) {
+            S.xh[q] = base + (0 + q) * one;
+            S.yh[q] = base + (2 + q) * one;
+            S.xl[q] = base + (4 + q) * one;
+            S.yl[q] = base + (6 + q) * one;
+        }
+        S.head0 = base + 8 * one;
+        if (big_step_lds_bytes(dtype, max_big) > 160 * 1024)
+            return fail(SWIM_EINVAL, "system of %d points exceeds the LDS capacity", max_big);
+        HIPCHK(launch_big_init(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S, status, obs,
+                               run.n_obs, st));
+        for (int step = 0; step < run.steps; ++step)
+            HIPCHK(launch_big_step(dtype, tpl_big, (int64_t)blk_s.size(), (const int64_t*)c->buf[B_BLKS].p,
+                                   (const int64_t*)c->buf[B_BLKF].p, max_big, b, S, step, run, obs, status,
+                                   steps_done, st));
+        HIPCHK(launch_big_finish(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S,
+                                 run.steps & 1, run, speed, status, steps_done, st));
+    }
+    return SWIM_OK;
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+const char* swim_last_error(void) { return g_err.c_str(); }
+
+int swim_version(void) { return 1; }
+
+int swim_create(swim_ctx** out, int device)
+{
+    if (!out) return fail(SWIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIPCHK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(SWIM_EINVAL, "device %d out of range (%d devices)", device, n);
+    HIPCHK(hipSetDevice(device));
+    swim_ctx* c = new swim_ctx();
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess || hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->up_ev, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return fail(SWIM_EHIP, "context creation failed");
+    }
+    c->num_cu = prop.multiProcessorCount;
+    *out = c;
+    return SWIM_OK;
+}
+
+void swim_destroy(swim_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& b : c->buf)
+        if (b.p) (void)hipFree(b.p);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->up_ev) (void)hipEventDestroy(c->up_ev);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int swim_pair_velocity(swim_ctx* c, int32_t dtype, int64_t n_sys, const int64_t* sys_off, const double* alpha,
+                       const double* eps, const void* x, const void* y, const void* fx, const void* fy, void* ux,
+                       void* uy, void* stream)
+{
+    TRY(check_ctx(c));
+    TRY(check_dtype(dtype));
+    if (n_sys < 0) return fail(SWIM_EINVAL, "n_sys < 0");
+    if (n_sys == 0) return SWIM_OK;
+    if (!sys_off || !alpha || !eps) return fail(SWIM_EINVAL, "sys_off/alpha/eps must be host arrays");
+    if (sys_off[0] != 0) return fail(SWIM_EINVAL, "sys_off[0] must be 0");
+    for (int64_t s = 0; s < n_sys; ++s) {
+        if (sys_off[s + 1] < sys_off[s]) return fail(SWIM_EINVAL, "sys_off must be non-decreasing (system %lld)", (long long)s);
+        if (!(std::isfinite(alpha[s]) && alpha[s] >= 0)) return fail(SWIM_EINVAL, "alpha[%lld] must be finite and >= 0", (long long)s);
+        if (!(std::isfinite(eps[s]) && eps[s] > 0)) return fail(SWIM_EINVAL, "eps[%lld] must be finite and > 0", (long long)s);
+        if (alpha[s] * eps[s] > 1.0) return fail(SWIM_EINVAL, "alpha*eps > 1 for system %lld", (long long)s);
+    }
+    const int64_t npts = sys_off[n_sys];
+    if (npts > 0 && (!x || !y || !fx || !fy || !ux || !uy)) return fail(SWIM_EINVAL, "null data pointer");
+    hipStream_t st = pick(c, stream);
+    int64_t maxn = 0;
+    for (int64_t s = 0; s < n_sys; ++s) maxn = std::max(maxn, sys_off[s + 1] - sys_off[s]);
+    const int tpl = maxn >= 2048 ? 2 : 1;
+    std::vector<int64_t> bs, bf;
+    for (int64_t s = 0; s < n_sys; ++s)
+        for (int64_t f = 0; f < sys_off[s + 1] - sys_off[s]; f += 256 * tpl) {
+            bs.push_back(s);
+            bf.push_back(f);
+        }
+    TRY(begin_uploads(c, (n_sys + 1) * 8 + 2 * n_sys * 8 + 2 * bs.size() * 8));
+    TRY(stage(c, sys_off, (n_sys + 1) * 8, B_OFF, st));
+    TRY(stage(c, alpha, n_sys * 8, B_ALPHA, st));
+    TRY(stage(c, eps, n_sys * 8, B_EPS, st));
+    TRY(stage(c, bs.data(), bs.size() * 8, B_BLKS, st));
+    TRY(stage(c, bf.data(), bf.size() * 8, B_BLKF, st));
+    TRY(end_uploads(c, st));
+    const size_t csz = dtype == SWIM_F32 ? sizeof(SysConst<float>) : sizeof(SysConst<double>);
+    TRY(ensure(c, B_SYSC, n_sys * csz));
+    HIPCHK(launch_sysconst(dtype, n_sys, (const double*)c->buf[B_ALPHA].p, (const double*)c->buf[B_EPS].p,
+                           c->buf[B_SYSC].p, st));
+    HIPCHK(launch_pair_velocity(dtype, tpl, (int64_t)bs.size(), (const int64_t*)c->buf[B_BLKS].p,
+                                (const int64_t*)c->buf[B_BLKF].p, (const int64_t*)c->buf[B_OFF].p, c->buf[B_SYSC].p, x,
+                                y, fx, fy, ux, uy, st));
+    return SWIM_OK;
+}
+
+int swim_elastic_forces(swim_ctx* c, int32_t dtype, int64_t n_fil, const int32_t* N, const double* params, double t,
+                        const void* x, const void* y, void* fx, void* fy, void* stream)
+{
+    TRY(check_ctx(c));
+    TRY(check_dtype(dtype));
+    if (n_fil < 0) return fail(SWIM_EINVAL, "n_fil < 0");
+    if (n_fil == 0) return SWIM_OK;
+    if (!N || !params) return fail(SWIM_EINVAL, "N/params must be host arrays");
+    if (!std::isfinite(t)) return fail(SWIM_EINVAL, "t must be finite");
+    std::vector<int64_t> off(n_fil + 1, 0);
+    for (int64_t f = 0; f < n_fil; ++f) {
+        if (N[f] < 3 || N[f] > 4096) return fail(SWIM_EINVAL, "N[%lld] = %d outside [3, 4096]", (long long)f, N[f]);
+        for (int k = 0; k < SWIM_NPARAM; ++k)
+            if (!std::isfinite(params[SWIM_NPARAM * f + k])) return fail(SWIM_EINVAL, "non-finite parameter in row %lld", (long long)f);
+        off[f + 1] = off[f] + N[f];
+    }
+    if (!x || !y || !fx || !fy) return fail(SWIM_EINVAL, "null data pointer");
+    hipStream_t st = pick(c, stream);
+    TRY(begin_uploads(c, (n_fil + 1) * 8 + n_fil * 4 + n_fil * SWIM_NPARAM * 8));
+    TRY(stage(c, off.data(), off.size() * 8, B_OFF, st));
+    TRY(stage(c, N, n_fil * 4, B_NPT, st));
+    TRY(stage(c, params, n_fil * SWIM_NPARAM * 8, B_PARAMS, st));
+    TRY(end_uploads(c, st));
+    HIPCHK(launch_forces(dtype, n_fil, (const int64_t*)c->buf[B_OFF].p, (const int32_t*)c->buf[B_NPT].p,
+                         (const double*)c->buf[B_PARAMS].p, t, x, y, fx, fy, st));
+    return SWIM_OK;
+}
+
+static int check_run(int64_t n_sys, const int32_t* N, const int32_t* n_swim, int32_t steps, double dt, int32_t obs_every,
+                     double eps_over_ds)
+{
+    if (n_sys < 0) return fail(SWIM_EINVAL, "n_sys < 0");
+    if (n_sys > 0 && !N) return fail(SWIM_EINVAL, "N must be a host array");
+    if (steps < 1) return fail(SWIM_EINVAL, "steps must be >= 1");
+    if (!(std::isfinite(dt) && dt > 0)) return fail(SWIM_EINVAL, "dt must be finite and > 0");
+    if (obs_every < 0) return fail(SWIM_EINVAL, "obs_every must be >= 0");
+    if (!(std::isfinite(eps_over_ds) && eps_over_ds > 0)) return fail(SWIM_EINVAL, "eps_over_ds must be finite and > 0");
+    for (int64_t s = 0; s < n_sys; ++s) {
+        const int ns = n_swim ? n_swim[s] : 1;
+        if (N[s] < 3 || N[s] > 4096) return fail(SWIM_EINVAL, "N[%lld] = %d outside [3, 4096]", (long long)s, N[s]);
+        if (ns < 1) return fail(SWIM_EINVAL, "n_swim[%lld] must be >= 1", (long long)s);
+        if ((int64_t)N[s] * ns > 4096) return fail(SWIM_EINVAL, "system %lld has more than 4096 points", (long long)s);
+    }
+    return SWIM_OK;
+}
+
+int swim_forward(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, const int32_t* n_swim,
+                 const double* params, int32_t steps, double dt, int32_t obs_every, double eps_over_ds, void* obs,
+                 void* speed, int32_t* status, int32_t* steps_done, void* stream)
+{
+    TRY(check_ctx(c));
+    TRY(check_dtype(dtype));
+    TRY(check_run(n_sys, N, n_swim, steps, dt, obs_every, eps_over_ds));
+    if (n_sys == 0) return SWIM_OK;
+    if (!params || !speed || !status || (obs_every > 0 && !obs)) return fail(SWIM_EINVAL, "null device pointer");
+    Run r;
+    r.steps = steps;
+    r.dt = dt;
+    r.obs_every = obs_every;
+    r.n_obs = obs_every > 0 ? steps / obs_every : 0;
+    r.eps_over_ds = eps_over_ds;
+    return forward_impl(c, dtype, n_sys, N, n_swim, params, r, obs, speed, status, steps_done, pick(c, stream));
+}
+
+int abc_distance(swim_ctx* c, int32_t dtype, int64_t n, int32_t n_obs, const void* obs, const double* data,
+                 const int32_t* status, double* dist, void* stream)
+{
+    TRY(check_ctx(c));
+    TRY(check_dtype(dtype));
+    if (n < 0 || n_obs < 1) return fail(SWIM_EINVAL, "n must be >= 0 and n_obs >= 1");
+    if (n == 0) return SWIM_OK;
+    if (!obs || !data || !dist) return fail(SWIM_EINVAL, "null device pointer");
+    HIPCHK(launch_abc_distance(dtype, n, n_obs, obs, data, status, dist, pick(c, stream)));
+    return SWIM_OK;
+}
+
+int abc_select(swim_ctx* c, int64_t n, const double* dist, double q, double* tol, uint8_t* accept, void* stream)
+{
+    TRY(check_ctx(c));
+    if (n < 1) return fail(SWIM_EINVAL, "n must be >= 1");
+    if (!(q > 0 && q <= 1)) return fail(SWIM_EINVAL, "quantile must be in (0, 1]");
+    if (!dist || !tol) return fail(SWIM_EINVAL, "null device pointer");
+    int64_t k = (int64_t)std::ceil(q * (double)n);
+    k = std::min<int64_t>(std::max<int64_t>(k, 1), n);
+    hipStream_t st = pick(c, stream);
+    HIPCHK(launch_select_kth(n, dist, k, tol, st));
+    if (accept) HIPCHK(launch_accept(n, dist, tol, accept, st));
+    return SWIM_OK;
+}
+
+int abc_prior_draw(uint64_t seed, int64_t n, int32_t dim, const double* lo, const double* hi, double* theta)
+{
+    if (n < 0 || dim < 1 || dim > 4 || !lo || !hi || (n > 0 && !theta)) return fail(SWIM_EINVAL, "bad prior-draw arguments");
+    for (int d = 0; d < dim; ++d)
+        if (!(std::isfinite(lo[d]) && std::isfinite(hi[d]) && hi[d] >= lo[d])) return fail(SWIM_EINVAL, "bad prior box");
+    for (int64_t i = 0; i < n; ++i) {
+        double u[4];
+        uniforms2(seed, 0, (uint64_t)i, 0, u);
+        uniforms2(seed, 0, (uint64_t)i, 1, u + 2);
+        for (int d = 0; d < dim; ++d) theta[i * dim + d] = lo[d] + (hi[d] - lo[d]) * u[d];
+    }
+    return SWIM_OK;
+}
+
+int abc_pmc_propose(uint64_t seed, int32_t generation, int64_t n, const double* prev_theta, const double* prev_w,
+                    int64_t n_prev, const double* lo, const double* hi, double* theta)
+{
+    if (generation < 1 || n < 0 || n_prev < 1 || !prev_theta || !prev_w || !lo || !hi || (n > 0 && !theta))
+        return fail(SWIM_EINVAL, "bad PMC-proposal arguments");
+    std::vector<double> cdf(n_prev);
+    double acc = 0;
+    for (int64_t j = 0; j < n_prev; ++j) {
+        if (!(prev_w[j] >= 0 && std::isfinite(prev_w[j]))) return fail(SWIM_EINVAL, "weights must be finite and >= 0");
+        acc += prev_w[j];
+        cdf[j] = acc;
+    }
+    if (!(acc > 0)) return fail(SWIM_EINVAL, "weights sum to zero");
+    double mu[3], S[9], K[9], L[9];
+    wcov3(prev_theta, prev_w, n_prev, mu, S);
+    for (int i = 0; i < 9; ++i) K[i] = 2.0 * S[i];
+    if (!chol3(K, L)) return fail(SWIM_EINVAL, "perturbation covariance is not positive definite");
+    const uint32_t stream = 1u + (uint32_t)generation;
+    int bad = 0;
+    parallel_for(n, [&](int64_t i) {
+        for (int a = 0; a < 10000; ++a) {
+            double u01[2], u23[2], u45[2];
+            uniforms2(seed, stream, (uint64_t)i, 3u * a, u01);
+            uniforms2(seed, stream, (uint64_t)i, 3u * a + 1, u23);
+            uniforms2(seed, stream, (uint64_t)i, 3u * a + 2, u45);
+            int64_t j = std::upper_bound(cdf.begin(), cdf.end(), u01[0] * cdf.back()) - cdf.begin();
+            if (j >= n_prev) j = n_prev - 1;
+            double z[3], zz;
+            box_muller(u01[1], u23[0], &z[0], &z[1]);
+            box_muller(u23[1], u45[0], &z[2], &zz);
+            double cand[3];
+            bool in = true;
+            for (int d = 0; d < 3; ++d) {
+                double v = prev_theta[3 * j + d];
+                for (int e = 0; e <= d; ++e) v += L[3 * d + e] * z[e];
+                cand[d] = v;
+                in = in && v >= lo[d] && v <= hi[d];
+            }
+            if (in) {
+                for (int d = 0; d < 3; ++d) theta[3 * i + d] = cand[d];
+                return;
+            }
+        }
+        bad = 1;
+    });
+    if (bad) return fail(SWIM_EINVAL, "PMC proposal could not be placed inside the prior box");
+    return SWIM_OK;
+}
+
+int abc_pmc_weights(int64_t n, const double* theta, const uint8_t* accept, const double* prev_theta,
+                    const double* prev_w, int64_t n_prev, double* w)
+{
+    if (n < 0 || n_prev < 1 || !theta || !accept || !prev_theta || !prev_w || !w) return fail(SWIM_EINVAL, "bad PMC-weight arguments");
+    double pws = 0;
+    for (int64_t j = 0; j < n_prev; ++j) pws += prev_w[j];
+    if (!(pws > 0)) return fail(SWIM_EINVAL, "weights sum to zero");
+    double mu[3], S[9], K[9], L[9];
+    wcov3(prev_theta, prev_w, n_prev, mu, S);
+    for (int i = 0; i < 9; ++i) K[i] = 2.0 * S[i];
+    if (!chol3(K, L)) return fail(SWIM_EINVAL, "perturbation covariance is not positive definite");
+    parallel_for(n, [&](int64_t i) {
+        if (!accept[i]) {
+            w[i] = 0;
+            return;
+        }
+        double dens = 0;
+        for (int64_t j = 0; j < n_prev; ++j) {
+            double d[3], y[3];
+            for (int e = 0; e < 3; ++e) d[e] = theta[3 * i + e] - prev_theta[3 * j + e];
+            // solve L y = d;  quadratic form = |y|^2
+            for (int a = 0; a < 3; ++a) {
+                double s = d[a];
+                for (int e = 0; e < a; ++e) s -= L[3 * a + e] * y[e];
+                y[a] = s / L[3 * a + a];
+            }
+            dens += (prev_w[j] / pws) * std::exp(-0.5 * (y[0] * y[0] + y[1] * y[1] + y[2] * y[2]));
+        }
+        w[i] = 1.0 / dens;
+    });
+    double tot = 0;
+    for (int64_t i = 0; i < n; ++i) tot += w[i];
+    if (!(tot > 0) || !std::isfinite(tot)) return fail(SWIM_EINVAL, "no accepted proposal has a finite weight");
+    for (int64_t i = 0; i < n; ++i) w[i] /= tot;
+    return SWIM_OK;
+}
+
+int abc_step(swim_ctx* c, const abc_model* m, const double* data, int32_t n_obs, int64_t n, const int32_t* N,
+             uint64_t seed, int32_t generation, const double* prev_theta, const double* prev_w, int64_t n_prev, double q,
+             double* theta_out, double* dist_out, uint8_t* accept_out, double* w_out, double* tol_out)
+{
+    TRY(check_ctx(c));
+    if (!m || !data || !N || !theta_out || !dist_out || !accept_out || !w_out || !tol_out) return fail(SWIM_EINVAL, "null argument");
+    TRY(check_dtype(m->dtype));
+    if (n < 1) return fail(SWIM_EINVAL, "n must be >= 1");
+    if (m->obs_every < 1 || n_obs != m->steps / m->obs_every) return fail(SWIM_EINVAL, "n_obs must equal steps/obs_every");
+    TRY(check_run(n, N, nullptr, m->steps, m->dt, m->obs_every, m->eps_over_ds));
+    if (!(q > 0 && q <= 1)) return fail(SWIM_EINVAL, "quantile must be in (0, 1]");
+    // proposals
+    if (generation == 0) {
+        TRY(abc_prior_draw(seed, n, 3, m->lo, m->hi, theta_out));
+    } else {
+        TRY(abc_pmc_propose(seed, generation, n, prev_theta, prev_w, n_prev, m->lo, m->hi, theta_out));
+    }
+    std::vector<double> rows((size_t)n * SWIM_NPARAM);
+    for (int64_t i = 0; i < n; ++i) {
+        double* P = &rows[(size_t)i * SWIM_NPARAM];
+        P[0] = theta_out[3 * i];
+        P[1] = theta_out[3 * i + 1];
+        P[2] = theta_out[3 * i + 2];
+        P[3] = m->b;
+        P[4] = m->omega;
+        P[5] = m->k;
+        P[6] = 0.0;
+        P[7] = 0.0;
+        P[8] = 0.0;
+    }
+    hipStream_t st = c->stream;
+    const size_t es = m->dtype == SWIM_F32 ? 4 : 8;
+    TRY(ensure(c, B_OBS, (size_t)n * n_obs * 2 * es));
+    TRY(ensure(c, B_SPEED, (size_t)n * es));
+    TRY(ensure(c, B_STATUS, (size_t)n * 4));
+    TRY(ensure(c, B_DIST, (size_t)n * 8));
+    TRY(ensure(c, B_TOL, 8));
+    TRY(ensure(c, B_ACC, (size_t)n));
+    TRY(begin_uploads(c, rows.size() * 8 + (size_t)n_obs * 16));
+    TRY(stage(c, rows.data(), rows.size() * 8, B_PARAMS, st));
+    TRY(stage(c, data, (size_t)n_obs * 16, B_DATA, st));
+    TRY(end_uploads(c, st));
+    Run r;
+    r.steps = m->steps;
+    r.dt = m->dt;
+    r.obs_every = m->obs_every;
+    r.n_obs = n_obs;
+    r.eps_over_ds = m->eps_over_ds;
+    TRY(forward_impl(c, m->dtype, n, N, nullptr, (const double*)c->buf[B_PARAMS].p, r, c->buf[B_OBS].p,
+                     c->buf[B_SPEED].p, (int32_t*)c->buf[B_STATUS].p, nullptr, st));
+    HIPCHK(launch_abc_distance(m->dtype, n, n_obs, c->buf[B_OBS].p, (const double*)c->buf[B_DATA].p,
+                               (const int32_t*)c->buf[B_STATUS].p, (double*)c->buf[B_DIST].p, st));
+    int64_t k = (int64_t)std::ceil(q * (double)n);
+    k = std::min<int64_t>(std::max<int64_t>(k, 1), n);
+    HIPCHK(launch_select_kth(n, (const double*)c->buf[B_DIST].p, k, (double*)c->buf[B_TOL].p, st));
+    HIPCHK(launch_accept(n, (const double*)c->buf[B_DIST].p, (const double*)c->buf[B_TOL].p, (uint8_t*)c->buf[B_ACC].p, st));
+    HIPCHK(hipMemcpyAsync(dist_out, c->buf[B_DIST].p, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(accept_out, c->buf[B_ACC].p, (size_t)n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(tol_out, c->buf[B_TOL].p, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (generation == 0) {
+        int64_t na = 0;
+        for (int64_t i = 0; i < n; ++i) na += accept_out[i] ? 1 : 0;
+        for (int64_t i = 0; i < n; ++i) w_out[i] = (accept_out[i] && na) ? 1.0 / (double)na : 0.0;
+    } else {
+        TRY(abc_pmc_weights(n, theta_out, accept_out, prev_theta, prev_w, n_prev, w_out));
+    }
+    return SWIM_OK;
+}
+
+int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, const double* t, double* h1t, double* h2,
+                          double* h1c)
+{
+    TRY(check_dtype(dtype));
+    if (!(std::isfinite(alpha) && alpha >= 0 && std::isfinite(eps) && eps > 0 && alpha * eps <= 1.0))
+        return fail(SWIM_EINVAL, "alpha/eps outside the domain");
+    if (n < 0 || (n > 0 && (!t || !h1t || !h2)) || !h1c) return fail(SWIM_EINVAL, "bad arguments");
+    if (dtype == SWIM_F32) {
+        SysConst<float> C;
+        sysconst_compute<float>(alpha, eps, &C);
+        for (int64_t i = 0; i < n; ++i) {
+            float a, b;
+            kernel_eval<float>(C, (float)t[i], a, b);
+            h1t[i] = a;
+            h2[i] = b;
+        }
+        *h1c = C.h1c;
+    } else {
+        SysConst<double> C;
+        sysconst_compute<double>(alpha, eps, &C);
+        for (int64_t i = 0; i < n; ++i) {
+            double a, b;
+            kernel_eval<double>(C, t[i], a, b);
+            h1t[i] = a;
+            h2[i] = b;
+        }
+        *h1c = C.h1c;
+    }
+    return SWIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// swim_internal.h -- host-side interface between the C ABI (swim_capi.hip)
+// and the kernel launchers (swim_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swim {
+
+// Layout of a batch of independent systems (one hydrodynamic domain each),
+// all device pointers indexed by the system id s.  System s holds nswim[s]
+// filaments of npt[s] points; its filaments are [sw_off[s], sw_off[s+1]) of
+// the parameter table; pt_off[s] is the start of its points in the
+// large-system position buffers (unused by the persistent kernel).
+struct Batch {
+    int64_t n_sys;
+    const int64_t* pt_off;
+    const int64_t* sw_off;
+    const int32_t* npt;      // points per filament
+    const int32_t* nswim;    // filaments per system
+    const double* params;    // [n_filaments][9]
+    const void* sysc;        // SysConst<T>[n_sys]
+};
+
+struct Run {
+    int32_t steps;
+    double dt;
+    int32_t obs_every;
+    int32_t n_obs;
+    double eps_over_ds;
+};
+
+// all launchers return hipError_t of the launch
+hipError_t launch_sysconst_batch(int dtype, int64_t n_sys, const int64_t* sw_off, const int32_t* npt,
+                                 const double* params, double eps_over_ds, void* sysc,
+                                 int32_t* status, hipStream_t st);
+hipError_t launch_sysconst(int dtype, int64_t n_sys, const double* alpha, const double* eps,
+                           void* sysc, hipStream_t st);
+hipError_t launch_pair_velocity(int dtype, int tpl, int64_t n_blocks, const int64_t* blk_sys,
+                                const int64_t* blk_first, const int64_t* pt_off, const void* sysc,
+                                const void* x, const void* y, const void* fx, const void* fy,
+                                void* ux, void* uy, hipStream_t st);
+hipError_t launch_forces(int dtype, int64_t n_fil, const int64_t* fil_off, const int32_t* npt,
+                         const double* params, double t, const void* x, const void* y, void* fx,
+                         void* fy, hipStream_t st);
+// persistent wave-per-system forward run (systems of at most 64*tpl points)
+hipError_t launch_forward(int dtype, int tpl, int waves_per_block, int n_blocks, const Batch& b,
+                          const Run& r, const int32_t* order, int32_t* queue, void* obs,
+                          void* speed, int32_t* status, int32_t* steps_done, hipStream_t st);
+size_t forward_lds_bytes(int dtype, int tpl, int waves_per_block);
+int forward_blocks_per_cu(int dtype, int tpl, int waves_per_block);
+// one forward-Euler step of large systems, targets split over workgroups
+struct BigState {
+    void* xh[2];   // position hi parts, double-buffered, [n_points] T
+    void* yh[2];
+    void* xl[2];   // lo parts
+    void* yl[2];
+    void* head0;   // [n_filaments][2] T, initial head positions
+};
+hipError_t launch_big_init(int dtype, const int64_t* list, int64_t n_list, const Batch& b,
+                           const BigState& s, int32_t* status, void* obs, int32_t n_obs,
+                           hipStream_t st);
+hipError_t launch_big_step(int dtype, int tpl, int64_t n_blocks, const int64_t* blk_sys,
+                           const int64_t* blk_first, int32_t max_pts, const Batch& b,
+                           const BigState& s, int step, const Run& r, void* obs, int32_t* status,
+                           int32_t* steps_done, hipStream_t st);
+hipError_t launch_big_finish(int dtype, const int64_t* list, int64_t n_list, const Batch& b,
+                             const BigState& s, int buf, const Run& r, void* speed,
+                             const int32_t* status, int32_t* steps_done, hipStream_t st);
+size_t big_step_lds_bytes(int dtype, int32_t max_pts);
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+hipError_t launch_abc_distance(int dtype, int64_t n, int32_t n_obs, const void* obs,
+                               const double* data, const int32_t* status, double* dist,
+                               hipStream_t st);
+// k-th smallest (1-based) of n doubles -> *out (device); single workgroup radix select
+hipError_t launch_select_kth(int64_t n, const double* v, int64_t k, double* out, hipStream_t st);
+hipError_t launch_accept(int64_t n, const double* dist, const double* tol, uint8_t* acc,
+                         hipStream_t st);
+
+}  // namespace swim

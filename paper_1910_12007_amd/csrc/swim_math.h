@@ -1,0 +1,335 @@
+// swim_math.h -- kernel functions of the regularized Brinkmanlet (Sec. 2.1,
+// eq. BrV) for the device, templated on the working precision.
+//
+// Velocity of point forces F_j at X_j:
+//   u(x) = sum_j [ H1(r) F_j + H2(r) (F_j . d) d ],  d = x - X_j, r = |d|,
+//   H1 = -B'',  H2 = (r B'' - B')/r^3,  (Delta - alpha^2) B = G,  Delta G = phi.
+// Blob reading (the paper defers G, B to its references): with
+// R = sqrt(r^2 + eps^2) and c = 1/(alpha eps K1(alpha eps)),
+//   g = Delta B = -c K0(alpha R)/(2 pi),   M(r) = int_0^r s g ds,
+//   H1 = M/r^2 - g,   H2 = (g - 2 M/r^2)/r^2;  alpha = 0 is the Stokes limit.
+//
+// Evaluation without cancellation.  Write t = r^2, w = alpha^2 R^2 =
+// alpha^2 t + w0 (w0 = alpha^2 eps^2), delta = t/eps^2 and
+// Q(w) = z K1(z) - 1 at z = sqrt(w).  Then
+//   g(t) - g(0) = -(c/2pi) [K0(w) - K0(w0)],
+//   H2 = (c/pi) alpha^2 Q[w0, w, w]   (second divided difference),
+//   H1 = H1(0) + Ht,   Ht = -(g(t) - g(0) + t H2)/2.
+// The constant H1(0) multiplies sum_j F_j and is added once per target.
+// For z <= 2 the ascending series K0 = -1/2 ln(w/4) I0(w) + P0(w),
+// Q = 1/2 ln(w/4) A(w) - B(w) (A&S 9.6.13, 9.6.11) turn these divided
+// differences into
+//   K0(w) - K0(w0) = -1/2 log1p(delta) I0(w) + U(t),
+//   H2 = (c/pi) [ V(t) + (D(w) lambda + Abar(w) S2) / (2 eps^2) ],
+// with lambda = log1p(delta)/delta, S2 = (1 - lambda)/delta (the Stokes
+// part), Abar = A/w, D = A' - Abar, and U, V polynomials in t whose
+// coefficients (Taylor coefficients of I0, P0, A, B at w0, times the log
+// ln(w0/4) where it appears) are computed once per system.  Every term is
+// then a sum of same-signed pieces.  For z > 2 the functions come from
+// K_nu(z) = exp(-z) z^-1/2 f_nu(2/z) with Chebyshev fits f_nu
+// (swim_kfit.h) and the closed form, which no longer cancels there.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "swim_kfit.h"
+
+#define SWIM_HD __host__ __device__ __forceinline__
+
+namespace swim {
+
+constexpr double PI = 3.14159265358979323846;
+constexpr double EULER_GAMMA = 0.57721566490153286061;
+constexpr int NT_MAX = 16;      // per-system polynomial length (max)
+constexpr int NSER_SETUP = 40;  // series length used by the FP64 set-up
+
+// ---------------------------------------------------------------------------
+// compile-time series coefficients
+// ---------------------------------------------------------------------------
+constexpr double fact(int n) { double f = 1.0; for (int i = 2; i <= n; ++i) f *= i; return f; }
+constexpr double pow4(int n) { double p = 1.0; for (int i = 0; i < n; ++i) p *= 4.0; return p; }
+// I0(w) = sum_k w^k / (4^k (k!)^2)
+constexpr double c_I0(int k) { return 1.0 / (pow4(k) * fact(k) * fact(k)); }
+// A(w) = z I1(z) = sum_{m>=1} A_m w^m,  A_m = 2 / (4^m (m-1)! m!)
+constexpr double c_A(int m) { return m < 1 ? 0.0 : 2.0 / (pow4(m) * fact(m - 1) * fact(m)); }
+// Abar(w) = A(w)/w = sum_k A_{k+1} w^k ;  D(w) = A' - Abar = sum_k k A_{k+1} w^k
+constexpr double c_Abar(int k) { return c_A(k + 1); }
+constexpr double c_D(int k) { return k * c_A(k + 1); }
+
+// precision traits: series lengths and thresholds per working type
+template <typename T> struct Prec;
+template <> struct Prec<float> {
+    static constexpr int NW = 9;       // terms of the w-polynomials I0, Abar, D (w <= 4)
+    static constexpr int NT = 10;      // terms of the per-system U, V polynomials
+    static constexpr int NDS = 14;     // terms of the small-delta series
+    static constexpr float DSMALL = 0.25f;
+    static constexpr int NKF = SWIM_KFIT_K0_F32_N;
+};
+template <> struct Prec<double> {
+    static constexpr int NW = 15;
+    static constexpr int NT = 16;
+    static constexpr int NDS = 28;
+    static constexpr double DSMALL = 0.25;
+    static constexpr int NKF = SWIM_KFIT_K0_F64_N;
+};
+
+template <typename T> SWIM_HD T kfit(int nu, T x);
+template <> SWIM_HD float kfit<float>(int nu, float x)
+{
+    // Clenshaw recurrence for sum_j c_j T_j(u), u = 2x - 1
+    const float u = 2.0f * x - 1.0f, u2 = 2.0f * u;
+    float b1 = 0.0f, b2 = 0.0f;
+#pragma unroll
+    for (int j = SWIM_KFIT_K0_F32_N - 1; j >= 1; --j) {
+        const float cj = nu ? (float)swim_kfit_k1_f32[j] : (float)swim_kfit_k0_f32[j];
+        const float b0 = fmaf(u2, b1, cj - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    const float c0 = nu ? (float)swim_kfit_k1_f32[0] : (float)swim_kfit_k0_f32[0];
+    return fmaf(u, b1, c0 - b2);
+}
+template <> SWIM_HD double kfit<double>(int nu, double x)
+{
+    const double u = 2.0 * x - 1.0, u2 = 2.0 * u;
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int j = SWIM_KFIT_K0_F64_N - 1; j >= 1; --j) {
+        const double cj = nu ? swim_kfit_k1_f64[j] : swim_kfit_k0_f64[j];
+        const double b0 = fma(u2, b1, cj - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    const double c0 = nu ? swim_kfit_k1_f64[0] : swim_kfit_k0_f64[0];
+    return fma(u, b1, c0 - b2);
+}
+
+// ---------------------------------------------------------------------------
+// per-system constants
+// ---------------------------------------------------------------------------
+template <typename T> struct alignas(16) SysConst {
+    T a2, e2, inv_e2, half_inv_e2;   // alpha^2, eps^2, 1/eps^2, 1/(2 eps^2)
+    T w0, inv_a2;                    // alpha^2 eps^2, 1/alpha^2 (0 if alpha = 0)
+    T cpi, c2pi;                     // c/pi, c/(2 pi)
+    T K0z0, q0, h1c, pad;            // K0(alpha eps), Q(w0), H1(0)
+    T U[NT_MAX];                     // U(t) = t * sum_n U[n] t^n
+    T V[NT_MAX];                     // V(t) = sum_n V[n] t^n
+};
+
+// FP64 values of K0, K1 and Q at small or large argument (set-up only)
+SWIM_HD void bessel_k01_q_f64(double z, double* K0, double* K1, double* Q)
+{
+    if (z <= 2.0) {
+        const double w = z * z, y = 0.25 * w, L = log(0.25 * w);
+        double I0 = 0, P0 = 0, A = 0, B = 0;
+        double termk = 1.0;          // y^k / (k!)^2
+        double psi1 = -EULER_GAMMA;  // psi(k+1)
+        for (int k = 0; k < NSER_SETUP; ++k) {
+            I0 += termk;
+            P0 += psi1 * termk;
+            // A_m, B_m with m = k + 1:  y^m / ((m-1)! m!) = termk * y / (k+1)
+            const double tm = termk * y / (k + 1);
+            A += 2.0 * tm;
+            B += (psi1 + (psi1 + 1.0 / (k + 1))) * tm;
+            termk *= y / ((double)(k + 1) * (k + 1));
+            psi1 += 1.0 / (k + 1);
+        }
+        *K0 = -0.5 * L * I0 + P0;
+        *Q = 0.5 * L * A - B;
+        *K1 = (1.0 + *Q) / z;
+    } else {
+        const double e = exp(-z) / sqrt(z), x = SWIM_KFIT_ZS / z;
+        *K0 = e * kfit<double>(0, x);
+        *K1 = e * kfit<double>(1, x);
+        *Q = z * *K1 - 1.0;
+    }
+}
+
+// Taylor coefficients at w0 of a power series p(w) = sum_m p_m w^m:
+// phat_n = sum_{m>=n} C(m, n) p_m w0^(m-n)
+SWIM_HD double taylor_at(const double* p, int M, int n, double w0)
+{
+    double s = 0.0, binom = 1.0, wp = 1.0;  // C(m, n), w0^(m-n) for m = n
+    for (int m = n; m < M; ++m) {
+        s += binom * p[m] * wp;
+        binom = binom * (m + 1) / (m + 1 - n);
+        wp *= w0;
+    }
+    return s;
+}
+
+// Computes the constants of one system in FP64 and rounds them to T.
+// Requires alpha >= 0, eps > 0, alpha * eps <= 1 (checked by the caller).
+template <typename T> SWIM_HD void sysconst_compute(double alpha, double eps, SysConst<T>* out)
+{
+    const double a2 = alpha * alpha, e2 = eps * eps, w0 = a2 * e2;
+    SysConst<T> C;
+    C.a2 = (T)a2;
+    C.e2 = (T)e2;
+    C.inv_e2 = (T)(1.0 / e2);
+    C.half_inv_e2 = (T)(0.5 / e2);
+    C.w0 = (T)w0;
+    C.pad = (T)0;
+    for (int n = 0; n < NT_MAX; ++n) { C.U[n] = (T)0; C.V[n] = (T)0; }
+    if (alpha == 0.0) {
+        C.inv_a2 = (T)0;
+        C.cpi = (T)(1.0 / PI);
+        C.c2pi = (T)(0.5 / PI);
+        C.K0z0 = (T)0;
+        C.q0 = (T)0;
+        C.h1c = (T)(-log(eps) / (4.0 * PI));
+        *out = C;
+        return;
+    }
+    const double z0 = alpha * eps;
+    double K0, K1, Q0;
+    bessel_k01_q_f64(z0, &K0, &K1, &Q0);
+    const double c = 1.0 / (z0 * K1);
+    C.inv_a2 = (T)(1.0 / a2);
+    C.cpi = (T)(c / PI);
+    C.c2pi = (T)(0.5 * c / PI);
+    C.K0z0 = (T)K0;
+    C.q0 = (T)Q0;
+    C.h1c = (T)(c * K0 / (4.0 * PI));
+    // power-series coefficients of I0, P0, A, B in w
+    double pI0[NSER_SETUP], pP0[NSER_SETUP], pA[NSER_SETUP], pB[NSER_SETUP];
+    double psi = -EULER_GAMMA;  // psi(k+1)
+    for (int k = 0; k < NSER_SETUP; ++k) {
+        const double ik = 1.0 / (pow4(k) * fact(k) * fact(k));
+        pI0[k] = ik;
+        pP0[k] = psi * ik;
+        if (k == 0) {
+            pA[0] = 0.0;
+            pB[0] = 0.0;
+        } else {
+            const double am = 1.0 / (pow4(k) * fact(k - 1) * fact(k));  // 1/(4^m (m-1)! m!), m = k
+            const double psim = psi;                                      // psi(m+1) with m = k
+            const double psim0 = psi - 1.0 / k;                           // psi(m)
+            pA[k] = 2.0 * am;
+            pB[k] = (psim0 + psim) * am;
+        }
+        psi += 1.0 / (k + 1);
+    }
+    const double L0 = log(0.25 * w0);
+    // U(t) = sum_{n>=1} [-L0/2 I0hat_n + P0hat_n] a2^n t^n,  stored as U[n-1]
+    // V(t) = sum_{n>=2} (n-1) [L0/2 Ahat_n - Bhat_n] a2^(n-1) t^(n-2), stored as V[n-2]
+    double a2n = a2;  // a2^n for n = 1
+    for (int n = 1; n <= NT_MAX; ++n) {
+        const double u = -0.5 * L0 * taylor_at(pI0, NSER_SETUP, n, w0) + taylor_at(pP0, NSER_SETUP, n, w0);
+        C.U[n - 1] = (T)(u * a2n);
+        a2n *= a2;
+    }
+    double a2m = a2;  // a2^(n-1) for n = 2
+    for (int n = 2; n < NT_MAX + 2; ++n) {
+        const double v = (n - 1) * (0.5 * L0 * taylor_at(pA, NSER_SETUP, n, w0) - taylor_at(pB, NSER_SETUP, n, w0));
+        C.V[n - 2] = (T)(v * a2m);
+        a2m *= a2;
+    }
+    *out = C;
+}
+
+// ---------------------------------------------------------------------------
+// per-pair kernel values:  Ht = H1(t) - H1(0),  H2(t)
+// t = 0 returns Ht = 0 and a finite H2 (the pair contributes nothing then).
+// ---------------------------------------------------------------------------
+SWIM_HD float log1p_t(float x) { return log1pf(x); }
+SWIM_HD double log1p_t(double x) { return log1p(x); }
+SWIM_HD float exp_t(float x) { return expf(x); }
+SWIM_HD double exp_t(double x) { return exp(x); }
+SWIM_HD float sqrt_t(float x) { return sqrtf(x); }
+SWIM_HD double sqrt_t(double x) { return sqrt(x); }
+SWIM_HD float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+SWIM_HD double fma_t(double a, double b, double c) { return fma(a, b, c); }
+
+template <typename T, int N>
+SWIM_HD T horner_const(T x, double (*cf)(int))
+{
+    T s = (T)cf(N - 1);
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) s = fma_t(s, x, (T)cf(k));
+    return s;
+}
+
+template <typename T, int N>
+SWIM_HD T horner_arr(T x, const T* c)
+{
+    T s = c[N - 1];
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) s = fma_t(s, x, c[k]);
+    return s;
+}
+
+template <typename T>
+SWIM_HD void kernel_small_z(const SysConst<T>& C, T t, T w, T& Ht, T& H2)
+{
+    using P = Prec<T>;
+    const T delta = t * C.inv_e2;
+    // delta = 0 is the self pair: its value is multiplied by zero, so lambda
+    // and S2 are taken at the clamped delta; 0 < delta < DSMALL (near contact,
+    // rare) sums their series instead of cancelling.
+    const T dc = delta >= (T)P::DSMALL ? delta : (T)P::DSMALL;
+    const T lc = log1p_t(dc);
+    T ell, lam, S2;
+    if (delta >= (T)P::DSMALL || delta == (T)0) {
+        ell = delta == (T)0 ? (T)0 : lc;
+        const T rd = (T)1 / dc;
+        lam = lc * rd;
+        S2 = ((T)1 - lam) * rd;
+    } else {
+        ell = log1p_t(delta);
+        // lambda = sum (-d)^m/(m+1),  S2 = sum (-d)^m/(m+2)
+        T a = (T)0, b = (T)0;
+#pragma unroll
+        for (int m = P::NDS - 1; m >= 0; --m) {
+            a = fma_t(a, -delta, (T)1 / (T)(m + 1));
+            b = fma_t(b, -delta, (T)1 / (T)(m + 2));
+        }
+        lam = a;
+        S2 = b;
+    }
+    // global w-polynomials
+    T I0w = (T)c_I0(P::NW - 1), Ab = (T)c_Abar(P::NW - 1), Dw = (T)c_D(P::NW - 1);
+#pragma unroll
+    for (int k = P::NW - 2; k >= 0; --k) {
+        I0w = fma_t(I0w, w, (T)c_I0(k));
+        Ab = fma_t(Ab, w, (T)c_Abar(k));
+        Dw = fma_t(Dw, w, (T)c_D(k));
+    }
+    const T Ut = t * horner_arr<T, P::NT>(t, C.U);
+    const T Vt = horner_arr<T, P::NT>(t, C.V);
+    H2 = C.cpi * fma_t(C.half_inv_e2, fma_t(Dw, lam, Ab * S2), Vt);
+    const T gt = -C.c2pi * fma_t((T)-0.5 * ell, I0w, Ut);
+    Ht = (T)-0.5 * fma_t(t, H2, gt);
+}
+
+template <typename T>
+SWIM_HD void kernel_large_z(const SysConst<T>& C, T t, T w, T& Ht, T& H2)
+{
+    const T z = sqrt_t(w);
+    const T rz = (T)1 / z;
+    const T e = exp_t(-z) * sqrt_t(rz);
+    const T x = (T)SWIM_KFIT_ZS * rz;
+    const T K0 = e * kfit<T>(0, x);
+    const T K1 = e * kfit<T>(1, x);
+    const T g = -C.c2pi * K0;
+    const T gt = -C.c2pi * (K0 - C.K0z0);
+    const T q = fma_t(z, K1, (T)-1);
+    const T rt = (T)1 / t;
+    const T Mt = C.c2pi * (q - C.q0) * C.inv_a2 * rt;  // M(r)/r^2
+    H2 = (g - (T)2 * Mt) * rt;
+    Ht = (T)-0.5 * fma_t(t, H2, gt);
+}
+
+template <typename T>
+SWIM_HD void kernel_eval(const SysConst<T>& C, T t, T& Ht, T& H2)
+{
+    const T w = fma_t(C.a2, t, C.w0);
+    if (w <= (T)(SWIM_KFIT_ZS * SWIM_KFIT_ZS))
+        kernel_small_z<T>(C, t, w, Ht, H2);
+    else
+        kernel_large_z<T>(C, t, w, Ht, H2);
+}
+
+}  // namespace swim

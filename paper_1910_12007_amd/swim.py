@@ -1,0 +1,229 @@
+"""Thin ctypes binding of libswim (include/swim.h).
+
+Functions carry the C names and only marshal arguments: device arrays are
+torch tensors on the HIP device (their data pointers are passed), host arrays
+are numpy arrays.  Every computation happens inside libswim.so; there is no
+Python or CPU fallback -- if the library is missing, loading raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswim.so")
+
+SWIM_OK, SWIM_EINVAL, SWIM_EHIP, SWIM_ENOMEM, SWIM_ESTATE = 0, -1, -2, -3, -4
+SWIM_F32, SWIM_F64 = 0, 1
+SWIM_ST_OK, SWIM_ST_NONFINITE, SWIM_ST_BOUND, SWIM_ST_BADPARAM = 0, 1, 2, 3
+SWIM_NPARAM = 9
+
+_c = ctypes
+_P = _c.c_void_p
+_I64P = _c.POINTER(_c.c_int64)
+_I32P = _c.POINTER(_c.c_int32)
+_DP = _c.POINTER(_c.c_double)
+_U8P = _c.POINTER(_c.c_uint8)
+
+# name -> (restype, argtypes); mirrors include/swim.h
+SIGNATURES = {
+    "swim_create": (_c.c_int, [_c.POINTER(_P), _c.c_int]),
+    "swim_destroy": (None, [_P]),
+    "swim_last_error": (_c.c_char_p, []),
+    "swim_version": (_c.c_int, []),
+    "swim_pair_velocity": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I64P, _DP, _DP, _P, _P, _P, _P, _P, _P, _P]),
+    "swim_elastic_forces": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I32P, _DP, _c.c_double, _P, _P, _P, _P, _P]),
+    "swim_forward": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I32P, _I32P, _P, _c.c_int32, _c.c_double,
+                                _c.c_int32, _c.c_double, _P, _P, _P, _P, _P]),
+    "abc_distance": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _c.c_int32, _P, _P, _P, _P, _P]),
+    "abc_select": (_c.c_int, [_P, _c.c_int64, _P, _c.c_double, _P, _P, _P]),
+    "abc_prior_draw": (_c.c_int, [_c.c_uint64, _c.c_int64, _c.c_int32, _DP, _DP, _DP]),
+    "abc_pmc_propose": (_c.c_int, [_c.c_uint64, _c.c_int32, _c.c_int64, _DP, _DP, _c.c_int64, _DP, _DP, _DP]),
+    "abc_pmc_weights": (_c.c_int, [_c.c_int64, _DP, _U8P, _DP, _DP, _c.c_int64, _DP]),
+    "abc_step": (_c.c_int, [_P, _P, _DP, _c.c_int32, _c.c_int64, _I32P, _c.c_uint64, _c.c_int32, _DP, _DP,
+                            _c.c_int64, _c.c_double, _DP, _DP, _U8P, _DP, _DP]),
+    "swim_kernel_eval_host": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_double, _c.c_int64, _DP, _DP, _DP, _DP]),
+}
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libswim.so not built ({LIB_PATH}); run `python -m paper_1910_12007_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+class SwimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libswim error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != SWIM_OK:
+        raise SwimError(rc, lib().swim_last_error().decode())
+    return rc
+
+
+class abc_model(ctypes.Structure):
+    _fields_ = [("lo", _c.c_double * 3), ("hi", _c.c_double * 3), ("b", _c.c_double), ("omega", _c.c_double),
+                ("k", _c.c_double), ("steps", _c.c_int32), ("obs_every", _c.c_int32), ("dt", _c.c_double),
+                ("eps_over_ds", _c.c_double), ("dtype", _c.c_int32), ("use_graph", _c.c_int32)]
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return _P(t.data_ptr())
+
+
+def _stream(s):
+    if s is None:
+        return None
+    return _P(s.cuda_stream if hasattr(s, "cuda_stream") else int(s))
+
+
+def _h(a, dtype, ptr):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ptr)
+
+
+def dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return SWIM_F32
+    if t.dtype == torch.float64:
+        return SWIM_F64
+    raise ValueError("dtype must be float32 or float64")
+
+
+class Context:
+    """Owns one swim_ctx."""
+
+    def __init__(self, device=0):
+        h = _P()
+        _check(lib().swim_create(ctypes.byref(h), int(device)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().swim_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def swim_pair_velocity(ctx, sys_off, alpha, eps, x, y, fx, fy, ux, uy, stream=None):
+    so, so_p = _h(sys_off, np.int64, _I64P)
+    a, a_p = _h(alpha, np.float64, _DP)
+    e, e_p = _h(eps, np.float64, _DP)
+    return _check(lib().swim_pair_velocity(ctx.handle, dtype_code(x), len(a), so_p, a_p, e_p, _dptr(x), _dptr(y),
+                                           _dptr(fx), _dptr(fy), _dptr(ux), _dptr(uy), _stream(stream)))
+
+
+def swim_elastic_forces(ctx, N, params, t, x, y, fx, fy, stream=None):
+    n, n_p = _h(N, np.int32, _I32P)
+    P, P_p = _h(params, np.float64, _DP)
+    return _check(lib().swim_elastic_forces(ctx.handle, dtype_code(x), len(n), n_p, P_p, float(t), _dptr(x),
+                                            _dptr(y), _dptr(fx), _dptr(fy), _stream(stream)))
+
+
+def swim_forward(ctx, N, n_swim, params, steps, dt, obs_every, eps_over_ds, obs, speed, status, steps_done=None,
+                 stream=None):
+    n, n_p = _h(N, np.int32, _I32P)
+    if n_swim is None:
+        ns_p = None
+    else:
+        ns, ns_p = _h(n_swim, np.int32, _I32P)
+    return _check(lib().swim_forward(ctx.handle, dtype_code(speed), len(n), n_p, ns_p, _dptr(params), int(steps),
+                                     float(dt), int(obs_every), float(eps_over_ds), _dptr(obs), _dptr(speed),
+                                     _dptr(status), _dptr(steps_done), _stream(stream)))
+
+
+def abc_distance(ctx, obs, data, status, dist, stream=None):
+    n, n_obs = obs.shape[0], obs.shape[1]
+    return _check(lib().abc_distance(ctx.handle, dtype_code(obs), n, n_obs, _dptr(obs), _dptr(data),
+                                     _dptr(status), _dptr(dist), _stream(stream)))
+
+
+def abc_select(ctx, dist, q, tol, accept=None, stream=None):
+    return _check(lib().abc_select(ctx.handle, dist.numel(), _dptr(dist), float(q), _dptr(tol), _dptr(accept),
+                                   _stream(stream)))
+
+
+def abc_prior_draw(seed, n, lo, hi):
+    lo_, lo_p = _h(lo, np.float64, _DP)
+    hi_, hi_p = _h(hi, np.float64, _DP)
+    out = np.empty((n, len(lo_)))
+    _check(lib().abc_prior_draw(int(seed), int(n), len(lo_), lo_p, hi_p, out.ctypes.data_as(_DP)))
+    return out
+
+
+def abc_pmc_propose(seed, generation, n, prev_theta, prev_w, lo, hi):
+    pt, pt_p = _h(prev_theta, np.float64, _DP)
+    pw, pw_p = _h(prev_w, np.float64, _DP)
+    lo_, lo_p = _h(lo, np.float64, _DP)
+    hi_, hi_p = _h(hi, np.float64, _DP)
+    out = np.empty((n, 3))
+    _check(lib().abc_pmc_propose(int(seed), int(generation), int(n), pt_p, pw_p, pt.shape[0], lo_p, hi_p,
+                                 out.ctypes.data_as(_DP)))
+    return out
+
+
+def abc_pmc_weights(theta, accept, prev_theta, prev_w):
+    th, th_p = _h(theta, np.float64, _DP)
+    ac, ac_p = _h(accept, np.uint8, _U8P)
+    pt, pt_p = _h(prev_theta, np.float64, _DP)
+    pw, pw_p = _h(prev_w, np.float64, _DP)
+    w = np.empty(th.shape[0])
+    _check(lib().abc_pmc_weights(th.shape[0], th_p, ac_p, pt_p, pw_p, pt.shape[0], w.ctypes.data_as(_DP)))
+    return w
+
+
+def abc_step(ctx, model, data, N, seed, generation, q, prev_theta=None, prev_w=None):
+    d, d_p = _h(data, np.float64, _DP)
+    n_, n_p = _h(N, np.int32, _I32P)
+    n = len(n_)
+    if prev_theta is None:
+        pt_p = pw_p = None
+        n_prev = 0
+    else:
+        pt, pt_p = _h(prev_theta, np.float64, _DP)
+        pw, pw_p = _h(prev_w, np.float64, _DP)
+        n_prev = pt.shape[0]
+    theta = np.empty((n, 3))
+    dist = np.empty(n)
+    acc = np.empty(n, dtype=np.uint8)
+    w = np.empty(n)
+    tol = np.empty(1)
+    _check(lib().abc_step(ctx.handle, ctypes.byref(model), d_p, d.shape[0], n, n_p, int(seed), int(generation),
+                          pt_p, pw_p, n_prev, float(q), theta.ctypes.data_as(_DP), dist.ctypes.data_as(_DP),
+                          acc.ctypes.data_as(_U8P), w.ctypes.data_as(_DP), tol.ctypes.data_as(_DP)))
+    return dict(theta=theta, dist=dist, accept=acc.astype(bool), w=w, tol=float(tol[0]))
+
+
+def swim_kernel_eval_host(dtype, alpha, eps, t):
+    t_, t_p = _h(t, np.float64, _DP)
+    h1t, h2 = np.empty_like(t_), np.empty_like(t_)
+    h1c = ctypes.c_double()
+    _check(lib().swim_kernel_eval_host(int(dtype), float(alpha), float(eps), t_.size, t_p,
+                                       h1t.ctypes.data_as(_DP), h2.ctypes.data_as(_DP), ctypes.byref(h1c)))
+    return h1t, h2, h1c.value

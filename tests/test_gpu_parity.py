@@ -1,0 +1,231 @@
+"""GPU parity of libswim against the FP64 oracle (run on an MI355X).
+
+Tolerances (norm-wise relative, over the whole vector of one evaluation):
+  velocity sum, FP64 build  1e-12;  FP32 build 1e-5
+  head-displacement series of a forward run, FP64 1e-12;  FP32 1e-4 (plus
+  one FP32 ulp of each stored head position, the outputs' own rounding)
+  elastic forces from FP32 positions: 1e-4 (the strain l/ds - 1 of a spring
+  is a difference of O(1) numbers; at strains ~1e-3 a few ulp of l become
+  ~1e-4 of the tension), FP64 1e-11.
+Inputs are rounded to the kernel's precision first and the oracle gets the
+same rounded values.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1910_12007_amd import inputs, swim  # noqa: E402
+
+DT = {swim.SWIM_F32: torch.float32, swim.SWIM_F64: torch.float64}
+NP = {swim.SWIM_F32: np.float32, swim.SWIM_F64: np.float64}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = swim.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _systems():
+    """(N, n_swim, alpha) of one multi-system call: ragged sizes across the
+    256-point tiles, several swimmers in one fluid, Stokes to alpha = 10."""
+    return [(64, 1, 1.0), (128, 1, 0.0), (300, 1, 2.0), (96, 3, 1e-3), (200, 2, 10.0), (520, 1, 5.0)]
+
+
+@pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-12), (swim.SWIM_F32, 1e-5)])
+def test_pair_velocity_matches_oracle(ctx, oracle_core, dtype, tol):
+    xs, ys, fxs, fys, off, alphas, epss = [], [], [], [], [0], [], []
+    for k, (N, nsw, a) in enumerate(_systems()):
+        x, y = inputs.filament_geometry(N, seed=10 + k, n_swim=nsw)
+        fx, fy = inputs.force_pattern(N, seed=20 + k, n_swim=nsw)
+        xs.append(x); ys.append(y); fxs.append(fx); fys.append(fy)
+        off.append(off[-1] + N * nsw)
+        alphas.append(a)
+        epss.append(1.5 / (N - 1))
+    X, Y, FX, FY = (np.concatenate(v).astype(NP[dtype]) for v in (xs, ys, fxs, fys))
+    td = DT[dtype]
+    ux = torch.empty(len(X), dtype=td, device="cuda")
+    uy = torch.empty_like(ux)
+    swim.swim_pair_velocity(ctx, np.array(off), alphas, epss, dev(X, td), dev(Y, td), dev(FX, td), dev(FY, td), ux, uy)
+    torch.cuda.synchronize()
+    gx, gy = ux.cpu().double().numpy(), uy.cpu().double().numpy()
+    for s in range(len(alphas)):
+        sl = slice(off[s], off[s + 1])
+        ox, oy = oracle_core.velocity(X[sl], Y[sl], FX[sl], FY[sl], alphas[s], epss[s])
+        e = rel(np.concatenate([gx[sl], gy[sl]]), np.concatenate([ox, oy]))
+        assert e < tol, (s, _systems()[s], e)
+
+
+@pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-11), (swim.SWIM_F32, 1e-4)])
+def test_elastic_forces_match_oracle(ctx, oracle_core, dtype, tol):
+    Ns = [5, 64, 127, 300]
+    rows, xs, ys = [], [], []
+    for k, N in enumerate(Ns):
+        x, y = inputs.filament_geometry(N, seed=30 + k)
+        xs.append(x); ys.append(y)
+        rows.append(inputs.param_rows(1, Sb=0.1 * (k + 1), Ss=300.0 * (k + 1), phase=0.3 * k)[0])
+    P = np.array(rows)
+    X, Y = (np.concatenate(v).astype(NP[dtype]) for v in (xs, ys))
+    td = DT[dtype]
+    fx = torch.empty(len(X), dtype=td, device="cuda")
+    fy = torch.empty_like(fx)
+    t = 0.0123
+    swim.swim_elastic_forces(ctx, Ns, P, t, dev(X, td), dev(Y, td), fx, fy)
+    torch.cuda.synchronize()
+    gx, gy = fx.cpu().double().numpy(), fy.cpu().double().numpy()
+    o = 0
+    for k, N in enumerate(Ns):
+        sl = slice(o, o + N)
+        k0 = oracle_core.kappa0(N, P[k, 3], P[k, 5], P[k, 4], P[k, 6], t)
+        ox, oy = oracle_core.forces(X[sl], Y[sl], P[k, 1], P[k, 2], k0)
+        assert rel(np.concatenate([gx[sl], gy[sl]]), np.concatenate([ox, oy])) < tol, (N,)
+        o += N
+
+
+def run_forward(ctx, dtype, N, n_swim, P, steps, dt, obs_every):
+    td = DT[dtype]
+    N = np.atleast_1d(np.asarray(N, np.int32))
+    nfil = P.shape[0]
+    n_obs = steps // obs_every
+    obs = torch.full((nfil, n_obs, 2), float("nan"), dtype=td, device="cuda")
+    speed = torch.empty(nfil, dtype=td, device="cuda")
+    status = torch.empty(len(N), dtype=torch.int32, device="cuda")
+    swim.swim_forward(ctx, N, n_swim, dev(P, torch.float64), steps, dt, obs_every, 1.5, obs, speed, status)
+    torch.cuda.synchronize()
+    return obs.cpu().double().numpy(), speed.cpu().double().numpy(), status.cpu().numpy()
+
+
+def disp_err(obs, ref, x0):
+    """relative error of the head-displacement series (positions minus the
+    initial head position)."""
+    return rel(obs - x0, ref - x0)
+
+
+def check_traj(obs, ref, x0, tol, dtype):
+    """|obs - ref| <= tol |ref - x0| (+ one ulp of every stored position for
+    FP32 outputs, whose own rounding is not an error of the run)."""
+    err = np.linalg.norm(np.ravel(obs - ref))
+    allow = tol * np.linalg.norm(np.ravel(ref - x0))
+    if dtype == swim.SWIM_F32:
+        allow += np.linalg.norm(np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64))
+    assert err <= allow, (err, allow, disp_err(obs, ref, x0))
+
+
+@pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-12), (swim.SWIM_F32, 1e-4)])
+@pytest.mark.parametrize("alpha", [1.0, 0.0])
+def test_single_swimmer_run_matches_oracle(ctx, oracle_core, dtype, tol, alpha):
+    """N = 64, 2000 steps of dt = 1e-4, S_b = 0.1, S_s = 1e3, b = 0.1, k = omega = 2 pi."""
+    P = inputs.param_rows(1, alpha=alpha)
+    obs, speed, st = run_forward(ctx, dtype, [64], None, P, 2000, 1e-4, 100)
+    ref = oracle_core.forward(P, 64, 2000, 1e-4, 100)
+    assert st[0] == 0 and ref["status"] == 0
+    check_traj(obs[0], ref["obs"][0], np.array([1.0, 0.0]), tol, dtype)
+    assert abs(speed[0] / ref["speed"][0] - 1) < tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-12), (swim.SWIM_F32, 1e-4)])
+def test_uneven_batch_matches_oracle(ctx, oracle_core, dtype, tol):
+    """Systems of 64 to 512 points (every persistent-kernel bucket), 60 steps.
+    The heads start at the origin (x0 = -1): the run is short enough for the
+    head to move ~1e-5, which FP32 outputs resolve only near zero."""
+    Ns = [64, 96, 160, 200, 256, 320, 448, 512, 128, 64]
+    rng = np.random.Generator(np.random.PCG64(41))
+    P = inputs.param_rows(len(Ns), Sb=0.01, Ss=100.0, x0=-1.0)
+    P[:, 0] = rng.uniform(0, 10, len(Ns))
+    P[1, 0] = 0.0
+    steps, dt = 60, 2e-6
+    obs, speed, st = run_forward(ctx, dtype, Ns, None, P, steps, dt, 20)
+    for i, N in enumerate(Ns):
+        ref = oracle_core.forward(P[i:i + 1], N, steps, dt, 20)
+        assert st[i] == 0 and ref["status"] == 0
+        check_traj(obs[i], ref["obs"][0], np.array([0.0, 0.0]), tol, dtype)
+
+
+@pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-12), (swim.SWIM_F32, 1e-4)])
+def test_multi_swimmer_systems_match_oracle(ctx, oracle_core, dtype, tol):
+    """Interacting swimmers: a 3 x 64 system (persistent kernel) and an
+    8 x 80 system (per-step kernel with targets split over workgroups), on a
+    grid centred at the origin, 100 steps of dt = 5e-5."""
+    lay = inputs.dense_layout(n_samples=2, seed=5)
+    P1 = lay[0][:3].copy()
+    P1[:, 0] = 2.5
+    P2 = lay[1].copy()
+    P2[:, 0] = 0.7
+    for Q in (P1, P2):
+        Q[:, 7] -= 2.75
+        Q[:, 8] -= 0.75
+    P = np.vstack([P1, P2])
+    steps, dt = 100, 5e-5
+    obs, speed, st = run_forward(ctx, dtype, [64, 80], [3, 8], P, steps, dt, 50)
+    assert list(st) == [0, 0]
+    r1 = oracle_core.forward(P1, 64, steps, dt, 50)
+    r2 = oracle_core.forward(P2, 80, steps, dt, 50)
+    for m in range(3):
+        check_traj(obs[m], r1["obs"][m], np.array([P1[m, 7] + 1.0, P1[m, 8]]), tol, dtype)
+    for m in range(8):
+        check_traj(obs[3 + m], r2["obs"][m], np.array([P2[m, 7] + 1.0, P2[m, 8]]), tol, dtype)
+
+
+def test_blowup_and_bad_parameters_are_statuses(ctx):
+    P = inputs.param_rows(3, alpha=2.0)
+    P[0, 1], P[0, 2] = 1.0, 1e4      # beyond the explicit-Euler bound at N = 128
+    P[2, 0] = 1000.0                  # alpha * eps > 1
+    obs, speed, st = run_forward(ctx, swim.SWIM_F32, [128, 128, 128], None, P, 400, 5e-5, 100)
+    assert st[0] in (swim.SWIM_ST_NONFINITE, swim.SWIM_ST_BOUND)
+    assert st[1] == swim.SWIM_ST_OK
+    assert st[2] == swim.SWIM_ST_BADPARAM
+    assert np.isnan(speed[0]) and np.isnan(speed[2]) and np.isfinite(speed[1])
+    assert np.all(np.isnan(obs[2])) and np.all(np.isfinite(obs[1]))
+
+
+def test_argument_errors(ctx):
+    x = torch.zeros(4, dtype=torch.float32, device="cuda")
+    with pytest.raises(swim.SwimError):
+        swim.swim_pair_velocity(ctx, [0, 4], [1.0], [-0.1], x, x, x, x, x, x)
+    with pytest.raises(swim.SwimError):
+        swim.swim_pair_velocity(ctx, [0, 4], [100.0], [0.1], x, x, x, x, x, x)
+    P = dev(inputs.param_rows(1), torch.float64)
+    with pytest.raises(swim.SwimError):
+        swim.swim_forward(ctx, [2], None, P, 10, 1e-4, 1, 1.5, x, x[:1], torch.zeros(1, dtype=torch.int32,
+                                                                                         device="cuda"))
+    with pytest.raises(swim.SwimError):
+        swim.swim_forward(ctx, [64], None, P, 0, 1e-4, 1, 1.5, x, x[:1], torch.zeros(1, dtype=torch.int32,
+                                                                                          device="cuda"))
+
+
+def test_abc_distance_and_select_match_oracle(ctx):
+    from oracle import abc
+    rng = np.random.Generator(np.random.PCG64(8))
+    n, n_obs = 5000, 50
+    data = rng.standard_normal((n_obs, 2))
+    obs = (data[None] + rng.standard_normal((n, n_obs, 2)) * rng.uniform(0.01, 1, (n, 1, 1))).astype(np.float32)
+    status = np.zeros(n, np.int32)
+    status[::97] = 1
+    obs[5, 3, 0] = np.nan
+    dist = torch.empty(n, dtype=torch.float64, device="cuda")
+    swim.abc_distance(ctx, dev(obs, torch.float32), dev(data, torch.float64), dev(status, torch.int32), dist)
+    tol = torch.empty(1, dtype=torch.float64, device="cuda")
+    acc = torch.empty(n, dtype=torch.uint8, device="cuda")
+    swim.abc_select(ctx, dist, 0.05, tol, acc)
+    torch.cuda.synchronize()
+    ref = abc.distance(np.where(status[:, None, None] != 0, np.nan, obs.astype(np.float64)), data)
+    got = dist.cpu().numpy()
+    np.testing.assert_allclose(got[np.isfinite(ref)], ref[np.isfinite(ref)], rtol=1e-14)
+    assert np.array_equal(np.isinf(got), np.isinf(ref))
+    # the tolerance is an order statistic of the GPU distances: compare exactly
+    assert tol.item() == abc.tolerance(got, 0.05)
+    assert np.array_equal(acc.cpu().numpy().astype(bool), abc.accept(got, tol.item()))
