@@ -63,6 +63,7 @@ def main():
     ap.add_argument("--euler-steps", type=int, default=5000)
     ap.add_argument("--cpu-steps", type=int, default=1200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--wps", type=int, default=0, help="waves per system (0: library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the swimmer batches are "
@@ -74,7 +75,8 @@ def main():
     from paper_1910_12007_amd import inputs, swim
 
     ctx = swim.Context(0)
-    stream = torch.cuda.current_stream()
+    # a stream of our own: the library runs on it and the events time it
+    stream = torch.cuda.Stream()
     n, N, steps, dt, obs_every = args.n, 128, args.euler_steps, 5e-5, 100
     n_obs = steps // obs_every
     theta = swim.abc_prior_draw(1, n, inputs.PRIOR_LO, inputs.PRIOR_HI)
@@ -102,6 +104,8 @@ def main():
         swim.abc_distance(ctx, obs, data, status, dist, stream=stream)
         swim.abc_select(ctx, dist, 0.05, tol, acc, stream=stream)
 
+    if args.wps:
+        swim.swim_set_option(ctx, swim.SWIM_OPT_WPS, args.wps)
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -141,7 +145,7 @@ def main():
         "runs_stopped": int(np.sum(st != 0)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_forward<float,2> (persistent forward run)",
+                     "kernel": "k_forward<float,2,wps> (persistent forward run)",
                      "kernel_ms": fwd_ms, "flop_per_pair": FLOP_PER_PAIR},
     }
     if not args.no_cpu:

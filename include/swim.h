@@ -78,6 +78,19 @@ void swim_destroy(swim_ctx *ctx);
 const char *swim_last_error(void);
 int swim_version(void);
 
+/* Launch-shape options of a context (the autotuner sets them):
+ *   SWIM_OPT_WPS     wavefronts that share one system in the persistent
+ *                    kernel, splitting its sources: 0 (automatic), 1, 2, 4,
+ *                    8, 16 (reduced when the partial sums would not fit LDS);
+ *   SWIM_OPT_BIG_TPL targets per lane of the large-system kernel:
+ *                    0 (automatic), 1, 2, 4.
+ * Results do not depend on the options beyond rounding of the source-split
+ * partial sums.  SWIM_EINVAL for an unknown key or value. */
+#define SWIM_OPT_WPS 1
+#define SWIM_OPT_BIG_TPL 2
+int swim_set_option(swim_ctx *ctx, int32_t key, int32_t value);
+int swim_get_option(swim_ctx *ctx, int32_t key, int32_t *value);
+
 /* One evaluation of the dense velocity sum of eq. (BrV), Sec. 2.1:
  *   u_i = sum_j [ H1(r_ij) F_j + H2(r_ij) (F_j . x_ij) x_ij ],
  * x_ij = X_i - X_j, over all points j of the system of i (self term

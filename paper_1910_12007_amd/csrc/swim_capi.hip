@@ -34,10 +34,15 @@ int fail(int code, const char* fmt, ...)
     return code;
 }
 
+// A failed HIP call is reported through the return code; HIP's per-thread
+// last-error state is cleared so later, unrelated HIP users do not see it.
 #define HIPCHK(call)                                                                       \
     do {                                                                                   \
         hipError_t e_ = (call);                                                            \
-        if (e_ != hipSuccess) return fail(SWIM_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+        if (e_ != hipSuccess) {                                                            \
+            (void)hipGetLastError();                                                       \
+            return fail(SWIM_EHIP, "%s: %s", #call, hipGetErrorString(e_));                \
+        }                                                                                  \
     } while (0)
 
 #define TRY(expr)                 \
@@ -62,6 +67,8 @@ struct swim_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int num_cu = 0;
+    int opt_wps = 0;      // waves per system in the persistent kernel (0: automatic)
+    int opt_big_tpl = 0;  // targets per lane of the large-system kernel (0: automatic)
     DevBuf buf[B_NBUF];
     void* pinned = nullptr;
     size_t pinned_cap = 0, pin_off = 0;
@@ -285,7 +292,7 @@ int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
         order.insert(order.end(), v.begin(), v.end());
     }
     // large systems: target blocks of 256 * tpl_big points
-    const int tpl_big = 1;
+    const int tpl_big = c->opt_big_tpl ? c->opt_big_tpl : 1;
     std::vector<int64_t> blk_s, blk_f;
     for (int64_t s : big_list)
         for (int64_t f = 0; f < pts[s]; f += 256 * tpl_big) {
@@ -323,13 +330,14 @@ int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
         const int tpl = bucket_span[k].first;
         const int64_t start = bucket_span[k].second;
         const int64_t count = (k + 1 < bucket_span.size() ? bucket_span[k + 1].second : (int64_t)order.size()) - start;
-        const int wpb = 4;
-        const int per_cu = forward_blocks_per_cu(dtype, tpl, wpb);
-        const int64_t need = (count + wpb - 1) / wpb;
-        const int nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * c->num_cu));
+        int wps = c->opt_wps ? c->opt_wps : 16;
+        // the wave partial sums of one system must fit the LDS
+        while (wps > 1 && forward_lds_bytes(dtype, tpl, wps) > 160 * 1024) wps /= 2;
+        const int per_cu = forward_blocks_per_cu(dtype, tpl, wps);
+        const int nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(count, (int64_t)per_cu * c->num_cu));
         Batch bk = b;
         bk.n_sys = count;
-        HIPCHK(launch_forward(dtype, tpl, wpb, nblocks, bk, run, (const int32_t*)c->buf[B_ORDER].p + start,
+        HIPCHK(launch_forward(dtype, tpl, wps, nblocks, bk, run, (const int32_t*)c->buf[B_ORDER].p + start,
                               (int32_t*)c->buf[B_QUEUE].p + k, obs, speed, status, steps_done, st));
     }
     if (!big_list.empty()) {
@@ -401,6 +409,31 @@ void swim_destroy(swim_ctx* c)
     if (c->up_ev) (void)hipEventDestroy(c->up_ev);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
+}
+
+int swim_set_option(swim_ctx* c, int32_t key, int32_t value)
+{
+    if (!c) return fail(SWIM_EINVAL, "null context");
+    if (key == SWIM_OPT_WPS) {
+        if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+            return fail(SWIM_EINVAL, "waves per system must be 0, 1, 2, 4, 8 or 16");
+        c->opt_wps = value;
+    } else if (key == SWIM_OPT_BIG_TPL) {
+        if (value != 0 && value != 1 && value != 2 && value != 4) return fail(SWIM_EINVAL, "targets per lane must be 0, 1, 2 or 4");
+        c->opt_big_tpl = value;
+    } else {
+        return fail(SWIM_EINVAL, "unknown option %d", key);
+    }
+    return SWIM_OK;
+}
+
+int swim_get_option(swim_ctx* c, int32_t key, int32_t* value)
+{
+    if (!c || !value) return fail(SWIM_EINVAL, "null argument");
+    if (key == SWIM_OPT_WPS) *value = c->opt_wps;
+    else if (key == SWIM_OPT_BIG_TPL) *value = c->opt_big_tpl;
+    else return fail(SWIM_EINVAL, "unknown option %d", key);
+    return SWIM_OK;
 }
 
 int swim_pair_velocity(swim_ctx* c, int32_t dtype, int64_t n_sys, const int64_t* sys_off, const double* alpha,

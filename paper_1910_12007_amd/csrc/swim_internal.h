@@ -43,12 +43,13 @@ hipError_t launch_pair_velocity(int dtype, int tpl, int64_t n_blocks, const int6
 hipError_t launch_forces(int dtype, int64_t n_fil, const int64_t* fil_off, const int32_t* npt,
                          const double* params, double t, const void* x, const void* y, void* fx,
                          void* fy, hipStream_t st);
-// persistent wave-per-system forward run (systems of at most 64*tpl points)
-hipError_t launch_forward(int dtype, int tpl, int waves_per_block, int n_blocks, const Batch& b,
+// persistent forward run, one workgroup of wps wavefronts per system
+// (systems of at most 64*tpl points; tpl in {1,2,3,4,6,8}, wps in {1,2,4})
+hipError_t launch_forward(int dtype, int tpl, int wps, int n_blocks, const Batch& b,
                           const Run& r, const int32_t* order, int32_t* queue, void* obs,
                           void* speed, int32_t* status, int32_t* steps_done, hipStream_t st);
-size_t forward_lds_bytes(int dtype, int tpl, int waves_per_block);
-int forward_blocks_per_cu(int dtype, int tpl, int waves_per_block);
+size_t forward_lds_bytes(int dtype, int tpl, int wps);
+int forward_blocks_per_cu(int dtype, int tpl, int wps);
 // one forward-Euler step of large systems, targets split over workgroups
 struct BigState {
     void* xh[2];   // position hi parts, double-buffered, [n_points] T

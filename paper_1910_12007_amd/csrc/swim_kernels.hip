@@ -302,190 +302,242 @@ __global__ void k_forces(int64_t n_fil, const int64_t* fil_off, const int32_t* n
 }
 
 // ---------------------------------------------------------------------------
-// persistent forward run: one wavefront per system, systems taken from an
-// LPT-ordered queue; every time step (forces -> velocity sum -> Euler) stays
-// inside the wave, positions and forces live in LDS.
+// persistent forward run: one workgroup of WPS wavefronts per system, systems
+// taken from a longest-first work queue; every time step (forces -> velocity
+// sum -> Euler) stays inside the workgroup, positions and forces live in LDS.
+// Each wavefront sums over 1/WPS of the sources for all targets; partial
+// velocities are reduced through LDS in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
-template <typename T, int TPL>
-__device__ void run_system(const Batch& b, const Run& r, int s, Src4<T>* src, T* lox, T* loy, T* obs,
-                           T* speed, int32_t* status, int32_t* steps_done, int lane)
+template <typename T> struct FwdLds {
+    Src4<T>* src;  // [NMAX] positions (hi) and forces
+    T* lox;        // [NMAX] lo parts
+    T* loy;
+    T* part;       // [WPS][2][NMAX] partial velocities (WPS > 1)
+    T* red;        // [2][WPS] wave partial sums of the forces
+};
+
+template <typename T, int TPL, int WPS>
+__device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>& L, T* obs, T* speed,
+                           int32_t* status, int32_t* steps_done)
 {
     constexpr bool COMP = sizeof(T) == 4;
+    constexpr int NMAX = 64 * TPL, NT = 64 * WPS, OWN = (NMAX + NT - 1) / NT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int N = b.npt[s];
-    const int n = N * b.nswim[s];
+    const int nsw = b.nswim[s];
+    const int n = N * nsw;
     const int64_t f0 = b.sw_off[s];
     if (status[s] == SWIM_ST_BADPARAM_) {
         // parameters outside the kernel's domain: no run, NaN outputs
-        for (int m = lane; m < b.nswim[s]; m += 64) {
+        for (int m = tid; m < nsw; m += NT) {
             T* q = obs + (f0 + m) * (int64_t)r.n_obs * 2;
             for (int o = 0; o < 2 * r.n_obs; ++o) q[o] = (T)NAN;
             speed[f0 + m] = (T)NAN;
         }
-        if (lane == 0 && steps_done) steps_done[s] = 0;
+        if (tid == 0 && steps_done) steps_done[s] = 0;
+        __syncthreads();
         return;
     }
     const SysConst<T> C = ((const SysConst<T>*)b.sysc)[s];
     const double dsd = 1.0 / (double)(N - 1);
 
-    T xh[TPL], yh[TPL], xl[TPL], yl[TPL], hx0[TPL], hy0[TPL];
-    FilP<T> fp[TPL];
-    int loc[TPL], fil[TPL];
-    bool own[TPL];
+    // owned points i = tid + NT*q: positions as (hi, lo)
+    T xh[OWN], yh[OWN], xl[OWN], yl[OWN];
 #pragma unroll
-    for (int k = 0; k < TPL; ++k) {
-        const int i = lane + 64 * k;
-        own[k] = i < n;
-        const int m = own[k] ? i / N : 0;
-        const int p = own[k] ? i - m * N : 0;
-        fil[k] = m;
-        loc[k] = p;
-        fp[k] = load_filp<T>(b.params, f0 + m, N);
+    for (int q = 0; q < OWN; ++q) {
+        const int i = tid + NT * q;
+        const bool own = i < n;
+        const int m = own ? i / N : 0;
+        const int p = own ? i - m * N : 0;
         const double X = b.params[9 * (f0 + m) + 7] + (double)p * dsd;
         const double Y = b.params[9 * (f0 + m) + 8];
-        xh[k] = (T)X;
-        yh[k] = (T)Y;
-        xl[k] = COMP ? (T)(X - (double)xh[k]) : (T)0;
-        yl[k] = COMP ? (T)(Y - (double)yh[k]) : (T)0;
-        hx0[k] = xh[k] + xl[k];
-        hy0[k] = yh[k] + yl[k];
-        if (own[k]) {
-            src[i].x = xh[k];
-            src[i].y = yh[k];
-            lox[i] = xl[k];
-            loy[i] = yl[k];
+        xh[q] = (T)X;
+        yh[q] = (T)Y;
+        xl[q] = COMP ? (T)(X - (double)xh[q]) : (T)0;
+        yl[q] = COMP ? (T)(Y - (double)yh[q]) : (T)0;
+        if (own) {
+            L.src[i].x = xh[q];
+            L.src[i].y = yh[q];
+            L.lox[i] = xl[q];
+            L.loy[i] = yl[q];
             if (p == N - 1) {
                 // samples a stopped run never reaches stay NaN
-                T* q = obs + (f0 + m) * (int64_t)r.n_obs * 2;
-                for (int o = 0; o < 2 * r.n_obs; ++o) q[o] = (T)NAN;
+                T* o = obs + (f0 + m) * (int64_t)r.n_obs * 2;
+                for (int k = 0; k < 2 * r.n_obs; ++k) o[k] = (T)NAN;
             }
         }
     }
-    wave_sync();
+    __syncthreads();
     int st = 0, done = r.steps;
+    const T dt = (T)r.dt;
+    const int chunk = (n + WPS - 1) / WPS;
+    const int j0 = min(n, wave * chunk), j1 = min(n, j0 + chunk);
     for (int step = 0; step < r.steps; ++step) {
         const T t = (T)((double)step * r.dt);
-        T Fx[TPL], Fy[TPL];
+        // forces of the owned points (reads positions only)
         T sfx = (T)0, sfy = (T)0;
 #pragma unroll
-        for (int k = 0; k < TPL; ++k) {
-            if (own[k]) {
-                const int base = fil[k] * N;
+        for (int q = 0; q < OWN; ++q) {
+            const int i = tid + NT * q;
+            if (i < n) {
+                const int m = i / N, p = i - m * N;
+                const int base = m * N;
+                const FilP<T> fp = load_filp<T>(b.params, f0 + m, N);
                 auto seg = [&](int kk, T& dx, T& dy) {
                     const int a = base + kk, c = base + kk + 1;
-                    dx = (src[c].x - src[a].x) + (COMP ? lox[c] - lox[a] : (T)0);
-                    dy = (src[c].y - src[a].y) + (COMP ? loy[c] - loy[a] : (T)0);
+                    dx = (L.src[c].x - L.src[a].x) + (COMP ? L.lox[c] - L.lox[a] : (T)0);
+                    dy = (L.src[c].y - L.src[a].y) + (COMP ? L.loy[c] - L.loy[a] : (T)0);
                 };
-                point_force<T>(seg, loc[k], fp[k], t, Fx[k], Fy[k]);
-                sfx += Fx[k];
-                sfy += Fy[k];
-            } else {
-                Fx[k] = Fy[k] = (T)0;
-            }
-        }
-        wave_sync();
-#pragma unroll
-        for (int k = 0; k < TPL; ++k) {
-            const int i = lane + 64 * k;
-            if (own[k]) {
-                src[i].fx = Fx[k];
-                src[i].fy = Fy[k];
+                T Fx, Fy;
+                point_force<T>(seg, p, fp, t, Fx, Fy);
+                L.src[i].fx = Fx;
+                L.src[i].fy = Fy;
+                sfx += Fx;
+                sfy += Fy;
             }
         }
         sfx = wave_sum(sfx);
         sfy = wave_sum(sfy);
-        wave_sync();
-        T ax[TPL], ay[TPL];
-#pragma unroll
-        for (int k = 0; k < TPL; ++k) ax[k] = ay[k] = (T)0;
-        pair_accumulate<T, TPL>(C, src, n, xh, yh, ax, ay);
-        bool bad = false;
-        const T dt = (T)r.dt;
-#pragma unroll
-        for (int k = 0; k < TPL; ++k) {
-            if (!own[k]) continue;
-            const T ux = fma_t(C.h1c, sfx, ax[k]);
-            const T uy = fma_t(C.h1c, sfy, ay[k]);
-            if (COMP) {
-                acc2(xh[k], xl[k], dt * ux);
-                acc2(yh[k], yl[k], dt * uy);
-            } else {
-                xh[k] = fma_t(dt, ux, xh[k]);
-                yh[k] = fma_t(dt, uy, yh[k]);
-            }
-            bad = bad || bad_t(xh[k]) || bad_t(yh[k]);
+        if (lane == 0) {
+            L.red[wave] = sfx;
+            L.red[WPS + wave] = sfy;
         }
-        const bool any_bad = __any(bad);
-        wave_sync();
+        __syncthreads();
+        T SFx = (T)0, SFy = (T)0;
+#pragma unroll
+        for (int w = 0; w < WPS; ++w) {
+            SFx += L.red[w];
+            SFy += L.red[WPS + w];
+        }
+        // pair sum: this wave's share of the sources, all targets
+        T xi[TPL], yi[TPL], ax[TPL], ay[TPL];
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             const int i = lane + 64 * k;
-            if (own[k]) {
-                src[i].x = xh[k];
-                src[i].y = yh[k];
-                lox[i] = xl[k];
-                loy[i] = yl[k];
+            xi[k] = i < n ? L.src[i].x : (T)0;
+            yi[k] = i < n ? L.src[i].y : (T)0;
+            ax[k] = ay[k] = (T)0;
+        }
+        pair_accumulate<T, TPL>(C, L.src + j0, j1 - j0, xi, yi, ax, ay);
+        if constexpr (WPS > 1) {
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) {
+                const int i = lane + 64 * k;
+                if (i < n) {
+                    L.part[(wave * 2 + 0) * NMAX + i] = ax[k];
+                    L.part[(wave * 2 + 1) * NMAX + i] = ay[k];
+                }
+            }
+            __syncthreads();
+        }
+        // Euler update of the owned points
+        int bad = 0;
+#pragma unroll
+        for (int q = 0; q < OWN; ++q) {
+            const int i = tid + NT * q;
+            if (i >= n) continue;
+            T ux, uy;
+            if constexpr (WPS > 1) {
+                ux = (T)0;
+                uy = (T)0;
+#pragma unroll
+                for (int w = 0; w < WPS; ++w) {
+                    ux += L.part[(w * 2 + 0) * NMAX + i];
+                    uy += L.part[(w * 2 + 1) * NMAX + i];
+                }
+            } else {
+                ux = ax[q];
+                uy = ay[q];
+            }
+            ux = fma_t(C.h1c, SFx, ux);
+            uy = fma_t(C.h1c, SFy, uy);
+            if (COMP) {
+                acc2(xh[q], xl[q], dt * ux);
+                acc2(yh[q], yl[q], dt * uy);
+            } else {
+                xh[q] = fma_t(dt, ux, xh[q]);
+                yh[q] = fma_t(dt, uy, yh[q]);
+            }
+            if (bad_t(xh[q]) || bad_t(yh[q])) bad = (isfinite(xh[q]) && isfinite(yh[q])) ? 2 : 1;
+        }
+        // every read of the old positions is done after this barrier
+        const int any_bad = __syncthreads_or(bad);
+#pragma unroll
+        for (int q = 0; q < OWN; ++q) {
+            const int i = tid + NT * q;
+            if (i < n) {
+                L.src[i].x = xh[q];
+                L.src[i].y = yh[q];
+                L.lox[i] = xl[q];
+                L.loy[i] = yl[q];
             }
         }
-        wave_sync();
         if (any_bad) {
-            bool nonfinite = false;
-#pragma unroll
-            for (int k = 0; k < TPL; ++k)
-                if (own[k]) nonfinite = nonfinite || !isfinite(xh[k]) || !isfinite(yh[k]);
-            st = __any(nonfinite) ? 1 : 2;
+            st = __syncthreads_or(bad == 1) ? 1 : 2;
             done = step + 1;
             break;
         }
+        __syncthreads();
         if (r.obs_every > 0 && (step + 1) % r.obs_every == 0) {
             const int o = (step + 1) / r.obs_every - 1;
 #pragma unroll
-            for (int k = 0; k < TPL; ++k) {
-                if (own[k] && loc[k] == N - 1) {
-                    T* q = obs + ((f0 + fil[k]) * (int64_t)r.n_obs + o) * 2;
-                    q[0] = xh[k] + xl[k];
-                    q[1] = yh[k] + yl[k];
+            for (int q = 0; q < OWN; ++q) {
+                const int i = tid + NT * q;
+                if (i < n && (i % N) == N - 1) {
+                    T* d = obs + ((f0 + i / N) * (int64_t)r.n_obs + o) * 2;
+                    d[0] = xh[q] + xl[q];
+                    d[1] = yh[q] + yl[q];
                 }
             }
         }
     }
     const T Tend = (T)((double)r.steps * r.dt);
 #pragma unroll
-    for (int k = 0; k < TPL; ++k) {
-        if (own[k] && loc[k] == N - 1) {
-            const int64_t f = f0 + fil[k];
+    for (int q = 0; q < OWN; ++q) {
+        const int i = tid + NT * q;
+        if (i < n && (i % N) == N - 1) {
+            const int64_t f = f0 + i / N;
             if (st) {
                 speed[f] = (T)NAN;
             } else {
-                const T dx = (xh[k] + xl[k]) - hx0[k], dy = (yh[k] + yl[k]) - hy0[k];
+                const T hx0 = (T)(b.params[9 * f + 7] + (double)(N - 1) * dsd);
+                const T hy0 = (T)b.params[9 * f + 8];
+                const T dx = (xh[q] + xl[q]) - hx0, dy = (yh[q] + yl[q]) - hy0;
                 speed[f] = sqrt_t(fma_t(dx, dx, dy * dy)) / Tend;
             }
         }
     }
-    if (lane == 0) {
+    if (tid == 0) {
         status[s] = st;
         if (steps_done) steps_done[s] = done;
     }
+    __syncthreads();
 }
 
-template <typename T, int TPL>
-__global__ __launch_bounds__(256) void k_forward(Batch b, Run r, const int32_t* order, int32_t* queue, T* obs,
-                                                 T* speed, int32_t* status, int32_t* steps_done)
+template <typename T, int TPL, int WPS>
+__global__ __launch_bounds__(64 * WPS) void k_forward(Batch b, Run r, const int32_t* order, int32_t* queue, T* obs,
+                                                      T* speed, int32_t* status, int32_t* steps_done)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NMAX = 64 * TPL;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    Src4<T>* src = reinterpret_cast<Src4<T>*>(smem) + wid * NMAX;
-    T* lo = reinterpret_cast<T*>(smem + (size_t)nw * NMAX * sizeof(Src4<T>)) + (size_t)wid * 2 * NMAX;
-    // Work queue: lane 0 takes the next system; readfirstlane makes the item
-    // an SGPR, so the loop exit is a scalar branch taken by the whole wave.
-    // A wave can take at most n_sys items, which bounds the loop.
+    __shared__ int s_item;
+    FwdLds<T> L;
+    L.src = reinterpret_cast<Src4<T>*>(smem);
+    L.lox = reinterpret_cast<T*>(smem + NMAX * sizeof(Src4<T>));
+    L.loy = L.lox + NMAX;
+    L.red = L.loy + NMAX;
+    L.part = L.red + 2 * WPS;
+    // Work queue: thread 0 takes the next system; the item reaches every
+    // thread through LDS and readfirstlane makes it an SGPR, so the loop exit
+    // is a uniform scalar branch.  A workgroup takes at most n_sys items.
     for (int64_t it = 0; it <= b.n_sys; ++it) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(queue, 1);
-        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, 64));
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
         if (item >= b.n_sys) break;
         const int s = __builtin_amdgcn_readfirstlane(order[item]);
-        run_system<T, TPL>(b, r, s, src, lo, lo + NMAX, obs, speed, status, steps_done, lane);
+        run_system<T, TPL, WPS>(b, r, s, L, obs, speed, status, steps_done);
     }
 }
 
@@ -807,43 +859,73 @@ hipError_t launch_forces(int dtype, int64_t n_fil, const int64_t* fil_off, const
     return hipGetLastError();
 }
 
-size_t forward_lds_bytes(int dtype, int tpl, int wpb)
+size_t forward_lds_bytes(int dtype, int tpl, int wps)
 {
     const size_t e = dtype == 0 ? sizeof(float) : sizeof(double);
-    return (size_t)wpb * 64 * tpl * (4 * e + 2 * e);
+    const size_t nmax = 64 * (size_t)tpl;
+    return nmax * 4 * e + 2 * nmax * e + 2 * (size_t)wps * e + (wps > 1 ? (size_t)wps * 2 * nmax * e : 0);
 }
 
-template <typename T, int TPL>
-static hipError_t fwd_launch(int wpb, int nblocks, const Batch& b, const Run& r, const int32_t* order, int32_t* q,
-                             void* obs, void* speed, int32_t* status, int32_t* done, hipStream_t st)
+template <typename T, int TPL, int WPS>
+static hipError_t fwd_launch(int nblocks, const Batch& b, const Run& r, const int32_t* order, int32_t* q, void* obs,
+                             void* speed, int32_t* status, int32_t* done, hipStream_t st)
 {
-    const size_t lds = forward_lds_bytes(sizeof(T) == 4 ? 0 : 1, TPL, wpb);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_forward<T, TPL>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    const size_t lds = forward_lds_bytes(sizeof(T) == 4 ? 0 : 1, TPL, WPS);
+    static size_t attr_lds = 0;
+    if (lds > attr_lds) {
+        // raise the dynamic-LDS limit to exactly what this launch needs
+        hipError_t e = hipFuncSetAttribute((const void*)k_forward<T, TPL, WPS>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_lds = lds;
     }
-    hipLaunchKernelGGL((k_forward<T, TPL>), dim3(nblocks), dim3(64 * wpb), lds, st, b, r, order, q, (T*)obs,
+    hipLaunchKernelGGL((k_forward<T, TPL, WPS>), dim3(nblocks), dim3(64 * WPS), lds, st, b, r, order, q, (T*)obs,
                        (T*)speed, status, done);
     return hipGetLastError();
 }
 
-hipError_t launch_forward(int dtype, int tpl, int wpb, int nblocks, const Batch& b, const Run& r,
+template <typename T, int TPL, int WPS>
+static int fwd_occupancy()
+{
+    int nb = 0;
+    const size_t lds = forward_lds_bytes(sizeof(T) == 4 ? 0 : 1, TPL, WPS);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_forward<T, TPL, WPS>, 64 * WPS, lds) != hipSuccess || nb < 1)
+        nb = 1;
+    return nb;
+}
+
+#define SWIM_FWD_TABLE(X, T)                                                                               \
+    X(T, 1, 1) X(T, 1, 2) X(T, 1, 4) X(T, 1, 8) X(T, 1, 16) X(T, 2, 1) X(T, 2, 2) X(T, 2, 4) X(T, 2, 8)      \
+    X(T, 2, 16) X(T, 3, 1) X(T, 3, 2) X(T, 3, 4) X(T, 3, 8) X(T, 3, 16) X(T, 4, 1) X(T, 4, 2) X(T, 4, 4)     \
+    X(T, 4, 8) X(T, 4, 16) X(T, 6, 1) X(T, 6, 2) X(T, 6, 4) X(T, 6, 8) X(T, 6, 16) X(T, 8, 1) X(T, 8, 2)      \
+    X(T, 8, 4) X(T, 8, 8) X(T, 8, 16)
+
+hipError_t launch_forward(int dtype, int tpl, int wps, int nblocks, const Batch& b, const Run& r,
                           const int32_t* order, int32_t* queue, void* obs, void* speed, int32_t* status,
                           int32_t* steps_done, hipStream_t st)
 {
-#define FWD_CASE(T, P) \
-    case P: return fwd_launch<T, P>(wpb, nblocks, b, r, order, queue, obs, speed, status, steps_done, st);
+#define FWD_CASE(T, P, W) \
+    if (tpl == P && wps == W) return fwd_launch<T, P, W>(nblocks, b, r, order, queue, obs, speed, status, steps_done, st);
     if (dtype == 0) {
-        switch (tpl) { FWD_CASE(float, 1) FWD_CASE(float, 2) FWD_CASE(float, 3) FWD_CASE(float, 4)
-                       FWD_CASE(float, 6) FWD_CASE(float, 8) default: return hipErrorInvalidValue; }
+        SWIM_FWD_TABLE(FWD_CASE, float)
     } else {
-        switch (tpl) { FWD_CASE(double, 1) FWD_CASE(double, 2) FWD_CASE(double, 3) FWD_CASE(double, 4)
-                       FWD_CASE(double, 6) FWD_CASE(double, 8) default: return hipErrorInvalidValue; }
+        SWIM_FWD_TABLE(FWD_CASE, double)
     }
 #undef FWD_CASE
+    return hipErrorInvalidValue;
+}
+
+int forward_blocks_per_cu(int dtype, int tpl, int wps)
+{
+#define OCC_CASE(T, P, W) \
+    if (tpl == P && wps == W) return fwd_occupancy<T, P, W>();
+    if (dtype == 0) {
+        SWIM_FWD_TABLE(OCC_CASE, float)
+    } else {
+        SWIM_FWD_TABLE(OCC_CASE, double)
+    }
+#undef OCC_CASE
+    return 1;
 }
 
 hipError_t launch_big_init(int dtype, const int64_t* list, int64_t n_list, const Batch& b, const BigState& s,
@@ -868,14 +950,14 @@ static hipError_t big_launch(int64_t nb, const int64_t* bs, const int64_t* bf, i
                              const BigState& s, int step, const Run& r, void* obs, int32_t* status, int32_t* done,
                              hipStream_t st)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_big_step<T, TPL>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
     const size_t lds = big_step_lds_bytes(sizeof(T) == 4 ? 0 : 1, max_pts);
+    static size_t attr_lds = 0;
+    if (lds > attr_lds) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_big_step<T, TPL>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_lds = lds;
+    }
     hipLaunchKernelGGL((k_big_step<T, TPL>), dim3((unsigned)nb), dim3(256), lds, st, bs, bf, b, s, step, r, (T*)obs,
                        status, done);
     return hipGetLastError();
@@ -937,26 +1019,3 @@ hipError_t launch_accept(int64_t n, const double* dist, const double* tol, uint8
 
 }  // namespace swim
 
-namespace swim {
-
-// resident workgroups per CU of the persistent forward kernel
-int forward_blocks_per_cu(int dtype, int tpl, int wpb)
-{
-    const size_t lds = forward_lds_bytes(dtype, tpl, wpb);
-    int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
-#define OCC_CASE(T, P) \
-    case P: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_forward<T, P>, 64 * wpb, lds); break;
-    if (dtype == 0) {
-        switch (tpl) { OCC_CASE(float, 1) OCC_CASE(float, 2) OCC_CASE(float, 3) OCC_CASE(float, 4)
-                       OCC_CASE(float, 6) OCC_CASE(float, 8) default: break; }
-    } else {
-        switch (tpl) { OCC_CASE(double, 1) OCC_CASE(double, 2) OCC_CASE(double, 3) OCC_CASE(double, 4)
-                       OCC_CASE(double, 6) OCC_CASE(double, 8) default: break; }
-    }
-#undef OCC_CASE
-    if (e != hipSuccess || nb < 1) nb = 1;
-    return nb;
-}
-
-}  // namespace swim

@@ -61,16 +61,16 @@ constexpr double c_D(int k) { return k * c_A(k + 1); }
 // precision traits: series lengths and thresholds per working type
 template <typename T> struct Prec;
 template <> struct Prec<float> {
-    static constexpr int NW = 9;       // terms of the w-polynomials I0, Abar, D (w <= 4)
-    static constexpr int NT = 10;      // terms of the per-system U, V polynomials
-    static constexpr int NDS = 14;     // terms of the small-delta series
+    static constexpr int NW = 9;       // terms of the w-polynomial Abar (w <= 4)
+    static constexpr int NT = 9;       // terms of the per-system U, V polynomials
+    static constexpr int NA = 4;       // terms of the near-contact atanh series
     static constexpr float DSMALL = 0.25f;
     static constexpr int NKF = SWIM_KFIT_K0_F32_N;
 };
 template <> struct Prec<double> {
     static constexpr int NW = 15;
     static constexpr int NT = 16;
-    static constexpr int NDS = 28;
+    static constexpr int NA = 9;
     static constexpr double DSMALL = 0.25;
     static constexpr int NKF = SWIM_KFIT_K0_F64_N;
 };
@@ -240,6 +240,51 @@ SWIM_HD float exp_t(float x) { return expf(x); }
 SWIM_HD double exp_t(double x) { return exp(x); }
 SWIM_HD float sqrt_t(float x) { return sqrtf(x); }
 SWIM_HD double sqrt_t(double x) { return sqrt(x); }
+
+// Fast FP32 forms for the pair loop.  On the device they are single VALU
+// transcendentals (v_rcp_f32, v_log_f32, v_sqrt_f32, v_rsq_f32; about 1 ulp);
+// the host pass of this header (used only by the host test hook) takes the
+// libm equivalents.  FP64 keeps the correctly rounded library calls.
+SWIM_HD float rcp_fast(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+SWIM_HD double rcp_fast(double x) { return 1.0 / x; }
+SWIM_HD float sqrt_fast(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+SWIM_HD double sqrt_fast(double x) { return sqrt(x); }
+SWIM_HD float rsqrt_fast(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsqf(x);
+#else
+    return 1.0f / sqrtf(x);
+#endif
+}
+SWIM_HD double rsqrt_fast(double x) { return 1.0 / sqrt(x); }
+// log1p(x) for x >= 1/4: u = 1 + x is rounded, u - 1 is exact, and the
+// factor x / (u - 1) restores the part of x the rounding dropped.
+SWIM_HD float log1p_fast(float x)
+{
+    const float u = 1.0f + x;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float l = __builtin_amdgcn_logf(u) * 0.693147180559945309f;
+#else
+    const float l = logf(u);
+#endif
+    return l * (x * rcp_fast(u - 1.0f));
+}
+SWIM_HD double log1p_fast(double x) { return log1p(x); }
 SWIM_HD float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
 SWIM_HD double fma_t(double a, double b, double c) { return fma(a, b, c); }
 
@@ -266,37 +311,41 @@ SWIM_HD void kernel_small_z(const SysConst<T>& C, T t, T w, T& Ht, T& H2)
 {
     using P = Prec<T>;
     const T delta = t * C.inv_e2;
-    // delta = 0 is the self pair: its value is multiplied by zero, so lambda
-    // and S2 are taken at the clamped delta; 0 < delta < DSMALL (near contact,
-    // rare) sums their series instead of cancelling.
-    const T dc = delta >= (T)P::DSMALL ? delta : (T)P::DSMALL;
-    const T lc = log1p_t(dc);
     T ell, lam, S2;
     if (delta >= (T)P::DSMALL || delta == (T)0) {
+        // delta = 0 is the self pair: its value is multiplied by zero, so
+        // lambda and S2 are taken at the clamped delta
+        const T dc = delta >= (T)P::DSMALL ? delta : (T)P::DSMALL;
+        const T lc = log1p_fast(dc);
         ell = delta == (T)0 ? (T)0 : lc;
-        const T rd = (T)1 / dc;
+        const T rd = rcp_fast(dc);
         lam = lc * rd;
         S2 = ((T)1 - lam) * rd;
     } else {
-        ell = log1p_t(delta);
-        // lambda = sum (-d)^m/(m+1),  S2 = sum (-d)^m/(m+2)
-        T a = (T)0, b = (T)0;
+        // near contact (rare): log1p(d) = 2 atanh(y), y = d/(2+d), so with
+        // Y = y^2 and Pa(Y) = sum_{m>=1} Y^(m-1)/(2m+1):
+        //   lambda = 2 (1 + Y Pa)/(2+d),  S2 = 1/(2+d) - 2 d Pa/(2+d)^3,
+        // both free of cancellation
+        const T r2 = (T)1 / ((T)2 + delta);
+        const T y = delta * r2, Y = y * y;
+        T pa = (T)(1.0 / (2 * P::NA + 1));
 #pragma unroll
-        for (int m = P::NDS - 1; m >= 0; --m) {
-            a = fma_t(a, -delta, (T)1 / (T)(m + 1));
-            b = fma_t(b, -delta, (T)1 / (T)(m + 2));
-        }
-        lam = a;
-        S2 = b;
+        for (int m = P::NA - 1; m >= 1; --m) pa = fma_t(pa, Y, (T)(1.0 / (2 * m + 1)));
+        const T Q = fma_t(Y, pa, (T)1);
+        ell = (T)2 * y * Q;
+        lam = (T)2 * Q * r2;
+        S2 = r2 - (T)2 * delta * r2 * r2 * r2 * pa;
     }
-    // global w-polynomials
-    T I0w = (T)c_I0(P::NW - 1), Ab = (T)c_Abar(P::NW - 1), Dw = (T)c_D(P::NW - 1);
+    // Abar(w) and its derivative in one Horner pass; D = w Abar' and
+    // I0 = 2 (Abar + w Abar') follow from the series coefficients
+    T Ab = (T)c_Abar(P::NW - 1), dA = (T)0;
 #pragma unroll
     for (int k = P::NW - 2; k >= 0; --k) {
-        I0w = fma_t(I0w, w, (T)c_I0(k));
+        dA = fma_t(dA, w, Ab);
         Ab = fma_t(Ab, w, (T)c_Abar(k));
-        Dw = fma_t(Dw, w, (T)c_D(k));
     }
+    const T Dw = w * dA;
+    const T I0w = (T)2 * (Ab + Dw);
     const T Ut = t * horner_arr<T, P::NT>(t, C.U);
     const T Vt = horner_arr<T, P::NT>(t, C.V);
     H2 = C.cpi * fma_t(C.half_inv_e2, fma_t(Dw, lam, Ab * S2), Vt);
@@ -307,16 +356,16 @@ SWIM_HD void kernel_small_z(const SysConst<T>& C, T t, T w, T& Ht, T& H2)
 template <typename T>
 SWIM_HD void kernel_large_z(const SysConst<T>& C, T t, T w, T& Ht, T& H2)
 {
-    const T z = sqrt_t(w);
-    const T rz = (T)1 / z;
-    const T e = exp_t(-z) * sqrt_t(rz);
+    const T z = sqrt_fast(w);
+    const T rz = rcp_fast(z);
+    const T e = exp_t(-z) * rsqrt_fast(z);
     const T x = (T)SWIM_KFIT_ZS * rz;
     const T K0 = e * kfit<T>(0, x);
     const T K1 = e * kfit<T>(1, x);
     const T g = -C.c2pi * K0;
     const T gt = -C.c2pi * (K0 - C.K0z0);
     const T q = fma_t(z, K1, (T)-1);
-    const T rt = (T)1 / t;
+    const T rt = rcp_fast(t);
     const T Mt = C.c2pi * (q - C.q0) * C.inv_a2 * rt;  // M(r)/r^2
     H2 = (g - (T)2 * Mt) * rt;
     Ht = (T)-0.5 * fma_t(t, H2, gt);

@@ -17,6 +17,7 @@ SWIM_OK, SWIM_EINVAL, SWIM_EHIP, SWIM_ENOMEM, SWIM_ESTATE = 0, -1, -2, -3, -4
 SWIM_F32, SWIM_F64 = 0, 1
 SWIM_ST_OK, SWIM_ST_NONFINITE, SWIM_ST_BOUND, SWIM_ST_BADPARAM = 0, 1, 2, 3
 SWIM_NPARAM = 9
+SWIM_OPT_WPS, SWIM_OPT_BIG_TPL = 1, 2
 
 _c = ctypes
 _P = _c.c_void_p
@@ -31,6 +32,8 @@ SIGNATURES = {
     "swim_destroy": (None, [_P]),
     "swim_last_error": (_c.c_char_p, []),
     "swim_version": (_c.c_int, []),
+    "swim_set_option": (_c.c_int, [_P, _c.c_int32, _c.c_int32]),
+    "swim_get_option": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int32)]),
     "swim_pair_velocity": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I64P, _DP, _DP, _P, _P, _P, _P, _P, _P, _P]),
     "swim_elastic_forces": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I32P, _DP, _c.c_double, _P, _P, _P, _P, _P]),
     "swim_forward": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I32P, _I32P, _P, _c.c_int32, _c.c_double,
@@ -129,6 +132,16 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def swim_set_option(ctx, key, value):
+    return _check(lib().swim_set_option(ctx.handle, int(key), int(value)))
+
+
+def swim_get_option(ctx, key):
+    v = ctypes.c_int32()
+    _check(lib().swim_get_option(ctx.handle, int(key), ctypes.byref(v)))
+    return v.value
 
 
 def swim_pair_velocity(ctx, sys_off, alpha, eps, x, y, fx, fy, ux, uy, stream=None):
