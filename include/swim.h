@@ -203,6 +203,95 @@ int abc_step(swim_ctx *ctx, const abc_model *model, const double *data, int32_t 
              const double *prev_w, int64_t n_prev, double q, double *theta_out, double *dist_out,
              uint8_t *accept_out, double *w_out, double *tol_out);
 
+/* ---------------------------------------------------------------------------
+ * Surrogate of the forward model (not in the paper; prescreens ABC
+ * proposals): an MLP 5 -> 256 -> 256 -> 256 -> 256 -> 33 with GELU
+ * x Phi(x) on the hidden layers.  Inputs (alpha, ln S_b, ln S_s, b, omega),
+ * outputs the head displacement at n_sum observation times (x, y) and the
+ * mean speed, all standardized.  BF16 MFMA with FP32 accumulation: every
+ * GEMM operand is rounded to bfloat16 (nearest-even); FP32 master weights.
+ * Parameters: one FP32 vector of SWIM_MLP_NPARAM values, for each layer
+ * l = 0..4 the weights W_l (fan_in x fan_out, row-major) then the bias b_l.
+ * --------------------------------------------------------------------------- */
+#define SWIM_MLP_NPARAM 207393
+#define SWIM_MLP_IN 5
+#define SWIM_MLP_OUT 33
+
+/* Y = f(X): X device float[n][5], Y device float[n][33].  Asynchronous. */
+int surrogate_forward(swim_ctx *ctx, int64_t n, const float *X, const float *params, float *Y,
+                      void *stream);
+
+/* Gradient of the loss mean((f(X) - T)^2) over the n x 33 outputs:
+ * grads device float[SWIM_MLP_NPARAM] (parameter layout), loss device float[1]
+ * (sum of squares; divide by 33 n) or NULL.  n <= 2^20.  Asynchronous. */
+int surrogate_grad(swim_ctx *ctx, int64_t n, const float *X, const float *T, const float *params,
+                   float *grads, float *loss, void *stream);
+
+/* Adam training (beta = 0.9, 0.999, eps = 1e-8): epochs x floor(n/batch)
+ * steps; step s of epoch e uses the rows perm[e*n + s*batch ...] (device
+ * int32[epochs][n], a permutation per epoch supplied by the caller).
+ * Row indices outside [0, n) give NaN rows (and a NaN loss), never reads
+ * out of bounds.  params, adam_m, adam_v device float[SWIM_MLP_NPARAM],
+ * updated in place
+ * (m, v start at zero for a fresh run).  loss_out device float[epochs *
+ * floor(n/batch)] (per-step sum of squares) or NULL.  Asynchronous. */
+int surrogate_train(swim_ctx *ctx, int64_t n, const float *X, const float *T, const int32_t *perm,
+                    int32_t epochs, int32_t batch, float lr, float *params, float *adam_m,
+                    float *adam_v, float *loss_out, void *stream);
+
+/* Prescreen: d_i = sqrt(mean_j (mu_j + sd_j f(X_i)_j - obs_j)^2) over the
+ * first n_sum outputs; keep[i] = d_i <= tol; idx[0..*n_keep) = the kept i in
+ * ascending order.  X device float[n][5]; out_mu, out_sd, obs_sum device
+ * float (de-standardization and observed summaries); dist device float[n]
+ * or NULL; keep device uint8[n]; idx device int64[n]; n_keep device
+ * int64[1].  Asynchronous. */
+int surrogate_prescreen(swim_ctx *ctx, int64_t n, const float *X, const float *params,
+                        const float *out_mu, const float *out_sd, const float *obs_sum,
+                        int32_t n_sum, float tol, float *dist, uint8_t *keep, int64_t *idx,
+                        int64_t *n_keep, void *stream);
+
+/* X[i] = (alpha, ln S_b, ln S_s, b, omega) of theta device double[n][3],
+ * standardized with mu, sd (device float[5]) unless both are NULL. */
+int surrogate_features(swim_ctx *ctx, int64_t n, const double *theta, double b, double omega,
+                       const float *mu, const float *sd, float *X, void *stream);
+
+/* T[i] = (obs_i[idx_j] - (x0, y0) for j < n_sum, speed_i): device
+ * float[n][2 n_sum + 1] from a forward run's obs / speed (dtype). */
+int surrogate_targets(swim_ctx *ctx, int32_t dtype, int64_t n, int32_t n_obs, const void *obs,
+                      const void *speed, double x0, double y0, const int32_t *sum_idx,
+                      int32_t n_sum, float *T, void *stream);
+
+/* Column mean and population standard deviation (1 if zero) of A device
+ * float[n][cols] into mu, sd device float[cols]; standardize in place. */
+int surrogate_colstats(swim_ctx *ctx, int64_t n, int32_t cols, const float *A, float *mu,
+                       float *sd, void *stream);
+int surrogate_standardize(swim_ctx *ctx, int64_t n, int32_t cols, float *A, const float *mu,
+                          const float *sd, void *stream);
+
+/* abc_prior_draw on the device: theta device double[n][3], identical values. */
+int abc_prior_draw_device(swim_ctx *ctx, uint64_t seed, int64_t n, const double *lo,
+                          const double *hi, double *theta, void *stream);
+
+/* Parameter rows (alpha, S_b, S_s, b, omega, k, 0, 0, 0) for swim_forward
+ * from theta rows idx[j] (idx NULL: row j), j < min(cap, *n_dev) (n_dev
+ * NULL: cap), theta device double[n_theta][3].  An index outside
+ * [0, n_theta) gives a NaN row, which swim_forward flags
+ * SWIM_ST_BADPARAM.  All device.  Asynchronous. */
+int swim_param_rows(swim_ctx *ctx, int64_t cap, const int64_t *n_dev, const int64_t *idx,
+                    int64_t n_theta, const double *theta, double b, double omega, double k,
+                    double *rows, void *stream);
+
+/* keep[i] = values[i] == want (values NULL: keep given), then idx[0..*n_keep)
+ * = the kept i in ascending order.  All device.  Asynchronous. */
+int swim_select(swim_ctx *ctx, int64_t n, const int32_t *values, int32_t want, uint8_t *keep,
+                int64_t *idx, int64_t *n_keep, void *stream);
+
+/* dst[j] = src[idx[j]] (rows of cols floats), j < min(cap, *n_dev); src
+ * device float[n_src][cols]; an index outside [0, n_src) gives a NaN row.
+ * Device.  Asynchronous. */
+int swim_gather_rows(swim_ctx *ctx, int64_t cap, const int64_t *n_dev, const int64_t *idx,
+                     int64_t n_src, const float *src, int32_t cols, float *dst, void *stream);
+
 /* Host evaluation of the device kernel functions (test hook): for squared
  * distances t[0..n) returns H1(t) - H1(0) and H2(t) as computed by the
  * kernels' own code compiled for the host, and H1(0) in *h1c. */

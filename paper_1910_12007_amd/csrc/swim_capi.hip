@@ -16,6 +16,7 @@
 #include "../../include/swim.h"
 #include "swim_internal.h"
 #include "swim_math.h"
+#include "swim_philox.h"
 
 using namespace swim;
 
@@ -58,8 +59,21 @@ struct DevBuf {
 
 enum BufId {
     B_OFF, B_SWOFF, B_NPT, B_NSW, B_ORDER, B_LIST, B_BLKS, B_BLKF, B_ALPHA, B_EPS, B_SYSC, B_QUEUE,
-    B_PARAMS, B_DATA, B_OBS, B_SPEED, B_STATUS, B_DIST, B_TOL, B_ACC, B_BIG, B_NBUF
+    B_PARAMS, B_DATA, B_OBS, B_SPEED, B_STATUS, B_DIST, B_TOL, B_ACC, B_BIG,
+    B_MLP_ACT, B_MLP_GRAD, B_MLP_BATCH, B_MLP_IDX, B_MLP_CNT, B_NBUF
 };
+
+// surrogate network: 5 -> 256 x 4 -> 33
+constexpr int MLP_L = 5;
+constexpr int MLP_W[MLP_L + 1] = {5, 256, 256, 256, 256, 33};
+int64_t mlp_offW(int l)
+{
+    int64_t o = 0;
+    for (int k = 0; k < l; ++k) o += (int64_t)MLP_W[k] * MLP_W[k + 1] + MLP_W[k + 1];
+    return o;
+}
+int64_t mlp_offb(int l) { return mlp_offW(l) + (int64_t)MLP_W[l] * MLP_W[l + 1]; }
+constexpr int64_t MLP_NPARAM = 207393;
 
 }  // namespace
 
@@ -152,48 +166,10 @@ int choose_tpl(int pts)
     return -1;
 }
 
-// ------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) and the variates ABC draws
-// ------------------------------------------------------------------------
-struct U4 {
-    uint32_t v[4];
-};
-
-U4 philox(U4 c, uint32_t k0, uint32_t k1)
-{
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c.v[0];
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.v[2];
-        const uint32_t h0 = (uint32_t)(p0 >> 32), l0 = (uint32_t)p0;
-        const uint32_t h1 = (uint32_t)(p1 >> 32), l1 = (uint32_t)p1;
-        U4 n;
-        n.v[0] = h1 ^ c.v[1] ^ k0;
-        n.v[1] = l1;
-        n.v[2] = h0 ^ c.v[3] ^ k1;
-        n.v[3] = l0;
-        c = n;
-    }
-    return c;
-}
-
-// two U(0,1) doubles for (seed, stream, index, draw); 53 bits each
+// two U(0,1) doubles of the library's Philox4x32-10 stream (swim_philox.h)
 void uniforms2(uint64_t seed, uint32_t stream, uint64_t index, uint32_t draw, double* u)
 {
-    U4 c;
-    c.v[0] = (uint32_t)index;
-    c.v[1] = (uint32_t)(index >> 32);
-    c.v[2] = draw;
-    c.v[3] = stream;
-    const U4 w = philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const double sc = 1.0 / 9007199254740992.0;
-    const uint64_t a = ((uint64_t)w.v[0] << 21) + (w.v[1] >> 11);
-    const uint64_t b = ((uint64_t)w.v[2] << 21) + (w.v[3] >> 11);
-    u[0] = ((double)a + 0.5) * sc;
-    u[1] = ((double)b + 0.5) * sc;
+    philox_uniforms2(seed, stream, index, draw, u);
 }
 
 void box_muller(double u, double v, double* z0, double* z1)
@@ -362,6 +338,81 @@ int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
                                    steps_done, st));
         HIPCHK(launch_big_finish(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S,
                                  run.steps & 1, run, speed, status, steps_done, st));
+    }
+    return SWIM_OK;
+}
+
+
+// ------------------------------------------------------------------------
+// surrogate MLP: forward and backward over M rows (workspace in the ctx)
+// activation workspace layout (floats): pre[4][M*256], H[4][M*256],
+// Y[M*33], dY[M*33], dA[2][M*256], rowsq[M]
+// ------------------------------------------------------------------------
+struct MlpAct {
+    float* pre[4];
+    float* H[4];
+    float *Y, *dY, *dA[2], *rowsq;
+};
+
+int mlp_act(swim_ctx* c, int64_t M, MlpAct* a)
+{
+    const int64_t H = 256, O = 33;
+    const int64_t total = 8 * M * H + 2 * M * O + 2 * M * H + M;
+    TRY(ensure(c, B_MLP_ACT, (size_t)total * 4));
+    float* p = (float*)c->buf[B_MLP_ACT].p;
+    for (int l = 0; l < 4; ++l) a->pre[l] = p + l * M * H;
+    for (int l = 0; l < 4; ++l) a->H[l] = p + (4 + l) * M * H;
+    a->Y = p + 8 * M * H;
+    a->dY = a->Y + M * O;
+    a->dA[0] = a->dY + M * O;
+    a->dA[1] = a->dA[0] + M * H;
+    a->rowsq = a->dA[1] + M * H;
+    return SWIM_OK;
+}
+
+int mlp_forward(const float* X, const float* P, int64_t M, const MlpAct& a, float* Y, hipStream_t st)
+{
+    const float* in = X;
+    int64_t ldin = MLP_W[0];
+    for (int l = 0; l < MLP_L; ++l) {
+        const int K = MLP_W[l], N = MLP_W[l + 1];
+        const float* W = P + mlp_offW(l);
+        const float* b = P + mlp_offb(l);
+        if (l < MLP_L - 1) {
+            HIPCHK(launch_gemm_bf16(1, (int)M, N, K, in, ldin, 1, W, N, 1, a.pre[l], N, b, a.H[l], st));
+            in = a.H[l];
+            ldin = N;
+        } else {
+            HIPCHK(launch_gemm_bf16(2, (int)M, N, K, in, ldin, 1, W, N, 1, Y, N, b, nullptr, st));
+        }
+    }
+    return SWIM_OK;
+}
+
+// gradients of the mean-squared error into G (layout of the parameters);
+// loss (device, optional) = mean over the M x 33 outputs
+int mlp_backward(const float* X, const float* T, const float* P, int64_t M, const MlpAct& a, float* G, float* loss,
+                 hipStream_t st)
+{
+    const int O = MLP_W[MLP_L];
+    HIPCHK(launch_mse_grad((int)M, O, a.Y, T, a.dY, a.rowsq, st));
+    if (loss) HIPCHK(launch_colsum((int)M, 1, a.rowsq, 1, loss, st));
+    const float* dA = a.dY;
+    int cur = 0;
+    for (int l = MLP_L - 1; l >= 0; --l) {
+        const int K = MLP_W[l], N = MLP_W[l + 1];
+        const float* Hin = l > 0 ? a.H[l - 1] : X;
+        // dW_l = Hin^T dA  (K x N, summed over the M rows)
+        HIPCHK(launch_gemm_bf16(0, K, N, (int)M, Hin, 1, K, dA, N, 1, G + mlp_offW(l), N, nullptr, nullptr, st));
+        HIPCHK(launch_colsum((int)M, N, dA, N, G + mlp_offb(l), st));
+        if (l > 0) {
+            // dA_{l-1} = (dA W_l^T) * gelu'(pre_{l-1})
+            float* out = a.dA[cur];
+            HIPCHK(launch_gemm_bf16(3, (int)M, K, N, dA, N, 1, P + mlp_offW(l), 1, N, out, K, nullptr, a.pre[l - 1],
+                                    st));
+            dA = out;
+            cur ^= 1;
+        }
     }
     return SWIM_OK;
 }
@@ -769,6 +820,179 @@ int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, co
         }
         *h1c = C.h1c;
     }
+    return SWIM_OK;
+}
+
+// ==========================================================================
+// surrogate
+// ==========================================================================
+int surrogate_forward(swim_ctx* c, int64_t n, const float* X, const float* params, float* Y, void* stream)
+{
+    TRY(check_ctx(c));
+    if (n < 0 || (n > 0 && (!X || !params || !Y))) return fail(SWIM_EINVAL, "bad surrogate_forward arguments");
+    hipStream_t st = pick(c, stream);
+    const int64_t CH = 65536;
+    MlpAct a;
+    TRY(mlp_act(c, std::min(n, CH), &a));
+    for (int64_t r = 0; r < n; r += CH) {
+        const int64_t m = std::min(CH, n - r);
+        TRY(mlp_forward(X + r * MLP_W[0], params, m, a, Y + r * MLP_W[MLP_L], st));
+    }
+    return SWIM_OK;
+}
+
+int surrogate_grad(swim_ctx* c, int64_t n, const float* X, const float* T, const float* params, float* grads,
+                   float* loss, void* stream)
+{
+    TRY(check_ctx(c));
+    if (n < 1 || n > (1 << 20) || !X || !T || !params || !grads) return fail(SWIM_EINVAL, "bad surrogate_grad arguments");
+    hipStream_t st = pick(c, stream);
+    MlpAct a;
+    TRY(mlp_act(c, n, &a));
+    TRY(mlp_forward(X, params, n, a, a.Y, st));
+    TRY(mlp_backward(X, T, params, n, a, grads, loss, st));
+    return SWIM_OK;
+}
+
+int surrogate_train(swim_ctx* c, int64_t n, const float* X, const float* T, const int32_t* perm, int32_t epochs,
+                    int32_t batch, float lr, float* params, float* adam_m, float* adam_v, float* loss_out, void* stream)
+{
+    TRY(check_ctx(c));
+    if (n < 1 || epochs < 1 || batch < 1 || batch > n || batch > (1 << 16) || !(lr > 0) || !X || !T || !perm || !params ||
+        !adam_m || !adam_v)
+        return fail(SWIM_EINVAL, "bad surrogate_train arguments");
+    hipStream_t st = pick(c, stream);
+    MlpAct a;
+    TRY(mlp_act(c, batch, &a));
+    TRY(ensure(c, B_MLP_GRAD, (size_t)MLP_NPARAM * 4));
+    TRY(ensure(c, B_MLP_BATCH, (size_t)batch * (MLP_W[0] + MLP_W[MLP_L]) * 4));
+    float* G = (float*)c->buf[B_MLP_GRAD].p;
+    float* Xb = (float*)c->buf[B_MLP_BATCH].p;
+    float* Tb = Xb + (size_t)batch * MLP_W[0];
+    const int64_t spe = n / batch;
+    const double b1 = 0.9, b2 = 0.999;
+    int64_t t = 0;
+    for (int e = 0; e < epochs; ++e) {
+        for (int64_t s = 0; s < spe; ++s) {
+            ++t;
+            HIPCHK(launch_gather_rows(batch, perm + (int64_t)e * n + s * batch, n, X, MLP_W[0], T, MLP_W[MLP_L], Xb, Tb,
+                                      st));
+            TRY(mlp_forward(Xb, params, batch, a, a.Y, st));
+            TRY(mlp_backward(Xb, Tb, params, batch, a, G, loss_out ? loss_out + e * spe + s : nullptr, st));
+            HIPCHK(launch_adam(MLP_NPARAM, params, G, adam_m, adam_v, lr, (float)b1, (float)b2,
+                               (float)(1.0 - std::pow(b1, (double)t)), (float)(1.0 - std::pow(b2, (double)t)), 1e-8f, st));
+        }
+    }
+    return SWIM_OK;
+}
+
+int surrogate_prescreen(swim_ctx* c, int64_t n, const float* X, const float* params, const float* out_mu,
+                        const float* out_sd, const float* obs_sum, int32_t n_sum, float tol, float* dist, uint8_t* keep,
+                        int64_t* idx, int64_t* n_keep, void* stream)
+{
+    TRY(check_ctx(c));
+    if (n < 1 || n_sum < 1 || n_sum > MLP_W[MLP_L] || !(tol >= 0) || !X || !params || !out_mu || !out_sd || !obs_sum ||
+        !keep || !idx || !n_keep)
+        return fail(SWIM_EINVAL, "bad surrogate_prescreen arguments");
+    hipStream_t st = pick(c, stream);
+    const int64_t CH = 65536;
+    MlpAct a;
+    TRY(mlp_act(c, std::min(n, CH), &a));
+    for (int64_t r = 0; r < n; r += CH) {
+        const int64_t m = std::min(CH, n - r);
+        TRY(mlp_forward(X + r * MLP_W[0], params, m, a, a.Y, st));
+        HIPCHK(launch_prescreen((int)m, MLP_W[MLP_L], n_sum, a.Y, out_mu, out_sd, obs_sum, tol, dist ? dist + r : nullptr,
+                                keep + r, st));
+    }
+    TRY(ensure(c, B_MLP_CNT, (size_t)((n + 255) / 256) * 4));
+    HIPCHK(launch_compact(n, keep, (int32_t*)c->buf[B_MLP_CNT].p, idx, n_keep, st));
+    return SWIM_OK;
+}
+
+int surrogate_features(swim_ctx* c, int64_t n, const double* theta, double b, double omega, const float* mu,
+                       const float* sd, float* X, void* stream)
+{
+    TRY(check_ctx(c));
+    if (n < 0 || (n > 0 && (!theta || !X)) || ((mu == nullptr) != (sd == nullptr)))
+        return fail(SWIM_EINVAL, "bad surrogate_features arguments");
+    HIPCHK(launch_features(n, theta, b, omega, mu, sd, X, pick(c, stream)));
+    return SWIM_OK;
+}
+
+int surrogate_targets(swim_ctx* c, int32_t dtype, int64_t n, int32_t n_obs, const void* obs, const void* speed,
+                      double x0, double y0, const int32_t* sum_idx, int32_t n_sum, float* T, void* stream)
+{
+    TRY(check_ctx(c));
+    TRY(check_dtype(dtype));
+    if (n < 0 || n_obs < 1 || n_sum < 1 || n_sum > 64 || !sum_idx || (n > 0 && (!obs || !speed || !T)))
+        return fail(SWIM_EINVAL, "bad surrogate_targets arguments");
+    for (int j = 0; j < n_sum; ++j)
+        if (sum_idx[j] < 0 || sum_idx[j] >= n_obs) return fail(SWIM_EINVAL, "summary index %d out of range", sum_idx[j]);
+    hipStream_t st = pick(c, stream);
+    TRY(begin_uploads(c, (size_t)n_sum * 4));
+    TRY(stage(c, sum_idx, (size_t)n_sum * 4, B_MLP_IDX, st));
+    TRY(end_uploads(c, st));
+    HIPCHK(launch_targets(dtype, n, n_obs, obs, speed, x0, y0, (const int32_t*)c->buf[B_MLP_IDX].p, n_sum, T, st));
+    return SWIM_OK;
+}
+
+int surrogate_colstats(swim_ctx* c, int64_t n, int32_t cols, const float* A, float* mu, float* sd, void* stream)
+{
+    TRY(check_ctx(c));
+    if (n < 1 || cols < 1 || !A || !mu || !sd) return fail(SWIM_EINVAL, "bad surrogate_colstats arguments");
+    HIPCHK(launch_colstats(n, cols, A, mu, sd, pick(c, stream)));
+    return SWIM_OK;
+}
+
+int surrogate_standardize(swim_ctx* c, int64_t n, int32_t cols, float* A, const float* mu, const float* sd,
+                          void* stream)
+{
+    TRY(check_ctx(c));
+    if (n < 0 || cols < 1 || (n > 0 && (!A || !mu || !sd))) return fail(SWIM_EINVAL, "bad surrogate_standardize arguments");
+    HIPCHK(launch_standardize(n, cols, A, mu, sd, pick(c, stream)));
+    return SWIM_OK;
+}
+
+int abc_prior_draw_device(swim_ctx* c, uint64_t seed, int64_t n, const double* lo, const double* hi, double* theta,
+                          void* stream)
+{
+    TRY(check_ctx(c));
+    if (n < 0 || !lo || !hi || (n > 0 && !theta)) return fail(SWIM_EINVAL, "bad prior-draw arguments");
+    for (int d = 0; d < 3; ++d)
+        if (!(std::isfinite(lo[d]) && std::isfinite(hi[d]) && hi[d] >= lo[d])) return fail(SWIM_EINVAL, "bad prior box");
+    HIPCHK(launch_prior_draw(seed, n, lo, hi, theta, pick(c, stream)));
+    return SWIM_OK;
+}
+
+int swim_param_rows(swim_ctx* c, int64_t cap, const int64_t* n_dev, const int64_t* idx, int64_t n_theta,
+                    const double* theta, double b, double omega, double k, double* rows, void* stream)
+{
+    TRY(check_ctx(c));
+    if (cap < 0 || n_theta < 0 || (cap > 0 && (!theta || !rows))) return fail(SWIM_EINVAL, "bad swim_param_rows arguments");
+    if (!idx && cap > n_theta) return fail(SWIM_EINVAL, "cap exceeds n_theta");
+    HIPCHK(launch_param_rows(cap, n_dev, idx, n_theta, theta, b, omega, k, rows, pick(c, stream)));
+    return SWIM_OK;
+}
+
+int swim_select(swim_ctx* c, int64_t n, const int32_t* values, int32_t want, uint8_t* keep, int64_t* idx,
+                int64_t* n_keep, void* stream)
+{
+    TRY(check_ctx(c));
+    if (n < 1 || !keep || !idx || !n_keep) return fail(SWIM_EINVAL, "bad swim_select arguments");
+    hipStream_t st = pick(c, stream);
+    if (values) HIPCHK(launch_flag_eq(n, values, want, keep, st));
+    TRY(ensure(c, B_MLP_CNT, (size_t)((n + 255) / 256) * 4));
+    HIPCHK(launch_compact(n, keep, (int32_t*)c->buf[B_MLP_CNT].p, idx, n_keep, st));
+    return SWIM_OK;
+}
+
+int swim_gather_rows(swim_ctx* c, int64_t cap, const int64_t* n_dev, const int64_t* idx, int64_t n_src,
+                     const float* src, int32_t cols, float* dst, void* stream)
+{
+    TRY(check_ctx(c));
+    if (cap < 0 || cols < 1 || n_src < 0 || (cap > 0 && (!n_dev || !idx || !src || !dst)))
+        return fail(SWIM_EINVAL, "bad swim_gather_rows arguments");
+    HIPCHK(launch_gather_f32(cap, n_dev, idx, n_src, src, cols, dst, pick(c, stream)));
     return SWIM_OK;
 }
 

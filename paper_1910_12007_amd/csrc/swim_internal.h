@@ -79,4 +79,37 @@ hipError_t launch_select_kth(int64_t n, const double* v, int64_t k, double* out,
 hipError_t launch_accept(int64_t n, const double* dist, const double* tol, uint8_t* acc,
                          hipStream_t st);
 
+// surrogate MLP (swim_mlp.hip)
+hipError_t launch_gemm_bf16(int epi, int M, int N, int K, const float* A, int64_t sam, int64_t sak,
+                            const float* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc,
+                            const float* bias, float* aux, hipStream_t st);
+hipError_t launch_colsum(int M, int N, const float* A, int64_t lda, float* out, hipStream_t st);
+hipError_t launch_mse_grad(int M, int N, const float* Y, const float* T, float* dY, float* rowsq,
+                           hipStream_t st);
+hipError_t launch_gather_rows(int M, const int32_t* perm, int64_t nrows, const float* X, int nx,
+                              const float* T, int nt, float* Xb, float* Tb, hipStream_t st);
+hipError_t launch_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                       float b2, float c1, float c2, float eps, hipStream_t st);
+hipError_t launch_prescreen(int M, int N, int n_sum, const float* Y, const float* mu,
+                            const float* sd, const float* obs, float tol, float* dist,
+                            uint8_t* keep, hipStream_t st);
+hipError_t launch_compact(int64_t n, const uint8_t* keep, int32_t* counts, int64_t* idx,
+                          int64_t* total, hipStream_t st);
+hipError_t launch_features(int64_t n, const double* theta, double b, double om, const float* mu,
+                           const float* sd, float* X, hipStream_t st);
+hipError_t launch_targets(int dtype, int64_t n, int n_obs, const void* obs, const void* speed,
+                          double x0, double y0, const int32_t* idx, int n_sum, float* T,
+                          hipStream_t st);
+hipError_t launch_colstats(int64_t n, int cols, const float* A, float* mu, float* sd, hipStream_t st);
+hipError_t launch_standardize(int64_t n, int cols, float* A, const float* mu, const float* sd,
+                              hipStream_t st);
+hipError_t launch_prior_draw(uint64_t seed, int64_t n, const double* lo, const double* hi,
+                             double* theta, hipStream_t st);
+hipError_t launch_param_rows(int64_t cap, const int64_t* n_dev, const int64_t* idx, int64_t n_theta,
+                             const double* theta, double b, double om, double kw, double* rows,
+                             hipStream_t st);
+hipError_t launch_gather_f32(int64_t cap, const int64_t* n_dev, const int64_t* idx, int64_t n_src,
+                             const float* src, int cols, float* dst, hipStream_t st);
+hipError_t launch_flag_eq(int64_t n, const int32_t* v, int32_t want, uint8_t* keep, hipStream_t st);
+
 }  // namespace swim

@@ -13,6 +13,7 @@
 #include <stdint.h>
 
 #include "swim_internal.h"
+#include "swim_philox.h"
 
 namespace swim {
 
@@ -152,16 +153,19 @@ __global__ void k_mse_grad(int M, int N, const float* Y, const float* T, float* 
     if (rowsq) rowsq[m] = sq;
 }
 
-// rows of X and T picked by perm[0..M) into the batch buffers
-__global__ void k_gather_rows(int M, const int32_t* perm, const float* X, int nx, const float* T, int nt, float* Xb,
-                              float* Tb)
+// rows of X and T picked by perm[0..M) into the batch buffers; an index
+// outside [0, nrows) yields a NaN row (the loss turns NaN) instead of a read
+// out of bounds
+__global__ void k_gather_rows(int M, const int32_t* perm, int64_t nrows, const float* X, int nx, const float* T, int nt,
+                              float* Xb, float* Tb)
 {
     const int m = blockIdx.x;
     if (m >= M) return;
     const int64_t src = perm[m];
+    const bool ok = src >= 0 && src < nrows;
     for (int c = threadIdx.x; c < nx + nt; c += blockDim.x) {
-        if (c < nx) Xb[(int64_t)m * nx + c] = X[src * nx + c];
-        else Tb[(int64_t)m * nt + c - nx] = T[src * nt + c - nx];
+        if (c < nx) Xb[(int64_t)m * nx + c] = ok ? X[src * nx + c] : NAN;
+        else Tb[(int64_t)m * nt + c - nx] = ok ? T[src * nt + c - nx] : NAN;
     }
 }
 
@@ -273,10 +277,10 @@ hipError_t launch_mse_grad(int M, int N, const float* Y, const float* T, float* 
     return hipGetLastError();
 }
 
-hipError_t launch_gather_rows(int M, const int32_t* perm, const float* X, int nx, const float* T, int nt, float* Xb,
-                              float* Tb, hipStream_t st)
+hipError_t launch_gather_rows(int M, const int32_t* perm, int64_t nrows, const float* X, int nx, const float* T, int nt,
+                              float* Xb, float* Tb, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gather_rows, dim3(M), dim3(64), 0, st, M, perm, X, nx, T, nt, Xb, Tb);
+    hipLaunchKernelGGL(k_gather_rows, dim3(M), dim3(64), 0, st, M, perm, nrows, X, nx, T, nt, Xb, Tb);
     return hipGetLastError();
 }
 
@@ -303,6 +307,210 @@ hipError_t launch_compact(int64_t n, const uint8_t* keep, int32_t* counts, int64
     hipLaunchKernelGGL(k_count_blocks, dim3((unsigned)nb), dim3(256), 0, st, n, keep, counts);
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(64), 0, st, nb, counts, total);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)nb), dim3(256), 0, st, n, keep, counts, idx);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// surrogate data preparation
+// ---------------------------------------------------------------------------
+// X[i] = (alpha, ln S_b, ln S_s, b, omega), standardized when mu/sd are given
+__global__ void k_features(int64_t n, const double* theta, double b, double om, const float* mu, const float* sd,
+                           float* X)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double f[5] = {theta[3 * i], log(theta[3 * i + 1]), log(theta[3 * i + 2]), b, om};
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        float v = (float)f[c];
+        if (mu) v = (v - mu[c]) / sd[c];
+        X[i * 5 + c] = v;
+    }
+}
+
+// T[i] = (head displacement at the chosen samples, x then y, ..., speed)
+template <typename T>
+__global__ void k_targets(int64_t n, int n_obs, const T* obs, const T* speed, double x0, double y0, const int32_t* idx,
+                          int n_sum, float* Tout)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int nt = 2 * n_sum + 1;
+    for (int j = 0; j < n_sum; ++j) {
+        const T* o = obs + (i * n_obs + idx[j]) * 2;
+        Tout[i * nt + 2 * j] = (float)((double)o[0] - x0);
+        Tout[i * nt + 2 * j + 1] = (float)((double)o[1] - y0);
+    }
+    Tout[i * nt + 2 * n_sum] = (float)speed[i];
+}
+
+// column mean and standard deviation (population), one workgroup per column,
+// fixed summation order
+__global__ __launch_bounds__(256) void k_colstats(int64_t n, int cols, const float* A, float* mu, float* sd)
+{
+    __shared__ double red[256];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)A[i * cols + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double m = red[0] / (double)n;
+    __syncthreads();
+    double q = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double d = (double)A[i * cols + c] - m;
+        q += d * d;
+    }
+    red[threadIdx.x] = q;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        mu[c] = (float)m;
+        const double v = red[0] / (double)n;
+        sd[c] = v > 0.0 ? (float)sqrt(v) : 1.0f;
+    }
+}
+
+__global__ void k_standardize(int64_t n, int cols, float* A, const float* mu, const float* sd)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * cols) return;
+    const int c = (int)(e % cols);
+    A[e] = (A[e] - mu[c]) / sd[c];
+}
+
+// prior draws on the device, identical to the host abc_prior_draw:
+// theta[i][d] = lo[d] + (hi[d] - lo[d]) u_d, u from Philox stream 0, draws 0, 1
+__global__ void k_prior_draw(uint64_t seed, int64_t n, double lo0, double lo1, double lo2, double hi0, double hi1,
+                             double hi2, double* theta)
+{
+    // separately rounded multiply and add, as the host draw computes them
+    // (the default contraction would fuse them into one FMA)
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double u[4];
+    philox_uniforms2(seed, 0, (uint64_t)i, 0, u);
+    philox_uniforms2(seed, 0, (uint64_t)i, 1, u + 2);
+    const double lo[3] = {lo0, lo1, lo2}, hi[3] = {hi0, hi1, hi2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) theta[3 * i + d] = lo[d] + (hi[d] - lo[d]) * u[d];
+}
+
+// param rows (alpha, S_b, S_s, b, omega, k, 0, 0, 0) of the theta rows idx[j]
+// (idx NULL: j itself), j < *n_dev; an index outside [0, n_theta) gives a
+// NaN row (that system is then flagged SWIM_ST_BADPARAM)
+__global__ void k_param_rows(int64_t cap, const int64_t* n_dev, const int64_t* idx, int64_t n_theta,
+                             const double* theta, double b, double om, double kw, double* rows)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cap || (n_dev && j >= *n_dev)) return;
+    const int64_t i = idx ? idx[j] : j;
+    const bool ok = i >= 0 && i < n_theta;
+    double* P = rows + 9 * j;
+    P[0] = ok ? theta[3 * i] : NAN;
+    P[1] = ok ? theta[3 * i + 1] : NAN;
+    P[2] = ok ? theta[3 * i + 2] : NAN;
+    P[3] = b;
+    P[4] = om;
+    P[5] = kw;
+    P[6] = 0.0;
+    P[7] = 0.0;
+    P[8] = 0.0;
+}
+
+// dst[j] = src[idx[j]] (rows of `cols` floats), j < *n_dev; an index outside
+// [0, n_src) gives a NaN row
+__global__ void k_gather_f32(int64_t cap, const int64_t* n_dev, const int64_t* idx, int64_t n_src, const float* src,
+                             int cols, float* dst)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = e / cols;
+    if (j >= cap || j >= *n_dev) return;
+    const int c = (int)(e % cols);
+    const int64_t i = idx[j];
+    dst[j * cols + c] = (i >= 0 && i < n_src) ? src[i * cols + c] : NAN;
+}
+
+__global__ void k_flag_eq(int64_t n, const int32_t* v, int32_t want, uint8_t* keep)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) keep[i] = v[i] == want ? 1 : 0;
+}
+
+hipError_t launch_features(int64_t n, const double* theta, double b, double om, const float* mu, const float* sd,
+                           float* X, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, theta, b, om, mu, sd, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_targets(int dtype, int64_t n, int n_obs, const void* obs, const void* speed, double x0, double y0,
+                          const int32_t* idx, int n_sum, float* T, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const dim3 g((unsigned)((n + 255) / 256));
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_targets<float>, g, dim3(256), 0, st, n, n_obs, (const float*)obs, (const float*)speed, x0,
+                           y0, idx, n_sum, T);
+    else
+        hipLaunchKernelGGL(k_targets<double>, g, dim3(256), 0, st, n, n_obs, (const double*)obs, (const double*)speed,
+                           x0, y0, idx, n_sum, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_colstats(int64_t n, int cols, const float* A, float* mu, float* sd, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_colstats, dim3(cols), dim3(256), 0, st, n, cols, A, mu, sd);
+    return hipGetLastError();
+}
+
+hipError_t launch_standardize(int64_t n, int cols, float* A, const float* mu, const float* sd, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_standardize, dim3((unsigned)((n * cols + 255) / 256)), dim3(256), 0, st, n, cols, A, mu, sd);
+    return hipGetLastError();
+}
+
+hipError_t launch_prior_draw(uint64_t seed, int64_t n, const double* lo, const double* hi, double* theta,
+                             hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prior_draw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, seed, n, lo[0], lo[1], lo[2],
+                       hi[0], hi[1], hi[2], theta);
+    return hipGetLastError();
+}
+
+hipError_t launch_param_rows(int64_t cap, const int64_t* n_dev, const int64_t* idx, int64_t n_theta,
+                             const double* theta, double b, double om, double kw, double* rows, hipStream_t st)
+{
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_param_rows, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, cap, n_dev, idx, n_theta,
+                       theta, b, om, kw, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_f32(int64_t cap, const int64_t* n_dev, const int64_t* idx, int64_t n_src, const float* src,
+                             int cols, float* dst, hipStream_t st)
+{
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_f32, dim3((unsigned)((cap * cols + 255) / 256)), dim3(256), 0, st, cap, n_dev, idx,
+                       n_src, src, cols, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_flag_eq(int64_t n, const int32_t* v, int32_t want, uint8_t* keep, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flag_eq, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, v, want, keep);
     return hipGetLastError();
 }
 

@@ -119,3 +119,35 @@ def surrogate_inputs(n, seed):
 def observation_noise(n_obs, sigma=1e-3, seed=20191027):
     rng = np.random.Generator(np.random.PCG64(seed))
     return sigma * rng.standard_normal((n_obs, 2))
+
+
+MLP_LAYERS = (5, 256, 256, 256, 256, 33)
+
+
+def mlp_init(seed=0, layers=MLP_LAYERS):
+    """He-uniform initial weights (U(+-sqrt(6/fan_in))) and zero biases, as a
+    list of (W, b) and as the flat FP32 vector of the library's layout
+    (per layer: W row-major fan_in x fan_out, then b)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    params = []
+    for a, b in zip(layers[:-1], layers[1:]):
+        lim = np.sqrt(6.0 / a)
+        params.append((rng.uniform(-lim, lim, (a, b)).astype(np.float32).astype(np.float64), np.zeros(b)))
+    flat = np.concatenate([np.concatenate([W.ravel(), b]) for W, b in params]).astype(np.float32)
+    return params, flat
+
+
+def unflatten(flat, layers=MLP_LAYERS):
+    out, o = [], 0
+    for a, b in zip(layers[:-1], layers[1:]):
+        W = np.asarray(flat[o:o + a * b], dtype=np.float64).reshape(a, b)
+        o += a * b
+        bb = np.asarray(flat[o:o + b], dtype=np.float64)
+        o += b
+        out.append((W, bb))
+    return out
+
+
+def epoch_permutations(n, epochs, seed=4):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)

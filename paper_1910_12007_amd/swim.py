@@ -18,6 +18,7 @@ SWIM_F32, SWIM_F64 = 0, 1
 SWIM_ST_OK, SWIM_ST_NONFINITE, SWIM_ST_BOUND, SWIM_ST_BADPARAM = 0, 1, 2, 3
 SWIM_NPARAM = 9
 SWIM_OPT_WPS, SWIM_OPT_BIG_TPL = 1, 2
+SWIM_MLP_NPARAM, SWIM_MLP_IN, SWIM_MLP_OUT = 207393, 5, 33
 
 _c = ctypes
 _P = _c.c_void_p
@@ -46,6 +47,22 @@ SIGNATURES = {
     "abc_step": (_c.c_int, [_P, _P, _DP, _c.c_int32, _c.c_int64, _I32P, _c.c_uint64, _c.c_int32, _DP, _DP,
                             _c.c_int64, _c.c_double, _DP, _DP, _U8P, _DP, _DP]),
     "swim_kernel_eval_host": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_double, _c.c_int64, _DP, _DP, _DP, _DP]),
+    "surrogate_forward": (_c.c_int, [_P, _c.c_int64, _P, _P, _P, _P]),
+    "surrogate_grad": (_c.c_int, [_P, _c.c_int64, _P, _P, _P, _P, _P, _P]),
+    "surrogate_train": (_c.c_int, [_P, _c.c_int64, _P, _P, _P, _c.c_int32, _c.c_int32, _c.c_float, _P, _P, _P, _P,
+                                   _P]),
+    "surrogate_prescreen": (_c.c_int, [_P, _c.c_int64, _P, _P, _P, _P, _P, _c.c_int32, _c.c_float, _P, _P, _P, _P,
+                                       _P]),
+    "surrogate_features": (_c.c_int, [_P, _c.c_int64, _P, _c.c_double, _c.c_double, _P, _P, _P, _P]),
+    "surrogate_targets": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _c.c_int32, _P, _P, _c.c_double, _c.c_double, _I32P,
+                                     _c.c_int32, _P, _P]),
+    "surrogate_colstats": (_c.c_int, [_P, _c.c_int64, _c.c_int32, _P, _P, _P, _P]),
+    "surrogate_standardize": (_c.c_int, [_P, _c.c_int64, _c.c_int32, _P, _P, _P, _P]),
+    "abc_prior_draw_device": (_c.c_int, [_P, _c.c_uint64, _c.c_int64, _DP, _DP, _P, _P]),
+    "swim_param_rows": (_c.c_int, [_P, _c.c_int64, _P, _P, _c.c_int64, _P, _c.c_double, _c.c_double, _c.c_double, _P,
+                                   _P]),
+    "swim_select": (_c.c_int, [_P, _c.c_int64, _P, _c.c_int32, _P, _P, _P, _P]),
+    "swim_gather_rows": (_c.c_int, [_P, _c.c_int64, _P, _P, _c.c_int64, _P, _c.c_int32, _P, _P]),
 }
 
 _LIB = None
@@ -240,3 +257,74 @@ def swim_kernel_eval_host(dtype, alpha, eps, t):
     _check(lib().swim_kernel_eval_host(int(dtype), float(alpha), float(eps), t_.size, t_p,
                                        h1t.ctypes.data_as(_DP), h2.ctypes.data_as(_DP), ctypes.byref(h1c)))
     return h1t, h2, h1c.value
+
+
+# --------------------------------------------------------------------------
+# surrogate (device tensors unless noted)
+# --------------------------------------------------------------------------
+def surrogate_forward(ctx, X, params, Y, stream=None):
+    return _check(lib().surrogate_forward(ctx.handle, X.shape[0], _dptr(X), _dptr(params), _dptr(Y), _stream(stream)))
+
+
+def surrogate_grad(ctx, X, T, params, grads, loss=None, stream=None):
+    return _check(lib().surrogate_grad(ctx.handle, X.shape[0], _dptr(X), _dptr(T), _dptr(params), _dptr(grads),
+                                       _dptr(loss), _stream(stream)))
+
+
+def surrogate_train(ctx, X, T, perm, epochs, batch, lr, params, adam_m, adam_v, loss_out=None, stream=None):
+    return _check(lib().surrogate_train(ctx.handle, X.shape[0], _dptr(X), _dptr(T), _dptr(perm), int(epochs),
+                                        int(batch), float(lr), _dptr(params), _dptr(adam_m), _dptr(adam_v),
+                                        _dptr(loss_out), _stream(stream)))
+
+
+def surrogate_prescreen(ctx, X, params, out_mu, out_sd, obs_sum, n_sum, tol, keep, idx, n_keep, dist=None,
+                        stream=None):
+    return _check(lib().surrogate_prescreen(ctx.handle, X.shape[0], _dptr(X), _dptr(params), _dptr(out_mu),
+                                            _dptr(out_sd), _dptr(obs_sum), int(n_sum), float(tol), _dptr(dist),
+                                            _dptr(keep), _dptr(idx), _dptr(n_keep), _stream(stream)))
+
+
+def surrogate_features(ctx, theta, b, omega, X, mu=None, sd=None, stream=None):
+    return _check(lib().surrogate_features(ctx.handle, theta.shape[0], _dptr(theta), float(b), float(omega),
+                                           _dptr(mu), _dptr(sd), _dptr(X), _stream(stream)))
+
+
+def surrogate_targets(ctx, obs, speed, x0, y0, sum_idx, T, stream=None):
+    si, si_p = _h(sum_idx, np.int32, _I32P)
+    return _check(lib().surrogate_targets(ctx.handle, dtype_code(obs), obs.shape[0], obs.shape[1], _dptr(obs),
+                                          _dptr(speed), float(x0), float(y0), si_p, len(si), _dptr(T),
+                                          _stream(stream)))
+
+
+def surrogate_colstats(ctx, A, mu, sd, stream=None):
+    return _check(lib().surrogate_colstats(ctx.handle, A.shape[0], A.shape[1], _dptr(A), _dptr(mu), _dptr(sd),
+                                           _stream(stream)))
+
+
+def surrogate_standardize(ctx, A, mu, sd, stream=None):
+    return _check(lib().surrogate_standardize(ctx.handle, A.shape[0], A.shape[1], _dptr(A), _dptr(mu), _dptr(sd),
+                                              _stream(stream)))
+
+
+def abc_prior_draw_device(ctx, seed, lo, hi, theta, stream=None):
+    lo_, lo_p = _h(lo, np.float64, _DP)
+    hi_, hi_p = _h(hi, np.float64, _DP)
+    return _check(lib().abc_prior_draw_device(ctx.handle, int(seed), theta.shape[0], lo_p, hi_p, _dptr(theta),
+                                              _stream(stream)))
+
+
+def swim_param_rows(ctx, theta, b, omega, k, rows, idx=None, n_dev=None, cap=None, stream=None):
+    cap = rows.shape[0] if cap is None else cap
+    return _check(lib().swim_param_rows(ctx.handle, int(cap), _dptr(n_dev), _dptr(idx), theta.shape[0], _dptr(theta),
+                                        float(b), float(omega), float(k), _dptr(rows), _stream(stream)))
+
+
+def swim_select(ctx, keep, idx, n_keep, values=None, want=0, stream=None):
+    return _check(lib().swim_select(ctx.handle, keep.numel(), _dptr(values), int(want), _dptr(keep), _dptr(idx),
+                                    _dptr(n_keep), _stream(stream)))
+
+
+def swim_gather_rows(ctx, idx, n_dev, src, dst, cap=None, stream=None):
+    cap = dst.shape[0] if cap is None else cap
+    return _check(lib().swim_gather_rows(ctx.handle, int(cap), _dptr(n_dev), _dptr(idx), src.shape[0], _dptr(src),
+                                         src.shape[1], _dptr(dst), _stream(stream)))
