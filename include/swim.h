@@ -151,8 +151,11 @@ int swim_forward(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const int32_t *N,
 int abc_distance(swim_ctx *ctx, int32_t dtype, int64_t n, int32_t n_obs, const void *obs,
                  const double *data, const int32_t *status, double *dist, void *stream);
 
-/* Percentile tolerance: tol = k-th smallest of dist[0..n), k = ceil(q*n)
- * clamped to [1, n]; accept[i] = dist[i] <= tol (ties accepted).
+/* Percentile tolerance over the completed runs: tol = k-th smallest finite
+ * value of dist[0..n), k = ceil(q * n_f) clamped to [1, n_f], n_f the
+ * number of finite distances (failed runs carry +inf and are rejected);
+ * tol = +inf when n_f = 0.  accept[i] = dist[i] finite and <= tol (ties
+ * accepted).
  * dist device double[n]; tol device double[1] (written);
  * accept device uint8[n] (written) or NULL.  Asynchronous. */
 int abc_select(swim_ctx *ctx, int64_t n, const double *dist, double q, double *tol,

@@ -7,8 +7,11 @@ eq. (model_err).  Definitions used:
 
 * distance  d_i = sqrt( mean over the n_obs head samples and both coordinates
   of (obs_i - data)^2 );  a failed forward run has d_i = +inf.
-* tolerance tol = the k-th smallest distance, k = ceil(q * P) (1-based);
-  accept d_i <= tol (ties accepted).
+* tolerance tol = the k-th smallest finite distance, k = ceil(q * P_f)
+  (1-based), P_f the number of forward runs that completed (finite d_i):
+  failed runs are rejected and take no part in the percentile.  With no
+  completed run tol = +inf.  accept d_i <= tol for finite d_i (ties
+  accepted).
 * prior: uniform box on (alpha, S_b, S_s), linear scale.
 * PMC (Beaumont, Cornuet, Marin & Robert 2009): proposals resample the previous
   accepted population by its normalized weights and perturb with a Gaussian of
@@ -37,15 +40,19 @@ def distance(obs, data):
 
 
 def tolerance(d, q):
-    """k-th smallest distance with k = ceil(q P)."""
+    """k-th smallest finite distance with k = ceil(q P_f)."""
     d = np.asarray(d, dtype=np.float64)
-    k = int(np.ceil(q * d.size))
-    k = min(max(k, 1), d.size)
-    return float(np.sort(d)[k - 1])
+    f = np.sort(d[np.isfinite(d)])
+    if f.size == 0:
+        return float("inf")
+    k = int(np.ceil(q * f.size))
+    k = min(max(k, 1), f.size)
+    return float(f[k - 1])
 
 
 def accept(d, tol):
-    return np.asarray(d) <= tol
+    d = np.asarray(d)
+    return np.isfinite(d) & (d <= tol)
 
 
 def prior_draw(seed, n, lo, hi):

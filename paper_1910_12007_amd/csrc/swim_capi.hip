@@ -614,10 +614,8 @@ int abc_select(swim_ctx* c, int64_t n, const double* dist, double q, double* tol
     if (n < 1) return fail(SWIM_EINVAL, "n must be >= 1");
     if (!(q > 0 && q <= 1)) return fail(SWIM_EINVAL, "quantile must be in (0, 1]");
     if (!dist || !tol) return fail(SWIM_EINVAL, "null device pointer");
-    int64_t k = (int64_t)std::ceil(q * (double)n);
-    k = std::min<int64_t>(std::max<int64_t>(k, 1), n);
     hipStream_t st = pick(c, stream);
-    HIPCHK(launch_select_kth(n, dist, k, tol, st));
+    HIPCHK(launch_select_kth(n, dist, q, tol, st));
     if (accept) HIPCHK(launch_accept(n, dist, tol, accept, st));
     return SWIM_OK;
 }
@@ -774,9 +772,7 @@ int abc_step(swim_ctx* c, const abc_model* m, const double* data, int32_t n_obs,
                      c->buf[B_SPEED].p, (int32_t*)c->buf[B_STATUS].p, nullptr, st));
     HIPCHK(launch_abc_distance(m->dtype, n, n_obs, c->buf[B_OBS].p, (const double*)c->buf[B_DATA].p,
                                (const int32_t*)c->buf[B_STATUS].p, (double*)c->buf[B_DIST].p, st));
-    int64_t k = (int64_t)std::ceil(q * (double)n);
-    k = std::min<int64_t>(std::max<int64_t>(k, 1), n);
-    HIPCHK(launch_select_kth(n, (const double*)c->buf[B_DIST].p, k, (double*)c->buf[B_TOL].p, st));
+    HIPCHK(launch_select_kth(n, (const double*)c->buf[B_DIST].p, q, (double*)c->buf[B_TOL].p, st));
     HIPCHK(launch_accept(n, (const double*)c->buf[B_DIST].p, (const double*)c->buf[B_TOL].p, (uint8_t*)c->buf[B_ACC].p, st));
     HIPCHK(hipMemcpyAsync(dist_out, c->buf[B_DIST].p, (size_t)n * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(accept_out, c->buf[B_ACC].p, (size_t)n, hipMemcpyDeviceToHost, st));

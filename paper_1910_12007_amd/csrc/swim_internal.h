@@ -75,7 +75,7 @@ hipError_t launch_abc_distance(int dtype, int64_t n, int32_t n_obs, const void* 
                                const double* data, const int32_t* status, double* dist,
                                hipStream_t st);
 // k-th smallest (1-based) of n doubles -> *out (device); single workgroup radix select
-hipError_t launch_select_kth(int64_t n, const double* v, int64_t k, double* out, hipStream_t st);
+hipError_t launch_select_kth(int64_t n, const double* v, double q, double* out, hipStream_t st);
 hipError_t launch_accept(int64_t n, const double* dist, const double* tol, uint8_t* acc,
                          hipStream_t st);
 

@@ -736,13 +736,31 @@ __device__ __forceinline__ double dunkey(uint64_t k)
     return __longlong_as_double(u);
 }
 
-__global__ __launch_bounds__(1024) void k_select_kth(int64_t n, const double* v, int64_t k, double* out)
+// tolerance = k-th smallest finite value of v, k = ceil(q * n_finite)
+// clamped to [1, n_finite] (+inf when no value is finite): count the finite
+// values, then an 8-pass MSB-first radix select over the order-preserving
+// 64-bit keys of the doubles.  One workgroup.
+__global__ __launch_bounds__(1024) void k_select_kth(int64_t n, const double* v, double q, double* out)
 {
     __shared__ unsigned int hist[256];
     __shared__ uint64_t s_prefix, s_mask;
     __shared__ int64_t s_rank;
+    __shared__ unsigned long long s_nf;
     const int tid = threadIdx.x;
+    if (tid == 0) s_nf = 0;
+    __syncthreads();
+    unsigned long long nf = 0;
+    for (int64_t i = tid; i < n; i += blockDim.x) nf += isfinite(v[i]) ? 1 : 0;
+    atomicAdd(&s_nf, nf);
+    __syncthreads();
+    const int64_t n_fin = (int64_t)s_nf;
+    if (n_fin == 0) {
+        if (tid == 0) *out = INFINITY;
+        return;
+    }
     if (tid == 0) {
+        int64_t k = (int64_t)ceil(q * (double)n_fin);
+        k = k < 1 ? 1 : (k > n_fin ? n_fin : k);
         s_prefix = 0;
         s_mask = 0;
         s_rank = k - 1;
@@ -776,7 +794,7 @@ __global__ __launch_bounds__(1024) void k_select_kth(int64_t n, const double* v,
 __global__ void k_accept(int64_t n, const double* dist, const double* tol, uint8_t* acc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) acc[i] = dist[i] <= *tol ? 1 : 0;
+    if (i < n) acc[i] = (isfinite(dist[i]) && dist[i] <= *tol) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1004,9 +1022,9 @@ hipError_t launch_abc_distance(int dtype, int64_t n, int32_t n_obs, const void* 
     return hipGetLastError();
 }
 
-hipError_t launch_select_kth(int64_t n, const double* v, int64_t k, double* out, hipStream_t st)
+hipError_t launch_select_kth(int64_t n, const double* v, double q, double* out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_select_kth, dim3(1), dim3(1024), 0, st, n, v, k, out);
+    hipLaunchKernelGGL(k_select_kth, dim3(1), dim3(1024), 0, st, n, v, q, out);
     return hipGetLastError();
 }
 

@@ -35,8 +35,15 @@ def test_tolerance_is_inverted_cdf_quantile():
     d = rng.exponential(size=4096)
     for q in (0.05, 0.1, 0.25, 0.5):
         assert abs(abc.tolerance(d, q) - np.quantile(d, q, method="inverted_cdf")) == 0
+    # failed runs (d = inf) are rejected and excluded from the percentile
     d[::7] = np.inf
-    assert abc.accept(d, abc.tolerance(d, 0.05)).sum() == int(np.ceil(0.05 * d.size))
+    nf = int(np.isfinite(d).sum())
+    assert abc.tolerance(d, 0.05) == np.quantile(d[np.isfinite(d)], 0.05, method="inverted_cdf")
+    assert abc.accept(d, abc.tolerance(d, 0.05)).sum() == int(np.ceil(0.05 * nf))
+    assert abc.accept(d, abc.tolerance(d, 1.0)).sum() == nf
+    # no completed run: nothing is accepted
+    assert abc.tolerance(np.full(5, np.inf), 0.5) == np.inf
+    assert not abc.accept(np.full(5, np.inf), np.inf).any()
 
 
 def test_distance_definition():
