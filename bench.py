@@ -12,7 +12,9 @@ resident in device memory before the timed region.
 
 Prints one JSON line.  value = Brinkmanlet pair evaluations per second
 (ordered pairs i, j of one system, self included, per completed Euler step;
-runs that blow up count only the steps they computed).
+runs that blow up count only the steps they computed).  The line also
+carries the surrogate-prescreened ABC comparison (accepted samples per
+second of both methods on the same 1M prior draws; --no-surrogate skips it).
 """
 import argparse
 import json
@@ -54,6 +56,30 @@ def cpu_baseline(steps_cpu):
                       f"{dt:.1f} s"}
 
 
+def surrogate_leg(ctx, data):
+    """Surrogate-prescreened ABC against plain batched ABC on the same 1M
+    prior draws (tolerance: the 5th percentile of the completed runs of the
+    4096-draw batch; MLP trained on 65536 completed runs)."""
+    from paper_1910_12007_amd import surrogate_abc
+    r = surrogate_abc.run(ctx, data)
+    s, p, t = r["surrogate"], r["plain"], r["training"]
+    return {
+        "tolerance": r["tol"], "prescreen_factor": r["factor"], "proposals": s["proposals"],
+        "plain_accepted": p["accepted"], "plain_seconds": p["seconds"], "plain_accepts_per_s": p["accepts_per_s"],
+        "survivors": s["survivors"], "surrogate_accepted": s["accepted"], "prescreen_ms": s["ms_prescreen"],
+        "rerun_ms": s["ms_rerun"], "surrogate_accepts_per_s": s["accepts_per_s"], "gain": r["gain"],
+        "recall": s["recall"], "accepted_not_in_plain": s["not_in_plain"],
+        "posterior_mean_rel_err": [float(x) for x in r["mean_rel_err"]],
+        "intervals_overlap": [bool(x) for x in r["intervals_overlap"]],
+        "posterior_mean_plain": [float(x) for x in p["post"]["mean"]],
+        "posterior_mean_surrogate": [float(x) for x in s["post"]["mean"]],
+        "training_rows": t["rows"], "training_draws": t["draws"], "training_steps": t["steps"],
+        "training_set_s": t["t_data"], "training_s": t["t_train"],
+        "surrogate_accepts_per_s_with_training": s["accepts_per_s_with_training"],
+        "gain_with_training": r["gain_with_training"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +90,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=1200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--wps", type=int, default=0, help="waves per system (0: library default)")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-prescreened ABC comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the swimmer batches are "
@@ -148,6 +175,8 @@ def main():
                      "kernel": "k_forward<float,2,wps> (persistent forward run)",
                      "kernel_ms": fwd_ms, "flop_per_pair": FLOP_PER_PAIR},
     }
+    if not args.no_surrogate:
+        out["surrogate_abc"] = surrogate_leg(ctx, load_data())
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     ctx.close()

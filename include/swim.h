@@ -295,6 +295,43 @@ int swim_select(swim_ctx *ctx, int64_t n, const int32_t *values, int32_t want, u
 int swim_gather_rows(swim_ctx *ctx, int64_t cap, const int64_t *n_dev, const int64_t *idx,
                      int64_t n_src, const float *src, int32_t cols, float *dst, void *stream);
 
+/* Training set of the surrogate, end to end on the device: n_runs prior
+ * draws (abc_prior_draw values, Philox seed), one forward run each with N
+ * points (model's steps, dt, dtype), inputs (alpha, ln S_b, ln S_s, b,
+ * omega) and targets (head displacement from its start (1, 0) at the
+ * observation indices sum_idx[0..n_sum), then the mean speed).  Runs that
+ * did not complete (status != 0), or whose head moved farther than
+ * max_disp (> 0) from its start in either coordinate at a summary time (an
+ * Euler instability still below the blow-up bound), are dropped; the first
+ * min(kept, cap) kept runs, in draw order, are written to X (device float[cap][5])
+ * and T (device float[cap][33]) standardized by their own column mean and
+ * standard deviation, returned in in_mu, in_sd (device float[5]) and
+ * out_mu, out_sd (device float[33]).  n_sum must be 16; *n_out (host) =
+ * rows written.  Synchronizes once (for the count). */
+int surrogate_dataset(swim_ctx *ctx, const abc_model *model, int32_t N, int64_t n_runs,
+                      uint64_t seed, const int32_t *sum_idx, int32_t n_sum, double max_disp,
+                      int64_t cap, float *X, float *T, float *in_mu, float *in_sd, float *out_mu,
+                      float *out_sd, int64_t *n_out, void *stream);
+
+/* Surrogate-prescreened rejection ABC, end to end (synchronous; runs on the
+ * context's stream).  n_prop prior draws (abc_prior_draw values, Philox
+ * seed) on the device; the surrogate (params, input and output
+ * standardization) predicts their summaries, and those whose surrogate
+ * distance to the observed summaries (data at sum_idx minus the head's
+ * start (1, 0)) is <= factor * tol survive.  The first min(survivors, cap)
+ * survivors, in draw order, are re-run on the plain forward model (N
+ * points, model's steps, dt, dtype) and accepted when their ABC distance to
+ * data (host double[n_obs][2]) is finite and <= tol.  Host outputs:
+ * theta_out double[cap][3], dist_out double[cap], accept_out uint8[cap],
+ * *n_surv = survivors (may exceed cap), ms_out float[2] (prescreen and
+ * re-run milliseconds on the device) or NULL. */
+int abc_prescreened(swim_ctx *ctx, const abc_model *model, int32_t N, const float *params,
+                    const float *in_mu, const float *in_sd, const float *out_mu,
+                    const float *out_sd, const int32_t *sum_idx, int32_t n_sum, const double *data,
+                    int32_t n_obs, double tol, double factor, int64_t n_prop, uint64_t seed,
+                    int64_t cap, double *theta_out, double *dist_out, uint8_t *accept_out,
+                    int64_t *n_surv, float *ms_out);
+
 /* Host evaluation of the device kernel functions (test hook): for squared
  * distances t[0..n) returns H1(t) - H1(0) and H2(t) as computed by the
  * kernels' own code compiled for the host, and H1(0) in *h1c. */

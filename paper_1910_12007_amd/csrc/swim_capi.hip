@@ -60,7 +60,8 @@ struct DevBuf {
 enum BufId {
     B_OFF, B_SWOFF, B_NPT, B_NSW, B_ORDER, B_LIST, B_BLKS, B_BLKF, B_ALPHA, B_EPS, B_SYSC, B_QUEUE,
     B_PARAMS, B_DATA, B_OBS, B_SPEED, B_STATUS, B_DIST, B_TOL, B_ACC, B_BIG,
-    B_MLP_ACT, B_MLP_GRAD, B_MLP_BATCH, B_MLP_IDX, B_MLP_CNT, B_NBUF
+    B_MLP_ACT, B_MLP_GRAD, B_MLP_BATCH, B_MLP_IDX, B_MLP_CNT,
+    B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_NBUF
 };
 
 // surrogate network: 5 -> 256 x 4 -> 33
@@ -837,6 +838,33 @@ int surrogate_forward(swim_ctx* c, int64_t n, const float* X, const float* param
     return SWIM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// surrogate distance of n standardized inputs in chunks of 65536 rows, then
+// the compaction of the kept rows
+int prescreen_impl(swim_ctx* c, int64_t n, const float* X, const float* params, const float* out_mu,
+                   const float* out_sd, const float* obs_sum, int32_t n_sum, float tol, float* dist, uint8_t* keep,
+                   int64_t* idx, int64_t* n_keep, hipStream_t st)
+{
+    const int64_t CH = 65536;
+    MlpAct a;
+    TRY(mlp_act(c, std::min(n, CH), &a));
+    for (int64_t r = 0; r < n; r += CH) {
+        const int64_t m = std::min(CH, n - r);
+        TRY(mlp_forward(X + r * MLP_W[0], params, m, a, a.Y, st));
+        HIPCHK(launch_prescreen((int)m, MLP_W[MLP_L], n_sum, a.Y, out_mu, out_sd, obs_sum, tol, dist ? dist + r : nullptr,
+                                keep + r, st));
+    }
+    TRY(ensure(c, B_MLP_CNT, (size_t)((n + 255) / 256) * 4));
+    HIPCHK(launch_compact(n, keep, (int32_t*)c->buf[B_MLP_CNT].p, idx, n_keep, st));
+    return SWIM_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int surrogate_grad(swim_ctx* c, int64_t n, const float* X, const float* T, const float* params, float* grads,
                    float* loss, void* stream)
 {
@@ -890,19 +918,8 @@ int surrogate_prescreen(swim_ctx* c, int64_t n, const float* X, const float* par
     if (n < 1 || n_sum < 1 || n_sum > MLP_W[MLP_L] || !(tol >= 0) || !X || !params || !out_mu || !out_sd || !obs_sum ||
         !keep || !idx || !n_keep)
         return fail(SWIM_EINVAL, "bad surrogate_prescreen arguments");
-    hipStream_t st = pick(c, stream);
-    const int64_t CH = 65536;
-    MlpAct a;
-    TRY(mlp_act(c, std::min(n, CH), &a));
-    for (int64_t r = 0; r < n; r += CH) {
-        const int64_t m = std::min(CH, n - r);
-        TRY(mlp_forward(X + r * MLP_W[0], params, m, a, a.Y, st));
-        HIPCHK(launch_prescreen((int)m, MLP_W[MLP_L], n_sum, a.Y, out_mu, out_sd, obs_sum, tol, dist ? dist + r : nullptr,
-                                keep + r, st));
-    }
-    TRY(ensure(c, B_MLP_CNT, (size_t)((n + 255) / 256) * 4));
-    HIPCHK(launch_compact(n, keep, (int32_t*)c->buf[B_MLP_CNT].p, idx, n_keep, st));
-    return SWIM_OK;
+    return prescreen_impl(c, n, X, params, out_mu, out_sd, obs_sum, n_sum, tol, dist, keep, idx, n_keep,
+                          pick(c, stream));
 }
 
 int surrogate_features(swim_ctx* c, int64_t n, const double* theta, double b, double omega, const float* mu,
@@ -992,4 +1009,192 @@ int swim_gather_rows(swim_ctx* c, int64_t cap, const int64_t* n_dev, const int64
     return SWIM_OK;
 }
 
+int surrogate_dataset(swim_ctx* c, const abc_model* m, int32_t N, int64_t n_runs, uint64_t seed, const int32_t* sum_idx,
+                      int32_t n_sum, double max_disp, int64_t cap, float* X, float* T, float* in_mu, float* in_sd,
+                      float* out_mu, float* out_sd, int64_t* n_out, void* stream)
+{
+    TRY(check_ctx(c));
+    if (!m || !sum_idx || !n_out || !X || !T || !in_mu || !in_sd || !out_mu || !out_sd)
+        return fail(SWIM_EINVAL, "null argument");
+    TRY(check_dtype(m->dtype));
+    if (n_runs < 1 || cap < 1) return fail(SWIM_EINVAL, "n_runs and cap must be >= 1");
+    if (!(max_disp > 0)) return fail(SWIM_EINVAL, "max_disp must be > 0");
+    if (2 * n_sum + 1 != MLP_W[MLP_L]) return fail(SWIM_EINVAL, "n_sum must be %d", (MLP_W[MLP_L] - 1) / 2);
+    if (m->obs_every < 1) return fail(SWIM_EINVAL, "obs_every must be >= 1");
+    const int32_t n_obs = m->steps / m->obs_every;
+    for (int j = 0; j < n_sum; ++j)
+        if (sum_idx[j] < 0 || sum_idx[j] >= n_obs) return fail(SWIM_EINVAL, "summary index %d out of range", sum_idx[j]);
+    for (int d = 0; d < 3; ++d)
+        if (!(std::isfinite(m->lo[d]) && std::isfinite(m->hi[d]) && m->hi[d] >= m->lo[d] && m->lo[d] >= 0))
+            return fail(SWIM_EINVAL, "bad prior box");
+    if (!(m->lo[1] > 0 && m->lo[2] > 0)) return fail(SWIM_EINVAL, "the prior of S_b and S_s must be positive (log inputs)");
+    std::vector<int32_t> Nv((size_t)n_runs, N);
+    TRY(check_run(n_runs, Nv.data(), nullptr, m->steps, m->dt, m->obs_every, m->eps_over_ds));
+    hipStream_t st = pick(c, stream);
+    const size_t es = m->dtype == SWIM_F32 ? 4 : 8;
+    const int nx = MLP_W[0], nt = MLP_W[MLP_L];
+    TRY(ensure(c, B_PS_THETA, (size_t)n_runs * 24));
+    TRY(ensure(c, B_PARAMS, (size_t)n_runs * SWIM_NPARAM * 8));
+    TRY(ensure(c, B_OBS, (size_t)n_runs * n_obs * 2 * es));
+    TRY(ensure(c, B_SPEED, (size_t)n_runs * es));
+    TRY(ensure(c, B_STATUS, (size_t)n_runs * 4));
+    TRY(ensure(c, B_PS_KEEP, (size_t)n_runs));
+    TRY(ensure(c, B_PS_IDX, (size_t)n_runs * 8));
+    TRY(ensure(c, B_PS_NK, 8));
+    TRY(ensure(c, B_PS_X, (size_t)n_runs * nx * 4));
+    TRY(ensure(c, B_DS_T, (size_t)n_runs * nt * 4));
+    double* theta = (double*)c->buf[B_PS_THETA].p;
+    double* rows = (double*)c->buf[B_PARAMS].p;
+    HIPCHK(launch_prior_draw(seed, n_runs, m->lo, m->hi, theta, st));
+    HIPCHK(launch_param_rows(n_runs, nullptr, nullptr, n_runs, theta, m->b, m->omega, m->k, rows, st));
+    Run r;
+    r.steps = m->steps;
+    r.dt = m->dt;
+    r.obs_every = m->obs_every;
+    r.n_obs = n_obs;
+    r.eps_over_ds = m->eps_over_ds;
+    TRY(forward_impl(c, m->dtype, n_runs, Nv.data(), nullptr, rows, r, c->buf[B_OBS].p, c->buf[B_SPEED].p,
+                     (int32_t*)c->buf[B_STATUS].p, nullptr, st));
+    float* Xall = (float*)c->buf[B_PS_X].p;
+    float* Tall = (float*)c->buf[B_DS_T].p;
+    HIPCHK(launch_features(n_runs, theta, m->b, m->omega, nullptr, nullptr, Xall, st));
+    TRY(begin_uploads(c, (size_t)n_sum * 4));
+    TRY(stage(c, sum_idx, (size_t)n_sum * 4, B_MLP_IDX, st));
+    TRY(end_uploads(c, st));
+    // the head starts at (L, 0) = (1, 0): parameter rows carry a zero offset
+    HIPCHK(launch_targets(m->dtype, n_runs, n_obs, c->buf[B_OBS].p, c->buf[B_SPEED].p, 1.0, 0.0,
+                          (const int32_t*)c->buf[B_MLP_IDX].p, n_sum, Tall, st));
+    uint8_t* keep = (uint8_t*)c->buf[B_PS_KEEP].p;
+    int64_t* idx = (int64_t*)c->buf[B_PS_IDX].p;
+    int64_t* nk = (int64_t*)c->buf[B_PS_NK].p;
+    HIPCHK(launch_flag_eq(n_runs, (const int32_t*)c->buf[B_STATUS].p, SWIM_ST_OK, keep, st));
+    HIPCHK(launch_flag_bounded(n_runs, Tall, nt, 2 * n_sum, (float)max_disp, keep, st));
+    TRY(ensure(c, B_MLP_CNT, (size_t)((n_runs + 255) / 256) * 4));
+    HIPCHK(launch_compact(n_runs, keep, (int32_t*)c->buf[B_MLP_CNT].p, idx, nk, st));
+    int64_t n_keep = 0;
+    HIPCHK(hipMemcpyAsync(&n_keep, nk, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int64_t n = std::min(n_keep, cap);
+    *n_out = n;
+    if (n == 0) return SWIM_OK;
+    HIPCHK(launch_gather_f32(n, nk, idx, n_runs, Xall, nx, X, st));
+    HIPCHK(launch_gather_f32(n, nk, idx, n_runs, Tall, nt, T, st));
+    HIPCHK(launch_colstats(n, nx, X, in_mu, in_sd, st));
+    HIPCHK(launch_standardize(n, nx, X, in_mu, in_sd, st));
+    HIPCHK(launch_colstats(n, nt, T, out_mu, out_sd, st));
+    HIPCHK(launch_standardize(n, nt, T, out_mu, out_sd, st));
+    return SWIM_OK;
+}
+
+int abc_prescreened(swim_ctx* c, const abc_model* m, int32_t N, const float* params, const float* in_mu,
+                    const float* in_sd, const float* out_mu, const float* out_sd, const int32_t* sum_idx,
+                    int32_t n_sum, const double* data, int32_t n_obs, double tol, double factor, int64_t n_prop,
+                    uint64_t seed, int64_t cap, double* theta_out, double* dist_out, uint8_t* accept_out,
+                    int64_t* n_surv, float* ms_out)
+{
+    TRY(check_ctx(c));
+    if (!m || !params || !in_mu || !in_sd || !out_mu || !out_sd || !sum_idx || !data || !n_surv ||
+        (cap > 0 && (!theta_out || !dist_out || !accept_out)))
+        return fail(SWIM_EINVAL, "null argument");
+    TRY(check_dtype(m->dtype));
+    if (n_prop < 1 || cap < 0) return fail(SWIM_EINVAL, "n_prop must be >= 1 and cap >= 0");
+    if (!(tol >= 0) || !(factor > 0) || !std::isfinite(tol * factor)) return fail(SWIM_EINVAL, "bad tolerance");
+    if (2 * n_sum + 1 != MLP_W[MLP_L]) return fail(SWIM_EINVAL, "n_sum must be %d", (MLP_W[MLP_L] - 1) / 2);
+    if (m->obs_every < 1 || n_obs != m->steps / m->obs_every) return fail(SWIM_EINVAL, "n_obs must equal steps/obs_every");
+    for (int j = 0; j < n_sum; ++j)
+        if (sum_idx[j] < 0 || sum_idx[j] >= n_obs) return fail(SWIM_EINVAL, "summary index %d out of range", sum_idx[j]);
+    for (int d = 0; d < 3; ++d)
+        if (!(std::isfinite(m->lo[d]) && std::isfinite(m->hi[d]) && m->hi[d] >= m->lo[d] && m->lo[d] >= 0))
+            return fail(SWIM_EINVAL, "bad prior box");
+    if (!(m->lo[1] > 0 && m->lo[2] > 0)) return fail(SWIM_EINVAL, "the prior of S_b and S_s must be positive (log inputs)");
+    {
+        const int32_t N1 = N;
+        TRY(check_run(1, &N1, nullptr, m->steps, m->dt, m->obs_every, m->eps_over_ds));
+    }
+    hipStream_t st = c->stream;
+    const size_t es = m->dtype == SWIM_F32 ? 4 : 8;
+    const int nx = MLP_W[0];
+    // observed summaries: head displacement from its start (1, 0)
+    std::vector<float> osum(2 * n_sum);
+    for (int j = 0; j < n_sum; ++j) {
+        osum[2 * j] = (float)(data[2 * sum_idx[j]] - 1.0);
+        osum[2 * j + 1] = (float)data[2 * sum_idx[j] + 1];
+    }
+    TRY(ensure(c, B_PS_THETA, (size_t)n_prop * 24));
+    TRY(ensure(c, B_PS_X, (size_t)n_prop * nx * 4));
+    TRY(ensure(c, B_PS_KEEP, (size_t)n_prop));
+    TRY(ensure(c, B_PS_IDX, (size_t)n_prop * 8));
+    TRY(ensure(c, B_PS_NK, 8));
+    TRY(begin_uploads(c, osum.size() * 4 + (size_t)n_obs * 16 + 8));
+    TRY(stage(c, osum.data(), osum.size() * 4, B_PS_SUM, st));
+    TRY(stage(c, data, (size_t)n_obs * 16, B_DATA, st));
+    TRY(stage(c, &tol, 8, B_TOL, st));
+    TRY(end_uploads(c, st));
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard()
+        {
+            for (int i = 0; i < 3; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } guard{ev};
+    if (ms_out)
+        for (int i = 0; i < 3; ++i) HIPCHK(hipEventCreate(&ev[i]));
+    if (ms_out) HIPCHK(hipEventRecord(ev[0], st));
+    double* theta = (double*)c->buf[B_PS_THETA].p;
+    float* X = (float*)c->buf[B_PS_X].p;
+    int64_t* idx = (int64_t*)c->buf[B_PS_IDX].p;
+    int64_t* nk = (int64_t*)c->buf[B_PS_NK].p;
+    HIPCHK(launch_prior_draw(seed, n_prop, m->lo, m->hi, theta, st));
+    HIPCHK(launch_features(n_prop, theta, m->b, m->omega, in_mu, in_sd, X, st));
+    TRY(prescreen_impl(c, n_prop, X, params, out_mu, out_sd, (const float*)c->buf[B_PS_SUM].p, 2 * n_sum,
+                       (float)(factor * tol), nullptr, (uint8_t*)c->buf[B_PS_KEEP].p, idx, nk, st));
+    if (ms_out) HIPCHK(hipEventRecord(ev[1], st));
+    int64_t n_keep = 0;
+    HIPCHK(hipMemcpyAsync(&n_keep, nk, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *n_surv = n_keep;
+    const int64_t n = std::min(n_keep, cap);
+    if (n > 0) {
+        TRY(ensure(c, B_PARAMS, (size_t)n * SWIM_NPARAM * 8));
+        TRY(ensure(c, B_OBS, (size_t)n * n_obs * 2 * es));
+        TRY(ensure(c, B_SPEED, (size_t)n * es));
+        TRY(ensure(c, B_STATUS, (size_t)n * 4));
+        TRY(ensure(c, B_DIST, (size_t)n * 8));
+        TRY(ensure(c, B_ACC, (size_t)n));
+        double* rows = (double*)c->buf[B_PARAMS].p;
+        HIPCHK(launch_param_rows(n, nk, idx, n_prop, theta, m->b, m->omega, m->k, rows, st));
+        std::vector<int32_t> Nv((size_t)n, N);
+        Run r;
+        r.steps = m->steps;
+        r.dt = m->dt;
+        r.obs_every = m->obs_every;
+        r.n_obs = n_obs;
+        r.eps_over_ds = m->eps_over_ds;
+        TRY(forward_impl(c, m->dtype, n, Nv.data(), nullptr, rows, r, c->buf[B_OBS].p, c->buf[B_SPEED].p,
+                         (int32_t*)c->buf[B_STATUS].p, nullptr, st));
+        HIPCHK(launch_abc_distance(m->dtype, n, n_obs, c->buf[B_OBS].p, (const double*)c->buf[B_DATA].p,
+                                   (const int32_t*)c->buf[B_STATUS].p, (double*)c->buf[B_DIST].p, st));
+        HIPCHK(launch_accept(n, (const double*)c->buf[B_DIST].p, (const double*)c->buf[B_TOL].p,
+                             (uint8_t*)c->buf[B_ACC].p, st));
+    }
+    if (ms_out) HIPCHK(hipEventRecord(ev[2], st));
+    std::vector<double> hrows((size_t)n * SWIM_NPARAM);
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(hrows.data(), c->buf[B_PARAMS].p, hrows.size() * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(dist_out, c->buf[B_DIST].p, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(accept_out, c->buf[B_ACC].p, (size_t)n, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) theta_out[3 * i + d] = hrows[(size_t)i * SWIM_NPARAM + d];
+    if (ms_out) {
+        HIPCHK(hipEventElapsedTime(&ms_out[0], ev[0], ev[1]));
+        HIPCHK(hipEventElapsedTime(&ms_out[1], ev[1], ev[2]));
+    }
+    return SWIM_OK;
+}
+
 }  // extern "C"
+

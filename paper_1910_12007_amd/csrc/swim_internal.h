@@ -111,5 +111,7 @@ hipError_t launch_param_rows(int64_t cap, const int64_t* n_dev, const int64_t* i
 hipError_t launch_gather_f32(int64_t cap, const int64_t* n_dev, const int64_t* idx, int64_t n_src,
                              const float* src, int cols, float* dst, hipStream_t st);
 hipError_t launch_flag_eq(int64_t n, const int32_t* v, int32_t want, uint8_t* keep, hipStream_t st);
+hipError_t launch_flag_bounded(int64_t n, const float* T, int nt, int n_disp, float max_disp, uint8_t* keep,
+                               hipStream_t st);
 
 }  // namespace swim

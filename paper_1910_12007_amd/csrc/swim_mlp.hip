@@ -445,6 +445,17 @@ __global__ void k_flag_eq(int64_t n, const int32_t* v, int32_t want, uint8_t* ke
     if (i < n) keep[i] = v[i] == want ? 1 : 0;
 }
 
+// keep[i] &= every one of the first n_disp entries of row i of T is finite
+// with magnitude <= max_disp
+__global__ void k_flag_bounded(int64_t n, const float* T, int nt, int n_disp, float max_disp, uint8_t* keep)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool ok = keep[i] != 0;
+    for (int j = 0; j < n_disp; ++j) ok = ok && fabsf(T[i * nt + j]) <= max_disp;
+    keep[i] = ok ? 1 : 0;
+}
+
 hipError_t launch_features(int64_t n, const double* theta, double b, double om, const float* mu, const float* sd,
                            float* X, hipStream_t st)
 {
@@ -511,6 +522,15 @@ hipError_t launch_flag_eq(int64_t n, const int32_t* v, int32_t want, uint8_t* ke
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_flag_eq, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, v, want, keep);
+    return hipGetLastError();
+}
+
+hipError_t launch_flag_bounded(int64_t n, const float* T, int nt, int n_disp, float max_disp, uint8_t* keep,
+                               hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flag_bounded, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T, nt, n_disp,
+                       max_disp, keep);
     return hipGetLastError();
 }
 

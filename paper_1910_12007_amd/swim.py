@@ -63,6 +63,11 @@ SIGNATURES = {
                                    _P]),
     "swim_select": (_c.c_int, [_P, _c.c_int64, _P, _c.c_int32, _P, _P, _P, _P]),
     "swim_gather_rows": (_c.c_int, [_P, _c.c_int64, _P, _P, _c.c_int64, _P, _c.c_int32, _P, _P]),
+    "surrogate_dataset": (_c.c_int, [_P, _P, _c.c_int32, _c.c_int64, _c.c_uint64, _I32P, _c.c_int32, _c.c_double,
+                                     _c.c_int64, _P, _P, _P, _P, _P, _P, _I64P, _P]),
+    "abc_prescreened": (_c.c_int, [_P, _P, _c.c_int32, _P, _P, _P, _P, _P, _I32P, _c.c_int32, _DP, _c.c_int32,
+                                   _c.c_double, _c.c_double, _c.c_int64, _c.c_uint64, _c.c_int64, _DP, _DP, _U8P,
+                                   _I64P, _c.POINTER(_c.c_float)]),
 }
 
 _LIB = None
@@ -328,3 +333,32 @@ def swim_gather_rows(ctx, idx, n_dev, src, dst, cap=None, stream=None):
     cap = dst.shape[0] if cap is None else cap
     return _check(lib().swim_gather_rows(ctx.handle, int(cap), _dptr(n_dev), _dptr(idx), src.shape[0], _dptr(src),
                                          src.shape[1], _dptr(dst), _stream(stream)))
+
+
+def surrogate_dataset(ctx, model, N, n_runs, seed, sum_idx, max_disp, X, T, in_mu, in_sd, out_mu, out_sd,
+                      stream=None):
+    """Returns the number of rows written (kept runs, at most X.shape[0])."""
+    si, si_p = _h(sum_idx, np.int32, _I32P)
+    n_out = ctypes.c_int64()
+    _check(lib().surrogate_dataset(ctx.handle, ctypes.byref(model), int(N), int(n_runs), int(seed), si_p, len(si),
+                                   float(max_disp), X.shape[0], _dptr(X), _dptr(T), _dptr(in_mu), _dptr(in_sd), _dptr(out_mu),
+                                   _dptr(out_sd), ctypes.byref(n_out), _stream(stream)))
+    return n_out.value
+
+
+def abc_prescreened(ctx, model, N, params, in_mu, in_sd, out_mu, out_sd, sum_idx, data, tol, factor, n_prop,
+                    seed, cap):
+    si, si_p = _h(sum_idx, np.int32, _I32P)
+    d, d_p = _h(data, np.float64, _DP)
+    theta = np.empty((cap, 3))
+    dist = np.empty(cap)
+    acc = np.empty(cap, dtype=np.uint8)
+    n_surv = ctypes.c_int64()
+    ms = (ctypes.c_float * 2)()
+    _check(lib().abc_prescreened(ctx.handle, ctypes.byref(model), int(N), _dptr(params), _dptr(in_mu), _dptr(in_sd),
+                                 _dptr(out_mu), _dptr(out_sd), si_p, len(si), d_p, d.shape[0], float(tol),
+                                 float(factor), int(n_prop), int(seed), int(cap), theta.ctypes.data_as(_DP),
+                                 dist.ctypes.data_as(_DP), acc.ctypes.data_as(_U8P), ctypes.byref(n_surv), ms))
+    n = min(n_surv.value, cap)
+    return dict(n_surv=n_surv.value, theta=theta[:n], dist=dist[:n], accept=acc[:n].astype(bool),
+                ms_prescreen=float(ms[0]), ms_rerun=float(ms[1]))
