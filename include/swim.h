@@ -334,7 +334,10 @@ int abc_prescreened(swim_ctx *ctx, const abc_model *model, int32_t N, const floa
 
 /* Host evaluation of the device kernel functions (test hook): for squared
  * distances t[0..n) returns H1(t) - H1(0) and H2(t) as computed by the
- * kernels' own code compiled for the host, and H1(0) in *h1c. */
+ * kernels' own code compiled for the host, and H1(0) in *h1c.  SWIM_F32
+ * follows the FP32 device path: cubic pieces of a per-system table in
+ * v = 1 + t/eps^2 (16 per octave, v < 2^24), built from the FP64
+ * evaluation; direct FP32 evaluation beyond. */
 int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, const double *t,
                           double *h1t, double *h2, double *h1c);
 

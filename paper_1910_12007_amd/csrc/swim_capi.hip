@@ -61,7 +61,7 @@ enum BufId {
     B_OFF, B_SWOFF, B_NPT, B_NSW, B_ORDER, B_LIST, B_BLKS, B_BLKF, B_ALPHA, B_EPS, B_SYSC, B_QUEUE,
     B_PARAMS, B_DATA, B_OBS, B_SPEED, B_STATUS, B_DIST, B_TOL, B_ACC, B_BIG,
     B_MLP_ACT, B_MLP_GRAD, B_MLP_BATCH, B_MLP_IDX, B_MLP_CNT,
-    B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_NBUF
+    B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_TAB, B_BLKSL, B_NBUF
 };
 
 // surrogate network: 5 -> 256 x 4 -> 33
@@ -229,6 +229,24 @@ template <typename F> void parallel_for(int64_t n, F f)
     for (auto& x : th) x.join();
 }
 
+// Per-system constants in the run's precision; FP32 runs also get the FP64
+// constants (after the FP32 ones, 16-byte aligned) from which the kernel
+// tables are built.
+int sysconst_buffers(swim_ctx* c, int32_t dtype, int64_t n_sys, void** sysc, void** sysc64)
+{
+    if (dtype == SWIM_F32) {
+        const size_t a = (size_t)n_sys * sizeof(SysConst<float>);
+        TRY(ensure(c, B_SYSC, a + (size_t)n_sys * sizeof(SysConst<double>)));
+        *sysc = c->buf[B_SYSC].p;
+        *sysc64 = (char*)c->buf[B_SYSC].p + a;
+    } else {
+        TRY(ensure(c, B_SYSC, (size_t)n_sys * sizeof(SysConst<double>)));
+        *sysc = c->buf[B_SYSC].p;
+        *sysc64 = nullptr;
+    }
+    return SWIM_OK;
+}
+
 // ------------------------------------------------------------------------
 // forward run (shared by swim_forward and abc_step)
 // ------------------------------------------------------------------------
@@ -270,14 +288,15 @@ int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
     }
     // large systems: target blocks of 256 * tpl_big points
     const int tpl_big = c->opt_big_tpl ? c->opt_big_tpl : 1;
-    std::vector<int64_t> blk_s, blk_f;
-    for (int64_t s : big_list)
-        for (int64_t f = 0; f < pts[s]; f += 256 * tpl_big) {
-            blk_s.push_back(s);
+    std::vector<int64_t> blk_s, blk_f, blk_sl;
+    for (size_t q = 0; q < big_list.size(); ++q)
+        for (int64_t f = 0; f < pts[big_list[q]]; f += 256 * tpl_big) {
+            blk_s.push_back(big_list[q]);
             blk_f.push_back(f);
+            blk_sl.push_back((int64_t)q);
         }
     const size_t es = dtype == SWIM_F32 ? 4 : 8;
-    size_t total = (sw_off.size() + big_off.size() + big_list.size() + blk_s.size() + blk_f.size()) * 8 +
+    size_t total = (sw_off.size() + big_off.size() + big_list.size() + 3 * blk_s.size()) * 8 +
                    (nsw.size() + order.size()) * 4 + n_sys * 4 + 64;
     TRY(begin_uploads(c, total));
     TRY(stage(c, sw_off.data(), sw_off.size() * 8, B_SWOFF, st));
@@ -288,12 +307,13 @@ int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
     TRY(stage(c, big_list.data(), big_list.size() * 8, B_LIST, st));
     TRY(stage(c, blk_s.data(), blk_s.size() * 8, B_BLKS, st));
     TRY(stage(c, blk_f.data(), blk_f.size() * 8, B_BLKF, st));
+    TRY(stage(c, blk_sl.data(), blk_sl.size() * 8, B_BLKSL, st));
     TRY(end_uploads(c, st));
-    const size_t csz = dtype == SWIM_F32 ? sizeof(SysConst<float>) : sizeof(SysConst<double>);
-    TRY(ensure(c, B_SYSC, n_sys * csz));
+    void *sysc, *sysc64;
+    TRY(sysconst_buffers(c, dtype, n_sys, &sysc, &sysc64));
     TRY(ensure(c, B_QUEUE, 8 * 4));
     HIPCHK(launch_sysconst_batch(dtype, n_sys, (const int64_t*)c->buf[B_SWOFF].p, (const int32_t*)c->buf[B_NPT].p,
-                                 params_dev, run.eps_over_ds, c->buf[B_SYSC].p, status, st));
+                                 params_dev, run.eps_over_ds, sysc, sysc64, status, st));
     Batch b;
     b.n_sys = n_sys;
     b.pt_off = (const int64_t*)c->buf[B_OFF].p;
@@ -301,7 +321,8 @@ int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
     b.npt = (const int32_t*)c->buf[B_NPT].p;
     b.nswim = (const int32_t*)c->buf[B_NSW].p;
     b.params = params_dev;
-    b.sysc = c->buf[B_SYSC].p;
+    b.sysc = sysc;
+    b.sysc64 = sysc64;
     HIPCHK(launch_fill_i32((int32_t*)c->buf[B_QUEUE].p, 0, 8, st));
     for (size_t k = 0; k < bucket_span.size(); ++k) {
         const int tpl = bucket_span[k].first;
@@ -329,14 +350,21 @@ int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
             S.yl[q] = base + (6 + q) * one;
         }
         S.head0 = base + 8 * one;
+        S.tab = nullptr;
         if (big_step_lds_bytes(dtype, max_big) > 160 * 1024)
             return fail(SWIM_EINVAL, "system of %d points exceeds the LDS capacity", max_big);
+        if (dtype == SWIM_F32) {
+            TRY(ensure(c, B_TAB, big_list.size() * table_bytes()));
+            HIPCHK(launch_table_build((const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), sysc64,
+                                      c->buf[B_TAB].p, st));
+            S.tab = c->buf[B_TAB].p;
+        }
         HIPCHK(launch_big_init(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S, status, obs,
                                run.n_obs, st));
         for (int step = 0; step < run.steps; ++step)
             HIPCHK(launch_big_step(dtype, tpl_big, (int64_t)blk_s.size(), (const int64_t*)c->buf[B_BLKS].p,
-                                   (const int64_t*)c->buf[B_BLKF].p, max_big, b, S, step, run, obs, status,
-                                   steps_done, st));
+                                   (const int64_t*)c->buf[B_BLKF].p, (const int64_t*)c->buf[B_BLKSL].p, max_big, b, S,
+                                   step, run, obs, status, steps_done, st));
         HIPCHK(launch_big_finish(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S,
                                  run.steps & 1, run, speed, status, steps_done, st));
     }
@@ -523,13 +551,13 @@ int swim_pair_velocity(swim_ctx* c, int32_t dtype, int64_t n_sys, const int64_t*
     TRY(stage(c, bs.data(), bs.size() * 8, B_BLKS, st));
     TRY(stage(c, bf.data(), bf.size() * 8, B_BLKF, st));
     TRY(end_uploads(c, st));
-    const size_t csz = dtype == SWIM_F32 ? sizeof(SysConst<float>) : sizeof(SysConst<double>);
-    TRY(ensure(c, B_SYSC, n_sys * csz));
-    HIPCHK(launch_sysconst(dtype, n_sys, (const double*)c->buf[B_ALPHA].p, (const double*)c->buf[B_EPS].p,
-                           c->buf[B_SYSC].p, st));
+    void *sysc, *sysc64;
+    TRY(sysconst_buffers(c, dtype, n_sys, &sysc, &sysc64));
+    HIPCHK(launch_sysconst(dtype, n_sys, (const double*)c->buf[B_ALPHA].p, (const double*)c->buf[B_EPS].p, sysc,
+                           sysc64, st));
     HIPCHK(launch_pair_velocity(dtype, tpl, (int64_t)bs.size(), (const int64_t*)c->buf[B_BLKS].p,
-                                (const int64_t*)c->buf[B_BLKF].p, (const int64_t*)c->buf[B_OFF].p, c->buf[B_SYSC].p, x,
-                                y, fx, fy, ux, uy, st));
+                                (const int64_t*)c->buf[B_BLKF].p, (const int64_t*)c->buf[B_OFF].p, sysc, sysc64, x, y,
+                                fx, fy, ux, uy, st));
     return SWIM_OK;
 }
 
@@ -797,11 +825,22 @@ int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, co
         return fail(SWIM_EINVAL, "alpha/eps outside the domain");
     if (n < 0 || (n > 0 && (!t || !h1t || !h2)) || !h1c) return fail(SWIM_EINVAL, "bad arguments");
     if (dtype == SWIM_F32) {
+        // the device's FP32 path: the per-system table, direct evaluation
+        // beyond its last octave
         SysConst<float> C;
         sysconst_compute<float>(alpha, eps, &C);
+        SysConst<double> C64;
+        sysconst_compute<double>(alpha, eps, &C64);
+        std::vector<TabE> tab(TAB_N);
+        for (int i = 0; i < TAB_N; ++i) tab_interval(C64, eps * eps, i, tab[i]);
         for (int64_t i = 0; i < n; ++i) {
-            float a, b;
-            kernel_eval<float>(C, (float)t[i], a, b);
+            float a, b, u;
+            const float tf = (float)t[i];
+            const uint32_t k = tab_locate(tf, C.inv_e2, u);
+            if (k < (uint32_t)TAB_N)
+                tab_eval(tab[k], u, a, b);
+            else
+                kernel_eval<float>(C, tf, a, b);
             h1t[i] = a;
             h2[i] = b;
         }

@@ -143,25 +143,79 @@ __device__ __forceinline__ void point_force(const Seg& seg, int p, const FilP<T>
 
 // Accumulate the velocity sum of eq. (BrV) over sources src[0..n) for the
 // TPL targets (xi, yi) of this lane; the constant H1(0) part is added by the
-// caller once as h1c * sum_j F_j.
+// caller once as h1c * sum_j F_j.  FP64 evaluates the kernel functions
+// directly; FP32 reads them from the system's table in LDS (tab), with the
+// direct evaluation for pairs beyond its last octave.
 template <typename T, int TPL>
-__device__ __forceinline__ void pair_accumulate(const SysConst<T>& C, const Src4<T>* src, int n,
+__device__ __forceinline__ void pair_accumulate(const SysConst<T>& C, const TabE* tab, const Src4<T>* src, int n,
                                                 const T (&xi)[TPL], const T (&yi)[TPL],
                                                 T (&ax)[TPL], T (&ay)[TPL])
 {
-    for (int j = 0; j < n; ++j) {
-        const Src4<T> s = src[j];
+    if constexpr (sizeof(T) == 4) {
+        // table pass; a pair beyond the table contributes nothing here and
+        // flags its lane
+        bool far = false;
+        const float ie2 = C.inv_e2;
+        for (int j = 0; j < n; ++j) {
+            const Src4<T> s = src[j];
 #pragma unroll
-        for (int k = 0; k < TPL; ++k) {
-            const T dx = xi[k] - s.x, dy = yi[k] - s.y;
-            const T t = fma_t(dx, dx, dy * dy);
-            T Ht, H2;
-            kernel_eval<T>(C, t, Ht, H2);
-            const T h2fd = H2 * fma_t(s.fx, dx, s.fy * dy);
-            ax[k] = fma_t(Ht, s.fx, fma_t(h2fd, dx, ax[k]));
-            ay[k] = fma_t(Ht, s.fy, fma_t(h2fd, dy, ay[k]));
+            for (int k = 0; k < TPL; ++k) {
+                const T dx = xi[k] - s.x, dy = yi[k] - s.y;
+                const T t = fma_t(dx, dx, dy * dy);
+                float u, Ht, H2;
+                const uint32_t id = tab_locate(t, ie2, u);
+                const bool in = id < (uint32_t)TAB_N;
+                far = far || !in;
+                tab_eval(tab[in ? id : 0u], u, Ht, H2);
+                Ht = in ? Ht : 0.0f;
+                H2 = in ? H2 : 0.0f;
+                const T h2fd = H2 * fma_t(s.fx, dx, s.fy * dy);
+                ax[k] = fma_t(Ht, s.fx, fma_t(h2fd, dx, ax[k]));
+                ay[k] = fma_t(Ht, s.fy, fma_t(h2fd, dy, ay[k]));
+            }
+        }
+        // direct evaluation of the flagged pairs, only where a lane has one
+        if (__any(far)) {
+            for (int j = 0; j < n; ++j) {
+                const Src4<T> s = src[j];
+#pragma unroll
+                for (int k = 0; k < TPL; ++k) {
+                    const T dx = xi[k] - s.x, dy = yi[k] - s.y;
+                    const T t = fma_t(dx, dx, dy * dy);
+                    float u;
+                    if (tab_locate(t, ie2, u) >= (uint32_t)TAB_N) {
+                        T Ht, H2;
+                        kernel_eval<T>(C, t, Ht, H2);
+                        const T h2fd = H2 * fma_t(s.fx, dx, s.fy * dy);
+                        ax[k] = fma_t(Ht, s.fx, fma_t(h2fd, dx, ax[k]));
+                        ay[k] = fma_t(Ht, s.fy, fma_t(h2fd, dy, ay[k]));
+                    }
+                }
+            }
+        }
+    } else {
+        for (int j = 0; j < n; ++j) {
+            const Src4<T> s = src[j];
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) {
+                const T dx = xi[k] - s.x, dy = yi[k] - s.y;
+                const T t = fma_t(dx, dx, dy * dy);
+                T Ht, H2;
+                kernel_eval<T>(C, t, Ht, H2);
+                const T h2fd = H2 * fma_t(s.fx, dx, s.fy * dy);
+                ax[k] = fma_t(Ht, s.fx, fma_t(h2fd, dx, ax[k]));
+                ay[k] = fma_t(Ht, s.fy, fma_t(h2fd, dy, ay[k]));
+            }
         }
     }
+}
+
+// the FP32 kernel table of one system, built cooperatively by nthreads
+// threads (thread id tid) into tab; not inlined, so that the FP64
+// evaluation's registers do not add to those of the caller's loops
+__device__ __attribute__((noinline)) void tab_build(const SysConst<double>* C64, TabE* tab, int tid, int nthreads)
+{
+    for (int i = tid; i < TAB_N; i += nthreads) tab_interval(*C64, C64->e2, i, tab[i]);
 }
 
 // error-free (hi, lo) += d  (TwoSum, then renormalize)
@@ -180,10 +234,13 @@ template <typename T> __device__ __forceinline__ void acc2(T& hi, T& lo, T d)
 // set-up
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_sysconst(int64_t n, const double* alpha, const double* eps, SysConst<T>* out)
+__global__ void k_sysconst(int64_t n, const double* alpha, const double* eps, SysConst<T>* out,
+                           SysConst<double>* out64)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) sysconst_compute<T>(alpha[i], eps[i], out + i);
+    if (i >= n) return;
+    sysconst_compute<T>(alpha[i], eps[i], out + i);
+    if (out64) sysconst_compute<double>(alpha[i], eps[i], out64 + i);
 }
 
 // per-system constants of a forward batch; systems whose parameters leave
@@ -191,7 +248,7 @@ __global__ void k_sysconst(int64_t n, const double* alpha, const double* eps, Sy
 // flagged SWIM_ST_BADPARAM_ and skipped by the run kernels.
 template <typename T>
 __global__ void k_sysconst_batch(int64_t n, const int64_t* sw_off, const int32_t* npt, const double* params,
-                                 double eps_over_ds, SysConst<T>* out, int32_t* status)
+                                 double eps_over_ds, SysConst<T>* out, SysConst<double>* out64, int32_t* status)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -202,6 +259,17 @@ __global__ void k_sysconst_batch(int64_t n, const int64_t* sw_off, const int32_t
         for (int c = 0; c < 9; ++c) ok = ok && isfinite(params[9 * f + c]);
     status[s] = ok ? 0 : SWIM_ST_BADPARAM_;
     sysconst_compute<T>(ok ? alpha : 0.0, eps, out + s);
+    if (out64) sysconst_compute<double>(ok ? alpha : 0.0, eps, out64 + s);
+}
+
+// FP32 kernel tables of the listed systems, one thread per interval
+__global__ void k_table_build(const int64_t* list, const SysConst<double>* sysc64, TabE* tab)
+{
+    const int64_t slot = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= TAB_N) return;
+    const SysConst<double>& C = sysc64[list[slot]];
+    tab_interval(C, C.e2, i, tab[slot * TAB_N + i]);
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
@@ -218,17 +286,19 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
 template <typename T, int TPL>
 __global__ __launch_bounds__(256) void k_pair_velocity(const int64_t* blk_sys, const int64_t* blk_first,
                                                         const int64_t* pt_off, const SysConst<T>* sysc,
-                                                        const T* x, const T* y, const T* fx, const T* fy,
-                                                        T* ux, T* uy)
+                                                        const SysConst<double>* sysc64, const T* x, const T* y,
+                                                        const T* fx, const T* fy, T* ux, T* uy)
 {
     __shared__ Src4<T> tile[256];
     __shared__ T red[2][4];
+    __shared__ TabE tab[sizeof(T) == 4 ? TAB_N : 1];
     const int tid = threadIdx.x;
     const int64_t s = blk_sys[blockIdx.x];
     const int64_t first = blk_first[blockIdx.x];
     const int64_t p0 = pt_off[s];
     const int64_t n = pt_off[s + 1] - p0;
     const SysConst<T> C = sysc[s];
+    if constexpr (sizeof(T) == 4) tab_build(sysc64 + s, tab, tid, 256);
     T xi[TPL], yi[TPL], ax[TPL], ay[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -256,7 +326,7 @@ __global__ __launch_bounds__(256) void k_pair_velocity(const int64_t* blk_sys, c
         tile[tid] = v;
         __syncthreads();
         const int m = (int)((n - j0) < 256 ? (n - j0) : 256);
-        pair_accumulate<T, TPL>(C, tile, m, xi, yi, ax, ay);
+        pair_accumulate<T, TPL>(C, tab, tile, m, xi, yi, ax, ay);
     }
     sfx = wave_sum(sfx);
     sfy = wave_sum(sfy);
@@ -309,6 +379,7 @@ __global__ void k_forces(int64_t n_fil, const int64_t* fil_off, const int32_t* n
 // velocities are reduced through LDS in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
 template <typename T> struct FwdLds {
+    TabE* tab;     // [TAB_N] FP32 kernel table (FP32 runs)
     Src4<T>* src;  // [NMAX] positions (hi) and forces
     T* lox;        // [NMAX] lo parts
     T* loy;
@@ -340,6 +411,7 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
     }
     const SysConst<T> C = ((const SysConst<T>*)b.sysc)[s];
     const double dsd = 1.0 / (double)(N - 1);
+    if constexpr (COMP) tab_build((const SysConst<double>*)b.sysc64 + s, L.tab, tid, NT);
 
     // owned points i = tid + NT*q: positions as (hi, lo)
     T xh[OWN], yh[OWN], xl[OWN], yl[OWN];
@@ -418,7 +490,7 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
             yi[k] = i < n ? L.src[i].y : (T)0;
             ax[k] = ay[k] = (T)0;
         }
-        pair_accumulate<T, TPL>(C, L.src + j0, j1 - j0, xi, yi, ax, ay);
+        pair_accumulate<T, TPL>(C, L.tab, L.src + j0, j1 - j0, xi, yi, ax, ay);
         if constexpr (WPS > 1) {
 #pragma unroll
             for (int k = 0; k < TPL; ++k) {
@@ -521,9 +593,11 @@ __global__ __launch_bounds__(64 * WPS) void k_forward(Batch b, Run r, const int3
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NMAX = 64 * TPL;
     __shared__ int s_item;
+    constexpr size_t TABB = sizeof(T) == 4 ? TAB_N * sizeof(TabE) : 0;
     FwdLds<T> L;
-    L.src = reinterpret_cast<Src4<T>*>(smem);
-    L.lox = reinterpret_cast<T*>(smem + NMAX * sizeof(Src4<T>));
+    L.tab = reinterpret_cast<TabE*>(smem);
+    L.src = reinterpret_cast<Src4<T>*>(smem + TABB);
+    L.lox = reinterpret_cast<T*>(smem + TABB + NMAX * sizeof(Src4<T>));
     L.loy = L.lox + NMAX;
     L.red = L.loy + NMAX;
     L.part = L.red + 2 * WPS;
@@ -581,17 +655,24 @@ __global__ void k_big_init(const int64_t* list, Batch b, BigState S, int32_t* st
 }
 
 template <typename T, int TPL>
-__global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const int64_t* blk_first, Batch b,
-                                                  BigState S, int step, Run r, T* obs, int32_t* status,
-                                                  int32_t* steps_done)
+__global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const int64_t* blk_first,
+                                                  const int64_t* blk_slot, Batch b, BigState S, int step, Run r,
+                                                  T* obs, int32_t* status, int32_t* steps_done)
 {
     constexpr bool COMP = sizeof(T) == 4;
+    constexpr size_t TABB = COMP ? TAB_N * sizeof(TabE) : 0;
     extern __shared__ __align__(16) unsigned char smem[];
-    Src4<T>* src = reinterpret_cast<Src4<T>*>(smem);
+    TabE* tab = reinterpret_cast<TabE*>(smem);
+    Src4<T>* src = reinterpret_cast<Src4<T>*>(smem + TABB);
     __shared__ T red[2][4];
     const int tid = threadIdx.x;
     const int64_t s = blk_sys[blockIdx.x];
     if (status[s] != 0) return;
+    if constexpr (COMP) {
+        // this system's table, built once before the first step
+        const TabE* g = (const TabE*)S.tab + blk_slot[blockIdx.x] * TAB_N;
+        for (int i = tid; i < TAB_N; i += 256) tab[i] = g[i];
+    }
     const int64_t first = blk_first[blockIdx.x];
     const int64_t p0 = b.pt_off[s];
     const int N = b.npt[s];
@@ -642,7 +723,7 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
         yi[k] = i < n ? src[i].y : (T)0;
         ax[k] = ay[k] = (T)0;
     }
-    pair_accumulate<T, TPL>(C, src, n, xi, yi, ax, ay);
+    pair_accumulate<T, TPL>(C, tab, src, n, xi, yi, ax, ay);
     const T dt = (T)r.dt;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -803,29 +884,39 @@ __global__ void k_accept(int64_t n, const double* dist, const double* tol, uint8
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t launch_sysconst_batch(int dtype, int64_t n_sys, const int64_t* sw_off, const int32_t* npt,
-                                 const double* params, double eps_over_ds, void* sysc, int32_t* status,
-                                 hipStream_t st)
+                                 const double* params, double eps_over_ds, void* sysc, void* sysc64,
+                                 int32_t* status, hipStream_t st)
 {
     if (n_sys <= 0) return hipSuccess;
     if (dtype == 0)
         hipLaunchKernelGGL(k_sysconst_batch<float>, dim3(nblk(n_sys, 64)), dim3(64), 0, st, n_sys, sw_off, npt,
-                           params, eps_over_ds, (SysConst<float>*)sysc, status);
+                           params, eps_over_ds, (SysConst<float>*)sysc, (SysConst<double>*)sysc64, status);
     else
         hipLaunchKernelGGL(k_sysconst_batch<double>, dim3(nblk(n_sys, 64)), dim3(64), 0, st, n_sys, sw_off, npt,
-                           params, eps_over_ds, (SysConst<double>*)sysc, status);
+                           params, eps_over_ds, (SysConst<double>*)sysc, (SysConst<double>*)nullptr, status);
     return hipGetLastError();
 }
 
 hipError_t launch_sysconst(int dtype, int64_t n_sys, const double* alpha, const double* eps, void* sysc,
-                           hipStream_t st)
+                           void* sysc64, hipStream_t st)
 {
     if (n_sys <= 0) return hipSuccess;
     if (dtype == 0)
         hipLaunchKernelGGL(k_sysconst<float>, dim3(nblk(n_sys, 64)), dim3(64), 0, st, n_sys, alpha, eps,
-                           (SysConst<float>*)sysc);
+                           (SysConst<float>*)sysc, (SysConst<double>*)sysc64);
     else
         hipLaunchKernelGGL(k_sysconst<double>, dim3(nblk(n_sys, 64)), dim3(64), 0, st, n_sys, alpha, eps,
-                           (SysConst<double>*)sysc);
+                           (SysConst<double>*)sysc, (SysConst<double>*)nullptr);
+    return hipGetLastError();
+}
+
+size_t table_bytes() { return (size_t)TAB_N * sizeof(TabE); }
+
+hipError_t launch_table_build(const int64_t* list, int64_t n_list, const void* sysc64, void* tab, hipStream_t st)
+{
+    if (n_list <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_table_build, dim3(nblk(TAB_N, 64), (unsigned)n_list), dim3(64), 0, st, list,
+                       (const SysConst<double>*)sysc64, (TabE*)tab);
     return hipGetLastError();
 }
 
@@ -838,21 +929,21 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st)
 
 template <typename T, int TPL>
 static void pair_launch(int64_t nb, const int64_t* bs, const int64_t* bf, const int64_t* off, const void* sysc,
-                        const void* x, const void* y, const void* fx, const void* fy, void* ux, void* uy,
-                        hipStream_t st)
+                        const void* sysc64, const void* x, const void* y, const void* fx, const void* fy, void* ux,
+                        void* uy, hipStream_t st)
 {
     hipLaunchKernelGGL((k_pair_velocity<T, TPL>), dim3((unsigned)nb), dim3(256), 0, st, bs, bf, off,
-                       (const SysConst<T>*)sysc, (const T*)x, (const T*)y, (const T*)fx, (const T*)fy, (T*)ux,
-                       (T*)uy);
+                       (const SysConst<T>*)sysc, (const SysConst<double>*)sysc64, (const T*)x, (const T*)y,
+                       (const T*)fx, (const T*)fy, (T*)ux, (T*)uy);
 }
 
 hipError_t launch_pair_velocity(int dtype, int tpl, int64_t nb, const int64_t* bs, const int64_t* bf,
-                                const int64_t* off, const void* sysc, const void* x, const void* y,
-                                const void* fx, const void* fy, void* ux, void* uy, hipStream_t st)
+                                const int64_t* off, const void* sysc, const void* sysc64, const void* x,
+                                const void* y, const void* fx, const void* fy, void* ux, void* uy, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
 #define PAIR_CASE(T, P) \
-    case P: pair_launch<T, P>(nb, bs, bf, off, sysc, x, y, fx, fy, ux, uy, st); break;
+    case P: pair_launch<T, P>(nb, bs, bf, off, sysc, sysc64, x, y, fx, fy, ux, uy, st); break;
     if (dtype == 0) {
         switch (tpl) { PAIR_CASE(float, 1) PAIR_CASE(float, 2) PAIR_CASE(float, 4) default: return hipErrorInvalidValue; }
     } else {
@@ -881,7 +972,8 @@ size_t forward_lds_bytes(int dtype, int tpl, int wps)
 {
     const size_t e = dtype == 0 ? sizeof(float) : sizeof(double);
     const size_t nmax = 64 * (size_t)tpl;
-    return nmax * 4 * e + 2 * nmax * e + 2 * (size_t)wps * e + (wps > 1 ? (size_t)wps * 2 * nmax * e : 0);
+    return (dtype == 0 ? table_bytes() : 0) + nmax * 4 * e + 2 * nmax * e + 2 * (size_t)wps * e +
+           (wps > 1 ? (size_t)wps * 2 * nmax * e : 0);
 }
 
 template <typename T, int TPL, int WPS>
@@ -960,13 +1052,13 @@ hipError_t launch_big_init(int dtype, const int64_t* list, int64_t n_list, const
 
 size_t big_step_lds_bytes(int dtype, int32_t max_pts)
 {
-    return (size_t)max_pts * 4 * (dtype == 0 ? sizeof(float) : sizeof(double));
+    return (dtype == 0 ? table_bytes() : 0) + (size_t)max_pts * 4 * (dtype == 0 ? sizeof(float) : sizeof(double));
 }
 
 template <typename T, int TPL>
-static hipError_t big_launch(int64_t nb, const int64_t* bs, const int64_t* bf, int32_t max_pts, const Batch& b,
-                             const BigState& s, int step, const Run& r, void* obs, int32_t* status, int32_t* done,
-                             hipStream_t st)
+static hipError_t big_launch(int64_t nb, const int64_t* bs, const int64_t* bf, const int64_t* bsl, int32_t max_pts,
+                             const Batch& b, const BigState& s, int step, const Run& r, void* obs, int32_t* status,
+                             int32_t* done, hipStream_t st)
 {
     const size_t lds = big_step_lds_bytes(sizeof(T) == 4 ? 0 : 1, max_pts);
     static size_t attr_lds = 0;
@@ -976,17 +1068,17 @@ static hipError_t big_launch(int64_t nb, const int64_t* bs, const int64_t* bf, i
         if (e != hipSuccess) return e;
         attr_lds = lds;
     }
-    hipLaunchKernelGGL((k_big_step<T, TPL>), dim3((unsigned)nb), dim3(256), lds, st, bs, bf, b, s, step, r, (T*)obs,
-                       status, done);
+    hipLaunchKernelGGL((k_big_step<T, TPL>), dim3((unsigned)nb), dim3(256), lds, st, bs, bf, bsl, b, s, step, r,
+                       (T*)obs, status, done);
     return hipGetLastError();
 }
 
-hipError_t launch_big_step(int dtype, int tpl, int64_t nb, const int64_t* bs, const int64_t* bf, int32_t max_pts,
-                           const Batch& b, const BigState& s, int step, const Run& r, void* obs, int32_t* status,
-                           int32_t* steps_done, hipStream_t st)
+hipError_t launch_big_step(int dtype, int tpl, int64_t nb, const int64_t* bs, const int64_t* bf, const int64_t* bsl,
+                           int32_t max_pts, const Batch& b, const BigState& s, int step, const Run& r, void* obs,
+                           int32_t* status, int32_t* steps_done, hipStream_t st)
 {
 #define BIG_CASE(T, P) \
-    case P: return big_launch<T, P>(nb, bs, bf, max_pts, b, s, step, r, obs, status, steps_done, st);
+    case P: return big_launch<T, P>(nb, bs, bf, bsl, max_pts, b, s, step, r, obs, status, steps_done, st);
     if (dtype == 0) {
         switch (tpl) { BIG_CASE(float, 1) BIG_CASE(float, 2) BIG_CASE(float, 4) default: return hipErrorInvalidValue; }
     } else {

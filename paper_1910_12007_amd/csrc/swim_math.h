@@ -381,4 +381,81 @@ SWIM_HD void kernel_eval(const SysConst<T>& C, T t, T& Ht, T& H2)
         kernel_large_z<T>(C, t, w, Ht, H2);
 }
 
+// ---------------------------------------------------------------------------
+// FP32 evaluation by table.  In the variable v = 1 + t/eps^2 (t = r^2) the
+// functions Ht(t) and H2(t) are smooth on every interval
+// [2^e (1 + j/16), 2^e (1 + (j+1)/16)), e = 0..TAB_OCT-1, j = 0..15, whose
+// index is read straight from the bits of the float v (exponent and the top
+// four mantissa bits) and whose local coordinate u in [0, 1) is the rest of
+// the mantissa.  On each interval both functions are the cubic in u through
+// their values at the Chebyshev-Lobatto nodes u = 0, 1/4, 3/4, 1, evaluated
+// once per system in FP64 by kernel_eval<double>.  The relative width 1/16
+// of an interval bounds the interpolation error by about 4e-3 (1/16)^4
+// max|f''''| in units of the function's own scale (about 1e-7 for the log
+// and 1/t behaviour of these kernels); rounding the coefficients to FP32
+// adds one unit roundoff.  Pairs beyond the last octave fall back to the
+// direct evaluation.
+// ---------------------------------------------------------------------------
+constexpr int TAB_M = 4;                     // intervals per octave: 2^TAB_M
+constexpr int TAB_OCT = 24;                  // octaves of v, which covers [1, 2^24)
+constexpr int TAB_N = TAB_OCT << TAB_M;      // intervals per system
+constexpr int TAB_SHIFT = 23 - TAB_M;        // mantissa bits of u
+struct alignas(16) TabE {
+    float h[4];  // Ht(u) = h0 + u (h1 + u (h2 + u h3))
+    float g[4];  // H2(u)
+};
+
+// cubic through (0, f0), (1/4, f1), (3/4, f2), (1, f3), monomial coefficients
+SWIM_HD void cubic_lobatto(const double (&f)[4], float (&c)[4])
+{
+    // Newton divided differences on the nodes 0, 1/4, 3/4, 1
+    const double x1 = 0.25, x2 = 0.75;
+    const double d01 = (f[1] - f[0]) / x1;
+    const double d12 = (f[2] - f[1]) / (x2 - x1);
+    const double d23 = (f[3] - f[2]) / (1.0 - x2);
+    const double d012 = (d12 - d01) / x2;
+    const double d123 = (d23 - d12) / (1.0 - x1);
+    const double d0123 = d123 - d012;
+    // p = f0 + d01 u + d012 u (u - x1) + d0123 u (u - x1) (u - x2)
+    c[0] = (float)f[0];
+    c[1] = (float)(d01 - d012 * x1 + d0123 * x1 * x2);
+    c[2] = (float)(d012 - d0123 * (x1 + x2));
+    c[3] = (float)d0123;
+}
+
+// interval i of the table of the system with FP64 constants C and eps^2 = e2
+SWIM_HD void tab_interval(const SysConst<double>& C, double e2, int i, TabE& out)
+{
+    const int e = i >> TAB_M, j = i & ((1 << TAB_M) - 1);
+    const double a = ldexp(1.0, e);
+    const double v0 = a * (1.0 + (double)j / (double)(1 << TAB_M)), hv = a / (double)(1 << TAB_M);
+    const double un[4] = {0.0, 0.25, 0.75, 1.0};
+    double fh[4], fg[4];
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+        // t = 0 is taken as a vanishing positive t, whose evaluation follows
+        // the near-contact series and gives the limits H2(0) and Ht(0) = 0
+        const double t = fmax((v0 - 1.0 + hv * un[k]) * e2, 1e-300);
+        kernel_eval<double>(C, t, fh[k], fg[k]);
+    }
+    cubic_lobatto(fh, out.h);
+    cubic_lobatto(fg, out.g);
+}
+
+// table index and local coordinate of t (index >= TAB_N: outside the table,
+// non-finite t included)
+SWIM_HD uint32_t tab_locate(float t, float inv_e2, float& u)
+{
+    const float v = fmaf(t, inv_e2, 1.0f);
+    uint32_t bits = __builtin_bit_cast(uint32_t, v) - 0x3F800000u;
+    u = (float)(bits & ((1u << TAB_SHIFT) - 1u)) * (1.0f / (float)(1u << TAB_SHIFT));
+    return bits >> TAB_SHIFT;
+}
+
+SWIM_HD void tab_eval(const TabE& e, float u, float& Ht, float& H2)
+{
+    Ht = fmaf(fmaf(fmaf(e.h[3], u, e.h[2]), u, e.h[1]), u, e.h[0]);
+    H2 = fmaf(fmaf(fmaf(e.g[3], u, e.g[2]), u, e.g[1]), u, e.g[0]);
+}
+
 }  // namespace swim

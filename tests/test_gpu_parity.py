@@ -71,6 +71,34 @@ def test_pair_velocity_matches_oracle(ctx, oracle_core, dtype, tol):
         assert e < tol, (s, _systems()[s], e)
 
 
+@pytest.mark.parametrize("alpha", [0.0, 0.7])
+def test_pair_velocity_far_pairs(ctx, oracle_core, alpha):
+    """FP32 pairs beyond the kernel table (r^2/eps^2 >= 2^24, here two
+    filaments about 60 body lengths apart at eps = 1.5/127) take the direct
+    evaluation; near pairs in the same system still use the table."""
+    N = 128
+    x1, y1 = inputs.filament_geometry(N, seed=41, n_swim=1)
+    x2, y2 = inputs.filament_geometry(N, seed=42, n_swim=1)
+    X = np.concatenate([x1, x2 + 60.0]).astype(np.float32)
+    Y = np.concatenate([y1, y2 + 5.0]).astype(np.float32)
+    fx1, fy1 = inputs.force_pattern(N, seed=43, n_swim=1)
+    fx2, fy2 = inputs.force_pattern(N, seed=44, n_swim=1)
+    # a net force on each filament makes the far pairs' share of the
+    # velocity large (a dropped or wrong far term fails the tolerance)
+    FX = np.concatenate([fx1 + 2.0, fx2 - 3.0]).astype(np.float32)
+    FY = np.concatenate([fy1 - 1.0, fy2 + 4.0]).astype(np.float32)
+    eps = 1.5 / (N - 1)
+    assert ((60.0 - 1.0) / eps) ** 2 > 2.0 ** 24
+    ux = torch.empty(2 * N, dtype=torch.float32, device="cuda")
+    uy = torch.empty_like(ux)
+    swim.swim_pair_velocity(ctx, np.array([0, 2 * N]), [alpha], [eps], dev(X, torch.float32), dev(Y, torch.float32),
+                            dev(FX, torch.float32), dev(FY, torch.float32), ux, uy)
+    torch.cuda.synchronize()
+    ox, oy = oracle_core.velocity(X, Y, FX, FY, alpha, eps)
+    g = np.concatenate([ux.cpu().double().numpy(), uy.cpu().double().numpy()])
+    assert rel(g, np.concatenate([ox, oy])) < 1e-5
+
+
 @pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-11), (swim.SWIM_F32, 1e-4)])
 def test_elastic_forces_match_oracle(ctx, oracle_core, dtype, tol):
     Ns = [5, 64, 127, 300]
