@@ -27,10 +27,22 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic FP32 operations of one pair evaluation (small-argument branch
-# of the kernel functions, transcendentals counted once, FMA = 2)
-FLOP_PER_PAIR = 123
+# Roofline of the dominant kernel (the persistent forward kernel).  Its pair
+# loop reads the kernel functions from a per-system table, so it is bound by
+# VALU instruction issue, not by FP32 FLOP: 28 VALU lane-operations per pair
+# evaluation (k_forward<float, 2, 16> hot loop: 56 per iteration of two
+# pairs, loop control excluded; 32 FP32 FLOP of them, FMA = 2, and 6
+# integer).  Peak issue rate without packed FP32: 256 CUs x 4 SIMDs x 16
+# lanes per clock x 2.4 GHz = 39.3e12 lane-operations/s (x 2 = 78.6 TFLOP/s
+# of FMA; the 157.3 TFLOP/s FP32 figure assumes packed FP32).
+VALU_OPS_PER_PAIR = 28
+FP32_FLOP_PER_PAIR = 32
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
+# HBM bytes of one launch of that kernel on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the same counters
+# over a 256 MiB device copy (x2.0 and x1.0)
+TRAFFIC_BYTES = (30490.2 * 2.0 + 37704.0) * 1024
 
 
 def load_data():
@@ -54,6 +66,46 @@ def cpu_baseline(steps_cpu):
     return {"value": pairs / dt, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
             "sample": f"1 swimmer (true alpha, S_b, S_s), N=128, {steps_cpu} of 5000 steps, FP64, "
                       f"{dt:.1f} s"}
+
+
+# weights of the surrogate MLP 5 -> 256 x 4 -> 33 (multiply-adds per row)
+MLP_MACS = 5 * 256 + 3 * 256 * 256 + 256 * 33
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def mlp_leg(ctx, stream, rows=1 << 20, train_rows=65536, batch=1024, epochs=2):
+    """BF16 MFMA throughput of the surrogate kernels: a forward pass over
+    `rows` inputs (the prescreen's GEMMs) and Adam training steps of
+    `batch` rows, timed with HIP events on the library's stream.
+    Algorithmic FLOP: 2 per multiply-add of the unpadded layers; a training
+    step is a forward and a backward pass (3x the forward's GEMM work)."""
+    import torch
+    from paper_1910_12007_amd import inputs, swim
+    g = torch.Generator().manual_seed(7)
+    X = torch.randn(rows, 5, generator=g).to("cuda")
+    Y = torch.empty(rows, 33, device="cuda")
+    Xt = X[:train_rows].contiguous()
+    Tt = torch.randn(train_rows, 33, generator=g).to("cuda")
+    params = torch.from_numpy(inputs.mlp_init(0)[1]).to("cuda")
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    perm = torch.from_numpy(inputs.epoch_permutations(train_rows, epochs, 7)).to("cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    swim.surrogate_forward(ctx, X, params, Y, stream=stream)  # warm-up
+    ev[0].record(stream)
+    swim.surrogate_forward(ctx, X, params, Y, stream=stream)
+    ev[1].record(stream)
+    ev[2].record(stream)
+    swim.surrogate_train(ctx, Xt, Tt, perm, epochs, batch, 1e-3, params, m, v, stream=stream)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    fwd_ms, train_ms = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+    steps = epochs * (train_rows // batch)
+    fwd_tf = 2.0 * MLP_MACS * rows / (fwd_ms * 1e-3) / 1e12
+    train_tf = 6.0 * MLP_MACS * batch * steps / (train_ms * 1e-3) / 1e12
+    return {"forward_rows": rows, "forward_ms": fwd_ms, "forward_tflops": fwd_tf,
+            "train_steps": steps, "train_batch": batch, "train_ms": train_ms, "train_tflops": train_tf,
+            "peak_tflops": BF16_PEAK_TFLOPS, "forward_frac": fwd_tf / BF16_PEAK_TFLOPS,
+            "train_frac": train_tf / BF16_PEAK_TFLOPS, "dtype": "bf16 operands, fp32 accumulation"}
 
 
 def surrogate_leg(ctx, data):
@@ -91,6 +143,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--wps", type=int, default=0, help="waves per system (0: library default)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-prescreened ABC comparison")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes (3 times), the reference "
+                         "for scaling the HBM byte counters, and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the swimmer batches are "
@@ -98,6 +153,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_bytes:
+        a = torch.empty(args.copy_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4}), flush=True)
+        return
 
     from paper_1910_12007_amd import inputs, swim
 
@@ -148,7 +213,7 @@ def main():
     fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     n_acc = int(acc.sum().item())
     st = status.cpu().numpy()
-    achieved = FLOP_PER_PAIR * pairs / (fwd_ms * 1e-3) / 1e12
+    achieved = VALU_OPS_PER_PAIR * pairs / (fwd_ms * 1e-3) / 1e12
     out = {
         "metric": "swimmer steps/s & Brinkmanlet pair-evals/s; ABC accepts/s surrogate vs plain",
         "value": pairs * args.steps / wall,
@@ -170,11 +235,15 @@ def main():
         "abc_accepted": n_acc,
         "abc_tolerance": tol.item(),
         "runs_stopped": int(np.sum(st != 0)),
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_forward<float,2,wps> (persistent forward run)",
-                     "kernel_ms": fwd_ms, "flop_per_pair": FLOP_PER_PAIR},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "TOP/s (VALU lane-operations)", "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": TRAFFIC_BYTES,
+                     "kernel": "k_forward<float,2,16> (persistent forward run)", "kernel_ms": fwd_ms,
+                     "valu_ops_per_pair": VALU_OPS_PER_PAIR, "fp32_flop_per_pair": FP32_FLOP_PER_PAIR,
+                     "fp32_tflops": FP32_FLOP_PER_PAIR * pairs / (fwd_ms * 1e-3) / 1e12,
+                     "fp32_peak_tflops": FP32_PEAK_TFLOPS},
     }
+    out["surrogate_mfma"] = mlp_leg(ctx, stream)
     if not args.no_surrogate:
         out["surrogate_abc"] = surrogate_leg(ctx, load_data())
     if not args.no_cpu:

@@ -61,7 +61,7 @@ enum BufId {
     B_OFF, B_SWOFF, B_NPT, B_NSW, B_ORDER, B_LIST, B_BLKS, B_BLKF, B_ALPHA, B_EPS, B_SYSC, B_QUEUE,
     B_PARAMS, B_DATA, B_OBS, B_SPEED, B_STATUS, B_DIST, B_TOL, B_ACC, B_BIG,
     B_MLP_ACT, B_MLP_GRAD, B_MLP_BATCH, B_MLP_IDX, B_MLP_CNT,
-    B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_TAB, B_BLKSL, B_NBUF
+    B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_TAB, B_NBUF
 };
 
 // surrogate network: 5 -> 256 x 4 -> 33
@@ -250,9 +250,9 @@ int sysconst_buffers(swim_ctx* c, int32_t dtype, int64_t n_sys, void** sysc, voi
 // ------------------------------------------------------------------------
 // forward run (shared by swim_forward and abc_step)
 // ------------------------------------------------------------------------
-int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, const int32_t* nswim,
-                 const double* params_dev, const Run& run, void* obs, void* speed, int32_t* status,
-                 int32_t* steps_done, hipStream_t st)
+int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, const int32_t* nswim,
+                  const double* params_dev, const Run& run, void* obs, void* speed, int32_t* status,
+                  int32_t* steps_done, hipStream_t st)
 {
     if (n_sys == 0) return SWIM_OK;
     std::vector<int64_t> sw_off(n_sys + 1, 0), big_off(n_sys, 0);
@@ -288,15 +288,14 @@ int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
     }
     // large systems: target blocks of 256 * tpl_big points
     const int tpl_big = c->opt_big_tpl ? c->opt_big_tpl : 1;
-    std::vector<int64_t> blk_s, blk_f, blk_sl;
-    for (size_t q = 0; q < big_list.size(); ++q)
-        for (int64_t f = 0; f < pts[big_list[q]]; f += 256 * tpl_big) {
-            blk_s.push_back(big_list[q]);
+    std::vector<int64_t> blk_s, blk_f;
+    for (int64_t s : big_list)
+        for (int64_t f = 0; f < pts[s]; f += 256 * tpl_big) {
+            blk_s.push_back(s);
             blk_f.push_back(f);
-            blk_sl.push_back((int64_t)q);
         }
     const size_t es = dtype == SWIM_F32 ? 4 : 8;
-    size_t total = (sw_off.size() + big_off.size() + big_list.size() + 3 * blk_s.size()) * 8 +
+    size_t total = (sw_off.size() + big_off.size() + big_list.size() + 2 * blk_s.size()) * 8 +
                    (nsw.size() + order.size()) * 4 + n_sys * 4 + 64;
     TRY(begin_uploads(c, total));
     TRY(stage(c, sw_off.data(), sw_off.size() * 8, B_SWOFF, st));
@@ -307,7 +306,6 @@ int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
     TRY(stage(c, big_list.data(), big_list.size() * 8, B_LIST, st));
     TRY(stage(c, blk_s.data(), blk_s.size() * 8, B_BLKS, st));
     TRY(stage(c, blk_f.data(), blk_f.size() * 8, B_BLKF, st));
-    TRY(stage(c, blk_sl.data(), blk_sl.size() * 8, B_BLKSL, st));
     TRY(end_uploads(c, st));
     void *sysc, *sysc64;
     TRY(sysconst_buffers(c, dtype, n_sys, &sysc, &sysc64));
@@ -323,6 +321,12 @@ int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
     b.params = params_dev;
     b.sysc = sysc;
     b.sysc64 = sysc64;
+    b.tab = nullptr;
+    if (dtype == SWIM_F32) {
+        TRY(ensure(c, B_TAB, (size_t)n_sys * table_bytes()));
+        HIPCHK(launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, st));
+        b.tab = c->buf[B_TAB].p;
+    }
     HIPCHK(launch_fill_i32((int32_t*)c->buf[B_QUEUE].p, 0, 8, st));
     for (size_t k = 0; k < bucket_span.size(); ++k) {
         const int tpl = bucket_span[k].first;
@@ -350,27 +354,45 @@ int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
             S.yl[q] = base + (6 + q) * one;
         }
         S.head0 = base + 8 * one;
-        S.tab = nullptr;
         if (big_step_lds_bytes(dtype, max_big) > 160 * 1024)
             return fail(SWIM_EINVAL, "system of %d points exceeds the LDS capacity", max_big);
-        if (dtype == SWIM_F32) {
-            TRY(ensure(c, B_TAB, big_list.size() * table_bytes()));
-            HIPCHK(launch_table_build((const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), sysc64,
-                                      c->buf[B_TAB].p, st));
-            S.tab = c->buf[B_TAB].p;
-        }
         HIPCHK(launch_big_init(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S, status, obs,
                                run.n_obs, st));
         for (int step = 0; step < run.steps; ++step)
             HIPCHK(launch_big_step(dtype, tpl_big, (int64_t)blk_s.size(), (const int64_t*)c->buf[B_BLKS].p,
-                                   (const int64_t*)c->buf[B_BLKF].p, (const int64_t*)c->buf[B_BLKSL].p, max_big, b, S,
-                                   step, run, obs, status, steps_done, st));
+                                   (const int64_t*)c->buf[B_BLKF].p, max_big, b, S, step, run, obs, status,
+                                   steps_done, st));
         HIPCHK(launch_big_finish(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S,
                                  run.steps & 1, run, speed, status, steps_done, st));
     }
     return SWIM_OK;
 }
 
+
+// FP32 runs keep one kernel table per system in HBM (12 KB each), so very
+// large batches run in chunks of FWD_CHUNK systems; the systems are
+// independent and their order within a batch does not change any result.
+constexpr int64_t FWD_CHUNK = 262144;
+
+int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, const int32_t* nswim,
+                 const double* params_dev, const Run& run, void* obs, void* speed, int32_t* status,
+                 int32_t* steps_done, hipStream_t st)
+{
+    if (dtype != SWIM_F32 || n_sys <= FWD_CHUNK)
+        return forward_chunk(c, dtype, n_sys, N, nswim, params_dev, run, obs, speed, status, steps_done, st);
+    const size_t es = 4;
+    int64_t f0 = 0;  // first filament of the chunk
+    for (int64_t s0 = 0; s0 < n_sys; s0 += FWD_CHUNK) {
+        const int64_t m = std::min(FWD_CHUNK, n_sys - s0);
+        int64_t nf = 0;
+        for (int64_t s = s0; s < s0 + m; ++s) nf += nswim ? nswim[s] : 1;
+        TRY(forward_chunk(c, dtype, m, N + s0, nswim ? nswim + s0 : nullptr, params_dev + f0 * SWIM_NPARAM, run,
+                          (char*)obs + (size_t)f0 * run.n_obs * 2 * es, (char*)speed + (size_t)f0 * es, status + s0,
+                          steps_done ? steps_done + s0 : nullptr, st));
+        f0 += nf;
+    }
+    return SWIM_OK;
+}
 
 // ------------------------------------------------------------------------
 // surrogate MLP: forward and backward over M rows (workspace in the ctx)
@@ -555,8 +577,14 @@ int swim_pair_velocity(swim_ctx* c, int32_t dtype, int64_t n_sys, const int64_t*
     TRY(sysconst_buffers(c, dtype, n_sys, &sysc, &sysc64));
     HIPCHK(launch_sysconst(dtype, n_sys, (const double*)c->buf[B_ALPHA].p, (const double*)c->buf[B_EPS].p, sysc,
                            sysc64, st));
+    void* tab = nullptr;
+    if (dtype == SWIM_F32) {
+        TRY(ensure(c, B_TAB, (size_t)n_sys * table_bytes()));
+        HIPCHK(launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, st));
+        tab = c->buf[B_TAB].p;
+    }
     HIPCHK(launch_pair_velocity(dtype, tpl, (int64_t)bs.size(), (const int64_t*)c->buf[B_BLKS].p,
-                                (const int64_t*)c->buf[B_BLKF].p, (const int64_t*)c->buf[B_OFF].p, sysc, sysc64, x, y,
+                                (const int64_t*)c->buf[B_BLKF].p, (const int64_t*)c->buf[B_OFF].p, sysc, tab, x, y,
                                 fx, fy, ux, uy, st));
     return SWIM_OK;
 }

@@ -21,6 +21,7 @@ struct Batch {
     const double* params;    // [n_filaments][9]
     const void* sysc;        // SysConst<T>[n_sys]
     const void* sysc64;      // SysConst<double>[n_sys] (FP32 runs: builds the kernel tables)
+    const void* tab;         // FP32 runs: TabE[n_sys][TAB_N] kernel tables
 };
 
 struct Run {
@@ -40,13 +41,12 @@ hipError_t launch_sysconst(int dtype, int64_t n_sys, const double* alpha, const 
                            void* sysc, void* sysc64, hipStream_t st);
 hipError_t launch_pair_velocity(int dtype, int tpl, int64_t n_blocks, const int64_t* blk_sys,
                                 const int64_t* blk_first, const int64_t* pt_off, const void* sysc,
-                                const void* sysc64, const void* x, const void* y, const void* fx,
+                                const void* tab, const void* x, const void* y, const void* fx,
                                 const void* fy, void* ux, void* uy, hipStream_t st);
 // bytes of one system's FP32 kernel table
 size_t table_bytes();
-// FP32 kernel tables of the systems list[0..n_list) into tab[slot][...]
-hipError_t launch_table_build(const int64_t* list, int64_t n_list, const void* sysc64, void* tab,
-                              hipStream_t st);
+// FP32 kernel tables of systems [s0, s0 + n) (FP64 constants sysc64) into tab[s]
+hipError_t launch_table_build(int64_t s0, int64_t n, const void* sysc64, void* tab, hipStream_t st);
 hipError_t launch_forces(int dtype, int64_t n_fil, const int64_t* fil_off, const int32_t* npt,
                          const double* params, double t, const void* x, const void* y, void* fx,
                          void* fy, hipStream_t st);
@@ -64,13 +64,12 @@ struct BigState {
     void* xl[2];   // lo parts
     void* yl[2];
     void* head0;   // [n_filaments][2] T, initial head positions
-    const void* tab;  // FP32: kernel tables, one per entry of the large-system list
 };
 hipError_t launch_big_init(int dtype, const int64_t* list, int64_t n_list, const Batch& b,
                            const BigState& s, int32_t* status, void* obs, int32_t n_obs,
                            hipStream_t st);
 hipError_t launch_big_step(int dtype, int tpl, int64_t n_blocks, const int64_t* blk_sys,
-                           const int64_t* blk_first, const int64_t* blk_slot, int32_t max_pts, const Batch& b,
+                           const int64_t* blk_first, int32_t max_pts, const Batch& b,
                            const BigState& s, int step, const Run& r, void* obs, int32_t* status,
                            int32_t* steps_done, hipStream_t st);
 hipError_t launch_big_finish(int dtype, const int64_t* list, int64_t n_list, const Batch& b,

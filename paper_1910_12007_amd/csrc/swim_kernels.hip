@@ -210,12 +210,12 @@ __device__ __forceinline__ void pair_accumulate(const SysConst<T>& C, const TabE
     }
 }
 
-// the FP32 kernel table of one system, built cooperatively by nthreads
-// threads (thread id tid) into tab; not inlined, so that the FP64
-// evaluation's registers do not add to those of the caller's loops
-__device__ __attribute__((noinline)) void tab_build(const SysConst<double>* C64, TabE* tab, int tid, int nthreads)
+// copy one system's FP32 kernel table from HBM into LDS (nthreads threads)
+__device__ __forceinline__ void tab_load(const TabE* g, TabE* tab, int tid, int nthreads)
 {
-    for (int i = tid; i < TAB_N; i += nthreads) tab_interval(*C64, C64->e2, i, tab[i]);
+    const float4* src = reinterpret_cast<const float4*>(g);
+    float4* dst = reinterpret_cast<float4*>(tab);
+    for (int i = tid; i < 2 * TAB_N; i += nthreads) dst[i] = src[i];
 }
 
 // error-free (hi, lo) += d  (TwoSum, then renormalize)
@@ -262,14 +262,16 @@ __global__ void k_sysconst_batch(int64_t n, const int64_t* sw_off, const int32_t
     if (out64) sysconst_compute<double>(ok ? alpha : 0.0, eps, out64 + s);
 }
 
-// FP32 kernel tables of the listed systems, one thread per interval
-__global__ void k_table_build(const int64_t* list, const SysConst<double>* sysc64, TabE* tab)
+// FP32 kernel tables of systems [s0, s0 + n), one thread per interval; the
+// FP64 evaluation's registers stay out of the kernels that use the tables
+__global__ __launch_bounds__(64) void k_table_build(int64_t s0, int64_t n, const SysConst<double>* sysc64, TabE* tab)
 {
-    const int64_t slot = blockIdx.y;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= TAB_N) return;
-    const SysConst<double>& C = sysc64[list[slot]];
-    tab_interval(C, C.e2, i, tab[slot * TAB_N + i]);
+    const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int64_t s = s0 + e / TAB_N;
+    const int i = (int)(e % TAB_N);
+    if (e >= n * TAB_N) return;
+    const SysConst<double>& C = sysc64[s];
+    tab_interval(C, C.e2, i, tab[s * TAB_N + i]);
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
@@ -286,8 +288,8 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
 template <typename T, int TPL>
 __global__ __launch_bounds__(256) void k_pair_velocity(const int64_t* blk_sys, const int64_t* blk_first,
                                                         const int64_t* pt_off, const SysConst<T>* sysc,
-                                                        const SysConst<double>* sysc64, const T* x, const T* y,
-                                                        const T* fx, const T* fy, T* ux, T* uy)
+                                                        const TabE* tabs, const T* x, const T* y, const T* fx,
+                                                        const T* fy, T* ux, T* uy)
 {
     __shared__ Src4<T> tile[256];
     __shared__ T red[2][4];
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(256) void k_pair_velocity(const int64_t* blk_sys, c
     const int64_t p0 = pt_off[s];
     const int64_t n = pt_off[s + 1] - p0;
     const SysConst<T> C = sysc[s];
-    if constexpr (sizeof(T) == 4) tab_build(sysc64 + s, tab, tid, 256);
+    if constexpr (sizeof(T) == 4) tab_load(tabs + s * TAB_N, tab, tid, 256);
     T xi[TPL], yi[TPL], ax[TPL], ay[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -411,7 +413,7 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
     }
     const SysConst<T> C = ((const SysConst<T>*)b.sysc)[s];
     const double dsd = 1.0 / (double)(N - 1);
-    if constexpr (COMP) tab_build((const SysConst<double>*)b.sysc64 + s, L.tab, tid, NT);
+    if constexpr (COMP) tab_load((const TabE*)b.tab + (int64_t)s * TAB_N, L.tab, tid, NT);
 
     // owned points i = tid + NT*q: positions as (hi, lo)
     T xh[OWN], yh[OWN], xl[OWN], yl[OWN];
@@ -655,9 +657,9 @@ __global__ void k_big_init(const int64_t* list, Batch b, BigState S, int32_t* st
 }
 
 template <typename T, int TPL>
-__global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const int64_t* blk_first,
-                                                  const int64_t* blk_slot, Batch b, BigState S, int step, Run r,
-                                                  T* obs, int32_t* status, int32_t* steps_done)
+__global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const int64_t* blk_first, Batch b,
+                                                  BigState S, int step, Run r, T* obs, int32_t* status,
+                                                  int32_t* steps_done)
 {
     constexpr bool COMP = sizeof(T) == 4;
     constexpr size_t TABB = COMP ? TAB_N * sizeof(TabE) : 0;
@@ -668,11 +670,7 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
     const int tid = threadIdx.x;
     const int64_t s = blk_sys[blockIdx.x];
     if (status[s] != 0) return;
-    if constexpr (COMP) {
-        // this system's table, built once before the first step
-        const TabE* g = (const TabE*)S.tab + blk_slot[blockIdx.x] * TAB_N;
-        for (int i = tid; i < TAB_N; i += 256) tab[i] = g[i];
-    }
+    if constexpr (COMP) tab_load((const TabE*)b.tab + s * TAB_N, tab, tid, 256);
     const int64_t first = blk_first[blockIdx.x];
     const int64_t p0 = b.pt_off[s];
     const int N = b.npt[s];
@@ -912,10 +910,10 @@ hipError_t launch_sysconst(int dtype, int64_t n_sys, const double* alpha, const 
 
 size_t table_bytes() { return (size_t)TAB_N * sizeof(TabE); }
 
-hipError_t launch_table_build(const int64_t* list, int64_t n_list, const void* sysc64, void* tab, hipStream_t st)
+hipError_t launch_table_build(int64_t s0, int64_t n, const void* sysc64, void* tab, hipStream_t st)
 {
-    if (n_list <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_table_build, dim3(nblk(TAB_N, 64), (unsigned)n_list), dim3(64), 0, st, list,
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_table_build, dim3((unsigned)nblk(n * TAB_N, 64)), dim3(64), 0, st, s0, n,
                        (const SysConst<double>*)sysc64, (TabE*)tab);
     return hipGetLastError();
 }
@@ -929,21 +927,21 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st)
 
 template <typename T, int TPL>
 static void pair_launch(int64_t nb, const int64_t* bs, const int64_t* bf, const int64_t* off, const void* sysc,
-                        const void* sysc64, const void* x, const void* y, const void* fx, const void* fy, void* ux,
+                        const void* tab, const void* x, const void* y, const void* fx, const void* fy, void* ux,
                         void* uy, hipStream_t st)
 {
     hipLaunchKernelGGL((k_pair_velocity<T, TPL>), dim3((unsigned)nb), dim3(256), 0, st, bs, bf, off,
-                       (const SysConst<T>*)sysc, (const SysConst<double>*)sysc64, (const T*)x, (const T*)y,
-                       (const T*)fx, (const T*)fy, (T*)ux, (T*)uy);
+                       (const SysConst<T>*)sysc, (const TabE*)tab, (const T*)x, (const T*)y, (const T*)fx,
+                       (const T*)fy, (T*)ux, (T*)uy);
 }
 
 hipError_t launch_pair_velocity(int dtype, int tpl, int64_t nb, const int64_t* bs, const int64_t* bf,
-                                const int64_t* off, const void* sysc, const void* sysc64, const void* x,
-                                const void* y, const void* fx, const void* fy, void* ux, void* uy, hipStream_t st)
+                                const int64_t* off, const void* sysc, const void* tab, const void* x, const void* y,
+                                const void* fx, const void* fy, void* ux, void* uy, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
 #define PAIR_CASE(T, P) \
-    case P: pair_launch<T, P>(nb, bs, bf, off, sysc, sysc64, x, y, fx, fy, ux, uy, st); break;
+    case P: pair_launch<T, P>(nb, bs, bf, off, sysc, tab, x, y, fx, fy, ux, uy, st); break;
     if (dtype == 0) {
         switch (tpl) { PAIR_CASE(float, 1) PAIR_CASE(float, 2) PAIR_CASE(float, 4) default: return hipErrorInvalidValue; }
     } else {
@@ -1056,9 +1054,9 @@ size_t big_step_lds_bytes(int dtype, int32_t max_pts)
 }
 
 template <typename T, int TPL>
-static hipError_t big_launch(int64_t nb, const int64_t* bs, const int64_t* bf, const int64_t* bsl, int32_t max_pts,
-                             const Batch& b, const BigState& s, int step, const Run& r, void* obs, int32_t* status,
-                             int32_t* done, hipStream_t st)
+static hipError_t big_launch(int64_t nb, const int64_t* bs, const int64_t* bf, int32_t max_pts, const Batch& b,
+                             const BigState& s, int step, const Run& r, void* obs, int32_t* status, int32_t* done,
+                             hipStream_t st)
 {
     const size_t lds = big_step_lds_bytes(sizeof(T) == 4 ? 0 : 1, max_pts);
     static size_t attr_lds = 0;
@@ -1068,17 +1066,17 @@ static hipError_t big_launch(int64_t nb, const int64_t* bs, const int64_t* bf, c
         if (e != hipSuccess) return e;
         attr_lds = lds;
     }
-    hipLaunchKernelGGL((k_big_step<T, TPL>), dim3((unsigned)nb), dim3(256), lds, st, bs, bf, bsl, b, s, step, r,
-                       (T*)obs, status, done);
+    hipLaunchKernelGGL((k_big_step<T, TPL>), dim3((unsigned)nb), dim3(256), lds, st, bs, bf, b, s, step, r, (T*)obs,
+                       status, done);
     return hipGetLastError();
 }
 
-hipError_t launch_big_step(int dtype, int tpl, int64_t nb, const int64_t* bs, const int64_t* bf, const int64_t* bsl,
-                           int32_t max_pts, const Batch& b, const BigState& s, int step, const Run& r, void* obs,
-                           int32_t* status, int32_t* steps_done, hipStream_t st)
+hipError_t launch_big_step(int dtype, int tpl, int64_t nb, const int64_t* bs, const int64_t* bf, int32_t max_pts,
+                           const Batch& b, const BigState& s, int step, const Run& r, void* obs, int32_t* status,
+                           int32_t* steps_done, hipStream_t st)
 {
 #define BIG_CASE(T, P) \
-    case P: return big_launch<T, P>(nb, bs, bf, bsl, max_pts, b, s, step, r, obs, status, steps_done, st);
+    case P: return big_launch<T, P>(nb, bs, bf, max_pts, b, s, step, r, obs, status, steps_done, st);
     if (dtype == 0) {
         switch (tpl) { BIG_CASE(float, 1) BIG_CASE(float, 2) BIG_CASE(float, 4) default: return hipErrorInvalidValue; }
     } else {

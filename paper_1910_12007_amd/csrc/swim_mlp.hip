@@ -65,18 +65,22 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const fl
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    // consecutive threads take consecutive addresses of each operand: along k
+    // when its k stride is 1, along m (n) otherwise (the transposed operands
+    // of the backward pass)
+    const bool a_k_fast = sak == 1, b_n_fast = sbn == 1 || sbk != 1;
     for (int k0 = 0; k0 < K; k0 += GK) {
 #pragma unroll
         for (int i = 0; i < (GT * GK) / 256; ++i) {
             const int e = tid + 256 * i;
-            const int r = e / GK, kk = e % GK;
+            const int r = a_k_fast ? e / GK : e % GT, kk = a_k_fast ? e % GK : e / GT;
             const int m = m0 + r, k = k0 + kk;
             As[r][kk] = (m < M && k < K) ? f2bf(A[(int64_t)m * sam + (int64_t)k * sak]) : (uint16_t)0;
         }
 #pragma unroll
         for (int i = 0; i < (GT * GK) / 256; ++i) {
             const int e = tid + 256 * i;
-            const int kk = e / GT, c = e % GT;
+            const int kk = b_n_fast ? e / GT : e % GK, c = b_n_fast ? e % GT : e / GK;
             const int n = n0 + c, k = k0 + kk;
             Bs[c][kk] = (n < N && k < K) ? f2bf(B[(int64_t)k * sbk + (int64_t)n * sbn]) : (uint16_t)0;
         }
@@ -128,14 +132,25 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const fl
             }
 }
 
-// out[n] = sum_m A[m*lda + n]  (bias gradients), fixed summation order
-__global__ void k_colsum(int M, int N, const float* A, int64_t lda, float* out)
+// out[n] = sum_m A[m*lda + n]  (bias gradients): a workgroup sums 64
+// columns, 16 row groups each summing every 16th row, then the 16 partial
+// sums in a fixed order (deterministic)
+__global__ __launch_bounds__(1024) void k_colsum(int M, int N, const float* A, int64_t lda, float* out)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+    __shared__ float part[16][64];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + c;
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += A[(int64_t)m * lda + n];
-    out[n] = s;
+    if (n < N)
+        for (int m = g; m < M; m += 16) s += A[(int64_t)m * lda + n];
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0 && n < N) {
+        float t = 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t += part[q][c];
+        out[n] = t;
+    }
 }
 
 // dY = 2 (Y - T) / (M * N); per-row squared error (for the loss)
@@ -267,7 +282,7 @@ hipError_t launch_gemm_bf16(int epi, int M, int N, int K, const float* A, int64_
 
 hipError_t launch_colsum(int M, int N, const float* A, int64_t lda, float* out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, st, M, N, A, lda, out);
+    hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64), dim3(1024), 0, st, M, N, A, lda, out);
     return hipGetLastError();
 }
 
