@@ -37,12 +37,17 @@ sys.path.insert(0, ROOT)
 # of FMA; the 157.3 TFLOP/s FP32 figure assumes packed FP32).
 VALU_OPS_PER_PAIR = 28
 FP32_FLOP_PER_PAIR = 32
+# the large-system kernel k_big_step<float, 1> (one target per lane, FP64
+# accumulation): 79 VALU per unrolled iteration of two pairs, loop control
+# included
+VALU_OPS_PER_PAIR_BIG = 39
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 # HBM bytes of one launch of that kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the same counters
-# over a 256 MiB device copy (x2.0 and x1.0)
-TRAFFIC_BYTES = (30490.2 * 2.0 + 37704.0) * 1024
+# over a 256 MiB device copy (x2.0 and x1.0); None until the counters are
+# taken again for the kernel as it stands
+TRAFFIC_BYTES = None
 
 
 def load_data():
@@ -108,6 +113,74 @@ def mlp_leg(ctx, stream, rows=1 << 20, train_rows=65536, batch=1024, epochs=2):
             "train_frac": train_tf / BF16_PEAK_TFLOPS, "dtype": "bf16 operands, fp32 accumulation"}
 
 
+def dense_leg(ctx, stream, with_oracle, samples=64, steps=1000):
+    """Large-N dense workload: `samples` independent systems of 8 interacting
+    swimmers of N = 512 (4096 points) on a 2 x 4 grid of spacing 1.5, random
+    beat phases, alpha ~ U[0, 10] (seed 3), FP32.  The stated dt = 2e-5 is
+    beyond forward Euler's stability bound at N = 512 (dt * rho ~ 51), so the
+    run uses the largest stable power-of-two fraction, dt / 32; the work per
+    step does not depend on dt.  Runs on the per-step large-system kernel.
+    With the oracle: the velocity of sample 0 at its initial configuration
+    (forces at t = 0) against the FP64 oracle, all 4096 points."""
+    import torch
+    from paper_1910_12007_amd import inputs, swim
+    lay = inputs.dense_layout(n_samples=samples, seed=3)
+    P = torch.from_numpy(lay.reshape(-1, 9)).to("cuda")
+    N = np.full(samples, 512, np.int32)
+    nsw = np.full(samples, 8, np.int32)
+    dt = 2e-5 / 32
+    nfil = samples * 8
+    obs = torch.empty((nfil, steps // 100, 2), dtype=torch.float32, device="cuda")
+    speed = torch.empty(nfil, dtype=torch.float32, device="cuda")
+    status = torch.empty(samples, dtype=torch.int32, device="cuda")
+    done = torch.empty(samples, dtype=torch.int32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    warm = torch.empty((nfil, 1, 2), dtype=torch.float32, device="cuda")
+    swim.swim_forward(ctx, N, nsw, P, 10, dt, 10, 1.5, warm, speed, status, done, stream=stream)  # warm-up
+    ev[0].record(stream)
+    swim.swim_forward(ctx, N, nsw, P, steps, dt, 100, 1.5, obs, speed, status, done, stream=stream)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    d = done.cpu().numpy().astype(np.int64)
+    pairs = float(np.sum(d * 4096 * 4096))
+    out = {"workload": f"{samples} samples x 8 swimmers x N=512 (2x4 grid, spacing 1.5), {steps} Euler steps of "
+                       f"dt=2e-5/32 (stability), FP32, per-step large-system kernel",
+           "ms": ms, "pair_evals_per_s": pairs / (ms * 1e-3), "swimmer_steps_per_s": float(np.sum(d)) * 8 / (ms * 1e-3),
+           "runs_stopped": int(np.sum(status.cpu().numpy() != 0)),
+           "valu_tops": VALU_OPS_PER_PAIR_BIG * pairs / (ms * 1e-3) / 1e12, "valu_peak_tops": VALU_PEAK_TOPS,
+           "valu_frac": VALU_OPS_PER_PAIR_BIG * pairs / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+           "valu_ops_per_pair": VALU_OPS_PER_PAIR_BIG}
+    if with_oracle:
+        from oracle import core
+        P0 = lay[0]
+        xs, ys = [], []
+        for m in range(8):
+            s_ = np.arange(512) / 511.0
+            xs.append(P0[m, 7] + s_)
+            ys.append(np.full(512, P0[m, 8]))
+        X, Y = np.concatenate(xs), np.concatenate(ys)
+        kap = [core.kappa0(512, P0[m, 3], P0[m, 5], P0[m, 4], P0[m, 6], 0.0) for m in range(8)]
+        F = [core.forces(xs[m], ys[m], P0[m, 1], P0[m, 2], kap[m]) for m in range(8)]
+        FX = np.concatenate([f[0] for f in F])
+        FY = np.concatenate([f[1] for f in F])
+        # the oracle takes the FP32 run's inputs (positions, forces rounded to FP32)
+        X, Y, FX, FY = (a.astype(np.float32).astype(np.float64) for a in (X, Y, FX, FY))
+        eps = 1.5 / 511
+        ox, oy = core.velocity(X, Y, FX, FY, P0[0, 0], eps)
+        t32 = torch.float32
+        ux = torch.empty(4096, dtype=t32, device="cuda")
+        uy = torch.empty_like(ux)
+        dv = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda")
+        swim.swim_pair_velocity(ctx, np.array([0, 4096]), [P0[0, 0]], [eps], dv(X), dv(Y), dv(FX), dv(FY), ux, uy,
+                                stream=stream)
+        torch.cuda.synchronize()
+        g = np.concatenate([ux.cpu().double().numpy(), uy.cpu().double().numpy()])
+        r = np.concatenate([ox, oy])
+        out["sample0_velocity_rel_err_vs_fp64_oracle"] = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+    return out
+
+
 def surrogate_leg(ctx, data):
     """Surrogate-prescreened ABC against plain batched ABC on the same 1M
     prior draws (tolerance: the 5th percentile of the completed runs of the
@@ -143,6 +216,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--wps", type=int, default=0, help="waves per system (0: library default)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-prescreened ABC comparison")
+    ap.add_argument("--no-dense", action="store_true", help="skip the large-N dense workload")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times), the reference "
                          "for scaling the HBM byte counters, and exit")
@@ -244,6 +318,8 @@ def main():
                      "fp32_peak_tflops": FP32_PEAK_TFLOPS},
     }
     out["surrogate_mfma"] = mlp_leg(ctx, stream)
+    if not args.no_dense:
+        out["dense"] = dense_leg(ctx, stream, with_oracle=not args.no_cpu)
     if not args.no_surrogate:
         out["surrogate_abc"] = surrogate_leg(ctx, load_data())
     if not args.no_cpu:

@@ -860,7 +860,7 @@ int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, co
         SysConst<double> C64;
         sysconst_compute<double>(alpha, eps, &C64);
         std::vector<TabE> tab(TAB_N);
-        for (int i = 0; i < TAB_N; ++i) tab_interval(C64, eps * eps, i, tab[i]);
+        for (int i = 0; i < TAB_N; ++i) tab_interval(C64, eps * eps, i, tab[i], nullptr);
         for (int64_t i = 0; i < n; ++i) {
             float a, b, u;
             const float tf = (float)t[i];

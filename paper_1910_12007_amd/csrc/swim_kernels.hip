@@ -147,7 +147,7 @@ __device__ __forceinline__ void point_force(const Seg& seg, int p, const FilP<T>
 // directly; FP32 reads them from the system's table in LDS (tab), with the
 // direct evaluation for pairs beyond its last octave.
 template <typename T, int TPL>
-__device__ __forceinline__ void pair_accumulate(const SysConst<T>& C, const TabE* tab, const Src4<T>* src, int n,
+__device__ __forceinline__ void pair_accumulate(const SysConst<T>& C, const TabSys* tab, const Src4<T>* src, int n,
                                                 const T (&xi)[TPL], const T (&yi)[TPL],
                                                 T (&ax)[TPL], T (&ay)[TPL])
 {
@@ -166,7 +166,7 @@ __device__ __forceinline__ void pair_accumulate(const SysConst<T>& C, const TabE
                 const uint32_t id = tab_locate(t, ie2, u);
                 const bool in = id < (uint32_t)TAB_N;
                 far = far || !in;
-                tab_eval(tab[in ? id : 0u], u, Ht, H2);
+                tab_eval(tab->e[in ? id : 0u], u, Ht, H2);
                 Ht = in ? Ht : 0.0f;
                 H2 = in ? H2 : 0.0f;
                 const T h2fd = H2 * fma_t(s.fx, dx, s.fy * dy);
@@ -210,12 +210,71 @@ __device__ __forceinline__ void pair_accumulate(const SysConst<T>& C, const TabE
     }
 }
 
+// FP32 pair sum with FP64 accumulation, for lanes that sum whole large
+// systems.  Filament forces alternate in sign with magnitudes far above the
+// velocity they produce (bending forces ~4e2 against velocities ~10 for
+// N = 512), so the FP32 rounding of Ht * F_j (Ht ~ 0.3) and of an FP32
+// running sum each leave ~1e-5 of relative error over thousands of sources.
+// Here Ht = h0 + (h0lo + increment) keeps the constant term in two floats,
+// the small in-interval increment is evaluated in FP32, and the products
+// (exact in FP64) accumulate in FP64, which this chip issues at the FP32
+// rate.  The H2 term stays in FP32 up to its product.
+template <int TPL>
+__device__ __forceinline__ void pair_accumulate_x(const SysConst<float>& C, const TabSys* tab,
+                                                  const Src4<float>* src, int n, const float (&xi)[TPL],
+                                                  const float (&yi)[TPL], double (&ax)[TPL], double (&ay)[TPL])
+{
+    bool far = false;
+    const float ie2 = C.inv_e2;
+    for (int j = 0; j < n; ++j) {
+        const Src4<float> s = src[j];
+        const double fx = s.fx, fy = s.fy;
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+            const float dx = xi[k] - s.x, dy = yi[k] - s.y;
+            const float t = fmaf(dx, dx, dy * dy);
+            float u;
+            const uint32_t id = tab_locate(t, ie2, u);
+            const bool in = id < (uint32_t)TAB_N;
+            far = far || !in;
+            const uint32_t ic = in ? id : 0u;
+            const TabE& e = tab->e[ic];
+            const float inc = u * fmaf(fmaf(e.h[3], u, e.h[2]), u, e.h[1]);
+            const float hi = in ? e.h[0] : 0.0f;
+            const float lo = in ? tab->h0lo[ic] + inc : 0.0f;
+            const float H2 = in ? fmaf(fmaf(fmaf(e.g[3], u, e.g[2]), u, e.g[1]), u, e.g[0]) : 0.0f;
+            const float h2fd = H2 * fmaf(s.fx, dx, s.fy * dy);
+            ax[k] = fma((double)hi, fx, fma((double)lo, fx, fma((double)h2fd, (double)dx, ax[k])));
+            ay[k] = fma((double)hi, fy, fma((double)lo, fy, fma((double)h2fd, (double)dy, ay[k])));
+        }
+    }
+    if (__any(far)) {
+        for (int j = 0; j < n; ++j) {
+            const Src4<float> s = src[j];
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) {
+                const float dx = xi[k] - s.x, dy = yi[k] - s.y;
+                const float t = fmaf(dx, dx, dy * dy);
+                float u;
+                if (tab_locate(t, ie2, u) >= (uint32_t)TAB_N) {
+                    float Ht, H2;
+                    kernel_eval<float>(C, t, Ht, H2);
+                    const float h2fd = H2 * fmaf(s.fx, dx, s.fy * dy);
+                    ax[k] = fma((double)Ht, (double)s.fx, fma((double)h2fd, (double)dx, ax[k]));
+                    ay[k] = fma((double)Ht, (double)s.fy, fma((double)h2fd, (double)dy, ay[k]));
+                }
+            }
+        }
+    }
+}
+
 // copy one system's FP32 kernel table from HBM into LDS (nthreads threads)
-__device__ __forceinline__ void tab_load(const TabE* g, TabE* tab, int tid, int nthreads)
+__device__ __forceinline__ void tab_load(const TabSys* g, TabSys* tab, int tid, int nthreads)
 {
     const float4* src = reinterpret_cast<const float4*>(g);
     float4* dst = reinterpret_cast<float4*>(tab);
-    for (int i = tid; i < 2 * TAB_N; i += nthreads) dst[i] = src[i];
+    constexpr int NV = (int)(sizeof(TabSys) / sizeof(float4));
+    for (int i = tid; i < NV; i += nthreads) dst[i] = src[i];
 }
 
 // error-free (hi, lo) += d  (TwoSum, then renormalize)
@@ -264,14 +323,14 @@ __global__ void k_sysconst_batch(int64_t n, const int64_t* sw_off, const int32_t
 
 // FP32 kernel tables of systems [s0, s0 + n), one thread per interval; the
 // FP64 evaluation's registers stay out of the kernels that use the tables
-__global__ __launch_bounds__(64) void k_table_build(int64_t s0, int64_t n, const SysConst<double>* sysc64, TabE* tab)
+__global__ __launch_bounds__(64) void k_table_build(int64_t s0, int64_t n, const SysConst<double>* sysc64, TabSys* tab)
 {
     const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int64_t s = s0 + e / TAB_N;
     const int i = (int)(e % TAB_N);
     if (e >= n * TAB_N) return;
     const SysConst<double>& C = sysc64[s];
-    tab_interval(C, C.e2, i, tab[s * TAB_N + i]);
+    tab_interval(C, C.e2, i, tab[s].e[i], &tab[s].h0lo[i]);
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
@@ -288,20 +347,23 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
 template <typename T, int TPL>
 __global__ __launch_bounds__(256) void k_pair_velocity(const int64_t* blk_sys, const int64_t* blk_first,
                                                         const int64_t* pt_off, const SysConst<T>* sysc,
-                                                        const TabE* tabs, const T* x, const T* y, const T* fx,
+                                                        const TabSys* tabs, const T* x, const T* y, const T* fx,
                                                         const T* fy, T* ux, T* uy)
 {
     __shared__ Src4<T> tile[256];
-    __shared__ T red[2][4];
-    __shared__ TabE tab[sizeof(T) == 4 ? TAB_N : 1];
+    __shared__ double red[2][4];
+    __shared__ TabSys tab_s[1];
+    TabSys* tab = tab_s;
     const int tid = threadIdx.x;
     const int64_t s = blk_sys[blockIdx.x];
     const int64_t first = blk_first[blockIdx.x];
     const int64_t p0 = pt_off[s];
     const int64_t n = pt_off[s + 1] - p0;
     const SysConst<T> C = sysc[s];
-    if constexpr (sizeof(T) == 4) tab_load(tabs + s * TAB_N, tab, tid, 256);
+    if constexpr (sizeof(T) == 4) tab_load(tabs + s, tab, tid, 256);
+    // FP32 accumulates in FP64 (pair_accumulate_x); FP64 in FP64
     T xi[TPL], yi[TPL], ax[TPL], ay[TPL];
+    double axd[TPL], ayd[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         const int64_t i = first + tid + 256 * k;
@@ -309,8 +371,11 @@ __global__ __launch_bounds__(256) void k_pair_velocity(const int64_t* blk_sys, c
         yi[k] = i < n ? y[p0 + i] : (T)0;
         ax[k] = (T)0;
         ay[k] = (T)0;
+        axd[k] = ayd[k] = 0.0;
     }
-    T sfx = (T)0, sfy = (T)0;
+    // sum of the forces in FP64: it multiplies H1(0) in every target's
+    // velocity, and the forces of a filament cancel to a small total
+    double sfx = 0.0, sfy = 0.0;
     for (int64_t j0 = 0; j0 < n; j0 += 256) {
         const int64_t j = j0 + tid;
         Src4<T> v;
@@ -328,7 +393,10 @@ __global__ __launch_bounds__(256) void k_pair_velocity(const int64_t* blk_sys, c
         tile[tid] = v;
         __syncthreads();
         const int m = (int)((n - j0) < 256 ? (n - j0) : 256);
-        pair_accumulate<T, TPL>(C, tab, tile, m, xi, yi, ax, ay);
+        if constexpr (sizeof(T) == 4)
+            pair_accumulate_x<TPL>(C, tab, tile, m, xi, yi, axd, ayd);
+        else
+            pair_accumulate<T, TPL>(C, tab, tile, m, xi, yi, ax, ay);
     }
     sfx = wave_sum(sfx);
     sfy = wave_sum(sfy);
@@ -337,14 +405,19 @@ __global__ __launch_bounds__(256) void k_pair_velocity(const int64_t* blk_sys, c
         red[1][tid >> 6] = sfy;
     }
     __syncthreads();
-    const T SFx = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    const T SFy = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const double SFxd = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const double SFyd = red[1][0] + red[1][1] + red[1][2] + red[1][3];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         const int64_t i = first + tid + 256 * k;
         if (i < n) {
-            ux[p0 + i] = fma_t(C.h1c, SFx, ax[k]);
-            uy[p0 + i] = fma_t(C.h1c, SFy, ay[k]);
+            if constexpr (sizeof(T) == 4) {
+                ux[p0 + i] = (T)fma((double)C.h1c, SFxd, axd[k]);
+                uy[p0 + i] = (T)fma((double)C.h1c, SFyd, ayd[k]);
+            } else {
+                ux[p0 + i] = fma_t(C.h1c, (T)SFxd, ax[k]);
+                uy[p0 + i] = fma_t(C.h1c, (T)SFyd, ay[k]);
+            }
         }
     }
 }
@@ -381,7 +454,7 @@ __global__ void k_forces(int64_t n_fil, const int64_t* fil_off, const int32_t* n
 // velocities are reduced through LDS in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
 template <typename T> struct FwdLds {
-    TabE* tab;     // [TAB_N] FP32 kernel table (FP32 runs)
+    TabSys* tab;   // FP32 kernel table (FP32 runs)
     Src4<T>* src;  // [NMAX] positions (hi) and forces
     T* lox;        // [NMAX] lo parts
     T* loy;
@@ -413,7 +486,7 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
     }
     const SysConst<T> C = ((const SysConst<T>*)b.sysc)[s];
     const double dsd = 1.0 / (double)(N - 1);
-    if constexpr (COMP) tab_load((const TabE*)b.tab + (int64_t)s * TAB_N, L.tab, tid, NT);
+    if constexpr (COMP) tab_load((const TabSys*)b.tab + s, L.tab, tid, NT);
 
     // owned points i = tid + NT*q: positions as (hi, lo)
     T xh[OWN], yh[OWN], xl[OWN], yl[OWN];
@@ -449,6 +522,8 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
     for (int step = 0; step < r.steps; ++step) {
         const T t = (T)((double)step * r.dt);
         // forces of the owned points (reads positions only)
+        // force sums: one point per thread, then a 64-lane tree and the
+        // WPS wave sums (short sums, FP32 is enough here)
         T sfx = (T)0, sfy = (T)0;
 #pragma unroll
         for (int q = 0; q < OWN; ++q) {
@@ -595,9 +670,9 @@ __global__ __launch_bounds__(64 * WPS) void k_forward(Batch b, Run r, const int3
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NMAX = 64 * TPL;
     __shared__ int s_item;
-    constexpr size_t TABB = sizeof(T) == 4 ? TAB_N * sizeof(TabE) : 0;
+    constexpr size_t TABB = sizeof(T) == 4 ? sizeof(TabSys) : 0;
     FwdLds<T> L;
-    L.tab = reinterpret_cast<TabE*>(smem);
+    L.tab = reinterpret_cast<TabSys*>(smem);
     L.src = reinterpret_cast<Src4<T>*>(smem + TABB);
     L.lox = reinterpret_cast<T*>(smem + TABB + NMAX * sizeof(Src4<T>));
     L.loy = L.lox + NMAX;
@@ -662,15 +737,15 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
                                                   int32_t* steps_done)
 {
     constexpr bool COMP = sizeof(T) == 4;
-    constexpr size_t TABB = COMP ? TAB_N * sizeof(TabE) : 0;
+    constexpr size_t TABB = COMP ? sizeof(TabSys) : 0;
     extern __shared__ __align__(16) unsigned char smem[];
-    TabE* tab = reinterpret_cast<TabE*>(smem);
+    TabSys* tab = reinterpret_cast<TabSys*>(smem);
     Src4<T>* src = reinterpret_cast<Src4<T>*>(smem + TABB);
-    __shared__ T red[2][4];
+    __shared__ double red[2][4];
     const int tid = threadIdx.x;
     const int64_t s = blk_sys[blockIdx.x];
     if (status[s] != 0) return;
-    if constexpr (COMP) tab_load((const TabE*)b.tab + s * TAB_N, tab, tid, 256);
+    if constexpr (COMP) tab_load((const TabSys*)b.tab + s, tab, tid, 256);
     const int64_t first = blk_first[blockIdx.x];
     const int64_t p0 = b.pt_off[s];
     const int N = b.npt[s];
@@ -682,7 +757,7 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
     const T* xl = (const T*)S.xl[cur] + p0;
     const T* yl = (const T*)S.yl[cur] + p0;
     const T t = (T)((double)step * r.dt);
-    T sfx = (T)0, sfy = (T)0;
+    double sfx = 0.0, sfy = 0.0;   // FP64: multiplies H1(0) in every velocity
     for (int i = tid; i < n; i += 256) {
         const int m = i / N, p = i - m * N;
         const FilP<T> q = load_filp<T>(b.params, f0 + m, N);
@@ -710,26 +785,39 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
         red[1][tid >> 6] = sfy;
     }
     __syncthreads();
-    const T SFx = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    const T SFy = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const double SFxd = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const double SFyd = red[1][0] + red[1][1] + red[1][2] + red[1][3];
     const SysConst<T> C = ((const SysConst<T>*)b.sysc)[s];
+    // FP32 sums whole large systems per lane: FP64 accumulation
+    // (pair_accumulate_x); FP64 runs accumulate in FP64 anyway
     T xi[TPL], yi[TPL], ax[TPL], ay[TPL];
+    double axd[TPL], ayd[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         const int64_t i = first + tid + 256 * k;
         xi[k] = i < n ? src[i].x : (T)0;
         yi[k] = i < n ? src[i].y : (T)0;
         ax[k] = ay[k] = (T)0;
+        axd[k] = ayd[k] = 0.0;
     }
-    pair_accumulate<T, TPL>(C, tab, src, n, xi, yi, ax, ay);
+    if constexpr (COMP)
+        pair_accumulate_x<TPL>(C, tab, src, n, xi, yi, axd, ayd);
+    else
+        pair_accumulate<T, TPL>(C, tab, src, n, xi, yi, ax, ay);
     const T dt = (T)r.dt;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         const int64_t i = first + tid + 256 * k;
         if (i >= n) continue;
         T hx = xi[k], hy = yi[k], lx = xl[i], ly = yl[i];
-        const T ux = fma_t(C.h1c, SFx, ax[k]);
-        const T uy = fma_t(C.h1c, SFy, ay[k]);
+        T ux, uy;
+        if constexpr (COMP) {
+            ux = (T)fma((double)C.h1c, SFxd, axd[k]);
+            uy = (T)fma((double)C.h1c, SFyd, ayd[k]);
+        } else {
+            ux = fma_t(C.h1c, (T)SFxd, ax[k]);
+            uy = fma_t(C.h1c, (T)SFyd, ay[k]);
+        }
         if (COMP) {
             acc2(hx, lx, dt * ux);
             acc2(hy, ly, dt * uy);
@@ -908,13 +996,13 @@ hipError_t launch_sysconst(int dtype, int64_t n_sys, const double* alpha, const 
     return hipGetLastError();
 }
 
-size_t table_bytes() { return (size_t)TAB_N * sizeof(TabE); }
+size_t table_bytes() { return sizeof(TabSys); }
 
 hipError_t launch_table_build(int64_t s0, int64_t n, const void* sysc64, void* tab, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_table_build, dim3((unsigned)nblk(n * TAB_N, 64)), dim3(64), 0, st, s0, n,
-                       (const SysConst<double>*)sysc64, (TabE*)tab);
+                       (const SysConst<double>*)sysc64, (TabSys*)tab);
     return hipGetLastError();
 }
 
@@ -931,7 +1019,7 @@ static void pair_launch(int64_t nb, const int64_t* bs, const int64_t* bf, const 
                         void* uy, hipStream_t st)
 {
     hipLaunchKernelGGL((k_pair_velocity<T, TPL>), dim3((unsigned)nb), dim3(256), 0, st, bs, bf, off,
-                       (const SysConst<T>*)sysc, (const TabE*)tab, (const T*)x, (const T*)y, (const T*)fx,
+                       (const SysConst<T>*)sysc, (const TabSys*)tab, (const T*)x, (const T*)y, (const T*)fx,
                        (const T*)fy, (T*)ux, (T*)uy);
 }
 

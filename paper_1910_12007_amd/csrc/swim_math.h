@@ -404,6 +404,12 @@ struct alignas(16) TabE {
     float h[4];  // Ht(u) = h0 + u (h1 + u (h2 + u h3))
     float g[4];  // H2(u)
 };
+// one system's table; h0lo[i] = Ht at the start of interval i minus its
+// FP32 value e[i].h[0], for the kernels that accumulate in FP64
+struct alignas(16) TabSys {
+    TabE e[TAB_N];
+    float h0lo[TAB_N];
+};
 
 // cubic through (0, f0), (1/4, f1), (3/4, f2), (1, f3), monomial coefficients
 SWIM_HD void cubic_lobatto(const double (&f)[4], float (&c)[4])
@@ -424,7 +430,8 @@ SWIM_HD void cubic_lobatto(const double (&f)[4], float (&c)[4])
 }
 
 // interval i of the table of the system with FP64 constants C and eps^2 = e2
-SWIM_HD void tab_interval(const SysConst<double>& C, double e2, int i, TabE& out)
+// (h0lo, if not null: the FP32 remainder of the constant coefficient of Ht)
+SWIM_HD void tab_interval(const SysConst<double>& C, double e2, int i, TabE& out, float* h0lo = nullptr)
 {
     const int e = i >> TAB_M, j = i & ((1 << TAB_M) - 1);
     const double a = ldexp(1.0, e);
@@ -440,6 +447,7 @@ SWIM_HD void tab_interval(const SysConst<double>& C, double e2, int i, TabE& out
     }
     cubic_lobatto(fh, out.h);
     cubic_lobatto(fg, out.g);
+    if (h0lo) *h0lo = (float)(fh[0] - (double)out.h[0]);
 }
 
 // table index and local coordinate of t (index >= TAB_N: outside the table,

@@ -221,6 +221,38 @@ def test_multi_swimmer_systems_match_oracle(ctx, oracle_core, dtype, tol):
         check_traj(obs[3 + m], r2["obs"][m], np.array([P2[m, 7] + 1.0, P2[m, 8]]), tol, dtype, steps, 3.0)
 
 
+def test_dense_sample_velocity_at_full_size(ctx, oracle_core):
+    """One velocity evaluation of the large-N dense workload at its full size:
+    sample 0 (8 swimmers x 512 points on the 2 x 4 grid, alpha from seed 3)
+    at its initial configuration, forces of the oracle at t = 0, all 4096
+    velocities against the FP64 oracle in FP32 and FP64."""
+    lay = inputs.dense_layout(n_samples=1, seed=3)[0]
+    s = np.arange(512) / 511.0
+    X = np.concatenate([lay[m, 7] + s for m in range(8)])
+    Y = np.concatenate([np.full(512, lay[m, 8]) for m in range(8)])
+    F = [oracle_core.forces(X[512 * m:512 * (m + 1)], Y[512 * m:512 * (m + 1)], lay[m, 1], lay[m, 2],
+                            oracle_core.kappa0(512, lay[m, 3], lay[m, 5], lay[m, 4], lay[m, 6], 0.0))
+         for m in range(8)]
+    FX = np.concatenate([f[0] for f in F])
+    FY = np.concatenate([f[1] for f in F])
+    eps = 1.5 / 511
+    for dtype, tol in ((swim.SWIM_F32, 1e-5), (swim.SWIM_F64, 1e-12)):
+        # both sides take the same inputs: the FP32 run's positions and
+        # forces rounded to FP32 (at |x| ~ 5 that rounding alone moves
+        # neighbouring points by 1e-4 of their spacing)
+        Xd, Yd, FXd, FYd = (a.astype(NP[dtype]).astype(np.float64) for a in (X, Y, FX, FY))
+        ox, oy = oracle_core.velocity(Xd, Yd, FXd, FYd, lay[0, 0], eps)
+        td = DT[dtype]
+        ux = torch.empty(4096, dtype=td, device="cuda")
+        uy = torch.empty_like(ux)
+        swim.swim_pair_velocity(ctx, np.array([0, 4096]), [lay[0, 0]], [eps], dev(Xd, td), dev(Yd, td),
+                                dev(FXd, td), dev(FYd, td), ux, uy)
+        torch.cuda.synchronize()
+        g = np.concatenate([ux.cpu().double().numpy(), uy.cpu().double().numpy()])
+        ref = np.concatenate([ox, oy])
+        assert rel(g, ref) < tol, (dtype, rel(g, ref))
+
+
 def test_blowup_and_bad_parameters_are_statuses(ctx):
     P = inputs.param_rows(3, alpha=2.0)
     P[0, 1], P[0, 2] = 1.0, 1e4      # beyond the explicit-Euler bound at N = 128
