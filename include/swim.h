@@ -71,23 +71,37 @@ extern "C" {
 
 typedef struct swim_ctx swim_ctx;
 
-/* Creates a context on HIP device `device` with its own stream.  *out is set
- * to NULL on failure. */
+/* Creates a context on HIP device `device` with its own stream (a blocking
+ * stream at the default priority: it is ordered with work on the legacy NULL
+ * stream, so host-side preparation of buffers on that stream needs no extra
+ * synchronization).  *out is set to NULL on failure. */
 int swim_create(swim_ctx **out, int device);
 void swim_destroy(swim_ctx *ctx);
 const char *swim_last_error(void);
 int swim_version(void);
 
-/* Launch-shape options of a context (the autotuner sets them):
+/* Launch options of a context (the autotuner sets the first two):
  *   SWIM_OPT_WPS     wavefronts that share one system in the persistent
  *                    kernel, splitting its sources: 0 (automatic), 1, 2, 4,
  *                    8, 16 (reduced when the partial sums would not fit LDS);
  *   SWIM_OPT_BIG_TPL targets per lane of the large-system kernel:
- *                    0 (automatic), 1, 2, 4.
+ *                    0 (automatic), 1, 2, 4;
+ *   SWIM_OPT_GRAPH   forward runs as a captured hipGraph: 0 never (eager
+ *                    launches), 1 (default) capture when a call repeats the
+ *                    previous call's layout (systems, sizes, run length,
+ *                    options and every buffer address) and replay it while
+ *                    that layout recurs, 2 capture every new layout at once.
+ *                    Parameter values may change between replays: they are
+ *                    uploaded before the graph runs.
+ * Read-only counters (swim_get_option): SWIM_OPT_GRAPH_LAUNCHES (graph
+ * replays and first launches so far), SWIM_OPT_GRAPH_CAPTURES.
  * Results do not depend on the options beyond rounding of the source-split
  * partial sums.  SWIM_EINVAL for an unknown key or value. */
 #define SWIM_OPT_WPS 1
 #define SWIM_OPT_BIG_TPL 2
+#define SWIM_OPT_GRAPH 3
+#define SWIM_OPT_GRAPH_LAUNCHES 4
+#define SWIM_OPT_GRAPH_CAPTURES 5
 int swim_set_option(swim_ctx *ctx, int32_t key, int32_t value);
 int swim_get_option(swim_ctx *ctx, int32_t key, int32_t *value);
 
@@ -204,7 +218,7 @@ typedef struct {
 int abc_step(swim_ctx *ctx, const abc_model *model, const double *data, int32_t n_obs, int64_t n,
              const int32_t *N, uint64_t seed, int32_t generation, const double *prev_theta,
              const double *prev_w, int64_t n_prev, double q, double *theta_out, double *dist_out,
-             uint8_t *accept_out, double *w_out, double *tol_out);
+             uint8_t *accept_out, double *w_out, double *tol_out, int32_t *steps_out);
 
 /* ---------------------------------------------------------------------------
  * Surrogate of the forward model (not in the paper; prescreens ABC

@@ -61,7 +61,7 @@ enum BufId {
     B_OFF, B_SWOFF, B_NPT, B_NSW, B_ORDER, B_LIST, B_BLKS, B_BLKF, B_ALPHA, B_EPS, B_SYSC, B_QUEUE,
     B_PARAMS, B_DATA, B_OBS, B_SPEED, B_STATUS, B_DIST, B_TOL, B_ACC, B_BIG,
     B_MLP_ACT, B_MLP_GRAD, B_MLP_BATCH, B_MLP_IDX, B_MLP_CNT,
-    B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_TAB, B_NBUF
+    B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_TAB, B_DONE, B_NBUF
 };
 
 // surrogate network: 5 -> 256 x 4 -> 33
@@ -78,12 +78,26 @@ constexpr int64_t MLP_NPARAM = 207393;
 
 }  // namespace
 
+// a captured forward-run launch sequence, replayed while its layout and
+// buffers are unchanged
+struct FwdGraph {
+    uint64_t key = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+constexpr int N_GRAPHS = 4;
+
 struct swim_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int num_cu = 0;
     int opt_wps = 0;      // waves per system in the persistent kernel (0: automatic)
     int opt_big_tpl = 0;  // targets per lane of the large-system kernel (0: automatic)
+    int opt_graph = 1;    // 0: eager launches; 1: capture on a repeated layout; 2: capture always
+    FwdGraph graphs[N_GRAPHS];
+    uint64_t graph_clock = 0, last_key = 0;
+    int64_t graph_launches = 0, graph_captures = 0;
     DevBuf buf[B_NBUF];
     void* pinned = nullptr;
     size_t pinned_cap = 0, pin_off = 0;
@@ -158,6 +172,20 @@ int check_ctx(swim_ctx* c)
 }
 
 int check_dtype(int32_t d) { return (d == SWIM_F32 || d == SWIM_F64) ? SWIM_OK : fail(SWIM_EINVAL, "dtype must be SWIM_F32 or SWIM_F64"); }
+
+// FNV-1a over the bytes that describe a launch layout
+struct Fnv {
+    uint64_t v = 1469598103934665603ull;
+    void add_bytes(const void* p, size_t n)
+    {
+        const unsigned char* b = (const unsigned char*)p;
+        for (size_t i = 0; i < n; ++i) {
+            v ^= b[i];
+            v *= 1099511628211ull;
+        }
+    }
+    template <typename V> void add(const V& x) { add_bytes(&x, sizeof(x)); }
+};
 
 constexpr int TPL_CHOICES[] = {1, 2, 3, 4, 6, 8};
 int choose_tpl(int pts)
@@ -310,8 +338,7 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     void *sysc, *sysc64;
     TRY(sysconst_buffers(c, dtype, n_sys, &sysc, &sysc64));
     TRY(ensure(c, B_QUEUE, 8 * 4));
-    HIPCHK(launch_sysconst_batch(dtype, n_sys, (const int64_t*)c->buf[B_SWOFF].p, (const int32_t*)c->buf[B_NPT].p,
-                                 params_dev, run.eps_over_ds, sysc, sysc64, status, st));
+    if (dtype == SWIM_F32) TRY(ensure(c, B_TAB, (size_t)n_sys * table_bytes()));
     Batch b;
     b.n_sys = n_sys;
     b.pt_off = (const int64_t*)c->buf[B_OFF].p;
@@ -321,32 +348,32 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     b.params = params_dev;
     b.sysc = sysc;
     b.sysc64 = sysc64;
-    b.tab = nullptr;
-    if (dtype == SWIM_F32) {
-        TRY(ensure(c, B_TAB, (size_t)n_sys * table_bytes()));
-        HIPCHK(launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, st));
-        b.tab = c->buf[B_TAB].p;
-    }
-    HIPCHK(launch_fill_i32((int32_t*)c->buf[B_QUEUE].p, 0, 8, st));
+    b.tab = dtype == SWIM_F32 ? c->buf[B_TAB].p : nullptr;
+    // launch shapes of the persistent buckets (and their LDS limits, set
+    // here: nothing inside a stream capture may change them)
+    struct Bucket {
+        int tpl, wps, nblocks;
+        int64_t start, count;
+    };
+    std::vector<Bucket> bk;
     for (size_t k = 0; k < bucket_span.size(); ++k) {
-        const int tpl = bucket_span[k].first;
-        const int64_t start = bucket_span[k].second;
-        const int64_t count = (k + 1 < bucket_span.size() ? bucket_span[k + 1].second : (int64_t)order.size()) - start;
-        int wps = c->opt_wps ? c->opt_wps : 16;
+        Bucket q;
+        q.tpl = bucket_span[k].first;
+        q.start = bucket_span[k].second;
+        q.count = (k + 1 < bucket_span.size() ? bucket_span[k + 1].second : (int64_t)order.size()) - q.start;
+        q.wps = c->opt_wps ? c->opt_wps : 16;
         // the wave partial sums of one system must fit the LDS
-        while (wps > 1 && forward_lds_bytes(dtype, tpl, wps) > 160 * 1024) wps /= 2;
-        const int per_cu = forward_blocks_per_cu(dtype, tpl, wps);
-        const int nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(count, (int64_t)per_cu * c->num_cu));
-        Batch bk = b;
-        bk.n_sys = count;
-        HIPCHK(launch_forward(dtype, tpl, wps, nblocks, bk, run, (const int32_t*)c->buf[B_ORDER].p + start,
-                              (int32_t*)c->buf[B_QUEUE].p + k, obs, speed, status, steps_done, st));
+        while (q.wps > 1 && forward_lds_bytes(dtype, q.tpl, q.wps) > 160 * 1024) q.wps /= 2;
+        const int per_cu = forward_blocks_per_cu(dtype, q.tpl, q.wps);
+        q.nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(q.count, (int64_t)per_cu * c->num_cu));
+        HIPCHK(prepare_forward(dtype, q.tpl, q.wps));
+        bk.push_back(q);
     }
+    BigState S{};
     if (!big_list.empty()) {
         const size_t one = (size_t)big_pts * es;
         TRY(ensure(c, B_BIG, 8 * one + sw_off[n_sys] * 2 * es + 256));
         char* base = (char*)c->buf[B_BIG].p;
-        BigState S;
         for (int q = 0; q < 2; ++q) {
             S.xh[q] = base + (0 + q) * one;
             S.yh[q] = base + (2 + q) * one;
@@ -356,15 +383,106 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
         S.head0 = base + 8 * one;
         if (big_step_lds_bytes(dtype, max_big) > 160 * 1024)
             return fail(SWIM_EINVAL, "system of %d points exceeds the LDS capacity", max_big);
-        HIPCHK(launch_big_init(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S, status, obs,
-                               run.n_obs, st));
-        for (int step = 0; step < run.steps; ++step)
-            HIPCHK(launch_big_step(dtype, tpl_big, (int64_t)blk_s.size(), (const int64_t*)c->buf[B_BLKS].p,
-                                   (const int64_t*)c->buf[B_BLKF].p, max_big, b, S, step, run, obs, status,
-                                   steps_done, st));
-        HIPCHK(launch_big_finish(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S,
-                                 run.steps & 1, run, speed, status, steps_done, st));
+        HIPCHK(prepare_big_step(dtype, tpl_big, max_big));
     }
+    // the launch sequence of the run (uploads above are not part of it)
+    auto launch_all = [&]() -> hipError_t {
+        hipError_t e = launch_sysconst_batch(dtype, n_sys, (const int64_t*)c->buf[B_SWOFF].p,
+                                             (const int32_t*)c->buf[B_NPT].p, params_dev, run.eps_over_ds, sysc,
+                                             sysc64, status, st);
+        if (e == hipSuccess && dtype == SWIM_F32) e = launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, st);
+        if (e == hipSuccess) e = launch_fill_i32((int32_t*)c->buf[B_QUEUE].p, 0, 8, st);
+        for (size_t k = 0; k < bk.size() && e == hipSuccess; ++k) {
+            Batch bb = b;
+            bb.n_sys = bk[k].count;
+            e = launch_forward(dtype, bk[k].tpl, bk[k].wps, bk[k].nblocks, bb, run,
+                               (const int32_t*)c->buf[B_ORDER].p + bk[k].start, (int32_t*)c->buf[B_QUEUE].p + k, obs,
+                               speed, status, steps_done, st);
+        }
+        if (!big_list.empty() && e == hipSuccess) {
+            e = launch_big_init(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S, status, obs,
+                                run.n_obs, st);
+            for (int step = 0; step < run.steps && e == hipSuccess; ++step)
+                e = launch_big_step(dtype, tpl_big, (int64_t)blk_s.size(), (const int64_t*)c->buf[B_BLKS].p,
+                                    (const int64_t*)c->buf[B_BLKF].p, max_big, b, S, step, run, obs, status,
+                                    steps_done, st);
+            if (e == hipSuccess)
+                e = launch_big_finish(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S,
+                                      run.steps & 1, run, speed, status, steps_done, st);
+        }
+        return e;
+    };
+    if (c->opt_graph == 0) {
+        HIPCHK(launch_all());
+        return SWIM_OK;
+    }
+    // key of the layout: everything the launch sequence bakes in
+    Fnv h;
+    h.add(dtype);
+    h.add(n_sys);
+    h.add_bytes(N, (size_t)n_sys * 4);
+    h.add_bytes(nsw.data(), nsw.size() * 4);
+    h.add(run.steps);
+    h.add(run.dt);
+    h.add(run.obs_every);
+    h.add(run.n_obs);
+    h.add(run.eps_over_ds);
+    h.add(tpl_big);
+    for (const Bucket& q : bk) {
+        h.add(q.tpl);
+        h.add(q.wps);
+        h.add(q.nblocks);
+    }
+    const void* ptrs[] = {params_dev, obs, speed, status, steps_done, sysc, sysc64, b.tab, c->buf[B_SWOFF].p,
+                          c->buf[B_OFF].p, c->buf[B_NPT].p, c->buf[B_NSW].p, c->buf[B_ORDER].p, c->buf[B_LIST].p,
+                          c->buf[B_BLKS].p, c->buf[B_BLKF].p, c->buf[B_QUEUE].p, c->buf[B_BIG].p, st};
+    h.add_bytes(ptrs, sizeof(ptrs));
+    const uint64_t key = h.v;
+    ++c->graph_clock;
+    for (auto& g : c->graphs)
+        if (g.exec && g.key == key) {
+            g.last_use = c->graph_clock;
+            HIPCHK(hipGraphLaunch(g.exec, st));
+            ++c->graph_launches;
+            return SWIM_OK;
+        }
+    if (c->opt_graph == 1 && key != c->last_key) {
+        // first sight of this layout: run eagerly, capture if it recurs
+        c->last_key = key;
+        HIPCHK(launch_all());
+        return SWIM_OK;
+    }
+    // capture into the least recently used slot
+    FwdGraph* slot = &c->graphs[0];
+    for (auto& g : c->graphs)
+        if (!g.exec || g.last_use < slot->last_use) slot = &g;
+    if (slot->exec) HIPCHK(hipGraphExecDestroy(slot->exec));
+    if (slot->graph) HIPCHK(hipGraphDestroy(slot->graph));
+    slot->exec = nullptr;
+    slot->graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const hipError_t le = launch_all();
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return fail(SWIM_EHIP, "capture of the forward run failed: %s", hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return fail(SWIM_EHIP, "instantiation of the forward-run graph failed");
+    }
+    slot->graph = graph;
+    slot->exec = exec;
+    slot->key = key;
+    slot->last_use = c->graph_clock;
+    c->last_key = key;
+    ++c->graph_captures;
+    HIPCHK(hipGraphLaunch(exec, st));
+    ++c->graph_launches;
     return SWIM_OK;
 }
 
@@ -490,7 +608,7 @@ int swim_create(swim_ctx** out, int device)
     swim_ctx* c = new swim_ctx();
     c->device = device;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess || hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess || hipStreamCreateWithFlags(&c->stream, hipStreamDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->up_ev, hipEventDisableTiming) != hipSuccess) {
         delete c;
         return fail(SWIM_EHIP, "context creation failed");
@@ -507,6 +625,10 @@ void swim_destroy(swim_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto& b : c->buf)
         if (b.p) (void)hipFree(b.p);
+    for (auto& g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->up_ev) (void)hipEventDestroy(c->up_ev);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -523,6 +645,9 @@ int swim_set_option(swim_ctx* c, int32_t key, int32_t value)
     } else if (key == SWIM_OPT_BIG_TPL) {
         if (value != 0 && value != 1 && value != 2 && value != 4) return fail(SWIM_EINVAL, "targets per lane must be 0, 1, 2 or 4");
         c->opt_big_tpl = value;
+    } else if (key == SWIM_OPT_GRAPH) {
+        if (value < 0 || value > 2) return fail(SWIM_EINVAL, "graph mode must be 0, 1 or 2");
+        c->opt_graph = value;
     } else {
         return fail(SWIM_EINVAL, "unknown option %d", key);
     }
@@ -534,6 +659,9 @@ int swim_get_option(swim_ctx* c, int32_t key, int32_t* value)
     if (!c || !value) return fail(SWIM_EINVAL, "null argument");
     if (key == SWIM_OPT_WPS) *value = c->opt_wps;
     else if (key == SWIM_OPT_BIG_TPL) *value = c->opt_big_tpl;
+    else if (key == SWIM_OPT_GRAPH) *value = c->opt_graph;
+    else if (key == SWIM_OPT_GRAPH_LAUNCHES) *value = (int32_t)c->graph_launches;
+    else if (key == SWIM_OPT_GRAPH_CAPTURES) *value = (int32_t)c->graph_captures;
     else return fail(SWIM_EINVAL, "unknown option %d", key);
     return SWIM_OK;
 }
@@ -779,7 +907,8 @@ int abc_pmc_weights(int64_t n, const double* theta, const uint8_t* accept, const
 
 int abc_step(swim_ctx* c, const abc_model* m, const double* data, int32_t n_obs, int64_t n, const int32_t* N,
              uint64_t seed, int32_t generation, const double* prev_theta, const double* prev_w, int64_t n_prev, double q,
-             double* theta_out, double* dist_out, uint8_t* accept_out, double* w_out, double* tol_out)
+             double* theta_out, double* dist_out, uint8_t* accept_out, double* w_out, double* tol_out,
+             int32_t* steps_out)
 {
     TRY(check_ctx(c));
     if (!m || !data || !N || !theta_out || !dist_out || !accept_out || !w_out || !tol_out) return fail(SWIM_EINVAL, "null argument");
@@ -825,8 +954,10 @@ int abc_step(swim_ctx* c, const abc_model* m, const double* data, int32_t n_obs,
     r.obs_every = m->obs_every;
     r.n_obs = n_obs;
     r.eps_over_ds = m->eps_over_ds;
+    if (steps_out) TRY(ensure(c, B_DONE, (size_t)n * 4));
+    int32_t* done_dev = steps_out ? (int32_t*)c->buf[B_DONE].p : nullptr;
     TRY(forward_impl(c, m->dtype, n, N, nullptr, (const double*)c->buf[B_PARAMS].p, r, c->buf[B_OBS].p,
-                     c->buf[B_SPEED].p, (int32_t*)c->buf[B_STATUS].p, nullptr, st));
+                     c->buf[B_SPEED].p, (int32_t*)c->buf[B_STATUS].p, done_dev, st));
     HIPCHK(launch_abc_distance(m->dtype, n, n_obs, c->buf[B_OBS].p, (const double*)c->buf[B_DATA].p,
                                (const int32_t*)c->buf[B_STATUS].p, (double*)c->buf[B_DIST].p, st));
     HIPCHK(launch_select_kth(n, (const double*)c->buf[B_DIST].p, q, (double*)c->buf[B_TOL].p, st));
@@ -834,6 +965,7 @@ int abc_step(swim_ctx* c, const abc_model* m, const double* data, int32_t n_obs,
     HIPCHK(hipMemcpyAsync(dist_out, c->buf[B_DIST].p, (size_t)n * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(accept_out, c->buf[B_ACC].p, (size_t)n, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(tol_out, c->buf[B_TOL].p, 8, hipMemcpyDeviceToHost, st));
+    if (steps_out) HIPCHK(hipMemcpyAsync(steps_out, done_dev, (size_t)n * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (generation == 0) {
         int64_t na = 0;

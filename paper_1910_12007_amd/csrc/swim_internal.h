@@ -56,6 +56,10 @@ hipError_t launch_forward(int dtype, int tpl, int wps, int n_blocks, const Batch
                           const Run& r, const int32_t* order, int32_t* queue, void* obs,
                           void* speed, int32_t* status, int32_t* steps_done, hipStream_t st);
 size_t forward_lds_bytes(int dtype, int tpl, int wps);
+// set the kernels' dynamic-LDS limits ahead of launches (needed before a
+// stream capture, in which the launch itself must not change attributes)
+hipError_t prepare_forward(int dtype, int tpl, int wps);
+hipError_t prepare_big_step(int dtype, int tpl, int32_t max_pts);
 int forward_blocks_per_cu(int dtype, int tpl, int wps);
 // one forward-Euler step of large systems, targets split over workgroups
 struct BigState {

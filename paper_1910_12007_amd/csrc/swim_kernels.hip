@@ -1062,19 +1062,29 @@ size_t forward_lds_bytes(int dtype, int tpl, int wps)
            (wps > 1 ? (size_t)wps * 2 * nmax * e : 0);
 }
 
+// raise the kernel's dynamic-LDS limit to what its launches need (outside
+// any stream capture: a launch inside a capture finds it already set)
 template <typename T, int TPL, int WPS>
-static hipError_t fwd_launch(int nblocks, const Batch& b, const Run& r, const int32_t* order, int32_t* q, void* obs,
-                             void* speed, int32_t* status, int32_t* done, hipStream_t st)
+static hipError_t fwd_prepare()
 {
     const size_t lds = forward_lds_bytes(sizeof(T) == 4 ? 0 : 1, TPL, WPS);
     static size_t attr_lds = 0;
     if (lds > attr_lds) {
-        // raise the dynamic-LDS limit to exactly what this launch needs
         hipError_t e = hipFuncSetAttribute((const void*)k_forward<T, TPL, WPS>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_lds = lds;
     }
+    return hipSuccess;
+}
+
+template <typename T, int TPL, int WPS>
+static hipError_t fwd_launch(int nblocks, const Batch& b, const Run& r, const int32_t* order, int32_t* q, void* obs,
+                             void* speed, int32_t* status, int32_t* done, hipStream_t st)
+{
+    const size_t lds = forward_lds_bytes(sizeof(T) == 4 ? 0 : 1, TPL, WPS);
+    hipError_t e = fwd_prepare<T, TPL, WPS>();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_forward<T, TPL, WPS>), dim3(nblocks), dim3(64 * WPS), lds, st, b, r, order, q, (T*)obs,
                        (T*)speed, status, done);
     return hipGetLastError();
@@ -1111,6 +1121,19 @@ hipError_t launch_forward(int dtype, int tpl, int wps, int nblocks, const Batch&
     return hipErrorInvalidValue;
 }
 
+hipError_t prepare_forward(int dtype, int tpl, int wps)
+{
+#define PREP_CASE(T, P, W) \
+    if (tpl == P && wps == W) return fwd_prepare<T, P, W>();
+    if (dtype == 0) {
+        SWIM_FWD_TABLE(PREP_CASE, float)
+    } else {
+        SWIM_FWD_TABLE(PREP_CASE, double)
+    }
+#undef PREP_CASE
+    return hipErrorInvalidValue;
+}
+
 int forward_blocks_per_cu(int dtype, int tpl, int wps)
 {
 #define OCC_CASE(T, P, W) \
@@ -1142,9 +1165,7 @@ size_t big_step_lds_bytes(int dtype, int32_t max_pts)
 }
 
 template <typename T, int TPL>
-static hipError_t big_launch(int64_t nb, const int64_t* bs, const int64_t* bf, int32_t max_pts, const Batch& b,
-                             const BigState& s, int step, const Run& r, void* obs, int32_t* status, int32_t* done,
-                             hipStream_t st)
+static hipError_t big_prepare(int32_t max_pts)
 {
     const size_t lds = big_step_lds_bytes(sizeof(T) == 4 ? 0 : 1, max_pts);
     static size_t attr_lds = 0;
@@ -1154,6 +1175,35 @@ static hipError_t big_launch(int64_t nb, const int64_t* bs, const int64_t* bf, i
         if (e != hipSuccess) return e;
         attr_lds = lds;
     }
+    return hipSuccess;
+}
+
+hipError_t prepare_big_step(int dtype, int tpl, int32_t max_pts)
+{
+    if (dtype == 0) {
+        switch (tpl) {
+            case 1: return big_prepare<float, 1>(max_pts);
+            case 2: return big_prepare<float, 2>(max_pts);
+            case 4: return big_prepare<float, 4>(max_pts);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (tpl) {
+        case 1: return big_prepare<double, 1>(max_pts);
+        case 2: return big_prepare<double, 2>(max_pts);
+        case 4: return big_prepare<double, 4>(max_pts);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int TPL>
+static hipError_t big_launch(int64_t nb, const int64_t* bs, const int64_t* bf, int32_t max_pts, const Batch& b,
+                             const BigState& s, int step, const Run& r, void* obs, int32_t* status, int32_t* done,
+                             hipStream_t st)
+{
+    const size_t lds = big_step_lds_bytes(sizeof(T) == 4 ? 0 : 1, max_pts);
+    hipError_t e = big_prepare<T, TPL>(max_pts);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_big_step<T, TPL>), dim3((unsigned)nb), dim3(256), lds, st, bs, bf, b, s, step, r, (T*)obs,
                        status, done);
     return hipGetLastError();

@@ -17,7 +17,7 @@ SWIM_OK, SWIM_EINVAL, SWIM_EHIP, SWIM_ENOMEM, SWIM_ESTATE = 0, -1, -2, -3, -4
 SWIM_F32, SWIM_F64 = 0, 1
 SWIM_ST_OK, SWIM_ST_NONFINITE, SWIM_ST_BOUND, SWIM_ST_BADPARAM = 0, 1, 2, 3
 SWIM_NPARAM = 9
-SWIM_OPT_WPS, SWIM_OPT_BIG_TPL = 1, 2
+SWIM_OPT_WPS, SWIM_OPT_BIG_TPL, SWIM_OPT_GRAPH, SWIM_OPT_GRAPH_LAUNCHES, SWIM_OPT_GRAPH_CAPTURES = 1, 2, 3, 4, 5
 SWIM_MLP_NPARAM, SWIM_MLP_IN, SWIM_MLP_OUT = 207393, 5, 33
 
 _c = ctypes
@@ -45,7 +45,7 @@ SIGNATURES = {
     "abc_pmc_propose": (_c.c_int, [_c.c_uint64, _c.c_int32, _c.c_int64, _DP, _DP, _c.c_int64, _DP, _DP, _DP]),
     "abc_pmc_weights": (_c.c_int, [_c.c_int64, _DP, _U8P, _DP, _DP, _c.c_int64, _DP]),
     "abc_step": (_c.c_int, [_P, _P, _DP, _c.c_int32, _c.c_int64, _I32P, _c.c_uint64, _c.c_int32, _DP, _DP,
-                            _c.c_int64, _c.c_double, _DP, _DP, _U8P, _DP, _DP]),
+                            _c.c_int64, _c.c_double, _DP, _DP, _U8P, _DP, _DP, _I32P]),
     "swim_kernel_eval_host": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_double, _c.c_int64, _DP, _DP, _DP, _DP]),
     "surrogate_forward": (_c.c_int, [_P, _c.c_int64, _P, _P, _P, _P]),
     "surrogate_grad": (_c.c_int, [_P, _c.c_int64, _P, _P, _P, _P, _P, _P]),
@@ -249,10 +249,12 @@ def abc_step(ctx, model, data, N, seed, generation, q, prev_theta=None, prev_w=N
     acc = np.empty(n, dtype=np.uint8)
     w = np.empty(n)
     tol = np.empty(1)
+    steps = np.empty(n, dtype=np.int32)
     _check(lib().abc_step(ctx.handle, ctypes.byref(model), d_p, d.shape[0], n, n_p, int(seed), int(generation),
                           pt_p, pw_p, n_prev, float(q), theta.ctypes.data_as(_DP), dist.ctypes.data_as(_DP),
-                          acc.ctypes.data_as(_U8P), w.ctypes.data_as(_DP), tol.ctypes.data_as(_DP)))
-    return dict(theta=theta, dist=dist, accept=acc.astype(bool), w=w, tol=float(tol[0]))
+                          acc.ctypes.data_as(_U8P), w.ctypes.data_as(_DP), tol.ctypes.data_as(_DP),
+                          steps.ctypes.data_as(_I32P)))
+    return dict(theta=theta, dist=dist, accept=acc.astype(bool), w=w, tol=float(tol[0]), steps=steps)
 
 
 def swim_kernel_eval_host(dtype, alpha, eps, t):
