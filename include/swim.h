@@ -105,6 +105,26 @@ int swim_version(void);
 int swim_set_option(swim_ctx *ctx, int32_t key, int32_t value);
 int swim_get_option(swim_ctx *ctx, int32_t key, int32_t *value);
 
+/* Autotuner of the launch shapes (synchronous).  Times forward runs of
+ * probe_steps steps of the given batch (layout and parameter rows as for
+ * swim_forward; params device) on the context's stream, eagerly:
+ *   - for every size bucket of the persistent kernel present in the batch
+ *     (systems of up to 64*tpl points, tpl in {1,2,3,4,6,8}), the waves per
+ *     system among 2, 4, 8, 16 (those whose partial sums fit the LDS), one
+ *     bucket at a time with the others at their current choice;
+ *   - if the batch has systems over 512 points, the targets per lane of
+ *     the large-system kernel among 1, 2, 4.
+ * The choices stay in the context (used by every later run whose
+ * SWIM_OPT_WPS is 0; the large-system choice sets SWIM_OPT_BIG_TPL) and
+ * are returned in chosen (host int32[9]: waves per system for tpl = 1..8,
+ * 0 where not tuned, then the large-system targets per lane). */
+int swim_autotune(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const int32_t *N,
+                  const int32_t *n_swim, const double *params, int32_t probe_steps, double dt,
+                  double eps_over_ds, int32_t *chosen);
+/* Tuned shapes of a context to / from a small text file (path host string). */
+int swim_tune_save(swim_ctx *ctx, const char *path);
+int swim_tune_load(swim_ctx *ctx, const char *path);
+
 /* One evaluation of the dense velocity sum of eq. (BrV), Sec. 2.1:
  *   u_i = sum_j [ H1(r_ij) F_j + H2(r_ij) (F_j . x_ij) x_ij ],
  * x_ij = X_i - X_j, over all points j of the system of i (self term

@@ -95,6 +95,7 @@ struct swim_ctx {
     int opt_wps = 0;      // waves per system in the persistent kernel (0: automatic)
     int opt_big_tpl = 0;  // targets per lane of the large-system kernel (0: automatic)
     int opt_graph = 1;    // 0: eager launches; 1: capture on a repeated layout; 2: capture always
+    int tuned_wps[2][9] = {};  // autotuned waves per system [dtype][tpl] (0: not tuned)
     FwdGraph graphs[N_GRAPHS];
     uint64_t graph_clock = 0, last_key = 0;
     int64_t graph_launches = 0, graph_captures = 0;
@@ -361,7 +362,7 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
         q.tpl = bucket_span[k].first;
         q.start = bucket_span[k].second;
         q.count = (k + 1 < bucket_span.size() ? bucket_span[k + 1].second : (int64_t)order.size()) - q.start;
-        q.wps = c->opt_wps ? c->opt_wps : 16;
+        q.wps = c->opt_wps ? c->opt_wps : (c->tuned_wps[dtype][q.tpl] ? c->tuned_wps[dtype][q.tpl] : 16);
         // the wave partial sums of one system must fit the LDS
         while (q.wps > 1 && forward_lds_bytes(dtype, q.tpl, q.wps) > 160 * 1024) q.wps /= 2;
         const int per_cu = forward_blocks_per_cu(dtype, q.tpl, q.wps);
@@ -1392,6 +1393,149 @@ int abc_prescreened(swim_ctx* c, const abc_model* m, int32_t N, const float* par
         HIPCHK(hipEventElapsedTime(&ms_out[0], ev[0], ev[1]));
         HIPCHK(hipEventElapsedTime(&ms_out[1], ev[1], ev[2]));
     }
+    return SWIM_OK;
+}
+
+
+// ==========================================================================
+// autotuner
+// ==========================================================================
+int swim_autotune(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, const int32_t* n_swim,
+                  const double* params, int32_t probe_steps, double dt, double eps_over_ds, int32_t* chosen)
+{
+    TRY(check_ctx(c));
+    TRY(check_dtype(dtype));
+    if (n_sys < 1 || !N || !params || !chosen) return fail(SWIM_EINVAL, "bad swim_autotune arguments");
+    if (probe_steps < 1) return fail(SWIM_EINVAL, "probe_steps must be >= 1");
+    TRY(check_run(n_sys, N, n_swim, probe_steps, dt, probe_steps, eps_over_ds));
+    hipStream_t st = c->stream;
+    int64_t nfil = 0;
+    bool has_tpl[9] = {};
+    bool has_big = false;
+    for (int64_t s = 0; s < n_sys; ++s) {
+        const int nsw = n_swim ? n_swim[s] : 1;
+        nfil += nsw;
+        const int tpl = choose_tpl(N[s] * nsw);
+        if (tpl > 0) has_tpl[tpl] = true;
+        else has_big = true;
+    }
+    const size_t es = dtype == SWIM_F32 ? 4 : 8;
+    TRY(ensure(c, B_OBS, (size_t)nfil * 2 * es));
+    TRY(ensure(c, B_SPEED, (size_t)nfil * es));
+    TRY(ensure(c, B_STATUS, (size_t)n_sys * 4));
+    Run r;
+    r.steps = probe_steps;
+    r.dt = dt;
+    r.obs_every = probe_steps;
+    r.n_obs = 1;
+    r.eps_over_ds = eps_over_ds;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SWIM_EHIP, "event creation failed");
+    }
+    const int save_graph = c->opt_graph, save_wps = c->opt_wps, save_big = c->opt_big_tpl;
+    c->opt_graph = 0;
+    c->opt_wps = 0;
+    int rc = SWIM_OK;
+    auto timed = [&](float* ms) -> int {
+        // one untimed run first: first launches pay for code loading
+        for (int rep = 0; rep < 2; ++rep) {
+            if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) return fail(SWIM_EHIP, "event record failed");
+            TRY(forward_impl(c, dtype, n_sys, N, n_swim, params, r, c->buf[B_OBS].p, c->buf[B_SPEED].p,
+                             (int32_t*)c->buf[B_STATUS].p, nullptr, st));
+        }
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipEventElapsedTime(ms, e0, e1));
+        return SWIM_OK;
+    };
+    // waves per system, one size bucket at a time (the others at their
+    // current choice), then targets per lane of the large-system kernel
+    const int wps_cand[] = {2, 4, 8, 16};
+    for (int tpl = 1; tpl <= 8 && rc == SWIM_OK; ++tpl) {
+        if (!has_tpl[tpl]) continue;
+        float best = 0.f;
+        int best_w = 16;
+        for (int w : wps_cand) {
+            if (forward_lds_bytes(dtype, tpl, w) > 160 * 1024) continue;
+            c->tuned_wps[dtype][tpl] = w;
+            float ms = 0.f;
+            rc = timed(&ms);
+            if (rc != SWIM_OK) break;
+            if (best == 0.f || ms < best) {
+                best = ms;
+                best_w = w;
+            }
+        }
+        c->tuned_wps[dtype][tpl] = best_w;
+    }
+    int best_big = save_big ? save_big : 1;
+    if (has_big && rc == SWIM_OK) {
+        float best = 0.f;
+        for (int t : {1, 2, 4}) {
+            c->opt_big_tpl = t;
+            float ms = 0.f;
+            rc = timed(&ms);
+            if (rc != SWIM_OK) break;
+            if (best == 0.f || ms < best) {
+                best = ms;
+                best_big = t;
+            }
+        }
+    }
+    c->opt_graph = save_graph;
+    c->opt_wps = save_wps;
+    c->opt_big_tpl = rc == SWIM_OK ? best_big : save_big;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SWIM_OK) return rc;
+    for (int tpl = 1; tpl <= 8; ++tpl) chosen[tpl - 1] = c->tuned_wps[dtype][tpl];
+    chosen[8] = c->opt_big_tpl;
+    return SWIM_OK;
+}
+
+int swim_tune_save(swim_ctx* c, const char* path)
+{
+    TRY(check_ctx(c));
+    if (!path) return fail(SWIM_EINVAL, "null path");
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(SWIM_EINVAL, "cannot write %s", path);
+    fprintf(f, "swim-tune 1\n");
+    for (int d = 0; d < 2; ++d) {
+        fprintf(f, "wps %d", d);
+        for (int t = 1; t <= 8; ++t) fprintf(f, " %d", c->tuned_wps[d][t]);
+        fprintf(f, "\n");
+    }
+    fprintf(f, "big_tpl %d\n", c->opt_big_tpl);
+    const bool ok = fclose(f) == 0;
+    return ok ? SWIM_OK : fail(SWIM_EINVAL, "write error on %s", path);
+}
+
+int swim_tune_load(swim_ctx* c, const char* path)
+{
+    TRY(check_ctx(c));
+    if (!path) return fail(SWIM_EINVAL, "null path");
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(SWIM_EINVAL, "cannot read %s", path);
+    int ver = 0, tuned[2][9] = {}, big = 0;
+    bool ok = fscanf(f, " swim-tune %d", &ver) == 1 && ver == 1;
+    for (int d = 0; d < 2 && ok; ++d) {
+        int dd = -1;
+        ok = fscanf(f, " wps %d", &dd) == 1 && dd == d;
+        for (int t = 1; t <= 8 && ok; ++t) {
+            ok = fscanf(f, " %d", &tuned[d][t]) == 1;
+            const int w = tuned[d][t];
+            ok = ok && (w == 0 || w == 1 || w == 2 || w == 4 || w == 8 || w == 16);
+        }
+    }
+    ok = ok && fscanf(f, " big_tpl %d", &big) == 1 && (big == 0 || big == 1 || big == 2 || big == 4);
+    fclose(f);
+    if (!ok) return fail(SWIM_EINVAL, "%s is not a tune file of this library", path);
+    for (int d = 0; d < 2; ++d)
+        for (int t = 1; t <= 8; ++t) c->tuned_wps[d][t] = tuned[d][t];
+    c->opt_big_tpl = big;
     return SWIM_OK;
 }
 

@@ -35,6 +35,10 @@ SIGNATURES = {
     "swim_version": (_c.c_int, []),
     "swim_set_option": (_c.c_int, [_P, _c.c_int32, _c.c_int32]),
     "swim_get_option": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int32)]),
+    "swim_autotune": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I32P, _I32P, _P, _c.c_int32, _c.c_double, _c.c_double,
+                                 _I32P]),
+    "swim_tune_save": (_c.c_int, [_P, _c.c_char_p]),
+    "swim_tune_load": (_c.c_int, [_P, _c.c_char_p]),
     "swim_pair_velocity": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I64P, _DP, _DP, _P, _P, _P, _P, _P, _P, _P]),
     "swim_elastic_forces": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I32P, _DP, _c.c_double, _P, _P, _P, _P, _P]),
     "swim_forward": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I32P, _I32P, _P, _c.c_int32, _c.c_double,
@@ -164,6 +168,25 @@ def swim_get_option(ctx, key):
     v = ctypes.c_int32()
     _check(lib().swim_get_option(ctx.handle, int(key), ctypes.byref(v)))
     return v.value
+
+
+def swim_autotune(ctx, dtype, N, n_swim, params, probe_steps, dt, eps_over_ds=1.5):
+    """Returns the chosen shapes: waves per system for tpl 1..8 (0: not
+    tuned) and the large-system targets per lane."""
+    n, n_p = _h(N, np.int32, _I32P)
+    ns, ns_p = (None, None) if n_swim is None else _h(n_swim, np.int32, _I32P)
+    out = np.zeros(9, dtype=np.int32)
+    _check(lib().swim_autotune(ctx.handle, int(dtype), len(n), n_p, ns_p, _dptr(params), int(probe_steps), float(dt),
+                               float(eps_over_ds), out.ctypes.data_as(_I32P)))
+    return dict(wps={t: int(out[t - 1]) for t in (1, 2, 3, 4, 6, 8)}, big_tpl=int(out[8]))
+
+
+def swim_tune_save(ctx, path):
+    return _check(lib().swim_tune_save(ctx.handle, str(path).encode()))
+
+
+def swim_tune_load(ctx, path):
+    return _check(lib().swim_tune_load(ctx.handle, str(path).encode()))
 
 
 def swim_pair_velocity(ctx, sys_off, alpha, eps, x, y, fx, fy, ux, uy, stream=None):
