@@ -181,6 +181,45 @@ def dense_leg(ctx, stream, with_oracle, samples=64, steps=1000):
     return out
 
 
+def pmc_leg(ctx, data, n=16384, steps=5000, dt=5e-5, quantiles=(0.5, 0.25, 0.1)):
+    """Uneven batching with population Monte Carlo: n particles, each with
+    its own filament size N ~ U{64, 96, ..., 512} (seed 2) and the batched
+    workload's priors, steps and dt; three generations at the 50th, 25th and
+    10th percentile tolerances (Philox seed 2).  The launch shapes come from
+    the autotuner run on generation 0's draws; each generation is one
+    abc_step (host proposals and weights in FP64, FP32 forward runs, device
+    distances and percentile), its forward runs replayed from a captured
+    graph once the layout repeats."""
+    import torch
+    from paper_1910_12007_amd import inputs, swim, surrogate_abc
+    N = inputs.uneven_sizes(n, seed=2)
+    model = surrogate_abc.batch_model(steps=steps, dt=dt)
+    theta0 = swim.abc_prior_draw(2, n, inputs.PRIOR_LO, inputs.PRIOR_HI)
+    t0 = time.perf_counter()
+    chosen = swim.swim_autotune(ctx, swim.SWIM_F32, N, None, torch.from_numpy(inputs.theta_rows(theta0)).cuda(),
+                                50, dt)
+    tune_s = time.perf_counter() - t0
+    gens = []
+    prev_theta = prev_w = None
+    for g, q in enumerate(quantiles):
+        t0 = time.perf_counter()
+        r = swim.abc_step(ctx, model, data, N, 2, g, q, prev_theta, prev_w)
+        sec = time.perf_counter() - t0
+        steps_done = r["steps"].astype(np.int64)
+        pairs = float(np.sum(steps_done * N.astype(np.int64) ** 2))
+        acc = r["accept"]
+        gens.append({"generation": g, "quantile": q, "seconds": sec, "tolerance": r["tol"],
+                     "completed": int(np.isfinite(r["dist"]).sum()), "accepted": int(acc.sum()),
+                     "pair_evals_per_s": pairs / sec, "swimmer_steps_per_s": float(np.sum(steps_done)) / sec,
+                     "posterior_mean": [float(x) for x in np.average(r["theta"][acc], axis=0, weights=r["w"][acc])]
+                     if acc.any() else None})
+        prev_theta, prev_w = r["theta"][acc], r["w"][acc]
+    return {"workload": f"{n} particles, N ~ U{{64..512 step 32}} (seed 2), {steps} steps dt={dt}, PMC generations "
+                        f"at quantiles {list(quantiles)}, FP32",
+            "autotune_s": tune_s, "tuned_waves_per_system": {str(k): v for k, v in chosen["wps"].items() if v},
+            "graph_launches": swim.swim_get_option(ctx, swim.SWIM_OPT_GRAPH_LAUNCHES), "generations": gens}
+
+
 def surrogate_leg(ctx, data):
     """Surrogate-prescreened ABC against plain batched ABC on the same 1M
     prior draws (tolerance: the 5th percentile of the completed runs of the
@@ -217,6 +256,7 @@ def main():
     ap.add_argument("--wps", type=int, default=0, help="waves per system (0: library default)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-prescreened ABC comparison")
     ap.add_argument("--no-dense", action="store_true", help="skip the large-N dense workload")
+    ap.add_argument("--no-pmc", action="store_true", help="skip the uneven-N PMC workload")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times), the reference "
                          "for scaling the HBM byte counters, and exit")
@@ -320,6 +360,8 @@ def main():
     out["surrogate_mfma"] = mlp_leg(ctx, stream)
     if not args.no_dense:
         out["dense"] = dense_leg(ctx, stream, with_oracle=not args.no_cpu)
+    if not args.no_pmc:
+        out["pmc_uneven"] = pmc_leg(ctx, load_data())
     if not args.no_surrogate:
         out["surrogate_abc"] = surrogate_leg(ctx, load_data())
     if not args.no_cpu:

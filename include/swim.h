@@ -221,18 +221,30 @@ int abc_pmc_weights(int64_t n, const double *theta, const uint8_t *accept,
                     const double *prev_theta, const double *prev_w, int64_t n_prev, double *w);
 
 /* One ABC generation end to end (synchronous; host arrays in and out):
- * proposals (prior draw for generation 0, PMC proposals otherwise) on the
- * host, forward runs, distances, percentile tolerance and acceptance on the
- * device, PMC weights on the host.  The device part of a generation is
- * captured once into a hipGraph and replayed while the layout is unchanged.
- * model: fixed swimmer constants and the run length. */
+ * proposals (prior draw for generation 0, PMC proposals otherwise; host,
+ * FP64), forward runs (device, model->dtype), distances, percentile
+ * tolerance and acceptance (device), weights (host: 1/n_accepted for
+ * generation 0, Beaumont weights otherwise).  The forward runs follow the
+ * context's SWIM_OPT_GRAPH mode (a repeated layout, e.g. the generations of
+ * one PMC run, is captured once and replayed); use_graph = 0 in the model
+ * forces eager launches for this call.
+ *   data       host double[n_obs][2], n_obs = model->steps / obs_every;
+ *   N          host int32[n], points of particle i;
+ *   prev_theta, prev_w  host double[n_prev][3], double[n_prev] (the previous
+ *              generation's accepted population; NULL for generation 0);
+ *   q          tolerance quantile in (0, 1] over the completed runs;
+ *   theta_out  host double[n][3]; dist_out host double[n] (+inf: failed);
+ *   accept_out host uint8[n]; w_out host double[n] (0 where rejected);
+ *   tol_out    host double[1]; steps_out host int32[n] or NULL (steps each
+ *              run completed).
+ * SWIM_EINVAL on bad arguments (before any launch). */
 typedef struct {
     double lo[3], hi[3];   /* uniform prior box on (alpha, S_b, S_s) */
     double b, omega, k;    /* beat amplitude, angular frequency, wavenumber */
     int32_t steps, obs_every;
     double dt, eps_over_ds;
     int32_t dtype;
-    int32_t use_graph;     /* 1: capture/replay the device sequence */
+    int32_t use_graph;     /* 0: eager launches for this call; 1: the context's graph mode */
 } abc_model;
 
 int abc_step(swim_ctx *ctx, const abc_model *model, const double *data, int32_t n_obs, int64_t n,

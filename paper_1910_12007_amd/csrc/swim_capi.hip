@@ -957,8 +957,12 @@ int abc_step(swim_ctx* c, const abc_model* m, const double* data, int32_t n_obs,
     r.eps_over_ds = m->eps_over_ds;
     if (steps_out) TRY(ensure(c, B_DONE, (size_t)n * 4));
     int32_t* done_dev = steps_out ? (int32_t*)c->buf[B_DONE].p : nullptr;
-    TRY(forward_impl(c, m->dtype, n, N, nullptr, (const double*)c->buf[B_PARAMS].p, r, c->buf[B_OBS].p,
-                     c->buf[B_SPEED].p, (int32_t*)c->buf[B_STATUS].p, done_dev, st));
+    const int save_graph = c->opt_graph;
+    if (!m->use_graph) c->opt_graph = 0;
+    const int frc = forward_impl(c, m->dtype, n, N, nullptr, (const double*)c->buf[B_PARAMS].p, r, c->buf[B_OBS].p,
+                                 c->buf[B_SPEED].p, (int32_t*)c->buf[B_STATUS].p, done_dev, st);
+    c->opt_graph = save_graph;
+    TRY(frc);
     HIPCHK(launch_abc_distance(m->dtype, n, n_obs, c->buf[B_OBS].p, (const double*)c->buf[B_DATA].p,
                                (const int32_t*)c->buf[B_STATUS].p, (double*)c->buf[B_DIST].p, st));
     HIPCHK(launch_select_kth(n, (const double*)c->buf[B_DIST].p, q, (double*)c->buf[B_TOL].p, st));

@@ -52,7 +52,7 @@ def batch_model(steps=5000, dt=5e-5, obs_every=100, dtype=swim.SWIM_F32):
         m.hi[d] = float(inputs.PRIOR_HI[d])
     m.b, m.omega, m.k = 0.1, 2 * np.pi, 2 * np.pi
     m.steps, m.obs_every, m.dt, m.eps_over_ds = steps, obs_every, dt, 1.5
-    m.dtype, m.use_graph = dtype, 0
+    m.dtype, m.use_graph = dtype, 1
     return m
 
 
