@@ -181,6 +181,38 @@ def dense_leg(ctx, stream, with_oracle, samples=64, steps=1000):
     return out
 
 
+def per_sample_leg(ctx, stream, P_all, n=256, N=128, steps=5000, dt=5e-5):
+    """The batched generation's first n draws as one fused persistent launch
+    against one launch per sample (each a batch of one system), both on the
+    library's path with inputs resident; HIP events on the same stream."""
+    import torch
+    from paper_1910_12007_amd import swim
+    P = P_all[:n].contiguous()
+    obs = torch.empty((n, steps // 100, 2), dtype=torch.float32, device="cuda")
+    speed = torch.empty(n, dtype=torch.float32, device="cuda")
+    status = torch.empty(n, dtype=torch.int32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    graph_mode = swim.swim_get_option(ctx, swim.SWIM_OPT_GRAPH)
+    swim.swim_set_option(ctx, swim.SWIM_OPT_GRAPH, 0)
+    try:
+        swim.swim_forward(ctx, np.full(n, N, np.int32), None, P, steps, dt, 100, 1.5, obs, speed, status,
+                          stream=stream)
+        ev[0].record(stream)
+        swim.swim_forward(ctx, np.full(n, N, np.int32), None, P, steps, dt, 100, 1.5, obs, speed, status,
+                          stream=stream)
+        ev[1].record(stream)
+        ev[2].record(stream)
+        for i in range(n):
+            swim.swim_forward(ctx, np.full(1, N, np.int32), None, P[i:i + 1], steps, dt, 100, 1.5, obs[i:i + 1],
+                              speed[i:i + 1], status[i:i + 1], stream=stream)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+    finally:
+        swim.swim_set_option(ctx, swim.SWIM_OPT_GRAPH, graph_mode)
+    fused, single = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+    return {"draws": n, "fused_ms": fused, "per_sample_launches_ms": single, "speedup": single / fused}
+
+
 def pmc_leg(ctx, data, n=16384, steps=5000, dt=5e-5, quantiles=(0.5, 0.25, 0.1)):
     """Uneven batching with population Monte Carlo: n particles, each with
     its own filament size N ~ U{64, 96, ..., 512} (seed 2) and the batched
@@ -358,6 +390,7 @@ def main():
                      "fp32_peak_tflops": FP32_PEAK_TFLOPS},
     }
     out["surrogate_mfma"] = mlp_leg(ctx, stream)
+    out["fused_vs_per_sample"] = per_sample_leg(ctx, stream, P)
     if not args.no_dense:
         out["dense"] = dense_leg(ctx, stream, with_oracle=not args.no_cpu)
     if not args.no_pmc:
