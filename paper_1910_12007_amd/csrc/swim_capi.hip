@@ -61,7 +61,7 @@ enum BufId {
     B_OFF, B_SWOFF, B_NPT, B_NSW, B_ORDER, B_LIST, B_BLKS, B_BLKF, B_ALPHA, B_EPS, B_SYSC, B_QUEUE,
     B_PARAMS, B_DATA, B_OBS, B_SPEED, B_STATUS, B_DIST, B_TOL, B_ACC, B_BIG,
     B_MLP_ACT, B_MLP_GRAD, B_MLP_BATCH, B_MLP_IDX, B_MLP_CNT,
-    B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_TAB, B_DONE, B_NBUF
+    B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_TAB, B_DONE, B_W16, B_NBUF
 };
 
 // surrogate network: 5 -> 256 x 4 -> 33
@@ -1032,13 +1032,11 @@ int surrogate_forward(swim_ctx* c, int64_t n, const float* X, const float* param
     TRY(check_ctx(c));
     if (n < 0 || (n > 0 && (!X || !params || !Y))) return fail(SWIM_EINVAL, "bad surrogate_forward arguments");
     hipStream_t st = pick(c, stream);
-    const int64_t CH = 65536;
-    MlpAct a;
-    TRY(mlp_act(c, std::min(n, CH), &a));
-    for (int64_t r = 0; r < n; r += CH) {
-        const int64_t m = std::min(CH, n - r);
-        TRY(mlp_forward(X + r * MLP_W[0], params, m, a, Y + r * MLP_W[MLP_L], st));
-    }
+    if (n == 0) return SWIM_OK;
+    TRY(ensure(c, B_W16, (size_t)mlp_w16_count() * 2));
+    HIPCHK(launch_pack_w16(params, (uint16_t*)c->buf[B_W16].p, st));
+    HIPCHK(launch_mlp_fused(0, n, X, (const uint16_t*)c->buf[B_W16].p, params, Y, nullptr, nullptr, nullptr, 0, 0.f,
+                            nullptr, nullptr, st));
     return SWIM_OK;
 }
 
@@ -1046,21 +1044,16 @@ int surrogate_forward(swim_ctx* c, int64_t n, const float* X, const float* param
 
 namespace {
 
-// surrogate distance of n standardized inputs in chunks of 65536 rows, then
-// the compaction of the kept rows
+// surrogate distance of n standardized inputs (fused MLP kernel: the
+// activations never leave LDS), then the compaction of the kept rows
 int prescreen_impl(swim_ctx* c, int64_t n, const float* X, const float* params, const float* out_mu,
                    const float* out_sd, const float* obs_sum, int32_t n_sum, float tol, float* dist, uint8_t* keep,
                    int64_t* idx, int64_t* n_keep, hipStream_t st)
 {
-    const int64_t CH = 65536;
-    MlpAct a;
-    TRY(mlp_act(c, std::min(n, CH), &a));
-    for (int64_t r = 0; r < n; r += CH) {
-        const int64_t m = std::min(CH, n - r);
-        TRY(mlp_forward(X + r * MLP_W[0], params, m, a, a.Y, st));
-        HIPCHK(launch_prescreen((int)m, MLP_W[MLP_L], n_sum, a.Y, out_mu, out_sd, obs_sum, tol, dist ? dist + r : nullptr,
-                                keep + r, st));
-    }
+    TRY(ensure(c, B_W16, (size_t)mlp_w16_count() * 2));
+    HIPCHK(launch_pack_w16(params, (uint16_t*)c->buf[B_W16].p, st));
+    HIPCHK(launch_mlp_fused(1, n, X, (const uint16_t*)c->buf[B_W16].p, params, nullptr, out_mu, out_sd, obs_sum, n_sum,
+                            tol, dist, keep, st));
     TRY(ensure(c, B_MLP_CNT, (size_t)((n + 255) / 256) * 4));
     HIPCHK(launch_compact(n, keep, (int32_t*)c->buf[B_MLP_CNT].p, idx, n_keep, st));
     return SWIM_OK;

@@ -125,4 +125,13 @@ hipError_t launch_flag_eq(int64_t n, const int32_t* v, int32_t want, uint8_t* ke
 hipError_t launch_flag_bounded(int64_t n, const float* T, int nt, int n_disp, float max_disp, uint8_t* keep,
                                hipStream_t st);
 
+// fused MLP inference (mode 0: outputs Y[M][33]; mode 1: prescreen distance
+// and keep flag), from the bfloat16 weight copy W16 (launch_pack_w16)
+size_t mlp_fused_lds_bytes();
+int64_t mlp_w16_count();
+hipError_t launch_pack_w16(const float* P, uint16_t* W16, hipStream_t st);
+hipError_t launch_mlp_fused(int mode, int64_t M, const float* X, const uint16_t* W16, const float* P, float* Y,
+                            const float* out_mu, const float* out_sd, const float* obs, int n_sum, float tol,
+                            float* dist, uint8_t* keep, hipStream_t st);
+
 }  // namespace swim

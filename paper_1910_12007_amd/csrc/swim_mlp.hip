@@ -549,4 +549,262 @@ hipError_t launch_flag_bounded(int64_t n, const float* T, int nt, int n_disp, fl
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference: every workgroup carries a tile of MLP_RT rows through all
+// five layers.  Activations stay in LDS as bfloat16 (the rounding every GEMM
+// operand gets anyway), weights come from a bfloat16 copy packed per layer
+// as W^T [n][k] (k padded to a multiple of 16, n of the last layer to 48)
+// and pass through LDS in chunks of MLP_KC k, double-buffered: the next
+// chunk (of this layer or the next) is read into registers while the
+// current one feeds the MFMAs.  Each of the 4 waves owns 32
+// rows and all output columns; MFMA 16x16x16 bf16 with FP32 accumulation,
+// in the same k order as the layer-by-layer path.  MODE 0 writes the
+// outputs; MODE 1 computes the prescreen distance of every row.
+// ---------------------------------------------------------------------------
+constexpr int MLP_RT = 128, MLP_HP = 256 + 8, MLP_KC = 64, MLP_WP = MLP_KC + 8;
+constexpr int MLP_NL = 5;
+constexpr int mlp_kp(int l) { return l == 0 ? 16 : 256; }   // padded K
+constexpr int mlp_np(int l) { return l == MLP_NL - 1 ? 48 : 256; }  // padded N
+constexpr int mlp_k(int l) { return l == 0 ? 5 : 256; }
+constexpr int mlp_n(int l) { return l == MLP_NL - 1 ? 33 : 256; }
+constexpr int64_t mlp_w16_off(int l)
+{
+    int64_t o = 0;
+    for (int k = 0; k < l; ++k) o += (int64_t)mlp_np(k) * mlp_kp(k);
+    return o;
+}
+constexpr int64_t MLP_W16_TOTAL = mlp_w16_off(MLP_NL);
+constexpr int64_t mlp_offW_d(int l)
+{
+    int64_t o = 0;
+    for (int k = 0; k < l; ++k) o += (int64_t)mlp_k(k) * mlp_n(k) + mlp_n(k);
+    return o;
+}
+
+// bfloat16 copy of the weights, transposed and padded (zeros)
+__global__ void k_pack_w16(const float* P, uint16_t* W16)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= MLP_W16_TOTAL) return;
+    int l = 0;
+    while (l + 1 < MLP_NL && e >= mlp_w16_off(l + 1)) ++l;
+    const int64_t i = e - mlp_w16_off(l);
+    const int n = (int)(i / mlp_kp(l)), k = (int)(i % mlp_kp(l));
+    const float v = (n < mlp_n(l) && k < mlp_k(l)) ? P[mlp_offW_d(l) + (int64_t)k * mlp_n(l) + n] : 0.0f;
+    W16[e] = f2bf(v);
+}
+
+// weight chunk c of layer l (rows n < Np(l), k in [64c, 64c + kce)) as
+// per-thread 16-byte pieces: global -> registers, registers -> LDS
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+struct WChunk {
+    u32x4_t v[8];
+};
+__device__ __forceinline__ const uint16_t* mlp_wl(const uint16_t* W16, int l)
+{
+    return W16 + (l == 0 ? 0 : (l == MLP_NL - 1 ? mlp_w16_off(MLP_NL - 1) : mlp_w16_off(1) + (int64_t)(l - 1) * 65536));
+}
+__device__ __forceinline__ int mlp_chunks(int l) { return l == 0 ? 1 : 256 / MLP_KC; }
+// One code path for every layer: each thread moves 8 pieces of 16 bytes;
+// the loads are clamped to a valid piece (so the prefetch is always fully
+// defined and stays in registers), only valid pieces are stored.
+__device__ __forceinline__ void wchunk_geom(int l, int& Kp, int& Np, int& per)
+{
+    Kp = l == 0 ? 16 : 256;
+    Np = l == MLP_NL - 1 ? 48 : 256;
+    per = (Kp < MLP_KC ? Kp : MLP_KC) / 8;
+}
+__device__ __forceinline__ void wchunk_load(const uint16_t* W16, int l, int c, int tid, WChunk& w)
+{
+    int Kp, Np, per;
+    wchunk_geom(l, Kp, Np, per);
+    const uint16_t* Wl = mlp_wl(W16, l);
+    const int last = Np * per - 1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int e = min(tid + 256 * q, last);
+        const int n = e / per, p = e - (e / per) * per;
+        w.v[q] = *reinterpret_cast<const u32x4_t*>(Wl + (int64_t)n * Kp + MLP_KC * c + 8 * p);
+    }
+}
+__device__ __forceinline__ void wchunk_store(int l, int tid, const WChunk& w, uint16_t* Ws)
+{
+    int Kp, Np, per;
+    wchunk_geom(l, Kp, Np, per);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int e = tid + 256 * q;
+        if (e < Np * per) {
+            const int n = e / per, p = e - (e / per) * per;
+            *reinterpret_cast<u32x4_t*>(Ws + n * MLP_WP + 8 * p) = w.v[q];
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_mlp_fused(int64_t M, const float* __restrict__ X,
+                                                   const uint16_t* __restrict__ W16, const float* __restrict__ P,
+                                                   float* __restrict__ Y, const float* __restrict__ out_mu,
+                                                   const float* __restrict__ out_sd, const float* __restrict__ obs,
+                                                   int n_sum, float tol, float* __restrict__ dist,
+                                                   uint8_t* __restrict__ keep)
+{
+    extern __shared__ __align__(16) uint16_t mlp_smem[];
+    uint16_t* Hs = mlp_smem;                    // [MLP_RT][MLP_HP]
+    uint16_t* Wb = mlp_smem + MLP_RT * MLP_HP;  // [2][256][MLP_WP], double-buffered
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * MLP_RT;
+    // inputs, k padded to 16
+    for (int e = tid; e < MLP_RT * 16; e += 256) {
+        const int r = e >> 4, k = e & 15;
+        const float v = (r0 + r < M && k < 5) ? X[(r0 + r) * 5 + k] : 0.0f;
+        Hs[r * MLP_HP + k] = f2bf(v);
+    }
+    const int wr = 32 * wave;  // this wave's rows
+    const int rowq = 4 * (lane >> 4), col = lane & 15;
+    // the weight chunks of all layers form one sequence g = 0, 1, ...;
+    // chunk g lives in Wbuf[g & 1], chunk g + 1 is fetched while g is used
+    WChunk nxt;
+    wchunk_load(W16, 0, 0, tid, nxt);
+    wchunk_store(0, tid, nxt, Wb);
+    int g = 0;
+#pragma unroll 1
+    for (int l = 0; l < MLP_NL; ++l) {
+        const int NT = l == MLP_NL - 1 ? 3 : 16;  // 16-wide column tiles
+        const int nchunk = mlp_chunks(l);
+        const int kce = l == 0 ? 16 : MLP_KC;
+        f32x4_t acc[2][16];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int c = 0; c < 16; ++c) acc[t][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+        for (int ch = 0; ch < nchunk; ++ch, ++g) {
+            __syncthreads();  // chunk g stored; the previous user of Wbuf[(g + 1) & 1] done
+            // fetch the next chunk of the sequence (this layer's next, or the
+            // next layer's first)
+            const bool more = ch + 1 < nchunk || l + 1 < MLP_NL;
+            const int nl = ch + 1 < nchunk ? l : l + 1, nc = ch + 1 < nchunk ? ch + 1 : 0;
+            if (more) wchunk_load(W16, nl, nc, tid, nxt);
+            const uint16_t* Ws = Wb + (g & 1) * 256 * MLP_WP;
+            const int kc = MLP_KC * ch;
+            for (int ks = 0; ks < kce; ks += 16) {
+                const int kq = ks + 4 * (lane >> 4);
+                bf16x4_t av[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const uint2 v = *reinterpret_cast<const uint2*>(Hs + (wr + 16 * t + col) * MLP_HP + kc + kq);
+                    av[t] = __builtin_bit_cast(bf16x4_t, v);
+                }
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    if (c < NT) {
+                        const uint2 v = *reinterpret_cast<const uint2*>(Ws + (16 * c + col) * MLP_WP + kq);
+                        const bf16x4_t bv = __builtin_bit_cast(bf16x4_t, v);
+                        acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[0], bv, acc[0][c], 0, 0, 0);
+                        acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[1], bv, acc[1][c], 0, 0, 0);
+                    }
+                }
+            }
+            if (more) wchunk_store(nl, tid, nxt, Wb + ((g + 1) & 1) * 256 * MLP_WP);
+        }
+        const float* bias = P + mlp_offW_d(l) + (int64_t)mlp_k(l) * mlp_n(l);
+        if (l < MLP_NL - 1) {
+            // bias, GELU, back into this wave's rows of the activations
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    const int n = 16 * c + col;
+                    const float bn = bias[n];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        Hs[(wr + 16 * t + rowq + r) * MLP_HP + n] = f2bf(gelu_f(acc[t][c][r] + bn));
+                }
+        } else if (MODE == 0) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int n = 16 * c + col;
+                    if (n >= 33) continue;
+                    const float bn = bias[n];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t row = r0 + wr + 16 * t + rowq + r;
+                        if (row < M) Y[row * 33 + n] = acc[t][c][r] + bn;
+                    }
+                }
+        } else {
+            // prescreen: d = sqrt(mean_{n < n_sum} (mu_n + sd_n y_n - obs_n)^2)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                float sq[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int n = 16 * c + col;
+                    if (n < n_sum) {
+                        const float bn = bias[n], mu = out_mu[n], sd = out_sd[n], ob = obs[n];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float dv = fmaf(sd, acc[t][c][r] + bn, mu) - ob;
+                            sq[r] = fmaf(dv, dv, sq[r]);
+                        }
+                    }
+                }
+                // sum over the 16 lanes that hold the same rows, fixed tree
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int o = 8; o >= 1; o >>= 1) sq[r] += __shfl_xor(sq[r], o, 16);
+                if (col == 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t row = r0 + wr + 16 * t + rowq + r;
+                        if (row < M) {
+                            const float d = sqrtf(sq[r] / (float)n_sum);
+                            if (dist) dist[row] = d;
+                            keep[row] = (d <= tol) ? 1 : 0;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+size_t mlp_fused_lds_bytes() { return (size_t)(MLP_RT * MLP_HP + 2 * 256 * MLP_WP) * sizeof(uint16_t); }
+int64_t mlp_w16_count() { return MLP_W16_TOTAL; }
+
+hipError_t launch_pack_w16(const float* P, uint16_t* W16, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_w16, dim3((unsigned)((MLP_W16_TOTAL + 255) / 256)), dim3(256), 0, st, P, W16);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_fused(int mode, int64_t M, const float* X, const uint16_t* W16, const float* P, float* Y,
+                            const float* out_mu, const float* out_sd, const float* obs, int n_sum, float tol,
+                            float* dist, uint8_t* keep, hipStream_t st)
+{
+    if (M <= 0) return hipSuccess;
+    const size_t lds = mlp_fused_lds_bytes();
+    static bool attr[2] = {false, false};
+    if (!attr[mode != 0]) {
+        hipError_t e = mode == 0 ? hipFuncSetAttribute((const void*)k_mlp_fused<0>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                                 : hipFuncSetAttribute((const void*)k_mlp_fused<1>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr[mode != 0] = true;
+    }
+    const dim3 grid((unsigned)((M + MLP_RT - 1) / MLP_RT));
+    if (mode == 0)
+        hipLaunchKernelGGL(k_mlp_fused<0>, grid, dim3(256), lds, st, M, X, W16, P, Y, out_mu, out_sd, obs, n_sum, tol,
+                           dist, keep);
+    else
+        hipLaunchKernelGGL(k_mlp_fused<1>, grid, dim3(256), lds, st, M, X, W16, P, Y, out_mu, out_sd, obs, n_sum, tol,
+                           dist, keep);
+    return hipGetLastError();
+}
+
 }  // namespace swim
