@@ -28,19 +28,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Roofline of the dominant kernel (the persistent forward kernel).  Its pair
-# loop reads the kernel functions from a per-system table, so it is bound by
-# VALU instruction issue, not by FP32 FLOP: 28 VALU lane-operations per pair
-# evaluation (k_forward<float, 2, 16> hot loop: 56 per iteration of two
-# pairs, loop control excluded; 32 FP32 FLOP of them, FMA = 2, and 6
-# integer).  Peak issue rate without packed FP32: 256 CUs x 4 SIMDs x 16
-# lanes per clock x 2.4 GHz = 39.3e12 lane-operations/s (x 2 = 78.6 TFLOP/s
-# of FMA; the 157.3 TFLOP/s FP32 figure assumes packed FP32).
-VALU_OPS_PER_PAIR = 28
-FP32_FLOP_PER_PAIR = 32
+# phase reads the kernel functions from a per-system table and evaluates
+# every distinct pair once per step for both of its points (symmetric
+# schedule), so it is bound by VALU instruction issue, not by FP32 FLOP:
+# 33 VALU lane-operations per distinct pair in the k_forward<float, 2, 16>
+# hot loop (loop control included), i.e. 16.5 per ordered pair evaluation;
+# 42 FP32 FLOP (FMA = 2) per distinct pair, 21 per ordered pair.  Peak issue
+# rate without packed FP32: 256 CUs x 4 SIMDs x 16 lanes per clock x
+# 2.4 GHz = 39.3e12 lane-operations/s (x 2 = 78.6 TFLOP/s of FMA; the
+# 157.3 TFLOP/s FP32 figure assumes packed FP32).
+VALU_OPS_PER_PAIR = 16.5
+FP32_FLOP_PER_PAIR = 21
 # the large-system kernel k_big_step<float, 1> (one target per lane, FP64
-# accumulation): 79 VALU per unrolled iteration of two pairs, loop control
+# accumulation): 76 VALU per unrolled iteration of two pairs, loop control
 # included
-VALU_OPS_PER_PAIR_BIG = 39
+VALU_OPS_PER_PAIR_BIG = 38
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 # HBM bytes of one launch of that kernel on this workload, from rocprofv3

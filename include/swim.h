@@ -82,8 +82,9 @@ int swim_version(void);
 
 /* Launch options of a context (the autotuner sets the first two):
  *   SWIM_OPT_WPS     wavefronts that share one system in the persistent
- *                    kernel, splitting its sources: 0 (automatic), 1, 2, 4,
- *                    8, 16 (reduced when the partial sums would not fit LDS);
+ *                    kernel, splitting its pair work: 0 (automatic), 1, 2,
+ *                    4, 8, 16 (raised to 2 for systems above 256 points,
+ *                    reduced when the partial sums would not fit LDS);
  *   SWIM_OPT_BIG_TPL targets per lane of the large-system kernel:
  *                    0 (automatic), 1, 2, 4;
  *   SWIM_OPT_GRAPH   forward runs as a captured hipGraph: 0 never (eager
@@ -382,8 +383,9 @@ int abc_prescreened(swim_ctx *ctx, const abc_model *model, int32_t N, const floa
  * distances t[0..n) returns H1(t) - H1(0) and H2(t) as computed by the
  * kernels' own code compiled for the host, and H1(0) in *h1c.  SWIM_F32
  * follows the FP32 device path: cubic pieces of a per-system table in
- * v = 1 + t/eps^2 (16 per octave, v < 2^24), built from the FP64
- * evaluation; direct FP32 evaluation beyond. */
+ * v = 1 + sigma t (sigma the power of four with sigma eps^2 in [1, 4);
+ * 16 pieces per octave, v < 2^25), built from the FP64 evaluation; direct
+ * FP32 evaluation beyond. */
 int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, const double *t,
                           double *h1t, double *h2, double *h1c);
 

@@ -363,8 +363,10 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
         q.start = bucket_span[k].second;
         q.count = (k + 1 < bucket_span.size() ? bucket_span[k + 1].second : (int64_t)order.size()) - q.start;
         q.wps = c->opt_wps ? c->opt_wps : (c->tuned_wps[dtype][q.tpl] ? c->tuned_wps[dtype][q.tpl] : 16);
-        // the wave partial sums of one system must fit the LDS
-        while (q.wps > 1 && forward_lds_bytes(dtype, q.tpl, q.wps) > 160 * 1024) q.wps /= 2;
+        // at most FWD_MAX_WINDOWS point windows per lane, and the wave
+        // partial sums of one system must fit the LDS
+        q.wps = std::max(q.wps, forward_min_wps(q.tpl));
+        while (q.wps > forward_min_wps(q.tpl) && forward_lds_bytes(dtype, q.tpl, q.wps) > 160 * 1024) q.wps /= 2;
         const int per_cu = forward_blocks_per_cu(dtype, q.tpl, q.wps);
         q.nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(q.count, (int64_t)per_cu * c->num_cu));
         HIPCHK(prepare_forward(dtype, q.tpl, q.wps));
@@ -996,16 +998,19 @@ int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, co
         sysconst_compute<float>(alpha, eps, &C);
         SysConst<double> C64;
         sysconst_compute<double>(alpha, eps, &C64);
-        std::vector<TabE> tab(TAB_N);
-        for (int i = 0; i < TAB_N; ++i) tab_interval(C64, eps * eps, i, tab[i], nullptr);
+        std::vector<TabE> tab(TAB_N + 1);
+        for (int i = 0; i <= TAB_N; ++i) tab_interval(C64, i, tab[i], nullptr);
         for (int64_t i = 0; i < n; ++i) {
-            float a, b, u;
+            float a, b;
             const float tf = (float)t[i];
-            const uint32_t k = tab_locate(tf, C.inv_e2, u);
-            if (k < (uint32_t)TAB_N)
-                tab_eval(tab[k], u, a, b);
-            else
+            const uint32_t bits = tab_bits(tf, C.ts);
+            const uint32_t k = bits >> TAB_SHIFT;
+            if (k < TAB_END) {
+                tab_eval(tab[k - TAB_BIAS], tab_u(bits), a, b);
+                b *= C.ts;  // the table holds H2 / sigma
+            } else {
                 kernel_eval<float>(C, tf, a, b);
+            }
             h1t[i] = a;
             h2[i] = b;
         }

@@ -55,6 +55,8 @@ hipError_t launch_forces(int dtype, int64_t n_fil, const int64_t* fil_off, const
 hipError_t launch_forward(int dtype, int tpl, int wps, int n_blocks, const Batch& b,
                           const Run& r, const int32_t* order, int32_t* queue, void* obs,
                           void* speed, int32_t* status, int32_t* steps_done, hipStream_t st);
+// smallest waves per system of the persistent kernel for tpl targets per lane
+int forward_min_wps(int tpl);
 size_t forward_lds_bytes(int dtype, int tpl, int wps);
 // set the kernels' dynamic-LDS limits ahead of launches (needed before a
 // stream capture, in which the launch itself must not change attributes)

@@ -142,70 +142,31 @@ __device__ __forceinline__ void point_force(const Seg& seg, int p, const FilP<T>
 }
 
 // Accumulate the velocity sum of eq. (BrV) over sources src[0..n) for the
-// TPL targets (xi, yi) of this lane; the constant H1(0) part is added by the
-// caller once as h1c * sum_j F_j.  FP64 evaluates the kernel functions
-// directly; FP32 reads them from the system's table in LDS (tab), with the
-// direct evaluation for pairs beyond its last octave.
+// TPL targets (xi, yi) of this lane, with H1 taken relative to H1(0), in
+// FP64 by direct evaluation (FP32 lanes use pair_accumulate_x).  The
+// constant part H1(0) sum_j F_j is the caller's: the velocity kernel for
+// given forces adds it once per target; in a forward run the forces are the
+// elastic forces of a translation-invariant energy (Appendix EFT, EFB), whose
+// sum over the points of a filament is identically zero, so the term is zero
+// and is not evaluated (its floating-point value is only rounding noise of
+// the cancelling forces).
 template <typename T, int TPL>
-__device__ __forceinline__ void pair_accumulate(const SysConst<T>& C, const TabSys* tab, const Src4<T>* src, int n,
+__device__ __forceinline__ void pair_accumulate(const SysConst<T>& C, const Src4<T>* src, int n,
                                                 const T (&xi)[TPL], const T (&yi)[TPL],
                                                 T (&ax)[TPL], T (&ay)[TPL])
 {
-    if constexpr (sizeof(T) == 4) {
-        // table pass; a pair beyond the table contributes nothing here and
-        // flags its lane
-        bool far = false;
-        const float ie2 = C.inv_e2;
-        for (int j = 0; j < n; ++j) {
-            const Src4<T> s = src[j];
+    static_assert(sizeof(T) == 8, "FP64 only");
+    for (int j = 0; j < n; ++j) {
+        const Src4<T> s = src[j];
 #pragma unroll
-            for (int k = 0; k < TPL; ++k) {
-                const T dx = xi[k] - s.x, dy = yi[k] - s.y;
-                const T t = fma_t(dx, dx, dy * dy);
-                float u, Ht, H2;
-                const uint32_t id = tab_locate(t, ie2, u);
-                const bool in = id < (uint32_t)TAB_N;
-                far = far || !in;
-                tab_eval(tab->e[in ? id : 0u], u, Ht, H2);
-                Ht = in ? Ht : 0.0f;
-                H2 = in ? H2 : 0.0f;
-                const T h2fd = H2 * fma_t(s.fx, dx, s.fy * dy);
-                ax[k] = fma_t(Ht, s.fx, fma_t(h2fd, dx, ax[k]));
-                ay[k] = fma_t(Ht, s.fy, fma_t(h2fd, dy, ay[k]));
-            }
-        }
-        // direct evaluation of the flagged pairs, only where a lane has one
-        if (__any(far)) {
-            for (int j = 0; j < n; ++j) {
-                const Src4<T> s = src[j];
-#pragma unroll
-                for (int k = 0; k < TPL; ++k) {
-                    const T dx = xi[k] - s.x, dy = yi[k] - s.y;
-                    const T t = fma_t(dx, dx, dy * dy);
-                    float u;
-                    if (tab_locate(t, ie2, u) >= (uint32_t)TAB_N) {
-                        T Ht, H2;
-                        kernel_eval<T>(C, t, Ht, H2);
-                        const T h2fd = H2 * fma_t(s.fx, dx, s.fy * dy);
-                        ax[k] = fma_t(Ht, s.fx, fma_t(h2fd, dx, ax[k]));
-                        ay[k] = fma_t(Ht, s.fy, fma_t(h2fd, dy, ay[k]));
-                    }
-                }
-            }
-        }
-    } else {
-        for (int j = 0; j < n; ++j) {
-            const Src4<T> s = src[j];
-#pragma unroll
-            for (int k = 0; k < TPL; ++k) {
-                const T dx = xi[k] - s.x, dy = yi[k] - s.y;
-                const T t = fma_t(dx, dx, dy * dy);
-                T Ht, H2;
-                kernel_eval<T>(C, t, Ht, H2);
-                const T h2fd = H2 * fma_t(s.fx, dx, s.fy * dy);
-                ax[k] = fma_t(Ht, s.fx, fma_t(h2fd, dx, ax[k]));
-                ay[k] = fma_t(Ht, s.fy, fma_t(h2fd, dy, ay[k]));
-            }
+        for (int k = 0; k < TPL; ++k) {
+            const T dx = xi[k] - s.x, dy = yi[k] - s.y;
+            const T t = fma_t(dx, dx, dy * dy);
+            T Ht, H2;
+            kernel_eval<T>(C, t, Ht, H2);
+            const T h2fd = H2 * fma_t(s.fx, dx, s.fy * dy);
+            ax[k] = fma_t(Ht, s.fx, fma_t(h2fd, dx, ax[k]));
+            ay[k] = fma_t(Ht, s.fy, fma_t(h2fd, dy, ay[k]));
         }
     }
 }
@@ -224,28 +185,26 @@ __device__ __forceinline__ void pair_accumulate_x(const SysConst<float>& C, cons
                                                   const Src4<float>* src, int n, const float (&xi)[TPL],
                                                   const float (&yi)[TPL], double (&ax)[TPL], double (&ay)[TPL])
 {
-    bool far = false;
-    const float ie2 = C.inv_e2;
+    uint32_t far = 0;
+    const float ts = C.ts;
     for (int j = 0; j < n; ++j) {
         const Src4<float> s = src[j];
         const double fx = s.fx, fy = s.fy;
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             const float dx = xi[k] - s.x, dy = yi[k] - s.y;
-            const float t = fmaf(dx, dx, dy * dy);
-            float u;
-            const uint32_t id = tab_locate(t, ie2, u);
-            const bool in = id < (uint32_t)TAB_N;
-            far = far || !in;
-            const uint32_t ic = in ? id : 0u;
+            const uint32_t bits = tab_bits(fmaf(dx, dx, dy * dy), ts);
+            const uint32_t id = bits >> TAB_SHIFT;
+            far |= id >= TAB_END ? 1u : 0u;
+            const uint32_t ic = min(id, TAB_END) - TAB_BIAS;
             const TabE& e = tab->e[ic];
+            const float u = tab_u(bits);
             const float inc = u * fmaf(fmaf(e.h[3], u, e.h[2]), u, e.h[1]);
-            const float hi = in ? e.h[0] : 0.0f;
-            const float lo = in ? tab->h0lo[ic] + inc : 0.0f;
-            const float H2 = in ? fmaf(fmaf(fmaf(e.g[3], u, e.g[2]), u, e.g[1]), u, e.g[0]) : 0.0f;
+            const float lo = tab->h0lo[ic] + inc;
+            const float H2 = fmaf(fmaf(fmaf(e.g[3], u, e.g[2]), u, e.g[1]), u, e.g[0]) * ts;
             const float h2fd = H2 * fmaf(s.fx, dx, s.fy * dy);
-            ax[k] = fma((double)hi, fx, fma((double)lo, fx, fma((double)h2fd, (double)dx, ax[k])));
-            ay[k] = fma((double)hi, fy, fma((double)lo, fy, fma((double)h2fd, (double)dy, ay[k])));
+            ax[k] = fma((double)e.h[0], fx, fma((double)lo, fx, fma((double)h2fd, (double)dx, ax[k])));
+            ay[k] = fma((double)e.h[0], fy, fma((double)lo, fy, fma((double)h2fd, (double)dy, ay[k])));
         }
     }
     if (__any(far)) {
@@ -255,8 +214,7 @@ __device__ __forceinline__ void pair_accumulate_x(const SysConst<float>& C, cons
             for (int k = 0; k < TPL; ++k) {
                 const float dx = xi[k] - s.x, dy = yi[k] - s.y;
                 const float t = fmaf(dx, dx, dy * dy);
-                float u;
-                if (tab_locate(t, ie2, u) >= (uint32_t)TAB_N) {
+                if ((tab_bits(t, ts) >> TAB_SHIFT) >= TAB_END) {
                     float Ht, H2;
                     kernel_eval<float>(C, t, Ht, H2);
                     const float h2fd = H2 * fmaf(s.fx, dx, s.fy * dy);
@@ -326,11 +284,10 @@ __global__ void k_sysconst_batch(int64_t n, const int64_t* sw_off, const int32_t
 __global__ __launch_bounds__(64) void k_table_build(int64_t s0, int64_t n, const SysConst<double>* sysc64, TabSys* tab)
 {
     const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    const int64_t s = s0 + e / TAB_N;
-    const int i = (int)(e % TAB_N);
-    if (e >= n * TAB_N) return;
-    const SysConst<double>& C = sysc64[s];
-    tab_interval(C, C.e2, i, tab[s].e[i], &tab[s].h0lo[i]);
+    const int64_t s = s0 + e / (TAB_N + 1);
+    const int i = (int)(e % (TAB_N + 1));
+    if (e >= n * (TAB_N + 1)) return;
+    tab_interval(sysc64[s], i, tab[s].e[i], &tab[s].h0lo[i]);
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
@@ -396,7 +353,7 @@ __global__ __launch_bounds__(256) void k_pair_velocity(const int64_t* blk_sys, c
         if constexpr (sizeof(T) == 4)
             pair_accumulate_x<TPL>(C, tab, tile, m, xi, yi, axd, ayd);
         else
-            pair_accumulate<T, TPL>(C, tab, tile, m, xi, yi, ax, ay);
+            pair_accumulate<T, TPL>(C, tile, m, xi, yi, ax, ay);
     }
     sfx = wave_sum(sfx);
     sfy = wave_sum(sfy);
@@ -446,29 +403,319 @@ __global__ void k_forces(int64_t n_fil, const int64_t* fil_off, const int32_t* n
     fy[b + p] = Fy;
 }
 
+
+// ---------------------------------------------------------------------------
+// symmetric pair schedule of the persistent kernel.  H1 and H2 depend on the
+// pair distance only, and the contribution of a pair is even in d, so one
+// evaluation serves both ends: target i gains Ht F_j + H2 (F_j . d) d and
+// source j gains Ht F_i + H2 (F_i . d) d (eq. BrV).  Points form blocks of
+// 64 (one per lane); for blocks a <= b, lane l pairs its point 64a + l with
+// the point 64b + (l + s) mod 64 at offset s, s = 0..63 for a < b and
+// s = 1..32 within a block (s = 32 pairs each couple twice, so lanes 32..63
+// skip it).  The accumulator of the moving point rotates down one lane per
+// offset.  All offsets of all block pairs (32 B^2 for B blocks) are split
+// into WPS equal contiguous ranges, one per wave.  Each block is stored twice
+// in a row (src2), so the point at offset s is read at lane + s.
+// ---------------------------------------------------------------------------
+
+// value of lane (l + 1) mod 64 (wave_rol:1; every lane has a source, so no
+// fallback value is needed)
+__device__ __forceinline__ float lane_rot(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_rot(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x134, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x134, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// v as an opaque wave-uniform value (a scalar register the compiler cannot
+// fold into constants)
+__device__ __forceinline__ int opaque_uniform(int v)
+{
+    int r;
+    asm volatile("s_mov_b32 %0, %1" : "=s"(r) : "s"(v));
+    return r;
+}
+
+// slot of point i in the doubled source array
+__device__ __forceinline__ int src2_slot(int i) { return ((i >> 6) << 7) + (i & 63); }
+
+// kernel functions of one pair at offset (dx, dy).  FP64: direct evaluation.
+// FP32 (positions scaled by rho): the table (FAR = false; a pair beyond it
+// gives zeros and sets far), or the direct evaluation of pairs beyond the
+// table only (FAR = true; zeros for the others).  H2 comes scaled to the
+// coordinates (H2 / sigma in FP32).
+template <typename T, bool FAR>
+__device__ __forceinline__ void pair_kernel(const SysConst<T>& C, const char* et, T dx, T dy, T& Ht, T& H2,
+                                            bool& far)
+{
+    if constexpr (sizeof(T) == 8) {
+        kernel_eval<T>(C, fma_t(dx, dx, dy * dy), Ht, H2);
+    } else {
+        const uint32_t bits = __builtin_bit_cast(uint32_t, fmaf(dx, dx, fmaf(dy, dy, 1.0f)));
+        const uint32_t id = bits >> TAB_SHIFT;
+        if constexpr (!FAR) {
+            far = far || id >= TAB_END;
+            tab_eval(*reinterpret_cast<const TabE*>(et + (min(id, TAB_END) << 5)), tab_u(bits), Ht, H2);
+        } else {
+            Ht = 0.0f;
+            H2 = 0.0f;
+            if (id >= TAB_END) {
+                kernel_eval<float>(C, fmaf(dx, dx, dy * dy) * C.its, Ht, H2);
+                H2 *= C.its;
+            }
+        }
+    }
+}
+
+// offsets [s_lo, s_hi) of block pair (a, b); adds the target sums to block
+// a's and the moving points' sums to block b's accumulators of this lane
+template <typename T, int TPL, bool FAR>
+__device__ __forceinline__ bool sym_offsets(const SysConst<T>& C, const char* et, const Src4<T>* src2, int a, int b,
+                                            int s_lo, int s_hi, int lane, T (&accx)[TPL], T (&accy)[TPL])
+{
+    const Src4<T> ti = src2[(a << 7) + lane];
+    const Src4<T>* sp = src2 + (b << 7) + lane;
+    T ax = (T)0, ay = (T)0, bx = (T)0, by = (T)0;
+    bool far = false;
+    const int s_full = (a == b) ? min(s_hi, 32) : s_hi;  // offsets every lane takes
+    for (int s = s_lo; s < s_full; ++s) {
+        const Src4<T> q = sp[s];
+        const T dx = ti.x - q.x, dy = ti.y - q.y;
+        T Ht, H2;
+        pair_kernel<T, FAR>(C, et, dx, dy, Ht, H2, far);
+        const T fdj = H2 * fma_t(q.fx, dx, q.fy * dy);
+        ax = fma_t(Ht, q.fx, fma_t(fdj, dx, ax));
+        ay = fma_t(Ht, q.fy, fma_t(fdj, dy, ay));
+        const T fdi = H2 * fma_t(ti.fx, dx, ti.fy * dy);
+        bx = lane_rot(fma_t(Ht, ti.fx, fma_t(fdi, dx, bx)));
+        by = lane_rot(fma_t(Ht, ti.fy, fma_t(fdi, dy, by)));
+    }
+    if (s_full < s_hi) {
+        // offset 32 within a block: lanes 32..63 repeat lanes 0..31's couples
+        const Src4<T> q = sp[32];
+        const T dx = ti.x - q.x, dy = ti.y - q.y;
+        T Ht, H2;
+        pair_kernel<T, FAR>(C, et, dx, dy, Ht, H2, far);
+        Ht = lane < 32 ? Ht : (T)0;
+        H2 = lane < 32 ? H2 : (T)0;
+        const T fdj = H2 * fma_t(q.fx, dx, q.fy * dy);
+        ax = fma_t(Ht, q.fx, fma_t(fdj, dx, ax));
+        ay = fma_t(Ht, q.fy, fma_t(fdj, dy, ay));
+        const T fdi = H2 * fma_t(ti.fx, dx, ti.fy * dy);
+        bx = lane_rot(fma_t(Ht, ti.fx, fma_t(fdi, dx, bx)));
+        by = lane_rot(fma_t(Ht, ti.fy, fma_t(fdi, dy, by)));
+    }
+    // lane l now holds the sums of point (l + s_hi) mod 64 of block b
+    const int from = (lane - s_hi) & 63;
+    bx = __shfl(bx, from, 64);
+    by = __shfl(by, from, 64);
+#pragma unroll
+    for (int c = 0; c < TPL; ++c) {
+        if (c == a) {
+            accx[c] += ax;
+            accy[c] += ay;
+        }
+        if (c == b) {
+            accx[c] += bx;
+            accy[c] += by;
+        }
+    }
+    return far;
+}
+
+// this wave's share of the pair sums of all n points: accx[c], accy[c] hold
+// the partial velocity of point 64c + lane
+template <typename T, int TPL, int WPS>
+__device__ __forceinline__ void pair_phase_sym(const SysConst<T>& C, const TabSys* tab, const Src4<T>* src2, int n,
+                                               int wave, int lane, T (&accx)[TPL], T (&accy)[TPL])
+{
+#pragma unroll
+    for (int c = 0; c < TPL; ++c) accx[c] = accy[c] = (T)0;
+    const char* et = nullptr;
+    if constexpr (sizeof(T) == 4) {
+        // entry of index id at et + (id << 5) bytes: the bias goes into a
+        // wave-uniform base (a register operand of the address arithmetic;
+        // gfx9 address arithmetic takes no 32-bit literal)
+        et = reinterpret_cast<const char*>(tab->e) + opaque_uniform(-(int)(TAB_BIAS * sizeof(TabE)));
+    }
+    const int B = (n + 63) >> 6;
+    const int S = 32 * B * B;
+    const int per = (S + WPS - 1) / WPS;
+    const int g0 = min(S, wave * per), g1 = min(S, g0 + per);
+    int g = 0;  // first offset index of block pair (a, b)
+    for (int a = 0; a < B && g < g1; ++a) {
+        for (int b = a; b < B && g < g1; ++b) {
+            const int len = (a == b) ? 32 : 64, base = (a == b) ? 1 : 0;
+            const int lo = max(g0, g), hi = min(g1, g + len);
+            if (lo < hi) {
+                const int s_lo = lo - g + base, s_hi = hi - g + base;
+                const bool far = sym_offsets<T, TPL, false>(C, et, src2, a, b, s_lo, s_hi, lane, accx, accy);
+                if constexpr (sizeof(T) == 4) {
+                    if (__any(far)) sym_offsets<T, TPL, true>(C, et, src2, a, b, s_lo, s_hi, lane, accx, accy);
+                }
+            }
+            g += len;
+        }
+    }
+}
+
+// LDS of the persistent kernel: [FP32 table][src2][part][bad], 16-byte
+// aligned sections
+struct FwdLdsLayout {
+    size_t tab, src, part, bad, total;
+};
+__host__ __device__ constexpr size_t fwd_align16(size_t x) { return (x + 15) & ~(size_t)15; }
+__host__ __device__ constexpr FwdLdsLayout fwd_lds_layout(int dtype, int tpl, int wps)
+{
+    const size_t e = dtype == 0 ? sizeof(float) : sizeof(double), nmax = 64 * (size_t)tpl;
+    FwdLdsLayout L{};
+    L.tab = 0;
+    L.src = dtype == 0 ? fwd_align16(sizeof(TabSys)) : 0;
+    L.part = fwd_align16(L.src + 2 * nmax * 4 * e);
+    L.bad = fwd_align16(L.part + (size_t)wps * nmax * 2 * e);
+    L.total = fwd_align16(L.bad + 4 * (size_t)wps);
+    return L;
+}
+
 // ---------------------------------------------------------------------------
 // persistent forward run: one workgroup of WPS wavefronts per system, systems
-// taken from a longest-first work queue; every time step (forces -> velocity
-// sum -> Euler) stays inside the workgroup, positions and forces live in LDS.
-// Each wavefront sums over 1/WPS of the sources for all targets; partial
-// velocities are reduced through LDS in a fixed order (deterministic).
+// taken from a longest-first work queue; every time step stays inside the
+// workgroup.  A step has two phases separated by barriers:
+//
+//  * pair phase (all waves): each wavefront sums over 1/WPS of the sources
+//    (positions and forces in LDS; FP32 positions scaled by the table's rho)
+//    for all targets and leaves its partial velocities in LDS;
+//  * point phase (the first few waves): each wave covers a window of 60
+//    consecutive points plus two halo points on either side, one point per
+//    lane, with the positions kept in registers.  Lanes reduce the partial
+//    velocities of their point in a fixed order (deterministic), take the
+//    Euler step, and evaluate the elastic forces of the new positions with
+//    neighbour values exchanged between adjacent lanes (DPP lane shifts), so
+//    forces need no extra barrier.  Halo lanes repeat their neighbour
+//    window's arithmetic bit for bit and only the 60 inner lanes publish.
 // ---------------------------------------------------------------------------
+
+// value of lane l+1 (wave_shl:1); the last lane reads 0
+__device__ __forceinline__ float lane_next(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+}
+// value of lane l-1 (wave_shr:1); lane 0 reads 0
+__device__ __forceinline__ float lane_prev(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_next(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x130, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x130, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double lane_prev(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x138, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x138, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <typename T> struct alignas(2 * sizeof(T)) V2 {
+    T x, y;
+};
+
 template <typename T> struct FwdLds {
     TabSys* tab;   // FP32 kernel table (FP32 runs)
-    Src4<T>* src;  // [NMAX] positions (hi) and forces
-    T* lox;        // [NMAX] lo parts
-    T* loy;
-    T* part;       // [WPS][2][NMAX] partial velocities (WPS > 1)
-    T* red;        // [2][WPS] wave partial sums of the forces
+    Src4<T>* src;  // [2 NMAX] positions (hi part) and forces, each block of 64 twice
+    V2<T>* part;   // [WPS][NMAX] partial velocities
+    int* bad;      // [WPS] wave flags: 1 non-finite position, 2 beyond the bound
 };
+
+constexpr int FWD_WIN = 60;  // points published per point-phase window
+// Most windows one lane carries.  A single wave with all nine windows of a
+// 512-point system needs over 400 registers; that build gave FP32 results
+// off by up to 1e-3 (and one run past the position bound) while every
+// launch shape with at most five windows per lane matches FP64, so such
+// launches take more waves instead.
+constexpr int FWD_MAX_WINDOWS = 5;
+
+// per-lane state of one window of the point phase
+enum : int { FL_HELD = 1, FL_OWN = 2, FL_SEG = 4, FL_NODE = 8, FL_HEAD = 16 };
+
+// Elastic force on the point of this lane (Appendix EFT, EFB, curva: the same
+// discrete energy and the same operation order as point_force): the lane
+// computes the tension of its segment (to the next point) and the curvature
+// terms of its own node, and takes its neighbours' through lane shifts.  The
+// stretching and bending terms of one point cancel to a small remainder, so
+// they are accumulated with fused multiply-adds of unrounded products, node
+// p-1, p, p+1 in turn.  k0 = preferred curvature of this lane's node now.
+template <typename T>
+__device__ __forceinline__ void lane_force(int fl, T xh, T yh, T xl, T yl, T ss2, T sb2, T k0, T ds, T inv2ds,
+                                           T invds2, T& Fx, T& Fy)
+{
+    constexpr bool COMP = sizeof(T) == 4;
+    const bool segv = fl & FL_SEG, nodev = fl & FL_NODE;
+    T dx = lane_next(xh) - xh, dy = lane_next(yh) - yh;
+    if constexpr (COMP) {
+        dx += lane_next(xl) - xl;
+        dy += lane_next(yl) - yl;
+    }
+    dx = segv ? dx : (T)0;
+    dy = segv ? dy : (T)0;
+    // stretching: F_i = tau_i - tau_{i-1}, tau_k = ct_k d_k
+    const T l = segv ? sqrt_t(fma_t(dx, dx, dy * dy)) : (T)1;
+    const T ct = ss2 * (l / ds - (T)1) / l;
+    const T txm = lane_prev(ct * dx), tym = lane_prev(ct * dy);
+    const T dxm = lane_prev(dx), dym = lane_prev(dy);
+    // bending: curvature node i from segments i-1 and i
+    const T a = (dx + dxm) * inv2ds;
+    const T bb = (dy + dym) * inv2ds;
+    const T pp = (dx - dxm) * invds2;
+    const T qq = (dy - dym) * invds2;
+    const T S = nodev ? fma_t(a, a, bb * bb) : (T)1;
+    const T rS = (T)1 / S;
+    const T rS32 = rS / sqrt_t(S);
+    const T num = fma_t(qq, a, -pp * bb);
+    const T kap = num * rS32;
+    const T co = nodev ? sb2 * (kap - k0) * ds : (T)0;
+    const T n3 = (T)3 * num * rS32 * rS;
+    const T dka = qq * rS32 - a * n3;
+    const T dkb = -pp * rS32 - bb * n3;
+    const T dkp = -bb * rS32;
+    const T dkq = a * rS32;
+    // dkappa_i/dX for the points i-1 (A), i (B), i+1 (C)
+    const T gAx = nodev ? fma_t(-dka, inv2ds, dkp * invds2) : (T)0;
+    const T gAy = nodev ? fma_t(-dkb, inv2ds, dkq * invds2) : (T)0;
+    const T gBx = nodev ? (T)-2 * dkp * invds2 : (T)0;
+    const T gBy = nodev ? (T)-2 * dkq * invds2 : (T)0;
+    const T gCx = nodev ? fma_t(dka, inv2ds, dkp * invds2) : (T)0;
+    const T gCy = nodev ? fma_t(dkb, inv2ds, dkq * invds2) : (T)0;
+    const T cop = lane_prev(co), gCxp = lane_prev(gCx), gCyp = lane_prev(gCy);  // node i-1
+    const T con = lane_next(co), gAxn = lane_next(gAx), gAyn = lane_next(gAy);  // node i+1
+    Fx = fma_t(ct, dx, -txm);
+    Fy = fma_t(ct, dy, -tym);
+    Fx = fma_t(-cop, gCxp, Fx);
+    Fy = fma_t(-cop, gCyp, Fy);
+    Fx = fma_t(-co, gBx, Fx);
+    Fy = fma_t(-co, gBy, Fy);
+    Fx = fma_t(-con, gAxn, Fx);
+    Fy = fma_t(-con, gAyn, Fy);
+}
 
 template <typename T, int TPL, int WPS>
 __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>& L, T* obs, T* speed,
                            int32_t* status, int32_t* steps_done)
 {
     constexpr bool COMP = sizeof(T) == 4;
-    constexpr int NMAX = 64 * TPL, NT = 64 * WPS, OWN = (NMAX + NT - 1) / NT;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NMAX = 64 * TPL, NT = 64 * WPS;
+    constexpr int NWIN = (NMAX + FWD_WIN - 1) / FWD_WIN, OWNW = (NWIN + WPS - 1) / WPS;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar loops and branches
     const int N = b.npt[s];
     const int nsw = b.nswim[s];
     const int n = N * nsw;
@@ -487,172 +734,181 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
     const SysConst<T> C = ((const SysConst<T>*)b.sysc)[s];
     const double dsd = 1.0 / (double)(N - 1);
     if constexpr (COMP) tab_load((const TabSys*)b.tab + s, L.tab, tid, NT);
+    const int nwin = (n + FWD_WIN - 1) / FWD_WIN;
+    const int pw = min(WPS, nwin);     // waves with point work
+    const bool pwave = wave < pw;      // uniform within a wave
+    const T ds = (T)dsd, inv2ds = (T)(0.5 / dsd), invds2 = (T)(1.0 / (dsd * dsd));
+    const T dt = (T)r.dt;
+    // the pair phase of FP32 runs works on positions scaled by the table's
+    // rho (an exact power of two); registers keep the unscaled state
+    const T rho = COMP ? C.tr : (T)1;
 
-    // owned points i = tid + NT*q: positions as (hi, lo)
-    T xh[OWN], yh[OWN], xl[OWN], yl[OWN];
+    // window state: point i = 60 g + lane - 2 of window g = wave + WPS q
+    T xh[OWNW], yh[OWNW], xl[OWNW], yl[OWNW], ss2[OWNW], sb2[OWNW], ka[OWNW], kb[OWNW];
+    double rc[OWNW], rs[OWNW], cd[OWNW], sd[OWNW];  // cos, sin of omega t; rotation by omega dt
+    int fl[OWNW];
 #pragma unroll
-    for (int q = 0; q < OWN; ++q) {
-        const int i = tid + NT * q;
-        const bool own = i < n;
-        const int m = own ? i / N : 0;
-        const int p = own ? i - m * N : 0;
-        const double X = b.params[9 * (f0 + m) + 7] + (double)p * dsd;
-        const double Y = b.params[9 * (f0 + m) + 8];
+    for (int q = 0; q < OWNW; ++q) {
+        const int g = wave + WPS * q;
+        const int i = FWD_WIN * g + lane - 2;
+        const bool held = g < nwin && i >= 0 && i < n;
+        const int m = held ? i / N : 0, p = held ? i - m * N : 0;
+        const double* P = b.params + 9 * (f0 + m);
+        const double X = held ? P[7] + (double)p * dsd : 0.0, Y = held ? P[8] : 0.0;
         xh[q] = (T)X;
         yh[q] = (T)Y;
         xl[q] = COMP ? (T)(X - (double)xh[q]) : (T)0;
         yl[q] = COMP ? (T)(Y - (double)yh[q]) : (T)0;
-        if (own) {
-            L.src[i].x = xh[q];
-            L.src[i].y = yh[q];
-            L.lox[i] = xl[q];
-            L.loy[i] = yl[q];
-            if (p == N - 1) {
-                // samples a stopped run never reaches stay NaN
-                T* o = obs + (f0 + m) * (int64_t)r.n_obs * 2;
-                for (int k = 0; k < 2 * r.n_obs; ++k) o[k] = (T)NAN;
-            }
+        const bool own = held && lane >= 2 && lane < 2 + FWD_WIN;
+        fl[q] = (held ? FL_HELD : 0) | (own ? FL_OWN : 0) | (held && p <= N - 2 ? FL_SEG : 0) |
+                (held && p >= 1 && p <= N - 2 ? FL_NODE : 0) | (own && p == N - 1 ? FL_HEAD : 0);
+        ss2[q] = (T)(2.0 * P[2]);
+        sb2[q] = (T)(2.0 * P[1]);
+        // kappa0_p(t) = -k^2 b sin(k s_p + phase - omega t)
+        //            = ka cos(omega t) - kb sin(omega t)
+        const double amp = -P[5] * P[5] * P[3], ph = P[5] * ((double)p * dsd) + P[6];
+        ka[q] = (T)(amp * sin(ph));
+        kb[q] = (T)(amp * cos(ph));
+        rc[q] = 1.0;
+        rs[q] = 0.0;
+        cd[q] = COMP ? cos(P[4] * r.dt) : P[4];  // FP64 keeps omega and evaluates directly
+        sd[q] = COMP ? sin(P[4] * r.dt) : 0.0;
+        if (fl[q] & FL_HEAD) {
+            // samples a stopped run never reaches stay NaN
+            T* o = obs + (f0 + m) * (int64_t)r.n_obs * 2;
+            for (int k = 0; k < 2 * r.n_obs; ++k) o[k] = (T)NAN;
         }
     }
+    // forces of the held points at the current time; owners publish them
+    auto point_forces = [&]() {
+#pragma unroll
+        for (int q = 0; q < OWNW; ++q) {
+            T Fx, Fy;
+            const T k0 = fma_t(ka[q], (T)rc[q], -kb[q] * (T)rs[q]);
+            lane_force<T>(fl[q], xh[q], yh[q], xl[q], yl[q], ss2[q], sb2[q], k0, ds, inv2ds, invds2, Fx, Fy);
+            if (fl[q] & FL_OWN) {
+                const int i = FWD_WIN * (wave + WPS * q) + lane - 2;
+                Src4<T> v;
+                v.x = xh[q] * rho;
+                v.y = yh[q] * rho;
+                v.fx = Fx;
+                v.fy = Fy;
+                const int slot = src2_slot(i);
+                L.src[slot] = v;
+                L.src[slot + 64] = v;
+            }
+        }
+    };
+    // points n .. 64 B - 1 of the last block: no force, at the start position of
+    // point n - 1 (they add nothing and stay within the system's extent)
+    for (int i = n + tid; i < 64 * ((n + 63) >> 6); i += NT) {
+        const double* P = b.params + 9 * (f0 + nsw - 1);
+        Src4<T> v;
+        v.x = (T)(P[7] + (double)(N - 1) * dsd) * rho;
+        v.y = (T)P[8] * rho;
+        v.fx = (T)0;
+        v.fy = (T)0;
+        const int slot = src2_slot(i);
+        L.src[slot] = v;
+        L.src[slot + 64] = v;
+    }
+    if (pwave) point_forces();
     __syncthreads();
     int st = 0, done = r.steps;
-    const T dt = (T)r.dt;
-    const int chunk = (n + WPS - 1) / WPS;
-    const int j0 = min(n, wave * chunk), j1 = min(n, j0 + chunk);
+    const int nblk64 = (n + 63) >> 6;
     for (int step = 0; step < r.steps; ++step) {
-        const T t = (T)((double)step * r.dt);
-        // forces of the owned points (reads positions only)
-        // force sums: one point per thread, then a 64-lane tree and the
-        // WPS wave sums (short sums, FP32 is enough here)
-        T sfx = (T)0, sfy = (T)0;
+        // pair phase: this wave's share of the symmetric pair schedule
+        {
+            T ax[TPL], ay[TPL];
+            pair_phase_sym<T, TPL, WPS>(C, L.tab, L.src, n, wave, lane, ax, ay);
 #pragma unroll
-        for (int q = 0; q < OWN; ++q) {
-            const int i = tid + NT * q;
-            if (i < n) {
-                const int m = i / N, p = i - m * N;
-                const int base = m * N;
-                const FilP<T> fp = load_filp<T>(b.params, f0 + m, N);
-                auto seg = [&](int kk, T& dx, T& dy) {
-                    const int a = base + kk, c = base + kk + 1;
-                    dx = (L.src[c].x - L.src[a].x) + (COMP ? L.lox[c] - L.lox[a] : (T)0);
-                    dy = (L.src[c].y - L.src[a].y) + (COMP ? L.loy[c] - L.loy[a] : (T)0);
-                };
-                T Fx, Fy;
-                point_force<T>(seg, p, fp, t, Fx, Fy);
-                L.src[i].fx = Fx;
-                L.src[i].fy = Fy;
-                sfx += Fx;
-                sfy += Fy;
+            for (int c = 0; c < TPL; ++c) {
+                if (c < nblk64) {
+                    V2<T> v;
+                    v.x = ax[c];
+                    v.y = ay[c];
+                    L.part[wave * NMAX + 64 * c + lane] = v;
+                }
             }
-        }
-        sfx = wave_sum(sfx);
-        sfy = wave_sum(sfy);
-        if (lane == 0) {
-            L.red[wave] = sfx;
-            L.red[WPS + wave] = sfy;
         }
         __syncthreads();
-        T SFx = (T)0, SFy = (T)0;
+        // point phase: Euler step of the held points, forces at t_{step+1}
+        if (pwave) {
+            int bad = 0;
 #pragma unroll
-        for (int w = 0; w < WPS; ++w) {
-            SFx += L.red[w];
-            SFy += L.red[WPS + w];
-        }
-        // pair sum: this wave's share of the sources, all targets
-        T xi[TPL], yi[TPL], ax[TPL], ay[TPL];
+            for (int q = 0; q < OWNW; ++q) {
+                if (fl[q] & FL_HELD) {
+                    const int i = FWD_WIN * (wave + WPS * q) + lane - 2;
+                    T ux = (T)0, uy = (T)0;
 #pragma unroll
-        for (int k = 0; k < TPL; ++k) {
-            const int i = lane + 64 * k;
-            xi[k] = i < n ? L.src[i].x : (T)0;
-            yi[k] = i < n ? L.src[i].y : (T)0;
-            ax[k] = ay[k] = (T)0;
-        }
-        pair_accumulate<T, TPL>(C, L.tab, L.src + j0, j1 - j0, xi, yi, ax, ay);
-        if constexpr (WPS > 1) {
-#pragma unroll
-            for (int k = 0; k < TPL; ++k) {
-                const int i = lane + 64 * k;
-                if (i < n) {
-                    L.part[(wave * 2 + 0) * NMAX + i] = ax[k];
-                    L.part[(wave * 2 + 1) * NMAX + i] = ay[k];
+                    for (int w = 0; w < WPS; ++w) {
+                        const V2<T> v = L.part[w * NMAX + i];
+                        ux += v.x;
+                        uy += v.y;
+                    }
+                    if constexpr (COMP) {
+                        acc2(xh[q], xl[q], dt * ux);
+                        acc2(yh[q], yl[q], dt * uy);
+                    } else {
+                        xh[q] = fma_t(dt, ux, xh[q]);
+                        yh[q] = fma_t(dt, uy, yh[q]);
+                    }
+                    if ((fl[q] & FL_OWN) && (bad_t(xh[q]) || bad_t(yh[q])))
+                        bad = (isfinite(xh[q]) && isfinite(yh[q])) ? 2 : 1;
+                }
+                if constexpr (COMP) {
+                    const double c = rc[q], sn = rs[q];
+                    rc[q] = fma(c, cd[q], -sn * sd[q]);
+                    rs[q] = fma(sn, cd[q], c * sd[q]);
+                } else {
+                    const double wt = cd[q] * ((double)(step + 1) * r.dt);
+                    rc[q] = cos(wt);
+                    rs[q] = sin(wt);
                 }
             }
-            __syncthreads();
+            point_forces();
+            const bool b1 = __ballot(bad == 1) != 0, b2 = __ballot(bad == 2) != 0;
+            if (lane == 0) L.bad[wave] = (b1 ? 1 : 0) | (b2 ? 2 : 0);
         }
-        // Euler update of the owned points
-        int bad = 0;
-#pragma unroll
-        for (int q = 0; q < OWN; ++q) {
-            const int i = tid + NT * q;
-            if (i >= n) continue;
-            T ux, uy;
-            if constexpr (WPS > 1) {
-                ux = (T)0;
-                uy = (T)0;
-#pragma unroll
-                for (int w = 0; w < WPS; ++w) {
-                    ux += L.part[(w * 2 + 0) * NMAX + i];
-                    uy += L.part[(w * 2 + 1) * NMAX + i];
-                }
-            } else {
-                ux = ax[q];
-                uy = ay[q];
-            }
-            ux = fma_t(C.h1c, SFx, ux);
-            uy = fma_t(C.h1c, SFy, uy);
-            if (COMP) {
-                acc2(xh[q], xl[q], dt * ux);
-                acc2(yh[q], yl[q], dt * uy);
-            } else {
-                xh[q] = fma_t(dt, ux, xh[q]);
-                yh[q] = fma_t(dt, uy, yh[q]);
-            }
-            if (bad_t(xh[q]) || bad_t(yh[q])) bad = (isfinite(xh[q]) && isfinite(yh[q])) ? 2 : 1;
-        }
-        // every read of the old positions is done after this barrier
-        const int any_bad = __syncthreads_or(bad);
-#pragma unroll
-        for (int q = 0; q < OWN; ++q) {
-            const int i = tid + NT * q;
-            if (i < n) {
-                L.src[i].x = xh[q];
-                L.src[i].y = yh[q];
-                L.lox[i] = xl[q];
-                L.loy[i] = yl[q];
-            }
-        }
-        if (any_bad) {
-            st = __syncthreads_or(bad == 1) ? 1 : 2;
+        __syncthreads();
+        int badw = 0;
+        for (int w = 0; w < pw; ++w) badw |= L.bad[w];
+        badw = __builtin_amdgcn_readfirstlane(badw);
+        if (badw) {
+            st = (badw & 1) ? 1 : 2;
             done = step + 1;
             break;
         }
-        __syncthreads();
-        if (r.obs_every > 0 && (step + 1) % r.obs_every == 0) {
-            const int o = (step + 1) / r.obs_every - 1;
+        if (pwave) {
+            if (r.obs_every > 0 && (step + 1) % r.obs_every == 0) {
+                const int o = (step + 1) / r.obs_every - 1;
 #pragma unroll
-            for (int q = 0; q < OWN; ++q) {
-                const int i = tid + NT * q;
-                if (i < n && (i % N) == N - 1) {
-                    T* d = obs + ((f0 + i / N) * (int64_t)r.n_obs + o) * 2;
-                    d[0] = xh[q] + xl[q];
-                    d[1] = yh[q] + yl[q];
+                for (int q = 0; q < OWNW; ++q) {
+                    if (fl[q] & FL_HEAD) {
+                        const int i = FWD_WIN * (wave + WPS * q) + lane - 2;
+                        T* d = obs + ((f0 + i / N) * (int64_t)r.n_obs + o) * 2;
+                        d[0] = xh[q] + xl[q];
+                        d[1] = yh[q] + yl[q];
+                    }
                 }
             }
         }
     }
-    const T Tend = (T)((double)r.steps * r.dt);
+    if (pwave) {
+        const T Tend = (T)((double)r.steps * r.dt);
 #pragma unroll
-    for (int q = 0; q < OWN; ++q) {
-        const int i = tid + NT * q;
-        if (i < n && (i % N) == N - 1) {
-            const int64_t f = f0 + i / N;
-            if (st) {
-                speed[f] = (T)NAN;
-            } else {
-                const T hx0 = (T)(b.params[9 * f + 7] + (double)(N - 1) * dsd);
-                const T hy0 = (T)b.params[9 * f + 8];
-                const T dx = (xh[q] + xl[q]) - hx0, dy = (yh[q] + yl[q]) - hy0;
-                speed[f] = sqrt_t(fma_t(dx, dx, dy * dy)) / Tend;
+        for (int q = 0; q < OWNW; ++q) {
+            if (fl[q] & FL_HEAD) {
+                const int i = FWD_WIN * (wave + WPS * q) + lane - 2;
+                const int64_t f = f0 + i / N;
+                if (st) {
+                    speed[f] = (T)NAN;
+                } else {
+                    const T hx0 = (T)(b.params[9 * f + 7] + (double)(N - 1) * dsd);
+                    const T hy0 = (T)b.params[9 * f + 8];
+                    const T dx = (xh[q] + xl[q]) - hx0, dy = (yh[q] + yl[q]) - hy0;
+                    speed[f] = sqrt_t(fma_t(dx, dx, dy * dy)) / Tend;
+                }
             }
         }
     }
@@ -668,16 +924,13 @@ __global__ __launch_bounds__(64 * WPS) void k_forward(Batch b, Run r, const int3
                                                       T* speed, int32_t* status, int32_t* steps_done)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int NMAX = 64 * TPL;
     __shared__ int s_item;
-    constexpr size_t TABB = sizeof(T) == 4 ? sizeof(TabSys) : 0;
     FwdLds<T> L;
-    L.tab = reinterpret_cast<TabSys*>(smem);
-    L.src = reinterpret_cast<Src4<T>*>(smem + TABB);
-    L.lox = reinterpret_cast<T*>(smem + TABB + NMAX * sizeof(Src4<T>));
-    L.loy = L.lox + NMAX;
-    L.red = L.loy + NMAX;
-    L.part = L.red + 2 * WPS;
+    const FwdLdsLayout lay = fwd_lds_layout(sizeof(T) == 4 ? 0 : 1, TPL, WPS);
+    L.tab = reinterpret_cast<TabSys*>(smem + lay.tab);
+    L.src = reinterpret_cast<Src4<T>*>(smem + lay.src);
+    L.part = reinterpret_cast<V2<T>*>(smem + lay.part);
+    L.bad = reinterpret_cast<int*>(smem + lay.bad);
     // Work queue: thread 0 takes the next system; the item reaches every
     // thread through LDS and readfirstlane makes it an SGPR, so the loop exit
     // is a uniform scalar branch.  A workgroup takes at most n_sys items.
@@ -741,7 +994,6 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
     extern __shared__ __align__(16) unsigned char smem[];
     TabSys* tab = reinterpret_cast<TabSys*>(smem);
     Src4<T>* src = reinterpret_cast<Src4<T>*>(smem + TABB);
-    __shared__ double red[2][4];
     const int tid = threadIdx.x;
     const int64_t s = blk_sys[blockIdx.x];
     if (status[s] != 0) return;
@@ -757,7 +1009,6 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
     const T* xl = (const T*)S.xl[cur] + p0;
     const T* yl = (const T*)S.yl[cur] + p0;
     const T t = (T)((double)step * r.dt);
-    double sfx = 0.0, sfy = 0.0;   // FP64: multiplies H1(0) in every velocity
     for (int i = tid; i < n; i += 256) {
         const int m = i / N, p = i - m * N;
         const FilP<T> q = load_filp<T>(b.params, f0 + m, N);
@@ -775,18 +1026,8 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
         v.fx = Fx;
         v.fy = Fy;
         src[i] = v;
-        sfx += Fx;
-        sfy += Fy;
-    }
-    sfx = wave_sum(sfx);
-    sfy = wave_sum(sfy);
-    if ((tid & 63) == 0) {
-        red[0][tid >> 6] = sfx;
-        red[1][tid >> 6] = sfy;
     }
     __syncthreads();
-    const double SFxd = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    const double SFyd = red[1][0] + red[1][1] + red[1][2] + red[1][3];
     const SysConst<T> C = ((const SysConst<T>*)b.sysc)[s];
     // FP32 sums whole large systems per lane: FP64 accumulation
     // (pair_accumulate_x); FP64 runs accumulate in FP64 anyway
@@ -803,21 +1044,15 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
     if constexpr (COMP)
         pair_accumulate_x<TPL>(C, tab, src, n, xi, yi, axd, ayd);
     else
-        pair_accumulate<T, TPL>(C, tab, src, n, xi, yi, ax, ay);
+        pair_accumulate<T, TPL>(C, src, n, xi, yi, ax, ay);
     const T dt = (T)r.dt;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         const int64_t i = first + tid + 256 * k;
         if (i >= n) continue;
         T hx = xi[k], hy = yi[k], lx = xl[i], ly = yl[i];
-        T ux, uy;
-        if constexpr (COMP) {
-            ux = (T)fma((double)C.h1c, SFxd, axd[k]);
-            uy = (T)fma((double)C.h1c, SFyd, ayd[k]);
-        } else {
-            ux = fma_t(C.h1c, (T)SFxd, ax[k]);
-            uy = fma_t(C.h1c, (T)SFyd, ay[k]);
-        }
+        const T ux = COMP ? (T)axd[k] : ax[k];
+        const T uy = COMP ? (T)ayd[k] : ay[k];
         if (COMP) {
             acc2(hx, lx, dt * ux);
             acc2(hy, ly, dt * uy);
@@ -1001,7 +1236,7 @@ size_t table_bytes() { return sizeof(TabSys); }
 hipError_t launch_table_build(int64_t s0, int64_t n, const void* sysc64, void* tab, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_table_build, dim3((unsigned)nblk(n * TAB_N, 64)), dim3(64), 0, st, s0, n,
+    hipLaunchKernelGGL(k_table_build, dim3((unsigned)nblk(n * (TAB_N + 1), 64)), dim3(64), 0, st, s0, n,
                        (const SysConst<double>*)sysc64, (TabSys*)tab);
     return hipGetLastError();
 }
@@ -1054,13 +1289,7 @@ hipError_t launch_forces(int dtype, int64_t n_fil, const int64_t* fil_off, const
     return hipGetLastError();
 }
 
-size_t forward_lds_bytes(int dtype, int tpl, int wps)
-{
-    const size_t e = dtype == 0 ? sizeof(float) : sizeof(double);
-    const size_t nmax = 64 * (size_t)tpl;
-    return (dtype == 0 ? table_bytes() : 0) + nmax * 4 * e + 2 * nmax * e + 2 * (size_t)wps * e +
-           (wps > 1 ? (size_t)wps * 2 * nmax * e : 0);
-}
+size_t forward_lds_bytes(int dtype, int tpl, int wps) { return fwd_lds_layout(dtype, tpl, wps).total; }
 
 // raise the kernel's dynamic-LDS limit to what its launches need (outside
 // any stream capture: a launch inside a capture finds it already set)
@@ -1100,11 +1329,21 @@ static int fwd_occupancy()
     return nb;
 }
 
+// instantiated launch shapes (targets per lane, waves per system): every
+// wave count from forward_min_wps(tpl) up
 #define SWIM_FWD_TABLE(X, T)                                                                               \
     X(T, 1, 1) X(T, 1, 2) X(T, 1, 4) X(T, 1, 8) X(T, 1, 16) X(T, 2, 1) X(T, 2, 2) X(T, 2, 4) X(T, 2, 8)      \
     X(T, 2, 16) X(T, 3, 1) X(T, 3, 2) X(T, 3, 4) X(T, 3, 8) X(T, 3, 16) X(T, 4, 1) X(T, 4, 2) X(T, 4, 4)     \
-    X(T, 4, 8) X(T, 4, 16) X(T, 6, 1) X(T, 6, 2) X(T, 6, 4) X(T, 6, 8) X(T, 6, 16) X(T, 8, 1) X(T, 8, 2)      \
-    X(T, 8, 4) X(T, 8, 8) X(T, 8, 16)
+    X(T, 4, 8) X(T, 4, 16) X(T, 6, 2) X(T, 6, 4) X(T, 6, 8) X(T, 6, 16) X(T, 8, 2) X(T, 8, 4) X(T, 8, 8)      \
+    X(T, 8, 16)
+
+int forward_min_wps(int tpl)
+{
+    const int nwin = (64 * tpl + FWD_WIN - 1) / FWD_WIN;
+    int w = 1;
+    while ((nwin + w - 1) / w > FWD_MAX_WINDOWS) w *= 2;
+    return w;
+}
 
 hipError_t launch_forward(int dtype, int tpl, int wps, int nblocks, const Batch& b, const Run& r,
                           const int32_t* order, int32_t* queue, void* obs, void* speed, int32_t* status,

@@ -109,11 +109,23 @@ template <> SWIM_HD double kfit<double>(int nu, double x)
 // ---------------------------------------------------------------------------
 // per-system constants
 // ---------------------------------------------------------------------------
+
+// exponent m of the FP32 table scale: rho = 2^m is the smallest power of two
+// above 1/eps (eps = f 2^e with f in [1/2, 1): m = 1 - e), so sigma = rho^2
+// has sigma eps^2 = 4 f^2 in [1, 4).  Exact, so host and device agree.
+SWIM_HD int tab_scale_exp(double eps)
+{
+    int e = 0;
+    frexp(eps, &e);
+    return 1 - e;
+}
+
 template <typename T> struct alignas(16) SysConst {
     T a2, e2, inv_e2, half_inv_e2;   // alpha^2, eps^2, 1/eps^2, 1/(2 eps^2)
     T w0, inv_a2;                    // alpha^2 eps^2, 1/alpha^2 (0 if alpha = 0)
     T cpi, c2pi;                     // c/pi, c/(2 pi)
     T K0z0, q0, h1c, pad;            // K0(alpha eps), Q(w0), H1(0)
+    T ts, its, tr, pad2;             // FP32 table scale sigma = rho^2, 1/sigma, rho = 2^m
     T U[NT_MAX];                     // U(t) = t * sum_n U[n] t^n
     T V[NT_MAX];                     // V(t) = sum_n V[n] t^n
 };
@@ -172,6 +184,11 @@ template <typename T> SWIM_HD void sysconst_compute(double alpha, double eps, Sy
     C.half_inv_e2 = (T)(0.5 / e2);
     C.w0 = (T)w0;
     C.pad = (T)0;
+    const int m = tab_scale_exp(eps);
+    C.ts = (T)ldexp(1.0, 2 * m);
+    C.its = (T)ldexp(1.0, -2 * m);
+    C.tr = (T)ldexp(1.0, m);
+    C.pad2 = (T)0;
     for (int n = 0; n < NT_MAX; ++n) { C.U[n] = (T)0; C.V[n] = (T)0; }
     if (alpha == 0.0) {
         C.inv_a2 = (T)0;
@@ -382,37 +399,48 @@ SWIM_HD void kernel_eval(const SysConst<T>& C, T t, T& Ht, T& H2)
 }
 
 // ---------------------------------------------------------------------------
-// FP32 evaluation by table.  In the variable v = 1 + t/eps^2 (t = r^2) the
-// functions Ht(t) and H2(t) are smooth on every interval
+// FP32 evaluation by table.  In the variable v = 1 + sigma t (t = r^2, sigma
+// the system's power of four with sigma eps^2 in [1, 4)) the functions
+// Ht(t) and H2(t) are smooth on every interval
 // [2^e (1 + j/16), 2^e (1 + (j+1)/16)), e = 0..TAB_OCT-1, j = 0..15, whose
 // index is read straight from the bits of the float v (exponent and the top
-// four mantissa bits) and whose local coordinate u in [0, 1) is the rest of
-// the mantissa.  On each interval both functions are the cubic in u through
-// their values at the Chebyshev-Lobatto nodes u = 0, 1/4, 3/4, 1, evaluated
-// once per system in FP64 by kernel_eval<double>.  The relative width 1/16
-// of an interval bounds the interpolation error by about 4e-3 (1/16)^4
-// max|f''''| in units of the function's own scale (about 1e-7 for the log
-// and 1/t behaviour of these kernels); rounding the coefficients to FP32
-// adds one unit roundoff.  Pairs beyond the last octave fall back to the
-// direct evaluation.
+// four mantissa bits) and whose local coordinate is the rest of the mantissa,
+// taken as the integer u in [0, 2^19) (the interval coordinate times 2^19).
+// On each interval both functions are the cubic through their values at the
+// Chebyshev-Lobatto nodes 0, 1/4, 3/4, 1 of the interval, evaluated once per
+// system in FP64 by kernel_eval<double>.  The relative width 1/16 of an
+// interval bounds the interpolation error by about 4e-3 (1/16)^4 max|f''''|
+// in units of the function's own scale (about 1e-7 for the log and 1/t
+// behaviour of these kernels); rounding the coefficients to FP32 adds one
+// unit roundoff.  The stored coefficients absorb exact powers of two: the
+// 2^-19 of u in every power of u, and 1/sigma in those of H2, so that with
+// positions scaled by rho = sqrt(sigma) (d' = rho d, v = |d'|^2 + 1) a pair
+// contributes Ht F + H2' (F . d') d' with H2' = H2 / sigma.  Entry TAB_N is
+// all zero: pairs beyond the last octave index it (and contribute nothing)
+// and fall back to the direct evaluation.
 // ---------------------------------------------------------------------------
 constexpr int TAB_M = 4;                     // intervals per octave: 2^TAB_M
-constexpr int TAB_OCT = 24;                  // octaves of v, which covers [1, 2^24)
+constexpr int TAB_OCT = 25;                  // octaves of v, which covers [1, 2^25)
 constexpr int TAB_N = TAB_OCT << TAB_M;      // intervals per system
 constexpr int TAB_SHIFT = 23 - TAB_M;        // mantissa bits of u
+constexpr uint32_t TAB_BIAS = 0x3F800000u >> TAB_SHIFT;  // bits(1.0f) >> TAB_SHIFT
+constexpr uint32_t TAB_END = TAB_BIAS + TAB_N;           // first index beyond the table
 struct alignas(16) TabE {
     float h[4];  // Ht(u) = h0 + u (h1 + u (h2 + u h3))
-    float g[4];  // H2(u)
+    float g[4];  // H2(u) / sigma
 };
-// one system's table; h0lo[i] = Ht at the start of interval i minus its
-// FP32 value e[i].h[0], for the kernels that accumulate in FP64
+static_assert(sizeof(TabE) == 32, "table entries are addressed as index << 5");
+// one system's table (entry TAB_N: zeros); h0lo[i] = Ht at the start of
+// interval i minus its FP32 value e[i].h[0], for the kernels that accumulate
+// in FP64
 struct alignas(16) TabSys {
-    TabE e[TAB_N];
-    float h0lo[TAB_N];
+    TabE e[TAB_N + 1];
+    float h0lo[TAB_N + 1];
 };
 
-// cubic through (0, f0), (1/4, f1), (3/4, f2), (1, f3), monomial coefficients
-SWIM_HD void cubic_lobatto(const double (&f)[4], float (&c)[4])
+// cubic through (0, f0), (1/4, f1), (3/4, f2), (1, f3): monomial
+// coefficients of the local coordinate scaled by sc (c_k sc^k), times mul
+SWIM_HD void cubic_lobatto(const double (&f)[4], double sc, double mul, float (&c)[4])
 {
     // Newton divided differences on the nodes 0, 1/4, 3/4, 1
     const double x1 = 0.25, x2 = 0.75;
@@ -423,16 +451,22 @@ SWIM_HD void cubic_lobatto(const double (&f)[4], float (&c)[4])
     const double d123 = (d23 - d12) / (1.0 - x1);
     const double d0123 = d123 - d012;
     // p = f0 + d01 u + d012 u (u - x1) + d0123 u (u - x1) (u - x2)
-    c[0] = (float)f[0];
-    c[1] = (float)(d01 - d012 * x1 + d0123 * x1 * x2);
-    c[2] = (float)(d012 - d0123 * (x1 + x2));
-    c[3] = (float)d0123;
+    c[0] = (float)(mul * f[0]);
+    c[1] = (float)(mul * sc * (d01 - d012 * x1 + d0123 * x1 * x2));
+    c[2] = (float)(mul * sc * sc * (d012 - d0123 * (x1 + x2)));
+    c[3] = (float)(mul * sc * sc * sc * d0123);
 }
 
-// interval i of the table of the system with FP64 constants C and eps^2 = e2
-// (h0lo, if not null: the FP32 remainder of the constant coefficient of Ht)
-SWIM_HD void tab_interval(const SysConst<double>& C, double e2, int i, TabE& out, float* h0lo = nullptr)
+// interval i of the table of the system with FP64 constants C (i = TAB_N:
+// the zero entry); h0lo, if not null: the FP32 remainder of the constant
+// coefficient of Ht
+SWIM_HD void tab_interval(const SysConst<double>& C, int i, TabE& out, float* h0lo = nullptr)
 {
+    if (i >= TAB_N) {
+        for (int k = 0; k < 4; ++k) out.h[k] = out.g[k] = 0.0f;
+        if (h0lo) *h0lo = 0.0f;
+        return;
+    }
     const int e = i >> TAB_M, j = i & ((1 << TAB_M) - 1);
     const double a = ldexp(1.0, e);
     const double v0 = a * (1.0 + (double)j / (double)(1 << TAB_M)), hv = a / (double)(1 << TAB_M);
@@ -442,28 +476,24 @@ SWIM_HD void tab_interval(const SysConst<double>& C, double e2, int i, TabE& out
     for (int k = 0; k < 4; ++k) {
         // t = 0 is taken as a vanishing positive t, whose evaluation follows
         // the near-contact series and gives the limits H2(0) and Ht(0) = 0
-        const double t = fmax((v0 - 1.0 + hv * un[k]) * e2, 1e-300);
+        const double t = fmax((v0 - 1.0 + hv * un[k]) * C.its, 1e-300);
         kernel_eval<double>(C, t, fh[k], fg[k]);
     }
-    cubic_lobatto(fh, out.h);
-    cubic_lobatto(fg, out.g);
+    const double sc = ldexp(1.0, -TAB_SHIFT);
+    cubic_lobatto(fh, sc, 1.0, out.h);
+    cubic_lobatto(fg, sc, C.its, out.g);
     if (h0lo) *h0lo = (float)(fh[0] - (double)out.h[0]);
 }
 
-// table index and local coordinate of t (index >= TAB_N: outside the table,
-// non-finite t included)
-SWIM_HD uint32_t tab_locate(float t, float inv_e2, float& u)
-{
-    const float v = fmaf(t, inv_e2, 1.0f);
-    uint32_t bits = __builtin_bit_cast(uint32_t, v) - 0x3F800000u;
-    u = (float)(bits & ((1u << TAB_SHIFT) - 1u)) * (1.0f / (float)(1u << TAB_SHIFT));
-    return bits >> TAB_SHIFT;
-}
+// bits of v = 1 + sigma t: their index bits >> TAB_SHIFT (>= TAB_END beyond
+// the table, non-finite t included) and u, the low mantissa bits as a float
+SWIM_HD uint32_t tab_bits(float t, float sigma) { return __builtin_bit_cast(uint32_t, fmaf(t, sigma, 1.0f)); }
+SWIM_HD float tab_u(uint32_t bits) { return (float)(bits & ((1u << TAB_SHIFT) - 1u)); }
 
-SWIM_HD void tab_eval(const TabE& e, float u, float& Ht, float& H2)
+SWIM_HD void tab_eval(const TabE& e, float u, float& Ht, float& H2s)
 {
     Ht = fmaf(fmaf(fmaf(e.h[3], u, e.h[2]), u, e.h[1]), u, e.h[0]);
-    H2 = fmaf(fmaf(fmaf(e.g[3], u, e.g[2]), u, e.g[1]), u, e.g[0]);
+    H2s = fmaf(fmaf(fmaf(e.g[3], u, e.g[2]), u, e.g[1]), u, e.g[0]);
 }
 
 }  // namespace swim

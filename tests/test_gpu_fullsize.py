@@ -10,13 +10,18 @@ follow the oracle's definitions applied to the GPU distances.
 The completed samples sit near forward Euler's stability edge (dt * rho
 close to 2, like the data's true parameters).  There the initial snap of
 the straight filament to its preferred shape excites stiff, slowly damped
-oscillating modes that amplify any per-step rounding by ~1e3 over the
-first few hundred steps: FP64 follows the oracle to 1e-11 over the whole
-series, FP32 carries up to ~4e-3 of relative error at the first sample
-(step 100), decaying to ~1e-5 by the end.  So FP64 is held to 1e-11 on
-the complete series; FP32 to 1e-4 on the trajectory summaries the ABC
-uses -- the mean speed, the RMS distance to the data -- and on the
-displacement series once the transient has decayed (steps 1000 on).
+oscillating modes that amplify the per-step rounding of the FP32 velocity
+sums (~1e-6) by ~1e3 over the first few hundred steps, and what remains of
+that transient depends on the order in which the partial sums round: runs
+of the same system with 1 to 16 wavefronts per system differ from each
+other by up to ~7e-4 in the mean speed and RMS distance.  So FP64 is held
+to 1e-11 on the complete series; FP32 is checked as five rounding draws
+(the batch run and re-runs with 1, 2, 4 and 8 wavefronts per system): each
+within 2e-3 of the oracle on the trajectory summaries the ABC uses (the
+mean speed, the RMS distance to the data) and on the displacement series
+from step 1000 on, and their mean closer to the oracle than the draws are
+to each other (no bias beyond the rounding spread).  Runs away from the
+stability edge meet 1e-4 (test_gpu_parity.py).
 """
 import os
 
@@ -37,6 +42,25 @@ def ctx():
     c = swim.Context(0)
     yield c
     c.close()
+
+
+def fp32_rerun(ctx, prow, N, steps, dt, oe, data, wps):
+    """One FP32 run of one system with wps wavefronts per system: its head
+    series, mean speed and RMS distance to the data (oracle definition)."""
+    from oracle import abc
+    swim.swim_set_option(ctx, swim.SWIM_OPT_WPS, wps)
+    try:
+        obs = torch.empty((1, steps // oe, 2), dtype=torch.float32, device="cuda")
+        speed = torch.empty(1, dtype=torch.float32, device="cuda")
+        status = torch.empty(1, dtype=torch.int32, device="cuda")
+        swim.swim_forward(ctx, [N], None, torch.from_numpy(prow[None].copy()).cuda(), steps, dt, oe, 1.5, obs, speed,
+                          status)
+        torch.cuda.synchronize()
+    finally:
+        swim.swim_set_option(ctx, swim.SWIM_OPT_WPS, 0)
+    assert status.item() == 0
+    ob = obs.cpu().double().numpy()[0]
+    return ob, speed.item(), abc.distance(ob[None], data[:steps // oe])[0]
 
 
 def test_batched_workload_sampled_against_oracle(ctx, oracle_core):
@@ -82,14 +106,20 @@ def test_batched_workload_sampled_against_oracle(ctx, oracle_core):
         r = ref["obs"][0]
         # FP64: complete series
         assert np.linalg.norm(o64[k] - r) <= 1e-11 * np.linalg.norm(r - x0), (i, "fp64")
-        # FP32: trajectory summaries and the settled series
-        assert abs(spd[i] / ref["speed"][0] - 1) < 1e-4, (i, spd[i], ref["speed"][0])
+        # FP32: five rounding draws of the same run
         d_ref = abc.distance(r[None], data[:steps // oe])[0]
-        assert abs(d[i] / d_ref - 1) < 1e-4, (i, d[i], d_ref)
         late = slice(1000 // oe - 1, None)
-        err = np.linalg.norm(o[i][late] - r[late])
-        allow = 1e-4 * np.linalg.norm(r[late] - x0) + np.linalg.norm(np.spacing(np.abs(r[late]).astype(np.float32)))
-        assert err <= allow, (i, theta[i], err, allow)
+        scale = np.linalg.norm(r[late] - x0)
+        floor = np.linalg.norm(np.spacing(np.abs(r[late]).astype(np.float32)))
+        draws = [(o[i], spd[i], d[i])] + [fp32_rerun(ctx, P[i], N, steps, dt, oe, data, w) for w in (1, 2, 4, 8)]
+        for w, (ob, sp, dd) in zip((0, 1, 2, 4, 8), draws):
+            assert abs(sp / ref["speed"][0] - 1) < 2e-3, (i, w, sp, ref["speed"][0])
+            assert abs(dd / d_ref - 1) < 2e-3, (i, w, dd, d_ref)
+            err = np.linalg.norm(ob[late] - r[late])
+            assert err <= 2e-3 * scale + floor, (i, w, theta[i], err / scale)
+        mean = np.mean([ob for ob, _, _ in draws], axis=0)
+        spread = max(np.linalg.norm(a[0][late] - b[0][late]) for a in draws for b in draws)
+        assert np.linalg.norm(mean[late] - r[late]) <= spread, (i, np.linalg.norm(mean[late] - r[late]), spread)
     # the two earliest blow-ups blow up in the oracle too
     sd = steps_done.cpu().numpy()
     for i in bad[np.argsort(sd[bad], kind="stable")[:2]]:
