@@ -384,7 +384,7 @@ int abc_prescreened(swim_ctx *ctx, const abc_model *model, int32_t N, const floa
  * kernels' own code compiled for the host, and H1(0) in *h1c.  SWIM_F32
  * follows the FP32 device path: cubic pieces of a per-system table in
  * v = 1 + sigma t (sigma the power of four with sigma eps^2 in [1, 4);
- * 16 pieces per octave, v < 2^25), built from the FP64 evaluation; direct
+ * 16 pieces per octave, v < 2^44), built from the FP64 evaluation; direct
  * FP32 evaluation beyond. */
 int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, const double *t,
                           double *h1t, double *h2, double *h1c);

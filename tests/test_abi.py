@@ -58,6 +58,24 @@ def test_host_kernel_values_match_oracle(oracle_core, dtype, tol1, tol2):
             assert e2.max() < tol2, (alpha, N, e2.max())
 
 
+@pytest.mark.parametrize("alpha", [0.0, 0.5, 10.0])
+def test_host_kernel_far_octaves_match_oracle(oracle_core, alpha):
+    """The FP32 table's far octaves (r up to ~2^21 eps, where the pairs of a
+    run that drifts apart before it stops land) against the oracle.  The far
+    field of H2 decays by many orders, so both functions are compared on the
+    scale of a pair's contribution, |Ht| + t |H2| (at least 1/(8 pi))."""
+    for N in [64, 128, 512]:
+        eps = 1.5 / (N - 1)
+        t = (eps ** 2 * np.logspace(4, 12.5, 240)).astype(np.float32).astype(np.float64)
+        H1o, H2o = oracle_core.kernel(alpha, eps, np.concatenate([[0.0], t]))
+        h1t, h2, _ = swim.swim_kernel_eval_host(swim.SWIM_F32, alpha, eps, t)
+        sc = _scale(H1o[1:], H1o[0], t, H2o[1:])
+        e1 = np.abs(h1t - (H1o[1:] - H1o[0])) / sc
+        e2 = np.abs(h2 - H2o[1:]) * t / sc
+        assert e1.max() < 1e-6, (alpha, N, e1.max())
+        assert e2.max() < 5e-6, (alpha, N, e2.max())
+
+
 def test_host_kernel_rejects_out_of_domain():
     with pytest.raises(swim.SwimError):
         swim.swim_kernel_eval_host(swim.SWIM_F64, 100.0, 0.02, np.array([1.0]))
