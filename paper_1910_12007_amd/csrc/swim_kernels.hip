@@ -947,9 +947,12 @@ __global__ __launch_bounds__(64 * WPS) void k_forward(Batch b, Run r, const int3
 
 // ---------------------------------------------------------------------------
 // large systems: one launch per step, targets split over workgroups; every
-// workgroup rebuilds the forces of the whole system into LDS (O(N) work next
-// to its O(N * 256 * TPL) pair work), positions are double-buffered in HBM.
+// workgroup rebuilds the forces of the whole system, tile by tile, into LDS
+// (O(N) work next to its O(N * 256 * TPL) pair work), positions are
+// double-buffered in HBM.  The LDS holds the table and one tile of sources,
+// so any system size fits and two workgroups share a CU.
 // ---------------------------------------------------------------------------
+constexpr int BIG_TILE = 1024;  // sources per LDS tile
 template <typename T>
 __global__ void k_big_init(const int64_t* list, Batch b, BigState S, int32_t* status, T* obs, int32_t n_obs)
 {
@@ -993,7 +996,7 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
     constexpr size_t TABB = COMP ? sizeof(TabSys) : 0;
     extern __shared__ __align__(16) unsigned char smem[];
     TabSys* tab = reinterpret_cast<TabSys*>(smem);
-    Src4<T>* src = reinterpret_cast<Src4<T>*>(smem + TABB);
+    Src4<T>* src = reinterpret_cast<Src4<T>*>(smem + TABB);  // [BIG_TILE]
     const int tid = threadIdx.x;
     const int64_t s = blk_sys[blockIdx.x];
     if (status[s] != 0) return;
@@ -1009,25 +1012,6 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
     const T* xl = (const T*)S.xl[cur] + p0;
     const T* yl = (const T*)S.yl[cur] + p0;
     const T t = (T)((double)step * r.dt);
-    for (int i = tid; i < n; i += 256) {
-        const int m = i / N, p = i - m * N;
-        const FilP<T> q = load_filp<T>(b.params, f0 + m, N);
-        const int base = m * N;
-        auto seg = [&](int kk, T& dx, T& dy) {
-            const int a = base + kk, c = base + kk + 1;
-            dx = (xh[c] - xh[a]) + (COMP ? xl[c] - xl[a] : (T)0);
-            dy = (yh[c] - yh[a]) + (COMP ? yl[c] - yl[a] : (T)0);
-        };
-        T Fx, Fy;
-        point_force<T>(seg, p, q, t, Fx, Fy);
-        Src4<T> v;
-        v.x = xh[i];
-        v.y = yh[i];
-        v.fx = Fx;
-        v.fy = Fy;
-        src[i] = v;
-    }
-    __syncthreads();
     const SysConst<T> C = ((const SysConst<T>*)b.sysc)[s];
     // FP32 sums whole large systems per lane: FP64 accumulation
     // (pair_accumulate_x); FP64 runs accumulate in FP64 anyway
@@ -1036,15 +1020,42 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         const int64_t i = first + tid + 256 * k;
-        xi[k] = i < n ? src[i].x : (T)0;
-        yi[k] = i < n ? src[i].y : (T)0;
+        xi[k] = i < n ? xh[i] : (T)0;
+        yi[k] = i < n ? yh[i] : (T)0;
         ax[k] = ay[k] = (T)0;
         axd[k] = ayd[k] = 0.0;
     }
-    if constexpr (COMP)
-        pair_accumulate_x<TPL>(C, tab, src, n, xi, yi, axd, ayd);
-    else
-        pair_accumulate<T, TPL>(C, src, n, xi, yi, ax, ay);
+    // sources in tiles of BIG_TILE: the forces of a tile's points (read
+    // positions only) into LDS, then every target of this workgroup sums
+    // over them
+    for (int j0 = 0; j0 < n; j0 += BIG_TILE) {
+        const int m_t = min(BIG_TILE, n - j0);
+        if (j0 > 0) __syncthreads();  // the previous tile is consumed
+        for (int jj = tid; jj < m_t; jj += 256) {
+            const int i = j0 + jj;
+            const int m = i / N, p = i - m * N;
+            const FilP<T> q = load_filp<T>(b.params, f0 + m, N);
+            const int base = m * N;
+            auto seg = [&](int kk, T& dx, T& dy) {
+                const int a = base + kk, c = base + kk + 1;
+                dx = (xh[c] - xh[a]) + (COMP ? xl[c] - xl[a] : (T)0);
+                dy = (yh[c] - yh[a]) + (COMP ? yl[c] - yl[a] : (T)0);
+            };
+            T Fx, Fy;
+            point_force<T>(seg, p, q, t, Fx, Fy);
+            Src4<T> v;
+            v.x = xh[i];
+            v.y = yh[i];
+            v.fx = Fx;
+            v.fy = Fy;
+            src[jj] = v;
+        }
+        __syncthreads();
+        if constexpr (COMP)
+            pair_accumulate_x<TPL>(C, tab, src, m_t, xi, yi, axd, ayd);
+        else
+            pair_accumulate<T, TPL>(C, src, m_t, xi, yi, ax, ay);
+    }
     const T dt = (T)r.dt;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -1400,7 +1411,8 @@ hipError_t launch_big_init(int dtype, const int64_t* list, int64_t n_list, const
 
 size_t big_step_lds_bytes(int dtype, int32_t max_pts)
 {
-    return (dtype == 0 ? table_bytes() : 0) + (size_t)max_pts * 4 * (dtype == 0 ? sizeof(float) : sizeof(double));
+    (void)max_pts;  // sources are tiled: any system size
+    return (dtype == 0 ? table_bytes() : 0) + (size_t)BIG_TILE * 4 * (dtype == 0 ? sizeof(float) : sizeof(double));
 }
 
 template <typename T, int TPL>
