@@ -655,7 +655,7 @@ enum : int { FL_HELD = 1, FL_OWN = 2, FL_SEG = 4, FL_NODE = 8, FL_HEAD = 16 };
 // they are accumulated with fused multiply-adds of unrounded products, node
 // p-1, p, p+1 in turn.  k0 = preferred curvature of this lane's node now.
 template <typename T>
-__device__ __forceinline__ void lane_force(int fl, T xh, T yh, T xl, T yl, T ss2, T sb2, T k0, T ds, T inv2ds,
+__device__ __forceinline__ void lane_force(int fl, T xh, T yh, T xl, T yl, T ss2, T sb2, T k0, T ds, T ds2, T inv2ds,
                                            T invds2, T& Fx, T& Fy)
 {
     constexpr bool COMP = sizeof(T) == 4;
@@ -667,9 +667,22 @@ __device__ __forceinline__ void lane_force(int fl, T xh, T yh, T xl, T yl, T ss2
     }
     dx = segv ? dx : (T)0;
     dy = segv ? dy : (T)0;
-    // stretching: F_i = tau_i - tau_{i-1}, tau_k = ct_k d_k
-    const T l = segv ? sqrt_t(fma_t(dx, dx, dy * dy)) : (T)1;
-    const T ct = ss2 * (l / ds - (T)1) / l;
+    // stretching: F_i = tau_i - tau_{i-1}, tau_k = ct_k d_k with
+    // ct = 2 S_s (l/ds - 1) / l.  FP32 forms the strain as
+    // (l^2 - ds^2) / ((l + ds) ds), free of the cancellation in l/ds - 1, with
+    // hardware reciprocals (the divisions are not ill-conditioned); FP64
+    // follows point_force exactly.
+    T ct;
+    if constexpr (COMP) {
+        const float t2 = segv ? fmaf(dx, dx, dy * dy) : 1.0f;
+        const float rl = __builtin_amdgcn_rsqf(t2);
+        const float l = t2 * rl;
+        const float num = fmaf(dx, dx, fmaf(dy, dy, -ds2));
+        ct = ss2 * num * __builtin_amdgcn_rcpf((l + ds) * ds) * rl;
+    } else {
+        const T l = segv ? sqrt_t(fma_t(dx, dx, dy * dy)) : (T)1;
+        ct = ss2 * (l / ds - (T)1) / l;
+    }
     const T txm = lane_prev(ct * dx), tym = lane_prev(ct * dy);
     const T dxm = lane_prev(dx), dym = lane_prev(dy);
     // bending: curvature node i from segments i-1 and i
@@ -678,8 +691,15 @@ __device__ __forceinline__ void lane_force(int fl, T xh, T yh, T xl, T yl, T ss2
     const T pp = (dx - dxm) * invds2;
     const T qq = (dy - dym) * invds2;
     const T S = nodev ? fma_t(a, a, bb * bb) : (T)1;
-    const T rS = (T)1 / S;
-    const T rS32 = rS / sqrt_t(S);
+    T rS, rS32;  // 1/S, S^(-3/2)
+    if constexpr (COMP) {
+        const float rs = __builtin_amdgcn_rsqf(S);
+        rS = rs * rs;
+        rS32 = rS * rs;
+    } else {
+        rS = (T)1 / S;
+        rS32 = rS / sqrt_t(S);
+    }
     const T num = fma_t(qq, a, -pp * bb);
     const T kap = num * rS32;
     const T co = nodev ? sb2 * (kap - k0) * ds : (T)0;
@@ -737,7 +757,7 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
     const int nwin = (n + FWD_WIN - 1) / FWD_WIN;
     const int pw = min(WPS, nwin);     // waves with point work
     const bool pwave = wave < pw;      // uniform within a wave
-    const T ds = (T)dsd, inv2ds = (T)(0.5 / dsd), invds2 = (T)(1.0 / (dsd * dsd));
+    const T ds = (T)dsd, ds2 = (T)(dsd * dsd), inv2ds = (T)(0.5 / dsd), invds2 = (T)(1.0 / (dsd * dsd));
     const T dt = (T)r.dt;
     // the pair phase of FP32 runs works on positions scaled by the table's
     // rho (an exact power of two); registers keep the unscaled state
@@ -785,7 +805,7 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
         for (int q = 0; q < OWNW; ++q) {
             T Fx, Fy;
             const T k0 = fma_t(ka[q], (T)rc[q], -kb[q] * (T)rs[q]);
-            lane_force<T>(fl[q], xh[q], yh[q], xl[q], yl[q], ss2[q], sb2[q], k0, ds, inv2ds, invds2, Fx, Fy);
+            lane_force<T>(fl[q], xh[q], yh[q], xl[q], yl[q], ss2[q], sb2[q], k0, ds, ds2, inv2ds, invds2, Fx, Fy);
             if (fl[q] & FL_OWN) {
                 const int i = FWD_WIN * (wave + WPS * q) + lane - 2;
                 Src4<T> v;
@@ -816,6 +836,7 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
     __syncthreads();
     int st = 0, done = r.steps;
     const int nblk64 = (n + 63) >> 6;
+    int obs_left = r.obs_every, obs_k = 0;  // steps to the next sample, its index
     for (int step = 0; step < r.steps; ++step) {
         // pair phase: this wave's share of the symmetric pair schedule
         {
@@ -839,12 +860,15 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
             for (int q = 0; q < OWNW; ++q) {
                 if (fl[q] & FL_HELD) {
                     const int i = FWD_WIN * (wave + WPS * q) + lane - 2;
+                    // all partials in flight at once, then summed in wave order
+                    V2<T> pv[WPS];
+#pragma unroll
+                    for (int w = 0; w < WPS; ++w) pv[w] = L.part[w * NMAX + i];
                     T ux = (T)0, uy = (T)0;
 #pragma unroll
                     for (int w = 0; w < WPS; ++w) {
-                        const V2<T> v = L.part[w * NMAX + i];
-                        ux += v.x;
-                        uy += v.y;
+                        ux += pv[w].x;
+                        uy += pv[w].y;
                     }
                     if constexpr (COMP) {
                         acc2(xh[q], xl[q], dt * ux);
@@ -871,17 +895,18 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
             if (lane == 0) L.bad[wave] = (b1 ? 1 : 0) | (b2 ? 2 : 0);
         }
         __syncthreads();
-        int badw = 0;
-        for (int w = 0; w < pw; ++w) badw |= L.bad[w];
-        badw = __builtin_amdgcn_readfirstlane(badw);
+        // the point waves' flags, one per lane, combined by ballot (uniform)
+        const int bw = lane < pw ? L.bad[lane] : 0;
+        const int badw = (__ballot(bw & 1) ? 1 : 0) | (__ballot(bw & 2) ? 2 : 0);
         if (badw) {
             st = (badw & 1) ? 1 : 2;
             done = step + 1;
             break;
         }
-        if (pwave) {
-            if (r.obs_every > 0 && (step + 1) % r.obs_every == 0) {
-                const int o = (step + 1) / r.obs_every - 1;
+        if (r.obs_every > 0 && --obs_left == 0) {
+            obs_left = r.obs_every;
+            const int o = obs_k++;
+            if (pwave) {
 #pragma unroll
                 for (int q = 0; q < OWNW; ++q) {
                     if (fl[q] & FL_HEAD) {
