@@ -254,6 +254,60 @@ int abc_step(swim_ctx *ctx, const abc_model *model, const double *data, int32_t 
              uint8_t *accept_out, double *w_out, double *tol_out, int32_t *steps_out);
 
 /* ---------------------------------------------------------------------------
+ * TMCMC (Sec. 2.3, Algorithm TMCMC): transitional Markov chain Monte Carlo
+ * over the batched forward model, the sampler the paper uses.
+ * ------------------------------------------------------------------------- */
+
+/* Gaussian log-likelihood of forward runs, eqs. (likelihood)-(fitness) with
+ * Sigma = sigma_i^2 I over the m = 2 n_obs head coordinates of run i (obs:
+ * [n][n_obs][2] in the run's dtype, data: FP64 [n_obs][2], sigma: FP64 [n],
+ * status: int32 [n], logl: FP64 [n]; all device pointers):
+ * logl_i = -m/2 log(2 pi) - m log(sigma_i) - |D - g_i|^2 / (2 sigma_i^2),
+ * -inf where status_i != 0.  Asynchronous on `stream` (NULL: the context's
+ * stream).  SWIM_EINVAL for null pointers with n > 0 or n_obs < 1. */
+int tmcmc_loglik(swim_ctx *ctx, int32_t dtype, int64_t n, int32_t n_obs, const void *obs, const double *data,
+                 const double *sigma, const int32_t *status, double *logl, void *stream);
+
+typedef struct {
+    double lo[4], hi[4];   /* uniform prior box on (alpha, S_b, S_s, sigma); sigma: noise std, lo[3] > 0 */
+    double cv_target;      /* coefficient of variation of the plausibility weights per stage (1.0) */
+    double cov_scale;      /* b: proposal covariance = b^2 x weighted sample covariance (0.2) */
+    int32_t max_stages;    /* bound on the number of stages */
+} tmcmc_opts;
+
+/* One full TMCMC run (synchronous).  n samples per stage; the forward model
+ * of every sample is one swimmer of N points configured by `model` (its
+ * b, omega, k, steps, obs_every, dt, eps_over_ds, dtype, use_graph; the
+ * prior box comes from `opts`); data: host FP64 [n_obs][2] observed head
+ * positions, n_obs = steps / obs_every.
+ *
+ * Stage j computes the plausibility weights p(D|theta)^dq of the current
+ * samples, dq the largest increment (up to 1 - q_j) whose weights have a
+ * coefficient of variation of at most cv_target (bisection), S_j = their
+ * mean, the normalized weights and b^2 times their weighted covariance.  It
+ * then draws n samples by the weights (multinomial), and runs one Metropolis
+ * chain per drawn sample, as long as the number of times it was drawn, with
+ * target p(D|theta)^q_{j+1} pi(theta) and Gaussian proposals of that
+ * covariance.  Proposals outside the box are rejected without a run; runs
+ * that stop (blow-up) have zero likelihood.  All chains step together: one
+ * batched forward launch per Metropolis step.  The run ends after the
+ * stage at q = 1, or after max_stages stages.
+ *
+ * Outputs (host): theta_out [n][4] and logl_out [n], the final samples and
+ * their log-likelihoods; q_out [max_stages + 1] (q_0 = 0, ...,
+ * q_{n_stages}); *n_stages_out; *log_evidence_out = sum_j log S_j;
+ * accepted_out [max_stages] accepted moves per stage; *runs_out forward runs
+ * (may be NULL); *seconds_out wall time of the forward and likelihood calls
+ * (may be NULL).  Random numbers: Philox with key seed (prior: stream 0 as
+ * abc_prior_draw; resampling of stage j: stream 1000 + 2j; chains of stage
+ * j: stream 1001 + 2j).  SWIM_EINVAL for bad arguments or when no prior
+ * sample has a finite likelihood. */
+int tmcmc_run(swim_ctx *ctx, const abc_model *model, const tmcmc_opts *opts, const double *data, int32_t n_obs,
+              int32_t N, int64_t n, uint64_t seed, double *theta_out, double *logl_out, double *q_out,
+              int32_t *n_stages_out, double *log_evidence_out, int64_t *accepted_out, int64_t *runs_out,
+              double *seconds_out);
+
+/* ---------------------------------------------------------------------------
  * Surrogate of the forward model (not in the paper; prescreens ABC
  * proposals): an MLP 5 -> 256 -> 256 -> 256 -> 256 -> 33 with GELU
  * x Phi(x) on the hidden layers.  Inputs (alpha, ln S_b, ln S_s, b, omega),

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <string>
 #include <thread>
@@ -61,7 +62,8 @@ enum BufId {
     B_OFF, B_SWOFF, B_NPT, B_NSW, B_ORDER, B_LIST, B_BLKS, B_BLKF, B_ALPHA, B_EPS, B_SYSC, B_QUEUE,
     B_PARAMS, B_DATA, B_OBS, B_SPEED, B_STATUS, B_DIST, B_TOL, B_ACC, B_BIG,
     B_MLP_ACT, B_MLP_GRAD, B_MLP_BATCH, B_MLP_IDX, B_MLP_CNT,
-    B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_TAB, B_DONE, B_W16, B_NBUF
+    B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_TAB, B_DONE, B_W16, B_SIGMA, B_LOGL,
+    B_NBUF
 };
 
 // surrogate network: 5 -> 256 x 4 -> 33
@@ -1543,3 +1545,297 @@ int swim_tune_load(swim_ctx* c, const char* path)
 
 }  // extern "C"
 
+
+// ==========================================================================
+// TMCMC (Sec. 2.3, Algorithm TMCMC): transitional Markov chain Monte Carlo
+// over the batched forward model with the Gaussian likelihood of eqs.
+// (likelihood)-(fitness), Sigma = sigma^2 I, sigma the fourth parameter.
+// The host takes the stage decisions in FP64 (tempering exponent, weights,
+// covariance, resampling, Metropolis acceptance); every likelihood is a
+// forward run plus k_gauss_loglik on the device, one batched launch per
+// Metropolis step across all chains.  Random streams (Philox, key = seed):
+// prior stream 0 (abc_prior_draw); resampling draw k of stage j: stream
+// 1000 + 2j, index k, draw 0; chain c, step s (1-based) of stage j: stream
+// 1001 + 2j, index c, draws 3(s-1) .. 3(s-1)+2 (Box-Muller pairs (u0, u1),
+// (u2, u3); u4 decides acceptance).
+// ==========================================================================
+int tmcmc_loglik(swim_ctx* c, int32_t dtype, int64_t n, int32_t n_obs, const void* obs, const double* data,
+                 const double* sigma, const int32_t* status, double* logl, void* stream)
+{
+    TRY(check_ctx(c));
+    TRY(check_dtype(dtype));
+    if (n < 0 || n_obs < 1 || (n > 0 && (!obs || !data || !sigma || !status || !logl)))
+        return fail(SWIM_EINVAL, "bad log-likelihood arguments");
+    HIPCHK(launch_gauss_loglik(dtype, n, n_obs, obs, data, sigma, status, logl, pick(c, stream)));
+    return SWIM_OK;
+}
+
+namespace {
+constexpr int TM_D = 4;          // (alpha, S_b, S_s, sigma)
+constexpr int TM_BISECT = 80;    // bisection steps of the tempering increment
+
+// coefficient of variation (population standard deviation over mean) of the
+// weights exp(dq (l - lmax)) over the finite log-likelihoods
+double tm_weight_cv(const std::vector<double>& l, double lmax, double dq)
+{
+    double s = 0.0;
+    int64_t k = 0;
+    for (double v : l)
+        if (std::isfinite(v)) {
+            s += std::exp(dq * (v - lmax));
+            ++k;
+        }
+    const double m = s / (double)k;
+    double ss = 0.0;
+    for (double v : l)
+        if (std::isfinite(v)) {
+            const double d = std::exp(dq * (v - lmax)) - m;
+            ss += d * d;
+        }
+    return std::sqrt(ss / (double)k) / m;
+}
+
+bool chol_d(const double* A, double* L, int d)
+{
+    for (int i = 0; i < d * d; ++i) L[i] = 0.0;
+    for (int j = 0; j < d; ++j) {
+        double s = A[d * j + j];
+        for (int k = 0; k < j; ++k) s -= L[d * j + k] * L[d * j + k];
+        if (!(s > 0)) return false;
+        L[d * j + j] = std::sqrt(s);
+        for (int i = j + 1; i < d; ++i) {
+            double t = A[d * i + j];
+            for (int k = 0; k < j; ++k) t -= L[d * i + k] * L[d * j + k];
+            L[d * i + j] = t / L[d * j + j];
+        }
+    }
+    return true;
+}
+}  // namespace
+
+int tmcmc_run(swim_ctx* c, const abc_model* m, const tmcmc_opts* o, const double* data, int32_t n_obs, int32_t N,
+              int64_t n, uint64_t seed, double* theta_out, double* logl_out, double* q_out, int32_t* n_stages_out,
+              double* log_evidence_out, int64_t* accepted_out, int64_t* runs_out, double* seconds_out)
+{
+    TRY(check_ctx(c));
+    if (!m || !o || !data || !theta_out || !logl_out || !q_out || !n_stages_out || !log_evidence_out || !accepted_out)
+        return fail(SWIM_EINVAL, "null argument");
+    TRY(check_dtype(m->dtype));
+    if (n < 2) return fail(SWIM_EINVAL, "n must be >= 2");
+    if (m->obs_every < 1 || n_obs != m->steps / m->obs_every) return fail(SWIM_EINVAL, "n_obs must equal steps/obs_every");
+    if (o->max_stages < 1) return fail(SWIM_EINVAL, "max_stages must be >= 1");
+    if (!(o->cv_target > 0 && std::isfinite(o->cv_target))) return fail(SWIM_EINVAL, "cv_target must be > 0");
+    if (!(o->cov_scale > 0 && std::isfinite(o->cov_scale))) return fail(SWIM_EINVAL, "cov_scale must be > 0");
+    for (int d = 0; d < TM_D; ++d)
+        if (!(std::isfinite(o->lo[d]) && std::isfinite(o->hi[d]) && o->hi[d] > o->lo[d]))
+            return fail(SWIM_EINVAL, "bad prior box");
+    if (!(o->lo[3] > 0)) return fail(SWIM_EINVAL, "the prior box of sigma must be positive");
+    {
+        const int32_t Nchk = N;
+        TRY(check_run(1, &Nchk, nullptr, m->steps, m->dt, m->obs_every, m->eps_over_ds));
+    }
+    hipStream_t st = c->stream;
+    const size_t es = m->dtype == SWIM_F32 ? 4 : 8;
+    Run r;
+    r.steps = m->steps;
+    r.dt = m->dt;
+    r.obs_every = m->obs_every;
+    r.n_obs = n_obs;
+    r.eps_over_ds = m->eps_over_ds;
+    double t_eval = 0.0;
+    int64_t runs = 0;
+    // log-likelihoods of k parameter points (rows of TM_D), one batched
+    // forward launch and one likelihood launch
+    std::vector<double> rows, sig;
+    std::vector<int32_t> Nv;
+    auto evaluate = [&](const double* th, int64_t k, double* ll) -> int {
+        if (k == 0) return SWIM_OK;
+        const auto t0 = std::chrono::steady_clock::now();
+        rows.assign((size_t)k * SWIM_NPARAM, 0.0);
+        sig.resize((size_t)k);
+        Nv.assign((size_t)k, N);
+        for (int64_t i = 0; i < k; ++i) {
+            double* P = &rows[(size_t)i * SWIM_NPARAM];
+            P[0] = th[TM_D * i];
+            P[1] = th[TM_D * i + 1];
+            P[2] = th[TM_D * i + 2];
+            P[3] = m->b;
+            P[4] = m->omega;
+            P[5] = m->k;
+            sig[(size_t)i] = th[TM_D * i + 3];
+        }
+        TRY(ensure(c, B_OBS, (size_t)k * n_obs * 2 * es));
+        TRY(ensure(c, B_SPEED, (size_t)k * es));
+        TRY(ensure(c, B_STATUS, (size_t)k * 4));
+        TRY(ensure(c, B_SIGMA, (size_t)k * 8));
+        TRY(ensure(c, B_LOGL, (size_t)k * 8));
+        TRY(begin_uploads(c, rows.size() * 8 + sig.size() * 8 + (size_t)n_obs * 16));
+        TRY(stage(c, rows.data(), rows.size() * 8, B_PARAMS, st));
+        TRY(stage(c, sig.data(), sig.size() * 8, B_SIGMA, st));
+        TRY(stage(c, data, (size_t)n_obs * 16, B_DATA, st));
+        TRY(end_uploads(c, st));
+        const int save_graph = c->opt_graph;
+        if (!m->use_graph) c->opt_graph = 0;
+        const int frc = forward_impl(c, m->dtype, k, Nv.data(), nullptr, (const double*)c->buf[B_PARAMS].p, r,
+                                     c->buf[B_OBS].p, c->buf[B_SPEED].p, (int32_t*)c->buf[B_STATUS].p, nullptr, st);
+        c->opt_graph = save_graph;
+        TRY(frc);
+        HIPCHK(launch_gauss_loglik(m->dtype, k, n_obs, c->buf[B_OBS].p, (const double*)c->buf[B_DATA].p,
+                                   (const double*)c->buf[B_SIGMA].p, (const int32_t*)c->buf[B_STATUS].p,
+                                   (double*)c->buf[B_LOGL].p, st));
+        HIPCHK(hipMemcpyAsync(ll, c->buf[B_LOGL].p, (size_t)k * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        runs += k;
+        t_eval += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return SWIM_OK;
+    };
+    std::vector<double> theta((size_t)n * TM_D), logl((size_t)n);
+    TRY(abc_prior_draw(seed, n, TM_D, o->lo, o->hi, theta.data()));
+    TRY(evaluate(theta.data(), n, logl.data()));
+    q_out[0] = 0.0;
+    double q = 0.0, log_ev = 0.0;
+    int stage_no = 0;
+    std::vector<double> w((size_t)n), cdf((size_t)n), nth((size_t)n * TM_D), nll((size_t)n);
+    std::vector<int64_t> counts((size_t)n);
+    for (; stage_no < o->max_stages && q < 1.0; ++stage_no) {
+        double lmax = -INFINITY;
+        for (double v : logl)
+            if (std::isfinite(v)) lmax = std::max(lmax, v);
+        if (!std::isfinite(lmax)) return fail(SWIM_EINVAL, "no sample has a finite likelihood");
+        // tempering increment: the largest dq with weight CV <= cv_target
+        double dq;
+        if (tm_weight_cv(logl, lmax, 1.0 - q) <= o->cv_target) {
+            dq = 1.0 - q;
+        } else {
+            double lo = 0.0, hi = 1.0 - q;
+            for (int it = 0; it < TM_BISECT; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (tm_weight_cv(logl, lmax, mid) > o->cv_target)
+                    hi = mid;
+                else
+                    lo = mid;
+            }
+            dq = lo;
+        }
+        const double q_next = (dq == 1.0 - q) ? 1.0 : q + dq;
+        dq = q_next - q;  // the increment the weights use: from the rounded q_next
+        // weights, S_j, weighted mean and covariance
+        double W = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            w[i] = std::isfinite(logl[i]) ? std::exp(dq * (logl[i] - lmax)) : 0.0;
+            W += w[i];
+        }
+        log_ev += dq * lmax + std::log(W / (double)n);
+        double mu[TM_D] = {}, cov[TM_D * TM_D] = {}, L[TM_D * TM_D];
+        for (int64_t i = 0; i < n; ++i)
+            for (int d = 0; d < TM_D; ++d) mu[d] += (w[i] / W) * theta[TM_D * i + d];
+        for (int64_t i = 0; i < n; ++i) {
+            const double wb = w[i] / W;
+            for (int d = 0; d < TM_D; ++d)
+                for (int e = 0; e < TM_D; ++e)
+                    cov[TM_D * d + e] += wb * (theta[TM_D * i + d] - mu[d]) * (theta[TM_D * i + e] - mu[e]);
+        }
+        const double b2 = o->cov_scale * o->cov_scale;
+        for (int i = 0; i < TM_D * TM_D; ++i) cov[i] *= b2;
+        if (!chol_d(cov, L, TM_D)) {
+            for (int d = 0; d < TM_D; ++d) cov[TM_D * d + d] += 1e-12 * (o->hi[d] - o->lo[d]) * (o->hi[d] - o->lo[d]);
+            if (!chol_d(cov, L, TM_D)) return fail(SWIM_EINVAL, "proposal covariance is not positive definite");
+        }
+        // resampling: n multinomial draws by the normalized weights
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            acc += w[i] / W;
+            cdf[i] = acc;
+            counts[i] = 0;
+        }
+        for (int64_t k = 0; k < n; ++k) {
+            double u[2];
+            uniforms2(seed, 1000u + 2u * (uint32_t)stage_no, (uint64_t)k, 0, u);
+            int64_t j = std::upper_bound(cdf.begin(), cdf.end(), u[0] * cdf.back()) - cdf.begin();
+            if (j >= n) j = n - 1;
+            ++counts[j];
+        }
+        // Metropolis chains, one per drawn sample, stepped together
+        std::vector<int64_t> start, len, off;
+        int64_t maxlen = 0, pos = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (counts[i]) {
+                start.push_back(i);
+                len.push_back(counts[i]);
+                off.push_back(pos);
+                pos += counts[i];
+                maxlen = std::max(maxlen, counts[i]);
+            }
+        const int64_t nc = (int64_t)start.size();
+        std::vector<double> cur((size_t)nc * TM_D), lcur((size_t)nc), prop, uacc, lprop;
+        std::vector<int64_t> act;
+        for (int64_t ch = 0; ch < nc; ++ch) {
+            for (int d = 0; d < TM_D; ++d) cur[TM_D * ch + d] = theta[TM_D * start[ch] + d];
+            lcur[ch] = logl[start[ch]];
+        }
+        int64_t accepted = 0;
+        const uint32_t cstream = 1001u + 2u * (uint32_t)stage_no;
+        for (int64_t s = 1; s <= maxlen; ++s) {
+            act.clear();
+            for (int64_t ch = 0; ch < nc; ++ch)
+                if (len[ch] >= s) act.push_back(ch);
+            const int64_t na = (int64_t)act.size();
+            prop.resize((size_t)na * TM_D);
+            uacc.resize((size_t)na);
+            std::vector<char> inbox((size_t)na);
+            std::vector<double> batch;
+            for (int64_t a = 0; a < na; ++a) {
+                const int64_t ch = act[a];
+                double u01[2], u23[2], u45[2], z[4];
+                const uint32_t base = 3u * (uint32_t)(s - 1);
+                uniforms2(seed, cstream, (uint64_t)ch, base, u01);
+                uniforms2(seed, cstream, (uint64_t)ch, base + 1, u23);
+                uniforms2(seed, cstream, (uint64_t)ch, base + 2, u45);
+                box_muller(u01[0], u01[1], &z[0], &z[1]);
+                box_muller(u23[0], u23[1], &z[2], &z[3]);
+                uacc[a] = u45[0];
+                bool in = true;
+                for (int d = 0; d < TM_D; ++d) {
+                    double v = cur[TM_D * ch + d];
+                    for (int e = 0; e <= d; ++e) v += L[TM_D * d + e] * z[e];
+                    prop[TM_D * a + d] = v;
+                    in = in && v >= o->lo[d] && v <= o->hi[d];
+                }
+                inbox[a] = in;
+                if (in) batch.insert(batch.end(), &prop[TM_D * a], &prop[TM_D * a] + TM_D);
+            }
+            const int64_t nb = (int64_t)batch.size() / TM_D;
+            lprop.assign((size_t)nb, -INFINITY);
+            TRY(evaluate(batch.data(), nb, lprop.data()));
+            int64_t bi = 0;
+            for (int64_t a = 0; a < na; ++a) {
+                const int64_t ch = act[a];
+                if (inbox[a]) {
+                    const double lp = lprop[bi++];
+                    if (std::log(uacc[a]) < q_next * (lp - lcur[ch])) {
+                        for (int d = 0; d < TM_D; ++d) cur[TM_D * ch + d] = prop[TM_D * a + d];
+                        lcur[ch] = lp;
+                        ++accepted;
+                    }
+                }
+                const int64_t at = off[ch] + s - 1;
+                for (int d = 0; d < TM_D; ++d) nth[TM_D * at + d] = cur[TM_D * ch + d];
+                nll[at] = lcur[ch];
+            }
+        }
+        theta.swap(nth);
+        logl.swap(nll);
+        nth.resize((size_t)n * TM_D);
+        nll.resize((size_t)n);
+        accepted_out[stage_no] = accepted;
+        q = q_next;
+        q_out[stage_no + 1] = q;
+    }
+    memcpy(theta_out, theta.data(), theta.size() * 8);
+    memcpy(logl_out, logl.data(), logl.size() * 8);
+    *n_stages_out = stage_no;
+    *log_evidence_out = log_ev;
+    if (runs_out) *runs_out = runs;
+    if (seconds_out) *seconds_out = t_eval;
+    return SWIM_OK;
+}

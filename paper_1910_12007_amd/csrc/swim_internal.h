@@ -91,6 +91,8 @@ hipError_t launch_abc_distance(int dtype, int64_t n, int32_t n_obs, const void* 
 hipError_t launch_select_kth(int64_t n, const double* v, double q, double* out, hipStream_t st);
 hipError_t launch_accept(int64_t n, const double* dist, const double* tol, uint8_t* acc,
                          hipStream_t st);
+hipError_t launch_gauss_loglik(int dtype, int64_t n, int32_t n_obs, const void* obs, const double* data,
+                               const double* sigma, const int32_t* status, double* logl, hipStream_t st);
 
 // surrogate MLP (swim_mlp.hip)
 hipError_t launch_gemm_bf16(int epi, int M, int N, int K, const float* A, int64_t sam, int64_t sak,

@@ -1235,6 +1235,30 @@ __global__ void k_accept(int64_t n, const double* dist, const double* tol, uint8
     if (i < n) acc[i] = (isfinite(dist[i]) && dist[i] <= *tol) ? 1 : 0;
 }
 
+// Gaussian log-likelihood of each forward run (eqs. likelihood, fitness with
+// Sigma = sigma_i^2 I over the m = 2 n_obs head coordinates, in the order
+// x_0, y_0, x_1, y_1, ...): -m/2 log(2 pi) - m log(sigma_i) - J/2 with
+// J = |D - g|^2 / sigma_i^2, in FP64; -inf for a run that did not complete.
+template <typename T>
+__global__ void k_gauss_loglik(int64_t n, int32_t n_obs, const T* obs, const double* data, const double* sigma,
+                               const int32_t* status, double* logl)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (status[i] != 0) {
+        logl[i] = -INFINITY;
+        return;
+    }
+    const T* g = obs + i * (int64_t)n_obs * 2;
+    double J = 0.0;
+    for (int k = 0; k < 2 * n_obs; ++k) {
+        const double r = data[k] - (double)g[k];
+        J = fma(r, r, J);
+    }
+    const double sg = sigma[i], m = 2.0 * n_obs;
+    logl[i] = -0.5 * m * log(2.0 * M_PI) - m * log(sg) - 0.5 * J / (sg * sg);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1536,6 +1560,19 @@ hipError_t launch_accept(int64_t n, const double* dist, const double* tol, uint8
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_accept, dim3(nblk(n, 256)), dim3(256), 0, st, n, dist, tol, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauss_loglik(int dtype, int64_t n, int32_t n_obs, const void* obs, const double* data,
+                               const double* sigma, const int32_t* status, double* logl, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_gauss_loglik<float>, dim3(nblk(n, 256)), dim3(256), 0, st, n, n_obs, (const float*)obs,
+                           data, sigma, status, logl);
+    else
+        hipLaunchKernelGGL(k_gauss_loglik<double>, dim3(nblk(n, 256)), dim3(256), 0, st, n, n_obs, (const double*)obs,
+                           data, sigma, status, logl);
     return hipGetLastError();
 }
 

@@ -51,6 +51,9 @@ SIGNATURES = {
     "abc_step": (_c.c_int, [_P, _P, _DP, _c.c_int32, _c.c_int64, _I32P, _c.c_uint64, _c.c_int32, _DP, _DP,
                             _c.c_int64, _c.c_double, _DP, _DP, _U8P, _DP, _DP, _I32P]),
     "swim_kernel_eval_host": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_double, _c.c_int64, _DP, _DP, _DP, _DP]),
+    "tmcmc_loglik": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _c.c_int32, _P, _P, _P, _P, _P, _P]),
+    "tmcmc_run": (_c.c_int, [_P, _P, _P, _DP, _c.c_int32, _c.c_int32, _c.c_int64, _c.c_uint64, _DP, _DP, _DP, _I32P,
+                             _DP, _I64P, _I64P, _DP]),
     "surrogate_forward": (_c.c_int, [_P, _c.c_int64, _P, _P, _P, _P]),
     "surrogate_grad": (_c.c_int, [_P, _c.c_int64, _P, _P, _P, _P, _P, _P]),
     "surrogate_train": (_c.c_int, [_P, _c.c_int64, _P, _P, _P, _c.c_int32, _c.c_int32, _c.c_float, _P, _P, _P, _P,
@@ -107,6 +110,11 @@ class abc_model(ctypes.Structure):
     _fields_ = [("lo", _c.c_double * 3), ("hi", _c.c_double * 3), ("b", _c.c_double), ("omega", _c.c_double),
                 ("k", _c.c_double), ("steps", _c.c_int32), ("obs_every", _c.c_int32), ("dt", _c.c_double),
                 ("eps_over_ds", _c.c_double), ("dtype", _c.c_int32), ("use_graph", _c.c_int32)]
+
+
+class tmcmc_opts(ctypes.Structure):
+    _fields_ = [("lo", _c.c_double * 4), ("hi", _c.c_double * 4), ("cv_target", _c.c_double),
+                ("cov_scale", _c.c_double), ("max_stages", _c.c_int32)]
 
 
 def _dptr(t):
@@ -278,6 +286,39 @@ def abc_step(ctx, model, data, N, seed, generation, q, prev_theta=None, prev_w=N
                           acc.ctypes.data_as(_U8P), w.ctypes.data_as(_DP), tol.ctypes.data_as(_DP),
                           steps.ctypes.data_as(_I32P)))
     return dict(theta=theta, dist=dist, accept=acc.astype(bool), w=w, tol=float(tol[0]), steps=steps)
+
+
+def tmcmc_loglik(ctx, dtype, obs, data, sigma, status, logl, stream=None):
+    """Device tensors: obs [n][n_obs][2] (run dtype), data [n_obs][2] FP64,
+    sigma [n] FP64, status [n] int32 -> logl [n] FP64."""
+    n, n_obs = obs.shape[0], obs.shape[1]
+    _check(lib().tmcmc_loglik(ctx.handle, int(dtype), n, n_obs, _dptr(obs), _dptr(data), _dptr(sigma), _dptr(status),
+                              _dptr(logl), _stream(stream)))
+
+
+def tmcmc_run(ctx, model, lo, hi, data, N, n, seed, cv_target=1.0, cov_scale=0.2, max_stages=40):
+    """One TMCMC run over the forward model; host arrays in and out."""
+    d, d_p = _h(data, np.float64, _DP)
+    o = tmcmc_opts()
+    for i in range(4):
+        o.lo[i] = float(lo[i])
+        o.hi[i] = float(hi[i])
+    o.cv_target, o.cov_scale, o.max_stages = float(cv_target), float(cov_scale), int(max_stages)
+    theta = np.empty((n, 4))
+    logl = np.empty(n)
+    q = np.full(max_stages + 1, np.nan)
+    ns = np.zeros(1, dtype=np.int32)
+    lev = np.empty(1)
+    acc = np.zeros(max_stages, dtype=np.int64)
+    runs = np.zeros(1, dtype=np.int64)
+    secs = np.zeros(1)
+    _check(lib().tmcmc_run(ctx.handle, ctypes.byref(model), ctypes.byref(o), d_p, d.shape[0], int(N), int(n), int(seed),
+                           theta.ctypes.data_as(_DP), logl.ctypes.data_as(_DP), q.ctypes.data_as(_DP),
+                           ns.ctypes.data_as(_I32P), lev.ctypes.data_as(_DP), acc.ctypes.data_as(_I64P),
+                           runs.ctypes.data_as(_I64P), secs.ctypes.data_as(_DP)))
+    k = int(ns[0])
+    return dict(theta=theta, logl=logl, q=q[:k + 1], n_stages=k, log_evidence=float(lev[0]), accepted=acc[:k],
+                runs=int(runs[0]), seconds=float(secs[0]))
 
 
 def swim_kernel_eval_host(dtype, alpha, eps, t):

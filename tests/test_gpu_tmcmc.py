@@ -1,0 +1,100 @@
+"""TMCMC on the GPU against the oracle (Sec. 2.3, Algorithm TMCMC; likelihood
+eqs. (likelihood)-(fitness)).
+
+* tmcmc_loglik equals the oracle's Gaussian log-likelihood of the same model
+  outputs (FP32 and FP64 outputs; FP64 arithmetic on both sides).
+* tmcmc_run (FP64 forward model) follows the oracle's TMCMC driven by the
+  oracle's forward model, stage by stage, on a small swimmer (N = 8, 300
+  steps of dt = 1e-4, head every 30 steps, 64 samples per stage; the oracle
+  takes about 20 s): same stages, tempering exponents, accepted moves,
+  final samples and evidence.  The two sides
+  share only the seeded Philox streams; their likelihoods agree to ~1e-13,
+  so every Metropolis and resampling decision coincides.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1910_12007_amd import inputs, swim  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = swim.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("td", [torch.float32, torch.float64])
+def test_loglik_matches_oracle(ctx, td):
+    from oracle import tmcmc as otm
+    rng = np.random.Generator(np.random.PCG64(31))
+    n, n_obs = 1000, 50
+    data = rng.normal(size=(n_obs, 2))
+    obs = data[None] + rng.normal(scale=0.02, size=(n, n_obs, 2))
+    sigma = rng.uniform(1e-3, 0.1, n)
+    status = np.zeros(n, np.int32)
+    status[::17] = 2
+    obs_d = torch.from_numpy(obs).to(td).cuda()
+    ll = torch.empty(n, dtype=torch.float64, device="cuda")
+    dtype = swim.SWIM_F32 if td == torch.float32 else swim.SWIM_F64
+    swim.tmcmc_loglik(ctx, dtype, obs_d, torch.from_numpy(data).cuda(), torch.from_numpy(sigma).cuda(),
+                      torch.from_numpy(status).cuda(), ll)
+    torch.cuda.synchronize()
+    got = ll.cpu().numpy()
+    g = obs_d.cpu().double().numpy().reshape(n, -1)
+    g[status != 0] = np.nan
+    ref = otm.gauss_loglik(g, data.ravel(), sigma)
+    assert np.array_equal(np.isneginf(got), np.isneginf(ref))
+    ok = np.isfinite(ref)
+    np.testing.assert_allclose(got[ok], ref[ok], rtol=1e-12, atol=0)
+
+
+def small_problem():
+    N, steps, dt, oe = 8, 300, 1e-4, 30
+    true = np.array([1.5, 0.1, 1000.0])
+    from oracle import core
+    r = core.forward(inputs.theta_rows(true), N, steps, dt, oe)
+    assert r["status"] == 0
+    noise = np.random.Generator(np.random.PCG64(77)).normal(scale=5e-5, size=r["obs"][0].shape)
+    data = r["obs"][0] + noise
+    lo = np.array([0.5, 0.05, 500.0, 1e-5])
+    hi = np.array([3.0, 0.2, 2000.0, 5e-4])
+    return N, steps, dt, oe, data, lo, hi
+
+
+def test_tmcmc_run_matches_oracle(ctx):
+    from oracle import core
+    from oracle import tmcmc as otm
+    N, steps, dt, oe, data, lo, hi = small_problem()
+    n, seed = 64, 2024
+
+    def oracle_loglik(th):
+        th = np.atleast_2d(th)
+        out = np.empty(th.shape[0])
+        for i, t in enumerate(th):
+            r = core.forward(inputs.theta_rows(t[:3]), N, steps, dt, oe)
+            g = r["obs"][0].reshape(1, -1) if r["status"] == 0 else np.full((1, data.size), np.nan)
+            out[i] = otm.gauss_loglik(g, data.ravel(), t[3:4])[0]
+        return out
+
+    ref = otm.tmcmc(oracle_loglik, lo, hi, n, seed, cv_target=1.0, b=0.2, max_stages=30)
+    m = swim.abc_model()
+    m.b, m.omega, m.k = 0.1, 2 * np.pi, 2 * np.pi
+    m.steps, m.obs_every, m.dt, m.eps_over_ds = steps, oe, dt, 1.5
+    m.dtype, m.use_graph = swim.SWIM_F64, 1
+    got = swim.tmcmc_run(ctx, m, lo, hi, data, N, n, seed, cv_target=1.0, cov_scale=0.2, max_stages=30)
+    print({"stages": got["n_stages"], "q": got["q"], "accepted": got["accepted"], "runs": got["runs"],
+           "log_evidence": got["log_evidence"], "oracle_log_evidence": ref["log_evidence"]})
+    assert got["n_stages"] == len(ref["q"]) - 1 >= 2
+    np.testing.assert_allclose(got["q"], ref["q"], rtol=1e-9, atol=1e-15)
+    assert np.array_equal(got["accepted"], ref["accepted"])
+    assert got["runs"] == ref["evaluations"]
+    np.testing.assert_allclose(got["theta"], ref["theta"], rtol=1e-9, atol=1e-12 * (hi - lo).max())
+    np.testing.assert_allclose(got["logl"], ref["logl"], rtol=1e-9)
+    assert abs(got["log_evidence"] - ref["log_evidence"]) <= 1e-9 * abs(ref["log_evidence"]) + 1e-9
