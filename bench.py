@@ -255,6 +255,33 @@ def pmc_leg(ctx, data, n=16384, steps=5000, dt=5e-5, quantiles=(0.5, 0.25, 0.1))
             "graph_launches": swim.swim_get_option(ctx, swim.SWIM_OPT_GRAPH_LAUNCHES), "generations": gens}
 
 
+def tmcmc_leg(ctx, data, n=2048, seed=7):
+    """TMCMC (the paper's sampler) on the batched workload's model and data:
+    n samples per stage (the paper takes 2000), (alpha, S_b, S_s) on the
+    batched workload's prior box and the noise standard deviation sigma on
+    [1e-4, 1e-2]; FP32 forward runs, one batched launch per Metropolis step
+    across all chains.  Reports the stages, forward runs and their rate, and
+    the final-stage posterior against the parameters the data were made
+    with (2, 0.1, 1e3, sigma = 1e-3)."""
+    from paper_1910_12007_amd import inputs, swim, surrogate_abc
+    model = surrogate_abc.batch_model()
+    lo = np.append(inputs.PRIOR_LO, 1e-4)
+    hi = np.append(inputs.PRIOR_HI, 1e-2)
+    t0 = time.perf_counter()
+    r = swim.tmcmc_run(ctx, model, lo, hi, data, 128, n, seed, cv_target=1.0, cov_scale=0.2, max_stages=60)
+    wall = time.perf_counter() - t0
+    th = r["theta"]
+    truth = np.append(inputs.TRUE_THETA, 1e-3)
+    return {"workload": f"TMCMC, {n} samples per stage, N=128, 5000 steps dt=5e-05, FP32, "
+                        "theta = (alpha, S_b, S_s, sigma), data of the batched workload",
+            "stages": r["n_stages"], "q": [float(x) for x in r["q"]], "forward_runs": r["runs"],
+            "seconds": wall, "forward_seconds": r["seconds"], "forward_runs_per_s": r["runs"] / r["seconds"],
+            "accepted_per_stage": [int(x) for x in r["accepted"]], "log_evidence": r["log_evidence"],
+            "posterior_mean": th.mean(0).tolist(), "posterior_std": th.std(0).tolist(),
+            "true": truth.tolist(),
+            "z_scores_of_truth": ((truth - th.mean(0)) / th.std(0)).tolist()}
+
+
 def surrogate_leg(ctx, data):
     """Surrogate-prescreened ABC against plain batched ABC on the same 1M
     prior draws (tolerance: the 5th percentile of the completed runs of the
@@ -292,6 +319,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-prescreened ABC comparison")
     ap.add_argument("--no-dense", action="store_true", help="skip the large-N dense workload")
     ap.add_argument("--no-pmc", action="store_true", help="skip the uneven-N PMC workload")
+    ap.add_argument("--no-tmcmc", action="store_true", help="skip the TMCMC run")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times), the reference "
                          "for scaling the HBM byte counters, and exit")
@@ -398,6 +426,8 @@ def main():
         out["dense"] = dense_leg(ctx, stream, with_oracle=not args.no_cpu)
     if not args.no_pmc:
         out["pmc_uneven"] = pmc_leg(ctx, load_data())
+    if not args.no_tmcmc:
+        out["tmcmc"] = tmcmc_leg(ctx, load_data())
     if not args.no_surrogate:
         out["surrogate_abc"] = surrogate_leg(ctx, load_data())
     if not args.no_cpu:
