@@ -221,6 +221,28 @@ def test_multi_swimmer_systems_match_oracle(ctx, oracle_core, dtype, tol):
         check_traj(obs[3 + m], r2["obs"][m], np.array([P2[m, 7] + 1.0, P2[m, 8]]), tol, dtype, steps, 3.0)
 
 
+@pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-11), (swim.SWIM_F32, 1e-4)])
+def test_large_system_over_several_tiles_matches_oracle(ctx, oracle_core, dtype, tol):
+    """8 interacting swimmers of N = 140 (1120 points: the per-step
+    large-system kernel with two LDS tiles of sources), 20 steps of dt = 5e-5,
+    heads every 10 steps.  The heads move ~1e-2 in these 20 steps, small
+    against the velocities of the snapping filaments, so the 1e-12 norm-wise
+    bar per FP64 velocity evaluation (test_pair_velocity_matches_oracle)
+    leaves up to ~1e-11 on the head displacement; measured 6e-12."""
+    lay = inputs.dense_layout(n_samples=2, seed=5)
+    P = lay[1].copy()
+    P[:, 0] = 0.7
+    P[:, 7] -= 2.75
+    P[:, 8] -= 0.75
+    steps, dt = 20, 5e-5
+    obs, speed, st = run_forward(ctx, dtype, [140], [8], P, steps, dt, 10)
+    assert list(st) == [0]
+    ref = oracle_core.forward(P, 140, steps, dt, 10)
+    assert ref["status"] == 0
+    for m in range(8):
+        check_traj(obs[m], ref["obs"][m], np.array([P[m, 7] + 1.0, P[m, 8]]), tol, dtype, steps, 3.0)
+
+
 def test_dense_sample_velocity_at_full_size(ctx, oracle_core):
     """One velocity evaluation of the large-N dense workload at its full size:
     sample 0 (8 swimmers x 512 points on the 2 x 4 grid, alpha from seed 3)

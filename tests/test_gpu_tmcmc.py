@@ -98,3 +98,43 @@ def test_tmcmc_run_matches_oracle(ctx):
     np.testing.assert_allclose(got["theta"], ref["theta"], rtol=1e-9, atol=1e-12 * (hi - lo).max())
     np.testing.assert_allclose(got["logl"], ref["logl"], rtol=1e-9)
     assert abs(got["log_evidence"] - ref["log_evidence"]) <= 1e-9 * abs(ref["log_evidence"]) + 1e-9
+
+
+def test_fp32_run_agrees_with_fp64_in_distribution(ctx):
+    """FP32 forward runs change the likelihoods at the rounding level, so the
+    chains take other decisions: the FP32 run is compared in distribution
+    (256 samples per stage, the small problem): same number of stages within
+    one, posterior means within one FP64 posterior standard deviation,
+    evidence within 1 in log."""
+    N, steps, dt, oe, data, lo, hi = small_problem()
+    m = swim.abc_model()
+    m.b, m.omega, m.k = 0.1, 2 * np.pi, 2 * np.pi
+    m.steps, m.obs_every, m.dt, m.eps_over_ds = steps, oe, dt, 1.5
+    m.use_graph = 1
+    out = {}
+    for dt_ in (swim.SWIM_F64, swim.SWIM_F32):
+        m.dtype = dt_
+        out[dt_] = swim.tmcmc_run(ctx, m, lo, hi, data, N, 256, 99, max_stages=30)
+    a, b = out[swim.SWIM_F64], out[swim.SWIM_F32]
+    print({"stages": (a["n_stages"], b["n_stages"]), "mean64": a["theta"].mean(0), "mean32": b["theta"].mean(0),
+           "std64": a["theta"].std(0), "logZ": (a["log_evidence"], b["log_evidence"])})
+    assert a["q"][-1] == 1.0 and b["q"][-1] == 1.0
+    assert abs(a["n_stages"] - b["n_stages"]) <= 1
+    assert np.all(np.abs(a["theta"].mean(0) - b["theta"].mean(0)) <= a["theta"].std(0))
+    assert abs(a["log_evidence"] - b["log_evidence"]) < 1.0
+
+
+def test_tmcmc_argument_errors(ctx):
+    N, steps, dt, oe, data, lo, hi = small_problem()
+    m = swim.abc_model()
+    m.b, m.omega, m.k = 0.1, 2 * np.pi, 2 * np.pi
+    m.steps, m.obs_every, m.dt, m.eps_over_ds = steps, oe, dt, 1.5
+    m.dtype, m.use_graph = swim.SWIM_F64, 0
+    bad_lo = lo.copy()
+    bad_lo[3] = 0.0  # sigma must stay positive
+    for args in [(lo, hi, data, N, 1), (hi, lo, data, N, 16), (bad_lo, hi, data, N, 16), (lo, hi, data[:-1], N, 16),
+                 (lo, hi, data, 2, 16)]:
+        with pytest.raises(swim.SwimError):
+            swim.tmcmc_run(ctx, m, args[0], args[1], args[2], args[3], args[4], 1)
+    with pytest.raises(swim.SwimError):
+        swim.tmcmc_run(ctx, m, lo, hi, data, N, 16, 1, cv_target=0.0)
