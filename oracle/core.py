@@ -43,6 +43,19 @@ def lib():
         L.oracle_forward.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_double, ctypes.c_int,
                                      ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _I32]
         L.oracle_forward.restype = ctypes.c_int
+        L.oracle_sperm_zhat.argtypes = [ctypes.c_int, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, _D]
+        L.oracle_sperm_initial.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, _D, _D]
+        L.oracle_sperm_energy.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D,
+                                          ctypes.c_double, ctypes.c_double, _D, _D]
+        L.oracle_sperm_energy.restype = ctypes.c_double
+        L.oracle_sperm_forces.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D,
+                                          ctypes.c_double, ctypes.c_double, _D, _D, _D, _D]
+        L.oracle_sperm_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, _D, _D, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_int, _D, _D, _D, _D, _I32]
+        L.oracle_sperm_forward.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -140,3 +153,66 @@ def forward(params, N, steps, dt, obs_every, eps_over_ds=1.5):
     lib().oracle_forward(n_swim, N, _p(P), float(eps_over_ds), int(steps), float(dt),
                          int(obs_every), _p(obs), _p(speed), _p(xo), _p(yo), ctypes.byref(st))
     return dict(obs=obs[:, :n_obs], speed=speed, x=xo, y=yo, status=int(st.value))
+
+
+# ---------------------------------------------------------------------------
+# full sperm model (Appendix): system row SPERM_FIELDS, swimmer rows
+# (x0, y0, phase); geometry (nf, nh, H_r, dN) shared by all swimmers
+# ---------------------------------------------------------------------------
+SPERM_FIELDS = ("alpha", "KC", "KT", "KHT", "KHC", "KNT", "KNA", "a", "eta", "omega")
+
+
+def sperm_zhat(s, a, eta, omega, phase, t):
+    """Preferred flagellum curvature: second s-derivative of the tapered beat
+    a (1 - s) sin(eta s - omega t + phase)."""
+    s = _f64(s).ravel()
+    out = np.empty_like(s)
+    lib().oracle_sperm_zhat(s.size, _p(s), float(a), float(eta), float(omega), float(phase), float(t), _p(out))
+    return out
+
+
+def sperm_initial(nf, nh, hr, dn, x0=0.0, y0=0.0):
+    """Initial positions of one swimmer: flagellum points 0..nf-1, then the
+    head points 0..nh-1 (angle m 2 pi / nh about the head centre)."""
+    x, y = np.empty(nf + nh), np.empty(nf + nh)
+    lib().oracle_sperm_initial(int(nf), int(nh), float(hr), float(dn), float(x0), float(y0), _p(x), _p(y))
+    return x, y
+
+
+def sperm_energy(nf, nh, hr, dn, sys_row, phase, t, x, y):
+    """Discrete energy of one swimmer (swim_oracle.c lists its terms)."""
+    sp = _f64(sys_row)
+    x, y = _f64(x), _f64(y)
+    return lib().oracle_sperm_energy(int(nf), int(nh), float(hr), float(dn), _p(sp), float(phase), float(t),
+                                     _p(x), _p(y))
+
+
+def sperm_forces(nf, nh, hr, dn, sys_row, phase, t, x, y):
+    """F = -dE/dX of sperm_energy (eq. Fenergy)."""
+    sp = _f64(sys_row)
+    x, y = _f64(x), _f64(y)
+    fx, fy = np.empty_like(x), np.empty_like(x)
+    lib().oracle_sperm_forces(int(nf), int(nh), float(hr), float(dn), _p(sp), float(phase), float(t), _p(x),
+                              _p(y), _p(fx), _p(fy))
+    return fx, fy
+
+
+def sperm_forward(sys_row, swimmers, nf, nh, eps, hr, dn, steps, dt, obs_every):
+    """Forward-Euler run of one system of sperm swimmers.
+
+    swimmers: (n_swim, 3) rows (x0, y0, phase).  Returns dict(head, tail)
+    of shape (n_swim, n_obs + 1, 2) (sample 0: the initial state; NaN for
+    samples a stopped run does not reach), x, y (final positions) and
+    status."""
+    sp = _f64(sys_row)
+    sw = _f64(np.atleast_2d(swimmers))
+    n_swim = sw.shape[0]
+    n_obs = steps // obs_every if obs_every > 0 else 0
+    head = np.full((n_swim, n_obs + 1, 2), np.nan)
+    tail = np.full((n_swim, n_obs + 1, 2), np.nan)
+    x, y = np.empty(n_swim * (nf + nh)), np.empty(n_swim * (nf + nh))
+    st = ctypes.c_int32(0)
+    lib().oracle_sperm_forward(n_swim, int(nf), int(nh), float(eps), float(hr), float(dn), _p(sp), _p(sw),
+                               int(steps), float(dt), int(obs_every), _p(head), _p(tail), _p(x), _p(y),
+                               ctypes.byref(st))
+    return dict(head=head, tail=tail, x=x, y=y, status=int(st.value))

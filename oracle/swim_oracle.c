@@ -467,3 +467,297 @@ int oracle_forward(int n_swim, int N, const double *params, double eps_over_ds, 
     free(x); free(y); free(fx); free(fy); free(ux); free(uy); free(k0); free(h0);
     return 0;
 }
+
+/* ======================================================================== */
+/* Full sperm model (Appendix): flagellum of nf points with the tapered     */
+/* beat, a circular head of nh points, the neck, n_swim swimmers per fluid. */
+/*                                                                          */
+/* Geometry of one swimmer (left to right, Appendix): flagellum point k at  */
+/* (x0 + k ds, y0), ds = 1/(nf-1); head centre at the last flagellum point  */
+/* shifted right by H_r + dN; head point m at angle m dth, dth = 2 pi/nh,   */
+/* so m = nh/2 is the point at angle pi, nearest the flagellum.             */
+/*                                                                          */
+/* Discrete energy (trapezoid rule, centred differences, Appendix):          */
+/*   flagellum tension  K_T  sum_k (l_k/ds - 1)^2 ds          (EFT)         */
+/*   flagellum bending  K_C  sum_{k=1}^{nf-2} (zeta_k - zhat_k)^2 ds (EFB)  */
+/*       zhat = d^2/ds^2 of a (1-s) sin(eta s - omega t + phase)            */
+/*   head tension       K_HT sum_m (l_m/c - 1)^2 c, ring springs, rest c =  */
+/*                      the initial chord 2 H_r sin(dth/2)                  */
+/*   head diameters     K_HT sum_{m<nh/2} (d_m/(2 H_r) - 1)^2 (2 H_r),      */
+/*                      springs between points pi apart                     */
+/*   head bending       K_HC sum_m (kappa_m - 1/H_r)^2 c, closed curve      */
+/*   neck tension       K_NT sum over 5 springs (l/L0 - 1)^2 L0, L0 = the   */
+/*                      initial lengths: last flagellum point to the head   */
+/*                      points at pi - dth, pi, pi + dth; the one before it */
+/*                      to pi - dth and pi + dth                            */
+/*   neck angle         K_NA (z1 . z2)^2, z1 = H(pi) - F(nf-1),             */
+/*                      z2 = H(pi + dth) - H(pi - dth)                      */
+/* Every spring has the form K (l/L0 - 1)^2 L0 of the flagellum's discrete */
+/* tension.  F = -dE/dX (eq. Fenergy), the exact gradient of this energy.   */
+/* ------------------------------------------------------------------------ */
+
+/* system row: alpha, K_C, K_T, K_HT, K_HC, K_NT, K_NA, a, eta, omega */
+enum { SP_ALPHA, SP_KC, SP_KT, SP_KHT, SP_KHC, SP_KNT, SP_KNA, SP_A, SP_ETA, SP_OMEGA, SP_N };
+
+typedef struct {
+    int nf, nh;
+    double ds, hr, dn, dth, ch;
+    double L0[5];
+    int na[5], nb[5]; /* neck springs: point indices within the swimmer */
+} osperm;
+
+static void sperm_geom(osperm *g, int nf, int nh, double hr, double dn)
+{
+    g->nf = nf;
+    g->nh = nh;
+    g->ds = 1.0 / (double)(nf - 1);
+    g->hr = hr;
+    g->dn = dn;
+    g->dth = 2.0 * (double)PI_L / (double)nh;
+    g->ch = 2.0 * hr * sin(0.5 * g->dth);
+    const int c = nf + nh / 2;
+    const int a[5] = {nf - 1, nf - 1, nf - 1, nf - 2, nf - 2};
+    const int b[5] = {c - 1, c, c + 1, c - 1, c + 1};
+    for (int i = 0; i < 5; ++i) {
+        g->na[i] = a[i];
+        g->nb[i] = b[i];
+    }
+}
+
+/* initial positions of one swimmer whose first flagellum point is (x0, y0) */
+static void sperm_initial(const osperm *g, double x0, double y0, double *x, double *y)
+{
+    for (int k = 0; k < g->nf; ++k) {
+        x[k] = x0 + (double)k * g->ds;
+        y[k] = y0;
+    }
+    const double xc = x[g->nf - 1] + g->hr + g->dn, yc = y0;
+    for (int m = 0; m < g->nh; ++m) {
+        x[g->nf + m] = xc + g->hr * cos((double)m * g->dth);
+        y[g->nf + m] = yc + g->hr * sin((double)m * g->dth);
+    }
+}
+
+static void sperm_rest_lengths(osperm *g)
+{
+    double *x = malloc(sizeof(double) * (g->nf + g->nh)), *y = malloc(sizeof(double) * (g->nf + g->nh));
+    sperm_initial(g, 0.0, 0.0, x, y);
+    for (int i = 0; i < 5; ++i)
+        g->L0[i] = hypot(x[g->nb[i]] - x[g->na[i]], y[g->nb[i]] - y[g->na[i]]);
+    free(x);
+    free(y);
+}
+
+/* preferred flagellum curvature zhat(s, t) = d^2/ds^2 [a (1-s) sin(eta s - omega t + phase)]
+ *   = -2 a eta cos(psi) - a (1-s) eta^2 sin(psi),  psi = eta s - omega t + phase */
+static double sperm_zhat(double a, double eta, double omega, double phase, double s, double t)
+{
+    const double psi = eta * s - omega * t + phase;
+    return -2.0 * a * eta * cos(psi) - a * (1.0 - s) * eta * eta * sin(psi);
+}
+
+void oracle_sperm_zhat(int n, const double *s, double a, double eta, double omega, double phase, double t,
+                       double *out)
+{
+    for (int i = 0; i < n; ++i) out[i] = sperm_zhat(a, eta, omega, phase, s[i], t);
+}
+
+/* curvature (curva) at B from A, B, C with parameter step h */
+static double node_curvature(double xa, double ya, double xb, double yb, double xc, double yc, double h)
+{
+    const double xp = (xc - xa) / (2.0 * h), yp = (yc - ya) / (2.0 * h);
+    const double xpp = (xc - 2.0 * xb + xa) / (h * h), ypp = (yc - 2.0 * yb + ya) / (h * h);
+    return (ypp * xp - xpp * yp) / pow(xp * xp + yp * yp, 1.5);
+}
+
+static double spring_energy(double xa, double ya, double xb, double yb, double L0, double K)
+{
+    const double e = hypot(xb - xa, yb - ya) / L0 - 1.0;
+    return K * e * e * L0;
+}
+
+/* energy of one swimmer; sp = system row, phase = the swimmer's beat phase */
+static double sperm_energy(const osperm *g, const double *sp, double phase, double t, const double *x,
+                           const double *y)
+{
+    const int nf = g->nf, nh = g->nh;
+    const double *hx = x + nf, *hy = y + nf;
+    double E = 0.0;
+    for (int k = 0; k + 1 < nf; ++k) E += spring_energy(x[k], y[k], x[k + 1], y[k + 1], g->ds, sp[SP_KT]);
+    for (int k = 1; k + 1 < nf; ++k) {
+        const double z = node_curvature(x[k - 1], y[k - 1], x[k], y[k], x[k + 1], y[k + 1], g->ds);
+        const double d = z - sperm_zhat(sp[SP_A], sp[SP_ETA], sp[SP_OMEGA], phase, (double)k * g->ds, t);
+        E += sp[SP_KC] * d * d * g->ds;
+    }
+    for (int m = 0; m < nh; ++m) {
+        const int n = (m + 1) % nh, p = (m + nh - 1) % nh;
+        E += spring_energy(hx[m], hy[m], hx[n], hy[n], g->ch, sp[SP_KHT]);
+        const double d = node_curvature(hx[p], hy[p], hx[m], hy[m], hx[n], hy[n], g->ch) - 1.0 / g->hr;
+        E += sp[SP_KHC] * d * d * g->ch;
+    }
+    for (int m = 0; m < nh / 2; ++m)
+        E += spring_energy(hx[m], hy[m], hx[m + nh / 2], hy[m + nh / 2], 2.0 * g->hr, sp[SP_KHT]);
+    for (int i = 0; i < 5; ++i)
+        E += spring_energy(x[g->na[i]], y[g->na[i]], x[g->nb[i]], y[g->nb[i]], g->L0[i], sp[SP_KNT]);
+    const int c = nf + nh / 2, F = nf - 1;
+    const double z1x = x[c] - x[F], z1y = y[c] - y[F];
+    const double z2x = x[c + 1] - x[c - 1], z2y = y[c + 1] - y[c - 1];
+    const double dot = z1x * z2x + z1y * z2y;
+    E += sp[SP_KNA] * dot * dot;
+    return E;
+}
+
+/* dE/dX of K (l/L0 - 1)^2 L0 between points a and b, subtracted from the forces */
+static void spring_force(const double *x, const double *y, int a, int b, double L0, double K, double *fx,
+                         double *fy)
+{
+    const double dx = x[b] - x[a], dy = y[b] - y[a];
+    const double l = hypot(dx, dy);
+    const double g = 2.0 * K * (l / L0 - 1.0) / l; /* dE/dX_b = g (X_b - X_a) */
+    fx[b] -= g * dx;
+    fy[b] -= g * dy;
+    fx[a] += g * dx;
+    fy[a] += g * dy;
+}
+
+/* dE/dX of W (kappa_B - k0)^2 h at the node B of (A, B, C), step h */
+static void bend_force(const double *x, const double *y, int A, int B, int C, double h, double W, double k0,
+                       double *fx, double *fy)
+{
+    const double a = (x[C] - x[A]) / (2.0 * h), b = (y[C] - y[A]) / (2.0 * h);
+    const double p = (x[C] - 2.0 * x[B] + x[A]) / (h * h), q = (y[C] - 2.0 * y[B] + y[A]) / (h * h);
+    const double S = a * a + b * b, S32 = pow(S, 1.5);
+    const double num = q * a - p * b;
+    const double co = 2.0 * W * (num / S32 - k0) * h; /* dE/dkappa */
+    const double dka = q / S32 - 3.0 * a * num / (S32 * S);
+    const double dkb = -p / S32 - 3.0 * b * num / (S32 * S);
+    const double dkp = -b / S32, dkq = a / S32;
+    const double i2 = 1.0 / (2.0 * h), i1 = 1.0 / (h * h);
+    fx[A] -= co * (-dka * i2 + dkp * i1);
+    fy[A] -= co * (-dkb * i2 + dkq * i1);
+    fx[B] -= co * (-2.0 * dkp * i1);
+    fy[B] -= co * (-2.0 * dkq * i1);
+    fx[C] -= co * (dka * i2 + dkp * i1);
+    fy[C] -= co * (dkb * i2 + dkq * i1);
+}
+
+static void sperm_forces(const osperm *g, const double *sp, double phase, double t, const double *x,
+                         const double *y, double *fx, double *fy)
+{
+    const int nf = g->nf, nh = g->nh, n = nf + nh;
+    for (int i = 0; i < n; ++i) fx[i] = fy[i] = 0.0;
+    for (int k = 0; k + 1 < nf; ++k) spring_force(x, y, k, k + 1, g->ds, sp[SP_KT], fx, fy);
+    for (int k = 1; k + 1 < nf; ++k)
+        bend_force(x, y, k - 1, k, k + 1, g->ds, sp[SP_KC],
+                   sperm_zhat(sp[SP_A], sp[SP_ETA], sp[SP_OMEGA], phase, (double)k * g->ds, t), fx, fy);
+    for (int m = 0; m < nh; ++m) {
+        const int nx = nf + (m + 1) % nh, pv = nf + (m + nh - 1) % nh;
+        spring_force(x, y, nf + m, nx, g->ch, sp[SP_KHT], fx, fy);
+        bend_force(x, y, pv, nf + m, nx, g->ch, sp[SP_KHC], 1.0 / g->hr, fx, fy);
+    }
+    for (int m = 0; m < nh / 2; ++m) spring_force(x, y, nf + m, nf + m + nh / 2, 2.0 * g->hr, sp[SP_KHT], fx, fy);
+    for (int i = 0; i < 5; ++i) spring_force(x, y, g->na[i], g->nb[i], g->L0[i], sp[SP_KNT], fx, fy);
+    /* angle: E = K (z1.z2)^2; dE/dz1 = 2 K (z1.z2) z2, dE/dz2 = 2 K (z1.z2) z1 */
+    const int c = nf + nh / 2, F = nf - 1;
+    const double z1x = x[c] - x[F], z1y = y[c] - y[F];
+    const double z2x = x[c + 1] - x[c - 1], z2y = y[c + 1] - y[c - 1];
+    const double w = 2.0 * sp[SP_KNA] * (z1x * z2x + z1y * z2y);
+    fx[c] -= w * z2x;
+    fy[c] -= w * z2y;
+    fx[F] += w * z2x;
+    fy[F] += w * z2y;
+    fx[c + 1] -= w * z1x;
+    fy[c + 1] -= w * z1y;
+    fx[c - 1] += w * z1x;
+    fy[c - 1] += w * z1y;
+}
+
+void oracle_sperm_initial(int nf, int nh, double hr, double dn, double x0, double y0, double *x, double *y)
+{
+    osperm g;
+    sperm_geom(&g, nf, nh, hr, dn);
+    sperm_initial(&g, x0, y0, x, y);
+}
+
+double oracle_sperm_energy(int nf, int nh, double hr, double dn, const double *sp, double phase, double t,
+                           const double *x, const double *y)
+{
+    osperm g;
+    sperm_geom(&g, nf, nh, hr, dn);
+    sperm_rest_lengths(&g);
+    return sperm_energy(&g, sp, phase, t, x, y);
+}
+
+void oracle_sperm_forces(int nf, int nh, double hr, double dn, const double *sp, double phase, double t,
+                         const double *x, const double *y, double *fx, double *fy)
+{
+    osperm g;
+    sperm_geom(&g, nf, nh, hr, dn);
+    sperm_rest_lengths(&g);
+    sperm_forces(&g, sp, phase, t, x, y, fx, fy);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward run of one system of n_swim sperm swimmers in one fluid (alpha   */
+/* from the system row), blob width eps.  swp: n_swim rows (x0, y0, phase). */
+/* Each step n (t = n dt): forces of every swimmer, velocity sum over all   */
+/* points, Euler update, bound check.  Samples: index 0 is the initial      */
+/* state, index j >= 1 follows step j*obs_every; each sample stores the     */
+/* head centre (mean of the head points) and the tail end (flagellum point  */
+/* 0) of every swimmer: head[(m*(n_obs+1) + j)*2 + {0,1}], same for tail.   */
+/* Samples a stopped run does not reach are left untouched.                 */
+/* ------------------------------------------------------------------------ */
+int oracle_sperm_forward(int n_swim, int nf, int nh, double eps, double hr, double dn, const double *sp,
+                         const double *swp, int steps, double dt, int obs_every, double *head, double *tail,
+                         double *xout, double *yout, int *status)
+{
+    osperm g;
+    sperm_geom(&g, nf, nh, hr, dn);
+    sperm_rest_lengths(&g);
+    const int np = nf + nh;
+    const int64_t n = (int64_t)n_swim * np;
+    const int n_obs = obs_every > 0 ? steps / obs_every : 0;
+    double *x = malloc(sizeof(double) * n), *y = malloc(sizeof(double) * n);
+    double *fx = malloc(sizeof(double) * n), *fy = malloc(sizeof(double) * n);
+    double *ux = malloc(sizeof(double) * n), *uy = malloc(sizeof(double) * n);
+    okern k;
+    kernel_init(&k, sp[SP_ALPHA], eps);
+    for (int m = 0; m < n_swim; ++m) sperm_initial(&g, swp[3 * m], swp[3 * m + 1], x + m * np, y + m * np);
+    int st = 0;
+    for (int s = 0; s <= steps && st == 0; ++s) {
+        if (s % (obs_every > 0 ? obs_every : steps + 1) == 0 && s / (obs_every > 0 ? obs_every : 1) <= n_obs) {
+            const int j = obs_every > 0 ? s / obs_every : 0;
+            for (int m = 0; m < n_swim; ++m) {
+                double cx = 0.0, cy = 0.0;
+                for (int i = 0; i < nh; ++i) {
+                    cx += x[m * np + nf + i];
+                    cy += y[m * np + nf + i];
+                }
+                double *hd = head + ((int64_t)m * (n_obs + 1) + j) * 2;
+                double *tl = tail + ((int64_t)m * (n_obs + 1) + j) * 2;
+                hd[0] = cx / (double)nh;
+                hd[1] = cy / (double)nh;
+                tl[0] = x[m * np];
+                tl[1] = y[m * np];
+            }
+        }
+        if (s == steps) break;
+        const double t = (double)s * dt;
+        for (int m = 0; m < n_swim; ++m)
+            sperm_forces(&g, sp, swp[3 * m + 2], t, x + m * np, y + m * np, fx + m * np, fy + m * np);
+        velocity_sum(&k, n, x, y, fx, fy, ux, uy);
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] += dt * ux[i];
+            y[i] += dt * uy[i];
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            if (!isfinite(x[i]) || !isfinite(y[i])) { st = 1; break; }
+            if (fabs(x[i]) > 1e3 || fabs(y[i]) > 1e3) { st = 2; break; }
+        }
+    }
+    if (xout) memcpy(xout, x, sizeof(double) * n);
+    if (yout) memcpy(yout, y, sizeof(double) * n);
+    *status = st;
+    free(x); free(y); free(fx); free(fy); free(ux); free(uy);
+    return 0;
+}

@@ -1,0 +1,207 @@
+// swim_pairsum.h -- device building blocks shared by the persistent forward
+// kernels (filament and full sperm model): the dense regularized-Brinkmanlet
+// pair sum of eq. (BrV) in the symmetric lane schedule, the FP32 kernel
+// table's LDS copy, and the compensated (hi, lo) position update.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "swim_math.h"
+
+namespace swim {
+
+template <typename T> struct alignas(4 * sizeof(T)) Src4 {
+    T x, y, fx, fy;
+};
+
+template <typename T> struct alignas(2 * sizeof(T)) V2 {
+    T x, y;
+};
+
+// position outside the run bound |x| <= 1e3 (or not finite)
+__device__ __forceinline__ bool bad_t(float x) { return !(fabsf(x) <= 1e3f); }
+__device__ __forceinline__ bool bad_t(double x) { return !(fabs(x) <= 1e3); }
+
+// copy one system's FP32 kernel table from HBM into LDS (nthreads threads)
+__device__ __forceinline__ void tab_load(const TabSys* g, TabSys* tab, int tid, int nthreads)
+{
+    const float4* src = reinterpret_cast<const float4*>(g);
+    float4* dst = reinterpret_cast<float4*>(tab);
+    constexpr int NV = (int)(sizeof(TabSys) / sizeof(float4));
+    for (int i = tid; i < NV; i += nthreads) dst[i] = src[i];
+}
+
+// error-free (hi, lo) += d  (TwoSum, then renormalize)
+template <typename T> __device__ __forceinline__ void acc2(T& hi, T& lo, T d)
+{
+    const T s = hi + d;
+    const T bv = s - hi;
+    const T e = (hi - (s - bv)) + (d - bv);
+    const T l = lo + e;
+    const T h = s + l;
+    lo = l - (h - s);
+    hi = h;
+}
+
+// ---------------------------------------------------------------------------
+// symmetric pair schedule of the persistent kernel.  H1 and H2 depend on the
+// pair distance only, and the contribution of a pair is even in d, so one
+// evaluation serves both ends: target i gains Ht F_j + H2 (F_j . d) d and
+// source j gains Ht F_i + H2 (F_i . d) d (eq. BrV).  Points form blocks of
+// 64 (one per lane); for blocks a <= b, lane l pairs its point 64a + l with
+// the point 64b + (l + s) mod 64 at offset s, s = 0..63 for a < b and
+// s = 1..32 within a block (s = 32 pairs each couple twice, so lanes 32..63
+// skip it).  The accumulator of the moving point rotates down one lane per
+// offset.  All offsets of all block pairs (32 B^2 for B blocks) are split
+// into WPS equal contiguous ranges, one per wave.  Each block is stored twice
+// in a row (src2), so the point at offset s is read at lane + s.
+// ---------------------------------------------------------------------------
+
+// value of lane (l + 1) mod 64 (wave_rol:1; every lane has a source, so no
+// fallback value is needed)
+__device__ __forceinline__ float lane_rot(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_rot(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x134, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x134, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// v as an opaque wave-uniform value (a scalar register the compiler cannot
+// fold into constants)
+__device__ __forceinline__ int opaque_uniform(int v)
+{
+    int r;
+    asm volatile("s_mov_b32 %0, %1" : "=s"(r) : "s"(v));
+    return r;
+}
+
+// slot of point i in the doubled source array
+__device__ __forceinline__ int src2_slot(int i) { return ((i >> 6) << 7) + (i & 63); }
+
+// kernel functions of one pair at offset (dx, dy).  FP64: direct evaluation.
+// FP32 (positions scaled by rho): the table (FAR = false; a pair beyond it
+// gives zeros and sets far), or the direct evaluation of pairs beyond the
+// table only (FAR = true; zeros for the others).  H2 comes scaled to the
+// coordinates (H2 / sigma in FP32).
+template <typename T, bool FAR>
+__device__ __forceinline__ void pair_kernel(const SysConst<T>& C, const char* et, T dx, T dy, T& Ht, T& H2,
+                                            bool& far)
+{
+    if constexpr (sizeof(T) == 8) {
+        kernel_eval<T>(C, fma_t(dx, dx, dy * dy), Ht, H2);
+    } else {
+        const uint32_t bits = __builtin_bit_cast(uint32_t, fmaf(dx, dx, fmaf(dy, dy, 1.0f)));
+        const uint32_t id = bits >> TAB_SHIFT;
+        if constexpr (!FAR) {
+            far = far || id >= TAB_END;
+            tab_eval(*reinterpret_cast<const TabE*>(et + (min(id, TAB_END) << 5)), tab_u(bits), Ht, H2);
+        } else {
+            Ht = 0.0f;
+            H2 = 0.0f;
+            if (id >= TAB_END) {
+                kernel_eval<float>(C, fmaf(dx, dx, dy * dy) * C.its, Ht, H2);
+                H2 *= C.its;
+            }
+        }
+    }
+}
+
+// offsets [s_lo, s_hi) of block pair (a, b); adds the target sums to block
+// a's and the moving points' sums to block b's accumulators of this lane
+template <typename T, int TPL, bool FAR>
+__device__ __forceinline__ bool sym_offsets(const SysConst<T>& C, const char* et, const Src4<T>* src2, int a, int b,
+                                            int s_lo, int s_hi, int lane, T (&accx)[TPL], T (&accy)[TPL])
+{
+    const Src4<T> ti = src2[(a << 7) + lane];
+    const Src4<T>* sp = src2 + (b << 7) + lane;
+    T ax = (T)0, ay = (T)0, bx = (T)0, by = (T)0;
+    bool far = false;
+    const int s_full = (a == b) ? min(s_hi, 32) : s_hi;  // offsets every lane takes
+    for (int s = s_lo; s < s_full; ++s) {
+        const Src4<T> q = sp[s];
+        const T dx = ti.x - q.x, dy = ti.y - q.y;
+        T Ht, H2;
+        pair_kernel<T, FAR>(C, et, dx, dy, Ht, H2, far);
+        const T fdj = H2 * fma_t(q.fx, dx, q.fy * dy);
+        ax = fma_t(Ht, q.fx, fma_t(fdj, dx, ax));
+        ay = fma_t(Ht, q.fy, fma_t(fdj, dy, ay));
+        const T fdi = H2 * fma_t(ti.fx, dx, ti.fy * dy);
+        bx = lane_rot(fma_t(Ht, ti.fx, fma_t(fdi, dx, bx)));
+        by = lane_rot(fma_t(Ht, ti.fy, fma_t(fdi, dy, by)));
+    }
+    if (s_full < s_hi) {
+        // offset 32 within a block: lanes 32..63 repeat lanes 0..31's couples
+        const Src4<T> q = sp[32];
+        const T dx = ti.x - q.x, dy = ti.y - q.y;
+        T Ht, H2;
+        pair_kernel<T, FAR>(C, et, dx, dy, Ht, H2, far);
+        Ht = lane < 32 ? Ht : (T)0;
+        H2 = lane < 32 ? H2 : (T)0;
+        const T fdj = H2 * fma_t(q.fx, dx, q.fy * dy);
+        ax = fma_t(Ht, q.fx, fma_t(fdj, dx, ax));
+        ay = fma_t(Ht, q.fy, fma_t(fdj, dy, ay));
+        const T fdi = H2 * fma_t(ti.fx, dx, ti.fy * dy);
+        bx = lane_rot(fma_t(Ht, ti.fx, fma_t(fdi, dx, bx)));
+        by = lane_rot(fma_t(Ht, ti.fy, fma_t(fdi, dy, by)));
+    }
+    // lane l now holds the sums of point (l + s_hi) mod 64 of block b
+    const int from = (lane - s_hi) & 63;
+    bx = __shfl(bx, from, 64);
+    by = __shfl(by, from, 64);
+#pragma unroll
+    for (int c = 0; c < TPL; ++c) {
+        if (c == a) {
+            accx[c] += ax;
+            accy[c] += ay;
+        }
+        if (c == b) {
+            accx[c] += bx;
+            accy[c] += by;
+        }
+    }
+    return far;
+}
+
+// this wave's share of the pair sums of all n points: accx[c], accy[c] hold
+// the partial velocity of point 64c + lane
+template <typename T, int TPL, int WPS>
+__device__ __forceinline__ void pair_phase_sym(const SysConst<T>& C, const TabSys* tab, const Src4<T>* src2, int n,
+                                               int wave, int lane, T (&accx)[TPL], T (&accy)[TPL])
+{
+#pragma unroll
+    for (int c = 0; c < TPL; ++c) accx[c] = accy[c] = (T)0;
+    const char* et = nullptr;
+    if constexpr (sizeof(T) == 4) {
+        // entry of index id at et + (id << 5) bytes: the bias goes into a
+        // wave-uniform base (a register operand of the address arithmetic;
+        // gfx9 address arithmetic takes no 32-bit literal)
+        et = reinterpret_cast<const char*>(tab->e) + opaque_uniform(-(int)(TAB_BIAS * sizeof(TabE)));
+    }
+    const int B = (n + 63) >> 6;
+    const int S = 32 * B * B;
+    const int per = (S + WPS - 1) / WPS;
+    const int g0 = min(S, wave * per), g1 = min(S, g0 + per);
+    int g = 0;  // first offset index of block pair (a, b)
+    for (int a = 0; a < B && g < g1; ++a) {
+        for (int b = a; b < B && g < g1; ++b) {
+            const int len = (a == b) ? 32 : 64, base = (a == b) ? 1 : 0;
+            const int lo = max(g0, g), hi = min(g1, g + len);
+            if (lo < hi) {
+                const int s_lo = lo - g + base, s_hi = hi - g + base;
+                const bool far = sym_offsets<T, TPL, false>(C, et, src2, a, b, s_lo, s_hi, lane, accx, accy);
+                if constexpr (sizeof(T) == 4) {
+                    if (__any(far)) sym_offsets<T, TPL, true>(C, et, src2, a, b, s_lo, s_hi, lane, accx, accy);
+                }
+            }
+            g += len;
+        }
+    }
+}
+
+}  // namespace swim
