@@ -308,6 +308,82 @@ int tmcmc_run(swim_ctx *ctx, const abc_model *model, const tmcmc_opts *opts, con
               double *seconds_out);
 
 /* ---------------------------------------------------------------------------
+ * Full sperm model (Appendix, Table Tab:param): a flagellum of n_flag points
+ * with the tapered beat, a circular head of n_head points and the neck, with
+ * n_swim swimmers in one fluid per system.
+ *
+ * Geometry of one swimmer, left to right: flagellum point k at (x0 + k ds,
+ * y0), ds = 1/(n_flag-1).  The head centre is the last flagellum point
+ * shifted right by head_radius + neck_gap.  Head point m sits at angle
+ * m 2pi/n_head about that centre, so point n_head/2 (angle pi) is the one
+ * nearest the flagellum.
+ *
+ * Discrete energy (trapezoid rule, centred differences; every spring is
+ * K (l/L0 - 1)^2 L0, the trapezoid form of eq. EFT):
+ *   flagellum tension  K_T   between neighbours, rest ds
+ *   flagellum bending  K_C   sum_{k=1}^{n_flag-2} (zeta_k - zhat_k)^2 ds
+ *                      (eqs. EFB, curva), with zhat = d^2/ds^2 of
+ *                      a (1-s) sin(eta s - omega t + phase)
+ *   head ring          K_HT  neighbouring head points, rest 2 H_r sin(pi/n_head)
+ *   head diameters     K_HT  points pi apart, rest 2 H_r
+ *   head bending       K_HC  (kappa_m - 1/H_r)^2 times the chord, every node
+ *   neck springs       K_NT  last flagellum point to the head points at
+ *                      pi - dth, pi, pi + dth; the point before it to
+ *                      pi -+ dth; rest = initial lengths
+ *   neck angle         K_NA  (z1 . z2)^2, z1 = H(pi) - F(last),
+ *                      z2 = H(pi + dth) - H(pi - dth)
+ * Forces are F = -dE/dX (eq. Fenergy).  Velocities come from the eq. (BrV)
+ * sum over all points of the system, and positions advance by forward
+ * Euler (Sec. 2.1).
+ * ------------------------------------------------------------------------- */
+#define SWIM_SP_ALPHA 0 /* Brinkman resistance alpha >= 0                   */
+#define SWIM_SP_KC 1    /* K_C, flagellum curvature stiffness              */
+#define SWIM_SP_KT 2    /* K_tens, flagellum tensile stiffness             */
+#define SWIM_SP_KHT 3   /* K_H,tens, head tensile stiffness                */
+#define SWIM_SP_KHC 4   /* K_H,C, head curvature stiffness                 */
+#define SWIM_SP_KNT 5   /* K_N,tens, neck tensile stiffness                */
+#define SWIM_SP_KNA 6   /* K_N,ang, neck angle stiffness                   */
+#define SWIM_SP_A 7     /* beat amplitude a                                */
+#define SWIM_SP_ETA 8   /* beat wavenumber eta                             */
+#define SWIM_SP_OMEGA 9 /* beat angular frequency omega                    */
+#define SWIM_SP_NPARAM 10
+
+typedef struct swim_sperm_shape {
+    int32_t n_flag;     /* points on the flagellum, >= 4                       */
+    int32_t n_head;     /* points on the head, even, >= 4                      */
+    int32_t n_swim;     /* swimmers per system, >= 1;
+                           n_swim * (n_flag + n_head) <= 512                   */
+    int32_t reserved;   /* 0                                                   */
+    double eps;         /* blob width, > 0                                     */
+    double head_radius; /* H_r > 0                                             */
+    double neck_gap;    /* dN > 0: gap between the last flagellum point and
+                           the head                                            */
+} swim_sperm_shape;
+
+/* Runs n_sys independent systems of the full sperm model for `steps`
+ * forward-Euler steps of size dt.  Each step, at t = step*dt: forces of
+ * every swimmer, velocity sum over all points of the system, Euler update.
+ * sys_params  device double[n_sys][SWIM_SP_NPARAM].
+ * swim_params device double[n_sys * n_swim][3]: x0, y0 (first flagellum
+ *             point) and beat phase of each swimmer, systems in order.
+ * head, tail  device dtype[n_sys * n_swim][n_obs + 1][2], n_obs =
+ *             steps/obs_every (0 if obs_every == 0).  Sample 0 is the
+ *             initial state; sample j follows step j*obs_every.  head is
+ *             the head centre (mean of the head points) and tail is the
+ *             tail end (flagellum point 0).  Samples a stopped run does not
+ *             reach are NaN.
+ * status      device int32[n_sys]: SWIM_ST_* per system.  A row with
+ *             non-finite values, alpha < 0 or alpha*eps > 1 gets
+ *             SWIM_ST_BADPARAM and is not run.
+ * Systems run in a persistent kernel, one workgroup per system.
+ * SWIM_OPT_WPS set to 2, 4 or 8 selects its waves per system (otherwise 2
+ * for SWIM_F32 and 8 for SWIM_F64).
+ * SWIM_EINVAL for a bad shape or run length.  Asynchronous. */
+int swim_sperm_forward(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const swim_sperm_shape *shape,
+                       const double *sys_params, const double *swim_params, int32_t steps, double dt,
+                       int32_t obs_every, void *head, void *tail, int32_t *status, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Surrogate of the forward model (not in the paper; prescreens ABC
  * proposals): an MLP 5 -> 256 -> 256 -> 256 -> 256 -> 33 with GELU
  * x Phi(x) on the hidden layers.  Inputs (alpha, ln S_b, ln S_s, b, omega),

@@ -786,6 +786,82 @@ int swim_forward(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
     return forward_impl(c, dtype, n_sys, N, n_swim, params, r, obs, speed, status, steps_done, pick(c, stream));
 }
 
+int swim_sperm_forward(swim_ctx* c, int32_t dtype, int64_t n_sys, const swim_sperm_shape* shape,
+                       const double* sys_params, const double* swim_params, int32_t steps, double dt,
+                       int32_t obs_every, void* head, void* tail, int32_t* status, void* stream)
+{
+    TRY(check_ctx(c));
+    TRY(check_dtype(dtype));
+    if (!shape) return fail(SWIM_EINVAL, "null shape");
+    const swim_sperm_shape& sh = *shape;
+    if (n_sys < 0) return fail(SWIM_EINVAL, "n_sys < 0");
+    if (sh.n_flag < 4) return fail(SWIM_EINVAL, "n_flag must be >= 4");
+    if (sh.n_head < 4 || sh.n_head % 2) return fail(SWIM_EINVAL, "n_head must be even and >= 4");
+    if (sh.n_swim < 1) return fail(SWIM_EINVAL, "n_swim must be >= 1");
+    if ((int64_t)sh.n_swim * (sh.n_flag + sh.n_head) > 512)
+        return fail(SWIM_EINVAL, "n_swim * (n_flag + n_head) must be <= 512");
+    if (!(std::isfinite(sh.eps) && sh.eps > 0)) return fail(SWIM_EINVAL, "eps must be finite and > 0");
+    if (!(std::isfinite(sh.head_radius) && sh.head_radius > 0)) return fail(SWIM_EINVAL, "head_radius must be > 0");
+    if (!(std::isfinite(sh.neck_gap) && sh.neck_gap > 0)) return fail(SWIM_EINVAL, "neck_gap must be > 0");
+    if (steps < 1) return fail(SWIM_EINVAL, "steps must be >= 1");
+    if (!(std::isfinite(dt) && dt > 0)) return fail(SWIM_EINVAL, "dt must be finite and > 0");
+    if (obs_every < 0) return fail(SWIM_EINVAL, "obs_every must be >= 0");
+    if (n_sys == 0) return SWIM_OK;
+    if (!sys_params || !swim_params || !head || !tail || !status) return fail(SWIM_EINVAL, "null device pointer");
+    const hipStream_t st = pick(c, stream);
+    SpermShape g{};
+    g.nf = sh.n_flag;
+    g.nh = sh.n_head;
+    g.nsw = sh.n_swim;
+    g.ds = 1.0 / (double)(sh.n_flag - 1);
+    g.hr = sh.head_radius;
+    g.dn = sh.neck_gap;
+    g.dth = 2.0 * M_PI / (double)sh.n_head;
+    g.ch = 2.0 * sh.head_radius * std::sin(0.5 * g.dth);
+    g.eps = sh.eps;
+    {
+        // neck rest lengths from the initial geometry (first flagellum point
+        // at the origin)
+        const double xf1 = (double)(sh.n_flag - 1) * g.ds, xf2 = (double)(sh.n_flag - 2) * g.ds;
+        const double xc = xf1 + g.hr + g.dn;
+        const int c0 = sh.n_head / 2;
+        auto hx = [&](int m) { return xc + g.hr * std::cos((double)m * g.dth); };
+        auto hy = [&](int m) { return g.hr * std::sin((double)m * g.dth); };
+        g.L0[0] = std::hypot(hx(c0 - 1) - xf1, hy(c0 - 1));
+        g.L0[1] = std::hypot(hx(c0) - xf1, hy(c0));
+        g.L0[2] = std::hypot(hx(c0 + 1) - xf1, hy(c0 + 1));
+        g.L0[3] = std::hypot(hx(c0 - 1) - xf2, hy(c0 - 1));
+        g.L0[4] = std::hypot(hx(c0 + 1) - xf2, hy(c0 + 1));
+    }
+    SpermRun r{};
+    r.n_sys = n_sys;
+    r.sysp = sys_params;
+    r.swp = swim_params;
+    r.steps = steps;
+    r.dt = dt;
+    r.obs_every = obs_every;
+    r.n_obs = obs_every > 0 ? steps / obs_every : 0;
+    const int n = sh.n_swim * (sh.n_flag + sh.n_head);
+    const int tpl = choose_tpl(n);
+    // measured on 2048 systems of one and two swimmers: FP32 is fastest with
+    // two waves per system, FP64 with eight
+    int wps = dtype == SWIM_F32 ? 2 : 8;
+    if (c->opt_wps == 2 || c->opt_wps == 4 || c->opt_wps == 8) wps = c->opt_wps;
+    void *sysc, *sysc64;
+    TRY(sysconst_buffers(c, dtype, n_sys, &sysc, &sysc64));
+    if (dtype == SWIM_F32) TRY(ensure(c, B_TAB, (size_t)n_sys * table_bytes()));
+    TRY(ensure(c, B_QUEUE, 8 * 4));
+    HIPCHK(prepare_sperm(dtype, tpl, wps));
+    const int per_cu = sperm_blocks_per_cu(dtype, tpl, wps);
+    const int nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(n_sys, (int64_t)per_cu * c->num_cu));
+    HIPCHK(launch_sperm_setup(dtype, n_sys, sh.n_swim, sh.eps, sys_params, swim_params, sysc, sysc64, status, st));
+    if (dtype == SWIM_F32) HIPCHK(launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, st));
+    HIPCHK(launch_fill_i32((int32_t*)c->buf[B_QUEUE].p, 0, 8, st));
+    HIPCHK(launch_sperm_forward(dtype, tpl, wps, nblocks, g, r, sysc, dtype == SWIM_F32 ? c->buf[B_TAB].p : nullptr,
+                                (int32_t*)c->buf[B_QUEUE].p, head, tail, status, st));
+    return SWIM_OK;
+}
+
 int abc_distance(swim_ctx* c, int32_t dtype, int64_t n, int32_t n_obs, const void* obs, const double* data,
                  const int32_t* status, double* dist, void* stream)
 {

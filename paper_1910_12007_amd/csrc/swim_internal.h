@@ -138,4 +138,30 @@ hipError_t launch_mlp_fused(int mode, int64_t M, const float* X, const uint16_t*
                             const float* out_mu, const float* out_sd, const float* obs, int n_sum, float tol,
                             float* dist, uint8_t* keep, hipStream_t st);
 
+// full sperm model (swim_sperm.hip): shape shared by all systems of a call
+struct SpermShape {
+    int32_t nf, nh, nsw, pad;   // flagellum points, head points, swimmers per system
+    double ds, ch, hr, dn, dth; // 1/(nf-1), head chord, head radius, neck gap, 2 pi/nh
+    double eps;                 // blob width
+    double L0[5];               // neck rest lengths (last flagellum point to pi-dth, pi,
+                                // pi+dth; the one before to pi-dth, pi+dth)
+};
+struct SpermRun {
+    int64_t n_sys;
+    const double* sysp;  // [n_sys][SWIM_SP_NPARAM]
+    const double* swp;   // [n_sys * nsw][3]: x0, y0, phase
+    int32_t steps, obs_every, n_obs, pad;
+    double dt;
+};
+hipError_t launch_sperm_setup(int dtype, int64_t n_sys, int32_t nsw, double eps, const double* sysp,
+                              const double* swp, void* sysc, void* sysc64, int32_t* status, hipStream_t st);
+size_t sperm_lds_bytes(int dtype, int tpl, int wps);
+hipError_t prepare_sperm(int dtype, int tpl, int wps);
+int sperm_blocks_per_cu(int dtype, int tpl, int wps);
+// persistent run, one workgroup of wps wavefronts per system (tpl in
+// {1,2,3,4,6,8}, wps in {2,4,8})
+hipError_t launch_sperm_forward(int dtype, int tpl, int wps, int nblocks, const SpermShape& g, const SpermRun& r,
+                                const void* sysc, const void* tabs, int32_t* queue, void* head, void* tail,
+                                int32_t* status, hipStream_t st);
+
 }  // namespace swim

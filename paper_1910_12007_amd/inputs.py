@@ -16,6 +16,11 @@ ds = 1/(N-1), blob width eps = 1.5 ds, initially straight along x):
   dense    64 samples x 8 swimmers x N=512 on a 2x4 grid (spacing 1.5),
            phases~U[0,2pi), alpha~U[0,10].
   surrogate 65536 training runs (N=128) and 1M prescreened proposals.
+  sperm    full sperm model (Appendix, Table Tab:param): N_F = 50, N_H = 24,
+           eps = 0.045, K_tens = K_H,tens = K_N,ang = 1e4, K_N,tens = 500,
+           K_H,C = 0.8, a = 0.1, eta = 2 pi, omega = 4 pi; (alpha, K_C) ~
+           U[0,2] x U[0,16] (the paper's prior box); one swimmer, or two
+           swimmers with head centres d apart vertically, same beat phase.
 """
 import numpy as np
 
@@ -151,3 +156,37 @@ def unflatten(flat, layers=MLP_LAYERS):
 def epoch_permutations(n, epochs, seed=4):
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)
+
+
+# full sperm model: Table Tab:param constants (system row order SPERM_FIELDS)
+SPERM_FIELDS = ("alpha", "KC", "KT", "KHT", "KHC", "KNT", "KNA", "a", "eta", "omega")
+SPERM_TABLE = dict(alpha=1.0, KC=8.0, KT=1e4, KHT=1e4, KHC=0.8, KNT=500.0, KNA=1e4, a=0.1, eta=TWO_PI,
+                   omega=2.0 * TWO_PI)
+SPERM_PRIOR_LO = np.array([0.0, 0.0])   # (alpha, K_C)
+SPERM_PRIOR_HI = np.array([2.0, 16.0])
+
+
+def sperm_rows(n, seed=None, **overrides):
+    """(n, 10) system rows: Table values, (alpha, K_C) drawn from the prior box
+    when seed is given, then the overrides."""
+    P = np.empty((n, len(SPERM_FIELDS)))
+    for i, f in enumerate(SPERM_FIELDS):
+        P[:, i] = SPERM_TABLE[f]
+    if seed is not None:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        P[:, 0] = rng.uniform(SPERM_PRIOR_LO[0], SPERM_PRIOR_HI[0], n)
+        P[:, 1] = rng.uniform(SPERM_PRIOR_LO[1], SPERM_PRIOR_HI[1], n)
+    for f, v in overrides.items():
+        P[:, SPERM_FIELDS.index(f)] = v
+    return P
+
+
+def sperm_swimmers(n_sys, n_swim=1, d=0.5, phases=None):
+    """(n_sys * n_swim, 3) swimmer rows (x0, y0, phase): swimmers of one
+    system stacked vertically d apart (centred on y = 0), all starting at
+    x0 = 0; phases per swimmer (default 0)."""
+    W = np.zeros((n_sys, n_swim, 3))
+    W[:, :, 1] = (np.arange(n_swim) - 0.5 * (n_swim - 1)) * d
+    if phases is not None:
+        W[:, :, 2] = np.asarray(phases)
+    return W.reshape(-1, 3)

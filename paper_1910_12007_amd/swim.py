@@ -19,6 +19,9 @@ SWIM_ST_OK, SWIM_ST_NONFINITE, SWIM_ST_BOUND, SWIM_ST_BADPARAM = 0, 1, 2, 3
 SWIM_NPARAM = 9
 SWIM_OPT_WPS, SWIM_OPT_BIG_TPL, SWIM_OPT_GRAPH, SWIM_OPT_GRAPH_LAUNCHES, SWIM_OPT_GRAPH_CAPTURES = 1, 2, 3, 4, 5
 SWIM_MLP_NPARAM, SWIM_MLP_IN, SWIM_MLP_OUT = 207393, 5, 33
+# full sperm model: system row fields (SWIM_SP_*) and swimmer row width
+SPERM_FIELDS = ("alpha", "KC", "KT", "KHT", "KHC", "KNT", "KNA", "a", "eta", "omega")
+SWIM_SP_NPARAM, SWIM_SW_NPARAM = 10, 3
 
 _c = ctypes
 _P = _c.c_void_p
@@ -43,6 +46,8 @@ SIGNATURES = {
     "swim_elastic_forces": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I32P, _DP, _c.c_double, _P, _P, _P, _P, _P]),
     "swim_forward": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I32P, _I32P, _P, _c.c_int32, _c.c_double,
                                 _c.c_int32, _c.c_double, _P, _P, _P, _P, _P]),
+    "swim_sperm_forward": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _P, _P, _P, _c.c_int32, _c.c_double, _c.c_int32,
+                                      _P, _P, _P, _P]),
     "abc_distance": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _c.c_int32, _P, _P, _P, _P, _P]),
     "abc_select": (_c.c_int, [_P, _c.c_int64, _P, _c.c_double, _P, _P, _P]),
     "abc_prior_draw": (_c.c_int, [_c.c_uint64, _c.c_int64, _c.c_int32, _DP, _DP, _DP]),
@@ -428,3 +433,27 @@ def abc_prescreened(ctx, model, N, params, in_mu, in_sd, out_mu, out_sd, sum_idx
     n = min(n_surv.value, cap)
     return dict(n_surv=n_surv.value, theta=theta[:n], dist=dist[:n], accept=acc[:n].astype(bool),
                 ms_prescreen=float(ms[0]), ms_rerun=float(ms[1]))
+
+
+class swim_sperm_shape(ctypes.Structure):
+    _fields_ = [("n_flag", ctypes.c_int32), ("n_head", ctypes.c_int32), ("n_swim", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("eps", ctypes.c_double), ("head_radius", ctypes.c_double),
+                ("neck_gap", ctypes.c_double)]
+
+
+def sperm_shape(n_flag=50, n_head=24, n_swim=1, eps=0.045, head_radius=0.05, neck_gap=None):
+    """Shape of the full sperm model (defaults: Table Tab:param sizes and
+    blob; head radius 0.05 and neck gap ds, which the paper does not state)."""
+    return swim_sperm_shape(int(n_flag), int(n_head), int(n_swim), 0, float(eps), float(head_radius),
+                            float(1.0 / (n_flag - 1) if neck_gap is None else neck_gap))
+
+
+def swim_sperm_forward(ctx, dtype, shape, sys_params, swim_params, steps, dt, obs_every, head, tail, status,
+                       stream=None):
+    """sys_params device float64 (n_sys, 10); swim_params device float64
+    (n_sys * n_swim, 3); head, tail device tensors (n_sys * n_swim,
+    n_obs + 1, 2) of the run's dtype; status device int32 (n_sys,)."""
+    n_sys = status.numel()
+    return _check(lib().swim_sperm_forward(ctx.handle, int(dtype), n_sys, ctypes.byref(shape), _dptr(sys_params),
+                                           _dptr(swim_params), int(steps), float(dt), int(obs_every), _dptr(head),
+                                           _dptr(tail), _dptr(status), _stream(stream)))
