@@ -282,6 +282,59 @@ def tmcmc_leg(ctx, data, n=2048, seed=7):
             "z_scores_of_truth": ((truth - th.mean(0)) / th.std(0)).tolist()}
 
 
+def sperm_leg(ctx, stream, n=2000, steps=20000, dt=1e-5):
+    """Full sperm model (Appendix, Table Tab:param): one TMCMC stage's batch
+    of the paper's experiments, n = 2000 systems with (alpha, K_C) ~
+    U[0,2] x U[0,16] (seed 11), FP32, dt = 1e-5 (the Table's stiffnesses
+    diverge at the Table's dt).  The paper's run to T = 20 is 2M steps; the
+    leg times `steps` of them, all identical in work, and states the
+    extrapolation to a whole stage.  Configurations: one swimmer (74 points)
+    and two swimmers with head centres 0.5 apart (148 points).
+
+    Roofline: VALU issue bound.  Algorithmic work is n_pts^2 ordered pairs
+    per system step at VALU_OPS_PER_PAIR lane-operations each.  The
+    symmetric schedule evaluates 64-point blocks (32 B^2 offsets of 64
+    lanes, B = ceil(n_pts/64)), including padding, at 2 VALU_OPS_PER_PAIR
+    per evaluation; frac_scheduled is that work's share of peak."""
+    import torch
+    from paper_1910_12007_amd import inputs, swim
+    rows = torch.from_numpy(inputs.sperm_rows(n, seed=11)).to("cuda")
+    out = {"workload": f"full sperm model, {n} systems (alpha, K_C) ~ U[0,2]xU[0,16], FP32, {steps} Euler steps "
+                       f"of dt={dt} (T = 20 needs {int(round(20 / dt))})"}
+    for n_swim in (1, 2):
+        sw = torch.from_numpy(inputs.sperm_swimmers(n, n_swim, 0.5)).to("cuda")
+        oe = steps // 50
+        head = torch.empty((n * n_swim, 51, 2), dtype=torch.float32, device="cuda")
+        tail = torch.empty_like(head)
+        status = torch.empty(n, dtype=torch.int32, device="cuda")
+        shape = swim.sperm_shape(n_swim=n_swim)
+        swim.swim_sperm_forward(ctx, swim.SWIM_F32, shape, rows, sw, 100, dt, 2, head, tail, status,
+                                stream=stream)  # warm-up
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        swim.swim_sperm_forward(ctx, swim.SWIM_F32, shape, rows, sw, steps, dt, oe, head, tail, status, stream=stream)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1])
+        npts = n_swim * 74
+        B = (npts + 63) // 64
+        st = status.cpu().numpy()
+        pairs = float(n) * npts * npts * steps
+        sched = float(n) * 32 * B * B * 64 * steps
+        tops = VALU_OPS_PER_PAIR * pairs / (ms * 1e-3) / 1e12
+        out[f"{n_swim}_swimmer" + ("s" if n_swim > 1 else "")] = {
+            "points_per_system": npts, "ms": ms, "us_per_step": 1e3 * ms / steps,
+            "pair_evals_per_s": pairs / (ms * 1e-3), "swimmer_steps_per_s": float(n) * n_swim * steps / (ms * 1e-3),
+            "runs_stopped": int(np.sum(st != 0)),
+            "stage_seconds_to_T20": ms * 1e-3 * (20 / dt) / steps,
+            "roofline": {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS,
+                         "unit": "TOP/s (VALU lane-operations)", "frac": tops / VALU_PEAK_TOPS,
+                         "frac_scheduled": 2 * VALU_OPS_PER_PAIR * sched / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                         "kernel": "k_sperm_forward<float,%d,2>" % (1 if npts <= 64 else 2 if npts <= 128 else 3),
+                         "valu_ops_per_pair": VALU_OPS_PER_PAIR}}
+    return out
+
+
 def surrogate_leg(ctx, data):
     """Surrogate-prescreened ABC against plain batched ABC on the same 1M
     prior draws (tolerance: the 5th percentile of the completed runs of the
@@ -320,6 +373,7 @@ def main():
     ap.add_argument("--no-dense", action="store_true", help="skip the large-N dense workload")
     ap.add_argument("--no-pmc", action="store_true", help="skip the uneven-N PMC workload")
     ap.add_argument("--no-tmcmc", action="store_true", help="skip the TMCMC run")
+    ap.add_argument("--no-sperm", action="store_true", help="skip the full sperm-model workload")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times), the reference "
                          "for scaling the HBM byte counters, and exit")
@@ -428,6 +482,8 @@ def main():
         out["pmc_uneven"] = pmc_leg(ctx, load_data())
     if not args.no_tmcmc:
         out["tmcmc"] = tmcmc_leg(ctx, load_data())
+    if not args.no_sperm:
+        out["sperm"] = sperm_leg(ctx, stream)
     if not args.no_surrogate:
         out["surrogate_abc"] = surrogate_leg(ctx, load_data())
     if not args.no_cpu:
