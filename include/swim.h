@@ -383,6 +383,72 @@ int swim_sperm_forward(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const swim_s
                        const double *sys_params, const double *swim_params, int32_t steps, double dt,
                        int32_t obs_every, void *head, void *tail, int32_t *status, void *stream);
 
+/* Observables of the paper's experiments (Sec. 4) from a swim_sperm_forward
+ * run, for samples k = 1..n_obs:
+ *   SWIM_OBS_HEAD_VELOCITY   head-centre velocity of swimmer 0,
+ *                            (h_k - h_{k-1}) / dt_obs, x then y (Sec. 4.1);
+ *   SWIM_OBS_PAIR_DISTANCES  distance between the tail ends, then between
+ *                            the head centres, of swimmers 0 and 1 (Secs.
+ *                            4.2, 4.3; n_swim >= 2).
+ * head, tail device dtype[n_sys * n_swim][n_obs + 1][2] (swim_sperm_forward);
+ * status device int32[n_sys]; g device double[n_sys][n_obs][2] (written;
+ * NaN for systems whose status is not 0).  Asynchronous. */
+#define SWIM_OBS_HEAD_VELOCITY 0
+#define SWIM_OBS_PAIR_DISTANCES 1
+int swim_sperm_observables(swim_ctx *ctx, int32_t dtype, int32_t kind, int64_t n_sys, int32_t n_swim,
+                           int32_t n_obs, double dt_obs, const void *head, const void *tail,
+                           const int32_t *status, double *g, void *stream);
+
+/* Gaussian log-likelihood of eqs. (likelihood)-(fitness) with the diagonal
+ * covariance of Sec. 4.3.  Entries 0, 2, 4, ... (odd in the paper's 1-based
+ * numbering) have standard deviation sigma2[i][0]; entries 1, 3, ... have
+ * sigma2[i][1].  Equal values give Sigma = sigma^2 I.
+ *   log p = -n_obs log(2 pi) - n_obs (log s_a + log s_b)
+ *           - sum_a r^2 / (2 s_a^2) - sum_b r^2 / (2 s_b^2)
+ * g device double[n][n_obs][2]; data device double[n_obs][2];
+ * sigma2 device double[n][2]; status device int32[n] or NULL.
+ * logl device double[n] (written): -inf where status != 0, an output is not
+ * finite, or a sigma is not > 0.  Asynchronous. */
+int tmcmc_loglik2(swim_ctx *ctx, int64_t n, int32_t n_obs, const double *g, const double *data,
+                  const double *sigma2, const int32_t *status, double *logl, void *stream);
+
+/* TMCMC over the full sperm model (Sec. 4).  Each sample's forward run is
+ * one system of model->shape.n_swim swimmers placed by swim_rows.
+ * theta has n_theta = n_fields + n_sigma entries:
+ *   - entries 0 .. n_fields-1 set the system-row fields field[0..]; the
+ *     other fields keep sys_row;
+ *   - the last n_sigma entries are relative noise levels gamma = sigma/beta
+ *     (Sec. 4).  With n_sigma == 1: s_a = gamma beta[0], s_b = gamma beta[1].
+ *     With n_sigma == 2: s_a = gamma_a beta[0], s_b = gamma_b beta[1].
+ * The likelihood is that of tmcmc_loglik2 on the observables of `kind`.
+ * The stages, weights, resampling and chains are those of tmcmc_run over
+ * the n_theta parameters. */
+typedef struct sperm_tmcmc_model {
+    swim_sperm_shape shape;
+    double sys_row[SWIM_SP_NPARAM]; /* values of the fields not sampled          */
+    int32_t n_theta;                /* 2..4                                      */
+    int32_t n_sigma;                /* 1 or 2                                    */
+    int32_t field[3];               /* SWIM_SP_* set by theta[0..n_theta-n_sigma) */
+    int32_t kind;                   /* SWIM_OBS_*                                */
+    double beta[2];                 /* noise scales of entry types a and b, > 0 */
+    int32_t steps, obs_every;       /* n_obs = steps / obs_every >= 1            */
+    double dt;
+    int32_t dtype;                  /* SWIM_F32 or SWIM_F64                      */
+    int32_t reserved;               /* 0                                         */
+} sperm_tmcmc_model;
+
+/* One full TMCMC run over the sperm model (synchronous).  swim_rows: host
+ * double[n_swim][3] (x0, y0, phase) shared by all samples.  data: host
+ * double[n_obs][2] observables.  The prior box is opts->lo/hi[0..n_theta);
+ * the boxes of the noise levels must have lo >= 0.  Outputs as in tmcmc_run
+ * with n_theta columns: theta_out host double[n][n_theta], logl_out
+ * double[n], q_out double[max_stages + 1], accepted_out
+ * int64[max_stages]; runs_out and seconds_out may be NULL. */
+int tmcmc_sperm_run(swim_ctx *ctx, const sperm_tmcmc_model *model, const double *swim_rows,
+                    const tmcmc_opts *opts, const double *data, int32_t n_obs, int64_t n, uint64_t seed,
+                    double *theta_out, double *logl_out, double *q_out, int32_t *n_stages_out,
+                    double *log_evidence_out, int64_t *accepted_out, int64_t *runs_out, double *seconds_out);
+
 /* ---------------------------------------------------------------------------
  * Surrogate of the forward model (not in the paper; prescreens ABC
  * proposals): an MLP 5 -> 256 -> 256 -> 256 -> 256 -> 33 with GELU

@@ -216,3 +216,22 @@ def sperm_forward(sys_row, swimmers, nf, nh, eps, hr, dn, steps, dt, obs_every):
                                int(steps), float(dt), int(obs_every), _p(head), _p(tail), _p(x), _p(y),
                                ctypes.byref(st))
     return dict(head=head, tail=tail, x=x, y=y, status=int(st.value))
+
+
+def sperm_head_velocity(head, dt_obs):
+    """Sec. 4.1 observables: velocity of swimmer 0's head centre over each
+    sampling interval, (h_k - h_{k-1}) / dt_obs for k = 1..n_obs; head as
+    returned by sperm_forward.  (n_obs, 2)."""
+    h = np.asarray(head, dtype=np.float64)[0]
+    return (h[1:] - h[:-1]) / dt_obs
+
+
+def sperm_pair_distances(head, tail):
+    """Secs. 4.2-4.3 observables: at samples k = 1..n_obs, the distance
+    between the tail ends and between the head centres of swimmers 0 and 1,
+    in the order (tail, head).  (n_obs, 2)."""
+    h = np.asarray(head, dtype=np.float64)
+    t = np.asarray(tail, dtype=np.float64)
+    dt_ = np.linalg.norm(t[0, 1:] - t[1, 1:], axis=-1)
+    dh = np.linalg.norm(h[0, 1:] - h[1, 1:], axis=-1)
+    return np.stack([dt_, dh], axis=-1)

@@ -65,6 +65,27 @@ def gauss_loglik(g, D, sigma):
     return ll
 
 
+def gauss_loglik2(g, D, sigma_a, sigma_b):
+    """Log-likelihood of eqs. (likelihood)-(fitness) with the diagonal
+    covariance of Sec. 4.3: entries 0, 2, 4, ... (odd in 1-based numbering)
+    have standard deviation sigma_a, the others sigma_b.  g: (P, m) model
+    outputs (a row with a non-finite entry: -inf); D: (m,); sigma_a,
+    sigma_b: (P,) (a level that is not > 0: -inf)."""
+    g = np.asarray(g, dtype=np.float64)
+    g = g.reshape(g.shape[0], -1)
+    D = np.asarray(D, dtype=np.float64).ravel()
+    sa = np.asarray(sigma_a, dtype=np.float64)
+    sb = np.asarray(sigma_b, dtype=np.float64)
+    r2 = (D[None, :] - g) ** 2
+    Ja, Jb = r2[:, 0::2].sum(axis=1), r2[:, 1::2].sum(axis=1)
+    ma, mb = D[0::2].size, D[1::2].size
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ll = (-0.5 * (ma + mb) * np.log(2.0 * np.pi) - ma * np.log(sa) - mb * np.log(sb)
+              - 0.5 * Ja / sa ** 2 - 0.5 * Jb / sb ** 2)
+    ll[~np.all(np.isfinite(g), axis=1) | ~(sa > 0) | ~(sb > 0)] = -np.inf
+    return ll
+
+
 def weight_cv(logl, dq):
     """Coefficient of variation of the weights exp(dq (l - max l)) over the
     finite log-likelihoods."""

@@ -63,6 +63,7 @@ enum BufId {
     B_PARAMS, B_DATA, B_OBS, B_SPEED, B_STATUS, B_DIST, B_TOL, B_ACC, B_BIG,
     B_MLP_ACT, B_MLP_GRAD, B_MLP_BATCH, B_MLP_IDX, B_MLP_CNT,
     B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_TAB, B_DONE, B_W16, B_SIGMA, B_LOGL,
+    B_SP_SW, B_SP_HEAD, B_SP_TAIL, B_SP_G, B_SP_SIG,
     B_NBUF
 };
 
@@ -786,15 +787,14 @@ int swim_forward(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
     return forward_impl(c, dtype, n_sys, N, n_swim, params, r, obs, speed, status, steps_done, pick(c, stream));
 }
 
-int swim_sperm_forward(swim_ctx* c, int32_t dtype, int64_t n_sys, const swim_sperm_shape* shape,
-                       const double* sys_params, const double* swim_params, int32_t steps, double dt,
-                       int32_t obs_every, void* head, void* tail, int32_t* status, void* stream)
+}  // extern "C"
+
+namespace {
+
+int sperm_check(const swim_sperm_shape* shape, int32_t steps, double dt, int32_t obs_every)
 {
-    TRY(check_ctx(c));
-    TRY(check_dtype(dtype));
     if (!shape) return fail(SWIM_EINVAL, "null shape");
     const swim_sperm_shape& sh = *shape;
-    if (n_sys < 0) return fail(SWIM_EINVAL, "n_sys < 0");
     if (sh.n_flag < 4) return fail(SWIM_EINVAL, "n_flag must be >= 4");
     if (sh.n_head < 4 || sh.n_head % 2) return fail(SWIM_EINVAL, "n_head must be even and >= 4");
     if (sh.n_swim < 1) return fail(SWIM_EINVAL, "n_swim must be >= 1");
@@ -806,9 +806,12 @@ int swim_sperm_forward(swim_ctx* c, int32_t dtype, int64_t n_sys, const swim_spe
     if (steps < 1) return fail(SWIM_EINVAL, "steps must be >= 1");
     if (!(std::isfinite(dt) && dt > 0)) return fail(SWIM_EINVAL, "dt must be finite and > 0");
     if (obs_every < 0) return fail(SWIM_EINVAL, "obs_every must be >= 0");
-    if (n_sys == 0) return SWIM_OK;
-    if (!sys_params || !swim_params || !head || !tail || !status) return fail(SWIM_EINVAL, "null device pointer");
-    const hipStream_t st = pick(c, stream);
+    return SWIM_OK;
+}
+
+// geometry constants of a (checked) shape
+SpermShape sperm_geometry(const swim_sperm_shape& sh)
+{
     SpermShape g{};
     g.nf = sh.n_flag;
     g.nh = sh.n_head;
@@ -819,20 +822,28 @@ int swim_sperm_forward(swim_ctx* c, int32_t dtype, int64_t n_sys, const swim_spe
     g.dth = 2.0 * M_PI / (double)sh.n_head;
     g.ch = 2.0 * sh.head_radius * std::sin(0.5 * g.dth);
     g.eps = sh.eps;
-    {
-        // neck rest lengths from the initial geometry (first flagellum point
-        // at the origin)
-        const double xf1 = (double)(sh.n_flag - 1) * g.ds, xf2 = (double)(sh.n_flag - 2) * g.ds;
-        const double xc = xf1 + g.hr + g.dn;
-        const int c0 = sh.n_head / 2;
-        auto hx = [&](int m) { return xc + g.hr * std::cos((double)m * g.dth); };
-        auto hy = [&](int m) { return g.hr * std::sin((double)m * g.dth); };
-        g.L0[0] = std::hypot(hx(c0 - 1) - xf1, hy(c0 - 1));
-        g.L0[1] = std::hypot(hx(c0) - xf1, hy(c0));
-        g.L0[2] = std::hypot(hx(c0 + 1) - xf1, hy(c0 + 1));
-        g.L0[3] = std::hypot(hx(c0 - 1) - xf2, hy(c0 - 1));
-        g.L0[4] = std::hypot(hx(c0 + 1) - xf2, hy(c0 + 1));
-    }
+    // neck rest lengths from the initial geometry (first flagellum point at
+    // the origin)
+    const double xf1 = (double)(sh.n_flag - 1) * g.ds, xf2 = (double)(sh.n_flag - 2) * g.ds;
+    const double xc = xf1 + g.hr + g.dn;
+    const int c0 = sh.n_head / 2;
+    auto hx = [&](int m) { return xc + g.hr * std::cos((double)m * g.dth); };
+    auto hy = [&](int m) { return g.hr * std::sin((double)m * g.dth); };
+    g.L0[0] = std::hypot(hx(c0 - 1) - xf1, hy(c0 - 1));
+    g.L0[1] = std::hypot(hx(c0) - xf1, hy(c0));
+    g.L0[2] = std::hypot(hx(c0 + 1) - xf1, hy(c0 + 1));
+    g.L0[3] = std::hypot(hx(c0 - 1) - xf2, hy(c0 - 1));
+    g.L0[4] = std::hypot(hx(c0 + 1) - xf2, hy(c0 + 1));
+    return g;
+}
+
+// the launch sequence of a (checked) sperm run on stream st
+int sperm_forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const swim_sperm_shape& sh,
+                       const double* sys_params, const double* swim_params, int32_t steps, double dt,
+                       int32_t obs_every, void* head, void* tail, int32_t* status, hipStream_t st)
+{
+    if (n_sys == 0) return SWIM_OK;
+    const SpermShape g = sperm_geometry(sh);
     SpermRun r{};
     r.n_sys = n_sys;
     r.sysp = sys_params;
@@ -843,7 +854,7 @@ int swim_sperm_forward(swim_ctx* c, int32_t dtype, int64_t n_sys, const swim_spe
     r.n_obs = obs_every > 0 ? steps / obs_every : 0;
     const int n = sh.n_swim * (sh.n_flag + sh.n_head);
     const int tpl = choose_tpl(n);
-    // measured on 2048 systems of one and two swimmers: FP32 is fastest with
+    // measured on 2000 systems of one and two swimmers: FP32 is fastest with
     // two waves per system, FP64 with eight
     int wps = dtype == SWIM_F32 ? 2 : 8;
     if (c->opt_wps == 2 || c->opt_wps == 4 || c->opt_wps == 8) wps = c->opt_wps;
@@ -859,6 +870,52 @@ int swim_sperm_forward(swim_ctx* c, int32_t dtype, int64_t n_sys, const swim_spe
     HIPCHK(launch_fill_i32((int32_t*)c->buf[B_QUEUE].p, 0, 8, st));
     HIPCHK(launch_sperm_forward(dtype, tpl, wps, nblocks, g, r, sysc, dtype == SWIM_F32 ? c->buf[B_TAB].p : nullptr,
                                 (int32_t*)c->buf[B_QUEUE].p, head, tail, status, st));
+    return SWIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swim_sperm_forward(swim_ctx* c, int32_t dtype, int64_t n_sys, const swim_sperm_shape* shape,
+                       const double* sys_params, const double* swim_params, int32_t steps, double dt,
+                       int32_t obs_every, void* head, void* tail, int32_t* status, void* stream)
+{
+    TRY(check_ctx(c));
+    TRY(check_dtype(dtype));
+    if (n_sys < 0) return fail(SWIM_EINVAL, "n_sys < 0");
+    TRY(sperm_check(shape, steps, dt, obs_every));
+    if (n_sys == 0) return SWIM_OK;
+    if (!sys_params || !swim_params || !head || !tail || !status) return fail(SWIM_EINVAL, "null device pointer");
+    return sperm_forward_impl(c, dtype, n_sys, *shape, sys_params, swim_params, steps, dt, obs_every, head, tail,
+                              status, pick(c, stream));
+}
+
+int swim_sperm_observables(swim_ctx* c, int32_t dtype, int32_t kind, int64_t n_sys, int32_t n_swim, int32_t n_obs,
+                           double dt_obs, const void* head, const void* tail, const int32_t* status, double* g,
+                           void* stream)
+{
+    TRY(check_ctx(c));
+    TRY(check_dtype(dtype));
+    if (kind != SWIM_OBS_HEAD_VELOCITY && kind != SWIM_OBS_PAIR_DISTANCES) return fail(SWIM_EINVAL, "unknown kind");
+    if (n_sys < 0 || n_obs < 1 || n_swim < 1) return fail(SWIM_EINVAL, "bad sizes");
+    if (kind == SWIM_OBS_PAIR_DISTANCES && n_swim < 2) return fail(SWIM_EINVAL, "distances need two swimmers");
+    if (kind == SWIM_OBS_HEAD_VELOCITY && !(std::isfinite(dt_obs) && dt_obs > 0))
+        return fail(SWIM_EINVAL, "dt_obs must be > 0");
+    if (n_sys == 0) return SWIM_OK;
+    if (!head || !tail || !status || !g) return fail(SWIM_EINVAL, "null device pointer");
+    HIPCHK(launch_sperm_observables(dtype, kind, n_sys, n_swim, n_obs, dt_obs, head, tail, status, g,
+                                    pick(c, stream)));
+    return SWIM_OK;
+}
+
+int tmcmc_loglik2(swim_ctx* c, int64_t n, int32_t n_obs, const double* g, const double* data, const double* sigma2,
+                  const int32_t* status, double* logl, void* stream)
+{
+    TRY(check_ctx(c));
+    if (n < 0 || n_obs < 1 || (n > 0 && (!g || !data || !sigma2 || !logl)))
+        return fail(SWIM_EINVAL, "bad log-likelihood arguments");
+    HIPCHK(launch_gauss_loglik2(n, n_obs, g, data, sigma2, status, logl, pick(c, stream)));
     return SWIM_OK;
 }
 
@@ -1689,6 +1746,162 @@ bool chol_d(const double* A, double* L, int d)
 }
 }  // namespace
 
+// The TMCMC stages over D <= TM_D parameters (the first D of the four
+// normals of each chain step are used).  evaluate(theta, k, logl) returns
+// the log-likelihoods of k parameter rows of D values.
+template <typename Eval>
+int tmcmc_core(int D, const tmcmc_opts* o, int64_t n, uint64_t seed, Eval&& evaluate, double* theta_out,
+               double* logl_out, double* q_out, int32_t* n_stages_out, double* log_evidence_out, int64_t* accepted_out)
+{
+    std::vector<double> theta((size_t)n * D), logl((size_t)n);
+    TRY(abc_prior_draw(seed, n, D, o->lo, o->hi, theta.data()));
+    TRY(evaluate(theta.data(), n, logl.data()));
+    q_out[0] = 0.0;
+    double q = 0.0, log_ev = 0.0;
+    int stage_no = 0;
+    std::vector<double> w((size_t)n), cdf((size_t)n), nth((size_t)n * D), nll((size_t)n);
+    std::vector<int64_t> counts((size_t)n);
+    for (; stage_no < o->max_stages && q < 1.0; ++stage_no) {
+        double lmax = -INFINITY;
+        for (double v : logl)
+            if (std::isfinite(v)) lmax = std::max(lmax, v);
+        if (!std::isfinite(lmax)) return fail(SWIM_EINVAL, "no sample has a finite likelihood");
+        // tempering increment: the largest dq with weight CV <= cv_target
+        double dq;
+        if (tm_weight_cv(logl, lmax, 1.0 - q) <= o->cv_target) {
+            dq = 1.0 - q;
+        } else {
+            double lo = 0.0, hi = 1.0 - q;
+            for (int it = 0; it < TM_BISECT; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (tm_weight_cv(logl, lmax, mid) > o->cv_target)
+                    hi = mid;
+                else
+                    lo = mid;
+            }
+            dq = lo;
+        }
+        const double q_next = (dq == 1.0 - q) ? 1.0 : q + dq;
+        dq = q_next - q;  // the increment the weights use: from the rounded q_next
+        // weights, S_j, weighted mean and covariance
+        double W = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            w[i] = std::isfinite(logl[i]) ? std::exp(dq * (logl[i] - lmax)) : 0.0;
+            W += w[i];
+        }
+        log_ev += dq * lmax + std::log(W / (double)n);
+        double mu[TM_D] = {}, cov[TM_D * TM_D] = {}, L[TM_D * TM_D];  // D <= TM_D used
+        for (int64_t i = 0; i < n; ++i)
+            for (int d = 0; d < D; ++d) mu[d] += (w[i] / W) * theta[D * i + d];
+        for (int64_t i = 0; i < n; ++i) {
+            const double wb = w[i] / W;
+            for (int d = 0; d < D; ++d)
+                for (int e = 0; e < D; ++e)
+                    cov[D * d + e] += wb * (theta[D * i + d] - mu[d]) * (theta[D * i + e] - mu[e]);
+        }
+        const double b2 = o->cov_scale * o->cov_scale;
+        for (int i = 0; i < D * D; ++i) cov[i] *= b2;
+        if (!chol_d(cov, L, D)) {
+            for (int d = 0; d < D; ++d) cov[D * d + d] += 1e-12 * (o->hi[d] - o->lo[d]) * (o->hi[d] - o->lo[d]);
+            if (!chol_d(cov, L, D)) return fail(SWIM_EINVAL, "proposal covariance is not positive definite");
+        }
+        // resampling: n multinomial draws by the normalized weights
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            acc += w[i] / W;
+            cdf[i] = acc;
+            counts[i] = 0;
+        }
+        for (int64_t k = 0; k < n; ++k) {
+            double u[2];
+            uniforms2(seed, 1000u + 2u * (uint32_t)stage_no, (uint64_t)k, 0, u);
+            int64_t j = std::upper_bound(cdf.begin(), cdf.end(), u[0] * cdf.back()) - cdf.begin();
+            if (j >= n) j = n - 1;
+            ++counts[j];
+        }
+        // Metropolis chains, one per drawn sample, stepped together
+        std::vector<int64_t> start, len, off;
+        int64_t maxlen = 0, pos = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (counts[i]) {
+                start.push_back(i);
+                len.push_back(counts[i]);
+                off.push_back(pos);
+                pos += counts[i];
+                maxlen = std::max(maxlen, counts[i]);
+            }
+        const int64_t nc = (int64_t)start.size();
+        std::vector<double> cur((size_t)nc * D), lcur((size_t)nc), prop, uacc, lprop;
+        std::vector<int64_t> act;
+        for (int64_t ch = 0; ch < nc; ++ch) {
+            for (int d = 0; d < D; ++d) cur[D * ch + d] = theta[D * start[ch] + d];
+            lcur[ch] = logl[start[ch]];
+        }
+        int64_t accepted = 0;
+        const uint32_t cstream = 1001u + 2u * (uint32_t)stage_no;
+        for (int64_t s = 1; s <= maxlen; ++s) {
+            act.clear();
+            for (int64_t ch = 0; ch < nc; ++ch)
+                if (len[ch] >= s) act.push_back(ch);
+            const int64_t na = (int64_t)act.size();
+            prop.resize((size_t)na * D);
+            uacc.resize((size_t)na);
+            std::vector<char> inbox((size_t)na);
+            std::vector<double> batch;
+            for (int64_t a = 0; a < na; ++a) {
+                const int64_t ch = act[a];
+                double u01[2], u23[2], u45[2], z[4];
+                const uint32_t base = 3u * (uint32_t)(s - 1);
+                uniforms2(seed, cstream, (uint64_t)ch, base, u01);
+                uniforms2(seed, cstream, (uint64_t)ch, base + 1, u23);
+                uniforms2(seed, cstream, (uint64_t)ch, base + 2, u45);
+                box_muller(u01[0], u01[1], &z[0], &z[1]);
+                box_muller(u23[0], u23[1], &z[2], &z[3]);
+                uacc[a] = u45[0];
+                bool in = true;
+                for (int d = 0; d < D; ++d) {
+                    double v = cur[D * ch + d];
+                    for (int e = 0; e <= d; ++e) v += L[D * d + e] * z[e];
+                    prop[D * a + d] = v;
+                    in = in && v >= o->lo[d] && v <= o->hi[d];
+                }
+                inbox[a] = in;
+                if (in) batch.insert(batch.end(), &prop[D * a], &prop[D * a] + D);
+            }
+            const int64_t nb = (int64_t)batch.size() / D;
+            lprop.assign((size_t)nb, -INFINITY);
+            TRY(evaluate(batch.data(), nb, lprop.data()));
+            int64_t bi = 0;
+            for (int64_t a = 0; a < na; ++a) {
+                const int64_t ch = act[a];
+                if (inbox[a]) {
+                    const double lp = lprop[bi++];
+                    if (std::log(uacc[a]) < q_next * (lp - lcur[ch])) {
+                        for (int d = 0; d < D; ++d) cur[D * ch + d] = prop[D * a + d];
+                        lcur[ch] = lp;
+                        ++accepted;
+                    }
+                }
+                const int64_t at = off[ch] + s - 1;
+                for (int d = 0; d < D; ++d) nth[D * at + d] = cur[D * ch + d];
+                nll[at] = lcur[ch];
+            }
+        }
+        theta.swap(nth);
+        logl.swap(nll);
+        nth.resize((size_t)n * D);
+        nll.resize((size_t)n);
+        accepted_out[stage_no] = accepted;
+        q = q_next;
+        q_out[stage_no + 1] = q;
+    }
+    memcpy(theta_out, theta.data(), theta.size() * 8);
+    memcpy(logl_out, logl.data(), logl.size() * 8);
+    *n_stages_out = stage_no;
+    *log_evidence_out = log_ev;
+    return SWIM_OK;
+}
+
 int tmcmc_run(swim_ctx* c, const abc_model* m, const tmcmc_opts* o, const double* data, int32_t n_obs, int32_t N,
               int64_t n, uint64_t seed, double* theta_out, double* logl_out, double* q_out, int32_t* n_stages_out,
               double* log_evidence_out, int64_t* accepted_out, int64_t* runs_out, double* seconds_out)
@@ -1765,152 +1978,97 @@ int tmcmc_run(swim_ctx* c, const abc_model* m, const tmcmc_opts* o, const double
         t_eval += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         return SWIM_OK;
     };
-    std::vector<double> theta((size_t)n * TM_D), logl((size_t)n);
-    TRY(abc_prior_draw(seed, n, TM_D, o->lo, o->hi, theta.data()));
-    TRY(evaluate(theta.data(), n, logl.data()));
-    q_out[0] = 0.0;
-    double q = 0.0, log_ev = 0.0;
-    int stage_no = 0;
-    std::vector<double> w((size_t)n), cdf((size_t)n), nth((size_t)n * TM_D), nll((size_t)n);
-    std::vector<int64_t> counts((size_t)n);
-    for (; stage_no < o->max_stages && q < 1.0; ++stage_no) {
-        double lmax = -INFINITY;
-        for (double v : logl)
-            if (std::isfinite(v)) lmax = std::max(lmax, v);
-        if (!std::isfinite(lmax)) return fail(SWIM_EINVAL, "no sample has a finite likelihood");
-        // tempering increment: the largest dq with weight CV <= cv_target
-        double dq;
-        if (tm_weight_cv(logl, lmax, 1.0 - q) <= o->cv_target) {
-            dq = 1.0 - q;
-        } else {
-            double lo = 0.0, hi = 1.0 - q;
-            for (int it = 0; it < TM_BISECT; ++it) {
-                const double mid = 0.5 * (lo + hi);
-                if (tm_weight_cv(logl, lmax, mid) > o->cv_target)
-                    hi = mid;
-                else
-                    lo = mid;
-            }
-            dq = lo;
+    TRY(tmcmc_core(TM_D, o, n, seed, evaluate, theta_out, logl_out, q_out, n_stages_out, log_evidence_out,
+                   accepted_out));
+    if (runs_out) *runs_out = runs;
+    if (seconds_out) *seconds_out = t_eval;
+    return SWIM_OK;
+}
+
+// TMCMC over the full sperm model (Sec. 4): the stages of tmcmc_core; each
+// likelihood is a sperm forward run, the observables of model->kind and the
+// two-level Gaussian likelihood on the device.
+int tmcmc_sperm_run(swim_ctx* c, const sperm_tmcmc_model* m, const double* swim_rows, const tmcmc_opts* o,
+                    const double* data, int32_t n_obs, int64_t n, uint64_t seed, double* theta_out, double* logl_out,
+                    double* q_out, int32_t* n_stages_out, double* log_evidence_out, int64_t* accepted_out,
+                    int64_t* runs_out, double* seconds_out)
+{
+    TRY(check_ctx(c));
+    if (!m || !o || !swim_rows || !data || !theta_out || !logl_out || !q_out || !n_stages_out || !log_evidence_out ||
+        !accepted_out)
+        return fail(SWIM_EINVAL, "null argument");
+    TRY(check_dtype(m->dtype));
+    TRY(sperm_check(&m->shape, m->steps, m->dt, m->obs_every));
+    const int d = m->n_theta, ns = m->n_sigma, nf = d - ns;
+    if (d < 2 || d > TM_D) return fail(SWIM_EINVAL, "n_theta must be in [2, 4]");
+    if (ns < 1 || ns > 2 || nf < 1) return fail(SWIM_EINVAL, "n_sigma must be 1 or 2, with at least one model field");
+    for (int i = 0; i < nf; ++i)
+        if (m->field[i] < 0 || m->field[i] >= SWIM_SP_NPARAM) return fail(SWIM_EINVAL, "bad field index");
+    if (m->kind != SWIM_OBS_HEAD_VELOCITY && m->kind != SWIM_OBS_PAIR_DISTANCES)
+        return fail(SWIM_EINVAL, "unknown observable kind");
+    if (m->kind == SWIM_OBS_PAIR_DISTANCES && m->shape.n_swim < 2) return fail(SWIM_EINVAL, "distances need two swimmers");
+    if (!(m->beta[0] > 0 && m->beta[1] > 0 && std::isfinite(m->beta[0]) && std::isfinite(m->beta[1])))
+        return fail(SWIM_EINVAL, "beta must be finite and > 0");
+    if (m->obs_every < 1 || n_obs != m->steps / m->obs_every) return fail(SWIM_EINVAL, "n_obs must equal steps/obs_every");
+    if (n < 2) return fail(SWIM_EINVAL, "n must be >= 2");
+    if (o->max_stages < 1) return fail(SWIM_EINVAL, "max_stages must be >= 1");
+    if (!(o->cv_target > 0 && std::isfinite(o->cv_target))) return fail(SWIM_EINVAL, "cv_target must be > 0");
+    if (!(o->cov_scale > 0 && std::isfinite(o->cov_scale))) return fail(SWIM_EINVAL, "cov_scale must be > 0");
+    for (int k = 0; k < d; ++k)
+        if (!(std::isfinite(o->lo[k]) && std::isfinite(o->hi[k]) && o->hi[k] > o->lo[k]))
+            return fail(SWIM_EINVAL, "bad prior box");
+    for (int k = nf; k < d; ++k)
+        if (!(o->lo[k] >= 0)) return fail(SWIM_EINVAL, "the prior box of a noise level must be >= 0");
+    const int nsw = m->shape.n_swim;
+    const size_t es = m->dtype == SWIM_F32 ? 4 : 8;
+    const double dt_obs = m->dt * (double)m->obs_every;
+    hipStream_t st = c->stream;
+    double t_eval = 0.0;
+    int64_t runs = 0;
+    std::vector<double> rows, sw, sig;
+    auto evaluate = [&](const double* th, int64_t k, double* ll) -> int {
+        if (k == 0) return SWIM_OK;
+        const auto t0 = std::chrono::steady_clock::now();
+        rows.resize((size_t)k * SWIM_SP_NPARAM);
+        sw.resize((size_t)k * nsw * 3);
+        sig.resize((size_t)k * 2);
+        for (int64_t i = 0; i < k; ++i) {
+            double* P = &rows[(size_t)i * SWIM_SP_NPARAM];
+            for (int f = 0; f < SWIM_SP_NPARAM; ++f) P[f] = m->sys_row[f];
+            for (int f = 0; f < nf; ++f) P[m->field[f]] = th[(size_t)d * i + f];
+            memcpy(&sw[(size_t)i * nsw * 3], swim_rows, sizeof(double) * nsw * 3);
+            const double ga = th[(size_t)d * i + nf], gb = th[(size_t)d * i + d - 1];
+            sig[2 * i] = ga * m->beta[0];
+            sig[2 * i + 1] = gb * m->beta[1];
         }
-        const double q_next = (dq == 1.0 - q) ? 1.0 : q + dq;
-        dq = q_next - q;  // the increment the weights use: from the rounded q_next
-        // weights, S_j, weighted mean and covariance
-        double W = 0.0;
-        for (int64_t i = 0; i < n; ++i) {
-            w[i] = std::isfinite(logl[i]) ? std::exp(dq * (logl[i] - lmax)) : 0.0;
-            W += w[i];
-        }
-        log_ev += dq * lmax + std::log(W / (double)n);
-        double mu[TM_D] = {}, cov[TM_D * TM_D] = {}, L[TM_D * TM_D];
-        for (int64_t i = 0; i < n; ++i)
-            for (int d = 0; d < TM_D; ++d) mu[d] += (w[i] / W) * theta[TM_D * i + d];
-        for (int64_t i = 0; i < n; ++i) {
-            const double wb = w[i] / W;
-            for (int d = 0; d < TM_D; ++d)
-                for (int e = 0; e < TM_D; ++e)
-                    cov[TM_D * d + e] += wb * (theta[TM_D * i + d] - mu[d]) * (theta[TM_D * i + e] - mu[e]);
-        }
-        const double b2 = o->cov_scale * o->cov_scale;
-        for (int i = 0; i < TM_D * TM_D; ++i) cov[i] *= b2;
-        if (!chol_d(cov, L, TM_D)) {
-            for (int d = 0; d < TM_D; ++d) cov[TM_D * d + d] += 1e-12 * (o->hi[d] - o->lo[d]) * (o->hi[d] - o->lo[d]);
-            if (!chol_d(cov, L, TM_D)) return fail(SWIM_EINVAL, "proposal covariance is not positive definite");
-        }
-        // resampling: n multinomial draws by the normalized weights
-        double acc = 0.0;
-        for (int64_t i = 0; i < n; ++i) {
-            acc += w[i] / W;
-            cdf[i] = acc;
-            counts[i] = 0;
-        }
-        for (int64_t k = 0; k < n; ++k) {
-            double u[2];
-            uniforms2(seed, 1000u + 2u * (uint32_t)stage_no, (uint64_t)k, 0, u);
-            int64_t j = std::upper_bound(cdf.begin(), cdf.end(), u[0] * cdf.back()) - cdf.begin();
-            if (j >= n) j = n - 1;
-            ++counts[j];
-        }
-        // Metropolis chains, one per drawn sample, stepped together
-        std::vector<int64_t> start, len, off;
-        int64_t maxlen = 0, pos = 0;
-        for (int64_t i = 0; i < n; ++i)
-            if (counts[i]) {
-                start.push_back(i);
-                len.push_back(counts[i]);
-                off.push_back(pos);
-                pos += counts[i];
-                maxlen = std::max(maxlen, counts[i]);
-            }
-        const int64_t nc = (int64_t)start.size();
-        std::vector<double> cur((size_t)nc * TM_D), lcur((size_t)nc), prop, uacc, lprop;
-        std::vector<int64_t> act;
-        for (int64_t ch = 0; ch < nc; ++ch) {
-            for (int d = 0; d < TM_D; ++d) cur[TM_D * ch + d] = theta[TM_D * start[ch] + d];
-            lcur[ch] = logl[start[ch]];
-        }
-        int64_t accepted = 0;
-        const uint32_t cstream = 1001u + 2u * (uint32_t)stage_no;
-        for (int64_t s = 1; s <= maxlen; ++s) {
-            act.clear();
-            for (int64_t ch = 0; ch < nc; ++ch)
-                if (len[ch] >= s) act.push_back(ch);
-            const int64_t na = (int64_t)act.size();
-            prop.resize((size_t)na * TM_D);
-            uacc.resize((size_t)na);
-            std::vector<char> inbox((size_t)na);
-            std::vector<double> batch;
-            for (int64_t a = 0; a < na; ++a) {
-                const int64_t ch = act[a];
-                double u01[2], u23[2], u45[2], z[4];
-                const uint32_t base = 3u * (uint32_t)(s - 1);
-                uniforms2(seed, cstream, (uint64_t)ch, base, u01);
-                uniforms2(seed, cstream, (uint64_t)ch, base + 1, u23);
-                uniforms2(seed, cstream, (uint64_t)ch, base + 2, u45);
-                box_muller(u01[0], u01[1], &z[0], &z[1]);
-                box_muller(u23[0], u23[1], &z[2], &z[3]);
-                uacc[a] = u45[0];
-                bool in = true;
-                for (int d = 0; d < TM_D; ++d) {
-                    double v = cur[TM_D * ch + d];
-                    for (int e = 0; e <= d; ++e) v += L[TM_D * d + e] * z[e];
-                    prop[TM_D * a + d] = v;
-                    in = in && v >= o->lo[d] && v <= o->hi[d];
-                }
-                inbox[a] = in;
-                if (in) batch.insert(batch.end(), &prop[TM_D * a], &prop[TM_D * a] + TM_D);
-            }
-            const int64_t nb = (int64_t)batch.size() / TM_D;
-            lprop.assign((size_t)nb, -INFINITY);
-            TRY(evaluate(batch.data(), nb, lprop.data()));
-            int64_t bi = 0;
-            for (int64_t a = 0; a < na; ++a) {
-                const int64_t ch = act[a];
-                if (inbox[a]) {
-                    const double lp = lprop[bi++];
-                    if (std::log(uacc[a]) < q_next * (lp - lcur[ch])) {
-                        for (int d = 0; d < TM_D; ++d) cur[TM_D * ch + d] = prop[TM_D * a + d];
-                        lcur[ch] = lp;
-                        ++accepted;
-                    }
-                }
-                const int64_t at = off[ch] + s - 1;
-                for (int d = 0; d < TM_D; ++d) nth[TM_D * at + d] = cur[TM_D * ch + d];
-                nll[at] = lcur[ch];
-            }
-        }
-        theta.swap(nth);
-        logl.swap(nll);
-        nth.resize((size_t)n * TM_D);
-        nll.resize((size_t)n);
-        accepted_out[stage_no] = accepted;
-        q = q_next;
-        q_out[stage_no + 1] = q;
-    }
-    memcpy(theta_out, theta.data(), theta.size() * 8);
-    memcpy(logl_out, logl.data(), logl.size() * 8);
-    *n_stages_out = stage_no;
-    *log_evidence_out = log_ev;
+        TRY(ensure(c, B_SP_HEAD, (size_t)k * nsw * (n_obs + 1) * 2 * es));
+        TRY(ensure(c, B_SP_TAIL, (size_t)k * nsw * (n_obs + 1) * 2 * es));
+        TRY(ensure(c, B_SP_G, (size_t)k * n_obs * 2 * 8));
+        TRY(ensure(c, B_STATUS, (size_t)k * 4));
+        TRY(ensure(c, B_LOGL, (size_t)k * 8));
+        TRY(begin_uploads(c, rows.size() * 8 + sw.size() * 8 + sig.size() * 8 + (size_t)n_obs * 16));
+        TRY(stage(c, rows.data(), rows.size() * 8, B_PARAMS, st));
+        TRY(stage(c, sw.data(), sw.size() * 8, B_SP_SW, st));
+        TRY(stage(c, sig.data(), sig.size() * 8, B_SP_SIG, st));
+        TRY(stage(c, data, (size_t)n_obs * 16, B_DATA, st));
+        TRY(end_uploads(c, st));
+        TRY(sperm_forward_impl(c, m->dtype, k, m->shape, (const double*)c->buf[B_PARAMS].p,
+                               (const double*)c->buf[B_SP_SW].p, m->steps, m->dt, m->obs_every, c->buf[B_SP_HEAD].p,
+                               c->buf[B_SP_TAIL].p, (int32_t*)c->buf[B_STATUS].p, st));
+        HIPCHK(launch_sperm_observables(m->dtype, m->kind, k, nsw, n_obs, dt_obs, c->buf[B_SP_HEAD].p,
+                                        c->buf[B_SP_TAIL].p, (const int32_t*)c->buf[B_STATUS].p,
+                                        (double*)c->buf[B_SP_G].p, st));
+        HIPCHK(launch_gauss_loglik2(k, n_obs, (const double*)c->buf[B_SP_G].p, (const double*)c->buf[B_DATA].p,
+                                    (const double*)c->buf[B_SP_SIG].p, (const int32_t*)c->buf[B_STATUS].p,
+                                    (double*)c->buf[B_LOGL].p, st));
+        HIPCHK(hipMemcpyAsync(ll, c->buf[B_LOGL].p, (size_t)k * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        runs += k;
+        t_eval += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return SWIM_OK;
+    };
+    TRY(tmcmc_core(d, o, n, seed, evaluate, theta_out, logl_out, q_out, n_stages_out, log_evidence_out,
+                   accepted_out));
     if (runs_out) *runs_out = runs;
     if (seconds_out) *seconds_out = t_eval;
     return SWIM_OK;

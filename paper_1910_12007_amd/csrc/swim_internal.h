@@ -163,5 +163,15 @@ int sperm_blocks_per_cu(int dtype, int tpl, int wps);
 hipError_t launch_sperm_forward(int dtype, int tpl, int wps, int nblocks, const SpermShape& g, const SpermRun& r,
                                 const void* sysc, const void* tabs, int32_t* queue, void* head, void* tail,
                                 int32_t* status, hipStream_t st);
+// observables per system and sample k = 1..n_obs into g[n_sys][n_obs][2]:
+// kind 0 head-centre velocity of swimmer 0, kind 1 (tail, head) distances of
+// swimmers 0 and 1
+hipError_t launch_sperm_observables(int dtype, int kind, int64_t n_sys, int32_t nsw, int32_t n_obs, double dt_obs,
+                                    const void* head, const void* tail, const int32_t* status, double* g,
+                                    hipStream_t st);
+// Gaussian log-likelihood with standard deviations sig2[i][0] (entries 0,
+// 2, ...) and sig2[i][1] (entries 1, 3, ...); status may be NULL
+hipError_t launch_gauss_loglik2(int64_t n, int32_t n_obs, const double* g, const double* data, const double* sig2,
+                                const int32_t* status, double* logl, hipStream_t st);
 
 }  // namespace swim

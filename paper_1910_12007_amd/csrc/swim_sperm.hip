@@ -521,6 +521,70 @@ __global__ void k_sperm_setup(int64_t n_sys, int32_t nsw, double eps, const doub
     if (sysc64) sysconst_compute<double>(ok ? alpha : 0.0, eps, sysc64 + s);
 }
 
+// observables of a sperm run per system s and interval/sample k = 1..n_obs
+// (Sec. 4): kind 0, the head-centre velocity of swimmer 0,
+// (h_k - h_{k-1}) / dt_obs; kind 1, the distance between the tail ends and
+// between the head centres of swimmers 0 and 1 at sample k.  Stopped runs
+// give NaN.
+template <typename T>
+__global__ void k_sperm_observables(int kind, int64_t n_sys, int32_t nsw, int32_t n_obs, double dt_obs, const T* head,
+                                    const T* tail, const int32_t* status, double* g)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_sys * n_obs) return;
+    const int64_t s = e / n_obs;
+    const int k = (int)(e - s * n_obs) + 1;
+    double* o = g + 2 * e;
+    if (status[s] != 0) {
+        o[0] = NAN;
+        o[1] = NAN;
+        return;
+    }
+    const int64_t stride = (int64_t)(n_obs + 1) * 2;  // one swimmer's samples
+    const T* h0 = head + s * nsw * stride;
+    if (kind == 0) {
+        o[0] = ((double)h0[2 * k] - (double)h0[2 * k - 2]) / dt_obs;
+        o[1] = ((double)h0[2 * k + 1] - (double)h0[2 * k - 1]) / dt_obs;
+    } else {
+        const T* t0 = tail + s * nsw * stride;
+        const T *h1 = h0 + stride, *t1 = t0 + stride;
+        const double tx = (double)t0[2 * k] - (double)t1[2 * k], ty = (double)t0[2 * k + 1] - (double)t1[2 * k + 1];
+        const double hx = (double)h0[2 * k] - (double)h1[2 * k], hy = (double)h0[2 * k + 1] - (double)h1[2 * k + 1];
+        o[0] = sqrt(fma(tx, tx, ty * ty));
+        o[1] = sqrt(fma(hx, hx, hy * hy));
+    }
+}
+
+// Gaussian log-likelihood (eqs. likelihood, fitness) with a diagonal
+// covariance of two levels: entries 0, 2, 4, ... (the odd entries in 1-based
+// numbering) have standard deviation sig2[2i], the others sig2[2i+1].
+// A stopped run or a non-finite output gives -inf.
+__global__ void k_gauss_loglik2(int64_t n, int32_t n_obs, const double* g, const double* data, const double* sig2,
+                                const int32_t* status, double* logl)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* gi = g + i * (int64_t)n_obs * 2;
+    double Ja = 0.0, Jb = 0.0;
+    bool ok = status == nullptr || status[i] == 0;
+    for (int k = 0; k < n_obs && ok; ++k) {
+        ok = isfinite(gi[2 * k]) && isfinite(gi[2 * k + 1]);
+        const double ra = data[2 * k] - gi[2 * k], rb = data[2 * k + 1] - gi[2 * k + 1];
+        Ja = fma(ra, ra, Ja);
+        Jb = fma(rb, rb, Jb);
+    }
+    if (!ok) {
+        logl[i] = -INFINITY;
+        return;
+    }
+    const double sa = sig2[2 * i], sb = sig2[2 * i + 1], m = (double)n_obs;
+    if (!(sa > 0.0 && sb > 0.0)) {
+        logl[i] = -INFINITY;
+        return;
+    }
+    logl[i] = -m * log(2.0 * M_PI) - m * (log(sa) + log(sb)) - 0.5 * (Ja / (sa * sa) + Jb / (sb * sb));
+}
+
 template <typename T, int TPL, int WPS>
 hipError_t launch_sperm_t(int nblocks, const SpermShape& g, const SpermRun& r, const void* sysc, const void* tabs,
                           int32_t* queue, void* head, void* tail, int32_t* status, hipStream_t st)
@@ -605,6 +669,31 @@ hipError_t launch_sperm_forward(int dtype, int tpl, int wps, int nblocks, const 
         return launch_sperm_t<T, decltype(tp)::value, decltype(wp)::value>(nblocks, g, r, sysc, tabs, queue, head,
                                                                            tail, status, st);
     });
+}
+
+hipError_t launch_sperm_observables(int dtype, int kind, int64_t n_sys, int32_t nsw, int32_t n_obs, double dt_obs,
+                                    const void* head, const void* tail, const int32_t* status, double* g,
+                                    hipStream_t st)
+{
+    const int64_t m = n_sys * n_obs;
+    if (m == 0) return hipSuccess;
+    const unsigned nb = (unsigned)((m + 255) / 256);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_sperm_observables<float>, dim3(nb), dim3(256), 0, st, kind, n_sys, nsw, n_obs, dt_obs,
+                           (const float*)head, (const float*)tail, status, g);
+    else
+        hipLaunchKernelGGL(k_sperm_observables<double>, dim3(nb), dim3(256), 0, st, kind, n_sys, nsw, n_obs, dt_obs,
+                           (const double*)head, (const double*)tail, status, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauss_loglik2(int64_t n, int32_t n_obs, const double* g, const double* data, const double* sig2,
+                                const int32_t* status, double* logl, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gauss_loglik2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, n_obs, g, data, sig2,
+                       status, logl);
+    return hipGetLastError();
 }
 
 }  // namespace swim

@@ -22,6 +22,7 @@ SWIM_MLP_NPARAM, SWIM_MLP_IN, SWIM_MLP_OUT = 207393, 5, 33
 # full sperm model: system row fields (SWIM_SP_*) and swimmer row width
 SPERM_FIELDS = ("alpha", "KC", "KT", "KHT", "KHC", "KNT", "KNA", "a", "eta", "omega")
 SWIM_SP_NPARAM, SWIM_SW_NPARAM = 10, 3
+SWIM_OBS_HEAD_VELOCITY, SWIM_OBS_PAIR_DISTANCES = 0, 1
 
 _c = ctypes
 _P = _c.c_void_p
@@ -48,6 +49,11 @@ SIGNATURES = {
                                 _c.c_int32, _c.c_double, _P, _P, _P, _P, _P]),
     "swim_sperm_forward": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _P, _P, _P, _c.c_int32, _c.c_double, _c.c_int32,
                                       _P, _P, _P, _P]),
+    "swim_sperm_observables": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_int64, _c.c_int32, _c.c_int32,
+                                          _c.c_double, _P, _P, _P, _P, _P]),
+    "tmcmc_loglik2": (_c.c_int, [_P, _c.c_int64, _c.c_int32, _P, _P, _P, _P, _P, _P]),
+    "tmcmc_sperm_run": (_c.c_int, [_P, _P, _DP, _P, _DP, _c.c_int32, _c.c_int64, _c.c_uint64, _DP, _DP, _DP, _I32P,
+                                   _DP, _I64P, _I64P, _DP]),
     "abc_distance": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _c.c_int32, _P, _P, _P, _P, _P]),
     "abc_select": (_c.c_int, [_P, _c.c_int64, _P, _c.c_double, _P, _P, _P]),
     "abc_prior_draw": (_c.c_int, [_c.c_uint64, _c.c_int64, _c.c_int32, _DP, _DP, _DP]),
@@ -457,3 +463,69 @@ def swim_sperm_forward(ctx, dtype, shape, sys_params, swim_params, steps, dt, ob
     return _check(lib().swim_sperm_forward(ctx.handle, int(dtype), n_sys, ctypes.byref(shape), _dptr(sys_params),
                                            _dptr(swim_params), int(steps), float(dt), int(obs_every), _dptr(head),
                                            _dptr(tail), _dptr(status), _stream(stream)))
+
+
+def swim_sperm_observables(ctx, dtype, kind, n_swim, dt_obs, head, tail, status, g, stream=None):
+    """g device float64 (n_sys, n_obs, 2) from head/tail (n_sys * n_swim,
+    n_obs + 1, 2)."""
+    n_sys, n_obs = g.shape[0], g.shape[1]
+    return _check(lib().swim_sperm_observables(ctx.handle, int(dtype), int(kind), n_sys, int(n_swim), n_obs,
+                                               float(dt_obs), _dptr(head), _dptr(tail), _dptr(status), _dptr(g),
+                                               _stream(stream)))
+
+
+def tmcmc_loglik2(ctx, g, data, sigma2, status, logl, stream=None):
+    """g device float64 (n, n_obs, 2); data (n_obs, 2); sigma2 (n, 2);
+    status int32 (n,) or None; logl float64 (n,)."""
+    return _check(lib().tmcmc_loglik2(ctx.handle, g.shape[0], g.shape[1], _dptr(g), _dptr(data), _dptr(sigma2),
+                                      _dptr(status), _dptr(logl), _stream(stream)))
+
+
+class sperm_tmcmc_model(ctypes.Structure):
+    _fields_ = [("shape", swim_sperm_shape), ("sys_row", ctypes.c_double * 10), ("n_theta", ctypes.c_int32),
+                ("n_sigma", ctypes.c_int32), ("field", ctypes.c_int32 * 3), ("kind", ctypes.c_int32),
+                ("beta", ctypes.c_double * 2), ("steps", ctypes.c_int32), ("obs_every", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def sperm_model(shape, sys_row, fields, n_sigma, kind, beta, steps, obs_every, dt, dtype=SWIM_F64):
+    """fields: names from SPERM_FIELDS set by the leading theta entries."""
+    m = sperm_tmcmc_model()
+    m.shape = shape
+    for i, v in enumerate(sys_row):
+        m.sys_row[i] = float(v)
+    m.n_theta = len(fields) + int(n_sigma)
+    m.n_sigma = int(n_sigma)
+    for i, f in enumerate(fields[:3]):
+        m.field[i] = SPERM_FIELDS.index(f)
+    m.kind = int(kind)
+    m.beta[0], m.beta[1] = float(beta[0]), float(beta[1])
+    m.steps, m.obs_every, m.dt, m.dtype = int(steps), int(obs_every), float(dt), int(dtype)
+    return m
+
+
+def tmcmc_sperm_run(ctx, model, swim_rows, lo, hi, data, n, seed, cv_target=1.0, cov_scale=0.2, max_stages=40):
+    """One TMCMC run over the sperm model; host arrays in and out."""
+    sw, sw_p = _h(swim_rows, np.float64, _DP)
+    d_, d_p = _h(data, np.float64, _DP)
+    dth = model.n_theta
+    o = tmcmc_opts()
+    for i in range(min(4, len(lo), len(hi))):
+        o.lo[i] = float(lo[i])
+        o.hi[i] = float(hi[i])
+    o.cv_target, o.cov_scale, o.max_stages = float(cv_target), float(cov_scale), int(max_stages)
+    theta = np.empty((max(n, 1), max(dth, 1)))
+    logl = np.empty(max(n, 1))
+    q = np.full(max_stages + 1, np.nan)
+    ns = np.zeros(1, dtype=np.int32)
+    lev = np.empty(1)
+    acc = np.zeros(max_stages, dtype=np.int64)
+    runs = np.zeros(1, dtype=np.int64)
+    secs = np.zeros(1)
+    _check(lib().tmcmc_sperm_run(ctx.handle, ctypes.byref(model), sw_p, ctypes.byref(o), d_p, d_.shape[0], int(n),
+                                 int(seed), theta.ctypes.data_as(_DP), logl.ctypes.data_as(_DP),
+                                 q.ctypes.data_as(_DP), ns.ctypes.data_as(_I32P), lev.ctypes.data_as(_DP),
+                                 acc.ctypes.data_as(_I64P), runs.ctypes.data_as(_I64P), secs.ctypes.data_as(_DP)))
+    k = int(ns[0])
+    return dict(theta=theta, logl=logl, q=q[:k + 1], n_stages=k, log_evidence=float(lev[0]), accepted=acc[:k],
+                runs=int(runs[0]), seconds=float(secs[0]))

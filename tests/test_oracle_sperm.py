@@ -217,3 +217,27 @@ def test_forward_samples_and_one_step():
     ux, uy = core.velocity(X, Y, np.concatenate([f[0] for f in F]), np.concatenate([f[1] for f in F]), 0.6, 0.045)
     np.testing.assert_allclose(out["x"], X + 1e-5 * ux, rtol=0, atol=1e-15)
     np.testing.assert_allclose(out["y"], Y + 1e-5 * uy, rtol=0, atol=1e-15)
+
+
+def test_observables():
+    """Head-centre velocities of a run and the pair distances of two
+    swimmers: at sample 0 the heads and tails sit exactly d apart; a run's
+    velocities sum to the head's total displacement over the time."""
+    d = 0.5
+    sw = np.array([[0.0, d / 2, 0.0], [0.0, -d / 2, 0.0]])
+    out = core.sperm_forward(row(), sw, NF, NH, 0.045, HR, DN, 60, 1e-5, 20)
+    v = core.sperm_head_velocity(out["head"], 20 * 1e-5)
+    assert v.shape == (3, 2)
+    np.testing.assert_allclose(v.sum(0) * 20e-5, out["head"][0, -1] - out["head"][0, 0], rtol=1e-12, atol=1e-17)
+    dist = core.sperm_pair_distances(out["head"], out["tail"])
+    assert dist.shape == (3, 2)
+    h, t = out["head"], out["tail"]
+    assert np.hypot(*(t[0, 0] - t[1, 0])) == pytest.approx(d, abs=1e-15)
+    assert np.hypot(*(h[0, 0] - h[1, 0])) == pytest.approx(d, abs=1e-15)
+    np.testing.assert_allclose(dist[:, 0], np.hypot(*(t[0, 1:] - t[1, 1:]).T), rtol=1e-15)
+    np.testing.assert_allclose(dist[:, 1], np.hypot(*(h[0, 1:] - h[1, 1:]).T), rtol=1e-15)
+    # a uniformly moving head: constant velocity
+    H = np.zeros((1, 5, 2))
+    H[0, :, 0] = 0.3 + 0.01 * np.arange(5)
+    H[0, :, 1] = -0.002 * np.arange(5)
+    np.testing.assert_allclose(core.sperm_head_velocity(H, 0.5), np.tile([0.02, -0.004], (4, 1)), rtol=1e-12)

@@ -108,3 +108,22 @@ def test_zero_likelihood_region_enters_the_evidence():
     assert r["log_evidence"] == pytest.approx(c + np.log(p_hat), abs=1e-12)
     assert abs(p_hat - 0.5) < 3 * np.sqrt(0.25 / n)
     assert np.all(r["theta"][:, 0] < 0.5)
+
+
+def test_two_level_loglik_is_the_diagonal_normal_density():
+    rng = np.random.Generator(np.random.PCG64(21))
+    m = 40
+    D = rng.normal(size=m)
+    g = D[None] + rng.normal(scale=0.02, size=(4, m))
+    sa = np.array([0.01, 0.02, 0.05, 0.3])
+    sb = np.array([0.03, 0.02, 0.001, 1.0])
+    ll = tmcmc.gauss_loglik2(g, D, sa, sb)
+    for i in range(4):
+        sd = np.where(np.arange(m) % 2 == 0, sa[i], sb[i])
+        ref = stats.multivariate_normal(mean=g[i], cov=np.diag(sd ** 2)).logpdf(D)
+        assert abs(ll[i] - ref) <= 1e-10 * abs(ref)
+    # one level: the isotropic density
+    assert np.allclose(tmcmc.gauss_loglik2(g, D, sa, sa), tmcmc.gauss_loglik(g, D, sa), rtol=1e-13, atol=0)
+    g[1, 3] = np.nan
+    out = tmcmc.gauss_loglik2(g, D, sa, np.array([0.03, 0.02, 0.0, 1.0]))
+    assert np.isneginf(out[1]) and np.isneginf(out[2]) and np.isfinite(out[0])
