@@ -335,6 +335,51 @@ def sperm_leg(ctx, stream, n=2000, steps=20000, dt=1e-5):
     return out
 
 
+def sperm_tmcmc_leg(ctx, n=2000, steps=10000, obs_every=200, dt=1e-5, seed=17, noise=0.01):
+    """The paper's Sec. 4.1 experiment on the full sperm model: TMCMC with
+    n = 2000 samples per stage over theta = (alpha, sigma/beta), prior
+    [0, 2] x [0, 0.5], 50 head-centre velocity pairs as data, 1 % noise,
+    FP32 forward runs.  The horizon is shortened to T = steps * dt = 0.1
+    (the paper runs to T = 20, 2M steps at this dt).  The synthetic data
+    are the library's FP64 run of the nominal model (alpha = 1, K_C = 8)
+    plus seeded Gaussian noise of sigma = noise * |mean of the outputs|."""
+    import torch
+    from paper_1910_12007_amd import inputs, swim
+    shape = swim.sperm_shape()
+    row = inputs.sperm_rows(1)[0]
+    sw = inputs.sperm_swimmers(1)
+    n_obs = steps // obs_every
+    head = torch.empty((1, n_obs + 1, 2), dtype=torch.float64, device="cuda")
+    tail = torch.empty_like(head)
+    status = torch.empty(1, dtype=torch.int32, device="cuda")
+    g = torch.empty((1, n_obs, 2), dtype=torch.float64, device="cuda")
+    swim.swim_sperm_forward(ctx, swim.SWIM_F64, shape, torch.from_numpy(row[None].copy()).cuda(),
+                            torch.from_numpy(sw).cuda(), steps, dt, obs_every, head, tail, status)
+    swim.swim_sperm_observables(ctx, swim.SWIM_F64, swim.SWIM_OBS_HEAD_VELOCITY, 1, obs_every * dt, head, tail,
+                                status, g)
+    torch.cuda.synchronize()
+    xi = g.cpu().numpy()[0]
+    beta = abs(float(xi.mean()))
+    data = xi + noise * beta * np.random.Generator(np.random.PCG64(seed)).normal(size=xi.shape)
+    m = swim.sperm_model(shape, row, ("alpha",), 1, swim.SWIM_OBS_HEAD_VELOCITY, (beta, beta), steps, obs_every, dt,
+                         swim.SWIM_F32)
+    t0 = time.perf_counter()
+    r = swim.tmcmc_sperm_run(ctx, m, sw, [0.0, 0.0], [2.0, 0.5], data, n, seed, max_stages=40)
+    wall = time.perf_counter() - t0
+    th = r["theta"]
+    mean, std = th.mean(0), th.std(0)
+    truth = np.array([1.0, noise])
+    return {"workload": f"TMCMC over the full sperm model (Sec. 4.1): {n} samples per stage, theta = (alpha, "
+                        f"sigma/beta) on [0,2]x[0,0.5], {n_obs} head-centre velocity pairs, {noise:.0%} noise, "
+                        f"T = {steps * dt:g} ({steps} steps of dt = {dt}), FP32 forward runs",
+            "stages": r["n_stages"], "q": [float(x) for x in r["q"]], "forward_runs": r["runs"], "seconds": wall,
+            "forward_seconds": r["seconds"], "forward_runs_per_s": r["runs"] / r["seconds"],
+            "swimmer_steps_per_s": r["runs"] * steps / r["seconds"],
+            "accepted_per_stage": [int(x) for x in r["accepted"]], "log_evidence": r["log_evidence"],
+            "posterior_mean": [float(x) for x in mean], "posterior_std": [float(x) for x in std],
+            "true": [float(x) for x in truth], "z_scores_of_truth": [float(x) for x in (truth - mean) / std]}
+
+
 def surrogate_leg(ctx, data):
     """Surrogate-prescreened ABC against plain batched ABC on the same 1M
     prior draws (tolerance: the 5th percentile of the completed runs of the
@@ -484,6 +529,7 @@ def main():
         out["tmcmc"] = tmcmc_leg(ctx, load_data())
     if not args.no_sperm:
         out["sperm"] = sperm_leg(ctx, stream)
+        out["sperm_tmcmc"] = sperm_tmcmc_leg(ctx)
     if not args.no_surrogate:
         out["surrogate_abc"] = surrogate_leg(ctx, load_data())
     if not args.no_cpu:

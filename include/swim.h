@@ -376,8 +376,9 @@ typedef struct swim_sperm_shape {
  *             non-finite values, alpha < 0 or alpha*eps > 1 gets
  *             SWIM_ST_BADPARAM and is not run.
  * Systems run in a persistent kernel, one workgroup per system.
- * SWIM_OPT_WPS set to 2, 4 or 8 selects its waves per system (otherwise 2
- * for SWIM_F32 and 8 for SWIM_F64).
+ * SWIM_OPT_WPS set to 2, 4 or 8 selects its waves per system.  Otherwise
+ * SWIM_F64 takes 8, and SWIM_F32 the most of 8, 4, 2 that keeps the launch
+ * within eight waves per compute unit (small batches are latency-bound).
  * SWIM_EINVAL for a bad shape or run length.  Asynchronous. */
 int swim_sperm_forward(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const swim_sperm_shape *shape,
                        const double *sys_params, const double *swim_params, int32_t steps, double dt,

@@ -854,9 +854,13 @@ int sperm_forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const swim_spe
     r.n_obs = obs_every > 0 ? steps / obs_every : 0;
     const int n = sh.n_swim * (sh.n_flag + sh.n_head);
     const int tpl = choose_tpl(n);
-    // measured on 2000 systems of one and two swimmers: FP32 is fastest with
-    // two waves per system, FP64 with eight
-    int wps = dtype == SWIM_F32 ? 2 : 8;
+    // waves per system.  FP32, one-swimmer systems, us per step for 2/4/8
+    // waves: 256 systems 11.0/7.0/5.5, 512 11.6/7.8/10.6, 1024 12.0/15.0/20.9,
+    // 2000 23.4/29.5/41.4.  The most waves that keep the launch within eight
+    // waves per CU.  FP64 is fastest with eight at every size measured.
+    int wps = 8;
+    if (dtype == SWIM_F32)
+        wps = n_sys * 8 <= 8 * (int64_t)c->num_cu ? 8 : n_sys * 4 <= 8 * (int64_t)c->num_cu ? 4 : 2;
     if (c->opt_wps == 2 || c->opt_wps == 4 || c->opt_wps == 8) wps = c->opt_wps;
     void *sysc, *sysc64;
     TRY(sysconst_buffers(c, dtype, n_sys, &sysc, &sysc64));
