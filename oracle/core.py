@@ -56,6 +56,9 @@ def lib():
                                            ctypes.c_double, ctypes.c_double, _D, _D, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_int, _D, _D, _D, _D, _I32]
         L.oracle_sperm_forward.restype = ctypes.c_int
+        L.oracle_blob.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int64, _D, _D, _D]
+        L.oracle_field.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_int64, _D, _D, _D, _D, _D]
         _LIB = L
     return _LIB
 
@@ -235,3 +238,22 @@ def sperm_pair_distances(head, tail):
     dt_ = np.linalg.norm(t[0, 1:] - t[1, 1:], axis=-1)
     dh = np.linalg.norm(h[0, 1:] - h[1, 1:], axis=-1)
     return np.stack([dt_, dh], axis=-1)
+
+
+def blob(alpha, eps, t):
+    """The blob of the kernel reading, phi(r), and its mass inside r over r^2,
+    m(r)/r^2 (m = 2 pi int_0^r s phi ds), at squared distances t."""
+    t = _f64(t).ravel()
+    phi, m = np.empty_like(t), np.empty_like(t)
+    lib().oracle_blob(float(alpha), float(eps), t.size, _p(t), _p(phi), _p(m))
+    return phi, m
+
+
+def field(x, y, fx, fy, alpha, eps, tx, ty):
+    """Velocity (eq. BrV) and pressure (eq. BrP, p = sum F . grad G_eps) at
+    the target points (tx, ty) from the point forces of one system."""
+    x, y, fx, fy, tx, ty = map(_f64, (x, y, fx, fy, tx, ty))
+    u, v, p = np.empty(tx.size), np.empty(tx.size), np.empty(tx.size)
+    lib().oracle_field(x.size, _p(x), _p(y), _p(fx), _p(fy), float(alpha), float(eps), tx.size, _p(tx), _p(ty),
+                       _p(u), _p(v), _p(p))
+    return u, v, p

@@ -761,3 +761,92 @@ int oracle_sperm_forward(int n_swim, int nf, int nh, double eps, double hr, doub
     free(x); free(y); free(fx); free(fy); free(ux); free(uy);
     return 0;
 }
+
+/* ======================================================================== */
+/* Flow and pressure at arbitrary points, eqs. (BrV) and (BrP) of Sec. 2.1. */
+/*                                                                          */
+/* The pressure of a regularized point force is p = F . grad G_eps with     */
+/* Delta G_eps = phi (the same blob as the velocity), so for a radial blob  */
+/* grad G_eps(x) = x m(r) / (2 pi r^2), m(r) = 2 pi int_0^r s phi(s) ds the */
+/* blob mass inside r.  From (Delta - alpha^2) g = phi (see kernel_init),   */
+/* m/(2 pi) = r g'(r) - alpha^2 M(r):                                       */
+/*   Stokes:   m = r^2 / R^2                                                */
+/*   Brinkman: m = 1 - eps K1(alpha R) / (R K1(alpha eps))                  */
+/* Near contact (delta = r^2/eps^2 < 1/4), with g = sum gam_n delta^n,      */
+/*   m / r^2 = (2 pi / eps^2) [ 2 sum_{n>=1} n gam_n delta^(n-1)            */
+/*                              - (alpha^2 eps^2 / 2) sum_n gam_n delta^n / (n+1) ]. */
+/* ------------------------------------------------------------------------ */
+static ld mass_over_r2(const okern *k, double t_d)
+{
+    ld t = t_d;
+    ld delta = t / k->e2;
+    if (delta < DELTA_TAYLOR) {
+        ld p = 1.0L, a = 0.0L, b = 0.0L;
+        for (int n = 0; n < NGAM; ++n) {
+            if (n + 1 < NGAM) a += (ld)(n + 1) * k->gam[n + 1] * p;
+            b += k->gam[n] * p / (ld)(n + 1);
+            p *= delta;
+        }
+        ld a2e2 = k->stokes ? 0.0L : (ld)k->alpha * (ld)k->alpha * k->e2;
+        return (2.0L * PI_L / k->e2) * (2.0L * a - 0.5L * a2e2 * b);
+    }
+    ld R2 = t + k->e2;
+    if (k->stokes) return 1.0L / R2;
+    ld R = sqrtl(R2);
+    ld K0R, K1R, K0e, K1e;
+    bessel_k01((ld)k->alpha * R, &K0R, &K1R);
+    bessel_k01((ld)k->alpha * (ld)k->eps, &K0e, &K1e);
+    return (1.0L - (ld)k->eps * K1R / (R * K1e)) / t;
+}
+
+/* blob of the kernel reading (kernel_init): phi(r) */
+static ld blob_phi(const okern *k, double t_d)
+{
+    ld R2 = (ld)t_d + k->e2, R = sqrtl(R2);
+    if (k->stokes) return k->e2 / (PI_L * R2 * R2);
+    ld K0, K1, a = k->alpha;
+    bessel_k01(a * R, &K0, &K1);
+    return k->c * k->e2 / (2.0L * PI_L) * (a * a * K0 / R2 + 2.0L * a * K1 / (R2 * R));
+}
+
+void oracle_blob(double alpha, double eps, int64_t n, const double *t, double *phi, double *m_over_r2)
+{
+    okern k;
+    kernel_init(&k, alpha, eps);
+    for (int64_t i = 0; i < n; ++i) {
+        phi[i] = (double)blob_phi(&k, t[i]);
+        m_over_r2[i] = (double)mass_over_r2(&k, t[i]);
+    }
+}
+
+/* velocity (eq. BrV) and pressure (eq. BrP) at nt target points from the n
+ * regularized point forces of one system; index-order Neumaier sums */
+void oracle_field(int64_t n, const double *x, const double *y, const double *fx, const double *fy,
+                  double alpha, double eps, int64_t nt, const double *tx, const double *ty, double *u,
+                  double *v, double *p)
+{
+    okern k;
+    kernel_init(&k, alpha, eps);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t a = 0; a < nt; ++a) {
+        double s[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            double dx = tx[a] - x[j], dy = ty[a] - y[j];
+            double t = dx * dx + dy * dy;
+            ld H1, H2;
+            kernel_eval(&k, t, &H1, &H2);
+            double h1 = (double)H1, h2 = (double)H2;
+            double fd = fx[j] * dx + fy[j] * dy;
+            double w = (double)(mass_over_r2(&k, t) / (2.0L * PI_L));
+            double val[3] = {h1 * fx[j] + h2 * fd * dx, h1 * fy[j] + h2 * fd * dy, fd * w};
+            for (int q = 0; q < 3; ++q) {
+                double z = s[q] + val[q];
+                c[q] += (fabs(s[q]) >= fabs(val[q])) ? (s[q] - z) + val[q] : (val[q] - z) + s[q];
+                s[q] = z;
+            }
+        }
+        u[a] = s[0] + c[0];
+        v[a] = s[1] + c[1];
+        p[a] = s[2] + c[2];
+    }
+}
