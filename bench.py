@@ -380,6 +380,36 @@ def sperm_tmcmc_leg(ctx, n=2000, steps=10000, obs_every=200, dt=1e-5, seed=17, n
             "true": [float(x) for x in truth], "z_scores_of_truth": [float(x) for x in (truth - mean) / std]}
 
 
+def field_leg(ctx, stream, grid=1024):
+    """Flow and pressure picture (Sec. 2.1, eqs. BrV, BrP; Figs. 1 and 3):
+    velocity and pressure of two swimmers' point forces (2 x 128 points,
+    forces of a bent configuration, alpha = 1) on a grid x grid lattice of
+    targets, FP32 pair kernel evaluated directly (no table), FP64 sums and
+    pressure weights."""
+    import torch
+    from paper_1910_12007_amd import inputs, swim
+    N = 128
+    x, y = inputs.filament_geometry(N, 5, n_swim=2, spacing=0.5)
+    rng = np.random.Generator(np.random.PCG64(5))
+    f = rng.normal(size=(2, x.size))
+    f -= f.mean(axis=1, keepdims=True)
+    gx, gy = np.meshgrid(np.linspace(-0.5, 1.5, grid), np.linspace(-0.5, 1.0, grid))
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda")
+    X, Y, FX, FY, TX, TY = map(d, (x, y, f[0], f[1], gx.ravel(), gy.ravel()))
+    u = torch.empty(grid * grid, dtype=torch.float32, device="cuda")
+    v, p = torch.empty_like(u), torch.empty_like(u)
+    swim.swim_flow_field(ctx, X, Y, FX, FY, 1.0, 1.5 / (N - 1), TX, TY, u, v, p, stream=stream)  # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    swim.swim_flow_field(ctx, X, Y, FX, FY, 1.0, 1.5 / (N - 1), TX, TY, u, v, p, stream=stream)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    pairs = float(grid * grid) * x.size
+    return {"workload": f"velocity and pressure of 2 x {N} point forces on a {grid}x{grid} grid, alpha = 1, FP32",
+            "ms": ms, "target_source_pairs_per_s": pairs / (ms * 1e-3)}
+
+
 def surrogate_leg(ctx, data):
     """Surrogate-prescreened ABC against plain batched ABC on the same 1M
     prior draws (tolerance: the 5th percentile of the completed runs of the
@@ -530,6 +560,7 @@ def main():
     if not args.no_sperm:
         out["sperm"] = sperm_leg(ctx, stream)
         out["sperm_tmcmc"] = sperm_tmcmc_leg(ctx)
+        out["flow_field"] = field_leg(ctx, stream)
     if not args.no_surrogate:
         out["surrogate_abc"] = surrogate_leg(ctx, load_data())
     if not args.no_cpu:

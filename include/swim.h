@@ -141,6 +141,22 @@ int swim_pair_velocity(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const int64_
                        const double *alpha, const double *eps, const void *x, const void *y,
                        const void *fx, const void *fy, void *ux, void *uy, void *stream);
 
+/* Velocity (eq. BrV) and pressure (eq. BrP) of the n regularized point
+ * forces of one system at nt arbitrary target points, for flow and pressure
+ * pictures (Sec. 2.1).
+ *   u(x) = sum_j [ H1(r) F_j + H2(r) (F_j . d) d ],  d = x - X_j
+ *   p(x) = sum_j F_j . grad G_eps(d),  grad G_eps(d) = d m(r) / (2 pi r^2)
+ * G_eps solves Delta G_eps = phi, the blob of the velocity kernel, and m(r)
+ * is the blob mass inside r: m = r^2/R^2 for alpha = 0 and
+ * m = 1 - eps K1(alpha R) / (R K1(alpha eps)) otherwise, R^2 = r^2 + eps^2.
+ * x, y, fx, fy device dtype[n]; tx, ty device dtype[nt]; u, v, p device
+ * dtype[nt] (written).  alpha >= 0, eps > 0, alpha*eps <= 1.  Sums are
+ * accumulated in FP64.  The pair kernel is evaluated in dtype directly
+ * (no table); the pressure weight is evaluated in FP64.  Asynchronous. */
+int swim_flow_field(swim_ctx *ctx, int32_t dtype, int64_t n, const void *x, const void *y, const void *fx,
+                    const void *fy, double alpha, double eps, int64_t nt, const void *tx, const void *ty,
+                    void *u, void *v, void *p, void *stream);
+
 /* Elastic point forces F = -dE/dX (eqs. Fenergy, EFB, curva, EFT) at time t
  * for n_fil filaments stored back to back.
  * N        host int32[n_fil], 3 <= N[f] <= 4096 points of filament f.

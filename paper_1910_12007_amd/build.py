@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswim.so")
-SOURCES = ["swim_kernels.hip", "swim_mlp.hip", "swim_sperm.hip", "swim_capi.hip"]
+SOURCES = ["swim_kernels.hip", "swim_mlp.hip", "swim_sperm.hip", "swim_field.hip", "swim_capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SWIM_OFFLOAD_ARCH", "gfx950")
 

@@ -723,6 +723,51 @@ int swim_pair_velocity(swim_ctx* c, int32_t dtype, int64_t n_sys, const int64_t*
     return SWIM_OK;
 }
 
+int swim_flow_field(swim_ctx* c, int32_t dtype, int64_t n, const void* x, const void* y, const void* fx,
+                    const void* fy, double alpha, double eps, int64_t nt, const void* tx, const void* ty, void* u,
+                    void* v, void* p, void* stream)
+{
+    TRY(check_ctx(c));
+    TRY(check_dtype(dtype));
+    if (n < 0 || nt < 0) return fail(SWIM_EINVAL, "negative size");
+    if (!(std::isfinite(alpha) && alpha >= 0 && std::isfinite(eps) && eps > 0 && alpha * eps <= 1.0))
+        return fail(SWIM_EINVAL, "need alpha >= 0, eps > 0, alpha*eps <= 1");
+    if (nt == 0) return SWIM_OK;
+    if ((n > 0 && (!x || !y || !fx || !fy)) || !tx || !ty || !u || !v || !p)
+        return fail(SWIM_EINVAL, "null device pointer");
+    FieldConst fc{};
+    sysconst_compute<float>(alpha, eps, &fc.c32);
+    sysconst_compute<double>(alpha, eps, &fc.c64);
+    fc.h1c = fc.c64.h1c;
+    fc.e2 = eps * eps;
+    fc.inv_e2 = 1.0 / fc.e2;
+    fc.eps = eps;
+    fc.alpha = alpha;
+    fc.inv_2pi = 0.5 / M_PI;
+    fc.stokes = alpha == 0.0;
+    if (!fc.stokes) {
+        // near-contact series of w = m / (2 pi r^2) from g = sum_n gam_n delta^n,
+        // gam_n = -(c/2pi) (-1)^n kap_n, kap_n = (z0/2)^n K_n(z0) / n!,
+        // c = 1/(z0 K1(z0)): w = (1/eps^2) sum_n [2 (n+1) gam_{n+1}
+        // - (alpha^2 eps^2 / 2) gam_n / (n+1)] delta^n
+        const double z0 = alpha * eps;
+        double K0, K1, Q;
+        bessel_k01_q_f64(z0, &K0, &K1, &Q);
+        fc.K1e = K1;
+        const double cc = 1.0 / (z0 * K1);
+        double kap[FIELD_NSER + 1], gam[FIELD_NSER + 1];
+        kap[0] = K0;
+        kap[1] = 0.5 * z0 * K1;
+        for (int k = 1; k < FIELD_NSER; ++k)
+            kap[k + 1] = 0.25 * z0 * z0 * kap[k - 1] / ((double)k * (k + 1)) + (double)k * kap[k] / (k + 1);
+        for (int k = 0; k <= FIELD_NSER; ++k) gam[k] = -(cc * fc.inv_2pi) * ((k % 2) ? -1.0 : 1.0) * kap[k];
+        for (int k = 0; k < FIELD_NSER; ++k)
+            fc.ser[k] = fc.inv_e2 * (2.0 * (k + 1) * gam[k + 1] - 0.5 * z0 * z0 * gam[k] / (k + 1));
+    }
+    HIPCHK(launch_flow_field(dtype, n, x, y, fx, fy, fc, nt, tx, ty, u, v, p, pick(c, stream)));
+    return SWIM_OK;
+}
+
 int swim_elastic_forces(swim_ctx* c, int32_t dtype, int64_t n_fil, const int32_t* N, const double* params, double t,
                         const void* x, const void* y, void* fx, void* fy, void* stream)
 {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "swim_math.h"
+
 namespace swim {
 
 // Layout of a batch of independent systems (one hydrodynamic domain each),
@@ -173,5 +175,21 @@ hipError_t launch_sperm_observables(int dtype, int kind, int64_t n_sys, int32_t 
 // 2, ...) and sig2[i][1] (entries 1, 3, ...); status may be NULL
 hipError_t launch_gauss_loglik2(int64_t n, int32_t n_obs, const double* g, const double* data, const double* sig2,
                                 const int32_t* status, double* logl, hipStream_t st);
+
+// velocity and pressure at arbitrary points (swim_field.hip): constants of one
+// fluid and blob.  The pressure weight m(r) / (2 pi r^2) is inv_2pi / R^2
+// (stokes), the power series ser[] in delta = r^2/eps^2 for delta < 1/4, and
+// inv_2pi (1 - eps K1(alpha R) / (R K1e)) / r^2 otherwise.
+constexpr int FIELD_NSER = 26;
+struct FieldConst {
+    SysConst<float> c32;
+    SysConst<double> c64;
+    double h1c, inv_e2, e2, eps, alpha, K1e, inv_2pi;
+    int32_t stokes, pad;
+    double ser[FIELD_NSER];
+};
+hipError_t launch_flow_field(int dtype, int64_t n, const void* x, const void* y, const void* fx, const void* fy,
+                             const FieldConst& fc, int64_t nt, const void* tx, const void* ty, void* u, void* v,
+                             void* p, hipStream_t st);
 
 }  // namespace swim

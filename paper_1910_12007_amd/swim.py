@@ -54,6 +54,8 @@ SIGNATURES = {
     "tmcmc_loglik2": (_c.c_int, [_P, _c.c_int64, _c.c_int32, _P, _P, _P, _P, _P, _P]),
     "tmcmc_sperm_run": (_c.c_int, [_P, _P, _DP, _P, _DP, _c.c_int32, _c.c_int64, _c.c_uint64, _DP, _DP, _DP, _I32P,
                                    _DP, _I64P, _I64P, _DP]),
+    "swim_flow_field": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _P, _P, _P, _P, _c.c_double, _c.c_double, _c.c_int64,
+                                   _P, _P, _P, _P, _P, _P]),
     "abc_distance": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _c.c_int32, _P, _P, _P, _P, _P]),
     "abc_select": (_c.c_int, [_P, _c.c_int64, _P, _c.c_double, _P, _P, _P]),
     "abc_prior_draw": (_c.c_int, [_c.c_uint64, _c.c_int64, _c.c_int32, _DP, _DP, _DP]),
@@ -529,3 +531,10 @@ def tmcmc_sperm_run(ctx, model, swim_rows, lo, hi, data, n, seed, cv_target=1.0,
     k = int(ns[0])
     return dict(theta=theta, logl=logl, q=q[:k + 1], n_stages=k, log_evidence=float(lev[0]), accepted=acc[:k],
                 runs=int(runs[0]), seconds=float(secs[0]))
+
+
+def swim_flow_field(ctx, x, y, fx, fy, alpha, eps, tx, ty, u, v, p, stream=None):
+    """Velocity and pressure at target points (device tensors of one dtype)."""
+    return _check(lib().swim_flow_field(ctx.handle, dtype_code(x), x.numel(), _dptr(x), _dptr(y), _dptr(fx),
+                                        _dptr(fy), float(alpha), float(eps), tx.numel(), _dptr(tx), _dptr(ty),
+                                        _dptr(u), _dptr(v), _dptr(p), _stream(stream)))
