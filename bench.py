@@ -292,10 +292,8 @@ def sperm_leg(ctx, stream, n=2000, steps=20000, dt=1e-5):
     and two swimmers with head centres 0.5 apart (148 points).
 
     Roofline: VALU issue bound.  Algorithmic work is n_pts^2 ordered pairs
-    per system step at VALU_OPS_PER_PAIR lane-operations each.  The
-    symmetric schedule evaluates 64-point blocks (32 B^2 offsets of 64
-    lanes, B = ceil(n_pts/64)), including padding, at 2 VALU_OPS_PER_PAIR
-    per evaluation; frac_scheduled is that work's share of peak."""
+    per system step at VALU_OPS_PER_PAIR lane-operations each (the
+    symmetric schedule's cost per ordered pair)."""
     import torch
     from paper_1910_12007_amd import inputs, swim
     rows = torch.from_numpy(inputs.sperm_rows(n, seed=11)).to("cuda")
@@ -317,10 +315,8 @@ def sperm_leg(ctx, stream, n=2000, steps=20000, dt=1e-5):
         torch.cuda.synchronize()
         ms = ev[0].elapsed_time(ev[1])
         npts = n_swim * 74
-        B = (npts + 63) // 64
         st = status.cpu().numpy()
         pairs = float(n) * npts * npts * steps
-        sched = float(n) * 32 * B * B * 64 * steps
         tops = VALU_OPS_PER_PAIR * pairs / (ms * 1e-3) / 1e12
         out[f"{n_swim}_swimmer" + ("s" if n_swim > 1 else "")] = {
             "points_per_system": npts, "ms": ms, "us_per_step": 1e3 * ms / steps,
@@ -329,7 +325,6 @@ def sperm_leg(ctx, stream, n=2000, steps=20000, dt=1e-5):
             "stage_seconds_to_T20": ms * 1e-3 * (20 / dt) / steps,
             "roofline": {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS,
                          "unit": "TOP/s (VALU lane-operations)", "frac": tops / VALU_PEAK_TOPS,
-                         "frac_scheduled": 2 * VALU_OPS_PER_PAIR * sched / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
                          "kernel": "k_sperm_forward<float,%d,2>" % (1 if npts <= 64 else 2 if npts <= 128 else 3),
                          "valu_ops_per_pair": VALU_OPS_PER_PAIR}}
     return out

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "swim_math.h"
 
 namespace swim {
@@ -200,6 +202,101 @@ __device__ __forceinline__ void pair_phase_sym(const SysConst<T>& C, const TabSy
                 }
             }
             g += len;
+        }
+    }
+}
+
+// sum over the 64 lanes of a wavefront (butterfly; lane j's result is
+// deterministic)
+template <typename T> __device__ __forceinline__ T wave_total(T v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Whether the tail schedule below does less work than the padded symmetric
+// one for n points: r tail points (n = 64 Bf + r, 0 < r < 64) cost about
+// r (33 Bf + 52) lane-operations per lane against 33 for each of the
+// 32 (2 Bf + 1) offsets the padded last block adds.
+__host__ __device__ constexpr bool tail_pays(int n)
+{
+    const int Bf = n >> 6, r = n & 63;
+    return r != 0 && r * (33 * Bf + 52) < 33 * 32 * (2 * Bf + 1);
+}
+
+// Pair sums of n points whose last block is partly filled (r = n - 64 Bf
+// points, 0 < r < 64): the symmetric schedule covers the Bf full blocks,
+// and the r tail points take their pairs point by point instead of as a
+// padded block of 64:
+//  * tail point j against full block a: lane l evaluates the pair
+//    (64 a + l, tail j) once; point 64 a + l keeps its share, and the
+//    shares of tail point j, summed over all full blocks in each lane, are
+//    summed over the wavefront once and kept by lane j;
+//  * tail point j as a source within the tail: lanes l < r take the pair
+//    (tail l, tail j) for target tail l only.
+// Every ordered pair is taken once.  The full blocks' offsets are split
+// over the waves as in pair_phase_sym; tail point j goes to wave j mod WPS.
+template <typename T, int TPL, int WPS>
+__device__ __forceinline__ void pair_phase_tail(const SysConst<T>& C, const TabSys* tab, const Src4<T>* src2, int n,
+                                                int wave, int lane, T (&accx)[TPL], T (&accy)[TPL])
+{
+    const int Bf = n >> 6, r = n & 63;
+    pair_phase_sym<T, TPL, WPS>(C, tab, src2, 64 * Bf, wave, lane, accx, accy);
+    const char* et = nullptr;
+    if constexpr (sizeof(T) == 4)
+        et = reinterpret_cast<const char*>(tab->e) + opaque_uniform(-(int)(TAB_BIAS * sizeof(TabE)));
+    const bool tl_live = lane < r;
+    const Src4<T> tp = src2[src2_slot(64 * Bf + (tl_live ? lane : r - 1))];
+    for (int j = wave; j < r; j += WPS) {
+        const Src4<T> q = src2[src2_slot(64 * Bf + j)];
+        T bx = (T)0, by = (T)0;
+        bool far = false;
+        // one pass over tail point j's pairs; FAR selects the direct
+        // evaluation of pairs beyond the FP32 table (zeros for the others)
+        auto pass = [&](auto far_tag) {
+            constexpr bool FAR = decltype(far_tag)::value;
+#pragma unroll
+            for (int a = 0; a < TPL; ++a) {
+                if (a < Bf) {
+                    const Src4<T> ti = src2[(a << 7) + lane];
+                    const T dx = ti.x - q.x, dy = ti.y - q.y;
+                    T Ht, H2;
+                    pair_kernel<T, FAR>(C, et, dx, dy, Ht, H2, far);
+                    const T fdj = H2 * fma_t(q.fx, dx, q.fy * dy);
+                    accx[a] = fma_t(Ht, q.fx, fma_t(fdj, dx, accx[a]));
+                    accy[a] = fma_t(Ht, q.fy, fma_t(fdj, dy, accy[a]));
+                    const T fdi = H2 * fma_t(ti.fx, dx, ti.fy * dy);
+                    bx = fma_t(Ht, ti.fx, fma_t(fdi, dx, bx));
+                    by = fma_t(Ht, ti.fy, fma_t(fdi, dy, by));
+                }
+            }
+            const T dx = tp.x - q.x, dy = tp.y - q.y;
+            T Ht, H2;
+            pair_kernel<T, FAR>(C, et, dx, dy, Ht, H2, far);
+            Ht = tl_live ? Ht : (T)0;
+            H2 = tl_live ? H2 : (T)0;
+            const T fdj = H2 * fma_t(q.fx, dx, q.fy * dy);
+#pragma unroll
+            for (int c = 0; c < TPL; ++c) {
+                if (c == Bf) {
+                    accx[c] = fma_t(Ht, q.fx, fma_t(fdj, dx, accx[c]));
+                    accy[c] = fma_t(Ht, q.fy, fma_t(fdj, dy, accy[c]));
+                }
+            }
+        };
+        pass(std::integral_constant<bool, false>());
+        if constexpr (sizeof(T) == 4) {
+            if (__any(far)) pass(std::integral_constant<bool, true>());
+        }
+        bx = wave_total(bx);
+        by = wave_total(by);
+#pragma unroll
+        for (int c = 0; c < TPL; ++c) {
+            if (c == Bf && lane == j) {
+                accx[c] += bx;
+                accy[c] += by;
+            }
         }
     }
 }

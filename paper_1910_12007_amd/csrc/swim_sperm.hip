@@ -6,7 +6,8 @@
 //
 // One workgroup runs one system for all its steps (a persistent kernel fed
 // by a work queue).  The pair sum uses the symmetric lane schedule of
-// swim_pairsum.h.  The elastic forces are computed per point from the
+// swim_pairsum.h, with the partly filled last block of 64 points taken
+// point by point (74 points per swimmer leave 10 in it).  The elastic forces are computed per point from the
 // positions in LDS: every point evaluates the springs and curvature nodes it
 // belongs to, so forces need no atomics and no per-term buffers.
 //
@@ -411,7 +412,10 @@ __device__ void sperm_system(const SpermShape& g, const SpermRun& r, int64_t s, 
     for (int step = 0; step < r.steps; ++step) {
         {
             T ax[TPL], ay[TPL];
-            pair_phase_sym<T, TPL, WPS>(C, tab, src, n, wave, lane, ax, ay);
+            if (tail_pays(n))
+                pair_phase_tail<T, TPL, WPS>(C, tab, src, n, wave, lane, ax, ay);
+            else
+                pair_phase_sym<T, TPL, WPS>(C, tab, src, n, wave, lane, ax, ay);
 #pragma unroll
             for (int c = 0; c < TPL; ++c) {
                 if (64 * c < n) {
