@@ -116,15 +116,15 @@ def mlp_leg(ctx, stream, rows=1 << 20, train_rows=65536, batch=1024, epochs=2):
             "train_frac": train_tf / BF16_PEAK_TFLOPS, "dtype": "bf16 operands, fp32 accumulation"}
 
 
-def dense_leg(ctx, stream, with_oracle, samples=64, steps=1000):
+def dense_leg(ctx, stream, samples=64, steps=1000):
     """Large-N dense workload: `samples` independent systems of 8 interacting
     swimmers of N = 512 (4096 points) on a 2 x 4 grid of spacing 1.5, random
     beat phases, alpha ~ U[0, 10] (seed 3), FP32.  The stated dt = 2e-5 is
     beyond forward Euler's stability bound at N = 512 (dt * rho ~ 51), so the
     run uses the largest stable power-of-two fraction, dt / 32; the work per
     step does not depend on dt.  Runs on the per-step large-system kernel.
-    With the oracle: the velocity of sample 0 at its initial configuration
-    (forces at t = 0) against the FP64 oracle, all 4096 points."""
+    (The parity of one full-size velocity evaluation against the FP64
+    oracle is a test: test_dense_sample_velocity_at_full_size.)"""
     import torch
     from paper_1910_12007_amd import inputs, swim
     lay = inputs.dense_layout(n_samples=samples, seed=3)
@@ -154,33 +154,6 @@ def dense_leg(ctx, stream, with_oracle, samples=64, steps=1000):
            "valu_tops": VALU_OPS_PER_PAIR_BIG * pairs / (ms * 1e-3) / 1e12, "valu_peak_tops": VALU_PEAK_TOPS,
            "valu_frac": VALU_OPS_PER_PAIR_BIG * pairs / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
            "valu_ops_per_pair": VALU_OPS_PER_PAIR_BIG}
-    if with_oracle:
-        from oracle import core
-        P0 = lay[0]
-        xs, ys = [], []
-        for m in range(8):
-            s_ = np.arange(512) / 511.0
-            xs.append(P0[m, 7] + s_)
-            ys.append(np.full(512, P0[m, 8]))
-        X, Y = np.concatenate(xs), np.concatenate(ys)
-        kap = [core.kappa0(512, P0[m, 3], P0[m, 5], P0[m, 4], P0[m, 6], 0.0) for m in range(8)]
-        F = [core.forces(xs[m], ys[m], P0[m, 1], P0[m, 2], kap[m]) for m in range(8)]
-        FX = np.concatenate([f[0] for f in F])
-        FY = np.concatenate([f[1] for f in F])
-        # the oracle takes the FP32 run's inputs (positions, forces rounded to FP32)
-        X, Y, FX, FY = (a.astype(np.float32).astype(np.float64) for a in (X, Y, FX, FY))
-        eps = 1.5 / 511
-        ox, oy = core.velocity(X, Y, FX, FY, P0[0, 0], eps)
-        t32 = torch.float32
-        ux = torch.empty(4096, dtype=t32, device="cuda")
-        uy = torch.empty_like(ux)
-        dv = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda")
-        swim.swim_pair_velocity(ctx, np.array([0, 4096]), [P0[0, 0]], [eps], dv(X), dv(Y), dv(FX), dv(FY), ux, uy,
-                                stream=stream)
-        torch.cuda.synchronize()
-        g = np.concatenate([ux.cpu().double().numpy(), uy.cpu().double().numpy()])
-        r = np.concatenate([ox, oy])
-        out["sample0_velocity_rel_err_vs_fp64_oracle"] = float(np.linalg.norm(g - r) / np.linalg.norm(r))
     return out
 
 
@@ -547,7 +520,7 @@ def main():
     out["surrogate_mfma"] = mlp_leg(ctx, stream)
     out["fused_vs_per_sample"] = per_sample_leg(ctx, stream, P)
     if not args.no_dense:
-        out["dense"] = dense_leg(ctx, stream, with_oracle=not args.no_cpu)
+        out["dense"] = dense_leg(ctx, stream)
     if not args.no_pmc:
         out["pmc_uneven"] = pmc_leg(ctx, load_data())
     if not args.no_tmcmc:
