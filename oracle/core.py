@@ -17,6 +17,19 @@ _I64 = ctypes.POINTER(ctypes.c_int64)
 _I32 = ctypes.POINTER(ctypes.c_int32)
 
 
+class paper_blob:
+    """Context manager: the oracle's kernel functions use the paper's blob
+    3 eps^3 / (2 pi R^5) (eq. eqnblob; Stokes limit only) inside it."""
+
+    def __enter__(self):
+        lib().oracle_set_blob(1)
+        return self
+
+    def __exit__(self, *exc):
+        lib().oracle_set_blob(0)
+        return False
+
+
 def lib():
     """Load liboracle.so, building it with gcc if it is missing."""
     global _LIB
@@ -56,6 +69,7 @@ def lib():
                                            ctypes.c_double, ctypes.c_double, _D, _D, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_int, _D, _D, _D, _D, _I32]
         L.oracle_sperm_forward.restype = ctypes.c_int
+        L.oracle_set_blob.argtypes = [ctypes.c_int]
         L.oracle_blob.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int64, _D, _D, _D]
         L.oracle_field.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int64, _D, _D, _D, _D, _D]

@@ -135,9 +135,23 @@ static ld q_of(ld z)
 typedef struct {
     ld alpha, eps, e2;
     int stokes;
+    int paper; /* the paper's blob (eq. eqnblob), Stokes limit only */
     ld c, q0;
     ld gam[NGAM];
 } okern;
+
+/* Blob selection for the kernel functions below (test infrastructure:
+ * set per call by the Python wrapper).  0: the blob of the reading above;
+ * 1: the paper's blob phi = 3 eps^3 / (2 pi R^5) of eq. (eqnblob), whose
+ * Stokes Green function G (Delta G = phi) is
+ *   G = (ln(R + eps) - eps/R) / (2 pi)
+ * (r G' = m/(2 pi) with the blob mass m = 1 - eps^3/R^3).  Its kernel uses
+ * the same route as the other blob: M = int_0^r s G ds =
+ * [(r^2/2) ln(R + eps) - (R + 3 eps)(R - eps)/4] / (2 pi), H1 = M/r^2 - G,
+ * H2 = (G - 2M/r^2)/r^2; near contact the series of G in delta with the
+ * same formulas.  Only alpha = 0 (no closed form exists for alpha > 0). */
+static int g_blob = 0;
+void oracle_set_blob(int b) { g_blob = b; }
 
 static void kernel_init(okern *k, double alpha, double eps)
 {
@@ -146,6 +160,32 @@ static void kernel_init(okern *k, double alpha, double eps)
     k->eps = eps;
     k->e2 = (ld)eps * (ld)eps;
     k->stokes = (alpha == 0.0);
+    if (g_blob == 1) {
+        /* Taylor coefficients of G in delta: with a = sqrt(1 + delta) and
+         * u = (a - 1)/2, ln(1 + a) = ln 2 + ln(1 + u), whose coefficients L_n
+         * satisfy n L_n = n u_n - sum_{j=1}^{n-1} j L_j u_{n-j};
+         * eps/R = (1 + delta)^(-1/2). */
+        k->paper = 1;
+        k->c = 1.0L;
+        ld an[NGAM], bn[NGAM], un[NGAM], Ln[NGAM];
+        an[0] = 1.0L;
+        bn[0] = 1.0L;
+        for (int n = 1; n < NGAM; ++n) {
+            an[n] = an[n - 1] * (0.5L - (ld)(n - 1)) / (ld)n;
+            bn[n] = bn[n - 1] * (-0.5L - (ld)(n - 1)) / (ld)n;
+        }
+        un[0] = 0.0L;
+        for (int n = 1; n < NGAM; ++n) un[n] = 0.5L * an[n];
+        Ln[0] = 0.0L;
+        for (int n = 1; n < NGAM; ++n) {
+            ld acc = (ld)n * un[n];
+            for (int j = 1; j < n; ++j) acc -= (ld)j * Ln[j] * un[n - j];
+            Ln[n] = acc / (ld)n;
+        }
+        k->gam[0] = (logl((ld)eps) + logl(2.0L) - 1.0L) / (2.0L * PI_L);
+        for (int n = 1; n < NGAM; ++n) k->gam[n] = (Ln[n] - bn[n]) / (2.0L * PI_L);
+        return;
+    }
     if (k->stokes) {
         k->c = 1.0L;
         k->gam[0] = logl(k->e2) / (4.0L * PI_L);
@@ -182,6 +222,14 @@ static void kernel_eval(const okern *k, double t_d, ld *H1, ld *H2)
         }
         *H1 = h1;
         *H2 = h2 / k->e2;
+        return;
+    }
+    if (k->paper) {
+        ld R = sqrtl(t + k->e2), e = (ld)k->eps;
+        ld G = (logl(R + e) - e / R) / (2.0L * PI_L);
+        ld M = (0.5L * t * logl(R + e) - 0.25L * (R + 3.0L * e) * (R - e)) / (2.0L * PI_L);
+        *H1 = M / t - G;
+        *H2 = (G - 2.0L * M / t) / t;
         return;
     }
     if (k->stokes) {
@@ -791,6 +839,10 @@ static ld mass_over_r2(const okern *k, double t_d)
         return (2.0L * PI_L / k->e2) * (2.0L * a - 0.5L * a2e2 * b);
     }
     ld R2 = t + k->e2;
+    if (k->paper) {
+        ld R = sqrtl(R2), e = (ld)k->eps;
+        return (1.0L - e * e * e / (R2 * R)) / t;
+    }
     if (k->stokes) return 1.0L / R2;
     ld R = sqrtl(R2);
     ld K0R, K1R, K0e, K1e;
@@ -803,6 +855,7 @@ static ld mass_over_r2(const okern *k, double t_d)
 static ld blob_phi(const okern *k, double t_d)
 {
     ld R2 = (ld)t_d + k->e2, R = sqrtl(R2);
+    if (k->paper) return 3.0L * k->e2 * (ld)k->eps / (2.0L * PI_L * R2 * R2 * R);
     if (k->stokes) return k->e2 / (PI_L * R2 * R2);
     ld K0, K1, a = k->alpha;
     bessel_k01(a * R, &K0, &K1);
