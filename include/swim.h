@@ -94,15 +94,32 @@ int swim_version(void);
  *                    that layout recurs, 2 capture every new layout at once.
  *                    Parameter values may change between replays: they are
  *                    uploaded before the graph runs.
+ *   SWIM_OPT_BLOB    the regularization blob of the velocity kernel:
+ *                    SWIM_BLOB_READING (default), the unit-mass blob
+ *                    c eps^2/(2 pi) [alpha^2 K0(alpha R)/R^2 + 2 alpha
+ *                    K1(alpha R)/R^3] (eps^2/(pi R^4) at alpha = 0), whose
+ *                    Brinkmanlet has a closed form for every alpha; or
+ *                    SWIM_BLOB_PAPER, the blob of eq. (eqnblob), whose kernel
+ *                    has a closed form only in the Stokes limit:
+ *                    H2 = (R + 2 eps)/(4 pi R (R + eps)^2) and
+ *                    H1 = -[ln(R + eps) - eps (R + 2 eps)/(R (R + eps))]/(4 pi)
+ *                    - 1/(8 pi).  With SWIM_BLOB_PAPER, systems with
+ *                    alpha > 0 are SWIM_EINVAL (swim_pair_velocity,
+ *                    swim_flow_field) or get SWIM_ST_BADPARAM (batched runs).
+ *                    It applies to every velocity and pressure evaluation,
+ *                    including the pressure's blob mass (1 - eps^3/R^3).
  * Read-only counters (swim_get_option): SWIM_OPT_GRAPH_LAUNCHES (graph
  * replays and first launches so far), SWIM_OPT_GRAPH_CAPTURES.
- * Results do not depend on the options beyond rounding of the source-split
- * partial sums.  SWIM_EINVAL for an unknown key or value. */
+ * Results do not depend on the launch options beyond rounding of the
+ * source-split partial sums.  SWIM_EINVAL for an unknown key or value. */
 #define SWIM_OPT_WPS 1
 #define SWIM_OPT_BIG_TPL 2
 #define SWIM_OPT_GRAPH 3
 #define SWIM_OPT_GRAPH_LAUNCHES 4
 #define SWIM_OPT_GRAPH_CAPTURES 5
+#define SWIM_OPT_BLOB 6
+#define SWIM_BLOB_READING 0 /* default: the unit-mass blob whose Brinkmanlet has a closed form for all alpha */
+#define SWIM_BLOB_PAPER 1   /* eq. (eqnblob): 3 eps^3 / (2 pi (r^2 + eps^2)^(5/2)); alpha = 0 only */
 int swim_set_option(swim_ctx *ctx, int32_t key, int32_t value);
 int swim_get_option(swim_ctx *ctx, int32_t key, int32_t *value);
 

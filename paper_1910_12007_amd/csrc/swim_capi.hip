@@ -98,6 +98,7 @@ struct swim_ctx {
     int opt_wps = 0;      // waves per system in the persistent kernel (0: automatic)
     int opt_big_tpl = 0;  // targets per lane of the large-system kernel (0: automatic)
     int opt_graph = 1;    // 0: eager launches; 1: capture on a repeated layout; 2: capture always
+    int opt_blob = 0;     // 0: the kernel reading's blob; 1: the paper's blob (alpha = 0 only)
     int tuned_wps[2][9] = {};  // autotuned waves per system [dtype][tpl] (0: not tuned)
     FwdGraph graphs[N_GRAPHS];
     uint64_t graph_clock = 0, last_key = 0;
@@ -395,7 +396,7 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     auto launch_all = [&]() -> hipError_t {
         hipError_t e = launch_sysconst_batch(dtype, n_sys, (const int64_t*)c->buf[B_SWOFF].p,
                                              (const int32_t*)c->buf[B_NPT].p, params_dev, run.eps_over_ds, sysc,
-                                             sysc64, status, st);
+                                             sysc64, status, c->opt_blob, st);
         if (e == hipSuccess && dtype == SWIM_F32) e = launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, st);
         if (e == hipSuccess) e = launch_fill_i32((int32_t*)c->buf[B_QUEUE].p, 0, 8, st);
         for (size_t k = 0; k < bk.size() && e == hipSuccess; ++k) {
@@ -434,6 +435,7 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     h.add(run.n_obs);
     h.add(run.eps_over_ds);
     h.add(tpl_big);
+    h.add(c->opt_blob);
     for (const Bucket& q : bk) {
         h.add(q.tpl);
         h.add(q.wps);
@@ -654,6 +656,9 @@ int swim_set_option(swim_ctx* c, int32_t key, int32_t value)
     } else if (key == SWIM_OPT_GRAPH) {
         if (value < 0 || value > 2) return fail(SWIM_EINVAL, "graph mode must be 0, 1 or 2");
         c->opt_graph = value;
+    } else if (key == SWIM_OPT_BLOB) {
+        if (value != SWIM_BLOB_READING && value != SWIM_BLOB_PAPER) return fail(SWIM_EINVAL, "blob must be 0 or 1");
+        c->opt_blob = value;
     } else {
         return fail(SWIM_EINVAL, "unknown option %d", key);
     }
@@ -666,6 +671,7 @@ int swim_get_option(swim_ctx* c, int32_t key, int32_t* value)
     if (key == SWIM_OPT_WPS) *value = c->opt_wps;
     else if (key == SWIM_OPT_BIG_TPL) *value = c->opt_big_tpl;
     else if (key == SWIM_OPT_GRAPH) *value = c->opt_graph;
+    else if (key == SWIM_OPT_BLOB) *value = c->opt_blob;
     else if (key == SWIM_OPT_GRAPH_LAUNCHES) *value = (int32_t)c->graph_launches;
     else if (key == SWIM_OPT_GRAPH_CAPTURES) *value = (int32_t)c->graph_captures;
     else return fail(SWIM_EINVAL, "unknown option %d", key);
@@ -687,6 +693,8 @@ int swim_pair_velocity(swim_ctx* c, int32_t dtype, int64_t n_sys, const int64_t*
         if (!(std::isfinite(alpha[s]) && alpha[s] >= 0)) return fail(SWIM_EINVAL, "alpha[%lld] must be finite and >= 0", (long long)s);
         if (!(std::isfinite(eps[s]) && eps[s] > 0)) return fail(SWIM_EINVAL, "eps[%lld] must be finite and > 0", (long long)s);
         if (alpha[s] * eps[s] > 1.0) return fail(SWIM_EINVAL, "alpha*eps > 1 for system %lld", (long long)s);
+        if (c->opt_blob == SWIM_BLOB_PAPER && alpha[s] != 0.0)
+            return fail(SWIM_EINVAL, "the paper's blob has a kernel only for alpha = 0 (system %lld)", (long long)s);
     }
     const int64_t npts = sys_off[n_sys];
     if (npts > 0 && (!x || !y || !fx || !fy || !ux || !uy)) return fail(SWIM_EINVAL, "null data pointer");
@@ -710,7 +718,7 @@ int swim_pair_velocity(swim_ctx* c, int32_t dtype, int64_t n_sys, const int64_t*
     void *sysc, *sysc64;
     TRY(sysconst_buffers(c, dtype, n_sys, &sysc, &sysc64));
     HIPCHK(launch_sysconst(dtype, n_sys, (const double*)c->buf[B_ALPHA].p, (const double*)c->buf[B_EPS].p, sysc,
-                           sysc64, st));
+                           sysc64, c->opt_blob, st));
     void* tab = nullptr;
     if (dtype == SWIM_F32) {
         TRY(ensure(c, B_TAB, (size_t)n_sys * table_bytes()));
@@ -735,9 +743,12 @@ int swim_flow_field(swim_ctx* c, int32_t dtype, int64_t n, const void* x, const 
     if (nt == 0) return SWIM_OK;
     if ((n > 0 && (!x || !y || !fx || !fy)) || !tx || !ty || !u || !v || !p)
         return fail(SWIM_EINVAL, "null device pointer");
+    if (c->opt_blob == SWIM_BLOB_PAPER && alpha != 0.0)
+        return fail(SWIM_EINVAL, "the paper's blob has a kernel only for alpha = 0");
     FieldConst fc{};
-    sysconst_compute<float>(alpha, eps, &fc.c32);
-    sysconst_compute<double>(alpha, eps, &fc.c64);
+    sysconst_compute<float>(alpha, eps, &fc.c32, c->opt_blob);
+    sysconst_compute<double>(alpha, eps, &fc.c64, c->opt_blob);
+    fc.paper = c->opt_blob == SWIM_BLOB_PAPER;
     fc.h1c = fc.c64.h1c;
     fc.e2 = eps * eps;
     fc.inv_e2 = 1.0 / fc.e2;
@@ -914,7 +925,8 @@ int sperm_forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const swim_spe
     HIPCHK(prepare_sperm(dtype, tpl, wps));
     const int per_cu = sperm_blocks_per_cu(dtype, tpl, wps);
     const int nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(n_sys, (int64_t)per_cu * c->num_cu));
-    HIPCHK(launch_sperm_setup(dtype, n_sys, sh.n_swim, sh.eps, sys_params, swim_params, sysc, sysc64, status, st));
+    HIPCHK(launch_sperm_setup(dtype, n_sys, sh.n_swim, sh.eps, sys_params, swim_params, sysc, sysc64, status,
+                              c->opt_blob, st));
     if (dtype == SWIM_F32) HIPCHK(launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, st));
     HIPCHK(launch_fill_i32((int32_t*)c->buf[B_QUEUE].p, 0, 8, st));
     HIPCHK(launch_sperm_forward(dtype, tpl, wps, nblocks, g, r, sysc, dtype == SWIM_F32 ? c->buf[B_TAB].p : nullptr,

@@ -65,7 +65,11 @@ __global__ __launch_bounds__(256) void k_flow_field(int64_t n, const T* x, const
             const double t = fma(dxd, dxd, dyd * dyd);
             const double delta = t * fc.inv_e2;
             double w;
-            if (fc.stokes) {
+            if (fc.paper) {
+                // m = 1 - eps^3/R^3:  w = (R^2 + R eps + eps^2) / (2 pi R^3 (R + eps))
+                const double R2 = t + fc.e2, R = sqrt(R2);
+                w = fc.inv_2pi * (R2 + R * fc.eps + fc.e2) / (R2 * R * (R + fc.eps));
+            } else if (fc.stokes) {
                 w = fc.inv_2pi / (t + fc.e2);
             } else if (delta < 0.25) {
                 w = fc.ser[FIELD_NSER - 1];

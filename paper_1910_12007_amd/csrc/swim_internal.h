@@ -36,11 +36,13 @@ struct Run {
 
 // all launchers return hipError_t of the launch
 // (dtype 0 also writes the FP64 constants into sysc64, for the kernel tables)
+// blob: 0 the kernel reading's blob, 1 the paper's blob (alpha = 0 only;
+// batch rows with alpha > 0 get SWIM_ST_BADPARAM)
 hipError_t launch_sysconst_batch(int dtype, int64_t n_sys, const int64_t* sw_off, const int32_t* npt,
                                  const double* params, double eps_over_ds, void* sysc, void* sysc64,
-                                 int32_t* status, hipStream_t st);
+                                 int32_t* status, int blob, hipStream_t st);
 hipError_t launch_sysconst(int dtype, int64_t n_sys, const double* alpha, const double* eps,
-                           void* sysc, void* sysc64, hipStream_t st);
+                           void* sysc, void* sysc64, int blob, hipStream_t st);
 hipError_t launch_pair_velocity(int dtype, int tpl, int64_t n_blocks, const int64_t* blk_sys,
                                 const int64_t* blk_first, const int64_t* pt_off, const void* sysc,
                                 const void* tab, const void* x, const void* y, const void* fx,
@@ -156,7 +158,8 @@ struct SpermRun {
     double dt;
 };
 hipError_t launch_sperm_setup(int dtype, int64_t n_sys, int32_t nsw, double eps, const double* sysp,
-                              const double* swp, void* sysc, void* sysc64, int32_t* status, hipStream_t st);
+                              const double* swp, void* sysc, void* sysc64, int32_t* status, int blob,
+                              hipStream_t st);
 size_t sperm_lds_bytes(int dtype, int tpl, int wps);
 hipError_t prepare_sperm(int dtype, int tpl, int wps);
 int sperm_blocks_per_cu(int dtype, int tpl, int wps);
@@ -185,7 +188,7 @@ struct FieldConst {
     SysConst<float> c32;
     SysConst<double> c64;
     double h1c, inv_e2, e2, eps, alpha, K1e, inv_2pi;
-    int32_t stokes, pad;
+    int32_t stokes, paper;  // paper: the paper's blob (mass 1 - eps^3/R^3)
     double ser[FIELD_NSER];
 };
 hipError_t launch_flow_field(int dtype, int64_t n, const void* x, const void* y, const void* fx, const void* fy,

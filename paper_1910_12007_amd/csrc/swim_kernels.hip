@@ -227,12 +227,12 @@ __device__ __forceinline__ void pair_accumulate_x(const SysConst<float>& C, cons
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_sysconst(int64_t n, const double* alpha, const double* eps, SysConst<T>* out,
-                           SysConst<double>* out64)
+                           SysConst<double>* out64, int blob)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    sysconst_compute<T>(alpha[i], eps[i], out + i);
-    if (out64) sysconst_compute<double>(alpha[i], eps[i], out64 + i);
+    sysconst_compute<T>(alpha[i], eps[i], out + i, blob);
+    if (out64) sysconst_compute<double>(alpha[i], eps[i], out64 + i, blob);
 }
 
 // per-system constants of a forward batch; systems whose parameters leave
@@ -240,18 +240,20 @@ __global__ void k_sysconst(int64_t n, const double* alpha, const double* eps, Sy
 // flagged SWIM_ST_BADPARAM_ and skipped by the run kernels.
 template <typename T>
 __global__ void k_sysconst_batch(int64_t n, const int64_t* sw_off, const int32_t* npt, const double* params,
-                                 double eps_over_ds, SysConst<T>* out, SysConst<double>* out64, int32_t* status)
+                                 double eps_over_ds, SysConst<T>* out, SysConst<double>* out64, int32_t* status,
+                                 int blob)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double alpha = params[9 * sw_off[s]];
     const double eps = eps_over_ds / (double)(npt[s] - 1);
-    bool ok = isfinite(alpha) && alpha >= 0.0 && alpha * eps <= 1.0;
+    // the paper's blob has a kernel only in the Stokes limit
+    bool ok = isfinite(alpha) && alpha >= 0.0 && alpha * eps <= 1.0 && (blob == 0 || alpha == 0.0);
     for (int64_t f = sw_off[s]; f < sw_off[s + 1]; ++f)
         for (int c = 0; c < 9; ++c) ok = ok && isfinite(params[9 * f + c]);
     status[s] = ok ? 0 : SWIM_ST_BADPARAM_;
-    sysconst_compute<T>(ok ? alpha : 0.0, eps, out + s);
-    if (out64) sysconst_compute<double>(ok ? alpha : 0.0, eps, out64 + s);
+    sysconst_compute<T>(ok ? alpha : 0.0, eps, out + s, blob);
+    if (out64) sysconst_compute<double>(ok ? alpha : 0.0, eps, out64 + s, blob);
 }
 
 // FP32 kernel tables of systems [s0, s0 + n), one thread per interval; the
@@ -1078,28 +1080,28 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 
 hipError_t launch_sysconst_batch(int dtype, int64_t n_sys, const int64_t* sw_off, const int32_t* npt,
                                  const double* params, double eps_over_ds, void* sysc, void* sysc64,
-                                 int32_t* status, hipStream_t st)
+                                 int32_t* status, int blob, hipStream_t st)
 {
     if (n_sys <= 0) return hipSuccess;
     if (dtype == 0)
         hipLaunchKernelGGL(k_sysconst_batch<float>, dim3(nblk(n_sys, 64)), dim3(64), 0, st, n_sys, sw_off, npt,
-                           params, eps_over_ds, (SysConst<float>*)sysc, (SysConst<double>*)sysc64, status);
+                           params, eps_over_ds, (SysConst<float>*)sysc, (SysConst<double>*)sysc64, status, blob);
     else
         hipLaunchKernelGGL(k_sysconst_batch<double>, dim3(nblk(n_sys, 64)), dim3(64), 0, st, n_sys, sw_off, npt,
-                           params, eps_over_ds, (SysConst<double>*)sysc, (SysConst<double>*)nullptr, status);
+                           params, eps_over_ds, (SysConst<double>*)sysc, (SysConst<double>*)nullptr, status, blob);
     return hipGetLastError();
 }
 
 hipError_t launch_sysconst(int dtype, int64_t n_sys, const double* alpha, const double* eps, void* sysc,
-                           void* sysc64, hipStream_t st)
+                           void* sysc64, int blob, hipStream_t st)
 {
     if (n_sys <= 0) return hipSuccess;
     if (dtype == 0)
         hipLaunchKernelGGL(k_sysconst<float>, dim3(nblk(n_sys, 64)), dim3(64), 0, st, n_sys, alpha, eps,
-                           (SysConst<float>*)sysc, (SysConst<double>*)sysc64);
+                           (SysConst<float>*)sysc, (SysConst<double>*)sysc64, blob);
     else
         hipLaunchKernelGGL(k_sysconst<double>, dim3(nblk(n_sys, 64)), dim3(64), 0, st, n_sys, alpha, eps,
-                           (SysConst<double>*)sysc, (SysConst<double>*)nullptr);
+                           (SysConst<double>*)sysc, (SysConst<double>*)nullptr, blob);
     return hipGetLastError();
 }
 

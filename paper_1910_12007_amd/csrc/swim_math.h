@@ -124,8 +124,8 @@ template <typename T> struct alignas(16) SysConst {
     T a2, e2, inv_e2, half_inv_e2;   // alpha^2, eps^2, 1/eps^2, 1/(2 eps^2)
     T w0, inv_a2;                    // alpha^2 eps^2, 1/alpha^2 (0 if alpha = 0)
     T cpi, c2pi;                     // c/pi, c/(2 pi)
-    T K0z0, q0, h1c, pad;            // K0(alpha eps), Q(w0), H1(0)
-    T ts, its, tr, pad2;             // FP32 table scale sigma = rho^2, 1/sigma, rho = 2^m
+    T K0z0, q0, h1c, paper;          // K0(alpha eps), Q(w0), H1(0); 1: the paper's blob
+    T ts, its, tr, eps;              // FP32 table scale sigma = rho^2, 1/sigma, rho = 2^m; eps
     T U[NT_MAX];                     // U(t) = t * sum_n U[n] t^n
     T V[NT_MAX];                     // V(t) = sum_n V[n] t^n
 };
@@ -174,7 +174,9 @@ SWIM_HD double taylor_at(const double* p, int M, int n, double w0)
 
 // Computes the constants of one system in FP64 and rounds them to T.
 // Requires alpha >= 0, eps > 0, alpha * eps <= 1 (checked by the caller).
-template <typename T> SWIM_HD void sysconst_compute(double alpha, double eps, SysConst<T>* out)
+// blob 1 selects the paper's blob 3 eps^3 / (2 pi R^5) (eq. eqnblob), whose
+// kernel exists in closed form only for alpha = 0 (the caller checks).
+template <typename T> SWIM_HD void sysconst_compute(double alpha, double eps, SysConst<T>* out, int blob = 0)
 {
     const double a2 = alpha * alpha, e2 = eps * eps, w0 = a2 * e2;
     SysConst<T> C;
@@ -183,12 +185,12 @@ template <typename T> SWIM_HD void sysconst_compute(double alpha, double eps, Sy
     C.inv_e2 = (T)(1.0 / e2);
     C.half_inv_e2 = (T)(0.5 / e2);
     C.w0 = (T)w0;
-    C.pad = (T)0;
+    C.paper = (T)(blob == 1 ? 1 : 0);
     const int m = tab_scale_exp(eps);
     C.ts = (T)ldexp(1.0, 2 * m);
     C.its = (T)ldexp(1.0, -2 * m);
     C.tr = (T)ldexp(1.0, m);
-    C.pad2 = (T)0;
+    C.eps = (T)eps;
     for (int n = 0; n < NT_MAX; ++n) { C.U[n] = (T)0; C.V[n] = (T)0; }
     if (alpha == 0.0) {
         C.inv_a2 = (T)0;
@@ -196,7 +198,9 @@ template <typename T> SWIM_HD void sysconst_compute(double alpha, double eps, Sy
         C.c2pi = (T)(0.5 / PI);
         C.K0z0 = (T)0;
         C.q0 = (T)0;
-        C.h1c = (T)(-log(eps) / (4.0 * PI));
+        // H1(0): -ln(eps)/(4 pi) for the blob of the reading above;
+        // (1 - ln(2 eps))/(4 pi) for the paper's blob
+        C.h1c = blob == 1 ? (T)((1.0 - log(2.0 * eps)) / (4.0 * PI)) : (T)(-log(eps) / (4.0 * PI));
         *out = C;
         return;
     }
@@ -388,9 +392,28 @@ SWIM_HD void kernel_large_z(const SysConst<T>& C, T t, T w, T& Ht, T& H2)
     Ht = (T)-0.5 * fma_t(t, H2, gt);
 }
 
+// The paper's blob in the Stokes limit (G = (ln(R + eps) - eps/R)/(2 pi),
+// H1 = M/r^2 - G, H2 = (G - 2M/r^2)/r^2), in cancellation-free form:
+//   H2 = (R + 2 eps) / (4 pi R (R + eps)^2),
+//   Ht = (1/2pi) [ -1/2 log1p(t / (2 eps (R + eps))) - (3R + 4 eps) t / (4 R (R + eps)^2) ]
+template <typename T>
+SWIM_HD void kernel_paper_stokes(const SysConst<T>& C, T t, T& Ht, T& H2)
+{
+    const T e = C.eps;
+    const T R = sqrt_t(t + C.e2);
+    const T Re = R + e;
+    const T q = (T)1 / (R * Re * Re);
+    H2 = (T)(0.25 / PI) * (R + (T)2 * e) * q;
+    Ht = (T)(0.5 / PI) * ((T)-0.5 * log1p_t(t / ((T)2 * e * Re)) - (T)0.25 * ((T)3 * R + (T)4 * e) * t * q);
+}
+
 template <typename T>
 SWIM_HD void kernel_eval(const SysConst<T>& C, T t, T& Ht, T& H2)
 {
+    if (C.paper != (T)0) {
+        kernel_paper_stokes<T>(C, t, Ht, H2);
+        return;
+    }
     const T w = fma_t(C.a2, t, C.w0);
     if (w <= (T)(SWIM_KFIT_ZS * SWIM_KFIT_ZS))
         kernel_small_z<T>(C, t, w, Ht, H2);

@@ -511,18 +511,18 @@ __global__ __launch_bounds__(64 * WPS) void k_sperm_forward(SpermShape g, SpermR
 // per-system constants; rows outside the model's domain are flagged
 template <typename T>
 __global__ void k_sperm_setup(int64_t n_sys, int32_t nsw, double eps, const double* sysp, const double* swp,
-                              SysConst<T>* sysc, SysConst<double>* sysc64, int32_t* status)
+                              SysConst<T>* sysc, SysConst<double>* sysc64, int32_t* status, int blob)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_sys) return;
     const double* p = sysp + (int64_t)SWIM_SP_NPARAM * s;
     const double alpha = p[SWIM_SP_ALPHA];
-    bool ok = isfinite(alpha) && alpha >= 0.0 && alpha * eps <= 1.0;
+    bool ok = isfinite(alpha) && alpha >= 0.0 && alpha * eps <= 1.0 && (blob == 0 || alpha == 0.0);
     for (int c = 0; c < SWIM_SP_NPARAM; ++c) ok = ok && isfinite(p[c]);
     for (int c = 0; c < 3 * nsw; ++c) ok = ok && isfinite(swp[(int64_t)3 * nsw * s + c]);
     status[s] = ok ? 0 : ST_BADPARAM;
-    sysconst_compute<T>(ok ? alpha : 0.0, eps, sysc + s);
-    if (sysc64) sysconst_compute<double>(ok ? alpha : 0.0, eps, sysc64 + s);
+    sysconst_compute<T>(ok ? alpha : 0.0, eps, sysc + s, blob);
+    if (sysc64) sysconst_compute<double>(ok ? alpha : 0.0, eps, sysc64 + s, blob);
 }
 
 // observables of a sperm run per system s and interval/sample k = 1..n_obs
@@ -630,16 +630,17 @@ template <typename F> hipError_t sperm_dispatch(int dtype, int tpl, int wps, F f
 size_t sperm_lds_bytes(int dtype, int tpl, int wps) { return sperm_lds_layout(dtype, tpl, wps).total; }
 
 hipError_t launch_sperm_setup(int dtype, int64_t n_sys, int32_t nsw, double eps, const double* sysp,
-                              const double* swp, void* sysc, void* sysc64, int32_t* status, hipStream_t st)
+                              const double* swp, void* sysc, void* sysc64, int32_t* status, int blob,
+                              hipStream_t st)
 {
     if (n_sys == 0) return hipSuccess;
     const int nb = (int)((n_sys + 255) / 256);
     if (dtype == 0)
         hipLaunchKernelGGL(k_sperm_setup<float>, dim3(nb), dim3(256), 0, st, n_sys, nsw, eps, sysp, swp,
-                           (SysConst<float>*)sysc, (SysConst<double>*)sysc64, status);
+                           (SysConst<float>*)sysc, (SysConst<double>*)sysc64, status, blob);
     else
         hipLaunchKernelGGL(k_sperm_setup<double>, dim3(nb), dim3(256), 0, st, n_sys, nsw, eps, sysp, swp,
-                           (SysConst<double>*)sysc, (SysConst<double>*)nullptr, status);
+                           (SysConst<double>*)sysc, (SysConst<double>*)nullptr, status, blob);
     return hipGetLastError();
 }
 
