@@ -182,3 +182,30 @@ def test_tmcmc_sperm_argument_errors(ctx):
                dict(n=1), dict(shape=swim.sperm_shape(20, 8, 1), sw=sw[:1])):
         with pytest.raises(swim.SwimError):
             call(**kw)
+
+
+def test_fp32_sperm_run_agrees_with_fp64_in_distribution(ctx, oracle_core):
+    """FP32 forward runs change the likelihoods at the rounding level, so the
+    chains take other decisions.  The FP32 run is compared in distribution:
+    one swimmer, theta = (alpha, sigma/beta), 256 samples per stage.  Same
+    number of stages within one, posterior means within one FP64 posterior
+    standard deviation, evidence within 1 in log."""
+    shape = swim.sperm_shape()
+    dt, steps, oe = 1e-5, 60, 20
+    sys_row = inputs.sperm_rows(1)[0]
+    sw = inputs.sperm_swimmers(1)
+    r = oracle_core.sperm_forward(sys_row, sw, shape.n_flag, shape.n_head, EPS, HR, shape.neck_gap, steps, dt, oe)
+    xi = oracle_core.sperm_head_velocity(r["head"], oe * dt)
+    beta = [abs(xi.mean())] * 2
+    data = xi + 0.05 * beta[0] * np.random.Generator(np.random.PCG64(6)).normal(size=xi.shape)
+    out = {}
+    for dt_ in (swim.SWIM_F64, swim.SWIM_F32):
+        m = swim.sperm_model(shape, sys_row, ("alpha",), 1, swim.SWIM_OBS_HEAD_VELOCITY, beta, steps, oe, dt, dt_)
+        out[dt_] = swim.tmcmc_sperm_run(ctx, m, sw, [0.0, 0.01], [2.0, 0.5], data, 256, 41, max_stages=20)
+    a, b = out[swim.SWIM_F64], out[swim.SWIM_F32]
+    print({"stages": (a["n_stages"], b["n_stages"]), "mean64": a["theta"].mean(0), "mean32": b["theta"].mean(0),
+           "std64": a["theta"].std(0), "logZ": (a["log_evidence"], b["log_evidence"])})
+    assert a["q"][-1] == 1.0 and b["q"][-1] == 1.0
+    assert abs(a["n_stages"] - b["n_stages"]) <= 1
+    assert np.all(np.abs(a["theta"].mean(0) - b["theta"].mean(0)) <= a["theta"].std(0))
+    assert abs(a["log_evidence"] - b["log_evidence"]) < 1.0
