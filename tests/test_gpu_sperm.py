@@ -205,3 +205,52 @@ def test_argument_errors(ctx):
         with pytest.raises(swim.SwimError):
             swim.swim_sperm_forward(ctx, swim.SWIM_F64, swim.sperm_shape(), rows, sw, steps, dt, oe, head, tail,
                                     status)
+
+
+@pytest.mark.parametrize("nf,nh,nsw,steps", [(4, 4, 1, 40), (4, 4, 3, 40), (100, 28, 4, 10)])
+def test_extreme_shapes_match_oracle(ctx, oracle_core, nf, nh, nsw, steps):
+    """The smallest swimmer (a 4-point flagellum, a 4-point head) alone and
+    three of them, and the largest system the kernel takes (4 swimmers of
+    128 points: 512 points, eight blocks), FP64 against the oracle."""
+    dt, oe = 1e-5, 5
+    dn = 1.0 / (nf - 1)
+    shape = swim.sperm_shape(nf, nh, nsw, EPS, HR, dn)
+    rows = inputs.sperm_rows(1, alpha=0.9, KC=5.0)
+    sw = inputs.sperm_swimmers(1, nsw, 0.4, phases=np.linspace(0, 1, nsw))
+    n_obs = steps // oe
+    head = torch.empty((nsw, n_obs + 1, 2), dtype=torch.float64, device="cuda")
+    tail = torch.empty_like(head)
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    swim.swim_sperm_forward(ctx, swim.SWIM_F64, shape, torch.from_numpy(rows).cuda(), torch.from_numpy(sw).cuda(),
+                            steps, dt, oe, head, tail, st)
+    torch.cuda.synchronize()
+    ref = oracle_core.sperm_forward(rows[0], sw, nf, nh, EPS, HR, dn, steps, dt, oe)
+    assert st.item() == 0 and ref["status"] == 0
+    path = oracle_velocity_path_shape(oracle_core, rows[0], sw, nf, nh, dn, steps, dt)
+    for k, g in (("head", head), ("tail", tail)):
+        err = float(np.max(np.abs(g.cpu().numpy() - ref[k])))
+        print(k, {"err": err, "allow": 4e-12 * path})
+        assert err <= 4e-12 * path
+
+
+def oracle_velocity_path_shape(core, row, sw, nf, nh, dn, steps, dt):
+    """sum_k dt |u_k|_2 along the oracle's run for a given shape."""
+    xs, ys = zip(*[core.sperm_initial(nf, nh, HR, dn, s[0], s[1]) for s in sw])
+    x, y = np.concatenate(xs), np.concatenate(ys)
+    np_ = nf + nh
+    total = 0.0
+    for k in range(steps):
+        F = [core.sperm_forces(nf, nh, HR, dn, row, s[2], k * dt, x[m * np_:(m + 1) * np_], y[m * np_:(m + 1) * np_])
+             for m, s in enumerate(sw)]
+        ux, uy = core.velocity(x, y, np.concatenate([f[0] for f in F]), np.concatenate([f[1] for f in F]), row[0],
+                               EPS)
+        total += dt * np.sqrt(np.sum(ux * ux + uy * uy))
+        x, y = x + dt * ux, y + dt * uy
+    return total
+
+
+def test_empty_batch_is_a_no_op(ctx):
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    st = torch.empty(0, dtype=torch.int32, device="cuda")
+    swim.swim_sperm_forward(ctx, swim.SWIM_F64, swim.sperm_shape(), e, e, 10, 1e-5, 5, e, e, st)
+    torch.cuda.synchronize()
