@@ -19,7 +19,8 @@ _I32 = ctypes.POINTER(ctypes.c_int32)
 
 class paper_blob:
     """Context manager: the oracle's kernel functions use the paper's blob
-    3 eps^3 / (2 pi R^5) (eq. eqnblob; Stokes limit only) inside it."""
+    3 eps^3 / (2 pi R^5) (eq. eqnblob) inside it: closed forms in the Stokes
+    limit, quadrature for alpha > 0."""
 
     def __enter__(self):
         lib().oracle_set_blob(1)

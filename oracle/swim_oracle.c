@@ -105,6 +105,212 @@ static ld q_of(ld z)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Modified Bessel functions of the first kind, orders 0 and 1, scaled:     */
+/*   exp(-z) I_n(z) = (1/pi) int_0^pi exp(z (cos th - 1)) cos(n th) dth     */
+/* (A&S 9.6.19).  The integrand is even, 2 pi-periodic and entire, so the   */
+/* trapezoid rule on [0, pi] with half weights at both ends converges       */
+/* geometrically (64 nodes: aliasing error ~ I_128(z) e^-z); for large z it */
+/* is a Gaussian of width 1/sqrt(z) at th = 0, and the step is capped at    */
+/* 0.6/sqrt(z) as for K above.                                              */
+/* ------------------------------------------------------------------------ */
+static void bessel_i01_scaled(ld z, ld *i0e, ld *i1e)
+{
+    int n = 64;
+    if (z > 9.0L) {
+        int m = (int)(PI_L * sqrtl(z) / 0.6L) + 1;
+        if (m > n) n = m;
+    }
+    ld h = PI_L / (ld)n;
+    ld em = expl(-2.0L * z);
+    ld s0 = 0.5L * (1.0L + em), s1 = 0.5L * (1.0L - em);
+    for (int k = 1; k < n; ++k) {
+        ld c = cosl(h * (ld)k);
+        ld e = expl(z * (c - 1.0L));
+        s0 += e;
+        s1 += e * c;
+    }
+    *i0e = s0 / (ld)n;
+    *i1e = s1 / (ld)n;
+}
+
+/* 20-point Gauss-Legendre rule on [-1, 1]: nodes by Newton's method on    */
+/* P_20 from the standard initial guesses, weights 2/((1 - x^2) P_20'^2).   */
+#define NGL 20
+static ld gl_x[NGL], gl_w[NGL];
+static volatile int gl_ready = 0;
+static void gl_init(void)
+{
+    if (gl_ready) return;
+    ld xs[NGL], ws[NGL];
+    for (int i = 0; i < NGL; ++i) {
+        ld x = cosl(PI_L * ((ld)i + 0.75L) / ((ld)NGL + 0.5L)), dp = 1.0L;
+        for (int it = 0; it < 100; ++it) {
+            ld p0 = 1.0L, p1 = x;
+            for (int k = 2; k <= NGL; ++k) {
+                ld p2 = ((ld)(2 * k - 1) * x * p1 - (ld)(k - 1) * p0) / (ld)k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = (ld)NGL * (x * p1 - p0) / (x * x - 1.0L);
+            ld dx = p1 / dp;
+            x -= dx;
+            if (fabsl(dx) < 1e-24L) break;
+        }
+        ld p0 = 1.0L, p1 = x;
+        for (int k = 2; k <= NGL; ++k) {
+            ld p2 = ((ld)(2 * k - 1) * x * p1 - (ld)(k - 1) * p0) / (ld)k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = (ld)NGL * (x * p1 - p0) / (x * x - 1.0L);
+        xs[i] = x;
+        ws[i] = 2.0L / ((1.0L - x * x) * dp * dp);
+    }
+    for (int i = 0; i < NGL; ++i) {
+        gl_x[i] = xs[i];
+        gl_w[i] = ws[i];
+    }
+    gl_ready = 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The paper's blob (eq. eqnblob) for alpha > 0, where its Brinkmanlet has */
+/* no closed form.  g solves (Delta - alpha^2) g = phi, i.e. g is the       */
+/* convolution of phi with the free-space Green function -K0(alpha r)/2pi;  */
+/* averaging K0(alpha |x - y|) over the angle of y (Graf's addition theorem)*/
+/* leaves I0(alpha s<) K0(alpha s>), so with z = alpha r                    */
+/*   g(r) = -[K0(z) A(r) + I0(z) B(r)],                                     */
+/*   A = int_0^r phi(s) I0(alpha s) s ds,  B = int_r^inf phi(s) K0(alpha s) s ds. */
+/* Differentiating, r g' = z [K1(z) A - I1(z) B]; integrating the equation  */
+/* over the disc of radius r, r g' - alpha^2 M = m/(2 pi) with M = int_0^r  */
+/* s g ds and the blob mass m = 1 - eps^3/R^3, so                           */
+/*   M = (z K1 A - z I1 B - m/(2 pi)) / alpha^2.                            */
+/* For z <= 2 the same M is taken in the form                               */
+/*   M = Cq + r^2 [q(z)/z^2] A - r^2 [I1(z)/z] B,                           */
+/*   Cq = int_0^r phi(s) s (I0(alpha s) - 1)/alpha^2 ds,                    */
+/* (m/(2 pi) = A - alpha^2 Cq), in which no two large terms cancel.         */
+/* Quadrature: s = eps sinh(u) turns phi(s) s ds into (3/2pi) sinh u/cosh^4 u du, */
+/* analytic within pi/2 of the real axis; 20-point Gauss-Legendre panels of */
+/* width <= 1/2 in u, and, near s = r where exp(-alpha |s - r|) varies, of  */
+/* width <= 1 + x/4 in x = alpha |s - r|.  A and B are carried scaled,      */
+/* As = e^-z A and Bs = e^z B, so that no exponential overflows; panels     */
+/* stop once the integrand is below e^-50 of its size at s = r.             */
+/* Near contact (delta = r^2/eps^2 < 1/4) the kernel uses the series of g   */
+/* in delta: inserting g = sum gam_n delta^n and phi = sum phi_n delta^n,   */
+/* phi_n = 3/(2 pi eps^2) C(-5/2, n), into the equation gives               */
+/*   gam_{n+1} = eps^2 (phi_n + alpha^2 gam_n) / (4 (n+1)^2),               */
+/* so only gam_0 = g(0) = -int_0^inf phi(s) K0(alpha s) s ds is integrated  */
+/* (on panels refined geometrically towards the log singularity at s = 0). */
+/* ------------------------------------------------------------------------ */
+static ld pb_w(ld u)
+{
+    ld c = coshl(u);
+    return 3.0L * sinhl(u) / (2.0L * PI_L * c * c * c * c);
+}
+
+/* (I0(x) - 1) / alpha^2 at x = alpha s, from the ascending series (x <= 2) */
+static ld pb_i0m1(ld alpha, ld s)
+{
+    ld y = 0.25L * alpha * alpha * s * s, term = 1.0L, acc = 0.0L;
+    for (int k = 0; k < 60; ++k) {
+        acc += term;
+        term *= y / ((ld)(k + 2) * (ld)(k + 2));
+        if (term < 1e-30L * acc) break;
+    }
+    return 0.25L * s * s * acc;
+}
+
+static ld pb_b_tail(ld alpha, ld eps, ld r, ld u0);
+
+/* As, Bs and (z <= 2) Cq at radius r */
+static void pb_parts(ld alpha, ld eps, ld r, ld *As, ld *Bs, ld *Cq)
+{
+    ld z = alpha * r, ur = asinhl(r / eps);
+    int want_c = z <= 2.0L;
+    ld a = 0.0L, c = 0.0L, b = 0.0L;
+    ld uh = ur;
+    while (uh > 0.0L) {
+        ld x = alpha * (r - eps * sinhl(uh));
+        if (x - 3.0L * (ur - uh) > 50.0L) break;
+        ld sl = eps * sinhl(uh) - (1.0L + 0.25L * x) / alpha;
+        ld ul = sl > 0.0L ? asinhl(sl / eps) : 0.0L;
+        if (ul < uh - 0.5L) ul = uh - 0.5L;
+        if (ul < 0.0L) ul = 0.0L;
+        ld hm = 0.5L * (uh - ul), ct = 0.5L * (uh + ul);
+        for (int i = 0; i < NGL; ++i) {
+            ld u = ct + hm * gl_x[i], s = eps * sinhl(u), wq = hm * gl_w[i] * pb_w(u);
+            ld i0e, i1e;
+            bessel_i01_scaled(alpha * s, &i0e, &i1e);
+            a += wq * i0e * expl(alpha * s - z);
+            if (want_c) c += wq * pb_i0m1(alpha, s);
+        }
+        uh = ul;
+    }
+    b = pb_b_tail(alpha, eps, r, ur);
+    *As = a;
+    *Bs = b;
+    *Cq = c;
+}
+
+/* int over [ul, uh] of (3/2pi) sinh u/cosh^4 u K0(alpha s) exp(z) du */
+static ld pb_b_panel(ld alpha, ld eps, ld z, ld ul, ld uh)
+{
+    ld hm = 0.5L * (uh - ul), ct = 0.5L * (uh + ul), b = 0.0L;
+    for (int i = 0; i < NGL; ++i) {
+        ld u = ct + hm * gl_x[i], s = eps * sinhl(u), k0e, k1e;
+        bessel_k01_scaled(alpha * s, &k0e, &k1e);
+        b += hm * gl_w[i] * pb_w(u) * k0e * expl(z - alpha * s);
+    }
+    return b;
+}
+
+/* Bs = e^z int_{u0}^inf ..., panels from u0 upwards */
+static ld pb_b_tail(ld alpha, ld eps, ld r, ld u0)
+{
+    ld z = alpha * r, ul = u0, b = 0.0L;
+    for (;;) {
+        ld x = alpha * (eps * sinhl(ul) - r);
+        if (x + 3.0L * (ul - u0) > 50.0L) break;
+        ld uh = asinhl((eps * sinhl(ul) + (1.0L + 0.25L * x) / alpha) / eps);
+        if (uh > ul + 0.5L) uh = ul + 0.5L;
+        b += pb_b_panel(alpha, eps, z, ul, uh);
+        ul = uh;
+    }
+    return b;
+}
+
+/* g(0) = -int_0^inf phi K0(alpha s) s ds: panels [2^-(j+2), 2^-(j+1)],
+ * j = 0..63, towards the logarithm of K0 at s = 0, then from u = 1/2 on */
+static ld pb_g0(ld alpha, ld eps)
+{
+    ld b = 0.0L;
+    for (int j = 63; j >= 0; --j) b += pb_b_panel(alpha, eps, 0.0L, ldexpl(1.0L, -(j + 2)), ldexpl(1.0L, -(j + 1)));
+    return -(b + pb_b_tail(alpha, eps, 0.0L, 0.5L));
+}
+
+/* g(r) and M(r) of the paper's blob at alpha > 0 */
+static void pb_gM(ld alpha, ld eps, ld t, ld *g, ld *M)
+{
+    ld r = sqrtl(t), z = alpha * r;
+    ld As, Bs, Cq;
+    pb_parts(alpha, eps, r, &As, &Bs, &Cq);
+    ld k0e, k1e, i0e, i1e;
+    bessel_k01_scaled(z, &k0e, &k1e);
+    bessel_i01_scaled(z, &i0e, &i1e);
+    *g = -(k0e * As + i0e * Bs);
+    if (z <= 2.0L) {
+        ld ez = expl(z);
+        ld qz2 = q_of(z) / (z * z);
+        ld i1z = i1e * ez / z;
+        *M = Cq + t * qz2 * As * ez - t * i1z * Bs / ez;
+    } else {
+        ld R = sqrtl(t + eps * eps);
+        ld m = 1.0L - eps * eps * eps / (R * R * R);
+        *M = (z * (k1e * As - i1e * Bs) - m / (2.0L * PI_L)) / (alpha * alpha);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Kernel of eq. (BrV): v = sum_j [ H1(r) F_j + H2(r) (F_j . x) x ],       */
 /* H1 = -B'',  H2 = (r B'' - B')/r^3,  x = x_i - X_j, r = |x|.              */
 /*                                                                          */
@@ -135,7 +341,7 @@ static ld q_of(ld z)
 typedef struct {
     ld alpha, eps, e2;
     int stokes;
-    int paper; /* the paper's blob (eq. eqnblob), Stokes limit only */
+    int paper; /* the paper's blob (eq. eqnblob): 1 Stokes limit, 2 alpha > 0 */
     ld c, q0;
     ld gam[NGAM];
 } okern;
@@ -149,7 +355,8 @@ typedef struct {
  * the same route as the other blob: M = int_0^r s G ds =
  * [(r^2/2) ln(R + eps) - (R + 3 eps)(R - eps)/4] / (2 pi), H1 = M/r^2 - G,
  * H2 = (G - 2M/r^2)/r^2; near contact the series of G in delta with the
- * same formulas.  Only alpha = 0 (no closed form exists for alpha > 0). */
+ * same formulas.  For alpha > 0 (no closed form) g and M come from the
+ * quadrature of pb_gM and the series from gam_0 = g(0) (see above). */
 static int g_blob = 0;
 void oracle_set_blob(int b) { g_blob = b; }
 
@@ -160,6 +367,18 @@ static void kernel_init(okern *k, double alpha, double eps)
     k->eps = eps;
     k->e2 = (ld)eps * (ld)eps;
     k->stokes = (alpha == 0.0);
+    if (g_blob == 1 && alpha > 0.0) {
+        gl_init();
+        k->paper = 2;
+        k->c = 1.0L;
+        ld phin = 3.0L / (2.0L * PI_L * k->e2); /* phi_0; phi_n = phi_0 C(-5/2, n) */
+        k->gam[0] = pb_g0((ld)alpha, (ld)eps);
+        for (int n = 0; n + 1 < NGAM; ++n) {
+            k->gam[n + 1] = k->e2 * (phin + (ld)alpha * (ld)alpha * k->gam[n]) / (4.0L * (ld)(n + 1) * (ld)(n + 1));
+            phin *= (-2.5L - (ld)n) / (ld)(n + 1);
+        }
+        return;
+    }
     if (g_blob == 1) {
         /* Taylor coefficients of G in delta: with a = sqrt(1 + delta) and
          * u = (a - 1)/2, ln(1 + a) = ln 2 + ln(1 + u), whose coefficients L_n
@@ -222,6 +441,13 @@ static void kernel_eval(const okern *k, double t_d, ld *H1, ld *H2)
         }
         *H1 = h1;
         *H2 = h2 / k->e2;
+        return;
+    }
+    if (k->paper == 2) {
+        ld g, M;
+        pb_gM((ld)k->alpha, (ld)k->eps, t, &g, &M);
+        *H1 = M / t - g;
+        *H2 = (g - 2.0L * M / t) / t;
         return;
     }
     if (k->paper) {

@@ -1,5 +1,5 @@
 """Pins of the oracle's kernel for the paper's own blob, phi = 3 eps^3 /
-(2 pi (r^2 + eps^2)^(5/2)) (eq. eqnblob), in the Stokes limit:
+(2 pi (r^2 + eps^2)^(5/2)) (eq. eqnblob).  In the Stokes limit:
 
 * H2 equals the published regularized Stokeslet of this blob (Cortez,
   Fauci & Medovikov 2005, 2D), H1 equals it up to the constant -1/(8 pi)
@@ -9,10 +9,25 @@
 * velocity and pressure of a few forces satisfy the regularized Stokes
   equations Delta v = grad p - sum F phi(x - X_i), div v = 0, at field
   points (fourth-order differences).
+
+For alpha > 0 (no closed form; the oracle integrates):
+
+* g = -2 H1 - t H2, the solution of (Delta - alpha^2) g = phi, equals its
+  Fourier-Hankel integral -(1/2pi) int (1 + eps k) e^(-eps k) J0(k r) k dk /
+  (k^2 + alpha^2) (the blob's transform is (1 + eps k) e^(-eps k)), a route
+  that shares nothing with the oracle's real-space quadrature;
+* M = -t (H1 + t H2) is the integral of s g(s) from 0 to r;
+* velocity and pressure satisfy the regularized Brinkman equations;
+* alpha -> 0 recovers the closed forms above, and far from the blob the
+  kernel is that of a point force, g = -K0(alpha r)/(2 pi),
+  M = (alpha r K1(alpha r) - 1)/(2 pi alpha^2).
 """
+import warnings
+
 import numpy as np
 import pytest
 from scipy import integrate
+from scipy import special
 
 from oracle import core
 
@@ -54,3 +69,82 @@ def test_field_solves_the_regularized_stokes_equations(seed):
         rx, ry, div = tof.fd_check(0.0, seed)
     assert abs(rx) < 1e-5 and abs(ry) < 1e-5, (rx, ry)
     assert abs(div) < 1e-5
+
+
+def _g_fourier_hankel(r, alpha, eps):
+    f = lambda k: (1 + eps * k) * np.exp(-eps * k) * special.j0(k * r) * k / (k * k + alpha * alpha)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", integrate.IntegrationWarning)
+        v, _ = integrate.quad(f, 0, 80 / eps, limit=4000, epsabs=0, epsrel=1e-13)
+    return -v / (2 * np.pi)
+
+
+@pytest.mark.parametrize("alpha", [1e-3, 0.5, 5.0, 30.0])
+def test_brinkman_g_matches_its_fourier_hankel_integral(alpha):
+    eps = 0.03
+    # contact, the near-contact series, both sides of its switch at r = eps/2
+    r = np.array([0.0, 1e-4, 0.49 * eps, 0.51 * eps, eps, 3 * eps, 0.1, 0.5])
+    t = r * r
+    with core.paper_blob():
+        H1, H2 = core.kernel(alpha, eps, t)
+    g = -2 * H1 - t * H2
+    for ri, gi in zip(r, g):
+        gf = _g_fourier_hankel(ri, alpha, eps)
+        assert abs(gi - gf) <= 2e-14 * abs(gf), (alpha, ri, gi, gf)
+
+
+@pytest.mark.parametrize("alpha", [0.5, 8.0])
+def test_brinkman_M_is_the_integral_of_s_g(alpha):
+    eps = 0.03
+    with core.paper_blob():
+        def g(s):
+            H1, H2 = core.kernel(alpha, eps, np.array([s * s]))
+            return -2 * H1[0] - s * s * H2[0]
+        for r in (0.4 * eps, 2 * eps, 0.2, 1.0):
+            H1, H2 = core.kernel(alpha, eps, np.array([r * r]))
+            M = -r * r * (H1[0] + r * r * H2[0])
+            q, _ = integrate.quad(lambda s: s * g(s), 0, r, epsabs=0, epsrel=1e-13, limit=200,
+                                  points=[x for x in (0.5 * eps, eps, 4 * eps) if x < r])
+            assert abs(M - q) <= 1e-12 * abs(q), (alpha, r, M, q)
+
+
+@pytest.mark.parametrize("alpha,seed", [(0.7, 2), (6.0, 3)])
+def test_brinkman_field_solves_the_regularized_brinkman_equations(alpha, seed):
+    with core.paper_blob():
+        rx, ry, div = tof.fd_check(alpha, seed)
+    assert abs(rx) < 1e-5 and abs(ry) < 1e-5, (rx, ry)
+    assert abs(div) < 1e-5
+
+
+def test_brinkman_tends_to_the_stokes_limit():
+    eps, alpha = 0.03, 1e-5
+    t = np.concatenate([[1e-8], np.geomspace(1e-5, 1.0, 12)])
+    with core.paper_blob():
+        H1, H2 = core.kernel(alpha, eps, t)
+        H10, _ = core.kernel(alpha, eps, np.array([0.0]))
+        S1, S2 = core.kernel(0.0, eps, t)
+        S10, _ = core.kernel(0.0, eps, np.array([0.0]))
+    # the difference is O(alpha^2 r^2 log(alpha r)) relative
+    np.testing.assert_allclose(H2, S2, rtol=1e-8, atol=0)
+    np.testing.assert_allclose(H1 - H10[0], S1 - S10[0], rtol=1e-8, atol=1e-14)
+
+
+@pytest.mark.parametrize("alpha", [0.3, 4.0])
+def test_brinkman_far_field_is_that_of_a_point_force(alpha):
+    r = np.array([0.5, 1.0, 2.0])
+    t = r * r
+    z = alpha * r
+    g = -special.k0(z) / (2 * np.pi)
+    M = (z * special.k1(z) - 1) / (2 * np.pi * alpha ** 2)
+    P1, P2 = M / t - g, (g - 2 * M / t) / t
+    dev = []
+    for eps in (0.01, 0.005):
+        with core.paper_blob():
+            H1, H2 = core.kernel(alpha, eps, t)
+        d1, d2 = (H1 - P1) / P1, (H2 - P2) / P2
+        # the blob's second moment (2 eps^2) perturbs the point force at O((eps/r)^2)
+        assert np.all(np.abs(d1) <= 8 * (eps / r) ** 2) and np.all(np.abs(d2) <= 8 * (eps / r) ** 2)
+        dev.append((d1, d2))
+    for k in range(2):
+        ratio = dev[0][k] / dev[1][k]
+        assert np.all((ratio > 3.8) & (ratio < 4.25)), ratio
