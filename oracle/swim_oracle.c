@@ -111,10 +111,27 @@ static ld q_of(ld z)
 /* trapezoid rule on [0, pi] with half weights at both ends converges       */
 /* geometrically (64 nodes: aliasing error ~ I_128(z) e^-z); for large z it */
 /* is a Gaussian of width 1/sqrt(z) at th = 0, and the step is capped at    */
-/* 0.6/sqrt(z) as for K above.                                              */
+/* 0.6/sqrt(z) as for K above.  For z <= 9 the ascending series            */
+/*   I0 = sum_k y^k/(k!)^2,  I1 = (z/2) sum_k y^k/(k! (k+1)!),  y = z^2/4    */
+/* (A&S 9.6.10) is used instead: in the integral for I1 the cos(th) factor  */
+/* cancels to O(z), which would cost relative digits at small z.           */
 /* ------------------------------------------------------------------------ */
 static void bessel_i01_scaled(ld z, ld *i0e, ld *i1e)
 {
+    if (z <= 9.0L) {
+        ld y = 0.25L * z * z, a = 1.0L, b = 1.0L, s0 = 0.0L, s1 = 0.0L;
+        for (int k = 0; k < 100; ++k) {
+            s0 += a;
+            s1 += b;
+            a *= y / ((ld)(k + 1) * (ld)(k + 1));
+            b *= y / ((ld)(k + 1) * (ld)(k + 2));
+            if (a < 1e-24L * s0) break;
+        }
+        ld e = expl(-z);
+        *i0e = s0 * e;
+        *i1e = 0.5L * z * s1 * e;
+        return;
+    }
     int n = 64;
     if (z > 9.0L) {
         int m = (int)(PI_L * sqrtl(z) / 0.6L) + 1;
