@@ -99,15 +99,23 @@ int swim_version(void);
  *                    c eps^2/(2 pi) [alpha^2 K0(alpha R)/R^2 + 2 alpha
  *                    K1(alpha R)/R^3] (eps^2/(pi R^4) at alpha = 0), whose
  *                    Brinkmanlet has a closed form for every alpha; or
- *                    SWIM_BLOB_PAPER, the blob of eq. (eqnblob), whose kernel
- *                    has a closed form only in the Stokes limit:
+ *                    SWIM_BLOB_PAPER, the blob of eq. (eqnblob).  Its
+ *                    kernel has a closed form in the Stokes limit,
  *                    H2 = (R + 2 eps)/(4 pi R (R + eps)^2) and
  *                    H1 = -[ln(R + eps) - eps (R + 2 eps)/(R (R + eps))]/(4 pi)
- *                    - 1/(8 pi).  With SWIM_BLOB_PAPER, systems with
- *                    alpha > 0 are SWIM_EINVAL (swim_pair_velocity,
- *                    swim_flow_field) or get SWIM_ST_BADPARAM (batched runs).
- *                    It applies to every velocity and pressure evaluation,
- *                    including the pressure's blob mass (1 - eps^3/R^3).
+ *                    - 1/(8 pi).  For alpha > 0 there is none: g, the
+ *                    solution of (Delta - alpha^2) g = phi, comes from two
+ *                    radial integrals of the blob against I0 and K0 (Graf's
+ *                    addition theorem), taken by FP64 Gauss-Legendre
+ *                    quadrature, with H1 = M/r^2 - g, H2 = (g - 2M/r^2)/r^2,
+ *                    M = int_0^r s g ds.  FP32 runs read it from the
+ *                    per-system tables (built once per launch from the
+ *                    quadrature, about 3e3 kernel values per system); FP64
+ *                    evaluates the quadrature per pair, about 1e4 times
+ *                    the cost of the closed forms (a reference mode for
+ *                    small systems).  It applies to every velocity and
+ *                    pressure evaluation, including the pressure's blob
+ *                    mass (1 - eps^3/R^3).
  * Read-only counters (swim_get_option): SWIM_OPT_GRAPH_LAUNCHES (graph
  * replays and first launches so far), SWIM_OPT_GRAPH_CAPTURES.
  * Results do not depend on the launch options beyond rounding of the
@@ -119,7 +127,7 @@ int swim_version(void);
 #define SWIM_OPT_GRAPH_CAPTURES 5
 #define SWIM_OPT_BLOB 6
 #define SWIM_BLOB_READING 0 /* default: the unit-mass blob whose Brinkmanlet has a closed form for all alpha */
-#define SWIM_BLOB_PAPER 1   /* eq. (eqnblob): 3 eps^3 / (2 pi (r^2 + eps^2)^(5/2)); alpha = 0 only */
+#define SWIM_BLOB_PAPER 1   /* eq. (eqnblob): 3 eps^3 / (2 pi (r^2 + eps^2)^(5/2)) */
 int swim_set_option(swim_ctx *ctx, int32_t key, int32_t value);
 int swim_get_option(swim_ctx *ctx, int32_t key, int32_t *value);
 
@@ -165,11 +173,13 @@ int swim_pair_velocity(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const int64_
  *   p(x) = sum_j F_j . grad G_eps(d),  grad G_eps(d) = d m(r) / (2 pi r^2)
  * G_eps solves Delta G_eps = phi, the blob of the velocity kernel, and m(r)
  * is the blob mass inside r: m = r^2/R^2 for alpha = 0 and
- * m = 1 - eps K1(alpha R) / (R K1(alpha eps)) otherwise, R^2 = r^2 + eps^2.
+ * m = 1 - eps K1(alpha R) / (R K1(alpha eps)) otherwise, R^2 = r^2 + eps^2
+ * (with SWIM_BLOB_PAPER: m = 1 - eps^3/R^3 for every alpha).
  * x, y, fx, fy device dtype[n]; tx, ty device dtype[nt]; u, v, p device
  * dtype[nt] (written).  alpha >= 0, eps > 0, alpha*eps <= 1.  Sums are
  * accumulated in FP64.  The pair kernel is evaluated in dtype directly
- * (no table); the pressure weight is evaluated in FP64.  Asynchronous. */
+ * (no table; the paper's blob at alpha > 0 in FP64 for both dtypes); the
+ * pressure weight is evaluated in FP64.  Asynchronous. */
 int swim_flow_field(swim_ctx *ctx, int32_t dtype, int64_t n, const void *x, const void *y, const void *fx,
                     const void *fy, double alpha, double eps, int64_t nt, const void *tx, const void *ty,
                     void *u, void *v, void *p, void *stream);
@@ -615,8 +625,9 @@ int abc_prescreened(swim_ctx *ctx, const abc_model *model, int32_t N, const floa
  * follows the FP32 device path: cubic pieces of a per-system table in
  * v = 1 + sigma t (sigma the power of four with sigma eps^2 in [1, 4);
  * 16 pieces per octave, v < 2^44), built from the FP64 evaluation; direct
- * FP32 evaluation beyond. */
-int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, const double *t,
+ * FP32 evaluation beyond.  blob: SWIM_BLOB_READING or SWIM_BLOB_PAPER (as
+ * SWIM_OPT_BLOB); SWIM_EINVAL otherwise. */
+int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int32_t blob, int64_t n, const double *t,
                           double *h1t, double *h2, double *h1c);
 
 #ifdef __cplusplus

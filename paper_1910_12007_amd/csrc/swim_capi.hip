@@ -98,7 +98,7 @@ struct swim_ctx {
     int opt_wps = 0;      // waves per system in the persistent kernel (0: automatic)
     int opt_big_tpl = 0;  // targets per lane of the large-system kernel (0: automatic)
     int opt_graph = 1;    // 0: eager launches; 1: capture on a repeated layout; 2: capture always
-    int opt_blob = 0;     // 0: the kernel reading's blob; 1: the paper's blob (alpha = 0 only)
+    int opt_blob = 0;     // 0: the kernel reading's blob; 1: the paper's blob
     int tuned_wps[2][9] = {};  // autotuned waves per system [dtype][tpl] (0: not tuned)
     FwdGraph graphs[N_GRAPHS];
     uint64_t graph_clock = 0, last_key = 0;
@@ -693,8 +693,6 @@ int swim_pair_velocity(swim_ctx* c, int32_t dtype, int64_t n_sys, const int64_t*
         if (!(std::isfinite(alpha[s]) && alpha[s] >= 0)) return fail(SWIM_EINVAL, "alpha[%lld] must be finite and >= 0", (long long)s);
         if (!(std::isfinite(eps[s]) && eps[s] > 0)) return fail(SWIM_EINVAL, "eps[%lld] must be finite and > 0", (long long)s);
         if (alpha[s] * eps[s] > 1.0) return fail(SWIM_EINVAL, "alpha*eps > 1 for system %lld", (long long)s);
-        if (c->opt_blob == SWIM_BLOB_PAPER && alpha[s] != 0.0)
-            return fail(SWIM_EINVAL, "the paper's blob has a kernel only for alpha = 0 (system %lld)", (long long)s);
     }
     const int64_t npts = sys_off[n_sys];
     if (npts > 0 && (!x || !y || !fx || !fy || !ux || !uy)) return fail(SWIM_EINVAL, "null data pointer");
@@ -743,8 +741,6 @@ int swim_flow_field(swim_ctx* c, int32_t dtype, int64_t n, const void* x, const 
     if (nt == 0) return SWIM_OK;
     if ((n > 0 && (!x || !y || !fx || !fy)) || !tx || !ty || !u || !v || !p)
         return fail(SWIM_EINVAL, "null device pointer");
-    if (c->opt_blob == SWIM_BLOB_PAPER && alpha != 0.0)
-        return fail(SWIM_EINVAL, "the paper's blob has a kernel only for alpha = 0");
     FieldConst fc{};
     sysconst_compute<float>(alpha, eps, &fc.c32, c->opt_blob);
     sysconst_compute<double>(alpha, eps, &fc.c64, c->opt_blob);
@@ -1180,10 +1176,11 @@ int abc_step(swim_ctx* c, const abc_model* m, const double* data, int32_t n_obs,
     return SWIM_OK;
 }
 
-int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, const double* t, double* h1t, double* h2,
-                          double* h1c)
+int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int32_t blob, int64_t n, const double* t,
+                          double* h1t, double* h2, double* h1c)
 {
     TRY(check_dtype(dtype));
+    if (blob != SWIM_BLOB_READING && blob != SWIM_BLOB_PAPER) return fail(SWIM_EINVAL, "blob must be 0 or 1");
     if (!(std::isfinite(alpha) && alpha >= 0 && std::isfinite(eps) && eps > 0 && alpha * eps <= 1.0))
         return fail(SWIM_EINVAL, "alpha/eps outside the domain");
     if (n < 0 || (n > 0 && (!t || !h1t || !h2)) || !h1c) return fail(SWIM_EINVAL, "bad arguments");
@@ -1191,9 +1188,9 @@ int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, co
         // the device's FP32 path: the per-system table, direct evaluation
         // beyond its last octave
         SysConst<float> C;
-        sysconst_compute<float>(alpha, eps, &C);
+        sysconst_compute<float>(alpha, eps, &C, blob);
         SysConst<double> C64;
-        sysconst_compute<double>(alpha, eps, &C64);
+        sysconst_compute<double>(alpha, eps, &C64, blob);
         std::vector<TabE> tab(TAB_N + 1);
         for (int i = 0; i <= TAB_N; ++i) tab_interval(C64, i, tab[i], nullptr);
         for (int64_t i = 0; i < n; ++i) {
@@ -1213,7 +1210,7 @@ int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int64_t n, co
         *h1c = C.h1c;
     } else {
         SysConst<double> C;
-        sysconst_compute<double>(alpha, eps, &C);
+        sysconst_compute<double>(alpha, eps, &C, blob);
         for (int64_t i = 0; i < n; ++i) {
             double a, b;
             kernel_eval<double>(C, t[i], a, b);

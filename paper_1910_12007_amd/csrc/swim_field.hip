@@ -34,6 +34,7 @@ __global__ __launch_bounds__(256) void k_flow_field(int64_t n, const T* x, const
     __shared__ Src4<T> tile[FIELD_TILE];
     const SysConst<T> C = *reinterpret_cast<const SysConst<T>*>(sizeof(T) == 4 ? (const void*)&fc.c32
                                                                                    : (const void*)&fc.c64);
+    const bool pbrink = fc.paper && !fc.stokes;
     const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool live = a < nt;
     const double X = live ? (double)tx[a] : 0.0, Y = live ? (double)ty[a] : 0.0;
@@ -57,7 +58,15 @@ __global__ __launch_bounds__(256) void k_flow_field(int64_t n, const T* x, const
             const double dxd = X - (double)s.x, dyd = Y - (double)s.y;
             const T dx = (T)dxd, dy = (T)dyd;
             T Ht, H2;
-            kernel_eval<T>(C, fma_t(dx, dx, dy * dy), Ht, H2);
+            if (sizeof(T) == 4 && pbrink) {
+                // the paper's blob at alpha > 0 has no FP32 closed form: FP64
+                double a, b;
+                kernel_eval<double>(fc.c64, fma(dxd, dxd, dyd * dyd), a, b);
+                Ht = (T)a;
+                H2 = (T)b;
+            } else {
+                kernel_eval<T>(C, fma_t(dx, dx, dy * dy), Ht, H2);
+            }
             const T fd = fma_t(s.fx, dx, s.fy * dy);
             su += (double)fma_t(Ht, s.fx, H2 * fd * dx);
             sv += (double)fma_t(Ht, s.fy, H2 * fd * dy);

@@ -247,8 +247,7 @@ __global__ void k_sysconst_batch(int64_t n, const int64_t* sw_off, const int32_t
     if (s >= n) return;
     const double alpha = params[9 * sw_off[s]];
     const double eps = eps_over_ds / (double)(npt[s] - 1);
-    // the paper's blob has a kernel only in the Stokes limit
-    bool ok = isfinite(alpha) && alpha >= 0.0 && alpha * eps <= 1.0 && (blob == 0 || alpha == 0.0);
+    bool ok = isfinite(alpha) && alpha >= 0.0 && alpha * eps <= 1.0;
     for (int64_t f = sw_off[s]; f < sw_off[s + 1]; ++f)
         for (int c = 0; c < 9; ++c) ok = ok && isfinite(params[9 * f + c]);
     status[s] = ok ? 0 : SWIM_ST_BADPARAM_;

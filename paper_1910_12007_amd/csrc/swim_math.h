@@ -128,6 +128,13 @@ template <typename T> struct alignas(16) SysConst {
     T ts, its, tr, eps;              // FP32 table scale sigma = rho^2, 1/sigma, rho = 2^m; eps
     T U[NT_MAX];                     // U(t) = t * sum_n U[n] t^n
     T V[NT_MAX];                     // V(t) = sum_n V[n] t^n
+    // FP32 constants of the paper's blob at alpha > 0 (paper = 0 there): the
+    // direct evaluation, used only beyond the table's last octave (r > 2^21
+    // eps), takes the blob of the reading above, whose kernel differs from
+    // the paper blob's there by O(eps^2/r^2) apart from the constant
+    // H1(0); hoff = H1(0) of that blob - H1(0) of the paper's is added to Ht.
+    // 0 for every other system.
+    T hoff;
 };
 
 // FP64 values of K0, K1 and Q at small or large argument (set-up only)
@@ -172,14 +179,203 @@ SWIM_HD double taylor_at(const double* p, int M, int n, double w0)
     return s;
 }
 
+// ---------------------------------------------------------------------------
+// The paper's blob phi = 3 eps^3 / (2 pi R^5) (eq. eqnblob) for alpha > 0,
+// whose regularized Brinkmanlet has no closed form.  g, the solution of
+// (Delta - alpha^2) g = phi that vanishes at infinity, is phi convolved with
+// -K0(alpha r)/(2 pi); the angular average of K0(alpha |x - y|) is
+// I0(alpha s<) K0(alpha s>) (Graf's addition theorem), so with z = alpha r
+//   g(r) = -[K0(z) A(r) + I0(z) B(r)],
+//   A = int_0^r phi I0(alpha s) s ds,   B = int_r^inf phi K0(alpha s) s ds,
+//   r g'(r) = z [K1(z) A - I1(z) B].
+// The equation integrated over the disc of radius r gives
+// r g' - alpha^2 M = m/(2 pi), M = int_0^r s g ds, m = 1 - eps^3/R^3 the blob
+// mass inside r; for z <= 2 M is formed as
+//   M = Cq + r^2 [q(z)/z^2] A - r^2 [I1(z)/z] B,
+//   Cq = int_0^r phi s (I0(alpha s) - 1)/alpha^2 ds,
+// which adds no two nearly equal terms.  The integrals are taken in
+// u = asinh(s/eps), in which phi s ds = (3/2pi) sinh u / cosh^4 u du (poles
+// pi/2 off the real axis), by 10-point Gauss-Legendre panels at most 1/2
+// wide in u, and at most 1 + x/4 wide in x = alpha |s - r|, over which
+// exp(-x) (the ratio of the Bessel factors) varies.  A and B are carried as
+// As = exp(-z) A and Bs = exp(z) B, so nothing overflows; each integral stops
+// where its integrand has fallen below e^-42 of its value at s = r.  Near
+// contact (delta = r^2/eps^2 < 1/4) g is its power series in delta, whose
+// coefficients the equation gives from gam_0 = g(0):
+//   gam_{n+1} = eps^2 (phi_n + alpha^2 gam_n) / (4 (n+1)^2),
+//   phi_n = 3/(2 pi eps^2) C(-5/2, n).
+// All of this runs in FP64 and costs ~1e3 Bessel evaluations per kernel
+// value: it builds the FP32 tables once per system and is the direct FP64
+// evaluation.
+// ---------------------------------------------------------------------------
+constexpr double GL10_X[5] = {0.14887433898163122, 0.4333953941292472, 0.6794095682990244,
+                              0.8650633666889845, 0.9739065285171717};
+constexpr double GL10_W[5] = {0.295524224714753, 0.2692667193099965, 0.219086362515982,
+                              0.14945134915058036, 0.06667134430868807};
+constexpr int PB_NSER = 32;  // near-contact series length (delta < 1/4)
+
+// exp(-z) I0(z), exp(-z) I1(z): ascending series (A&S 9.6.10, positive
+// terms) for z <= 20, the asymptotic series (A&S 9.7.1) above, whose
+// smallest term, ~exp(-2z), is below the FP64 unit roundoff there
+SWIM_HD void bessel_i01e_f64(double z, double* i0e, double* i1e)
+{
+    if (z <= 20.0) {
+        const double y = 0.25 * z * z;
+        double a = 1.0, b = 1.0, s0 = 0.0, s1 = 0.0;  // y^k/(k!)^2, y^k/(k!(k+1)!)
+        for (int k = 0; k < 80; ++k) {
+            s0 += a;
+            s1 += b;
+            a *= y / ((double)(k + 1) * (k + 1));
+            b *= y / ((double)(k + 1) * (k + 2));
+            if (a < 1e-18 * s0) break;
+        }
+        const double e = exp(-z);
+        *i0e = s0 * e;
+        *i1e = 0.5 * z * s1 * e;
+    } else {
+        // I_nu ~ e^z / sqrt(2 pi z) sum_k (-1)^k prod_{j<=k} (4 nu^2 - (2j-1)^2) / (j 8 z)
+        double t0 = 1.0, t1 = 1.0, s0 = 1.0, s1 = 1.0;
+        const double r8 = 1.0 / (8.0 * z);
+        for (int k = 1; k < 60; ++k) {
+            const double o = (double)(2 * k - 1) * (2 * k - 1);
+            t0 *= -(0.0 - o) * r8 / k;
+            t1 *= -(4.0 - o) * r8 / k;
+            s0 += t0;
+            s1 += t1;
+            if (fabs(t0) < 1e-18 * s0 && fabs(t1) < 1e-18 * fabs(s1)) break;
+        }
+        const double c = 1.0 / sqrt(2.0 * PI * z);
+        *i0e = c * s0;
+        *i1e = c * s1;
+    }
+}
+
+// exp(z) K0(z), exp(z) K1(z)
+SWIM_HD void bessel_k01e_f64(double z, double* k0e, double* k1e)
+{
+    if (z <= SWIM_KFIT_ZS) {
+        double K0, K1, Q;
+        bessel_k01_q_f64(z, &K0, &K1, &Q);
+        const double e = exp(z);
+        *k0e = K0 * e;
+        *k1e = K1 * e;
+    } else {
+        const double c = 1.0 / sqrt(z), x = SWIM_KFIT_ZS / z;
+        *k0e = c * kfit<double>(0, x);
+        *k1e = c * kfit<double>(1, x);
+    }
+}
+
+SWIM_HD double pb_density(double u)
+{
+    const double c = cosh(u), c2 = c * c;
+    return (1.5 / PI) * sinh(u) / (c2 * c2);
+}
+
+// exp(alpha r) int_{u0}^inf (3/2pi) sinh u/cosh^4 u K0(alpha eps sinh u) du
+SWIM_HD double pb_outer(double alpha, double eps, double r, double u0)
+{
+    const double z = alpha * r;
+    double b = 0.0, ul = u0;
+    for (int p = 0; p < 400; ++p) {
+        const double sl = eps * sinh(ul), x = alpha * (sl - r);
+        if (x + 3.0 * (ul - u0) > 42.0) break;
+        const double uh = fmin(ul + 0.5, asinh((sl + (1.0 + 0.25 * x) / alpha) / eps));
+        const double hm = 0.5 * (uh - ul), ct = 0.5 * (uh + ul);
+        for (int i = 0; i < 10; ++i) {
+            const double u = i < 5 ? ct - hm * GL10_X[4 - i] : ct + hm * GL10_X[i - 5];
+            const double w = i < 5 ? GL10_W[4 - i] : GL10_W[i - 5];
+            const double s = eps * sinh(u);
+            double k0e, k1e;
+            bessel_k01e_f64(alpha * s, &k0e, &k1e);
+            b += hm * w * pb_density(u) * k0e * exp(z - alpha * s);
+        }
+        ul = uh;
+    }
+    return b;
+}
+
+// g(0) = -int_0^inf phi K0(alpha s) s ds; panels [2^-(j+2), 2^-(j+1)] in u
+// towards the logarithm of K0 at s = 0, then pb_outer from u = 1/2
+SWIM_HD double pb_g0(double alpha, double eps)
+{
+    double b = 0.0;
+    for (int j = 52; j >= 0; --j) {
+        const double ul = ldexp(1.0, -(j + 2)), uh = 2.0 * ul;
+        const double hm = 0.5 * (uh - ul), ct = 0.5 * (uh + ul);
+        for (int i = 0; i < 10; ++i) {
+            const double u = i < 5 ? ct - hm * GL10_X[4 - i] : ct + hm * GL10_X[i - 5];
+            const double w = i < 5 ? GL10_W[4 - i] : GL10_W[i - 5];
+            const double s = eps * sinh(u);
+            double k0e, k1e;
+            bessel_k01e_f64(alpha * s, &k0e, &k1e);
+            b += hm * w * pb_density(u) * k0e * exp(-alpha * s);
+        }
+    }
+    return -(b + pb_outer(alpha, eps, 0.0, 0.5));
+}
+
+// g(r) and M(r) for delta >= 1/4
+SWIM_HD void pb_gM(double alpha, double eps, double t, double* g, double* M)
+{
+    const double r = sqrt(t), z = alpha * r, ur = asinh(r / eps);
+    const bool small = z <= 2.0;
+    double as = 0.0, cq = 0.0, uh = ur;
+    for (int p = 0; p < 400 && uh > 0.0; ++p) {
+        const double sh = eps * sinh(uh), x = alpha * (r - sh);
+        if (x - 3.0 * (ur - uh) > 42.0) break;
+        const double sl = sh - (1.0 + 0.25 * x) / alpha;
+        const double ul = fmax(fmax(uh - 0.5, 0.0), sl > 0.0 ? asinh(sl / eps) : 0.0);
+        const double hm = 0.5 * (uh - ul), ct = 0.5 * (uh + ul);
+        for (int i = 0; i < 10; ++i) {
+            const double u = i < 5 ? ct - hm * GL10_X[4 - i] : ct + hm * GL10_X[i - 5];
+            const double w = hm * (i < 5 ? GL10_W[4 - i] : GL10_W[i - 5]) * pb_density(u);
+            const double s = eps * sinh(u), xs = alpha * s;
+            double i0e, i1e;
+            bessel_i01e_f64(xs, &i0e, &i1e);
+            as += w * i0e * exp(xs - z);
+            if (small) {
+                // (I0(xs) - 1)/alpha^2 = (s^2/4) sum_k (xs^2/4)^k / ((k+1)!)^2
+                const double y = 0.25 * xs * xs;
+                double term = 1.0, acc = 0.0;
+                for (int k = 0; k < 40; ++k) {
+                    acc += term;
+                    term *= y / ((double)(k + 2) * (k + 2));
+                    if (term < 1e-18 * acc) break;
+                }
+                cq += w * 0.25 * s * s * acc;
+            }
+        }
+        uh = ul;
+    }
+    const double bs = pb_outer(alpha, eps, r, ur);
+    double k0e, k1e, i0e, i1e;
+    bessel_k01e_f64(z, &k0e, &k1e);
+    bessel_i01e_f64(z, &i0e, &i1e);
+    *g = -(k0e * as + i0e * bs);
+    if (small) {
+        double K0, K1, Q;
+        bessel_k01_q_f64(z, &K0, &K1, &Q);
+        const double ez = exp(z);
+        *M = cq + t * (Q / (z * z)) * as * ez - t * (i1e * ez / z) * bs / ez;
+    } else {
+        const double R = sqrt(t + eps * eps);
+        const double m = 1.0 - eps * eps * eps / (R * R * R);
+        *M = (z * (k1e * as - i1e * bs) - m / (2.0 * PI)) / (alpha * alpha);
+    }
+}
+
 // Computes the constants of one system in FP64 and rounds them to T.
 // Requires alpha >= 0, eps > 0, alpha * eps <= 1 (checked by the caller).
-// blob 1 selects the paper's blob 3 eps^3 / (2 pi R^5) (eq. eqnblob), whose
-// kernel exists in closed form only for alpha = 0 (the caller checks).
-template <typename T> SWIM_HD void sysconst_compute(double alpha, double eps, SysConst<T>* out, int blob = 0)
+// blob 1 selects the paper's blob 3 eps^3 / (2 pi R^5) (eq. eqnblob): closed
+// forms at alpha = 0; for alpha > 0 the FP64 constants select the quadrature
+// (paper = 2, K0z0 = g(0)) and the FP32 ones those of the reading's blob with
+// H1(0) and hoff of the paper's (its FP32 values come from the tables).
+template <typename T> SWIM_HD void sysconst_base(double alpha, double eps, SysConst<T>* out, int blob)
 {
     const double a2 = alpha * alpha, e2 = eps * eps, w0 = a2 * e2;
     SysConst<T> C;
+    C.hoff = (T)0;
     C.a2 = (T)a2;
     C.e2 = (T)e2;
     C.inv_e2 = (T)(1.0 / e2);
@@ -249,6 +445,40 @@ template <typename T> SWIM_HD void sysconst_compute(double alpha, double eps, Sy
         a2m *= a2;
     }
     *out = C;
+}
+
+template <typename T> SWIM_HD void sysconst_compute(double alpha, double eps, SysConst<T>* out, int blob = 0)
+{
+    const double a2 = alpha * alpha, e2 = eps * eps, w0 = a2 * e2;
+    if (blob == 1 && alpha > 0.0) {
+        const double g0 = pb_g0(alpha, eps);
+        if constexpr (sizeof(T) == 8) {
+            SysConst<T> C{};
+            C.a2 = a2;
+            C.e2 = e2;
+            C.inv_e2 = 1.0 / e2;
+            C.half_inv_e2 = 0.5 / e2;
+            C.w0 = w0;
+            C.inv_a2 = 1.0 / a2;
+            C.K0z0 = g0;
+            C.h1c = -0.5 * g0;
+            C.paper = 2.0;
+            const int m = tab_scale_exp(eps);
+            C.ts = ldexp(1.0, 2 * m);
+            C.its = ldexp(1.0, -2 * m);
+            C.tr = ldexp(1.0, m);
+            C.eps = eps;
+            *out = C;
+        } else {
+            SysConst<double> R;
+            sysconst_base<double>(alpha, eps, &R, 0);
+            sysconst_base<T>(alpha, eps, out, 0);
+            out->h1c = (T)(-0.5 * g0);
+            out->hoff = (T)(R.h1c + 0.5 * g0);
+        }
+        return;
+    }
+    sysconst_base<T>(alpha, eps, out, blob);
 }
 
 // ---------------------------------------------------------------------------
@@ -407,10 +637,45 @@ SWIM_HD void kernel_paper_stokes(const SysConst<T>& C, T t, T& Ht, T& H2)
     Ht = (T)(0.5 / PI) * ((T)-0.5 * log1p_t(t / ((T)2 * e * Re)) - (T)0.25 * ((T)3 * R + (T)4 * e) * t * q);
 }
 
+// The paper's blob at alpha > 0 (FP64 constants with paper = 2): near
+// contact the series of g, Ht = -sum_{n>=1} gam_n delta^n (2n+1)/(2(n+1)),
+// H2 = (1/eps^2) sum_{n>=1} gam_n delta^(n-1) n/(n+1); beyond it
+// H1 = M/r^2 - g, H2 = (g - 2M/r^2)/r^2 from the quadrature.  Not inlined:
+// it is large and only systems of this blob call it.
+__host__ __device__ __attribute__((noinline)) inline void kernel_paper_brinkman(const SysConst<double>& C, double t,
+                                                                              double& Ht, double& H2)
+{
+    const double delta = t * C.inv_e2;
+    if (delta < 0.25) {
+        double gam = C.K0z0, phin = 1.5 / PI * C.inv_e2, p = 1.0, ht = 0.0, h2 = 0.0;
+        for (int n = 0; n + 1 < PB_NSER; ++n) {
+            gam = C.e2 * (phin + C.a2 * gam) / (4.0 * (n + 1) * (n + 1));  // gam_{n+1}
+            phin *= (-2.5 - n) / (n + 1);
+            h2 += gam * p * (n + 1) / (n + 2);
+            p *= delta;
+            ht -= gam * p * (2 * n + 3) / (2.0 * (n + 2));
+        }
+        Ht = ht;
+        H2 = h2 * C.inv_e2;
+        return;
+    }
+    double g, M;
+    pb_gM(sqrt(C.a2), C.eps, t, &g, &M);
+    const double Mt = M / t;
+    H2 = (g - 2.0 * Mt) / t;
+    Ht = Mt - g - C.h1c;
+}
+
 template <typename T>
 SWIM_HD void kernel_eval(const SysConst<T>& C, T t, T& Ht, T& H2)
 {
     if (C.paper != (T)0) {
+        if constexpr (sizeof(T) == 8) {
+            if (C.paper != 1.0) {
+                kernel_paper_brinkman(C, t, Ht, H2);
+                return;
+            }
+        }
         kernel_paper_stokes<T>(C, t, Ht, H2);
         return;
     }
@@ -419,6 +684,7 @@ SWIM_HD void kernel_eval(const SysConst<T>& C, T t, T& Ht, T& H2)
         kernel_small_z<T>(C, t, w, Ht, H2);
     else
         kernel_large_z<T>(C, t, w, Ht, H2);
+    if constexpr (sizeof(T) == 4) Ht += C.hoff;
 }
 
 // ---------------------------------------------------------------------------

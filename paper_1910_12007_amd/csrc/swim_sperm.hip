@@ -517,7 +517,7 @@ __global__ void k_sperm_setup(int64_t n_sys, int32_t nsw, double eps, const doub
     if (s >= n_sys) return;
     const double* p = sysp + (int64_t)SWIM_SP_NPARAM * s;
     const double alpha = p[SWIM_SP_ALPHA];
-    bool ok = isfinite(alpha) && alpha >= 0.0 && alpha * eps <= 1.0 && (blob == 0 || alpha == 0.0);
+    bool ok = isfinite(alpha) && alpha >= 0.0 && alpha * eps <= 1.0;
     for (int c = 0; c < SWIM_SP_NPARAM; ++c) ok = ok && isfinite(p[c]);
     for (int c = 0; c < 3 * nsw; ++c) ok = ok && isfinite(swp[(int64_t)3 * nsw * s + c]);
     status[s] = ok ? 0 : ST_BADPARAM;

@@ -64,7 +64,8 @@ SIGNATURES = {
     "abc_pmc_weights": (_c.c_int, [_c.c_int64, _DP, _U8P, _DP, _DP, _c.c_int64, _DP]),
     "abc_step": (_c.c_int, [_P, _P, _DP, _c.c_int32, _c.c_int64, _I32P, _c.c_uint64, _c.c_int32, _DP, _DP,
                             _c.c_int64, _c.c_double, _DP, _DP, _U8P, _DP, _DP, _I32P]),
-    "swim_kernel_eval_host": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_double, _c.c_int64, _DP, _DP, _DP, _DP]),
+    "swim_kernel_eval_host": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_double, _c.c_int32, _c.c_int64, _DP, _DP, _DP,
+                                         _DP]),
     "tmcmc_loglik": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _c.c_int32, _P, _P, _P, _P, _P, _P]),
     "tmcmc_run": (_c.c_int, [_P, _P, _P, _DP, _c.c_int32, _c.c_int32, _c.c_int64, _c.c_uint64, _DP, _DP, _DP, _I32P,
                              _DP, _I64P, _I64P, _DP]),
@@ -335,11 +336,11 @@ def tmcmc_run(ctx, model, lo, hi, data, N, n, seed, cv_target=1.0, cov_scale=0.2
                 runs=int(runs[0]), seconds=float(secs[0]))
 
 
-def swim_kernel_eval_host(dtype, alpha, eps, t):
+def swim_kernel_eval_host(dtype, alpha, eps, t, blob=0):
     t_, t_p = _h(t, np.float64, _DP)
     h1t, h2 = np.empty_like(t_), np.empty_like(t_)
     h1c = ctypes.c_double()
-    _check(lib().swim_kernel_eval_host(int(dtype), float(alpha), float(eps), t_.size, t_p,
+    _check(lib().swim_kernel_eval_host(int(dtype), float(alpha), float(eps), int(blob), t_.size, t_p,
                                        h1t.ctypes.data_as(_DP), h2.ctypes.data_as(_DP), ctypes.byref(h1c)))
     return h1t, h2, h1c.value
 

@@ -76,6 +76,40 @@ def test_host_kernel_far_octaves_match_oracle(oracle_core, alpha):
         assert e2.max() < 5e-6, (alpha, N, e2.max())
 
 
+@pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 2e-13), (swim.SWIM_F32, 2e-6)])
+def test_host_paper_blob_kernel_matches_oracle(oracle_core, dtype, tol):
+    """The paper's blob (eq. eqnblob): the closed forms at alpha = 0, and for
+    alpha > 0 the device's FP64 quadrature (and the FP32 tables built from
+    it) against the oracle's own quadrature, from near contact (the series
+    in delta) to the far octaves and beyond the FP32 table (r > 2^21 eps),
+    on the scale of a pair's contribution |Ht| + t |H2|."""
+    for alpha in [0.0, 1e-3, 0.5, 2.0, 10.0, 40.0]:
+        for N in [64, 512]:
+            eps = 1.5 / (N - 1)
+            if alpha * eps > 1:
+                continue
+            t = np.concatenate([[0.0], eps ** 2 * np.logspace(-4, 14, 90)])
+            if dtype == swim.SWIM_F32:
+                t = t.astype(np.float32).astype(np.float64)
+            with oracle_core.paper_blob():
+                H1o, H2o = oracle_core.kernel(alpha, eps, t)
+            h1t, h2, h1c = swim.swim_kernel_eval_host(dtype, alpha, eps, t, blob=swim.SWIM_BLOB_PAPER)
+            assert abs(h1c / H1o[0] - 1) < (1e-14 if dtype == swim.SWIM_F64 else 1e-7)
+            assert h1t[0] == 0.0
+            sc = _scale(H1o[1:], H1o[0], t[1:], H2o[1:])
+            e1 = np.abs(h1t[1:] - (H1o[1:] - H1o[0])) / sc
+            e2 = np.abs(h2[1:] - H2o[1:]) * t[1:] / sc
+            assert e1.max() < tol, (alpha, N, e1.max())
+            assert e2.max() < tol, (alpha, N, e2.max())
+            near = t[1:] < 100 * eps ** 2
+            assert np.all(np.abs(h2[1:][near] / H2o[1:][near] - 1) < 50 * tol), (alpha, N)
+
+
+def test_host_kernel_rejects_unknown_blob():
+    with pytest.raises(swim.SwimError):
+        swim.swim_kernel_eval_host(swim.SWIM_F64, 1.0, 0.02, np.array([1.0]), blob=2)
+
+
 def test_host_kernel_rejects_out_of_domain():
     with pytest.raises(swim.SwimError):
         swim.swim_kernel_eval_host(swim.SWIM_F64, 100.0, 0.02, np.array([1.0]))

@@ -1,9 +1,11 @@
-"""The paper's blob (eq. eqnblob) in the Stokes limit (SWIM_OPT_BLOB =
-SWIM_BLOB_PAPER) against the oracle with the same blob: one velocity
-evaluation, forward runs of the filament and of the full sperm model, and
-the flow and pressure field.  Bars as for the default blob: FP64 1e-12 (per
+"""The paper's blob (eq. eqnblob) (SWIM_OPT_BLOB = SWIM_BLOB_PAPER) against
+the oracle with the same blob: one velocity evaluation, forward runs of the
+filament and of the full sperm model, and the flow and pressure field, in
+the Stokes limit (closed forms) and for alpha > 0 (quadrature; FP32 from
+the tables built from it).  Bars as for the default blob: FP64 1e-12 (per
 evaluation, and on displacement series), FP32 1e-5 per evaluation and 1e-4
-on displacement series.  alpha > 0 is refused or flagged."""
+on displacement series.  The oracle integrates every pair at alpha > 0
+(~1 ms each), so those cases are small systems over few steps."""
 import numpy as np
 import pytest
 
@@ -34,9 +36,9 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
 
 
+@pytest.mark.parametrize("alpha,N", [(0.0, 100), (2.0, 24), (12.0, 24)])
 @pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-12), (swim.SWIM_F32, 1e-5)])
-def test_pair_velocity(paper, oracle_core, dtype, tol):
-    N = 100
+def test_pair_velocity(paper, oracle_core, dtype, tol, alpha, N):
     x, y = inputs.filament_geometry(N, 4, n_swim=2, spacing=0.3)
     fx, fy = [], []
     for m in range(2):
@@ -50,13 +52,13 @@ def test_pair_velocity(paper, oracle_core, dtype, tol):
     arr = [np.asarray(a, npd) for a in (x, y, fx, fy)]
     dev = [torch.from_numpy(a).cuda() for a in arr]
     ux, uy = torch.empty_like(dev[0]), torch.empty_like(dev[0])
-    swim.swim_pair_velocity(paper, np.array([0, 2 * N]), [0.0], [eps], *dev, ux, uy)
+    swim.swim_pair_velocity(paper, np.array([0, 2 * N]), [alpha], [eps], *dev, ux, uy)
     torch.cuda.synchronize()
     with oracle_core.paper_blob():
-        ox, oy = oracle_core.velocity(*[a.astype(np.float64) for a in arr], 0.0, eps)
-        rx, ry = oracle_core.velocity(*[a.astype(np.float64) for a in arr], 0.0, eps)
+        ox, oy = oracle_core.velocity(*[a.astype(np.float64) for a in arr], alpha, eps)
+        rx, ry = oracle_core.velocity(*[a.astype(np.float64) for a in arr], alpha, eps)
     # the two blobs differ (the option took effect)
-    kx, ky = oracle_core.velocity(*[a.astype(np.float64) for a in arr], 0.0, eps)
+    kx, ky = oracle_core.velocity(*[a.astype(np.float64) for a in arr], alpha, eps)
     assert rel(np.r_[kx, ky], np.r_[ox, oy]) > 1e-3
     err = rel(np.r_[ux.cpu().double().numpy(), uy.cpu().double().numpy()], np.r_[ox, oy])
     print({"dtype": dtype, "err": err})
@@ -144,17 +146,85 @@ def test_field(paper, oracle_core, dtype, tol):
     assert e1 <= tol and e2 <= tol
 
 
-def test_alpha_above_zero_is_refused(paper):
-    a = torch.zeros(4, dtype=torch.float64, device="cuda")
-    with pytest.raises(swim.SwimError):
-        swim.swim_pair_velocity(paper, np.array([0, 4]), [0.5], [0.02], a, a, a, a, a, a)
-    with pytest.raises(swim.SwimError):
-        swim.swim_flow_field(paper, a, a, a, a, 0.5, 0.02, a, a, a, a, a)
+@pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-12), (swim.SWIM_F32, 1e-4)])
+def test_filament_forward_brinkman(paper, oracle_core, dtype, tol):
+    """Two systems in one batch, alpha = 0 (closed forms) and alpha = 2
+    (quadrature), each against the oracle's run with the paper's blob."""
+    N, steps, dt, oe = 32, 20, 1e-4, 10
     P = inputs.param_rows(2, alpha=0.0)
-    P[1, 0] = 0.5
-    obs = torch.empty((2, 1, 2), dtype=torch.float64, device="cuda")
-    speed = torch.empty(2, dtype=torch.float64, device="cuda")
+    P[1, 0] = 2.0
+    td = torch.float32 if dtype == swim.SWIM_F32 else torch.float64
+    obs = torch.empty((2, steps // oe, 2), dtype=td, device="cuda")
+    speed = torch.empty(2, dtype=td, device="cuda")
     st = torch.empty(2, dtype=torch.int32, device="cuda")
-    swim.swim_forward(paper, [32, 32], None, torch.from_numpy(P).cuda(), 10, 1e-4, 10, 1.5, obs, speed, st)
+    swim.swim_forward(paper, [N, N], None, torch.from_numpy(P).cuda(), steps, dt, oe, 1.5, obs, speed, st)
     torch.cuda.synchronize()
-    assert list(st.cpu().numpy()) == [0, swim.SWIM_ST_BADPARAM]
+    assert list(st.cpu().numpy()) == [0, 0]
+    got = obs.cpu().double().numpy()
+    x0 = np.array([1.0, 0.0])
+    floor = 4 * np.finfo(np.float32 if dtype == swim.SWIM_F32 else np.float64).eps * np.sqrt(steps) * 4
+    with oracle_core.paper_blob():
+        refs = [oracle_core.forward(P[i:i + 1], N, steps, dt, oe)["obs"][0] for i in range(2)]
+    for i in range(2):
+        err = np.linalg.norm(got[i] - refs[i])
+        allow = tol * np.linalg.norm(refs[i] - x0) + floor
+        print({"alpha": P[i, 0], "err": err, "allow": allow})
+        assert err <= allow
+    assert rel(refs[1] - x0, refs[0] - x0) > 1e-4
+
+
+@pytest.mark.parametrize("dtype", [swim.SWIM_F64, swim.SWIM_F32])
+def test_sperm_forward_brinkman(paper, oracle_core, dtype):
+    """A small sperm model (12-point flagellum, 8-point head) at alpha = 0.9,
+    with the bars of the default blob's sperm runs: FP64 within 4e-12 of the
+    oracle's path length sum dt |u|, FP32 within 1e-4 of the displacement
+    plus the FP32 spacing of the positions."""
+    import test_gpu_sperm as tgs
+    nf, nh, steps, dt, oe = 12, 8, 40, 1e-5, 10
+    eps, hr, dn = 0.09, 0.05, 1.0 / 11
+    shape = swim.sperm_shape(nf, nh, 1, eps, hr, dn)
+    rows = inputs.sperm_rows(1, alpha=0.9, KC=5.0)
+    sw = inputs.sperm_swimmers(1)
+    td = torch.float32 if dtype == swim.SWIM_F32 else torch.float64
+    head = torch.empty((1, steps // oe + 1, 2), dtype=td, device="cuda")
+    tail = torch.empty_like(head)
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    swim.swim_sperm_forward(paper, dtype, shape, torch.from_numpy(rows).cuda(), torch.from_numpy(sw).cuda(), steps,
+                            dt, oe, head, tail, st)
+    torch.cuda.synchronize()
+    assert st.item() == 0
+    path = 0.0
+    with oracle_core.paper_blob():
+        ref = oracle_core.sperm_forward(rows[0], sw, nf, nh, eps, hr, dn, steps, dt, oe)
+        x, y = oracle_core.sperm_initial(nf, nh, hr, dn, sw[0, 0], sw[0, 1])
+        for k in range(steps):
+            fx, fy = oracle_core.sperm_forces(nf, nh, hr, dn, rows[0], sw[0, 2], k * dt, x, y)
+            ux, uy = oracle_core.velocity(x, y, fx, fy, rows[0][0], eps)
+            path += dt * np.sqrt(np.sum(ux * ux + uy * uy))
+            x, y = x + dt * ux, y + dt * uy
+    assert ref["status"] == 0
+    tgs.check(dtype, head.cpu().double().numpy(), ref["head"], path, steps, "head")
+    tgs.check(dtype, tail.cpu().double().numpy(), ref["tail"], path, steps, "tail")
+
+
+@pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-12), (swim.SWIM_F32, 1e-5)])
+def test_field_brinkman(paper, oracle_core, dtype, tol):
+    rng = np.random.Generator(np.random.PCG64(13))
+    x, y = rng.uniform(0, 1, 40), rng.uniform(0, 0.3, 40)
+    fx, fy = rng.normal(size=40), rng.normal(size=40)
+    gx, gy = np.meshgrid(np.linspace(-0.2, 1.2, 15), np.linspace(-0.2, 0.5, 10))
+    tx, ty = np.r_[gx.ravel(), x[:10]], np.r_[gy.ravel(), y[:10] + 0.003]
+    npd = np.float32 if dtype == swim.SWIM_F32 else np.float64
+    arr = [np.asarray(a, npd) for a in (x, y, fx, fy, tx, ty)]
+    dev = [torch.from_numpy(a).cuda() for a in arr]
+    u = torch.empty(tx.size, dtype=dev[0].dtype, device="cuda")
+    v, p = torch.empty_like(u), torch.empty_like(u)
+    swim.swim_flow_field(paper, *dev[:4], 2.0, 0.02, dev[4], dev[5], u, v, p)
+    torch.cuda.synchronize()
+    with oracle_core.paper_blob():
+        ou, ov, op = oracle_core.field(*[a.astype(np.float64) for a in arr[:4]], 2.0, 0.02,
+                                       arr[4].astype(np.float64), arr[5].astype(np.float64))
+    e1 = rel(np.r_[u.cpu().double().numpy(), v.cpu().double().numpy()], np.r_[ou, ov])
+    e2 = rel(p.cpu().double().numpy(), op)
+    print({"velocity": e1, "pressure": e2})
+    assert e1 <= tol and e2 <= tol
