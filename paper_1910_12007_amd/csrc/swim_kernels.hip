@@ -231,8 +231,7 @@ __global__ void k_sysconst(int64_t n, const double* alpha, const double* eps, Sy
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    sysconst_compute<T>(alpha[i], eps[i], out + i, blob);
-    if (out64) sysconst_compute<double>(alpha[i], eps[i], out64 + i, blob);
+    sysconst_compute2<T>(alpha[i], eps[i], out + i, out64 ? out64 + i : nullptr, blob);
 }
 
 // per-system constants of a forward batch; systems whose parameters leave
@@ -251,8 +250,7 @@ __global__ void k_sysconst_batch(int64_t n, const int64_t* sw_off, const int32_t
     for (int64_t f = sw_off[s]; f < sw_off[s + 1]; ++f)
         for (int c = 0; c < 9; ++c) ok = ok && isfinite(params[9 * f + c]);
     status[s] = ok ? 0 : SWIM_ST_BADPARAM_;
-    sysconst_compute<T>(ok ? alpha : 0.0, eps, out + s, blob);
-    if (out64) sysconst_compute<double>(ok ? alpha : 0.0, eps, out64 + s, blob);
+    sysconst_compute2<T>(ok ? alpha : 0.0, eps, out + s, out64 ? out64 + s : nullptr, blob);
 }
 
 // FP32 kernel tables of systems [s0, s0 + n), one thread per interval; the

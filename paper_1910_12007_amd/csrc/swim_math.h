@@ -272,15 +272,25 @@ SWIM_HD double pb_density(double u)
     return (1.5 / PI) * sinh(u) / (c2 * c2);
 }
 
+// Panel rule: widest panel in u and the cut-off exponent.  The direct FP64
+// evaluation takes (1/2, 42): ~1e-15 relative.  The FP32 tables, whose
+// cubic pieces are good to ~1e-7, are built with (1, 30): ~1e-12, at
+// about half the panels.
+struct PbRule {
+    double du, cut;
+};
+constexpr PbRule PB_EXACT = {0.5, 42.0};
+constexpr PbRule PB_TABLE = {1.0, 30.0};
+
 // exp(alpha r) int_{u0}^inf (3/2pi) sinh u/cosh^4 u K0(alpha eps sinh u) du
-SWIM_HD double pb_outer(double alpha, double eps, double r, double u0)
+SWIM_HD double pb_outer(double alpha, double eps, double r, double u0, PbRule q = PB_EXACT)
 {
     const double z = alpha * r;
     double b = 0.0, ul = u0;
     for (int p = 0; p < 400; ++p) {
         const double sl = eps * sinh(ul), x = alpha * (sl - r);
-        if (x + 3.0 * (ul - u0) > 42.0) break;
-        const double uh = fmin(ul + 0.5, asinh((sl + (1.0 + 0.25 * x) / alpha) / eps));
+        if (x + 3.0 * (ul - u0) > q.cut) break;
+        const double uh = fmin(ul + q.du, asinh((sl + (1.0 + 0.25 * x) / alpha) / eps));
         const double hm = 0.5 * (uh - ul), ct = 0.5 * (uh + ul);
         for (int i = 0; i < 10; ++i) {
             const double u = i < 5 ? ct - hm * GL10_X[4 - i] : ct + hm * GL10_X[i - 5];
@@ -316,16 +326,16 @@ SWIM_HD double pb_g0(double alpha, double eps)
 }
 
 // g(r) and M(r) for delta >= 1/4
-SWIM_HD void pb_gM(double alpha, double eps, double t, double* g, double* M)
+SWIM_HD void pb_gM(double alpha, double eps, double t, double* g, double* M, PbRule q = PB_EXACT)
 {
     const double r = sqrt(t), z = alpha * r, ur = asinh(r / eps);
     const bool small = z <= 2.0;
     double as = 0.0, cq = 0.0, uh = ur;
     for (int p = 0; p < 400 && uh > 0.0; ++p) {
         const double sh = eps * sinh(uh), x = alpha * (r - sh);
-        if (x - 3.0 * (ur - uh) > 42.0) break;
+        if (x - 3.0 * (ur - uh) > q.cut) break;
         const double sl = sh - (1.0 + 0.25 * x) / alpha;
-        const double ul = fmax(fmax(uh - 0.5, 0.0), sl > 0.0 ? asinh(sl / eps) : 0.0);
+        const double ul = fmax(fmax(uh - q.du, 0.0), sl > 0.0 ? asinh(sl / eps) : 0.0);
         const double hm = 0.5 * (uh - ul), ct = 0.5 * (uh + ul);
         for (int i = 0; i < 10; ++i) {
             const double u = i < 5 ? ct - hm * GL10_X[4 - i] : ct + hm * GL10_X[i - 5];
@@ -348,7 +358,7 @@ SWIM_HD void pb_gM(double alpha, double eps, double t, double* g, double* M)
         }
         uh = ul;
     }
-    const double bs = pb_outer(alpha, eps, r, ur);
+    const double bs = pb_outer(alpha, eps, r, ur, q);
     double k0e, k1e, i0e, i1e;
     bessel_k01e_f64(z, &k0e, &k1e);
     bessel_i01e_f64(z, &i0e, &i1e);
@@ -365,12 +375,8 @@ SWIM_HD void pb_gM(double alpha, double eps, double t, double* g, double* M)
     }
 }
 
-// Computes the constants of one system in FP64 and rounds them to T.
-// Requires alpha >= 0, eps > 0, alpha * eps <= 1 (checked by the caller).
-// blob 1 selects the paper's blob 3 eps^3 / (2 pi R^5) (eq. eqnblob): closed
-// forms at alpha = 0; for alpha > 0 the FP64 constants select the quadrature
-// (paper = 2, K0z0 = g(0)) and the FP32 ones those of the reading's blob with
-// H1(0) and hoff of the paper's (its FP32 values come from the tables).
+// Constants of the closed forms: the reading's blob (blob 0) for every
+// alpha, the paper's blob (blob 1) at alpha = 0.
 template <typename T> SWIM_HD void sysconst_base(double alpha, double eps, SysConst<T>* out, int blob)
 {
     const double a2 = alpha * alpha, e2 = eps * eps, w0 = a2 * e2;
@@ -447,38 +453,63 @@ template <typename T> SWIM_HD void sysconst_base(double alpha, double eps, SysCo
     *out = C;
 }
 
+// the paper's blob at alpha > 0, given g(0)
+template <typename T> SWIM_HD void sysconst_paper(double alpha, double eps, double g0, SysConst<T>* out)
+{
+    if constexpr (sizeof(T) == 8) {
+        const double a2 = alpha * alpha, e2 = eps * eps;
+        SysConst<T> C{};
+        C.a2 = a2;
+        C.e2 = e2;
+        C.inv_e2 = 1.0 / e2;
+        C.half_inv_e2 = 0.5 / e2;
+        C.w0 = a2 * e2;
+        C.inv_a2 = 1.0 / a2;
+        C.K0z0 = g0;
+        C.h1c = -0.5 * g0;
+        C.paper = 2.0;
+        const int m = tab_scale_exp(eps);
+        C.ts = ldexp(1.0, 2 * m);
+        C.its = ldexp(1.0, -2 * m);
+        C.tr = ldexp(1.0, m);
+        C.eps = eps;
+        *out = C;
+    } else {
+        SysConst<double> R;
+        sysconst_base<double>(alpha, eps, &R, 0);
+        sysconst_base<T>(alpha, eps, out, 0);
+        out->h1c = (T)(-0.5 * g0);
+        out->hoff = (T)(R.h1c + 0.5 * g0);
+    }
+}
+
+// Computes the constants of one system in FP64 and rounds them to T.
+// Requires alpha >= 0, eps > 0, alpha * eps <= 1 (checked by the caller).
+// blob 1 selects the paper's blob 3 eps^3 / (2 pi R^5) (eq. eqnblob): closed
+// forms at alpha = 0; for alpha > 0 the FP64 constants select the quadrature
+// (paper = 2, K0z0 = g(0)) and the FP32 ones those of the reading's blob with
+// H1(0) and hoff of the paper's (its FP32 values come from the tables).
 template <typename T> SWIM_HD void sysconst_compute(double alpha, double eps, SysConst<T>* out, int blob = 0)
 {
-    const double a2 = alpha * alpha, e2 = eps * eps, w0 = a2 * e2;
+    if (blob == 1 && alpha > 0.0)
+        sysconst_paper<T>(alpha, eps, pb_g0(alpha, eps), out);
+    else
+        sysconst_base<T>(alpha, eps, out, blob);
+}
+
+// the constants in T and, if out64 is not null, in FP64 (g(0) of the
+// paper's blob integrated once for both)
+template <typename T>
+SWIM_HD void sysconst_compute2(double alpha, double eps, SysConst<T>* out, SysConst<double>* out64, int blob)
+{
     if (blob == 1 && alpha > 0.0) {
         const double g0 = pb_g0(alpha, eps);
-        if constexpr (sizeof(T) == 8) {
-            SysConst<T> C{};
-            C.a2 = a2;
-            C.e2 = e2;
-            C.inv_e2 = 1.0 / e2;
-            C.half_inv_e2 = 0.5 / e2;
-            C.w0 = w0;
-            C.inv_a2 = 1.0 / a2;
-            C.K0z0 = g0;
-            C.h1c = -0.5 * g0;
-            C.paper = 2.0;
-            const int m = tab_scale_exp(eps);
-            C.ts = ldexp(1.0, 2 * m);
-            C.its = ldexp(1.0, -2 * m);
-            C.tr = ldexp(1.0, m);
-            C.eps = eps;
-            *out = C;
-        } else {
-            SysConst<double> R;
-            sysconst_base<double>(alpha, eps, &R, 0);
-            sysconst_base<T>(alpha, eps, out, 0);
-            out->h1c = (T)(-0.5 * g0);
-            out->hoff = (T)(R.h1c + 0.5 * g0);
-        }
+        sysconst_paper<T>(alpha, eps, g0, out);
+        if (out64) sysconst_paper<double>(alpha, eps, g0, out64);
         return;
     }
     sysconst_base<T>(alpha, eps, out, blob);
+    if (out64) sysconst_base<double>(alpha, eps, out64, blob);
 }
 
 // ---------------------------------------------------------------------------
@@ -643,7 +674,8 @@ SWIM_HD void kernel_paper_stokes(const SysConst<T>& C, T t, T& Ht, T& H2)
 // H1 = M/r^2 - g, H2 = (g - 2M/r^2)/r^2 from the quadrature.  Not inlined:
 // it is large and only systems of this blob call it.
 __host__ __device__ __attribute__((noinline)) inline void kernel_paper_brinkman(const SysConst<double>& C, double t,
-                                                                              double& Ht, double& H2)
+                                                                              double& Ht, double& H2,
+                                                                              PbRule q = PB_EXACT)
 {
     const double delta = t * C.inv_e2;
     if (delta < 0.25) {
@@ -660,7 +692,7 @@ __host__ __device__ __attribute__((noinline)) inline void kernel_paper_brinkman(
         return;
     }
     double g, M;
-    pb_gM(sqrt(C.a2), C.eps, t, &g, &M);
+    pb_gM(sqrt(C.a2), C.eps, t, &g, &M, q);
     const double Mt = M / t;
     H2 = (g - 2.0 * Mt) / t;
     Ht = Mt - g - C.h1c;
@@ -697,7 +729,8 @@ SWIM_HD void kernel_eval(const SysConst<T>& C, T t, T& Ht, T& H2)
 // taken as the integer u in [0, 2^19) (the interval coordinate times 2^19).
 // On each interval both functions are the cubic through their values at the
 // Chebyshev-Lobatto nodes 0, 1/4, 3/4, 1 of the interval, evaluated once per
-// system in FP64 by kernel_eval<double>.  The relative width 1/16 of an
+// system in FP64 by kernel_eval<double> (for the paper's blob at alpha > 0
+// by its quadrature with the table's panel rule).  The relative width 1/16 of an
 // interval bounds the interpolation error by about 4e-3 (1/16)^4 max|f''''|
 // in units of the function's own scale (about 1e-7 for the log and 1/t
 // behaviour of these kernels); rounding the coefficients to FP32 adds one
@@ -770,7 +803,10 @@ SWIM_HD void tab_interval(const SysConst<double>& C, int i, TabE& out, float* h0
         // t = 0 is taken as a vanishing positive t, whose evaluation follows
         // the near-contact series and gives the limits H2(0) and Ht(0) = 0
         const double t = fmax((v0 - 1.0 + hv * un[k]) * C.its, 1e-300);
-        kernel_eval<double>(C, t, fh[k], fg[k]);
+        if (C.paper == 2.0)
+            kernel_paper_brinkman(C, t, fh[k], fg[k], PB_TABLE);
+        else
+            kernel_eval<double>(C, t, fh[k], fg[k]);
     }
     const double sc = ldexp(1.0, -TAB_SHIFT);
     cubic_lobatto(fh, sc, 1.0, out.h);

@@ -521,8 +521,7 @@ __global__ void k_sperm_setup(int64_t n_sys, int32_t nsw, double eps, const doub
     for (int c = 0; c < SWIM_SP_NPARAM; ++c) ok = ok && isfinite(p[c]);
     for (int c = 0; c < 3 * nsw; ++c) ok = ok && isfinite(swp[(int64_t)3 * nsw * s + c]);
     status[s] = ok ? 0 : ST_BADPARAM;
-    sysconst_compute<T>(ok ? alpha : 0.0, eps, sysc + s, blob);
-    if (sysc64) sysconst_compute<double>(ok ? alpha : 0.0, eps, sysc64 + s, blob);
+    sysconst_compute2<T>(ok ? alpha : 0.0, eps, sysc + s, sysc64 ? sysc64 + s : nullptr, blob);
 }
 
 // observables of a sperm run per system s and interval/sample k = 1..n_obs
