@@ -266,10 +266,71 @@ SWIM_HD void bessel_k01e_f64(double z, double* k0e, double* k1e)
     }
 }
 
-SWIM_HD double pb_density(double u)
+// sinh(u) and the density (3/2pi) sinh u / cosh^4 u from one expm1
+// (e^u - e^-u = em + em/e with em = e^u - 1: no cancellation at small u)
+SWIM_HD void pb_point(double u, double* sh, double* dens)
 {
-    const double c = cosh(u), c2 = c * c;
-    return (1.5 / PI) * sinh(u) / (c2 * c2);
+    const double em = expm1(u), e = em + 1.0;
+    const double sn = 0.5 * (em + em / e), c = 0.5 * (e + 1.0 / e), c2 = c * c;
+    *sh = sn;
+    *dens = (1.5 / PI) * sn / (c2 * c2);
+}
+
+// reciprocals 1/(k+1)^2 and 1/(k+1) of the series recurrences below (a
+// multiplication per term instead of an FP64 division)
+struct PbRecip {
+    double sq[80], lin[80];
+    constexpr PbRecip() : sq(), lin()
+    {
+        for (int k = 0; k < 80; ++k) {
+            sq[k] = 1.0 / ((double)(k + 1) * (double)(k + 1));
+            lin[k] = 1.0 / (double)(k + 1);
+        }
+    }
+};
+static constexpr PbRecip PB_RECIP{};
+
+// K0(x) e^z for x >= z >= 0: the ascending series (A&S 9.6.13) times ez = e^z
+// for x <= 2, the K0 fit times e^(z - x) above
+SWIM_HD double pb_k0x(double x, double z, double ez)
+{
+    if (x <= SWIM_KFIT_ZS) {
+        const double y = 0.25 * x * x, L = log(0.5 * x) + EULER_GAMMA;
+        double term = 1.0, hk = 0.0, i0 = 0.0, sp = 0.0;  // y^k/(k!)^2, H_k
+        for (int k = 0; k < 40; ++k) {
+            i0 += term;
+            sp += hk * term;
+            term *= y * PB_RECIP.sq[k];
+            hk += PB_RECIP.lin[k];
+            if (term < 1e-18 * i0) break;
+        }
+        return (sp - L * i0) * ez;
+    }
+    return kfit<double>(0, SWIM_KFIT_ZS / x) * exp(z - x) / sqrt(x);
+}
+
+// I0(x) e^-z for 0 <= x <= z: the ascending series times enz = e^-z for
+// x <= 20, the asymptotic series times e^(x - z) above (as bessel_i01e_f64)
+SWIM_HD double pb_i0x(double x, double z, double enz)
+{
+    if (x <= 20.0) {
+        const double y = 0.25 * x * x;
+        double a = 1.0, s0 = 0.0;
+        for (int k = 0; k < 80; ++k) {
+            s0 += a;
+            a *= y * PB_RECIP.sq[k];
+            if (a < 1e-18 * s0) break;
+        }
+        return s0 * enz;
+    }
+    double t0 = 1.0, s0 = 1.0;
+    const double r8 = 1.0 / (8.0 * x);
+    for (int k = 1; k < 60; ++k) {
+        t0 *= (double)(2 * k - 1) * (2 * k - 1) * r8 * PB_RECIP.lin[k - 1];
+        s0 += t0;
+        if (t0 < 1e-18 * s0) break;
+    }
+    return s0 * exp(x - z) / sqrt(2.0 * PI * x);
 }
 
 // Panel rule: widest panel in u and the cut-off exponent.  The direct FP64
@@ -285,7 +346,7 @@ constexpr PbRule PB_TABLE = {1.0, 30.0};
 // exp(alpha r) int_{u0}^inf (3/2pi) sinh u/cosh^4 u K0(alpha eps sinh u) du
 SWIM_HD double pb_outer(double alpha, double eps, double r, double u0, PbRule q = PB_EXACT)
 {
-    const double z = alpha * r;
+    const double z = alpha * r, ez = exp(fmin(z, SWIM_KFIT_ZS));
     double b = 0.0, ul = u0;
     for (int p = 0; p < 400; ++p) {
         const double sl = eps * sinh(ul), x = alpha * (sl - r);
@@ -295,10 +356,9 @@ SWIM_HD double pb_outer(double alpha, double eps, double r, double u0, PbRule q 
         for (int i = 0; i < 10; ++i) {
             const double u = i < 5 ? ct - hm * GL10_X[4 - i] : ct + hm * GL10_X[i - 5];
             const double w = i < 5 ? GL10_W[4 - i] : GL10_W[i - 5];
-            const double s = eps * sinh(u);
-            double k0e, k1e;
-            bessel_k01e_f64(alpha * s, &k0e, &k1e);
-            b += hm * w * pb_density(u) * k0e * exp(z - alpha * s);
+            double sh, dens;
+            pb_point(u, &sh, &dens);
+            b += hm * w * dens * pb_k0x(alpha * eps * sh, z, ez);
         }
         ul = uh;
     }
@@ -316,10 +376,9 @@ SWIM_HD double pb_g0(double alpha, double eps)
         for (int i = 0; i < 10; ++i) {
             const double u = i < 5 ? ct - hm * GL10_X[4 - i] : ct + hm * GL10_X[i - 5];
             const double w = i < 5 ? GL10_W[4 - i] : GL10_W[i - 5];
-            const double s = eps * sinh(u);
-            double k0e, k1e;
-            bessel_k01e_f64(alpha * s, &k0e, &k1e);
-            b += hm * w * pb_density(u) * k0e * exp(-alpha * s);
+            double sh, dens;
+            pb_point(u, &sh, &dens);
+            b += hm * w * dens * pb_k0x(alpha * eps * sh, 0.0, 1.0);
         }
     }
     return -(b + pb_outer(alpha, eps, 0.0, 0.5));
@@ -330,6 +389,7 @@ SWIM_HD void pb_gM(double alpha, double eps, double t, double* g, double* M, PbR
 {
     const double r = sqrt(t), z = alpha * r, ur = asinh(r / eps);
     const bool small = z <= 2.0;
+    const double enz = exp(-z);
     double as = 0.0, cq = 0.0, uh = ur;
     for (int p = 0; p < 400 && uh > 0.0; ++p) {
         const double sh = eps * sinh(uh), x = alpha * (r - sh);
@@ -339,18 +399,18 @@ SWIM_HD void pb_gM(double alpha, double eps, double t, double* g, double* M, PbR
         const double hm = 0.5 * (uh - ul), ct = 0.5 * (uh + ul);
         for (int i = 0; i < 10; ++i) {
             const double u = i < 5 ? ct - hm * GL10_X[4 - i] : ct + hm * GL10_X[i - 5];
-            const double w = hm * (i < 5 ? GL10_W[4 - i] : GL10_W[i - 5]) * pb_density(u);
-            const double s = eps * sinh(u), xs = alpha * s;
-            double i0e, i1e;
-            bessel_i01e_f64(xs, &i0e, &i1e);
-            as += w * i0e * exp(xs - z);
+            double sh, dens;
+            pb_point(u, &sh, &dens);
+            const double w = hm * (i < 5 ? GL10_W[4 - i] : GL10_W[i - 5]) * dens;
+            const double s = eps * sh, xs = alpha * s;
+            as += w * pb_i0x(xs, z, enz);
             if (small) {
                 // (I0(xs) - 1)/alpha^2 = (s^2/4) sum_k (xs^2/4)^k / ((k+1)!)^2
                 const double y = 0.25 * xs * xs;
                 double term = 1.0, acc = 0.0;
                 for (int k = 0; k < 40; ++k) {
                     acc += term;
-                    term *= y / ((double)(k + 2) * (k + 2));
+                    term *= y * PB_RECIP.sq[k + 1];
                     if (term < 1e-18 * acc) break;
                 }
                 cq += w * 0.25 * s * s * acc;
