@@ -255,13 +255,38 @@ __global__ void k_sysconst_batch(int64_t n, const int64_t* sw_off, const int32_t
 
 // FP32 kernel tables of systems [s0, s0 + n), one thread per interval; the
 // FP64 evaluation's registers stay out of the kernels that use the tables
+// One wave per TAB_CHUNK consecutive intervals of one system: lane l < 63
+// evaluates nodes 0, 1/4, 3/4 of interval c * 63 + l and takes node 1 (the
+// next interval's node 0) from lane l + 1; lane 63 evaluates only that node
+// for lane 62.  Three kernel evaluations per entry instead of four.
+constexpr int TAB_CHUNK = 63;
+constexpr int TAB_WAVES = (TAB_N + 1 + TAB_CHUNK - 1) / TAB_CHUNK;  // waves per system
+
 __global__ __launch_bounds__(64) void k_table_build(int64_t s0, int64_t n, const SysConst<double>* sysc64, TabSys* tab)
 {
-    const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    const int64_t s = s0 + e / (TAB_N + 1);
-    const int i = (int)(e % (TAB_N + 1));
-    if (e >= n * (TAB_N + 1)) return;
-    tab_interval(sysc64[s], i, tab[s].e[i], &tab[s].h0lo[i]);
+    const int64_t w = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t s = s0 + w / TAB_WAVES;
+    const int i = (int)(w % TAB_WAVES) * TAB_CHUNK + lane;  // interval (lane < 63) or end node (lane 63)
+    const bool live = w < n * TAB_WAVES && i <= TAB_N;
+    double fh[4] = {0.0, 0.0, 0.0, 0.0}, fg[4] = {0.0, 0.0, 0.0, 0.0};
+    if (live) {
+        const SysConst<double>& C = sysc64[s];
+        tab_node(C, i, 0, fh[0], fg[0]);
+        if (lane < TAB_CHUNK && i < TAB_N) {
+            tab_node(C, i, 1, fh[1], fg[1]);
+            tab_node(C, i, 2, fh[2], fg[2]);
+        }
+    }
+    // every lane of the wave takes part in the shuffles
+    fh[3] = __shfl_down(fh[0], 1);
+    fg[3] = __shfl_down(fg[0], 1);
+    if (!live || lane == TAB_CHUNK) return;
+    if (i == TAB_N) {
+        tab_interval(sysc64[s], i, tab[s].e[i], &tab[s].h0lo[i]);  // the zero entry
+        return;
+    }
+    tab_assemble(sysc64[s], fh, fg, tab[s].e[i], &tab[s].h0lo[i]);
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
@@ -1107,7 +1132,7 @@ size_t table_bytes() { return sizeof(TabSys); }
 hipError_t launch_table_build(int64_t s0, int64_t n, const void* sysc64, void* tab, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_table_build, dim3((unsigned)nblk(n * (TAB_N + 1), 64)), dim3(64), 0, st, s0, n,
+    hipLaunchKernelGGL(k_table_build, dim3((unsigned)(n * TAB_WAVES)), dim3(64), 0, st, s0, n,
                        (const SysConst<double>*)sysc64, (TabSys*)tab);
     return hipGetLastError();
 }

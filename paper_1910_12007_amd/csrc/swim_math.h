@@ -843,9 +843,38 @@ SWIM_HD void cubic_lobatto(const double (&f)[4], double sc, double mul, float (&
     c[3] = (float)(mul * sc * sc * sc * d0123);
 }
 
+// FP64 kernel values at node k (coordinate 0, 1/4, 3/4, 1) of interval i
+// (i <= TAB_N; node 0 of i = TAB_N is the end of the last interval).  t = 0
+// is taken as a vanishing positive t, whose evaluation follows the
+// near-contact series and gives the limits H2(0) and Ht(0) = 0.  The end
+// of interval i and the start of interval i + 1 are the same t exactly
+// (dyadic values of v), so either evaluation serves both.
+SWIM_HD void tab_node(const SysConst<double>& C, int i, int k, double& fh, double& fg)
+{
+    const int e = i >> TAB_M, j = i & ((1 << TAB_M) - 1);
+    const double a = ldexp(1.0, e);
+    const double v0 = a * (1.0 + (double)j / (double)(1 << TAB_M)), hv = a / (double)(1 << TAB_M);
+    const double un = k == 0 ? 0.0 : k == 1 ? 0.25 : k == 2 ? 0.75 : 1.0;
+    const double t = fmax((v0 - 1.0 + hv * un) * C.its, 1e-300);
+    if (C.paper == 2.0)
+        kernel_paper_brinkman(C, t, fh, fg, PB_TABLE);
+    else
+        kernel_eval<double>(C, t, fh, fg);
+}
+
+// the table entry from its four node values; h0lo, if not null: the FP32
+// remainder of the constant coefficient of Ht
+SWIM_HD void tab_assemble(const SysConst<double>& C, const double (&fh)[4], const double (&fg)[4], TabE& out,
+                          float* h0lo)
+{
+    const double sc = ldexp(1.0, -TAB_SHIFT);
+    cubic_lobatto(fh, sc, 1.0, out.h);
+    cubic_lobatto(fg, sc, C.its, out.g);
+    if (h0lo) *h0lo = (float)(fh[0] - (double)out.h[0]);
+}
+
 // interval i of the table of the system with FP64 constants C (i = TAB_N:
-// the zero entry); h0lo, if not null: the FP32 remainder of the constant
-// coefficient of Ht
+// the zero entry)
 SWIM_HD void tab_interval(const SysConst<double>& C, int i, TabE& out, float* h0lo = nullptr)
 {
     if (i >= TAB_N) {
@@ -853,25 +882,10 @@ SWIM_HD void tab_interval(const SysConst<double>& C, int i, TabE& out, float* h0
         if (h0lo) *h0lo = 0.0f;
         return;
     }
-    const int e = i >> TAB_M, j = i & ((1 << TAB_M) - 1);
-    const double a = ldexp(1.0, e);
-    const double v0 = a * (1.0 + (double)j / (double)(1 << TAB_M)), hv = a / (double)(1 << TAB_M);
-    const double un[4] = {0.0, 0.25, 0.75, 1.0};
     double fh[4], fg[4];
 #pragma unroll 1
-    for (int k = 0; k < 4; ++k) {
-        // t = 0 is taken as a vanishing positive t, whose evaluation follows
-        // the near-contact series and gives the limits H2(0) and Ht(0) = 0
-        const double t = fmax((v0 - 1.0 + hv * un[k]) * C.its, 1e-300);
-        if (C.paper == 2.0)
-            kernel_paper_brinkman(C, t, fh[k], fg[k], PB_TABLE);
-        else
-            kernel_eval<double>(C, t, fh[k], fg[k]);
-    }
-    const double sc = ldexp(1.0, -TAB_SHIFT);
-    cubic_lobatto(fh, sc, 1.0, out.h);
-    cubic_lobatto(fg, sc, C.its, out.g);
-    if (h0lo) *h0lo = (float)(fh[0] - (double)out.h[0]);
+    for (int k = 0; k < 4; ++k) tab_node(C, i, k, fh[k], fg[k]);
+    tab_assemble(C, fh, fg, out, h0lo);
 }
 
 // bits of v = 1 + sigma t: their index bits >> TAB_SHIFT (>= TAB_END beyond
