@@ -46,11 +46,11 @@ VALU_OPS_PER_PAIR_BIG = 38
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 # HBM bytes of one launch of that kernel on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch: 52240.4 and 2134.3) scaled by
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch: 52365.1 and 2134.3) scaled by
 # the same counters over a 256 MiB device copy (x2.0 and x1.0), for the
 # kernel as it stands (profiles/k_forward_batch_4096x128_counters.md); set it
 # to None whenever the kernel changes until the counters are taken again
-TRAFFIC_BYTES = 52258.375 * 1024 * 2.0 + 2129.09375 * 1024 * 1.0
+TRAFFIC_BYTES = 52365.125 * 1024 * 2.0 + 2134.25 * 1024 * 1.0
 
 
 def load_data():
