@@ -166,6 +166,43 @@ SWIM_HD void bessel_k01_q_f64(double z, double* K0, double* K1, double* Q)
     }
 }
 
+// reciprocals 1/(k+1)^2 and 1/(k+1) for the series recurrences of the
+// set-up (a multiplication per term instead of an FP64 division)
+struct PbRecip {
+    double sq[80], lin[80];
+    constexpr PbRecip() : sq(), lin()
+    {
+        for (int k = 0; k < 80; ++k) {
+            sq[k] = 1.0 / ((double)(k + 1) * (double)(k + 1));
+            lin[k] = 1.0 / (double)(k + 1);
+        }
+    }
+};
+static constexpr PbRecip PB_RECIP{};
+
+// power-series coefficients in w of I0, P0 = sum_k psi(k+1) w^k/(4^k (k!)^2),
+// A = z I1 and B = sum_{m>=1} [psi(m) + psi(m+1)] w^m/(4^m (m-1)! m!), the
+// ascending series of the K0/K1 closed forms, fixed at compile time
+struct SetupSeries {
+    double I0[NSER_SETUP], P0[NSER_SETUP], A[NSER_SETUP], B[NSER_SETUP];
+    constexpr SetupSeries() : I0(), P0(), A(), B()
+    {
+        double psi = -EULER_GAMMA;  // psi(k+1)
+        for (int k = 0; k < NSER_SETUP; ++k) {
+            const double ik = 1.0 / (pow4(k) * fact(k) * fact(k));
+            I0[k] = ik;
+            P0[k] = psi * ik;
+            if (k > 0) {
+                const double am = 1.0 / (pow4(k) * fact(k - 1) * fact(k));  // 1/(4^m (m-1)! m!), m = k
+                A[k] = 2.0 * am;
+                B[k] = ((psi - 1.0 / k) + psi) * am;                         // psi(m) + psi(m+1)
+            }
+            psi += 1.0 / (k + 1);
+        }
+    }
+};
+static constexpr SetupSeries SETUP_SERIES{};
+
 // Taylor coefficients at w0 of a power series p(w) = sum_m p_m w^m:
 // phat_n = sum_{m>=n} C(m, n) p_m w0^(m-n)
 SWIM_HD double taylor_at(const double* p, int M, int n, double w0)
@@ -173,7 +210,7 @@ SWIM_HD double taylor_at(const double* p, int M, int n, double w0)
     double s = 0.0, binom = 1.0, wp = 1.0;  // C(m, n), w0^(m-n) for m = n
     for (int m = n; m < M; ++m) {
         s += binom * p[m] * wp;
-        binom = binom * (m + 1) / (m + 1 - n);
+        binom = binom * (m + 1) * PB_RECIP.lin[m - n];  // C(m+1, n) = C(m, n) (m+1)/(m+1-n)
         wp *= w0;
     }
     return s;
@@ -276,19 +313,6 @@ SWIM_HD void pb_point(double u, double* sh, double* dens)
     *dens = (1.5 / PI) * sn / (c2 * c2);
 }
 
-// reciprocals 1/(k+1)^2 and 1/(k+1) of the series recurrences below (a
-// multiplication per term instead of an FP64 division)
-struct PbRecip {
-    double sq[80], lin[80];
-    constexpr PbRecip() : sq(), lin()
-    {
-        for (int k = 0; k < 80; ++k) {
-            sq[k] = 1.0 / ((double)(k + 1) * (double)(k + 1));
-            lin[k] = 1.0 / (double)(k + 1);
-        }
-    }
-};
-static constexpr PbRecip PB_RECIP{};
 
 // K0(x) e^z for x >= z >= 0: the ascending series (A&S 9.6.13) times ez = e^z
 // for x <= 2, the K0 fit times e^(z - x) above
@@ -476,25 +500,10 @@ template <typename T> SWIM_HD void sysconst_base(double alpha, double eps, SysCo
     C.K0z0 = (T)K0;
     C.q0 = (T)Q0;
     C.h1c = (T)(c * K0 / (4.0 * PI));
-    // power-series coefficients of I0, P0, A, B in w
-    double pI0[NSER_SETUP], pP0[NSER_SETUP], pA[NSER_SETUP], pB[NSER_SETUP];
-    double psi = -EULER_GAMMA;  // psi(k+1)
-    for (int k = 0; k < NSER_SETUP; ++k) {
-        const double ik = 1.0 / (pow4(k) * fact(k) * fact(k));
-        pI0[k] = ik;
-        pP0[k] = psi * ik;
-        if (k == 0) {
-            pA[0] = 0.0;
-            pB[0] = 0.0;
-        } else {
-            const double am = 1.0 / (pow4(k) * fact(k - 1) * fact(k));  // 1/(4^m (m-1)! m!), m = k
-            const double psim = psi;                                      // psi(m+1) with m = k
-            const double psim0 = psi - 1.0 / k;                           // psi(m)
-            pA[k] = 2.0 * am;
-            pB[k] = (psim0 + psim) * am;
-        }
-        psi += 1.0 / (k + 1);
-    }
+    const double* pI0 = SETUP_SERIES.I0;
+    const double* pP0 = SETUP_SERIES.P0;
+    const double* pA = SETUP_SERIES.A;
+    const double* pB = SETUP_SERIES.B;
     const double L0 = log(0.25 * w0);
     // U(t) = sum_{n>=1} [-L0/2 I0hat_n + P0hat_n] a2^n t^n,  stored as U[n-1]
     // V(t) = sum_{n>=2} (n-1) [L0/2 Ahat_n - Bhat_n] a2^(n-1) t^(n-2), stored as V[n-2]
@@ -557,8 +566,36 @@ template <typename T> SWIM_HD void sysconst_compute(double alpha, double eps, Sy
         sysconst_base<T>(alpha, eps, out, blob);
 }
 
-// the constants in T and, if out64 is not null, in FP64 (g(0) of the
-// paper's blob integrated once for both)
+// FP64 constants rounded to T field by field (what sysconst_base<T> forms)
+template <typename T> SWIM_HD void sysconst_cast(const SysConst<double>& D, SysConst<T>* out)
+{
+    SysConst<T> C;
+    C.a2 = (T)D.a2;
+    C.e2 = (T)D.e2;
+    C.inv_e2 = (T)D.inv_e2;
+    C.half_inv_e2 = (T)D.half_inv_e2;
+    C.w0 = (T)D.w0;
+    C.inv_a2 = (T)D.inv_a2;
+    C.cpi = (T)D.cpi;
+    C.c2pi = (T)D.c2pi;
+    C.K0z0 = (T)D.K0z0;
+    C.q0 = (T)D.q0;
+    C.h1c = (T)D.h1c;
+    C.paper = (T)D.paper;
+    C.ts = (T)D.ts;
+    C.its = (T)D.its;
+    C.tr = (T)D.tr;
+    C.eps = (T)D.eps;
+    for (int n = 0; n < NT_MAX; ++n) {
+        C.U[n] = (T)D.U[n];
+        C.V[n] = (T)D.V[n];
+    }
+    C.hoff = (T)D.hoff;
+    *out = C;
+}
+
+// the constants in T and, if out64 is not null, in FP64 (one FP64 pass for
+// both; g(0) of the paper's blob integrated once)
 template <typename T>
 SWIM_HD void sysconst_compute2(double alpha, double eps, SysConst<T>* out, SysConst<double>* out64, int blob)
 {
@@ -568,8 +605,12 @@ SWIM_HD void sysconst_compute2(double alpha, double eps, SysConst<T>* out, SysCo
         if (out64) sysconst_paper<double>(alpha, eps, g0, out64);
         return;
     }
-    sysconst_base<T>(alpha, eps, out, blob);
-    if (out64) sysconst_base<double>(alpha, eps, out64, blob);
+    if (out64) {
+        sysconst_base<double>(alpha, eps, out64, blob);
+        sysconst_cast<T>(*out64, out);
+    } else {
+        sysconst_base<T>(alpha, eps, out, blob);
+    }
 }
 
 // ---------------------------------------------------------------------------
