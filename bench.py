@@ -402,11 +402,31 @@ def paper_blob_leg(ctx, stream, Ns, P, steps, dt, obs_every, default_ms):
         torch.cuda.synchronize()
         return ev[0].elapsed_time(ev[1])
 
+    # FP64 direct evaluation (the reference mode): one velocity sum of a
+    # 512-point system, alpha = 1, with each blob
+    m = 512
+    rng = np.random.Generator(np.random.PCG64(11))
+    pts = [torch.from_numpy(a).to("cuda") for a in (rng.uniform(0, 1, m), rng.uniform(0, 0.3, m),
+                                                   rng.normal(size=m), rng.normal(size=m))]
+    ux, uy = torch.empty_like(pts[0]), torch.empty_like(pts[0])
+
+    def timed_f64(blob):
+        swim.swim_set_option(ctx, swim.SWIM_OPT_BLOB, blob)
+        swim.swim_pair_velocity(ctx, np.array([0, m]), [1.0], [0.02], *pts, ux, uy, stream=stream)  # warm-up
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        swim.swim_pair_velocity(ctx, np.array([0, m]), [1.0], [0.02], *pts, ux, uy, stream=stream)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1])
+
     try:
         timed(1, 1, 1, one)  # warm-up
         one_paper = min(timed(1, 1, 1, one) for _ in range(2))
         one_default = min(timed(0, 1, 1, one) for _ in range(2))
         ms = timed(1, steps, obs_every, obs)
+        f64_paper = timed_f64(1)
+        f64_default = timed_f64(0)
     finally:
         swim.swim_set_option(ctx, swim.SWIM_OPT_BLOB, swim.SWIM_BLOB_READING)
     done_h = done.cpu().numpy().astype(np.int64)
@@ -415,7 +435,11 @@ def paper_blob_leg(ctx, stream, Ns, P, steps, dt, obs_every, default_ms):
                         "paper's blob, alpha > 0 (quadrature-built FP32 tables)",
             "ms": ms, "default_blob_ms": default_ms, "setup_ms": one_paper - one_default,
             "one_step_ms": one_paper, "one_step_default_ms": one_default,
-            "pair_evals_per_s": pairs / (ms * 1e-3), "runs_stopped": int((status != 0).sum().item())}
+            "pair_evals_per_s": pairs / (ms * 1e-3), "runs_stopped": int((status != 0).sum().item()),
+            "fp64_direct": {"workload": f"one FP64 velocity sum of {m} points, alpha = 1, eps = 0.02",
+                            "paper_ms": f64_paper, "default_ms": f64_default,
+                            "paper_pair_evals_per_s": m * m / (f64_paper * 1e-3),
+                            "default_pair_evals_per_s": m * m / (f64_default * 1e-3)}}
 
 
 def surrogate_leg(ctx, data):

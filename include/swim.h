@@ -110,10 +110,10 @@ int swim_version(void);
  *                    quadrature, with H1 = M/r^2 - g, H2 = (g - 2M/r^2)/r^2,
  *                    M = int_0^r s g ds.  FP32 runs read it from the
  *                    per-system tables (built once per launch from the
- *                    quadrature, about 3e3 kernel values per system); FP64
- *                    evaluates the quadrature per pair, about 1e4 times
- *                    the cost of the closed forms (a reference mode for
- *                    small systems).  It applies to every velocity and
+ *                    quadrature, about 2e3 kernel values per system); FP64
+ *                    evaluates the quadrature per pair, a few hundred
+ *                    times the cost of the closed forms (a reference mode
+ *                    for small systems).  It applies to every velocity and
  *                    pressure evaluation, including the pressure's blob
  *                    mass (1 - eps^3/R^3).
  * Read-only counters (swim_get_option): SWIM_OPT_GRAPH_LAUNCHES (graph

@@ -228,3 +228,57 @@ def test_field_brinkman(paper, oracle_core, dtype, tol):
     e2 = rel(p.cpu().double().numpy(), op)
     print({"velocity": e1, "pressure": e2})
     assert e1 <= tol and e2 <= tol
+
+
+def test_graph_replay_rebuilds_quadrature_tables(paper, oracle_core):
+    """FP32 runs with the paper's blob through a captured graph: the
+    per-system constants (g(0) by quadrature) and the quadrature-built tables
+    are set-up kernels inside the graph, so a replay with new alpha values in
+    the same parameter buffer must equal the eager run at those values, bit
+    for bit, and the oracle within the FP32 bar."""
+    N, steps, dt, oe = 32, 20, 1e-4, 10
+    P = inputs.param_rows(2, alpha=2.0)
+    P[1, 0] = 5.0
+    P2 = P.copy()
+    P2[:, 0] = [0.7, 9.0]
+    Pd = torch.from_numpy(P).cuda()
+    obs = torch.empty((2, steps // oe, 2), dtype=torch.float32, device="cuda")
+    speed = torch.empty(2, dtype=torch.float32, device="cuda")
+    st = torch.empty(2, dtype=torch.int32, device="cuda")
+
+    def run():
+        swim.swim_forward(paper, [N, N], None, Pd, steps, dt, oe, 1.5, obs, speed, st)
+        torch.cuda.synchronize()
+        assert list(st.cpu().numpy()) == [0, 0]
+        return obs.cpu().numpy().copy()
+
+    try:
+        swim.swim_set_option(paper, swim.SWIM_OPT_GRAPH, 0)
+        ref = run()
+        Pd.copy_(torch.from_numpy(P2))
+        torch.cuda.synchronize()
+        ref2 = run()
+        Pd.copy_(torch.from_numpy(P))
+        torch.cuda.synchronize()
+        swim.swim_set_option(paper, swim.SWIM_OPT_GRAPH, 1)
+        captures0 = swim.swim_get_option(paper, swim.SWIM_OPT_GRAPH_CAPTURES)
+        launches0 = swim.swim_get_option(paper, swim.SWIM_OPT_GRAPH_LAUNCHES)
+        for _ in range(3):
+            assert np.array_equal(run(), ref)
+        Pd.copy_(torch.from_numpy(P2))
+        torch.cuda.synchronize()
+        for _ in range(2):
+            assert np.array_equal(run(), ref2)
+        assert swim.swim_get_option(paper, swim.SWIM_OPT_GRAPH_CAPTURES) - captures0 == 1
+        assert swim.swim_get_option(paper, swim.SWIM_OPT_GRAPH_LAUNCHES) - launches0 == 4
+    finally:
+        swim.swim_set_option(paper, swim.SWIM_OPT_GRAPH, 1)
+    x0 = np.array([1.0, 0.0])
+    floor = 4 * np.finfo(np.float32).eps * np.sqrt(steps) * 4
+    with oracle_core.paper_blob():
+        for i in range(2):
+            r = oracle_core.forward(P2[i:i + 1], N, steps, dt, oe)["obs"][0]
+            err = np.linalg.norm(ref2[i] - r)
+            allow = 1e-4 * np.linalg.norm(r - x0) + floor
+            print({"alpha": P2[i, 0], "err": err, "allow": allow})
+            assert err <= allow
