@@ -105,6 +105,26 @@ def test_host_paper_blob_kernel_matches_oracle(oracle_core, dtype, tol):
             assert np.all(np.abs(h2[1:][near] / H2o[1:][near] - 1) < 50 * tol), (alpha, N)
 
 
+@pytest.mark.parametrize("alpha,eps", [(1e-10, 0.01), (1e-6, 0.01), (100.0, 0.01), (1000.0, 0.001), (0.3, 1e-4),
+                                       (0.5, 0.5)])
+def test_host_paper_blob_kernel_extremes(oracle_core, alpha, eps):
+    """The paper blob's quadrature at the ends of the domain (alpha from
+    1e-10 to alpha eps = 1, eps from 1e-4 to 0.5), at t = 0, at denormal-
+    small t, at both sides of the near-contact switch delta = 1/4 and out to
+    t = 1e6 eps^2: finite everywhere and within the bars above."""
+    t = np.concatenate([[0.0, 1e-300, 1e-30], eps ** 2 * np.array([0.2499999, 0.25, 0.2500001]),
+                        np.geomspace(1e-8, 1e6, 40)])
+    for dtype, tol in ((swim.SWIM_F64, 2e-13), (swim.SWIM_F32, 2e-6)):
+        tt = t if dtype == swim.SWIM_F64 else t.astype(np.float32).astype(np.float64)
+        with oracle_core.paper_blob():
+            H1o, H2o = oracle_core.kernel(alpha, eps, tt)
+        h1t, h2, _ = swim.swim_kernel_eval_host(dtype, alpha, eps, tt, blob=swim.SWIM_BLOB_PAPER)
+        assert np.all(np.isfinite(h1t)) and np.all(np.isfinite(h2))
+        sc = _scale(H1o[1:], H1o[0], tt[1:], H2o[1:])
+        assert np.max(np.abs(h1t[1:] - (H1o[1:] - H1o[0])) / sc) < tol
+        assert np.max(np.abs(h2[1:] - H2o[1:]) * tt[1:] / sc) < tol
+
+
 def test_host_kernel_rejects_unknown_blob():
     with pytest.raises(swim.SwimError):
         swim.swim_kernel_eval_host(swim.SWIM_F64, 1.0, 0.02, np.array([1.0]), blob=2)
