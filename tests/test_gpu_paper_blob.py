@@ -36,7 +36,7 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
 
 
-@pytest.mark.parametrize("alpha,N", [(0.0, 100), (2.0, 24), (12.0, 24)])
+@pytest.mark.parametrize("alpha,N", [(0.0, 100), (2.0, 24), (12.0, 24), (3.7, 128)])
 @pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-12), (swim.SWIM_F32, 1e-5)])
 def test_pair_velocity(paper, oracle_core, dtype, tol, alpha, N):
     x, y = inputs.filament_geometry(N, 4, n_swim=2, spacing=0.3)
