@@ -36,8 +36,8 @@ struct Run {
 
 // all launchers return hipError_t of the launch
 // (dtype 0 also writes the FP64 constants into sysc64, for the kernel tables)
-// blob: 0 the kernel reading's blob, 1 the paper's blob (alpha = 0 only;
-// batch rows with alpha > 0 get SWIM_ST_BADPARAM)
+// blob: 0 the kernel reading's blob, 1 the paper's blob (closed forms at
+// alpha = 0, quadrature for alpha > 0)
 hipError_t launch_sysconst_batch(int dtype, int64_t n_sys, const int64_t* sw_off, const int32_t* npt,
                                  const double* params, double eps_over_ds, void* sysc, void* sysc64,
                                  int32_t* status, int blob, hipStream_t st);
