@@ -352,7 +352,7 @@ def field_leg(ctx, stream, grid=1024):
     """Flow and pressure picture (Sec. 2.1, eqs. BrV, BrP; Figs. 1 and 3):
     velocity and pressure of two swimmers' point forces (2 x 128 points,
     forces of a bent configuration, alpha = 1) on a grid x grid lattice of
-    targets, FP32 pair kernel evaluated directly (no table), FP64 sums and
+    targets, FP32 pair kernel from the system's table, FP64 sums and
     pressure weights."""
     import torch
     from paper_1910_12007_amd import inputs, swim
@@ -427,6 +427,8 @@ def paper_blob_leg(ctx, stream, Ns, P, steps, dt, obs_every, default_ms):
         ms = timed(1, steps, obs_every, obs)
         f64_paper = timed_f64(1)
         f64_default = timed_f64(0)
+        swim.swim_set_option(ctx, swim.SWIM_OPT_BLOB, swim.SWIM_BLOB_PAPER)
+        field_paper = field_leg(ctx, stream)
     finally:
         swim.swim_set_option(ctx, swim.SWIM_OPT_BLOB, swim.SWIM_BLOB_READING)
     done_h = done.cpu().numpy().astype(np.int64)
@@ -436,6 +438,7 @@ def paper_blob_leg(ctx, stream, Ns, P, steps, dt, obs_every, default_ms):
             "ms": ms, "default_blob_ms": default_ms, "setup_ms": one_paper - one_default,
             "one_step_ms": one_paper, "one_step_default_ms": one_default,
             "pair_evals_per_s": pairs / (ms * 1e-3), "runs_stopped": int((status != 0).sum().item()),
+            "flow_field_ms": field_paper["ms"],
             "fp64_direct": {"workload": f"one FP64 velocity sum of {m} points, alpha = 1, eps = 0.02",
                             "paper_ms": f64_paper, "default_ms": f64_default,
                             "paper_pair_evals_per_s": m * m / (f64_paper * 1e-3),

@@ -177,9 +177,12 @@ int swim_pair_velocity(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const int64_
  * (with SWIM_BLOB_PAPER: m = 1 - eps^3/R^3 for every alpha).
  * x, y, fx, fy device dtype[n]; tx, ty device dtype[nt]; u, v, p device
  * dtype[nt] (written).  alpha >= 0, eps > 0, alpha*eps <= 1.  Sums are
- * accumulated in FP64.  The pair kernel is evaluated in dtype directly
- * (no table; the paper's blob at alpha > 0 in FP64 for both dtypes); the
- * pressure weight is evaluated in FP64.  Asynchronous. */
+ * accumulated in FP64.  FP32 reads the pair kernel from the system's table
+ * (as the forward runs do; built on the device at each call, for the
+ * paper's blob at alpha > 0 from its quadrature), with the direct FP32
+ * evaluation beyond it; FP64 evaluates it directly (the paper's blob at
+ * alpha > 0: quadrature per pair).  The pressure weight is evaluated in
+ * FP64.  Asynchronous. */
 int swim_flow_field(swim_ctx *ctx, int32_t dtype, int64_t n, const void *x, const void *y, const void *fx,
                     const void *fy, double alpha, double eps, int64_t nt, const void *tx, const void *ty,
                     void *u, void *v, void *p, void *stream);

@@ -771,7 +771,25 @@ int swim_flow_field(swim_ctx* c, int32_t dtype, int64_t n, const void* x, const 
         for (int k = 0; k < FIELD_NSER; ++k)
             fc.ser[k] = fc.inv_e2 * (2.0 * (k + 1) * gam[k + 1] - 0.5 * z0 * z0 * gam[k] / (k + 1));
     }
-    HIPCHK(launch_flow_field(dtype, n, x, y, fx, fy, fc, nt, tx, ty, u, v, p, pick(c, stream)));
+    hipStream_t st = pick(c, stream);
+    const void* tab = nullptr;
+    if (dtype == SWIM_F32) {
+        // FP32: the pair kernel from the system's table, as in the forward
+        // runs (built on the device from the FP64 kernel functions; for the
+        // paper's blob at alpha > 0 from its quadrature)
+        TRY(begin_uploads(c, 16));
+        TRY(stage(c, &alpha, 8, B_ALPHA, st));
+        TRY(stage(c, &eps, 8, B_EPS, st));
+        TRY(end_uploads(c, st));
+        void *sysc, *sysc64;
+        TRY(sysconst_buffers(c, SWIM_F32, 1, &sysc, &sysc64));
+        HIPCHK(launch_sysconst(SWIM_F32, 1, (const double*)c->buf[B_ALPHA].p, (const double*)c->buf[B_EPS].p, sysc,
+                               sysc64, c->opt_blob, st));
+        TRY(ensure(c, B_TAB, table_bytes()));
+        HIPCHK(launch_table_build(0, 1, sysc64, c->buf[B_TAB].p, st));
+        tab = c->buf[B_TAB].p;
+    }
+    HIPCHK(launch_flow_field(dtype, n, x, y, fx, fy, fc, nt, tx, ty, u, v, p, tab, st));
     return SWIM_OK;
 }
 

@@ -12,7 +12,8 @@
 // series in delta whose coefficients the host computes per call.
 //
 // One thread per target; the sources pass through LDS in tiles; every sum is
-// accumulated in FP64, the pair kernel is evaluated in the run's precision.
+// accumulated in FP64.  The pair kernel: FP32 from the system's table (as in
+// the forward runs), FP64 by direct evaluation.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -26,15 +27,16 @@ namespace {
 
 constexpr int FIELD_TILE = 1024;
 
+// tab (FP32 only): the system's kernel table, used for every pair inside it;
+// beyond it the direct evaluation (FP64: the direct evaluation throughout)
 template <typename T>
 __global__ __launch_bounds__(256) void k_flow_field(int64_t n, const T* x, const T* y, const T* fx, const T* fy,
                                                     FieldConst fc, int64_t nt, const T* tx, const T* ty, T* u, T* v,
-                                                    T* p)
+                                                    T* p, const TabSys* tab)
 {
     __shared__ Src4<T> tile[FIELD_TILE];
     const SysConst<T> C = *reinterpret_cast<const SysConst<T>*>(sizeof(T) == 4 ? (const void*)&fc.c32
                                                                                    : (const void*)&fc.c64);
-    const bool pbrink = fc.paper && !fc.stokes;
     const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool live = a < nt;
     const double X = live ? (double)tx[a] : 0.0, Y = live ? (double)ty[a] : 0.0;
@@ -57,16 +59,21 @@ __global__ __launch_bounds__(256) void k_flow_field(int64_t n, const T* x, const
             sfy += (double)s.fy;
             const double dxd = X - (double)s.x, dyd = Y - (double)s.y;
             const T dx = (T)dxd, dy = (T)dyd;
-            T Ht, H2;
-            if (sizeof(T) == 4 && pbrink) {
-                // the paper's blob at alpha > 0 has no FP32 closed form: FP64
-                double a, b;
-                kernel_eval<double>(fc.c64, fma(dxd, dxd, dyd * dyd), a, b);
-                Ht = (T)a;
-                H2 = (T)b;
-            } else {
-                kernel_eval<T>(C, fma_t(dx, dx, dy * dy), Ht, H2);
+            T Ht = (T)0, H2 = (T)0;
+            const T t2 = fma_t(dx, dx, dy * dy);
+            bool direct = true;
+            if constexpr (sizeof(T) == 4) {
+                if (tab) {
+                    const uint32_t bits = tab_bits(t2, C.ts);
+                    const uint32_t id = bits >> TAB_SHIFT;
+                    if (id < TAB_END) {
+                        tab_eval(tab->e[id - TAB_BIAS], tab_u(bits), Ht, H2);
+                        H2 *= C.ts;  // the table holds H2 / sigma
+                        direct = false;
+                    }
+                }
             }
+            if (direct) kernel_eval<T>(C, t2, Ht, H2);
             const T fd = fma_t(s.fx, dx, s.fy * dy);
             su += (double)fma_t(Ht, s.fx, H2 * fd * dx);
             sv += (double)fma_t(Ht, s.fy, H2 * fd * dy);
@@ -103,18 +110,18 @@ __global__ __launch_bounds__(256) void k_flow_field(int64_t n, const T* x, const
 
 hipError_t launch_flow_field(int dtype, int64_t n, const void* x, const void* y, const void* fx, const void* fy,
                              const FieldConst& fc, int64_t nt, const void* tx, const void* ty, void* u, void* v,
-                             void* p, hipStream_t st)
+                             void* p, const void* tab, hipStream_t st)
 {
     if (nt == 0) return hipSuccess;
     const unsigned nb = (unsigned)((nt + 255) / 256);
     if (dtype == 0)
         hipLaunchKernelGGL(k_flow_field<float>, dim3(nb), dim3(256), 0, st, n, (const float*)x, (const float*)y,
                            (const float*)fx, (const float*)fy, fc, nt, (const float*)tx, (const float*)ty, (float*)u,
-                           (float*)v, (float*)p);
+                           (float*)v, (float*)p, (const TabSys*)tab);
     else
         hipLaunchKernelGGL(k_flow_field<double>, dim3(nb), dim3(256), 0, st, n, (const double*)x, (const double*)y,
                            (const double*)fx, (const double*)fy, fc, nt, (const double*)tx, (const double*)ty,
-                           (double*)u, (double*)v, (double*)p);
+                           (double*)u, (double*)v, (double*)p, (const TabSys*)nullptr);
     return hipGetLastError();
 }
 
