@@ -282,3 +282,33 @@ def test_graph_replay_rebuilds_quadrature_tables(paper, oracle_core):
             allow = 1e-4 * np.linalg.norm(r - x0) + floor
             print({"alpha": P2[i, 0], "err": err, "allow": allow})
             assert err <= allow
+
+
+@pytest.mark.parametrize("dtype", [swim.SWIM_F64, swim.SWIM_F32])
+def test_edge_cases(paper, oracle_core, dtype):
+    """The paper's blob at alpha > 0: a field of no sources is zero, a field
+    of no targets is a no-op, and at the domain's edge alpha * eps = 1 the
+    velocity still meets its bar."""
+    td = torch.float32 if dtype == swim.SWIM_F32 else torch.float64
+    none = torch.empty(0, dtype=td, device="cuda")
+    tx = torch.linspace(0, 1, 5, dtype=td, device="cuda")
+    u = torch.full((5,), 7.0, dtype=td, device="cuda")
+    v, p = u.clone(), u.clone()
+    swim.swim_flow_field(paper, none, none, none, none, 2.0, 0.05, tx, tx, u, v, p)
+    torch.cuda.synchronize()
+    assert torch.all(u == 0) and torch.all(v == 0) and torch.all(p == 0)
+    swim.swim_flow_field(paper, tx, tx, tx, tx, 2.0, 0.05, none, none, none, none, none)
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(21))
+    pts = [rng.uniform(0, 1, 24), rng.uniform(0, 0.3, 24), rng.normal(size=24), rng.normal(size=24)]
+    npd = np.float32 if dtype == swim.SWIM_F32 else np.float64
+    arr = [a.astype(npd) for a in pts]
+    dev = [torch.from_numpy(a).cuda() for a in arr]
+    ux, uy = torch.empty_like(dev[0]), torch.empty_like(dev[0])
+    swim.swim_pair_velocity(paper, np.array([0, 24]), [20.0], [0.05], *dev, ux, uy)
+    torch.cuda.synchronize()
+    with oracle_core.paper_blob():
+        ox, oy = oracle_core.velocity(*[a.astype(np.float64) for a in arr], 20.0, 0.05)
+    err = rel(np.r_[ux.cpu().double().numpy(), uy.cpu().double().numpy()], np.r_[ox, oy])
+    print({"dtype": dtype, "err": err})
+    assert err <= (1e-12 if dtype == swim.SWIM_F64 else 1e-5)
