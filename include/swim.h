@@ -181,8 +181,9 @@ int swim_pair_velocity(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const int64_
  * (as the forward runs do; built on the device at each call, for the
  * paper's blob at alpha > 0 from its quadrature), with the direct FP32
  * evaluation beyond it; FP64 evaluates it directly (the paper's blob at
- * alpha > 0: quadrature per pair).  The pressure weight is evaluated in
- * FP64.  Asynchronous. */
+ * alpha > 0: quadrature per pair).  The pressure weight m/(2 pi r^2):
+ * FP32 from a second per-call table on the same intervals, FP64 directly.
+ * Sums are FP64 either way.  Asynchronous. */
 int swim_flow_field(swim_ctx *ctx, int32_t dtype, int64_t n, const void *x, const void *y, const void *fx,
                     const void *fy, double alpha, double eps, int64_t nt, const void *tx, const void *ty,
                     void *u, void *v, void *p, void *stream);

@@ -63,7 +63,7 @@ enum BufId {
     B_PARAMS, B_DATA, B_OBS, B_SPEED, B_STATUS, B_DIST, B_TOL, B_ACC, B_BIG,
     B_MLP_ACT, B_MLP_GRAD, B_MLP_BATCH, B_MLP_IDX, B_MLP_CNT,
     B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_TAB, B_DONE, B_W16, B_SIGMA, B_LOGL,
-    B_SP_SW, B_SP_HEAD, B_SP_TAIL, B_SP_G, B_SP_SIG,
+    B_SP_SW, B_SP_HEAD, B_SP_TAIL, B_SP_G, B_SP_SIG, B_WTAB,
     B_NBUF
 };
 
@@ -773,6 +773,7 @@ int swim_flow_field(swim_ctx* c, int32_t dtype, int64_t n, const void* x, const 
     }
     hipStream_t st = pick(c, stream);
     const void* tab = nullptr;
+    void* wtab = nullptr;
     if (dtype == SWIM_F32) {
         // FP32: the pair kernel from the system's table, as in the forward
         // runs (built on the device from the FP64 kernel functions; for the
@@ -788,8 +789,11 @@ int swim_flow_field(swim_ctx* c, int32_t dtype, int64_t n, const void* x, const 
         TRY(ensure(c, B_TAB, table_bytes()));
         HIPCHK(launch_table_build(0, 1, sysc64, c->buf[B_TAB].p, st));
         tab = c->buf[B_TAB].p;
+        // and the pressure weight's table on the same intervals
+        TRY(ensure(c, B_WTAB, (size_t)TAB_N * 16));
+        wtab = c->buf[B_WTAB].p;
     }
-    HIPCHK(launch_flow_field(dtype, n, x, y, fx, fy, fc, nt, tx, ty, u, v, p, tab, st));
+    HIPCHK(launch_flow_field(dtype, n, x, y, fx, fy, fc, nt, tx, ty, u, v, p, tab, wtab, st));
     return SWIM_OK;
 }
 

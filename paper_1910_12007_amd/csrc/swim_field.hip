@@ -27,12 +27,51 @@ namespace {
 
 constexpr int FIELD_TILE = 1024;
 
+// pressure weight m(r) / (2 pi r^2) at t = r^2, in FP64
+__device__ double field_weight(const FieldConst& fc, double t)
+{
+    const double delta = t * fc.inv_e2;
+    if (fc.paper) {
+        // m = 1 - eps^3/R^3:  w = (R^2 + R eps + eps^2) / (2 pi R^3 (R + eps))
+        const double R2 = t + fc.e2, R = sqrt(R2);
+        return fc.inv_2pi * (R2 + R * fc.eps + fc.e2) / (R2 * R * (R + fc.eps));
+    }
+    if (fc.stokes) return fc.inv_2pi / (t + fc.e2);
+    if (delta < 0.25) {
+        double w = fc.ser[FIELD_NSER - 1];
+        for (int q = FIELD_NSER - 2; q >= 0; --q) w = fma(w, delta, fc.ser[q]);
+        return w;
+    }
+    const double R = sqrt(t + fc.e2);
+    double K0, K1, Q;
+    bessel_k01_q_f64(fc.alpha * R, &K0, &K1, &Q);
+    return fc.inv_2pi * (1.0 - fc.eps * K1 / (R * fc.K1e)) / t;
+}
+
+// FP32 table of the pressure weight on the kernel table's intervals of
+// v = 1 + sigma t: the cubic through its FP64 values at the nodes 0, 1/4,
+// 3/4, 1 of each interval (one thread per interval)
+__global__ __launch_bounds__(256) void k_weight_table(FieldConst fc, float4* wt)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= TAB_N) return;
+    const int e = i >> TAB_M, j = i & ((1 << TAB_M) - 1);
+    const double a = ldexp(1.0, e);
+    const double v0 = a * (1.0 + (double)j / (double)(1 << TAB_M)), hv = a / (double)(1 << TAB_M);
+    const double un[4] = {0.0, 0.25, 0.75, 1.0};
+    double f[4];
+    for (int k = 0; k < 4; ++k) f[k] = field_weight(fc, fmax((v0 - 1.0 + hv * un[k]) * fc.c64.its, 1e-300));
+    float c[4];
+    cubic_lobatto(f, ldexp(1.0, -TAB_SHIFT), 1.0, c);
+    wt[i] = make_float4(c[0], c[1], c[2], c[3]);
+}
+
 // tab (FP32 only): the system's kernel table, used for every pair inside it;
 // beyond it the direct evaluation (FP64: the direct evaluation throughout)
 template <typename T>
 __global__ __launch_bounds__(256) void k_flow_field(int64_t n, const T* x, const T* y, const T* fx, const T* fy,
                                                     FieldConst fc, int64_t nt, const T* tx, const T* ty, T* u, T* v,
-                                                    T* p, const TabSys* tab)
+                                                    T* p, const TabSys* tab, const float4* wtab)
 {
     __shared__ Src4<T> tile[FIELD_TILE];
     const SysConst<T> C = *reinterpret_cast<const SysConst<T>*>(sizeof(T) == 4 ? (const void*)&fc.c32
@@ -77,25 +116,24 @@ __global__ __launch_bounds__(256) void k_flow_field(int64_t n, const T* x, const
             const T fd = fma_t(s.fx, dx, s.fy * dy);
             su += (double)fma_t(Ht, s.fx, H2 * fd * dx);
             sv += (double)fma_t(Ht, s.fy, H2 * fd * dy);
-            // pressure weight m(r) / (2 pi r^2) in FP64
+            // pressure weight m(r) / (2 pi r^2): FP32 from the weight table
+            // inside it, else in FP64
             const double t = fma(dxd, dxd, dyd * dyd);
-            const double delta = t * fc.inv_e2;
-            double w;
-            if (fc.paper) {
-                // m = 1 - eps^3/R^3:  w = (R^2 + R eps + eps^2) / (2 pi R^3 (R + eps))
-                const double R2 = t + fc.e2, R = sqrt(R2);
-                w = fc.inv_2pi * (R2 + R * fc.eps + fc.e2) / (R2 * R * (R + fc.eps));
-            } else if (fc.stokes) {
-                w = fc.inv_2pi / (t + fc.e2);
-            } else if (delta < 0.25) {
-                w = fc.ser[FIELD_NSER - 1];
-                for (int q = FIELD_NSER - 2; q >= 0; --q) w = fma(w, delta, fc.ser[q]);
-            } else {
-                const double R = sqrt(t + fc.e2);
-                double K0, K1, Q;
-                bessel_k01_q_f64(fc.alpha * R, &K0, &K1, &Q);
-                w = fc.inv_2pi * (1.0 - fc.eps * K1 / (R * fc.K1e)) / t;
+            double w = 0.0;
+            bool wdirect = true;
+            if constexpr (sizeof(T) == 4) {
+                if (wtab) {
+                    const uint32_t bits = tab_bits(t2, C.ts);
+                    const uint32_t id = bits >> TAB_SHIFT;
+                    if (id < TAB_END) {
+                        const float4 c = wtab[id - TAB_BIAS];
+                        const float uu = tab_u(bits);
+                        w = (double)fmaf(fmaf(fmaf(c.w, uu, c.z), uu, c.y), uu, c.x);
+                        wdirect = false;
+                    }
+                }
             }
+            if (wdirect) w = field_weight(fc, t);
             sp = fma((double)s.fx * dxd + (double)s.fy * dyd, w, sp);
         }
     }
@@ -110,18 +148,20 @@ __global__ __launch_bounds__(256) void k_flow_field(int64_t n, const T* x, const
 
 hipError_t launch_flow_field(int dtype, int64_t n, const void* x, const void* y, const void* fx, const void* fy,
                              const FieldConst& fc, int64_t nt, const void* tx, const void* ty, void* u, void* v,
-                             void* p, const void* tab, hipStream_t st)
+                             void* p, const void* tab, void* wtab, hipStream_t st)
 {
     if (nt == 0) return hipSuccess;
+    if (wtab) hipLaunchKernelGGL(k_weight_table, dim3((TAB_N + 255) / 256), dim3(256), 0, st, fc, (float4*)wtab);
     const unsigned nb = (unsigned)((nt + 255) / 256);
     if (dtype == 0)
         hipLaunchKernelGGL(k_flow_field<float>, dim3(nb), dim3(256), 0, st, n, (const float*)x, (const float*)y,
                            (const float*)fx, (const float*)fy, fc, nt, (const float*)tx, (const float*)ty, (float*)u,
-                           (float*)v, (float*)p, (const TabSys*)tab);
+                           (float*)v, (float*)p, (const TabSys*)tab, (const float4*)wtab);
     else
         hipLaunchKernelGGL(k_flow_field<double>, dim3(nb), dim3(256), 0, st, n, (const double*)x, (const double*)y,
                            (const double*)fx, (const double*)fy, fc, nt, (const double*)tx, (const double*)ty,
-                           (double*)u, (double*)v, (double*)p, (const TabSys*)nullptr);
+                           (double*)u, (double*)v, (double*)p, (const TabSys*)nullptr,
+                           (const float4*)nullptr);
     return hipGetLastError();
 }
 

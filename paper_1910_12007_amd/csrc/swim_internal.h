@@ -193,6 +193,6 @@ struct FieldConst {
 };
 hipError_t launch_flow_field(int dtype, int64_t n, const void* x, const void* y, const void* fx, const void* fy,
                              const FieldConst& fc, int64_t nt, const void* tx, const void* ty, void* u, void* v,
-                             void* p, const void* tab, hipStream_t st);
+                             void* p, const void* tab, void* wtab, hipStream_t st);
 
 }  // namespace swim
