@@ -148,3 +148,23 @@ def test_brinkman_far_field_is_that_of_a_point_force(alpha):
     for k in range(2):
         ratio = dev[0][k] / dev[1][k]
         assert np.all((ratio > 3.8) & (ratio < 4.25)), ratio
+
+
+@pytest.mark.parametrize("alpha", [1e-4, 0.01, 1.0, 10.0])
+def test_brinkman_far_field_matches_the_other_blob(alpha):
+    """Far from the blob (r >= 2^13 eps) the paper blob's kernel equals that
+    of the oracle's other blob up to the constant difference of their H1(0),
+    within 2 (eps/r)^2 of a pair's contribution |Ht| + t |H2|: the reading
+    behind the FP32 path's direct evaluation beyond its table (r > 2^21 eps,
+    where the bound is below 1e-12)."""
+    for eps in (0.0118, 0.003):
+        r = eps * 2.0 ** np.array([13.0, 14.0, 16.0, 20.0])
+        t = np.r_[0.0, r * r]
+        with core.paper_blob():
+            P1, P2 = core.kernel(alpha, eps, t)
+        R1, R2 = core.kernel(alpha, eps, t)
+        ht = P1[1:] - P1[0]
+        sc = np.maximum(np.abs(ht) + np.abs(t[1:] * P2[1:]), 1 / (8 * np.pi))
+        d1 = np.abs(ht - (R1[1:] - P1[0])) / sc
+        d2 = np.abs(P2[1:] - R2[1:]) * t[1:] / sc
+        assert np.all(d1 <= 2 * (eps / r) ** 2) and np.all(d2 <= 2 * (eps / r) ** 2), (alpha, eps, d1, d2)
