@@ -312,3 +312,43 @@ def test_edge_cases(paper, oracle_core, dtype):
     err = rel(np.r_[ux.cpu().double().numpy(), uy.cpu().double().numpy()], np.r_[ox, oy])
     print({"dtype": dtype, "err": err})
     assert err <= (1e-12 if dtype == swim.SWIM_F64 else 1e-5)
+
+
+def test_tmcmc_sperm_run_fp32(paper):
+    """TMCMC over a small sperm model with the paper's blob at alpha > 0,
+    FP32: every chain step relaunches the forward runs, whose set-up (g(0)
+    and the quadrature-built tables) follows each sample's alpha.  The data
+    come from an FP64 run at alpha = 1 plus 2 % noise.  The run completes
+    with samples inside the prior box, finite likelihoods and evidence, and
+    a posterior on alpha that covers the truth.  (The oracle, integrating
+    every pair, is too slow for the hundreds of runs a TMCMC run takes.)"""
+    nf, nh, steps, dt, oe = 12, 8, 60, 1e-5, 20
+    shape = swim.sperm_shape(nf, nh, 1, 0.09, 0.05, 1.0 / 11)
+    row = inputs.sperm_rows(1, alpha=1.0, KC=5.0)
+    sw = inputs.sperm_swimmers(1)
+    head = torch.empty((1, steps // oe + 1, 2), dtype=torch.float64, device="cuda")
+    tail = torch.empty_like(head)
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    swim.swim_sperm_forward(paper, swim.SWIM_F64, shape, torch.from_numpy(row).cuda(), torch.from_numpy(sw).cuda(),
+                            steps, dt, oe, head, tail, st)
+    g = torch.empty((1, steps // oe, 2), dtype=torch.float64, device="cuda")
+    swim.swim_sperm_observables(paper, swim.SWIM_F64, swim.SWIM_OBS_HEAD_VELOCITY, 1, oe * dt, head, tail, st, g)
+    torch.cuda.synchronize()
+    assert st.item() == 0
+    xi = g.cpu().numpy()[0]
+    beta = [abs(xi.mean())] * 2
+    rng = np.random.Generator(np.random.PCG64(9))
+    data = xi + 0.02 * beta[0] * rng.normal(size=xi.shape)
+    m = swim.sperm_model(shape, row[0], ("alpha",), 1, swim.SWIM_OBS_HEAD_VELOCITY, beta, steps, oe, dt,
+                         swim.SWIM_F32)
+    lo, hi = [0.0, 0.001], [2.0, 0.2]
+    got = swim.tmcmc_sperm_run(paper, m, sw, lo, hi, data, 128, 77, max_stages=12)
+    th = got["theta"]
+    print({"stages": got["n_stages"], "runs": got["runs"], "log_evidence": got["log_evidence"],
+           "mean": th.mean(0), "std": th.std(0)})
+    assert got["n_stages"] >= 1 and np.isfinite(got["log_evidence"])
+    assert np.all(np.isfinite(got["logl"]))
+    assert np.all(th >= np.array(lo)) and np.all(th <= np.array(hi))
+    a = th[:, 0]
+    assert a.min() <= 1.0 <= a.max()
+    assert abs(a.mean() - 1.0) <= 4 * a.std() + 0.05
