@@ -255,11 +255,13 @@ __global__ void k_sysconst_batch(int64_t n, const int64_t* sw_off, const int32_t
 
 // FP32 kernel tables of systems [s0, s0 + n), one thread per interval; the
 // FP64 evaluation's registers stay out of the kernels that use the tables
-// One wave per TAB_CHUNK consecutive intervals of one system: lane l < 63
-// evaluates nodes 0, 1/4, 3/4 of interval c * 63 + l and takes node 1 (the
-// next interval's node 0) from lane l + 1; lane 63 evaluates only that node
-// for lane 62.  Three kernel evaluations per entry instead of four.
-constexpr int TAB_CHUNK = 63;
+// One wave per TAB_CHUNK = 21 consecutive intervals of one system, one FP64
+// kernel value per lane: lanes 3j, 3j + 1, 3j + 2 evaluate the nodes 0, 1/4,
+// 3/4 of interval j, lane 63 the end of interval 20 (the next chunk's first
+// node); lane 3j gathers the interval's four values (its node 1 is the next
+// interval's node 0, at exactly the same t) and writes the entry.  Three
+// kernel values per entry, each on its own lane.
+constexpr int TAB_CHUNK = 21;
 constexpr int TAB_WAVES = (TAB_N + 1 + TAB_CHUNK - 1) / TAB_CHUNK;  // waves per system
 
 __global__ __launch_bounds__(64) void k_table_build(int64_t s0, int64_t n, const SysConst<double>* sysc64, TabSys* tab)
@@ -267,26 +269,27 @@ __global__ __launch_bounds__(64) void k_table_build(int64_t s0, int64_t n, const
     const int64_t w = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t s = s0 + w / TAB_WAVES;
-    const int i = (int)(w % TAB_WAVES) * TAB_CHUNK + lane;  // interval (lane < 63) or end node (lane 63)
-    const bool live = w < n * TAB_WAVES && i <= TAB_N;
-    double fh[4] = {0.0, 0.0, 0.0, 0.0}, fg[4] = {0.0, 0.0, 0.0, 0.0};
-    if (live) {
-        const SysConst<double>& C = sysc64[s];
-        tab_node(C, i, 0, fh[0], fg[0]);
-        if (lane < TAB_CHUNK && i < TAB_N) {
-            tab_node(C, i, 1, fh[1], fg[1]);
-            tab_node(C, i, 2, fh[2], fg[2]);
-        }
-    }
+    const int j = lane < 3 * TAB_CHUNK ? lane / 3 : TAB_CHUNK, k = lane < 3 * TAB_CHUNK ? lane % 3 : 0;
+    const int i = (int)(w % TAB_WAVES) * TAB_CHUNK + j;  // interval, or the end node (lane 63)
+    const bool live = w < n * TAB_WAVES && i <= TAB_N && (k == 0 || i < TAB_N);
+    double fh = 0.0, fg = 0.0;
+    if (live) tab_node(sysc64[s], i, k, fh, fg);
     // every lane of the wave takes part in the shuffles
-    fh[3] = __shfl_down(fh[0], 1);
-    fg[3] = __shfl_down(fg[0], 1);
-    if (!live || lane == TAB_CHUNK) return;
+    double h[4], g[4];
+    h[0] = fh;
+    g[0] = fg;
+#pragma unroll
+    for (int d = 1; d < 4; ++d) {
+        const int src = min(lane + d, 63);
+        h[d] = __shfl(fh, src);
+        g[d] = __shfl(fg, src);
+    }
+    if (!live || k != 0 || lane >= 3 * TAB_CHUNK) return;
     if (i == TAB_N) {
         tab_interval(sysc64[s], i, tab[s].e[i], &tab[s].h0lo[i]);  // the zero entry
         return;
     }
-    tab_assemble(sysc64[s], fh, fg, tab[s].e[i], &tab[s].h0lo[i]);
+    tab_assemble(sysc64[s], h, g, tab[s].e[i], &tab[s].h0lo[i]);
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
