@@ -359,13 +359,14 @@ SWIM_HD double pb_i0x(double x, double z, double enz)
 
 // Panel rule: widest panel in u and the cut-off exponent.  The direct FP64
 // evaluation takes (1/2, 42): ~1e-15 relative.  The FP32 tables, whose
-// cubic pieces are good to ~1e-7, are built with (1, 30): ~1e-12, at
-// about half the panels.
+// cubic pieces are good to ~1e-7, are built with (3/2, 26): 10-point rules
+// on panels 3/4 wide in half-width against poles pi/2 off the axis leave
+// ~1e-13, the cut-off e^-26 ~5e-12, at about a third of the panels.
 struct PbRule {
     double du, cut;
 };
 constexpr PbRule PB_EXACT = {0.5, 42.0};
-constexpr PbRule PB_TABLE = {1.0, 30.0};
+constexpr PbRule PB_TABLE = {1.5, 26.0};
 
 // exp(alpha r) int_{u0}^inf (3/2pi) sinh u/cosh^4 u K0(alpha eps sinh u) du
 SWIM_HD double pb_outer(double alpha, double eps, double r, double u0, PbRule q = PB_EXACT)
