@@ -81,3 +81,63 @@ def test_bf16_network_close_to_fp64_network():
     y16 = mlp.forward(P, X, True)[0]
     y64 = mlp.forward(P, X, False)[0]
     assert np.linalg.norm(y16 - y64) / np.linalg.norm(y64) < 2e-2
+
+
+def _torch_forward(P, X, bf16_ops):
+    """Independent float64 reference of the network: torch's F.linear per
+    layer (y = x W^T + b with W stored out x in), the exact-erf GELU on the
+    hidden layers only, a linear output layer.  With bf16_ops the GEMM
+    operands go through torch's own bfloat16 conversion."""
+    import torch.nn.functional as F
+
+    def op(a):
+        t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+        return t.float().to(torch.bfloat16).double() if bf16_ops else t
+
+    h = torch.from_numpy(np.asarray(X, dtype=np.float64))
+    for l, (W, b) in enumerate(P):
+        h = F.linear(op(h.numpy()), op(np.ascontiguousarray(W.T)), torch.from_numpy(b))
+        if l < len(P) - 1:
+            h = F.gelu(h, approximate="none")
+    return h.numpy()
+
+
+@pytest.mark.parametrize("layers", [(5, 7, 3), (5, 256, 256, 256, 256, 33), (5, 40, 9, 40, 2)])
+@pytest.mark.parametrize("bf16_ops", [False, True])
+def test_forward_matches_torch_reference(layers, bf16_ops):
+    """oracle mlp.forward against torch's layer primitives, non-square layers
+    included (a transposed weight would not even multiply), to 1e-13."""
+    P = _params(11, layers)
+    rng = np.random.Generator(np.random.PCG64(12))
+    X = rng.standard_normal((33, 5)) * 2.0
+    got = mlp.forward(P, X, bf16_ops)[0]
+    ref = _torch_forward(P, X, bf16_ops)
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def _planted(kind):
+    """Copies of mlp.forward with one plausible mistake each."""
+    def fwd(params, X):
+        h = np.asarray(X, dtype=np.float64)
+        for l, (W, b) in enumerate(params):
+            Wm = W.T if kind == "transposed" else W
+            a = h @ Wm + (0.0 if kind == "no_bias" else b)
+            if l < len(params) - 1 or kind == "gelu_on_output":
+                h = mlp.gelu(a)
+            else:
+                h = a
+        return h
+    return fwd
+
+
+@pytest.mark.parametrize("kind", ["gelu_on_output", "no_bias", "transposed"])
+def test_forward_pin_catches_planted_mistakes(kind):
+    """The torch reference separates the oracle's composition from each
+    planted mistake (square layers, so the transposed weight still runs)."""
+    P = _params(13, (5, 5, 5, 5))
+    rng = np.random.Generator(np.random.PCG64(14))
+    X = rng.standard_normal((17, 5))
+    ref = _torch_forward(P, X, False)
+    assert np.linalg.norm(mlp.forward(P, X, False)[0] - ref) <= 1e-13 * np.linalg.norm(ref)
+    bad = _planted(kind)(P, X)
+    assert np.linalg.norm(bad - ref) > 1e-3 * np.linalg.norm(ref)
