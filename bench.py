@@ -3,8 +3,10 @@
 Workload ("batch"): 4096 ABC parameter sets drawn from the uniform prior
 alpha in [0, 10], S_b in [0.01, 1], S_s in [1e2, 1e4] (Philox seed 1); every
 swimmer has N = 128 points and runs 5000 forward-Euler steps of dt = 5e-5,
-its head observed every 100 steps; FP32.  One bench step is one pass of the
-hot path over that batch: preferred curvature, elastic forces, dense
+its head observed every 100 steps; FP32; the paper's blob (eq. eqnblob, the
+library's default).  One bench step is one pass of the hot path over that
+batch: the per-system set-up (constants and the FP32 kernel tables of the
+paper's blob), then preferred curvature, elastic forces, dense
 regularized-Brinkmanlet velocity sum, Euler update and observations for all
 4096 swimmers (one persistent kernel), then the ABC distances against the
 observed data, the 5th-percentile tolerance and the accept mask.  Inputs are
@@ -27,18 +29,22 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Roofline of the dominant kernel (the persistent forward kernel).  Its pair
-# phase reads the kernel functions from a per-system table and evaluates
-# every distinct pair once per step for both of its points (symmetric
-# schedule), so it is bound by VALU instruction issue, not by FP32 FLOP:
-# 33 VALU lane-operations per distinct pair in the k_forward<float, 2, 16>
-# hot loop (loop control included), i.e. 16.5 per ordered pair evaluation;
-# 42 FP32 FLOP (FMA = 2) per distinct pair, 21 per ordered pair.  Peak issue
-# rate without packed FP32: 256 CUs x 4 SIMDs x 16 lanes per clock x
-# 2.4 GHz = 39.3e12 lane-operations/s (x 2 = 78.6 TFLOP/s of FMA; the
-# 157.3 TFLOP/s FP32 figure assumes packed FP32).
+# Roofline of the dominant kernel (the persistent forward kernel), in FP32
+# FLOP against the FP32 vector peak of 157.3 TFLOP/s.  Algorithmic work per
+# ordered pair evaluation of eq. (BrV) in its FP32 form: per distinct pair
+# (one evaluation serves both ends, symmetric schedule) the difference
+# vector (2), v = |d|^2 + 1 (2 FMA), the two cubics of the table (6 FMA),
+# and for each end F.d times H2 (MUL, FMA, MUL) and the two accumulations
+# (4 FMA): 42 FLOP (FMA = 2) per distinct pair, 21 per ordered pair.  The
+# kernel is bound by VALU instruction issue, not FLOP: integer and float
+# operations share the issue slots, 33 VALU lane-operations per distinct
+# pair in the k_forward<float, 2, 16> hot loop (loop control included),
+# 16.5 per ordered pair; the issue peak without packed FP32 is 256 CUs x 4
+# SIMDs x 16 lanes per clock x 2.4 GHz = 39.3e12 lane-operations/s, i.e.
+# 78.6 TFLOP/s of FMA (the build keeps packed FP32 off).
 VALU_OPS_PER_PAIR = 16.5
 FP32_FLOP_PER_PAIR = 21
+NONPACKED_FP32_PEAK_TFLOPS = 78.6
 # the large-system kernel k_big_step<float, 1> (one target per lane, FP64
 # accumulation): 76 VALU per unrolled iteration of two pairs, loop control
 # included
@@ -59,21 +65,76 @@ def load_data():
     return a[:, :2]
 
 
+def cpu_model():
+    """The host CPU model (lscpu), or the platform's processor string."""
+    import platform
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(steps_cpu):
-    """The FP64 oracle timed on the host cores for one swimmer of the same
-    workload (true parameters, N = 128) over steps_cpu steps."""
+    """The FP64 oracle as it stands, timed on the host cores on bounded
+    samples of the workloads (its paper-blob kernel integrates every pair at
+    alpha > 0, about 1 ms per pair on one core):
+      batch  one swimmer of the batched workload at the data's parameters
+             (alpha = 2), N = 128, the paper's blob, steps_cpu of its 5000
+             steps, all threads: the reported value;
+      single the single-swimmer workload on one core: N = 64, alpha = 1
+             (quadrature) for 3 of its 2000 steps (extrapolated to 2000),
+             and alpha = 0 (closed forms) in full;
+      dense  one velocity evaluation of the dense workload's sample 0
+             (8 x 512 points, its alpha), at 32 of its 4096 targets, all
+             threads.
+    The batched workload's 64-particle subset (5000 steps each) would take
+    about 5e9 pair quadratures, days on these cores: the batch sample's rate
+    stands for it."""
     from oracle import core
     from paper_1910_12007_amd import inputs
-    P = inputs.theta_rows(inputs.TRUE_THETA)
     core.lib()
+    threads = core.num_threads()
+    out = {"kind": "oracle", "cores": threads, "cpu_model": cpu_model(), "legs": {}}
+    P = inputs.theta_rows(inputs.TRUE_THETA)
     t0 = time.perf_counter()
     core.forward(P, 128, steps_cpu, 5e-5, 100)
-    dt = time.perf_counter() - t0
-    pairs = 128 * 128 * steps_cpu
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": pairs / dt, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 swimmer (true alpha, S_b, S_s), N=128, {steps_cpu} of 5000 steps, FP64, "
-                      f"{dt:.1f} s"}
+    sec = time.perf_counter() - t0
+    out["value"] = 128 * 128 * steps_cpu / sec
+    out["unit"] = "pair-evals/s"
+    out["sample"] = (f"1 swimmer of the batched workload (alpha, S_b, S_s = 2, 0.1, 1e3), N=128, paper's blob, "
+                     f"{steps_cpu} of 5000 steps, FP64, {sec:.1f} s on {threads} threads")
+    core.set_threads(1)
+    try:
+        single = {}
+        for alpha, k in ((1.0, 3), (0.0, 2000)):
+            Ps = inputs.param_rows(1, alpha=alpha)
+            t0 = time.perf_counter()
+            core.forward(Ps, 64, k, 1e-4, 100)
+            sec = time.perf_counter() - t0
+            single[f"alpha_{alpha:g}"] = {"steps": k, "seconds": sec, "pair_evals_per_s": 64 * 64 * k / sec,
+                                          "run_2000_steps_s_extrapolated": sec * 2000 / k}
+        out["legs"]["single_1_core"] = single
+    finally:
+        core.set_threads(threads)
+    lay = inputs.dense_layout(n_samples=1, seed=3)[0]
+    x = np.concatenate([lay[m, 7] + np.arange(512) / 511.0 for m in range(8)])
+    y = np.concatenate([np.full(512, lay[m, 8]) for m in range(8)])
+    F = [core.forces(x[512 * m:512 * (m + 1)], y[512 * m:512 * (m + 1)], lay[m, 1], lay[m, 2],
+                     core.kappa0(512, lay[m, 3], lay[m, 5], lay[m, 4], lay[m, 6], 0.0)) for m in range(8)]
+    fx, fy = np.concatenate([f[0] for f in F]), np.concatenate([f[1] for f in F])
+    idx = np.arange(0, 4096, 128)
+    t0 = time.perf_counter()
+    core.velocity_at(x, y, fx, fy, lay[0, 0], 1.5 / 511, idx)
+    sec = time.perf_counter() - t0
+    out["legs"]["dense_sample0"] = {"targets": int(idx.size), "sources": 4096, "alpha": float(lay[0, 0]),
+                                    "seconds": sec, "pair_evals_per_s": idx.size * 4096 / sec,
+                                    "one_step_s_extrapolated": sec * 4096 / idx.size}
+    return out
 
 
 # weights of the surrogate MLP 5 -> 256 x 4 -> 33 (multiply-adds per row)
@@ -151,8 +212,10 @@ def dense_leg(ctx, stream, samples=64, steps=1000):
                        f"dt=2e-5/32 (stability), FP32, per-step large-system kernel",
            "ms": ms, "pair_evals_per_s": pairs / (ms * 1e-3), "swimmer_steps_per_s": float(np.sum(d)) * 8 / (ms * 1e-3),
            "runs_stopped": int(np.sum(status.cpu().numpy() != 0)),
+           "fp32_tflops": FP32_FLOP_PER_PAIR * pairs / (ms * 1e-3) / 1e12,
+           "fp32_frac": FP32_FLOP_PER_PAIR * pairs / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
            "valu_tops": VALU_OPS_PER_PAIR_BIG * pairs / (ms * 1e-3) / 1e12, "valu_peak_tops": VALU_PEAK_TOPS,
-           "valu_frac": VALU_OPS_PER_PAIR_BIG * pairs / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+           "valu_issue_frac": VALU_OPS_PER_PAIR_BIG * pairs / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
            "valu_ops_per_pair": VALU_OPS_PER_PAIR_BIG}
     return out
 
@@ -291,15 +354,17 @@ def sperm_leg(ctx, stream, n=2000, steps=20000, dt=1e-5):
         st = status.cpu().numpy()
         pairs = float(n) * npts * npts * steps
         tops = VALU_OPS_PER_PAIR * pairs / (ms * 1e-3) / 1e12
+        tflops = FP32_FLOP_PER_PAIR * pairs / (ms * 1e-3) / 1e12
         out[f"{n_swim}_swimmer" + ("s" if n_swim > 1 else "")] = {
             "points_per_system": npts, "ms": ms, "us_per_step": 1e3 * ms / steps,
             "pair_evals_per_s": pairs / (ms * 1e-3), "swimmer_steps_per_s": float(n) * n_swim * steps / (ms * 1e-3),
             "runs_stopped": int(np.sum(st != 0)),
             "stage_seconds_to_T20": ms * 1e-3 * (20 / dt) / steps,
-            "roofline": {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS,
-                         "unit": "TOP/s (VALU lane-operations)", "frac": tops / VALU_PEAK_TOPS,
+            "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tflops / FP32_PEAK_TFLOPS,
                          "kernel": "k_sperm_forward<float,%d,2>" % (1 if npts <= 64 else 2 if npts <= 128 else 3),
-                         "valu_ops_per_pair": VALU_OPS_PER_PAIR}}
+                         "fp32_flop_per_pair": FP32_FLOP_PER_PAIR, "valu_ops_per_pair": VALU_OPS_PER_PAIR,
+                         "valu_issue_frac": tops / VALU_PEAK_TOPS}}
     return out
 
 
@@ -378,12 +443,14 @@ def field_leg(ctx, stream, grid=1024):
             "ms": ms, "target_source_pairs_per_s": pairs / (ms * 1e-3)}
 
 
-def paper_blob_leg(ctx, stream, Ns, P, steps, dt, obs_every, default_ms):
-    """The headline generation with the paper's blob (eq. eqnblob) at the
-    same prior draws (alpha > 0 for all of them): the per-system set-up now
-    integrates g(0) and builds every FP32 table from the FP64 quadrature,
-    the run itself reads the tables as before.  Set-up cost = a one-step
-    run with this blob minus a one-step run with the default blob."""
+def reading_blob_leg(ctx, stream, Ns, P, steps, dt, obs_every, paper_ms):
+    """The headline generation with the other blob of the library, the
+    reading's unit-mass blob (closed forms for every alpha), at the same
+    prior draws, for comparison with the default (the paper's blob, eq.
+    eqnblob).  Both read per-system FP32 tables, so a run step costs the
+    same; the difference is the per-system set-up: a one-step run with each
+    blob.  Also the FP64 direct evaluation with each blob (the paper's
+    integrates every pair: a reference mode)."""
     import torch
     from paper_1910_12007_amd import swim
     n = len(Ns)
@@ -402,8 +469,6 @@ def paper_blob_leg(ctx, stream, Ns, P, steps, dt, obs_every, default_ms):
         torch.cuda.synchronize()
         return ev[0].elapsed_time(ev[1])
 
-    # FP64 direct evaluation (the reference mode): one velocity sum of a
-    # 512-point system, alpha = 1, with each blob
     m = 512
     rng = np.random.Generator(np.random.PCG64(11))
     pts = [torch.from_numpy(a).to("cuda") for a in (rng.uniform(0, 1, m), rng.uniform(0, 0.3, m),
@@ -421,28 +486,25 @@ def paper_blob_leg(ctx, stream, Ns, P, steps, dt, obs_every, default_ms):
         return ev[0].elapsed_time(ev[1])
 
     try:
-        timed(1, 1, 1, one)  # warm-up
-        one_paper = min(timed(1, 1, 1, one) for _ in range(2))
-        one_default = min(timed(0, 1, 1, one) for _ in range(2))
-        ms = timed(1, steps, obs_every, obs)
-        f64_paper = timed_f64(1)
-        f64_default = timed_f64(0)
-        swim.swim_set_option(ctx, swim.SWIM_OPT_BLOB, swim.SWIM_BLOB_PAPER)
-        field_paper = field_leg(ctx, stream)
+        timed(swim.SWIM_BLOB_READING, 1, 1, one)  # warm-up
+        one_reading = min(timed(swim.SWIM_BLOB_READING, 1, 1, one) for _ in range(2))
+        one_paper = min(timed(swim.SWIM_BLOB_PAPER, 1, 1, one) for _ in range(2))
+        ms = timed(swim.SWIM_BLOB_READING, steps, obs_every, obs)
+        f64_paper = timed_f64(swim.SWIM_BLOB_PAPER)
+        f64_reading = timed_f64(swim.SWIM_BLOB_READING)
     finally:
-        swim.swim_set_option(ctx, swim.SWIM_OPT_BLOB, swim.SWIM_BLOB_READING)
+        swim.swim_set_option(ctx, swim.SWIM_OPT_BLOB, swim.SWIM_BLOB_PAPER)
     done_h = done.cpu().numpy().astype(np.int64)
     pairs = float(np.sum(done_h * Ns.astype(np.int64) ** 2))
     return {"workload": f"the headline generation ({n} prior draws, N={int(Ns[0])}, {steps} steps) with the "
-                        "paper's blob, alpha > 0 (quadrature-built FP32 tables)",
-            "ms": ms, "default_blob_ms": default_ms, "setup_ms": one_paper - one_default,
-            "one_step_ms": one_paper, "one_step_default_ms": one_default,
+                        "reading's blob (closed forms)",
+            "ms": ms, "paper_blob_ms": paper_ms, "one_step_ms": one_reading, "one_step_paper_ms": one_paper,
+            "paper_setup_extra_ms": one_paper - one_reading,
             "pair_evals_per_s": pairs / (ms * 1e-3), "runs_stopped": int((status != 0).sum().item()),
-            "flow_field_ms": field_paper["ms"],
             "fp64_direct": {"workload": f"one FP64 velocity sum of {m} points, alpha = 1, eps = 0.02",
-                            "paper_ms": f64_paper, "default_ms": f64_default,
+                            "paper_ms": f64_paper, "reading_ms": f64_reading,
                             "paper_pair_evals_per_s": m * m / (f64_paper * 1e-3),
-                            "default_pair_evals_per_s": m * m / (f64_default * 1e-3)}}
+                            "reading_pair_evals_per_s": m * m / (f64_reading * 1e-3)}}
 
 
 def surrogate_leg(ctx, data):
@@ -476,7 +538,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--euler-steps", type=int, default=5000)
-    ap.add_argument("--cpu-steps", type=int, default=1200)
+    ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--wps", type=int, default=0, help="waves per system (0: library default)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-prescreened ABC comparison")
@@ -554,7 +616,23 @@ def main():
     fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     n_acc = int(acc.sum().item())
     st = status.cpu().numpy()
-    achieved = VALU_OPS_PER_PAIR * pairs / (fwd_ms * 1e-3) / 1e12
+    # the forward call = per-system set-up + the persistent kernel; the
+    # set-up is the time of a one-step call of the same layout (its one step
+    # adds ~3 us), so the kernel's launch time is the difference
+    one = torch.empty((n, 1, 2), dtype=torch.float32, device="cuda")
+    sp1, st1 = torch.empty_like(speed), torch.empty_like(status)
+    setup = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        swim.swim_forward(ctx, Ns, None, P, 1, dt, 1, 1.5, one, sp1, st1, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        setup.append(a.elapsed_time(b))
+    setup_ms = float(np.median(setup))
+    kernel_ms = fwd_ms - setup_ms
+    tflops = FP32_FLOP_PER_PAIR * pairs / (kernel_ms * 1e-3) / 1e12
+    issue = VALU_OPS_PER_PAIR * pairs / (kernel_ms * 1e-3) / 1e12
     out = {
         "metric": "swimmer steps/s & Brinkmanlet pair-evals/s; ABC accepts/s surrogate vs plain",
         "value": pairs * args.steps / wall,
@@ -568,23 +646,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"batched ABC forward generation: {n} prior draws, N={N}, {steps} Euler steps "
-                               f"dt={dt}, head every {obs_every} steps, RMS distance, 5th-percentile tolerance",
-                   "particles": n, "N": N, "euler_steps": steps},
+        "config": {"workload": f"batched ABC forward generation with the paper's blob (eq. eqnblob): {n} prior "
+                               f"draws, N={N}, {steps} Euler steps dt={dt}, head every {obs_every} steps, RMS "
+                               "distance, 5th-percentile tolerance",
+                   "particles": n, "N": N, "euler_steps": steps, "blob": "paper (eq. eqnblob)"},
         "swimmer_steps_per_s": swimmer_steps * args.steps / wall,
         "abc_accepts_per_s": n_acc * args.steps / wall,
         "abc_accepted": n_acc,
         "abc_tolerance": tol.item(),
         "runs_stopped": int(np.sum(st != 0)),
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TOP/s (VALU lane-operations)", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": TRAFFIC_BYTES,
-                     "kernel": "k_forward<float,2,16> (persistent forward run)", "kernel_ms": fwd_ms,
-                     "valu_ops_per_pair": VALU_OPS_PER_PAIR, "fp32_flop_per_pair": FP32_FLOP_PER_PAIR,
-                     "fp32_tflops": FP32_FLOP_PER_PAIR * pairs / (fwd_ms * 1e-3) / 1e12,
-                     "fp32_peak_tflops": FP32_PEAK_TFLOPS},
+        "forward_call_ms": fwd_ms, "setup_ms": setup_ms,
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP32_PEAK_TFLOPS, "traffic": TRAFFIC_BYTES,
+                     "kernel": "k_forward<float,2,16> (persistent forward run)", "kernel_ms": kernel_ms,
+                     "fp32_flop_per_pair": FP32_FLOP_PER_PAIR, "pair_evals_per_launch": pairs,
+                     "nonpacked_fp32_peak_tflops": NONPACKED_FP32_PEAK_TFLOPS,
+                     "frac_of_nonpacked": tflops / NONPACKED_FP32_PEAK_TFLOPS,
+                     "valu_ops_per_pair": VALU_OPS_PER_PAIR, "valu_issue_tops": issue,
+                     "valu_issue_peak_tops": VALU_PEAK_TOPS, "valu_issue_frac": issue / VALU_PEAK_TOPS},
     }
-    out["paper_blob"] = paper_blob_leg(ctx, stream, Ns, P, steps, dt, obs_every, fwd_ms)
+    out["reading_blob"] = reading_blob_leg(ctx, stream, Ns, P, steps, dt, obs_every, fwd_ms)
     out["surrogate_mfma"] = mlp_leg(ctx, stream)
     out["fused_vs_per_sample"] = per_sample_leg(ctx, stream, P)
     if not args.no_dense:

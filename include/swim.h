@@ -29,6 +29,10 @@
  *     float or double accordingly.
  *   - Calls taking a stream are asynchronous on that hipStream_t (NULL = the
  *     context's stream); calls documented as synchronous wait for their work.
+ *     The context's workspace is shared by all its calls: a call on another
+ *     stream than the previous call first makes its stream wait for the work
+ *     enqueued on that previous stream (so keep a stream alive until a later
+ *     call has run on another one).
  *   - A context is not thread-safe: use one per host thread.
  *   - Per-sample numerical failure (blow-up of the explicit scheme) is a
  *     status value, not an error.
@@ -83,8 +87,10 @@ int swim_version(void);
 /* Launch options of a context (the autotuner sets the first two):
  *   SWIM_OPT_WPS     wavefronts that share one system in the persistent
  *                    kernel, splitting its pair work: 0 (automatic), 1, 2,
- *                    4, 8, 16 (raised to 2 for systems above 256 points,
- *                    reduced when the partial sums would not fit LDS);
+ *                    4, 8, 16 (reduced when the partial sums would not fit
+ *                    LDS).  Systems above 256 points need at least 2: a
+ *                    forward call with 1 and such a system fails with
+ *                    SWIM_EINVAL (the automatic choice never takes 1 there);
  *   SWIM_OPT_BIG_TPL targets per lane of the large-system kernel:
  *                    0 (automatic), 1, 2, 4;
  *   SWIM_OPT_GRAPH   forward runs as a captured hipGraph: 0 never (eager
@@ -95,12 +101,12 @@ int swim_version(void);
  *                    Parameter values may change between replays: they are
  *                    uploaded before the graph runs.
  *   SWIM_OPT_BLOB    the regularization blob of the velocity kernel:
- *                    SWIM_BLOB_READING (default), the unit-mass blob
+ *                    SWIM_BLOB_PAPER (default), the blob of eq. (eqnblob),
+ *                    or SWIM_BLOB_READING, the unit-mass blob
  *                    c eps^2/(2 pi) [alpha^2 K0(alpha R)/R^2 + 2 alpha
  *                    K1(alpha R)/R^3] (eps^2/(pi R^4) at alpha = 0), whose
- *                    Brinkmanlet has a closed form for every alpha; or
- *                    SWIM_BLOB_PAPER, the blob of eq. (eqnblob).  Its
- *                    kernel has a closed form in the Stokes limit,
+ *                    Brinkmanlet has a closed form for every alpha.  The
+ *                    paper's blob has a closed form in the Stokes limit,
  *                    H2 = (R + 2 eps)/(4 pi R (R + eps)^2) and
  *                    H1 = -[ln(R + eps) - eps (R + 2 eps)/(R (R + eps))]/(4 pi)
  *                    - 1/(8 pi).  For alpha > 0 there is none: g, the
@@ -108,9 +114,13 @@ int swim_version(void);
  *                    radial integrals of the blob against I0 and K0 (Graf's
  *                    addition theorem), taken by FP64 Gauss-Legendre
  *                    quadrature, with H1 = M/r^2 - g, H2 = (g - 2M/r^2)/r^2,
- *                    M = int_0^r s g ds.  FP32 runs read it from the
- *                    per-system tables (built once per launch from the
- *                    quadrature, about 2e3 kernel values per system); FP64
+ *                    M = int_0^r s g ds, and g(0) in closed form from the
+ *                    sine and cosine integrals.  FP32 runs read it from the
+ *                    per-system tables, built once per launch by one sweep
+ *                    over the table's 2113 nodes in increasing r (prefix
+ *                    and suffix sums of the two integrals over the gaps
+ *                    between nodes, a far-field expansion beyond
+ *                    alpha r = 40); FP64
  *                    evaluates the quadrature per pair, a few hundred
  *                    times the cost of the closed forms (a reference mode
  *                    for small systems).  It applies to every velocity and
@@ -126,8 +136,8 @@ int swim_version(void);
 #define SWIM_OPT_GRAPH_LAUNCHES 4
 #define SWIM_OPT_GRAPH_CAPTURES 5
 #define SWIM_OPT_BLOB 6
-#define SWIM_BLOB_READING 0 /* default: the unit-mass blob whose Brinkmanlet has a closed form for all alpha */
-#define SWIM_BLOB_PAPER 1   /* eq. (eqnblob): 3 eps^3 / (2 pi (r^2 + eps^2)^(5/2)) */
+#define SWIM_BLOB_READING 0 /* the unit-mass blob whose Brinkmanlet has a closed form for all alpha */
+#define SWIM_BLOB_PAPER 1   /* default: eq. (eqnblob), 3 eps^3 / (2 pi (r^2 + eps^2)^(5/2)) */
 int swim_set_option(swim_ctx *ctx, int32_t key, int32_t value);
 int swim_get_option(swim_ctx *ctx, int32_t key, int32_t *value);
 

@@ -17,18 +17,34 @@ _I64 = ctypes.POINTER(ctypes.c_int64)
 _I32 = ctypes.POINTER(ctypes.c_int32)
 
 
-class paper_blob:
-    """Context manager: the oracle's kernel functions use the paper's blob
-    3 eps^3 / (2 pi R^5) (eq. eqnblob) inside it: closed forms in the Stokes
-    limit, quadrature for alpha > 0."""
+class _blob:
+    """Context manager selecting the blob of the oracle's kernel functions
+    inside it, restoring the previous choice on exit."""
+
+    value = None
 
     def __enter__(self):
-        lib().oracle_set_blob(1)
+        self._prev = lib().oracle_get_blob()
+        lib().oracle_set_blob(self.value)
         return self
 
     def __exit__(self, *exc):
-        lib().oracle_set_blob(0)
+        lib().oracle_set_blob(self._prev)
         return False
+
+
+class paper_blob(_blob):
+    """The paper's blob 3 eps^3 / (2 pi R^5) (eq. eqnblob), the oracle's
+    default: closed forms in the Stokes limit, quadrature for alpha > 0."""
+
+    value = 1
+
+
+class reading_blob(_blob):
+    """The blob of the kernel reading (closed forms for every alpha; see
+    swim_oracle.c)."""
+
+    value = 0
 
 
 def lib():
@@ -71,11 +87,24 @@ def lib():
                                            ctypes.c_int, _D, _D, _D, _D, _I32]
         L.oracle_sperm_forward.restype = ctypes.c_int
         L.oracle_set_blob.argtypes = [ctypes.c_int]
+        L.oracle_get_blob.restype = ctypes.c_int
+        L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_blob.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int64, _D, _D, _D]
         L.oracle_field.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int64, _D, _D, _D, _D, _D]
         _LIB = L
     return _LIB
+
+
+def num_threads():
+    """Threads the oracle's parallel velocity sums use."""
+    return int(lib().oracle_num_threads())
+
+
+def set_threads(n):
+    """Sets the threads of the oracle's parallel velocity sums."""
+    lib().oracle_set_threads(int(n))
 
 
 def _p(a):

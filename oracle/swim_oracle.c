@@ -26,6 +26,9 @@
  * order j = 0, 1, ...
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -364,8 +367,9 @@ typedef struct {
 } okern;
 
 /* Blob selection for the kernel functions below (test infrastructure:
- * set per call by the Python wrapper).  0: the blob of the reading above;
- * 1: the paper's blob phi = 3 eps^3 / (2 pi R^5) of eq. (eqnblob), whose
+ * set by the Python wrapper).  1 (the default): the paper's blob
+ * phi = 3 eps^3 / (2 pi R^5) of eq. (eqnblob); 0: the blob of the reading
+ * above.  The paper's blob, whose
  * Stokes Green function G (Delta G = phi) is
  *   G = (ln(R + eps) - eps/R) / (2 pi)
  * (r G' = m/(2 pi) with the blob mass m = 1 - eps^3/R^3).  Its kernel uses
@@ -374,8 +378,28 @@ typedef struct {
  * H2 = (G - 2M/r^2)/r^2; near contact the series of G in delta with the
  * same formulas.  For alpha > 0 (no closed form) g and M come from the
  * quadrature of pb_gM and the series from gam_0 = g(0) (see above). */
-static int g_blob = 0;
+static int g_blob = 1;
 void oracle_set_blob(int b) { g_blob = b; }
+int oracle_get_blob(void) { return g_blob; }
+
+/* threads the OpenMP loops of the velocity sums use, and setting them */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
 
 static void kernel_init(okern *k, double alpha, double eps)
 {

@@ -98,7 +98,7 @@ struct swim_ctx {
     int opt_wps = 0;      // waves per system in the persistent kernel (0: automatic)
     int opt_big_tpl = 0;  // targets per lane of the large-system kernel (0: automatic)
     int opt_graph = 1;    // 0: eager launches; 1: capture on a repeated layout; 2: capture always
-    int opt_blob = 0;     // 0: the kernel reading's blob; 1: the paper's blob
+    int opt_blob = 1;     // 1: the paper's blob (eq. eqnblob); 0: the kernel reading's blob
     int tuned_wps[2][9] = {};  // autotuned waves per system [dtype][tpl] (0: not tuned)
     FwdGraph graphs[N_GRAPHS];
     uint64_t graph_clock = 0, last_key = 0;
@@ -107,6 +107,14 @@ struct swim_ctx {
     void* pinned = nullptr;
     size_t pinned_cap = 0, pin_off = 0;
     hipEvent_t up_ev = nullptr;
+    hipEvent_t sw_ev = nullptr;        // orders work across a change of stream
+    // auxiliary streams (default priority) and events that run the size
+    // buckets of one forward call side by side, forked from and joined to
+    // the call's stream (in a captured graph: parallel branches)
+    static constexpr int N_AUX = 3;
+    hipStream_t aux[N_AUX] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[N_AUX] = {};
+    hipStream_t last_stream = nullptr;  // stream of the previous call (null: none yet)
     bool broken = false;
 };
 
@@ -166,7 +174,24 @@ int end_uploads(swim_ctx* c, hipStream_t st)
     return SWIM_OK;
 }
 
-hipStream_t pick(swim_ctx* c, void* s) { return s ? (hipStream_t)s : c->stream; }
+// The stream a call runs on (null: the context's).  The context's device
+// buffers (offsets, constants, tables, staging targets) are shared by every
+// call, so when a call comes on another stream than the previous one, its
+// stream first waits for everything enqueued so far on that previous stream:
+// the new call's copies and kernels cannot overwrite buffers that kernels of
+// the previous call are still reading.
+hipStream_t pick(swim_ctx* c, void* s)
+{
+    hipStream_t st = s ? (hipStream_t)s : c->stream;
+    if (c->last_stream && st != c->last_stream) {
+        if (hipEventRecord(c->sw_ev, c->last_stream) != hipSuccess || hipStreamWaitEvent(st, c->sw_ev, 0) != hipSuccess) {
+            // the previous stream is gone: its work was ordered by its destruction
+            (void)hipGetLastError();
+        }
+    }
+    c->last_stream = st;
+    return st;
+}
 
 int check_ctx(swim_ctx* c)
 {
@@ -357,7 +382,7 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     // launch shapes of the persistent buckets (and their LDS limits, set
     // here: nothing inside a stream capture may change them)
     struct Bucket {
-        int tpl, wps, nblocks;
+        int tpl, wps, nblocks, lane = 0;
         int64_t start, count;
     };
     std::vector<Bucket> bk;
@@ -367,14 +392,47 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
         q.start = bucket_span[k].second;
         q.count = (k + 1 < bucket_span.size() ? bucket_span[k + 1].second : (int64_t)order.size()) - q.start;
         q.wps = c->opt_wps ? c->opt_wps : (c->tuned_wps[dtype][q.tpl] ? c->tuned_wps[dtype][q.tpl] : 16);
-        // at most FWD_MAX_WINDOWS point windows per lane, and the wave
-        // partial sums of one system must fit the LDS
+        // at most FWD_MAX_WINDOWS point windows per lane: fewer waves are not
+        // built (their one-wave instantiations exceed 256 VGPRs and spill to
+        // AGPRs), and an explicit request for them is refused; the wave
+        // partial sums of one system must also fit the LDS
+        if (c->opt_wps && c->opt_wps < forward_min_wps(q.tpl))
+            return fail(SWIM_EINVAL,
+                        "SWIM_OPT_WPS = %d is below the %d waves per system needed for systems of up to %d points "
+                        "(at most 5 point windows of 60 per lane)",
+                        c->opt_wps, forward_min_wps(q.tpl), 64 * q.tpl);
         q.wps = std::max(q.wps, forward_min_wps(q.tpl));
         while (q.wps > forward_min_wps(q.tpl) && forward_lds_bytes(dtype, q.tpl, q.wps) > 160 * 1024) q.wps /= 2;
         const int per_cu = forward_blocks_per_cu(dtype, q.tpl, q.wps);
         q.nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(q.count, (int64_t)per_cu * c->num_cu));
         HIPCHK(prepare_forward(dtype, q.tpl, q.wps));
         bk.push_back(q);
+    }
+    // lanes of the concurrent launch (longest processing time first): each
+    // part, in decreasing pair work, goes to the lane with the least work
+    int big_lane = 0;
+    {
+        const int parts = (int)bk.size() + (big_list.empty() ? 0 : 1);
+        const int lanes = std::min(parts, 1 + swim_ctx::N_AUX);
+        std::vector<std::pair<double, int>> work;  // (pair work, part: bucket k or -1 for the large systems)
+        for (size_t k = 0; k < bk.size(); ++k) {
+            double w = 0.0;
+            for (int64_t i = bk[k].start; i < bk[k].start + bk[k].count; ++i) w += (double)pts[order[i]] * pts[order[i]];
+            work.push_back({w, (int)k});
+        }
+        if (!big_list.empty()) {
+            double w = 0.0;
+            for (int64_t s : big_list) w += (double)pts[s] * pts[s];
+            work.push_back({w, -1});
+        }
+        std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+        std::vector<double> load(std::max(lanes, 1), 0.0);
+        for (const auto& wk : work) {
+            const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[l] += wk.first;
+            if (wk.second >= 0) bk[wk.second].lane = l;
+            else big_lane = l;
+        }
     }
     BigState S{};
     if (!big_list.empty()) {
@@ -397,25 +455,42 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
         hipError_t e = launch_sysconst_batch(dtype, n_sys, (const int64_t*)c->buf[B_SWOFF].p,
                                              (const int32_t*)c->buf[B_NPT].p, params_dev, run.eps_over_ds, sysc,
                                              sysc64, status, c->opt_blob, st);
-        if (e == hipSuccess && dtype == SWIM_F32) e = launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, st);
+        if (e == hipSuccess && dtype == SWIM_F32) e = launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, c->opt_blob, st);
         if (e == hipSuccess) e = launch_fill_i32((int32_t*)c->buf[B_QUEUE].p, 0, 8, st);
+        // Buckets (and the large systems) are independent: with more than
+        // one, they run side by side, the call's stream and up to N_AUX
+        // auxiliary streams each taking a share (lanes assigned in order of
+        // decreasing work), forked from the set-up above and joined before
+        // the call returns, so that one bucket's tail overlaps the others.
+        const int parts = (int)bk.size() + (big_list.empty() ? 0 : 1);
+        const int lanes = std::min(parts, 1 + swim_ctx::N_AUX);
+        auto lane_stream = [&](int l) { return l == 0 ? st : c->aux[l - 1]; };
+        if (e == hipSuccess && lanes > 1) {
+            e = hipEventRecord(c->fork_ev, st);
+            for (int l = 1; l < lanes && e == hipSuccess; ++l) e = hipStreamWaitEvent(c->aux[l - 1], c->fork_ev, 0);
+        }
         for (size_t k = 0; k < bk.size() && e == hipSuccess; ++k) {
             Batch bb = b;
             bb.n_sys = bk[k].count;
             e = launch_forward(dtype, bk[k].tpl, bk[k].wps, bk[k].nblocks, bb, run,
                                (const int32_t*)c->buf[B_ORDER].p + bk[k].start, (int32_t*)c->buf[B_QUEUE].p + k, obs,
-                               speed, status, steps_done, st);
+                               speed, status, steps_done, lane_stream(bk[k].lane % lanes));
         }
         if (!big_list.empty() && e == hipSuccess) {
+            const hipStream_t st_big = lane_stream(big_lane % lanes);
             e = launch_big_init(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S, status, obs,
-                                run.n_obs, st);
+                                run.n_obs, st_big);
             for (int step = 0; step < run.steps && e == hipSuccess; ++step)
                 e = launch_big_step(dtype, tpl_big, (int64_t)blk_s.size(), (const int64_t*)c->buf[B_BLKS].p,
                                     (const int64_t*)c->buf[B_BLKF].p, max_big, b, S, step, run, obs, status,
-                                    steps_done, st);
+                                    steps_done, st_big);
             if (e == hipSuccess)
                 e = launch_big_finish(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S,
-                                      run.steps & 1, run, speed, status, steps_done, st);
+                                      run.steps & 1, run, speed, status, steps_done, st_big);
+        }
+        for (int l = 1; l < lanes && e == hipSuccess; ++l) {
+            e = hipEventRecord(c->join_ev[l - 1], c->aux[l - 1]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, c->join_ev[l - 1], 0);
         }
         return e;
     };
@@ -440,7 +515,9 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
         h.add(q.tpl);
         h.add(q.wps);
         h.add(q.nblocks);
+        h.add(q.lane);
     }
+    h.add(big_lane);
     const void* ptrs[] = {params_dev, obs, speed, status, steps_done, sysc, sysc64, b.tab, c->buf[B_SWOFF].p,
                           c->buf[B_OFF].p, c->buf[B_NPT].p, c->buf[B_NSW].p, c->buf[B_ORDER].p, c->buf[B_LIST].p,
                           c->buf[B_BLKS].p, c->buf[B_BLKF].p, c->buf[B_QUEUE].p, c->buf[B_BIG].p, st};
@@ -617,11 +694,21 @@ int swim_create(swim_ctx** out, int device)
     c->device = device;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess || hipStreamCreateWithFlags(&c->stream, hipStreamDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&c->up_ev, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->up_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->sw_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess) {
         delete c;
         return fail(SWIM_EHIP, "context creation failed");
     }
     c->num_cu = prop.multiProcessorCount;
+    for (int k = 0; k < swim_ctx::N_AUX; ++k) {
+        if (hipStreamCreateWithFlags(&c->aux[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->join_ev[k], hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            swim_destroy(c);
+            return fail(SWIM_EHIP, "context creation failed (auxiliary streams)");
+        }
+    }
     *out = c;
     return SWIM_OK;
 }
@@ -639,6 +726,15 @@ void swim_destroy(swim_ctx* c)
     }
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->up_ev) (void)hipEventDestroy(c->up_ev);
+    if (c->sw_ev) (void)hipEventDestroy(c->sw_ev);
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    for (int k = 0; k < swim_ctx::N_AUX; ++k) {
+        if (c->aux[k]) {
+            (void)hipStreamSynchronize(c->aux[k]);
+            (void)hipStreamDestroy(c->aux[k]);
+        }
+        if (c->join_ev[k]) (void)hipEventDestroy(c->join_ev[k]);
+    }
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -720,7 +816,7 @@ int swim_pair_velocity(swim_ctx* c, int32_t dtype, int64_t n_sys, const int64_t*
     void* tab = nullptr;
     if (dtype == SWIM_F32) {
         TRY(ensure(c, B_TAB, (size_t)n_sys * table_bytes()));
-        HIPCHK(launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, st));
+        HIPCHK(launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, c->opt_blob, st));
         tab = c->buf[B_TAB].p;
     }
     HIPCHK(launch_pair_velocity(dtype, tpl, (int64_t)bs.size(), (const int64_t*)c->buf[B_BLKS].p,
@@ -787,7 +883,7 @@ int swim_flow_field(swim_ctx* c, int32_t dtype, int64_t n, const void* x, const 
         HIPCHK(launch_sysconst(SWIM_F32, 1, (const double*)c->buf[B_ALPHA].p, (const double*)c->buf[B_EPS].p, sysc,
                                sysc64, c->opt_blob, st));
         TRY(ensure(c, B_TAB, table_bytes()));
-        HIPCHK(launch_table_build(0, 1, sysc64, c->buf[B_TAB].p, st));
+        HIPCHK(launch_table_build(0, 1, sysc64, c->buf[B_TAB].p, c->opt_blob, st));
         tab = c->buf[B_TAB].p;
         // and the pressure weight's table on the same intervals
         TRY(ensure(c, B_WTAB, (size_t)TAB_N * 16));
@@ -945,7 +1041,7 @@ int sperm_forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const swim_spe
     const int nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(n_sys, (int64_t)per_cu * c->num_cu));
     HIPCHK(launch_sperm_setup(dtype, n_sys, sh.n_swim, sh.eps, sys_params, swim_params, sysc, sysc64, status,
                               c->opt_blob, st));
-    if (dtype == SWIM_F32) HIPCHK(launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, st));
+    if (dtype == SWIM_F32) HIPCHK(launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, c->opt_blob, st));
     HIPCHK(launch_fill_i32((int32_t*)c->buf[B_QUEUE].p, 0, 8, st));
     HIPCHK(launch_sperm_forward(dtype, tpl, wps, nblocks, g, r, sysc, dtype == SWIM_F32 ? c->buf[B_TAB].p : nullptr,
                                 (int32_t*)c->buf[B_QUEUE].p, head, tail, status, st));
@@ -1214,7 +1310,19 @@ int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int32_t blob,
         SysConst<double> C64;
         sysconst_compute<double>(alpha, eps, &C64, blob);
         std::vector<TabE> tab(TAB_N + 1);
-        for (int i = 0; i <= TAB_N; ++i) tab_interval(C64, i, tab[i], nullptr);
+        if (C64.paper == 2.0) {
+            // the paper's blob at alpha > 0: the nodes from the sweep
+            std::vector<double> fh(PB_NODES), fg(PB_NODES);
+            pb_table_nodes_host(C64, fh.data(), fg.data());
+            for (int i = 0; i < TAB_N; ++i) {
+                const double h4[4] = {fh[3 * i], fh[3 * i + 1], fh[3 * i + 2], fh[3 * i + 3]};
+                const double g4[4] = {fg[3 * i], fg[3 * i + 1], fg[3 * i + 2], fg[3 * i + 3]};
+                tab_assemble(C64, h4, g4, tab[i], nullptr);
+            }
+            tab_interval(C64, TAB_N, tab[TAB_N], nullptr);
+        } else {
+            for (int i = 0; i <= TAB_N; ++i) tab_interval(C64, i, tab[i], nullptr);
+        }
         for (int64_t i = 0; i < n; ++i) {
             float a, b;
             const float tf = (float)t[i];

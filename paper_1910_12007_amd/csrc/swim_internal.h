@@ -50,7 +50,7 @@ hipError_t launch_pair_velocity(int dtype, int tpl, int64_t n_blocks, const int6
 // bytes of one system's FP32 kernel table
 size_t table_bytes();
 // FP32 kernel tables of systems [s0, s0 + n) (FP64 constants sysc64) into tab[s]
-hipError_t launch_table_build(int64_t s0, int64_t n, const void* sysc64, void* tab, hipStream_t st);
+hipError_t launch_table_build(int64_t s0, int64_t n, const void* sysc64, void* tab, int blob, hipStream_t st);
 hipError_t launch_forces(int dtype, int64_t n_fil, const int64_t* fil_off, const int32_t* npt,
                          const double* params, double t, const void* x, const void* y, void* fx,
                          void* fy, hipStream_t st);

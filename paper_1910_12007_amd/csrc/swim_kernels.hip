@@ -292,6 +292,129 @@ __global__ __launch_bounds__(64) void k_table_build(int64_t s0, int64_t n, const
     tab_assemble(sysc64[s], h, g, tab[s].e[i], &tab[s].h0lo[i]);
 }
 
+// FP32 kernel tables with the paper's blob (eq. eqnblob): one workgroup of
+// PB_BLOCK threads per system.  A system at alpha > 0 (paper == 2) takes the
+// sweep of pb_table_nodes_host, split over the workgroup:
+//  1. thread tid integrates a contiguous run of the gaps [1, kL] and leaves
+//     the gap integrals in LDS (slot k of three node arrays);
+//  2. exclusive prefix sums of A and Cq and the suffix sum of B over the
+//     per-thread totals (a wave scan, then the waves in order);
+//  3. each thread turns its own slots into A(r_k), B(r_k), Cq(r_k) and then
+//     into the node values of the sweep;
+//  4. the nodes outside the sweep (and every node of a system at alpha = 0,
+//     closed forms) are spread over the threads;
+//  5. the entries are assembled from the node values as in k_table_build.
+constexpr int PB_BLOCK = 512;
+
+// exclusive scan of v over the workgroup in thread order (REV: from the last
+// thread down), plus its total; red holds PB_BLOCK / 64 values
+template <bool REV> __device__ double pb_block_scan(double v, double* red, double* total)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = PB_BLOCK / 64;
+    const int l = REV ? 63 - lane : lane;
+    double inc = v;  // inclusive scan within the wave, in order of l
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double u = __shfl(inc, REV ? min(lane + o, 63) : max(lane - o, 0), 64);
+        if (l >= o) inc += u;
+    }
+    if (l == 63) red[wave] = inc;
+    __syncthreads();
+    double before = 0.0, all = 0.0;
+    for (int w = 0; w < NW; ++w) {
+        const int ww = REV ? NW - 1 - w : w;
+        if (REV ? ww > wave : ww < wave) before += red[ww];
+        all += red[ww];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(PB_BLOCK) void k_table_build_pb(int64_t s0, const SysConst<double>* sysc64, TabSys* tab)
+{
+    __shared__ double s_fh[PB_NODES], s_fg[PB_NODES], s_c[PB_NODES];
+    __shared__ double s_red[PB_BLOCK / 64];
+    __shared__ double s_tail;
+    const int tid = threadIdx.x;
+    const int64_t s = s0 + blockIdx.x;
+    const SysConst<double> C = sysc64[s];
+    const bool sweep = C.paper == 2.0;
+    int kS = PB_NODES, kL = -1;
+    if (sweep) pb_sweep_range(C, kS, kL);
+    if (kL >= kS) {  // uniform over the workgroup
+        const double alpha = sqrt(C.a2), eps = C.eps;
+        const int per = (kL + PB_BLOCK - 1) / PB_BLOCK;
+        const int k0 = 1 + tid * per, k1 = min(kL + 1, k0 + per);
+        double ta = 0.0, tb = 0.0, tc = 0.0;
+        double ulo = (k0 > 1 && k0 <= kL) ? asinh(sqrt(pb_node_t(C.its, k0 - 1)) / eps) : 0.0;
+        for (int k = k0; k < k1; ++k) {
+            const double r = sqrt(pb_node_t(C.its, k));
+            const double uhi = asinh(r / eps);
+            double ga, gb, gc;
+            pb_gap(alpha, eps, ulo, uhi, k > kS, alpha * r <= 2.0, &ga, &gb, &gc);
+            ulo = uhi;
+            s_fh[k] = ga;
+            s_fg[k] = gb;
+            s_c[k] = gc;
+            ta += ga;
+            tb += gb;
+            tc += gc;
+        }
+        // B(r_L), the integral beyond the sweep's last node: the first wave
+        // takes one panel of pb_tail_panels per lane
+        if (tid < 64) {
+            const double rL = sqrt(pb_node_t(C.its, kL));
+            const double v = wave_total(pb_tail_panel(alpha, eps, rL, tid, 64));
+            if (tid == 0) s_tail = v;
+        }
+        double tot;
+        double A = pb_block_scan<false>(ta, s_red, &tot);
+        double Cq = pb_block_scan<false>(tc, s_red, &tot);
+        double B = pb_block_scan<true>(tb, s_red, &tot) + s_tail;
+        for (int k = k0; k < k1; ++k) {
+            A += s_fh[k];
+            Cq += s_c[k];
+            s_fh[k] = A;
+            s_c[k] = Cq;
+        }
+        for (int k = k1 - 1; k >= k0; --k) {
+            const double gb = s_fg[k];
+            s_fg[k] = B;
+            B += gb;
+        }
+        for (int k = max(k0, kS); k < k1; ++k) {
+            double fh, fg;
+            pb_node_sweep(alpha, eps, pb_node_t(C.its, k), s_fh[k], s_fg[k], s_c[k], C.h1c, fh, fg);
+            s_fh[k] = fh;
+            s_fg[k] = fg;
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < PB_NODES; k += PB_BLOCK) {
+        if (k >= kS && k <= kL) continue;
+        double fh, fg;
+        if (sweep)
+            pb_node_outside(C, k, kS, fh, fg);
+        else
+            kernel_paper_stokes<double>(C, pb_node_t(C.its, k), fh, fg);  // alpha = 0: closed forms
+        s_fh[k] = fh;
+        s_fg[k] = fg;
+    }
+    __syncthreads();
+    TabSys& T = tab[s];
+    for (int i = tid; i <= TAB_N; i += PB_BLOCK) {
+        if (i == TAB_N) {
+            tab_interval(C, i, T.e[i], &T.h0lo[i]);  // the zero entry
+            continue;
+        }
+        const double fh[4] = {s_fh[3 * i], s_fh[3 * i + 1], s_fh[3 * i + 2], s_fh[3 * i + 3]};
+        const double fg[4] = {s_fg[3 * i], s_fg[3 * i + 1], s_fg[3 * i + 2], s_fg[3 * i + 3]};
+        tab_assemble(C, fh, fg, T.e[i], &T.h0lo[i]);
+    }
+}
+
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -861,9 +984,15 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
     extern __shared__ __align__(16) unsigned char smem[];
     TabSys* tab = reinterpret_cast<TabSys*>(smem);
     Src4<T>* src = reinterpret_cast<Src4<T>*>(smem + TABB);  // [BIG_TILE]
+    __shared__ int s_status;
     const int tid = threadIdx.x;
     const int64_t s = blk_sys[blockIdx.x];
-    if (status[s] != 0) return;
+    // one read of the status per workgroup (other workgroups of this launch
+    // may raise it meanwhile), broadcast through LDS so that every wave
+    // takes the same exit before the barriers below
+    if (tid == 0) s_status = status[s];
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_status) != 0) return;
     if constexpr (COMP) tab_load((const TabSys*)b.tab + s, tab, tid, 256);
     const int64_t first = blk_first[blockIdx.x];
     const int64_t p0 = b.pt_off[s];
@@ -1132,11 +1261,15 @@ hipError_t launch_sysconst(int dtype, int64_t n_sys, const double* alpha, const 
 
 size_t table_bytes() { return sizeof(TabSys); }
 
-hipError_t launch_table_build(int64_t s0, int64_t n, const void* sysc64, void* tab, hipStream_t st)
+hipError_t launch_table_build(int64_t s0, int64_t n, const void* sysc64, void* tab, int blob, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_table_build, dim3((unsigned)(n * TAB_WAVES)), dim3(64), 0, st, s0, n,
-                       (const SysConst<double>*)sysc64, (TabSys*)tab);
+    if (blob == 1)
+        hipLaunchKernelGGL(k_table_build_pb, dim3((unsigned)n), dim3(PB_BLOCK), 0, st, s0,
+                           (const SysConst<double>*)sysc64, (TabSys*)tab);
+    else
+        hipLaunchKernelGGL(k_table_build, dim3((unsigned)(n * TAB_WAVES)), dim3(64), 0, st, s0, n,
+                           (const SysConst<double>*)sysc64, (TabSys*)tab);
     return hipGetLastError();
 }
 

@@ -409,6 +409,33 @@ SWIM_HD double pb_g0(double alpha, double eps)
     return -(b + pb_outer(alpha, eps, 0.0, 0.5));
 }
 
+// g(0) of the paper's blob in closed form.  The blob's Hankel transform is
+// (1 + k eps) exp(-k eps) and (Delta - alpha^2) g = phi, so with a = alpha eps
+//   g(0) = -(1/2pi) int_0^inf (1 + x) exp(-x) x / (x^2 + a^2) dx
+//        = -(1/2pi) [ gaux(a) + 1 - a faux(a) ],
+// faux = Ci(a) sin a - si(a) cos a and gaux = -Ci(a) cos a - si(a) sin a the
+// auxiliary functions of the sine and cosine integrals (A&S 5.2.6-5.2.7 and
+// their Laplace integrals 5.2.12-5.2.13), si = Si - pi/2, Ci and Si by their
+// power series (A&S 5.2.14, 5.2.16; a <= 1 in this library's domain).
+SWIM_HD double pb_g0_closed(double a)
+{
+    const double a2 = a * a;
+    double p = a, q = 1.0;  // (-1)^k a^(2k+1)/(2k+1)!, (-1)^k a^(2k)/(2k)!
+    double S = 0.0, Cs = 0.0;
+    for (int k = 0; k < 16; ++k) {
+        S += p * PB_RECIP.lin[2 * k];               // / (2k + 1)
+        if (k >= 1) Cs += q * (0.5 * PB_RECIP.lin[k - 1]);  // / (2k)
+        p *= -a2 * PB_RECIP.lin[2 * k + 1] * PB_RECIP.lin[2 * k + 2];  // / ((2k+2)(2k+3))
+        q *= -a2 * PB_RECIP.lin[2 * k] * PB_RECIP.lin[2 * k + 1];      // / ((2k+1)(2k+2))
+    }
+    const double Ci = EULER_GAMMA + log(a) + Cs;
+    const double si = S - 0.5 * PI;
+    const double sn = sin(a), cs = cos(a);
+    const double fa = Ci * sn - si * cs;
+    const double ga = -Ci * cs - si * sn;
+    return -(ga + 1.0 - a * fa) / (2.0 * PI);
+}
+
 // g(r) and M(r) for delta >= 1/4
 SWIM_HD void pb_gM(double alpha, double eps, double t, double* g, double* M, PbRule q = PB_EXACT)
 {
@@ -562,7 +589,7 @@ template <typename T> SWIM_HD void sysconst_paper(double alpha, double eps, doub
 template <typename T> SWIM_HD void sysconst_compute(double alpha, double eps, SysConst<T>* out, int blob = 0)
 {
     if (blob == 1 && alpha > 0.0)
-        sysconst_paper<T>(alpha, eps, pb_g0(alpha, eps), out);
+        sysconst_paper<T>(alpha, eps, pb_g0_closed(alpha * eps), out);
     else
         sysconst_base<T>(alpha, eps, out, blob);
 }
@@ -601,7 +628,7 @@ template <typename T>
 SWIM_HD void sysconst_compute2(double alpha, double eps, SysConst<T>* out, SysConst<double>* out64, int blob)
 {
     if (blob == 1 && alpha > 0.0) {
-        const double g0 = pb_g0(alpha, eps);
+        const double g0 = pb_g0_closed(alpha * eps);
         sysconst_paper<T>(alpha, eps, g0, out);
         if (out64) sysconst_paper<double>(alpha, eps, g0, out64);
         return;
@@ -844,7 +871,10 @@ SWIM_HD void kernel_eval(const SysConst<T>& C, T t, T& Ht, T& H2)
 // and fall back to the direct evaluation.  Far octaves cost nothing per
 // pair, and runs that drift far apart before they stop stay on the table.
 // ---------------------------------------------------------------------------
-constexpr int TAB_M = 4;                     // intervals per octave: 2^TAB_M
+#ifndef SWIM_TAB_M
+#define SWIM_TAB_M 4
+#endif
+constexpr int TAB_M = SWIM_TAB_M;            // intervals per octave: 2^TAB_M
 // octaves of v, which covers [1, 2^44): positions stay within 1e3 of the
 // origin (runs stop beyond), so pair distances are below 2830 and every pair
 // of a system with eps >= 1.4e-3 (N <= 1100 at eps = 1.5 ds) is in the table
@@ -939,6 +969,271 @@ SWIM_HD void tab_eval(const TabE& e, float u, float& Ht, float& H2s)
 {
     Ht = fmaf(fmaf(fmaf(e.h[3], u, e.h[2]), u, e.h[1]), u, e.h[0]);
     H2s = fmaf(fmaf(fmaf(e.g[3], u, e.g[2]), u, e.g[1]), u, e.g[0]);
+}
+
+// ---------------------------------------------------------------------------
+// The paper's blob at alpha > 0: all table nodes of one system in one sweep.
+//
+// The nodes of the FP32 table (node k: interval k/3 at coordinate 0, 1/4,
+// 3/4; node 3 TAB_N the end of the last interval) have increasing r.  With
+// A, B and Cq the integrals of pb_gM, each node needs
+//   A(r_k) = sum of the integrals of phi I0(alpha s) s over the gaps
+//            [r_{m-1}, r_m], m <= k (a prefix sum from s = 0),
+//   Cq(r_k) likewise (only where alpha r_k <= 2),
+//   B(r_k) = B(r_L) + the gaps m > k up to the last node L of the sweep
+//            (a suffix sum; B(r_L) is one tail integral, pb_outer),
+// and then g and M follow exactly as in pb_gM.  The gaps are narrow (at
+// most 1/64 in u beyond the first octave), so a 6-point Gauss-Legendre rule
+// per gap is exact to rounding for the blob's density (poles pi/2 off the
+// axis) and for the Bessel factors up to alpha r = PB_ZF (they change by at
+// most exp(PB_ZF/64) over a gap).  The sweep covers the nodes with
+// delta = t/eps^2 >= 1/4 and alpha r <= PB_ZF; below, g is the near-contact
+// series of kernel_paper_brinkman; beyond, the far-field expansion of
+// pb_node_far.  Every node value is one gap quadrature and one set of Bessel
+// functions instead of a panel quadrature of its own.
+// ---------------------------------------------------------------------------
+constexpr int PB_NODES = 3 * TAB_N + 1;  // table nodes of one system
+constexpr double PB_ZF = 40.0;           // alpha r beyond which the far-field expansion serves
+constexpr int PB_NA = 14;                // terms of the far-field expansion
+constexpr double GL6_X[3] = {0.23861918608319693, 0.66120938646626448, 0.93246951420315205};
+constexpr double GL6_W[3] = {0.46791393457269137, 0.36076157304813894, 0.17132449237916975};
+
+// t = r^2 of table node k (the t of tab_node: node k % 3 of interval k / 3)
+SWIM_HD double pb_node_t(double its, int k)
+{
+    const int i = k / 3, kk = k - 3 * i;
+    const int e = i >> TAB_M, j = i & ((1 << TAB_M) - 1);
+    const double a = ldexp(1.0, e);
+    const double v0 = a * (1.0 + (double)j / (double)(1 << TAB_M)), hv = a / (double)(1 << TAB_M);
+    const double un = kk == 0 ? 0.0 : kk == 1 ? 0.25 : 0.75;
+    return fmax((v0 - 1.0 + hv * un) * its, 1e-300);
+}
+
+// integrals over the gap [ulo, uhi] in u = asinh(s/eps) of the blob measure
+// phi s ds = (3/2pi) sinh u/cosh^4 u du times I0(alpha s) (ga), K0(alpha s)
+// (gb, if wantB) and (I0(alpha s) - 1)/alpha^2 (gc, if wantC)
+SWIM_HD void pb_gap(double alpha, double eps, double ulo, double uhi, bool wantB, bool wantC, double* ga, double* gb,
+                    double* gc)
+{
+    const double hm = 0.5 * (uhi - ulo), ct = 0.5 * (uhi + ulo);
+    double A = 0.0, B = 0.0, Cq = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < 6; ++i) {
+        const double u = i < 3 ? ct - hm * GL6_X[2 - i] : ct + hm * GL6_X[i - 3];
+        double sh, dens;
+        pb_point(u, &sh, &dens);
+        const double wd = hm * (i < 3 ? GL6_W[2 - i] : GL6_W[i - 3]) * dens;
+        const double s = eps * sh, xs = alpha * s;
+        A += wd * pb_i0x(xs, 0.0, 1.0);
+        if (wantB) B += wd * pb_k0x(xs, 0.0, 1.0);
+        if (wantC) {
+            // (I0(xs) - 1)/alpha^2 = (s^2/4) sum_k (xs^2/4)^k / ((k+1)!)^2
+            const double y = 0.25 * xs * xs;
+            double term = 1.0, acc = 0.0;
+            for (int k = 0; k < 40; ++k) {
+                acc += term;
+                term *= y * PB_RECIP.sq[k + 1];
+                if (term < 1e-18 * acc) break;
+            }
+            Cq += wd * 0.25 * s * s * acc;
+        }
+    }
+    *ga = A;
+    *gb = B;
+    *gc = Cq;
+}
+
+// The tail B(r) = int_r^inf phi K0(alpha s) s ds beyond the sweep's last
+// node, as np panels in d = u - u(r): panel p of [0, dmax] by 10-point
+// Gauss-Legendre.  Its integrand falls like exp(-x - 3 d) with
+// x = alpha (s - r), so dmax is where x + 3 d reaches 44 (at most 15): the
+// neglected remainder is below e^-44 of the integrand at s = r, and a panel
+// of dmax/np (np = 64) changes the exponent by at most (alpha r + 3) dmax/np.
+SWIM_HD double pb_tail_dmax(double alpha, double eps, double r)
+{
+    const double u0 = asinh(r / eps);
+    double lo = 0.0, hi = 15.0;
+    for (int it = 0; it < 40; ++it) {
+        const double d = 0.5 * (lo + hi);
+        const double x = alpha * (eps * sinh(u0 + d) - r);
+        if (x + 3.0 * d > 44.0) hi = d;
+        else lo = d;
+    }
+    return hi;
+}
+SWIM_HD double pb_tail_panel(double alpha, double eps, double r, int p, int np)
+{
+    const double u0 = asinh(r / eps), dmax = pb_tail_dmax(alpha, eps, r);
+    const double ul = u0 + dmax * p / np, uh = u0 + dmax * (p + 1) / np;
+    const double hm = 0.5 * (uh - ul), ct = 0.5 * (uh + ul);
+    double b = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < 10; ++i) {
+        const double u = i < 5 ? ct - hm * GL10_X[4 - i] : ct + hm * GL10_X[i - 5];
+        double sh, dens;
+        pb_point(u, &sh, &dens);
+        b += hm * (i < 5 ? GL10_W[4 - i] : GL10_W[i - 5]) * dens * pb_k0x(alpha * eps * sh, 0.0, 1.0);
+    }
+    return b;
+}
+
+// node values Ht, H2 from A(r), B(r), Cq(r) (the formulas of pb_gM)
+SWIM_HD void pb_node_sweep(double alpha, double eps, double t, double A, double B, double Cq, double h1c, double& fh,
+                           double& fg)
+{
+    const double r = sqrt(t), z = alpha * r;
+    double K0, K1, Q, i0e, i1e;
+    bessel_k01_q_f64(z, &K0, &K1, &Q);
+    bessel_i01e_f64(z, &i0e, &i1e);
+    const double ez = exp(z), I0 = i0e * ez, I1 = i1e * ez;
+    const double g = -(K0 * A + I0 * B);
+    double M;
+    if (z <= 2.0) {
+        M = Cq + t * (Q / (z * z)) * A - t * (I1 / z) * B;
+    } else {
+        const double R = sqrt(t + eps * eps);
+        const double m = 1.0 - eps * eps * eps / (R * R * R);
+        M = (z * (K1 * A - I1 * B) - m / (2.0 * PI)) / (alpha * alpha);
+    }
+    const double Mt = M / t;
+    fg = (g - 2.0 * Mt) / t;
+    fh = Mt - g - h1c;
+}
+
+// Far field (alpha r > PB_ZF).  There g is the decaying particular solution
+//   g = -sum_n Delta^n phi / alpha^(2n+2)
+// up to a multiple of K0(alpha r) (below exp(-PB_ZF)), and Delta maps
+// (R^2)^-q to 4 q^2 (R^2)^(-q-1) - 4 q (q+1) eps^2 (R^2)^(-q-2), so with
+// w = 1/(alpha R)^2, y = eps^2/R^2:
+//   g    = -(3 eps^3/(2 pi alpha^2 R^5)) sum_n w^n sum_j d_nj y^j,
+//   r g' = -(3 eps^3/(2 pi alpha^2 R^5)) (r^2/R^2) sum_n w^n sum_j -2 p_nj d_nj y^j,
+// p_nj = 5/2 + n + j; then M = (r g' - m/(2 pi))/alpha^2 (the equation
+// integrated over the disc of radius r).
+struct PbAsym {
+    double d[PB_NA][PB_NA], e[PB_NA][PB_NA];  // d_nj and -2 p_nj d_nj
+    constexpr PbAsym() : d(), e()
+    {
+        d[0][0] = 1.0;
+        for (int n = 0; n + 1 < PB_NA; ++n) {
+            for (int j = 0; j <= n + 1; ++j) {
+                double v = 0.0;
+                if (j <= n) {
+                    const double q = 2.5 + n + j;
+                    v += 4.0 * q * q * d[n][j];
+                }
+                if (j >= 1) {
+                    const double q = 2.5 + n + (j - 1);
+                    v -= 4.0 * q * (q + 1.0) * d[n][j - 1];
+                }
+                d[n + 1][j] = v;
+            }
+        }
+        for (int n = 0; n < PB_NA; ++n)
+            for (int j = 0; j <= n; ++j) e[n][j] = -2.0 * (2.5 + n + j) * d[n][j];
+    }
+};
+static constexpr PbAsym PB_ASYM{};
+
+SWIM_HD void pb_node_far(double alpha, double eps, double t, double h1c, double& fh, double& fg)
+{
+    const double e2 = eps * eps, R2 = t + e2, R = sqrt(R2), a2 = alpha * alpha;
+    const double w = 1.0 / (a2 * R2), y = e2 / R2;
+    double sg = 0.0, sr = 0.0, wn = 1.0;
+#pragma unroll 1
+    for (int n = 0; n < PB_NA; ++n) {
+        double pg = PB_ASYM.d[n][n], pr = PB_ASYM.e[n][n];
+#pragma unroll 1
+        for (int j = n - 1; j >= 0; --j) {
+            pg = pg * y + PB_ASYM.d[n][j];
+            pr = pr * y + PB_ASYM.e[n][j];
+        }
+        sg += wn * pg;
+        sr += wn * pr;
+        wn *= w;
+    }
+    const double pre = 3.0 * e2 * eps / (2.0 * PI * a2 * R2 * R2 * R);
+    const double g = -pre * sg;
+    const double rg = -pre * (t / R2) * sr;
+    const double m = 1.0 - y * (eps / R);
+    const double M = (rg - m / (2.0 * PI)) / a2;
+    const double Mt = M / t;
+    fg = (g - 2.0 * Mt) / t;
+    fh = Mt - g - h1c;
+}
+
+// the sweep's node range of a system: nodes [kS, kL] take pb_node_sweep
+// (delta >= 1/4 and alpha r <= PB_ZF); below kS the near-contact series,
+// beyond kL the far field
+SWIM_HD void pb_sweep_range(const SysConst<double>& C, int& kS, int& kL)
+{
+    const double alpha = sqrt(C.a2);
+    int lo = 0, hi = PB_NODES;  // first node with delta >= 1/4
+    while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (pb_node_t(C.its, mid) * C.inv_e2 >= 0.25) hi = mid;
+        else lo = mid + 1;
+    }
+    kS = lo;
+    lo = 0;
+    hi = PB_NODES;  // first node with alpha r > PB_ZF
+    while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (alpha * sqrt(pb_node_t(C.its, mid)) > PB_ZF) hi = mid;
+        else lo = mid + 1;
+    }
+    kL = lo - 1;
+}
+
+// the node values of a system outside the sweep (k < kS or k > kL)
+SWIM_HD void pb_node_outside(const SysConst<double>& C, int k, int kS, double& fh, double& fg)
+{
+    const double t = pb_node_t(C.its, k);
+    if (k < kS)
+        kernel_paper_brinkman(C, t, fh, fg);  // delta < 1/4: the series
+    else
+        pb_node_far(sqrt(C.a2), C.eps, t, C.h1c, fh, fg);
+}
+
+// Host form of the sweep (the device kernel splits the same sums over a
+// workgroup): FP64 values Ht, H2 of every table node of a system with the
+// paper's blob at alpha > 0 (C.paper == 2).
+inline void pb_table_nodes_host(const SysConst<double>& C, double* fh, double* fg)
+{
+    const double alpha = sqrt(C.a2), eps = C.eps;
+    int kS, kL;
+    pb_sweep_range(C, kS, kL);
+    for (int k = 0; k < PB_NODES; ++k)
+        if (k < kS || k > kL) pb_node_outside(C, k, kS, fh[k], fg[k]);
+    if (kL < kS) return;
+    const int ng = kL + 1;
+    double* ga = new double[ng];
+    double* gb = new double[ng];
+    double* gc = new double[ng];
+    double ulo = 0.0;
+    for (int k = 1; k <= kL; ++k) {
+        const double t = pb_node_t(C.its, k);
+        const double uhi = asinh(sqrt(t) / eps);
+        pb_gap(alpha, eps, ulo, uhi, k > kS, alpha * sqrt(t) <= 2.0, &ga[k], &gb[k], &gc[k]);
+        ulo = uhi;
+    }
+    const double rL = sqrt(pb_node_t(C.its, kL));
+    double B = 0.0;
+    for (int p = 0; p < 64; ++p) B += pb_tail_panel(alpha, eps, rL, p, 64);
+    double* Bk = new double[ng];
+    for (int k = kL; k >= kS; --k) {
+        Bk[k] = B;
+        if (k > kS) B += gb[k];
+    }
+    double A = 0.0, Cq = 0.0;
+    for (int k = 1; k <= kL; ++k) {
+        A += ga[k];
+        Cq += gc[k];
+        if (k >= kS) pb_node_sweep(alpha, eps, pb_node_t(C.its, k), A, Bk[k], Cq, C.h1c, fh[k], fg[k]);
+    }
+    delete[] ga;
+    delete[] gb;
+    delete[] gc;
+    delete[] Bk;
 }
 
 }  // namespace swim

@@ -12,8 +12,8 @@ The experiment:
    model; the first ``train_cap`` completed ones whose head stays within
    1.5 beat amplitudes of its start give (alpha,
    ln S_b, ln S_s, b, omega) -> 16 head displacements and the mean speed
-   (about 5 % of the draws qualify, so 65536 training runs take about 1.4M
-   draws);
+   (with the paper's blob about 2.3 % of the draws qualify, so 65536
+   training runs take about 3M draws);
 3. training: Adam (lr 1e-3, batch 1024, ``epochs`` epochs) on the GPU with
    the library's BF16 MFMA forward and backward kernels;
 4. prescreen ``n_prop`` fresh prior draws at ``factor * tol`` with the
@@ -129,7 +129,7 @@ def posterior_summary(theta):
     return dict(mean=theta.mean(0), lo=np.quantile(theta, 0.05, axis=0), hi=np.quantile(theta, 0.95, axis=0))
 
 
-def run(ctx, data, N=128, n_c1=4096, n_train_runs=1_400_000, train_cap=65536, epochs=20, n_prop=1 << 20,
+def run(ctx, data, N=128, n_c1=4096, n_train_runs=3_000_000, train_cap=65536, epochs=20, n_prop=1 << 20,
         factor=2.0, prop_seed=5, model=None, keep_surrogate=False):
     """The whole comparison.  Plain ABC runs on the same n_prop proposals
     (same Philox seed) as the prescreen, so the surrogate's accepted set is

@@ -336,7 +336,7 @@ def tmcmc_run(ctx, model, lo, hi, data, N, n, seed, cv_target=1.0, cov_scale=0.2
                 runs=int(runs[0]), seconds=float(secs[0]))
 
 
-def swim_kernel_eval_host(dtype, alpha, eps, t, blob=0):
+def swim_kernel_eval_host(dtype, alpha, eps, t, blob=SWIM_BLOB_PAPER):
     t_, t_p = _h(t, np.float64, _DP)
     h1t, h2 = np.empty_like(t_), np.empty_like(t_)
     h1c = ctypes.c_double()

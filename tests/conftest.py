@@ -18,3 +18,14 @@ def oracle_core():
     from oracle import core
     core.lib()
     return core
+
+
+@pytest.fixture(scope="module")
+def reading_blob_module():
+    """The oracle's kernel functions use the blob of the kernel reading (not
+    its default, the paper's blob) for the whole module: modules that pin
+    that kernel, or run the oracle's forward model at sizes where the paper
+    blob's per-pair quadrature would take hours."""
+    from oracle import core
+    with core.reading_blob():
+        yield

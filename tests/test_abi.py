@@ -11,6 +11,8 @@ import pytest
 
 from paper_1910_12007_amd import inputs, swim
 
+pytestmark = pytest.mark.usefixtures("reading_blob_module")
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -49,7 +51,7 @@ def test_host_kernel_values_match_oracle(oracle_core, dtype, tol1, tol2):
             if dtype == swim.SWIM_F32:
                 t = t.astype(np.float32).astype(np.float64)
             H1o, H2o = oracle_core.kernel(alpha, eps, t)
-            h1t, h2, h1c = swim.swim_kernel_eval_host(dtype, alpha, eps, t)
+            h1t, h2, h1c = swim.swim_kernel_eval_host(dtype, alpha, eps, t, blob=swim.SWIM_BLOB_READING)
             assert abs(h1c / H1o[0] - 1) < (1e-15 if dtype == swim.SWIM_F64 else 1e-7)
             assert h1t[0] == 0.0
             e1 = np.abs(h1t[1:] - (H1o[1:] - H1o[0])) / _scale(H1o[1:], H1o[0], t[1:], H2o[1:])
@@ -68,7 +70,7 @@ def test_host_kernel_far_octaves_match_oracle(oracle_core, alpha):
         eps = 1.5 / (N - 1)
         t = (eps ** 2 * np.logspace(4, 12.5, 240)).astype(np.float32).astype(np.float64)
         H1o, H2o = oracle_core.kernel(alpha, eps, np.concatenate([[0.0], t]))
-        h1t, h2, _ = swim.swim_kernel_eval_host(swim.SWIM_F32, alpha, eps, t)
+        h1t, h2, _ = swim.swim_kernel_eval_host(swim.SWIM_F32, alpha, eps, t, blob=swim.SWIM_BLOB_READING)
         sc = _scale(H1o[1:], H1o[0], t, H2o[1:])
         e1 = np.abs(h1t - (H1o[1:] - H1o[0])) / sc
         e2 = np.abs(h2 - H2o[1:]) * t / sc

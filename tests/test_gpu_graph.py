@@ -71,7 +71,13 @@ def test_graph_replays_match_eager(ctx, dtype):
         swim.swim_pair_velocity(ctx, np.array([0, 512]), [0.5], [0.01], x, x.flip(0).contiguous(), x, x, u, v)
         torch.cuda.synchronize()
 
+    # FP64 takes the reading's blob: the paper blob's per-pair quadrature
+    # would make the 640-point system's seven runs minutes long (its FP32
+    # tables, the default, are replayed here; test_gpu_paper_blob replays a
+    # graph that rebuilds them)
+    blob = swim.SWIM_BLOB_READING if dtype == swim.SWIM_F64 else swim.SWIM_BLOB_PAPER
     try:
+        swim.swim_set_option(ctx, swim.SWIM_OPT_BLOB, blob)
         swim.swim_set_option(ctx, swim.SWIM_OPT_GRAPH, 0)
         ref = run()
         assert np.all(ref[2] == 0) and np.all(ref[3] == steps)
@@ -105,3 +111,4 @@ def test_graph_replays_match_eager(ctx, dtype):
         assert swim.swim_get_option(ctx, swim.SWIM_OPT_GRAPH_LAUNCHES) - launches0 == 5
     finally:
         swim.swim_set_option(ctx, swim.SWIM_OPT_GRAPH, 1)
+        swim.swim_set_option(ctx, swim.SWIM_OPT_BLOB, swim.SWIM_BLOB_PAPER)

@@ -14,7 +14,7 @@ same rounded values.
 import numpy as np
 import pytest
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("reading_blob_module")]
 
 torch = pytest.importorskip("torch")
 
@@ -29,6 +29,7 @@ def ctx():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     c = swim.Context(0)
+    swim.swim_set_option(c, swim.SWIM_OPT_BLOB, swim.SWIM_BLOB_READING)
     yield c
     c.close()
 
@@ -39,6 +40,12 @@ def dev(a, dtype):
 
 def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def rel_max(a, b):
+    """max_i |a_i - b_i| / max_i |b_i|: point by point, so that a few wrong
+    points (near contact, a block's tail) cannot hide in a norm."""
+    return float(np.max(np.abs(np.ravel(a) - np.ravel(b))) / np.max(np.abs(np.ravel(b))))
 
 
 def _systems():
@@ -67,8 +74,9 @@ def test_pair_velocity_matches_oracle(ctx, oracle_core, dtype, tol):
     for s in range(len(alphas)):
         sl = slice(off[s], off[s + 1])
         ox, oy = oracle_core.velocity(X[sl], Y[sl], FX[sl], FY[sl], alphas[s], epss[s])
-        e = rel(np.concatenate([gx[sl], gy[sl]]), np.concatenate([ox, oy]))
-        assert e < tol, (s, _systems()[s], e)
+        g, r = np.concatenate([gx[sl], gy[sl]]), np.concatenate([ox, oy])
+        e, em = rel(g, r), rel_max(g, r)
+        assert e < tol and em < tol, (s, _systems()[s], e, em)
 
 
 @pytest.mark.parametrize("alpha", [0.0, 0.7])
@@ -96,7 +104,7 @@ def test_pair_velocity_far_pairs(ctx, oracle_core, alpha):
     torch.cuda.synchronize()
     ox, oy = oracle_core.velocity(X, Y, FX, FY, alpha, eps)
     g = np.concatenate([ux.cpu().double().numpy(), uy.cpu().double().numpy()])
-    assert rel(g, np.concatenate([ox, oy])) < 1e-5
+    assert rel(g, np.concatenate([ox, oy])) < 1e-5 and rel_max(g, np.concatenate([ox, oy])) < 1e-5
 
 
 @pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-11), (swim.SWIM_F32, 1e-4)])
@@ -173,9 +181,11 @@ def test_single_swimmer_run_matches_oracle(ctx, oracle_core, dtype, tol, alpha):
 @pytest.mark.parametrize("dtype,tol", [(swim.SWIM_F64, 1e-12), (swim.SWIM_F32, 1e-4)])
 def test_uneven_batch_matches_oracle(ctx, oracle_core, dtype, tol):
     """Systems of 64 to 512 points (every persistent-kernel bucket), 60 steps,
-    with 1, 2 and 4 wavefronts per system.  The heads start at the origin
-    (x0 = -1): the run is short enough for the head to move ~1e-5, which FP32
-    outputs resolve only near zero."""
+    with 1, 2 and 4 wavefronts per system (one wave only for the systems of
+    up to 256 points: larger ones need at least two, and asking for one is
+    an error).  The heads start at the origin (x0 = -1): the run is short
+    enough for the head to move ~1e-5, which FP32 outputs resolve only near
+    zero."""
     Ns = [64, 96, 160, 200, 256, 320, 448, 512, 128, 64]
     rng = np.random.Generator(np.random.PCG64(41))
     P = inputs.param_rows(len(Ns), Sb=0.01, Ss=100.0, x0=-1.0)
@@ -186,11 +196,13 @@ def test_uneven_batch_matches_oracle(ctx, oracle_core, dtype, tol):
     try:
         for wps in (1, 2, 4):
             swim.swim_set_option(ctx, swim.SWIM_OPT_WPS, wps)
-            obs, speed, st = run_forward(ctx, dtype, Ns, None, P, steps, dt, 20)
-            for i, N in enumerate(Ns):
-                assert st[i] == 0 and refs[i]["status"] == 0
-                check_traj(obs[i], refs[i]["obs"][0], np.array([0.0, 0.0]), tol, dtype, steps, 1.0)
-            again = run_forward(ctx, dtype, Ns, None, P, steps, dt, 20)
+            sel = [i for i, N in enumerate(Ns) if wps > 1 or N <= 256]
+            Ns_w = [Ns[i] for i in sel]
+            obs, speed, st = run_forward(ctx, dtype, Ns_w, None, P[sel], steps, dt, 20)
+            for k, i in enumerate(sel):
+                assert st[k] == 0 and refs[i]["status"] == 0
+                check_traj(obs[k], refs[i]["obs"][0], np.array([0.0, 0.0]), tol, dtype, steps, 1.0)
+            again = run_forward(ctx, dtype, Ns_w, None, P[sel], steps, dt, 20)
             assert np.array_equal(again[0], obs), "runs are not bit-reproducible"
     finally:
         swim.swim_set_option(ctx, swim.SWIM_OPT_WPS, 0)
@@ -303,7 +315,43 @@ def test_dense_sample_velocity_at_full_size(ctx, oracle_core):
         torch.cuda.synchronize()
         g = np.concatenate([ux.cpu().double().numpy(), uy.cpu().double().numpy()])
         ref = np.concatenate([ox, oy])
-        assert rel(g, ref) < tol, (dtype, rel(g, ref))
+        assert rel(g, ref) < tol and rel_max(g, ref) < tol, (dtype, rel(g, ref), rel_max(g, ref))
+
+
+def test_dense_sample_run(ctx, oracle_core):
+    """The dense workload's sample 0 (8 swimmers x 512 points, its alpha) as
+    a run at the benchmark's dt = 2e-5/32: the FP64 run against the oracle
+    over its first 3 steps (the oracle sums 4096^2 pairs per step on the host
+    cores), head of every swimmer every step, at 1e-12 of the displacement;
+    the FP32 run against the FP64 run over 100 steps, every 10, at 1e-4 of
+    the displacement (plus one FP32 spacing of the stored positions)."""
+    lay = inputs.dense_layout(n_samples=1, seed=3)[0]
+    P = dev(lay, torch.float64)
+    dt = 2e-5 / 32
+    x0 = lay[:, 7:9] + np.array([1.0, 0.0])
+    out = {}
+    for dtype, steps, oe in ((swim.SWIM_F64, 3, 1), (swim.SWIM_F64, 100, 10), (swim.SWIM_F32, 100, 10)):
+        td = DT[dtype]
+        obs = torch.empty((8, steps // oe, 2), dtype=td, device="cuda")
+        speed = torch.empty(8, dtype=td, device="cuda")
+        st = torch.empty(1, dtype=torch.int32, device="cuda")
+        swim.swim_forward(ctx, [512], [8], P, steps, dt, oe, 1.5, obs, speed, st)
+        torch.cuda.synchronize()
+        assert st.item() == 0
+        out[(dtype, steps)] = obs.cpu().double().numpy()
+    ref = oracle_core.forward(lay, 512, 3, dt, 1)
+    assert ref["status"] == 0
+    got = out[(swim.SWIM_F64, 3)]
+    disp = np.linalg.norm(ref["obs"] - x0[:, None, :])
+    err = np.linalg.norm(got - ref["obs"])
+    print({"fp64_vs_oracle": err / disp})
+    assert err <= 1e-12 * disp
+    o64, o32 = out[(swim.SWIM_F64, 100)], out[(swim.SWIM_F32, 100)]
+    disp = np.linalg.norm(o64 - x0[:, None, :])
+    floor = np.linalg.norm(np.spacing(np.abs(o64).astype(np.float32)))
+    err = np.linalg.norm(o32 - o64)
+    print({"fp32_vs_fp64": err / disp})
+    assert err <= 1e-4 * disp + floor
 
 
 def test_blowup_and_bad_parameters_are_statuses(ctx):
@@ -331,6 +379,16 @@ def test_argument_errors(ctx):
     with pytest.raises(swim.SwimError):
         swim.swim_forward(ctx, [64], None, P, 0, 1e-4, 1, 1.5, x, x[:1], torch.zeros(1, dtype=torch.int32,
                                                                                           device="cuda"))
+    # one wave per system for a 512-point system would carry nine point
+    # windows per lane: that shape is not built, and asking for it is an error
+    obs = torch.empty((1, 1, 2), dtype=torch.float32, device="cuda")
+    swim.swim_set_option(ctx, swim.SWIM_OPT_WPS, 1)
+    try:
+        with pytest.raises(swim.SwimError, match="SWIM_OPT_WPS"):
+            swim.swim_forward(ctx, [512], None, P, 1, 1e-6, 1, 1.5, obs, x[:1], torch.zeros(1, dtype=torch.int32,
+                                                                                            device="cuda"))
+    finally:
+        swim.swim_set_option(ctx, swim.SWIM_OPT_WPS, 0)
 
 
 def test_abc_distance_and_select_match_oracle(ctx):

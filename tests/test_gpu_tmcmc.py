@@ -14,7 +14,7 @@ eqs. (likelihood)-(fitness)).
 import numpy as np
 import pytest
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("reading_blob_module")]
 
 torch = pytest.importorskip("torch")
 
@@ -26,6 +26,7 @@ def ctx():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     c = swim.Context(0)
+    swim.swim_set_option(c, swim.SWIM_OPT_BLOB, swim.SWIM_BLOB_READING)
     yield c
     c.close()
 

@@ -17,6 +17,8 @@ from scipy import integrate
 
 from oracle import core
 
+pytestmark = pytest.mark.usefixtures("reading_blob_module")
+
 
 @pytest.mark.parametrize("alpha", [0.0, 0.4, 3.0, 10.0])
 def test_blob_mass_is_the_integral_of_the_blob(alpha):

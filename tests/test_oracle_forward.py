@@ -12,6 +12,8 @@ import pytest
 
 from paper_1910_12007_amd import inputs
 
+pytestmark = pytest.mark.usefixtures("reading_blob_module")
+
 
 def _run(core, N=24, steps=40, dt=1e-4, obs_every=10, **kw):
     P = inputs.param_rows(1, **kw)

@@ -10,6 +10,8 @@ import mpmath as mp
 import numpy as np
 import pytest
 
+pytestmark = pytest.mark.usefixtures("reading_blob_module")
+
 EPS64 = 1.5 / 63      # blob width at N = 64
 EPS512 = 1.5 / 511    # blob width at N = 512
 

@@ -20,6 +20,8 @@ import pytest
 
 from oracle import core
 
+pytestmark = pytest.mark.usefixtures("reading_blob_module")
+
 NF, NH = 50, 24
 DS = 1.0 / (NF - 1)
 HR, DN = 0.05, DS
