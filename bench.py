@@ -177,13 +177,16 @@ def mlp_leg(ctx, stream, rows=1 << 20, train_rows=65536, batch=1024, epochs=2):
             "train_frac": train_tf / BF16_PEAK_TFLOPS, "dtype": "bf16 operands, fp32 accumulation"}
 
 
-def dense_leg(ctx, stream, samples=64, steps=1000):
+def dense_leg(ctx, stream, samples=64, steps=1000, dt_div=64):
     """Large-N dense workload: `samples` independent systems of 8 interacting
     swimmers of N = 512 (4096 points) on a 2 x 4 grid of spacing 1.5, random
     beat phases, alpha ~ U[0, 10] (seed 3), FP32.  The stated dt = 2e-5 is
-    beyond forward Euler's stability bound at N = 512 (dt * rho ~ 51), so the
-    run uses the largest stable power-of-two fraction, dt / 32; the work per
-    step does not depend on dt.  Runs on the per-step large-system kernel.
+    beyond forward Euler's stability bound at N = 512 (dt * rho ~ 51 with the
+    other blob, ~1.4 times more with the paper's, whose H1(0) - H1(ds) is
+    larger), so the run uses a stable power-of-two fraction: dt / 64 (with
+    the paper's blob 56 of 64 samples blow up within 50 steps at dt / 32,
+    none in 1000 at dt / 48 or dt / 64); the work per step does not depend
+    on dt.  Runs on the per-step large-system kernel.
     (The parity of one full-size velocity evaluation against the FP64
     oracle is a test: test_dense_sample_velocity_at_full_size.)"""
     import torch
@@ -192,9 +195,10 @@ def dense_leg(ctx, stream, samples=64, steps=1000):
     P = torch.from_numpy(lay.reshape(-1, 9)).to("cuda")
     N = np.full(samples, 512, np.int32)
     nsw = np.full(samples, 8, np.int32)
-    dt = 2e-5 / 32
+    dt = 2e-5 / dt_div
     nfil = samples * 8
-    obs = torch.empty((nfil, steps // 100, 2), dtype=torch.float32, device="cuda")
+    oe = min(100, steps)
+    obs = torch.empty((nfil, steps // oe, 2), dtype=torch.float32, device="cuda")
     speed = torch.empty(nfil, dtype=torch.float32, device="cuda")
     status = torch.empty(samples, dtype=torch.int32, device="cuda")
     done = torch.empty(samples, dtype=torch.int32, device="cuda")
@@ -202,14 +206,14 @@ def dense_leg(ctx, stream, samples=64, steps=1000):
     warm = torch.empty((nfil, 1, 2), dtype=torch.float32, device="cuda")
     swim.swim_forward(ctx, N, nsw, P, 10, dt, 10, 1.5, warm, speed, status, done, stream=stream)  # warm-up
     ev[0].record(stream)
-    swim.swim_forward(ctx, N, nsw, P, steps, dt, 100, 1.5, obs, speed, status, done, stream=stream)
+    swim.swim_forward(ctx, N, nsw, P, steps, dt, oe, 1.5, obs, speed, status, done, stream=stream)
     ev[1].record(stream)
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[1])
     d = done.cpu().numpy().astype(np.int64)
     pairs = float(np.sum(d * 4096 * 4096))
     out = {"workload": f"{samples} samples x 8 swimmers x N=512 (2x4 grid, spacing 1.5), {steps} Euler steps of "
-                       f"dt=2e-5/32 (stability), FP32, per-step large-system kernel",
+                       f"dt=2e-5/{dt_div} (stability), FP32, per-step large-system kernel",
            "ms": ms, "pair_evals_per_s": pairs / (ms * 1e-3), "swimmer_steps_per_s": float(np.sum(d)) * 8 / (ms * 1e-3),
            "runs_stopped": int(np.sum(status.cpu().numpy() != 0)),
            "fp32_tflops": FP32_FLOP_PER_PAIR * pairs / (ms * 1e-3) / 1e12,
@@ -528,6 +532,9 @@ def surrogate_leg(ctx, data):
         "training_set_s": t["t_data"], "training_s": t["t_train"],
         "surrogate_accepts_per_s_with_training": s["accepts_per_s_with_training"],
         "gain_with_training": r["gain_with_training"],
+        "stopped_early": s["stopped_early"], "rerun_ms_without_early_stop": s["ms_rerun_without_early_stop"],
+        "gain_without_early_stop": r["gain_without_early_stop"],
+        "same_accepted_without_early_stop": s["same_accepted_without_early_stop"],
     }
 
 
@@ -549,6 +556,10 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times), the reference "
                          "for scaling the HBM byte counters, and exit")
+    ap.add_argument("--dense-only", type=int, default=0, metavar="STEPS",
+                    help="only run the large-N dense workload for this many Euler steps (for profiling "
+                         "its kernel), print its record and exit")
+    ap.add_argument("--dense-div", type=int, default=64, help="the dense workload's dt is 2e-5 / this")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the swimmer batches are "
@@ -572,6 +583,10 @@ def main():
     ctx = swim.Context(0)
     # a stream of our own: the library runs on it and the events time it
     stream = torch.cuda.Stream()
+    if args.dense_only:
+        print(json.dumps(dense_leg(ctx, stream, steps=args.dense_only, dt_div=args.dense_div)), flush=True)
+        ctx.close()
+        return
     n, N, steps, dt, obs_every = args.n, 128, args.euler_steps, 5e-5, 100
     n_obs = steps // obs_every
     theta = swim.abc_prior_draw(1, n, inputs.PRIOR_LO, inputs.PRIOR_HI)
@@ -669,7 +684,7 @@ def main():
     out["surrogate_mfma"] = mlp_leg(ctx, stream)
     out["fused_vs_per_sample"] = per_sample_leg(ctx, stream, P)
     if not args.no_dense:
-        out["dense"] = dense_leg(ctx, stream)
+        out["dense"] = dense_leg(ctx, stream, dt_div=args.dense_div)
     if not args.no_pmc:
         # a context of its own: the autotuner's launch shapes for this
         # workload stay out of the other legs

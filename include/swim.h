@@ -60,6 +60,9 @@ extern "C" {
 #define SWIM_ST_BOUND 2     /* |x| or |y| exceeded 1e3; run stopped   */
 #define SWIM_ST_BADPARAM 3  /* parameters outside the domain (alpha < 0,
                                alpha*eps > 1, non-finite); not run     */
+#define SWIM_ST_REJECTED 4  /* abc_prescreened only: the run stopped once its head's
+                               running squared deviation from the data passed the
+                               tolerance (its distance exceeds it)              */
 
 /* Parameter row of one filament: 9 doubles in this order. */
 #define SWIM_P_ALPHA 0 /* Brinkman resistance alpha >= 0 (one value per system)  */
@@ -136,6 +139,7 @@ int swim_version(void);
 #define SWIM_OPT_GRAPH_LAUNCHES 4
 #define SWIM_OPT_GRAPH_CAPTURES 5
 #define SWIM_OPT_BLOB 6
+#define SWIM_OPT_EARLY_STOP 7 /* abc_prescreened's early stop of rejected re-runs: 1 (default) or 0 */
 #define SWIM_BLOB_READING 0 /* the unit-mass blob whose Brinkmanlet has a closed form for all alpha */
 #define SWIM_BLOB_PAPER 1   /* default: eq. (eqnblob), 3 eps^3 / (2 pi (r^2 + eps^2)^(5/2)) */
 int swim_set_option(swim_ctx *ctx, int32_t key, int32_t value);
@@ -622,7 +626,12 @@ int surrogate_dataset(swim_ctx *ctx, const abc_model *model, int32_t N, int64_t 
  * start (1, 0)) is <= factor * tol survive.  The first min(survivors, cap)
  * survivors, in draw order, are re-run on the plain forward model (N
  * points, model's steps, dt, dtype) and accepted when their ABC distance to
- * data (host double[n_obs][2]) is finite and <= tol.  Host outputs:
+ * data (host double[n_obs][2]) is finite and <= tol.  The tolerance being
+ * known, a re-run stops (status SWIM_ST_REJECTED, distance +inf) once the
+ * running sum of its squared head deviations from the data exceeds
+ * 2 n_obs tol^2 (1 + 1e-6): that sum only grows, so the run's distance
+ * would exceed tol (SWIM_OPT_EARLY_STOP = 0 runs every survivor to the
+ * end; the accepted set is the same).  Host outputs:
  * theta_out double[cap][3], dist_out double[cap], accept_out uint8[cap],
  * *n_surv = survivors (may exceed cap), ms_out float[2] (prescreen and
  * re-run milliseconds on the device) or NULL. */

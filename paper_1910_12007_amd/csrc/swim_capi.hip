@@ -99,6 +99,7 @@ struct swim_ctx {
     int opt_big_tpl = 0;  // targets per lane of the large-system kernel (0: automatic)
     int opt_graph = 1;    // 0: eager launches; 1: capture on a repeated layout; 2: capture always
     int opt_blob = 1;     // 1: the paper's blob (eq. eqnblob); 0: the kernel reading's blob
+    int opt_early_stop = 1;  // abc_prescreened stops re-runs whose distance already exceeds tol
     int tuned_wps[2][9] = {};  // autotuned waves per system [dtype][tpl] (0: not tuned)
     FwdGraph graphs[N_GRAPHS];
     uint64_t graph_clock = 0, last_key = 0;
@@ -509,6 +510,8 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     h.add(run.obs_every);
     h.add(run.n_obs);
     h.add(run.eps_over_ds);
+    h.add(run.stop_data);
+    h.add(run.stop_ssq);
     h.add(tpl_big);
     h.add(c->opt_blob);
     for (const Bucket& q : bk) {
@@ -606,12 +609,15 @@ struct MlpAct {
     float* pre[4];
     float* H[4];
     float *Y, *dY, *dA[2], *rowsq;
+    float* ws;         // split-K partial sums of the GEMMs
+    int64_t ws_floats;
 };
 
 int mlp_act(swim_ctx* c, int64_t M, MlpAct* a)
 {
     const int64_t H = 256, O = 33;
-    const int64_t total = 8 * M * H + 2 * M * O + 2 * M * H + M;
+    const int64_t ws = 1 << 20;  // partial sums: 16 slices of 256 x 256, or 4 of 1024 x 256
+    const int64_t total = 8 * M * H + 2 * M * O + 2 * M * H + M + ws;
     TRY(ensure(c, B_MLP_ACT, (size_t)total * 4));
     float* p = (float*)c->buf[B_MLP_ACT].p;
     for (int l = 0; l < 4; ++l) a->pre[l] = p + l * M * H;
@@ -621,6 +627,8 @@ int mlp_act(swim_ctx* c, int64_t M, MlpAct* a)
     a->dA[0] = a->dY + M * O;
     a->dA[1] = a->dA[0] + M * H;
     a->rowsq = a->dA[1] + M * H;
+    a->ws = a->rowsq + M;
+    a->ws_floats = ws;
     return SWIM_OK;
 }
 
@@ -633,11 +641,12 @@ int mlp_forward(const float* X, const float* P, int64_t M, const MlpAct& a, floa
         const float* W = P + mlp_offW(l);
         const float* b = P + mlp_offb(l);
         if (l < MLP_L - 1) {
-            HIPCHK(launch_gemm_bf16(1, (int)M, N, K, in, ldin, 1, W, N, 1, a.pre[l], N, b, a.H[l], st));
+            HIPCHK(launch_gemm_bf16(1, (int)M, N, K, in, ldin, 1, W, N, 1, a.pre[l], N, b, a.H[l], a.ws, a.ws_floats,
+                                    st));
             in = a.H[l];
             ldin = N;
         } else {
-            HIPCHK(launch_gemm_bf16(2, (int)M, N, K, in, ldin, 1, W, N, 1, Y, N, b, nullptr, st));
+            HIPCHK(launch_gemm_bf16(2, (int)M, N, K, in, ldin, 1, W, N, 1, Y, N, b, nullptr, a.ws, a.ws_floats, st));
         }
     }
     return SWIM_OK;
@@ -657,13 +666,14 @@ int mlp_backward(const float* X, const float* T, const float* P, int64_t M, cons
         const int K = MLP_W[l], N = MLP_W[l + 1];
         const float* Hin = l > 0 ? a.H[l - 1] : X;
         // dW_l = Hin^T dA  (K x N, summed over the M rows)
-        HIPCHK(launch_gemm_bf16(0, K, N, (int)M, Hin, 1, K, dA, N, 1, G + mlp_offW(l), N, nullptr, nullptr, st));
+        HIPCHK(launch_gemm_bf16(0, K, N, (int)M, Hin, 1, K, dA, N, 1, G + mlp_offW(l), N, nullptr, nullptr, a.ws,
+                                a.ws_floats, st));
         HIPCHK(launch_colsum((int)M, N, dA, N, G + mlp_offb(l), st));
         if (l > 0) {
             // dA_{l-1} = (dA W_l^T) * gelu'(pre_{l-1})
             float* out = a.dA[cur];
             HIPCHK(launch_gemm_bf16(3, (int)M, K, N, dA, N, 1, P + mlp_offW(l), 1, N, out, K, nullptr, a.pre[l - 1],
-                                    st));
+                                    a.ws, a.ws_floats, st));
             dA = out;
             cur ^= 1;
         }
@@ -755,6 +765,9 @@ int swim_set_option(swim_ctx* c, int32_t key, int32_t value)
     } else if (key == SWIM_OPT_BLOB) {
         if (value != SWIM_BLOB_READING && value != SWIM_BLOB_PAPER) return fail(SWIM_EINVAL, "blob must be 0 or 1");
         c->opt_blob = value;
+    } else if (key == SWIM_OPT_EARLY_STOP) {
+        if (value != 0 && value != 1) return fail(SWIM_EINVAL, "early stop must be 0 or 1");
+        c->opt_early_stop = value;
     } else {
         return fail(SWIM_EINVAL, "unknown option %d", key);
     }
@@ -768,6 +781,7 @@ int swim_get_option(swim_ctx* c, int32_t key, int32_t* value)
     else if (key == SWIM_OPT_BIG_TPL) *value = c->opt_big_tpl;
     else if (key == SWIM_OPT_GRAPH) *value = c->opt_graph;
     else if (key == SWIM_OPT_BLOB) *value = c->opt_blob;
+    else if (key == SWIM_OPT_EARLY_STOP) *value = c->opt_early_stop;
     else if (key == SWIM_OPT_GRAPH_LAUNCHES) *value = (int32_t)c->graph_launches;
     else if (key == SWIM_OPT_GRAPH_CAPTURES) *value = (int32_t)c->graph_captures;
     else return fail(SWIM_EINVAL, "unknown option %d", key);
@@ -1697,6 +1711,13 @@ int abc_prescreened(swim_ctx* c, const abc_model* m, int32_t N, const float* par
         r.obs_every = m->obs_every;
         r.n_obs = n_obs;
         r.eps_over_ds = m->eps_over_ds;
+        // the tolerance is known: a survivor stops as soon as its running
+        // sum of squared head deviations exceeds 2 n_obs tol^2 (a hair
+        // above, so that rounding never rejects a run the distance accepts)
+        if (c->opt_early_stop) {
+            r.stop_data = (const double*)c->buf[B_DATA].p;
+            r.stop_ssq = 2.0 * n_obs * tol * tol * (1.0 + 1e-6);
+        }
         TRY(forward_impl(c, m->dtype, n, Nv.data(), nullptr, rows, r, c->buf[B_OBS].p, c->buf[B_SPEED].p,
                          (int32_t*)c->buf[B_STATUS].p, nullptr, st));
         HIPCHK(launch_abc_distance(m->dtype, n, n_obs, c->buf[B_OBS].p, (const double*)c->buf[B_DATA].p,

@@ -32,6 +32,13 @@ struct Run {
     int32_t obs_every;
     int32_t n_obs;
     double eps_over_ds;
+    // early rejection against a known tolerance (persistent kernel, one
+    // swimmer per system): with stop_data ([n_obs][2] head data) set, a run
+    // stops with SWIM_ST_REJECTED_ once the running sum of its squared head
+    // deviations exceeds stop_ssq (the sum only grows, so its final
+    // distance exceeds the tolerance)
+    const double* stop_data = nullptr;
+    double stop_ssq = 0.0;
 };
 
 // all launchers return hipError_t of the launch
@@ -99,9 +106,10 @@ hipError_t launch_gauss_loglik(int dtype, int64_t n, int32_t n_obs, const void* 
                                const double* sigma, const int32_t* status, double* logl, hipStream_t st);
 
 // surrogate MLP (swim_mlp.hip)
+// ws (ws_floats floats, may be null): workspace of the split-K partial sums
 hipError_t launch_gemm_bf16(int epi, int M, int N, int K, const float* A, int64_t sam, int64_t sak,
                             const float* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc,
-                            const float* bias, float* aux, hipStream_t st);
+                            const float* bias, float* aux, float* ws, int64_t ws_floats, hipStream_t st);
 hipError_t launch_colsum(int M, int N, const float* A, int64_t lda, float* out, hipStream_t st);
 hipError_t launch_mse_grad(int M, int N, const float* Y, const float* T, float* dY, float* rowsq,
                            hipStream_t st);

@@ -18,6 +18,7 @@
 namespace swim {
 
 constexpr int32_t SWIM_ST_BADPARAM_ = 3;
+constexpr int32_t SWIM_ST_REJECTED_ = 4;
 
 
 // LDS ordering between lanes of one wavefront: a wavefront's LDS operations
@@ -761,6 +762,11 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
             for (int k = 0; k < 2 * r.n_obs; ++k) o[k] = (T)NAN;
         }
     }
+    // early rejection (one swimmer per system): the head lane's running sum
+    // of squared deviations from the data
+    const bool early = r.stop_data != nullptr && nsw == 1;
+    double ssq = 0.0;
+    bool rejected = false;
     // forces of the held points at the current time; owners publish them
     auto point_forces = [&]() {
 #pragma unroll
@@ -854,14 +860,15 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
             }
             point_forces();
             const bool b1 = __ballot(bad == 1) != 0, b2 = __ballot(bad == 2) != 0;
-            if (lane == 0) L.bad[wave] = (b1 ? 1 : 0) | (b2 ? 2 : 0);
+            const bool b4 = __ballot(rejected) != 0;
+            if (lane == 0) L.bad[wave] = (b1 ? 1 : 0) | (b2 ? 2 : 0) | (b4 ? 4 : 0);
         }
         __syncthreads();
         // the point waves' flags, one per lane, combined by ballot (uniform)
         const int bw = lane < pw ? L.bad[lane] : 0;
-        const int badw = (__ballot(bw & 1) ? 1 : 0) | (__ballot(bw & 2) ? 2 : 0);
+        const int badw = (__ballot(bw & 1) ? 1 : 0) | (__ballot(bw & 2) ? 2 : 0) | (__ballot(bw & 4) ? 4 : 0);
         if (badw) {
-            st = (badw & 1) ? 1 : 2;
+            st = (badw & 1) ? 1 : (badw & 2) ? 2 : SWIM_ST_REJECTED_;
             done = step + 1;
             break;
         }
@@ -874,8 +881,15 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
                     if (fl[q] & FL_HEAD) {
                         const int i = FWD_WIN * (wave + WPS * q) + lane - 2;
                         T* d = obs + ((f0 + i / N) * (int64_t)r.n_obs + o) * 2;
-                        d[0] = xh[q] + xl[q];
-                        d[1] = yh[q] + yl[q];
+                        const T hx = xh[q] + xl[q], hy = yh[q] + yl[q];
+                        d[0] = hx;
+                        d[1] = hy;
+                        if (early) {
+                            const double ex = (double)hx - r.stop_data[2 * o];
+                            const double ey = (double)hy - r.stop_data[2 * o + 1];
+                            ssq = fma(ex, ex, fma(ey, ey, ssq));
+                            rejected = ssq > r.stop_ssq;
+                        }
                     }
                 }
             }

@@ -9,6 +9,8 @@
 // weights and activations and FP32 accumulation; FP32 master weights are
 // kept for Adam.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 
@@ -63,11 +65,34 @@ __device__ __forceinline__ float gelu_grad_f(float x)
 // Workgroup tile 64 x 64 (4 waves of 32 x 32 = 2 x 2 MFMA tiles), k chunks of 32.
 constexpr int GT = 64, GK = 32, GPAD = 8;
 
+// epilogue of one output element (the split-K reduction applies it too)
+template <int EPI>
+__device__ __forceinline__ void gemm_epilogue(float v, int n, int64_t o, float* __restrict__ C,
+                                              const float* __restrict__ bias, float* __restrict__ aux)
+{
+    if (EPI == 1) {
+        v += bias[n];
+        C[o] = v;
+        aux[o] = gelu_f(v);
+    } else if (EPI == 2) {
+        C[o] = v + bias[n];
+    } else if (EPI == 3) {
+        C[o] = v * gelu_grad_f(aux[o]);
+    } else {
+        C[o] = v;
+    }
+}
+
+// Split K: with part != nullptr, workgroup z of the grid's third dimension
+// takes the k chunks [z kper, (z + 1) kper) and writes its raw sums to
+// part[z][M][N]; k_gemm_reduce adds the slices in order of z and applies the
+// epilogue (deterministic).  This fills the chip when the M x N tiles are
+// few (the weight gradients: 256 x 256 outputs summed over a batch of 1024).
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const float* __restrict__ A, int64_t sam,
                                                    int64_t sak, const float* __restrict__ B, int64_t sbk, int64_t sbn,
                                                    float* __restrict__ C, int64_t ldc, const float* __restrict__ bias,
-                                                   float* __restrict__ aux)
+                                                   float* __restrict__ aux, float* __restrict__ part, int kper)
 {
     __shared__ uint16_t As[GT][GK + GPAD];   // [m][k]
     __shared__ uint16_t Bs[GT][GK + GPAD];   // [n][k]
@@ -83,7 +108,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const fl
     // when its k stride is 1, along m (n) otherwise (the transposed operands
     // of the backward pass)
     const bool a_k_fast = sak == 1, b_n_fast = sbn == 1 || sbk != 1;
-    for (int k0 = 0; k0 < K; k0 += GK) {
+    const int kbeg = part ? (int)blockIdx.z * kper * GK : 0;
+    const int kend = part ? min(K, kbeg + kper * GK) : K;
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
 #pragma unroll
         for (int i = 0; i < (GT * GK) / 256; ++i) {
             const int e = tid + 256 * i;
@@ -130,20 +157,24 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const fl
                 const int m = m0 + wm + 16 * a + 4 * (lane >> 4) + r;
                 const int n = n0 + wn + 16 * b + (lane & 15);
                 if (m >= M || n >= N) continue;
-                float v = acc[a][b][r];
-                const int64_t o = (int64_t)m * ldc + n;
-                if (EPI == 1) {
-                    v += bias[n];
-                    C[o] = v;
-                    aux[o] = gelu_f(v);
-                } else if (EPI == 2) {
-                    C[o] = v + bias[n];
-                } else if (EPI == 3) {
-                    C[o] = v * gelu_grad_f(aux[o]);
-                } else {
-                    C[o] = v;
-                }
+                if (part)
+                    part[((int64_t)blockIdx.z * M + m) * N + n] = acc[a][b][r];
+                else
+                    gemm_epilogue<EPI>(acc[a][b][r], n, (int64_t)m * ldc + n, C, bias, aux);
             }
+}
+
+// C(m, n) = sum over z of part[z][m][n], z ascending, then the epilogue
+template <int EPI>
+__global__ void k_gemm_reduce(int M, int N, int S, const float* __restrict__ part, float* __restrict__ C, int64_t ldc,
+                              const float* __restrict__ bias, float* __restrict__ aux)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)M * N) return;
+    const int m = (int)(e / N), n = (int)(e % N);
+    float v = 0.0f;
+    for (int z = 0; z < S; ++z) v += part[(int64_t)z * M * N + e];
+    gemm_epilogue<EPI>(v, n, (int64_t)m * ldc + n, C, bias, aux);
 }
 
 // out[n] = sum_m A[m*lda + n]  (bias gradients): a workgroup sums 64
@@ -280,17 +311,36 @@ __global__ void k_scatter(int64_t n, const uint8_t* keep, const int32_t* offs, i
 // ---------------------------------------------------------------------------
 hipError_t launch_gemm_bf16(int epi, int M, int N, int K, const float* A, int64_t sam, int64_t sak, const float* B,
                             int64_t sbk, int64_t sbn, float* C, int64_t ldc, const float* bias, float* aux,
-                            hipStream_t st)
+                            float* ws, int64_t ws_floats, hipStream_t st)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
-    const dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+    const int gx = (N + GT - 1) / GT, gy = (M + GT - 1) / GT, chunks = (K + GK - 1) / GK;
+    // split K into S slices when the output tiles alone leave CUs idle
+    int S = 1, kper = chunks;
+    if (ws && chunks >= 2 && gx * gy < 256) {
+        S = std::min(chunks, (256 + gx * gy - 1) / (gx * gy));
+        while (S > 1 && (int64_t)S * M * N > ws_floats) --S;
+        kper = (chunks + S - 1) / S;
+        S = (chunks + kper - 1) / kper;
+    }
+    float* part = S > 1 ? ws : nullptr;
+    const dim3 grid(gx, gy, S);
+#define SWIM_GEMM_CASE(E)                                                                                          \
+    case E:                                                                                                        \
+        hipLaunchKernelGGL(k_gemm_bf16<E>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, \
+                           aux, part, kper);                                                                       \
+        if (part)                                                                                                  \
+            hipLaunchKernelGGL(k_gemm_reduce<E>, dim3((unsigned)(((int64_t)M * N + 255) / 256)), dim3(256), 0, st, \
+                               M, N, S, part, C, ldc, bias, aux);                                                  \
+        break;
     switch (epi) {
-    case 0: hipLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, aux); break;
-    case 1: hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, aux); break;
-    case 2: hipLaunchKernelGGL(k_gemm_bf16<2>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, aux); break;
-    case 3: hipLaunchKernelGGL(k_gemm_bf16<3>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, aux); break;
+        SWIM_GEMM_CASE(0)
+        SWIM_GEMM_CASE(1)
+        SWIM_GEMM_CASE(2)
+        SWIM_GEMM_CASE(3)
     default: return hipErrorInvalidValue;
     }
+#undef SWIM_GEMM_CASE
     return hipGetLastError();
 }
 

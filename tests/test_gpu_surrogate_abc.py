@@ -7,7 +7,8 @@
   (65536 completed training runs, 1M proposals prescreened at 2x the
   5th-percentile tolerance, survivors re-run on the plain FP32 model):
   accepted samples per second at least 5x those of plain ABC on the same
-  proposals, posterior means within 2 %, 90 % intervals overlapping.
+  proposals, posterior means within 2 %, 90 % intervals overlapping; the
+  same accepted set with the re-runs' early stop off.
 """
 import numpy as np
 import pytest
@@ -113,10 +114,24 @@ def test_prescreened_matches_stepwise_calls(ctx):
     assert r["n_surv"] == n and n > 0
     surv = idx.cpu().numpy()[:n]
     assert np.array_equal(r["theta"], theta[surv])
-    # re-run = plain ABC's distances for the same parameters
+    # re-run = plain ABC's distances for the same parameters: equal where a
+    # run is accepted; a run stopped early (its running squared deviation
+    # past the tolerance) has distance +inf where plain ABC's is > tol; with
+    # the early stop off, every distance equals plain ABC's
     pl = swim.abc_step(ctx, model, dat, np.full(n_prop, 128, np.int32), 9, 0, 0.05)
-    assert np.array_equal(r["dist"], pl["dist"][surv])
-    assert np.array_equal(r["accept"], np.isfinite(pl["dist"][surv]) & (pl["dist"][surv] <= tol))
+    ref = pl["dist"][surv]
+    assert np.array_equal(r["accept"], np.isfinite(ref) & (ref <= tol))
+    fin = np.isfinite(r["dist"])
+    assert np.array_equal(r["dist"][fin], ref[fin])
+    assert np.all(~np.isfinite(ref[~fin]) | (ref[~fin] > tol))
+    assert (~fin & np.isfinite(ref)).sum() > 0  # some runs did stop early
+    swim.swim_set_option(ctx, swim.SWIM_OPT_EARLY_STOP, 0)
+    try:
+        rf = swim.abc_prescreened(ctx, model, 128, params, in_mu, in_sd, out_mu, out_sd, sum_idx, dat, tol, factor,
+                                  n_prop, 9, n_prop)
+    finally:
+        swim.swim_set_option(ctx, swim.SWIM_OPT_EARLY_STOP, 1)
+    assert np.array_equal(rf["dist"], ref) and np.array_equal(rf["accept"], r["accept"])
     # a cap below the survivor count runs the first cap survivors only
     r2 = swim.abc_prescreened(ctx, model, 128, params, in_mu, in_sd, out_mu, out_sd, sum_idx, dat, tol, factor,
                               n_prop, 9, 7)
@@ -134,5 +149,7 @@ def test_surrogate_gain_over_plain_abc(ctx):
     assert s["not_in_plain"] == 0
     assert s["recall"] >= 0.98
     assert r["gain"] >= 5.0
+    # the early stop changes the cost, not the accepted set
+    assert s["same_accepted_without_early_stop"]
     assert np.all(r["mean_rel_err"] <= 0.02)
     assert np.all(r["intervals_overlap"])
