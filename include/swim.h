@@ -180,6 +180,27 @@ int swim_pair_velocity(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const int64_
                        const double *alpha, const double *eps, const void *x, const void *y,
                        const void *fx, const void *fy, void *ux, void *uy, void *stream);
 
+/* swim_pair_velocity for callers that cannot allocate memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, with the call's
+ * workspace (system offsets, alpha, eps, block list, per-system constants
+ * and FP32 kernel tables) in a fixed device array of the library instead of
+ * context allocations, and its few host values copied from the stack by one
+ * synchronous copy on the stream (no pinned staging).  It calls no
+ * hipMalloc, hipFree or other allocating routine.
+ * Limits: n_sys <= 64 systems and at most 4160 pair-kernel blocks (256
+ * targets each: about 1M points in all); beyond either, SWIM_EINVAL with a
+ * message and nothing launched.  Each GPU holds one copy of the array
+ * (about 1.7 MB, kept until the process ends; its address is taken by
+ * swim_create for the context's device, else SWIM_ESTATE).  Every call on
+ * a GPU uses that GPU's one array: calls that overlap on one GPU (several
+ * streams or contexts, host threads) race and must be serialized by the
+ * caller.  Returns when the host values are on the device; the kernels run
+ * asynchronously on the stream. */
+int swim_pair_velocity_noalloc(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const int64_t *sys_off,
+                               const double *alpha, const double *eps, const void *x, const void *y,
+                               const void *fx, const void *fy, void *ux, void *uy, void *stream);
+
 /* Velocity (eq. BrV) and pressure (eq. BrP) of the n regularized point
  * forces of one system at nt arbitrary target points, for flow and pressure
  * pictures (Sec. 2.1).

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -80,6 +81,35 @@ int64_t mlp_offb(int l) { return mlp_offW(l) + (int64_t)MLP_W[l] * MLP_W[l + 1];
 constexpr int64_t MLP_NPARAM = 207393;
 
 }  // namespace
+
+// Workspace of swim_pair_velocity_noalloc: a fixed device array in place of
+// the context's allocations.  Sections (256-byte aligned): system offsets,
+// alpha, eps, the block list (system, first target) of the pair kernel, the
+// per-system constants (in the working type and in FP64) and the FP32 kernel
+// tables.  Every section is written by the call before its kernels read it,
+// so nothing needs clearing between calls.
+constexpr int64_t NOALLOC_MAX_SYS = 64;      // systems per call
+constexpr int64_t NOALLOC_MAX_BLOCKS = 4160; // pair-kernel blocks (256 targets each) per call
+constexpr size_t na_align(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t NA_OFF = 0;
+constexpr size_t NA_ALPHA = na_align(NA_OFF + (NOALLOC_MAX_SYS + 1) * 8);
+constexpr size_t NA_EPS = na_align(NA_ALPHA + NOALLOC_MAX_SYS * 8);
+constexpr size_t NA_BLKS = na_align(NA_EPS + NOALLOC_MAX_SYS * 8);
+constexpr size_t NA_BLKF = na_align(NA_BLKS + NOALLOC_MAX_BLOCKS * 8);
+constexpr size_t NA_SYSC = na_align(NA_BLKF + NOALLOC_MAX_BLOCKS * 8);  // end of the staged host data
+constexpr size_t NA_SYSC64 = na_align(NA_SYSC + NOALLOC_MAX_SYS * sizeof(SysConst<double>));
+constexpr size_t NA_TAB = na_align(NA_SYSC64 + NOALLOC_MAX_SYS * sizeof(SysConst<double>));
+constexpr size_t NA_BYTES = na_align(NA_TAB + NOALLOC_MAX_SYS * sizeof(TabSys));  // ~1.7 MB
+
+static_assert(sizeof(SysConst<float>) <= sizeof(SysConst<double>), "FP32 constants share the FP64 slots");
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+// The array's device address on each device, taken once per device by
+// swim_create (hipGetSymbolAddress with that device current).  Host code
+// uses these addresses, never the array's name.
+constexpr int NOALLOC_MAX_DEV = 64;
+static void* g_scratch_dev[NOALLOC_MAX_DEV];
+static std::mutex g_scratch_mu;
 
 // a captured forward-run launch sequence, replayed while its layout and
 // buffers are unchanged
@@ -719,6 +749,19 @@ int swim_create(swim_ctx** out, int device)
             return fail(SWIM_EHIP, "context creation failed (auxiliary streams)");
         }
     }
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (device < NOALLOC_MAX_DEV && !g_scratch_dev[device]) {
+            void* p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                (void)hipGetLastError();
+                swim_destroy(c);
+                return fail(SWIM_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            }
+            g_scratch_dev[device] = p;
+        }
+    }
     *out = c;
     return SWIM_OK;
 }
@@ -836,6 +879,69 @@ int swim_pair_velocity(swim_ctx* c, int32_t dtype, int64_t n_sys, const int64_t*
     HIPCHK(launch_pair_velocity(dtype, tpl, (int64_t)bs.size(), (const int64_t*)c->buf[B_BLKS].p,
                                 (const int64_t*)c->buf[B_BLKF].p, (const int64_t*)c->buf[B_OFF].p, sysc, tab, x, y,
                                 fx, fy, ux, uy, st));
+    return SWIM_OK;
+}
+
+int swim_pair_velocity_noalloc(swim_ctx* c, int32_t dtype, int64_t n_sys, const int64_t* sys_off,
+                               const double* alpha, const double* eps, const void* x, const void* y, const void* fx,
+                               const void* fy, void* ux, void* uy, void* stream)
+{
+    TRY(check_ctx(c));
+    TRY(check_dtype(dtype));
+    if (n_sys < 0) return fail(SWIM_EINVAL, "n_sys < 0");
+    if (n_sys == 0) return SWIM_OK;
+    if (n_sys > NOALLOC_MAX_SYS)
+        return fail(SWIM_EINVAL, "n_sys = %lld exceeds the no-allocation workspace (%lld systems)", (long long)n_sys,
+                    (long long)NOALLOC_MAX_SYS);
+    if (!sys_off || !alpha || !eps) return fail(SWIM_EINVAL, "sys_off/alpha/eps must be host arrays");
+    if (sys_off[0] != 0) return fail(SWIM_EINVAL, "sys_off[0] must be 0");
+    for (int64_t s = 0; s < n_sys; ++s) {
+        if (sys_off[s + 1] < sys_off[s]) return fail(SWIM_EINVAL, "sys_off must be non-decreasing (system %lld)", (long long)s);
+        if (!(std::isfinite(alpha[s]) && alpha[s] >= 0)) return fail(SWIM_EINVAL, "alpha[%lld] must be finite and >= 0", (long long)s);
+        if (!(std::isfinite(eps[s]) && eps[s] > 0)) return fail(SWIM_EINVAL, "eps[%lld] must be finite and > 0", (long long)s);
+        if (alpha[s] * eps[s] > 1.0) return fail(SWIM_EINVAL, "alpha*eps > 1 for system %lld", (long long)s);
+    }
+    const int64_t npts = sys_off[n_sys];
+    if (npts > 0 && (!x || !y || !fx || !fy || !ux || !uy)) return fail(SWIM_EINVAL, "null data pointer");
+    if (c->device >= NOALLOC_MAX_DEV || !g_scratch_dev[c->device])
+        return fail(SWIM_ESTATE, "no workspace address for device %d", c->device);
+    char* ws = (char*)g_scratch_dev[c->device];
+    int64_t maxn = 0;
+    for (int64_t s = 0; s < n_sys; ++s) maxn = std::max(maxn, sys_off[s + 1] - sys_off[s]);
+    const int tpl = maxn >= 2048 ? 2 : 1;
+    int64_t nb = 0;
+    for (int64_t s = 0; s < n_sys; ++s) nb += (sys_off[s + 1] - sys_off[s] + 256 * tpl - 1) / (256 * tpl);
+    if (nb > NOALLOC_MAX_BLOCKS)
+        return fail(SWIM_EINVAL, "%lld pair-kernel blocks exceed the no-allocation workspace (%lld)", (long long)nb,
+                    (long long)NOALLOC_MAX_BLOCKS);
+    // the host data of the call, laid out as in the workspace, on the stack;
+    // one synchronous copy on the stream (no pinned staging buffer)
+    alignas(16) unsigned char host[NA_SYSC];
+    memcpy(host + NA_OFF, sys_off, (size_t)(n_sys + 1) * 8);
+    memcpy(host + NA_ALPHA, alpha, (size_t)n_sys * 8);
+    memcpy(host + NA_EPS, eps, (size_t)n_sys * 8);
+    int64_t* bs = (int64_t*)(host + NA_BLKS);
+    int64_t* bf = (int64_t*)(host + NA_BLKF);
+    int64_t k = 0;
+    for (int64_t s = 0; s < n_sys; ++s)
+        for (int64_t f = 0; f < sys_off[s + 1] - sys_off[s]; f += 256 * tpl) {
+            bs[k] = s;
+            bf[k] = f;
+            ++k;
+        }
+    hipStream_t st = pick(c, stream);
+    HIPCHK(hipMemcpyWithStream(ws, host, NA_SYSC, hipMemcpyHostToDevice, st));
+    void* sysc = ws + NA_SYSC;
+    void* sysc64 = dtype == SWIM_F32 ? (void*)(ws + NA_SYSC64) : nullptr;
+    HIPCHK(launch_sysconst(dtype, n_sys, (const double*)(ws + NA_ALPHA), (const double*)(ws + NA_EPS), sysc, sysc64,
+                           c->opt_blob, st));
+    void* tab = nullptr;
+    if (dtype == SWIM_F32) {
+        tab = ws + NA_TAB;
+        HIPCHK(launch_table_build(0, n_sys, sysc64, tab, c->opt_blob, st));
+    }
+    HIPCHK(launch_pair_velocity(dtype, tpl, nb, (const int64_t*)(ws + NA_BLKS), (const int64_t*)(ws + NA_BLKF),
+                                (const int64_t*)(ws + NA_OFF), sysc, tab, x, y, fx, fy, ux, uy, st));
     return SWIM_OK;
 }
 

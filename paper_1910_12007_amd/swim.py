@@ -46,6 +46,8 @@ SIGNATURES = {
     "swim_tune_save": (_c.c_int, [_P, _c.c_char_p]),
     "swim_tune_load": (_c.c_int, [_P, _c.c_char_p]),
     "swim_pair_velocity": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I64P, _DP, _DP, _P, _P, _P, _P, _P, _P, _P]),
+    "swim_pair_velocity_noalloc": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I64P, _DP, _DP, _P, _P, _P, _P, _P, _P,
+                                              _P]),
     "swim_elastic_forces": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I32P, _DP, _c.c_double, _P, _P, _P, _P, _P]),
     "swim_forward": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _I32P, _I32P, _P, _c.c_int32, _c.c_double,
                                 _c.c_int32, _c.c_double, _P, _P, _P, _P, _P]),
@@ -219,6 +221,15 @@ def swim_pair_velocity(ctx, sys_off, alpha, eps, x, y, fx, fy, ux, uy, stream=No
     e, e_p = _h(eps, np.float64, _DP)
     return _check(lib().swim_pair_velocity(ctx.handle, dtype_code(x), len(a), so_p, a_p, e_p, _dptr(x), _dptr(y),
                                            _dptr(fx), _dptr(fy), _dptr(ux), _dptr(uy), _stream(stream)))
+
+
+def swim_pair_velocity_noalloc(ctx, sys_off, alpha, eps, x, y, fx, fy, ux, uy, stream=None):
+    so, so_p = _h(sys_off, np.int64, _I64P)
+    a, a_p = _h(alpha, np.float64, _DP)
+    e, e_p = _h(eps, np.float64, _DP)
+    return _check(lib().swim_pair_velocity_noalloc(ctx.handle, dtype_code(x), len(a), so_p, a_p, e_p, _dptr(x),
+                                                   _dptr(y), _dptr(fx), _dptr(fy), _dptr(ux), _dptr(uy),
+                                                   _stream(stream)))
 
 
 def swim_elastic_forces(ctx, N, params, t, x, y, fx, fy, stream=None):
