@@ -296,8 +296,10 @@ __global__ __launch_bounds__(64) void k_table_build(int64_t s0, int64_t n, const
 // FP32 kernel tables with the paper's blob (eq. eqnblob): one workgroup of
 // PB_BLOCK threads per system.  A system at alpha > 0 (paper == 2) takes the
 // sweep of pb_table_nodes_host, split over the workgroup:
-//  1. thread tid integrates a contiguous run of the gaps [1, kL] and leaves
-//     the gap integrals in LDS (slot k of three node arrays);
+//  1. thread tid of the first PB_SWEEP threads integrates a contiguous run
+//     of the gaps [1, kL] and leaves the gap integrals in LDS (slot k of
+//     three node arrays); the last wave meanwhile takes the tail integral
+//     beyond r_kL, one panel per lane;
 //  2. exclusive prefix sums of A and Cq and the suffix sum of B over the
 //     per-thread totals (a wave scan, then the waves in order);
 //  3. each thread turns its own slots into A(r_k), B(r_k), Cq(r_k) and then
@@ -306,6 +308,7 @@ __global__ __launch_bounds__(64) void k_table_build(int64_t s0, int64_t n, const
 //     closed forms) are spread over the threads;
 //  5. the entries are assembled from the node values as in k_table_build.
 constexpr int PB_BLOCK = 512;
+constexpr int PB_SWEEP = PB_BLOCK - 64;  // threads of the gap quadratures
 
 // exclusive scan of v over the workgroup in thread order (REV: from the last
 // thread down), plus its total; red holds PB_BLOCK / 64 values
@@ -333,21 +336,23 @@ template <bool REV> __device__ double pb_block_scan(double v, double* red, doubl
     return before + inc - v;
 }
 
-__global__ __launch_bounds__(PB_BLOCK) void k_table_build_pb(int64_t s0, const SysConst<double>* sysc64, TabSys* tab)
+__global__ __launch_bounds__(PB_BLOCK) void k_table_build_pb(int64_t s0, const SysConst<double>* __restrict__ sysc64,
+                                                             TabSys* __restrict__ tab)
 {
     __shared__ double s_fh[PB_NODES], s_fg[PB_NODES], s_c[PB_NODES];
     __shared__ double s_red[PB_BLOCK / 64];
     __shared__ double s_tail;
     const int tid = threadIdx.x;
     const int64_t s = s0 + blockIdx.x;
-    const SysConst<double> C = sysc64[s];
+    // read in place (uniform loads), not copied into per-lane registers
+    const SysConst<double>& C = sysc64[s];
     const bool sweep = C.paper == 2.0;
     int kS = PB_NODES, kL = -1;
     if (sweep) pb_sweep_range(C, kS, kL);
     if (kL >= kS) {  // uniform over the workgroup
         const double alpha = sqrt(C.a2), eps = C.eps;
-        const int per = (kL + PB_BLOCK - 1) / PB_BLOCK;
-        const int k0 = 1 + tid * per, k1 = min(kL + 1, k0 + per);
+        const int per = (kL + PB_SWEEP - 1) / PB_SWEEP;
+        const int k0 = tid < PB_SWEEP ? 1 + tid * per : kL + 1, k1 = min(kL + 1, k0 + per);
         double ta = 0.0, tb = 0.0, tc = 0.0;
         double ulo = (k0 > 1 && k0 <= kL) ? asinh(sqrt(pb_node_t(C.its, k0 - 1)) / eps) : 0.0;
         for (int k = k0; k < k1; ++k) {
@@ -363,12 +368,12 @@ __global__ __launch_bounds__(PB_BLOCK) void k_table_build_pb(int64_t s0, const S
             tb += gb;
             tc += gc;
         }
-        // B(r_L), the integral beyond the sweep's last node: the first wave
-        // takes one panel of pb_tail_panels per lane
-        if (tid < 64) {
+        // B(r_L), the integral beyond the sweep's last node: the last wave
+        // takes one panel of pb_tail_panel per lane
+        if (tid >= PB_SWEEP) {
             const double rL = sqrt(pb_node_t(C.its, kL));
-            const double v = wave_total(pb_tail_panel(alpha, eps, rL, tid, 64));
-            if (tid == 0) s_tail = v;
+            const double v = wave_total(pb_tail_panel(alpha, eps, rL, tid - PB_SWEEP, 64));
+            if (tid == PB_SWEEP) s_tail = v;
         }
         double tot;
         double A = pb_block_scan<false>(ta, s_red, &tot);

@@ -105,6 +105,57 @@ template <> SWIM_HD double kfit<double>(int nu, double x)
     const double c0 = nu ? swim_kfit_k1_f64[0] : swim_kfit_k0_f64[0];
     return fma(u, b1, c0 - b2);
 }
+// sqrt(z) exp(-z) I_nu(z) at x = SWIM_IFIT_IS / z in (0, 1] (z >= 8)
+SWIM_HD double ifit(int nu, double x)
+{
+    const double u = 2.0 * x - 1.0, u2 = 2.0 * u;
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int j = SWIM_IFIT_I0_F64_N - 1; j >= 1; --j) {
+        const double cj = nu ? swim_ifit_i1_f64[j] : swim_ifit_i0_f64[j];
+        const double b0 = fma(u2, b1, cj - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    const double c0 = nu ? swim_ifit_i1_f64[0] : swim_ifit_i0_f64[0];
+    return fma(u, b1, c0 - b2);
+}
+
+// Ascending series of fixed length in y = z^2/4 (A&S 9.6.10, 9.6.13),
+// summed by Horner's rule with compile-time coefficients (no divisions, no
+// data-dependent exits): all terms are positive, and the first omitted term
+// is below 1e-19 of the sum on the range each serves (z <= 8 for I0 and I1,
+// 24 terms; z <= 2 for the K0 pieces and the (I0 - 1) series, 16 terms).
+constexpr int NSER_I = 24, NSER_K = 16;
+struct BesselSeries {
+    double i0[NSER_I];  // 1/(k!)^2:                 I0 = sum i0_k y^k
+    double i1[NSER_I];  // 1/(k!(k+1)!):             I1 = (z/2) sum i1_k y^k
+    double hk[NSER_K];  // H_k/(k!)^2, H_k = sum_{j<=k} 1/j
+    double iq[NSER_K];  // 1/((k+1)!)^2:             (I0 - 1)/y = sum iq_k y^k
+    constexpr BesselSeries() : i0(), i1(), hk(), iq()
+    {
+        double a = 1.0, b = 1.0, h = 0.0;
+        for (int k = 0; k < NSER_I; ++k) {
+            i0[k] = a;
+            i1[k] = b;
+            if (k < NSER_K) {
+                hk[k] = h * a;
+                iq[k] = a / ((double)(k + 1) * (double)(k + 1));
+            }
+            a /= (double)(k + 1) * (double)(k + 1);
+            b /= (double)(k + 1) * (double)(k + 2);
+            h += 1.0 / (double)(k + 1);
+        }
+    }
+};
+static constexpr BesselSeries BSER{};
+template <int N> SWIM_HD double horner(const double (&c)[N], double y)
+{
+    double s = c[N - 1];
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) s = fma(s, y, c[k]);
+    return s;
+}
 
 // ---------------------------------------------------------------------------
 // per-system constants
@@ -137,49 +188,6 @@ template <typename T> struct alignas(16) SysConst {
     T hoff;
 };
 
-// FP64 values of K0, K1 and Q at small or large argument (set-up only)
-SWIM_HD void bessel_k01_q_f64(double z, double* K0, double* K1, double* Q)
-{
-    if (z <= 2.0) {
-        const double w = z * z, y = 0.25 * w, L = log(0.25 * w);
-        double I0 = 0, P0 = 0, A = 0, B = 0;
-        double termk = 1.0;          // y^k / (k!)^2
-        double psi1 = -EULER_GAMMA;  // psi(k+1)
-        for (int k = 0; k < NSER_SETUP; ++k) {
-            I0 += termk;
-            P0 += psi1 * termk;
-            // A_m, B_m with m = k + 1:  y^m / ((m-1)! m!) = termk * y / (k+1)
-            const double tm = termk * y / (k + 1);
-            A += 2.0 * tm;
-            B += (psi1 + (psi1 + 1.0 / (k + 1))) * tm;
-            termk *= y / ((double)(k + 1) * (k + 1));
-            psi1 += 1.0 / (k + 1);
-        }
-        *K0 = -0.5 * L * I0 + P0;
-        *Q = 0.5 * L * A - B;
-        *K1 = (1.0 + *Q) / z;
-    } else {
-        const double e = exp(-z) / sqrt(z), x = SWIM_KFIT_ZS / z;
-        *K0 = e * kfit<double>(0, x);
-        *K1 = e * kfit<double>(1, x);
-        *Q = z * *K1 - 1.0;
-    }
-}
-
-// reciprocals 1/(k+1)^2 and 1/(k+1) for the series recurrences of the
-// set-up (a multiplication per term instead of an FP64 division)
-struct PbRecip {
-    double sq[80], lin[80];
-    constexpr PbRecip() : sq(), lin()
-    {
-        for (int k = 0; k < 80; ++k) {
-            sq[k] = 1.0 / ((double)(k + 1) * (double)(k + 1));
-            lin[k] = 1.0 / (double)(k + 1);
-        }
-    }
-};
-static constexpr PbRecip PB_RECIP{};
-
 // power-series coefficients in w of I0, P0 = sum_k psi(k+1) w^k/(4^k (k!)^2),
 // A = z I1 and B = sum_{m>=1} [psi(m) + psi(m+1)] w^m/(4^m (m-1)! m!), the
 // ascending series of the K0/K1 closed forms, fixed at compile time
@@ -202,6 +210,44 @@ struct SetupSeries {
     }
 };
 static constexpr SetupSeries SETUP_SERIES{};
+
+// FP64 values of K0, K1 and Q at small or large argument (set-up only)
+SWIM_HD void bessel_k01_q_f64(double z, double* K0, double* K1, double* Q)
+{
+    if (z <= 2.0) {
+        // the ascending series in w = z^2 (A&S 9.6.13, 9.6.11), NSER_K
+        // terms: their first omitted term is below 1e-24
+        const double w = z * z, L = log(0.25 * w);
+        double I0 = 0, P0 = 0, A = 0, B = 0;
+#pragma unroll
+        for (int k = NSER_K - 1; k >= 0; --k) {
+            I0 = fma(I0, w, SETUP_SERIES.I0[k]);
+            P0 = fma(P0, w, SETUP_SERIES.P0[k]);
+            A = fma(A, w, SETUP_SERIES.A[k]);
+            B = fma(B, w, SETUP_SERIES.B[k]);
+        }
+        *K0 = -0.5 * L * I0 + P0;
+        *Q = 0.5 * L * A - B;
+        *K1 = (1.0 + *Q) / z;
+    } else {
+        const double e = exp(-z) / sqrt(z), x = SWIM_KFIT_ZS / z;
+        *K0 = e * kfit<double>(0, x);
+        *K1 = e * kfit<double>(1, x);
+        *Q = z * *K1 - 1.0;
+    }
+}
+
+// reciprocals 1/(k+1) for the series recurrences of the set-up (a
+// multiplication per term instead of an FP64 division)
+struct PbRecip {
+    double lin[80];
+    constexpr PbRecip() : lin()
+    {
+        for (int k = 0; k < 80; ++k) lin[k] = 1.0 / (double)(k + 1);
+    }
+};
+static constexpr PbRecip PB_RECIP{};
+
 
 // Taylor coefficients at w0 of a power series p(w) = sum_m p_m w^m:
 // phat_n = sum_{m>=n} C(m, n) p_m w0^(m-n)
@@ -251,39 +297,19 @@ constexpr double GL10_W[5] = {0.295524224714753, 0.2692667193099965, 0.219086362
                               0.14945134915058036, 0.06667134430868807};
 constexpr int PB_NSER = 32;  // near-contact series length (delta < 1/4)
 
-// exp(-z) I0(z), exp(-z) I1(z): ascending series (A&S 9.6.10, positive
-// terms) for z <= 20, the asymptotic series (A&S 9.7.1) above, whose
-// smallest term, ~exp(-2z), is below the FP64 unit roundoff there
+// exp(-z) I0(z), exp(-z) I1(z): the ascending series (A&S 9.6.10,
+// positive terms) for z <= 8, the Chebyshev fits of sqrt(z) exp(-z) I_nu(z)
+// in 8/z above (swim_kfit.h)
 SWIM_HD void bessel_i01e_f64(double z, double* i0e, double* i1e)
 {
-    if (z <= 20.0) {
-        const double y = 0.25 * z * z;
-        double a = 1.0, b = 1.0, s0 = 0.0, s1 = 0.0;  // y^k/(k!)^2, y^k/(k!(k+1)!)
-        for (int k = 0; k < 80; ++k) {
-            s0 += a;
-            s1 += b;
-            a *= y / ((double)(k + 1) * (k + 1));
-            b *= y / ((double)(k + 1) * (k + 2));
-            if (a < 1e-18 * s0) break;
-        }
-        const double e = exp(-z);
-        *i0e = s0 * e;
-        *i1e = 0.5 * z * s1 * e;
+    if (z <= SWIM_IFIT_IS) {
+        const double y = 0.25 * z * z, e = exp(-z);
+        *i0e = horner(BSER.i0, y) * e;
+        *i1e = 0.5 * z * horner(BSER.i1, y) * e;
     } else {
-        // I_nu ~ e^z / sqrt(2 pi z) sum_k (-1)^k prod_{j<=k} (4 nu^2 - (2j-1)^2) / (j 8 z)
-        double t0 = 1.0, t1 = 1.0, s0 = 1.0, s1 = 1.0;
-        const double r8 = 1.0 / (8.0 * z);
-        for (int k = 1; k < 60; ++k) {
-            const double o = (double)(2 * k - 1) * (2 * k - 1);
-            t0 *= -(0.0 - o) * r8 / k;
-            t1 *= -(4.0 - o) * r8 / k;
-            s0 += t0;
-            s1 += t1;
-            if (fabs(t0) < 1e-18 * s0 && fabs(t1) < 1e-18 * fabs(s1)) break;
-        }
-        const double c = 1.0 / sqrt(2.0 * PI * z);
-        *i0e = c * s0;
-        *i1e = c * s1;
+        const double c = 1.0 / sqrt(z), x = SWIM_IFIT_IS / z;
+        *i0e = c * ifit(0, x);
+        *i1e = c * ifit(1, x);
     }
 }
 
@@ -320,13 +346,11 @@ SWIM_HD double pb_k0x(double x, double z, double ez)
 {
     if (x <= SWIM_KFIT_ZS) {
         const double y = 0.25 * x * x, L = log(0.5 * x) + EULER_GAMMA;
-        double term = 1.0, hk = 0.0, i0 = 0.0, sp = 0.0;  // y^k/(k!)^2, H_k
-        for (int k = 0; k < 40; ++k) {
-            i0 += term;
-            sp += hk * term;
-            term *= y * PB_RECIP.sq[k];
-            hk += PB_RECIP.lin[k];
-            if (term < 1e-18 * i0) break;
+        double i0 = 0.0, sp = 0.0;  // sum y^k/(k!)^2, sum H_k y^k/(k!)^2
+#pragma unroll
+        for (int k = NSER_K - 1; k >= 0; --k) {
+            i0 = fma(i0, y, BSER.i0[k]);
+            sp = fma(sp, y, BSER.hk[k]);
         }
         return (sp - L * i0) * ez;
     }
@@ -334,27 +358,11 @@ SWIM_HD double pb_k0x(double x, double z, double ez)
 }
 
 // I0(x) e^-z for 0 <= x <= z: the ascending series times enz = e^-z for
-// x <= 20, the asymptotic series times e^(x - z) above (as bessel_i01e_f64)
+// x <= 8, the fit of sqrt(x) e^-x I0(x) times e^(x - z) / sqrt(x) above
 SWIM_HD double pb_i0x(double x, double z, double enz)
 {
-    if (x <= 20.0) {
-        const double y = 0.25 * x * x;
-        double a = 1.0, s0 = 0.0;
-        for (int k = 0; k < 80; ++k) {
-            s0 += a;
-            a *= y * PB_RECIP.sq[k];
-            if (a < 1e-18 * s0) break;
-        }
-        return s0 * enz;
-    }
-    double t0 = 1.0, s0 = 1.0;
-    const double r8 = 1.0 / (8.0 * x);
-    for (int k = 1; k < 60; ++k) {
-        t0 *= (double)(2 * k - 1) * (2 * k - 1) * r8 * PB_RECIP.lin[k - 1];
-        s0 += t0;
-        if (t0 < 1e-18 * s0) break;
-    }
-    return s0 * exp(x - z) / sqrt(2.0 * PI * x);
+    if (x <= SWIM_IFIT_IS) return horner(BSER.i0, 0.25 * x * x) * enz;
+    return ifit(0, SWIM_IFIT_IS / x) * exp(x - z) / sqrt(x);
 }
 
 // Panel rule: widest panel in u and the cut-off exponent.  The direct FP64
@@ -458,14 +466,7 @@ SWIM_HD void pb_gM(double alpha, double eps, double t, double* g, double* M, PbR
             as += w * pb_i0x(xs, z, enz);
             if (small) {
                 // (I0(xs) - 1)/alpha^2 = (s^2/4) sum_k (xs^2/4)^k / ((k+1)!)^2
-                const double y = 0.25 * xs * xs;
-                double term = 1.0, acc = 0.0;
-                for (int k = 0; k < 40; ++k) {
-                    acc += term;
-                    term *= y * PB_RECIP.sq[k + 1];
-                    if (term < 1e-18 * acc) break;
-                }
-                cq += w * 0.25 * s * s * acc;
+                cq += w * 0.25 * s * s * horner(BSER.iq, 0.25 * xs * xs);
             }
         }
         uh = ul;
@@ -1028,14 +1029,7 @@ SWIM_HD void pb_gap(double alpha, double eps, double ulo, double uhi, bool wantB
         if (wantB) B += wd * pb_k0x(xs, 0.0, 1.0);
         if (wantC) {
             // (I0(xs) - 1)/alpha^2 = (s^2/4) sum_k (xs^2/4)^k / ((k+1)!)^2
-            const double y = 0.25 * xs * xs;
-            double term = 1.0, acc = 0.0;
-            for (int k = 0; k < 40; ++k) {
-                acc += term;
-                term *= y * PB_RECIP.sq[k + 1];
-                if (term < 1e-18 * acc) break;
-            }
-            Cq += wd * 0.25 * s * s * acc;
+            Cq += wd * 0.25 * s * s * horner(BSER.iq, 0.25 * xs * xs);
         }
     }
     *ga = A;
@@ -1053,7 +1047,7 @@ SWIM_HD double pb_tail_dmax(double alpha, double eps, double r)
 {
     const double u0 = asinh(r / eps);
     double lo = 0.0, hi = 15.0;
-    for (int it = 0; it < 40; ++it) {
+    for (int it = 0; it < 24; ++it) {
         const double d = 0.5 * (lo + hi);
         const double x = alpha * (eps * sinh(u0 + d) - r);
         if (x + 3.0 * d > 44.0) hi = d;
