@@ -37,26 +37,29 @@ sys.path.insert(0, ROOT)
 # and for each end F.d times H2 (MUL, FMA, MUL) and the two accumulations
 # (4 FMA): 42 FLOP (FMA = 2) per distinct pair, 21 per ordered pair.  The
 # kernel is bound by VALU instruction issue, not FLOP: integer and float
-# operations share the issue slots, 33 VALU lane-operations per distinct
-# pair in the k_forward<float, 2, 16> hot loop (loop control included),
-# 16.5 per ordered pair; the issue peak without packed FP32 is 256 CUs x 4
-# SIMDs x 16 lanes per clock x 2.4 GHz = 39.3e12 lane-operations/s, i.e.
-# 78.6 TFLOP/s of FMA (the build keeps packed FP32 off).
-VALU_OPS_PER_PAIR = 16.5
+# operations share the issue slots.  rocprofv3's SQ_INSTS_VALU over the
+# launch gives 22.3 VALU lane-operations per ordered pair evaluation, all
+# work of the step included (the symmetric pair loop alone is 16.5 in the
+# ISA); the issue peak without packed FP32 is 256 CUs x 4 SIMDs x 16 lanes
+# per clock x 2.4 GHz = 39.3e12 lane-operations/s, i.e. 78.6 TFLOP/s of FMA
+# (the build keeps packed FP32 off).
+# (profiles/k_forward_batch_4096x128_counters.md)
+VALU_OPS_PER_PAIR = 22.3
+PAIR_LOOP_VALU_OPS = 16.5  # the symmetric pair loop alone (ISA), also the sperm kernel's
 FP32_FLOP_PER_PAIR = 21
 NONPACKED_FP32_PEAK_TFLOPS = 78.6
 # the large-system kernel k_big_step<float, 1> (one target per lane, FP64
-# accumulation): 76 VALU per unrolled iteration of two pairs, loop control
-# included
-VALU_OPS_PER_PAIR_BIG = 38
+# accumulation): 39.9 VALU lane-operations per pair evaluation from
+# SQ_INSTS_VALU (profiles/k_big_step_dense_64x8x512_counters.md)
+VALU_OPS_PER_PAIR_BIG = 39.9
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 # HBM bytes of one launch of that kernel on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch: 52365.1 and 2134.3) scaled by
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch: 52369.6 and 3098.9) scaled by
 # the same counters over a 256 MiB device copy (x2.0 and x1.0), for the
 # kernel as it stands (profiles/k_forward_batch_4096x128_counters.md); set it
 # to None whenever the kernel changes until the counters are taken again
-TRAFFIC_BYTES = 52365.125 * 1024 * 2.0 + 2134.25 * 1024 * 1.0
+TRAFFIC_BYTES = 52369.6 * 1024 * 2.0 + 3098.9 * 1024 * 1.0
 
 
 def load_data():
@@ -332,8 +335,9 @@ def sperm_leg(ctx, stream, n=2000, steps=20000, dt=1e-5):
     and two swimmers with head centres 0.5 apart (148 points).
 
     Roofline: VALU issue bound.  Algorithmic work is n_pts^2 ordered pairs
-    per system step at VALU_OPS_PER_PAIR lane-operations each (the
-    symmetric schedule's cost per ordered pair)."""
+    per system step at PAIR_LOOP_VALU_OPS lane-operations each (the
+    symmetric pair loop's cost per ordered pair; the point phase of the
+    step, with its head and neck terms, comes on top)."""
     import torch
     from paper_1910_12007_amd import inputs, swim
     rows = torch.from_numpy(inputs.sperm_rows(n, seed=11)).to("cuda")
@@ -357,7 +361,7 @@ def sperm_leg(ctx, stream, n=2000, steps=20000, dt=1e-5):
         npts = n_swim * 74
         st = status.cpu().numpy()
         pairs = float(n) * npts * npts * steps
-        tops = VALU_OPS_PER_PAIR * pairs / (ms * 1e-3) / 1e12
+        tops = PAIR_LOOP_VALU_OPS * pairs / (ms * 1e-3) / 1e12
         tflops = FP32_FLOP_PER_PAIR * pairs / (ms * 1e-3) / 1e12
         out[f"{n_swim}_swimmer" + ("s" if n_swim > 1 else "")] = {
             "points_per_system": npts, "ms": ms, "us_per_step": 1e3 * ms / steps,
@@ -367,8 +371,8 @@ def sperm_leg(ctx, stream, n=2000, steps=20000, dt=1e-5):
             "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": tflops / FP32_PEAK_TFLOPS,
                          "kernel": "k_sperm_forward<float,%d,2>" % (1 if npts <= 64 else 2 if npts <= 128 else 3),
-                         "fp32_flop_per_pair": FP32_FLOP_PER_PAIR, "valu_ops_per_pair": VALU_OPS_PER_PAIR,
-                         "valu_issue_frac": tops / VALU_PEAK_TOPS}}
+                         "fp32_flop_per_pair": FP32_FLOP_PER_PAIR, "pair_loop_valu_ops": PAIR_LOOP_VALU_OPS,
+                         "pair_loop_valu_issue_frac": tops / VALU_PEAK_TOPS}}
     return out
 
 
@@ -631,21 +635,20 @@ def main():
     fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     n_acc = int(acc.sum().item())
     st = status.cpu().numpy()
-    # the forward call = per-system set-up + the persistent kernel; the
-    # set-up is the time of a one-step call of the same layout (its one step
-    # adds ~3 us), so the kernel's launch time is the difference
-    one = torch.empty((n, 1, 2), dtype=torch.float32, device="cuda")
-    sp1, st1 = torch.empty_like(speed), torch.empty_like(status)
-    setup = []
-    for _ in range(3):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        swim.swim_forward(ctx, Ns, None, P, 1, dt, 1, 1.5, one, sp1, st1, stream=stream)
-        b.record(stream)
-        torch.cuda.synchronize()
-        setup.append(a.elapsed_time(b))
-    setup_ms = float(np.median(setup))
-    kernel_ms = fwd_ms - setup_ms
+    # the forward call = per-system set-up + the persistent kernel.  The
+    # kernel's own launch time: the same calls again with the library's
+    # timing events recorded right before and after the persistent launch,
+    # on the stream it runs on (SWIM_OPT_TIME_KERNEL; those calls launch
+    # eagerly instead of replaying the captured graph)
+    swim.swim_set_option(ctx, swim.SWIM_OPT_TIME_KERNEL, 1)
+    kus = []
+    for _ in range(max(3, args.steps)):
+        swim.swim_forward(ctx, Ns, None, P, steps, dt, obs_every, 1.5, obs, speed, status, done, stream=stream)
+        kus.append(swim.swim_get_option(ctx, swim.SWIM_OPT_KERNEL_US))
+    swim.swim_set_option(ctx, swim.SWIM_OPT_TIME_KERNEL, 0)
+    torch.cuda.synchronize()
+    kernel_ms = float(np.mean(kus)) * 1e-3
+    setup_ms = fwd_ms - kernel_ms
     tflops = FP32_FLOP_PER_PAIR * pairs / (kernel_ms * 1e-3) / 1e12
     issue = VALU_OPS_PER_PAIR * pairs / (kernel_ms * 1e-3) / 1e12
     out = {
@@ -674,6 +677,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / FP32_PEAK_TFLOPS, "traffic": TRAFFIC_BYTES,
                      "kernel": "k_forward<float,2,16> (persistent forward run)", "kernel_ms": kernel_ms,
+                     "kernel_ms_source": "HIP events around the persistent launch (SWIM_OPT_TIME_KERNEL), "
+                                         f"mean of {len(kus)} calls",
                      "fp32_flop_per_pair": FP32_FLOP_PER_PAIR, "pair_evals_per_launch": pairs,
                      "nonpacked_fp32_peak_tflops": NONPACKED_FP32_PEAK_TFLOPS,
                      "frac_of_nonpacked": tflops / NONPACKED_FP32_PEAK_TFLOPS,

@@ -131,6 +131,14 @@ int swim_version(void);
  *                    mass (1 - eps^3/R^3).
  * Read-only counters (swim_get_option): SWIM_OPT_GRAPH_LAUNCHES (graph
  * replays and first launches so far), SWIM_OPT_GRAPH_CAPTURES.
+ * SWIM_OPT_TIME_KERNEL = 1 makes every forward call (swim_forward and the
+ * calls that run it) launch eagerly and record two timing events on its
+ * stream, right before and right after its persistent launches (the
+ * per-system set-up excluded; several size buckets: from before their fork
+ * to after their join; a chunked call: its last chunk); SWIM_OPT_KERNEL_US
+ * (read-only) then waits for the last such call and returns that interval
+ * in microseconds (SWIM_ESTATE if no timed call was made since the option
+ * was set).
  * Results do not depend on the launch options beyond rounding of the
  * source-split partial sums.  SWIM_EINVAL for an unknown key or value. */
 #define SWIM_OPT_WPS 1
@@ -140,6 +148,8 @@ int swim_version(void);
 #define SWIM_OPT_GRAPH_CAPTURES 5
 #define SWIM_OPT_BLOB 6
 #define SWIM_OPT_EARLY_STOP 7 /* abc_prescreened's early stop of rejected re-runs: 1 (default) or 0 */
+#define SWIM_OPT_TIME_KERNEL 8 /* 1: time the persistent launches of forward calls (default 0) */
+#define SWIM_OPT_KERNEL_US 9   /* read-only: microseconds of the last timed forward call's launches */
 #define SWIM_BLOB_READING 0 /* the unit-mass blob whose Brinkmanlet has a closed form for all alpha */
 #define SWIM_BLOB_PAPER 1   /* default: eq. (eqnblob), 3 eps^3 / (2 pi (r^2 + eps^2)^(5/2)) */
 int swim_set_option(swim_ctx *ctx, int32_t key, int32_t value);

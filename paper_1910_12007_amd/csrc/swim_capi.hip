@@ -145,6 +145,11 @@ struct swim_ctx {
     static constexpr int N_AUX = 3;
     hipStream_t aux[N_AUX] = {};
     hipEvent_t fork_ev = nullptr, join_ev[N_AUX] = {};
+    // SWIM_OPT_TIME_KERNEL: timing events around the persistent launches of
+    // the last forward call (its last chunk), read by SWIM_OPT_KERNEL_US
+    int opt_time = 0;
+    hipEvent_t time_ev[2] = {};
+    bool timed = false;
     hipStream_t last_stream = nullptr;  // stream of the previous call (null: none yet)
     bool broken = false;
 };
@@ -488,6 +493,7 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
                                              sysc64, status, c->opt_blob, st);
         if (e == hipSuccess && dtype == SWIM_F32) e = launch_table_build(0, n_sys, sysc64, c->buf[B_TAB].p, c->opt_blob, st);
         if (e == hipSuccess) e = launch_fill_i32((int32_t*)c->buf[B_QUEUE].p, 0, 8, st);
+        if (e == hipSuccess && c->opt_time) e = hipEventRecord(c->time_ev[0], st);
         // Buckets (and the large systems) are independent: with more than
         // one, they run side by side, the call's stream and up to N_AUX
         // auxiliary streams each taking a share (lanes assigned in order of
@@ -523,10 +529,14 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
             e = hipEventRecord(c->join_ev[l - 1], c->aux[l - 1]);
             if (e == hipSuccess) e = hipStreamWaitEvent(st, c->join_ev[l - 1], 0);
         }
+        if (e == hipSuccess && c->opt_time) e = hipEventRecord(c->time_ev[1], st);
         return e;
     };
-    if (c->opt_graph == 0) {
+    if (c->opt_graph == 0 || c->opt_time) {
+        // timed calls launch eagerly: the events stay plain stream events
+        c->timed = false;
         HIPCHK(launch_all());
+        c->timed = c->opt_time != 0;
         return SWIM_OK;
     }
     // key of the layout: everything the launch sequence bakes in
@@ -736,8 +746,11 @@ int swim_create(swim_ctx** out, int device)
     if (hipGetDeviceProperties(&prop, device) != hipSuccess || hipStreamCreateWithFlags(&c->stream, hipStreamDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->up_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->sw_ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess) {
-        delete c;
+        hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->time_ev[0], hipEventDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->time_ev[1], hipEventDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        swim_destroy(c);
         return fail(SWIM_EHIP, "context creation failed");
     }
     c->num_cu = prop.multiProcessorCount;
@@ -781,6 +794,8 @@ void swim_destroy(swim_ctx* c)
     if (c->up_ev) (void)hipEventDestroy(c->up_ev);
     if (c->sw_ev) (void)hipEventDestroy(c->sw_ev);
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    for (auto& ev : c->time_ev)
+        if (ev) (void)hipEventDestroy(ev);
     for (int k = 0; k < swim_ctx::N_AUX; ++k) {
         if (c->aux[k]) {
             (void)hipStreamSynchronize(c->aux[k]);
@@ -811,6 +826,10 @@ int swim_set_option(swim_ctx* c, int32_t key, int32_t value)
     } else if (key == SWIM_OPT_EARLY_STOP) {
         if (value != 0 && value != 1) return fail(SWIM_EINVAL, "early stop must be 0 or 1");
         c->opt_early_stop = value;
+    } else if (key == SWIM_OPT_TIME_KERNEL) {
+        if (value != 0 && value != 1) return fail(SWIM_EINVAL, "kernel timing must be 0 or 1");
+        c->opt_time = value;
+        c->timed = false;
     } else {
         return fail(SWIM_EINVAL, "unknown option %d", key);
     }
@@ -825,6 +844,15 @@ int swim_get_option(swim_ctx* c, int32_t key, int32_t* value)
     else if (key == SWIM_OPT_GRAPH) *value = c->opt_graph;
     else if (key == SWIM_OPT_BLOB) *value = c->opt_blob;
     else if (key == SWIM_OPT_EARLY_STOP) *value = c->opt_early_stop;
+    else if (key == SWIM_OPT_TIME_KERNEL) *value = c->opt_time;
+    else if (key == SWIM_OPT_KERNEL_US) {
+        if (!c->timed) return fail(SWIM_ESTATE, "no timed forward call (set SWIM_OPT_TIME_KERNEL first)");
+        (void)hipSetDevice(c->device);
+        float ms = 0.0f;
+        HIPCHK(hipEventSynchronize(c->time_ev[1]));
+        HIPCHK(hipEventElapsedTime(&ms, c->time_ev[0], c->time_ev[1]));
+        *value = (int32_t)std::min(2.0e9, std::round(1e3 * (double)ms));
+    }
     else if (key == SWIM_OPT_GRAPH_LAUNCHES) *value = (int32_t)c->graph_launches;
     else if (key == SWIM_OPT_GRAPH_CAPTURES) *value = (int32_t)c->graph_captures;
     else return fail(SWIM_EINVAL, "unknown option %d", key);

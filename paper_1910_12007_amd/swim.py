@@ -19,7 +19,7 @@ SWIM_ST_OK, SWIM_ST_NONFINITE, SWIM_ST_BOUND, SWIM_ST_BADPARAM, SWIM_ST_REJECTED
 SWIM_NPARAM = 9
 SWIM_OPT_WPS, SWIM_OPT_BIG_TPL, SWIM_OPT_GRAPH, SWIM_OPT_GRAPH_LAUNCHES, SWIM_OPT_GRAPH_CAPTURES = 1, 2, 3, 4, 5
 SWIM_OPT_BLOB, SWIM_BLOB_READING, SWIM_BLOB_PAPER = 6, 0, 1
-SWIM_OPT_EARLY_STOP = 7
+SWIM_OPT_EARLY_STOP, SWIM_OPT_TIME_KERNEL, SWIM_OPT_KERNEL_US = 7, 8, 9
 SWIM_MLP_NPARAM, SWIM_MLP_IN, SWIM_MLP_OUT = 207393, 5, 33
 # full sperm model: system row fields (SWIM_SP_*) and swimmer row width
 SPERM_FIELDS = ("alpha", "KC", "KT", "KHT", "KHC", "KNT", "KNA", "a", "eta", "omega")

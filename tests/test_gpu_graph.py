@@ -112,3 +112,40 @@ def test_graph_replays_match_eager(ctx, dtype):
     finally:
         swim.swim_set_option(ctx, swim.SWIM_OPT_GRAPH, 1)
         swim.swim_set_option(ctx, swim.SWIM_OPT_BLOB, swim.SWIM_BLOB_PAPER)
+
+
+def test_kernel_timing_option(ctx):
+    """SWIM_OPT_TIME_KERNEL: timed calls (eager, events around the
+    persistent launches) give the same outputs as untimed ones, and
+    SWIM_OPT_KERNEL_US reports a positive interval no longer than the call;
+    reading it before any timed call, or setting a bad value, is an error."""
+    import time
+    P, N, nsw = _layout()
+    steps, dt, oe = 120, 2e-5, 40
+    nfil = P.shape[0]
+    Pd = torch.from_numpy(P).cuda()
+    outs = []
+    with pytest.raises(swim.SwimError):
+        swim.swim_set_option(ctx, swim.SWIM_OPT_TIME_KERNEL, 2)
+    swim.swim_set_option(ctx, swim.SWIM_OPT_TIME_KERNEL, 1)
+    try:
+        with pytest.raises(swim.SwimError):
+            swim.swim_get_option(ctx, swim.SWIM_OPT_KERNEL_US)
+        for timed in (1, 0):
+            swim.swim_set_option(ctx, swim.SWIM_OPT_TIME_KERNEL, timed)
+            obs = torch.empty((nfil, steps // oe, 2), dtype=torch.float32, device="cuda")
+            speed = torch.empty(nfil, dtype=torch.float32, device="cuda")
+            status = torch.empty(len(N), dtype=torch.int32, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            swim.swim_forward(ctx, N, nsw, Pd, steps, dt, oe, 1.5, obs, speed, status)
+            if timed:
+                us = swim.swim_get_option(ctx, swim.SWIM_OPT_KERNEL_US)
+                wall_us = 1e6 * (time.perf_counter() - t0)
+                assert 0 < us <= wall_us, (us, wall_us)
+            torch.cuda.synchronize()
+            outs.append((obs.cpu().numpy(), speed.cpu().numpy(), status.cpu().numpy()))
+    finally:
+        swim.swim_set_option(ctx, swim.SWIM_OPT_TIME_KERNEL, 0)
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b, equal_nan=True)

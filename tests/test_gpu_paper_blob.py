@@ -411,3 +411,59 @@ def test_batched_size_fp32_against_fp64(paper):
                "speed": abs(s32 / s64 - 1)})
         assert err <= bar * np.linalg.norm(o64 - x0) + floor
         assert abs(s32 / s64 - 1) <= bar
+
+
+def test_dense_sample_as_benchmarked(paper, oracle_core):
+    """The dense workload's sample 0 (8 swimmers x 512 points on the 2 x 4
+    grid, its alpha) with the paper's blob, as the benchmark runs it.  One
+    velocity evaluation at the initial configuration, all 4096 sources, on
+    16 sampled targets (both ends of every swimmer) against the oracle's
+    quadrature, which takes ~0.5 s per target: FP32 within 1e-5 and FP64
+    within 1e-12 of the largest sampled velocity.  Then the run at the
+    benchmark's dt = 2e-5/64: FP32 against the FP64 run over 100 steps,
+    head of every swimmer every 10, at 1e-4 of the displacement (plus one
+    FP32 spacing of the stored positions), both runs completing."""
+    lay = inputs.dense_layout(n_samples=1, seed=3)[0]
+    s = np.arange(512) / 511.0
+    X = np.concatenate([lay[m, 7] + s for m in range(8)])
+    Y = np.concatenate([np.full(512, lay[m, 8]) for m in range(8)])
+    F = [oracle_core.forces(X[512 * m:512 * (m + 1)], Y[512 * m:512 * (m + 1)], lay[m, 1], lay[m, 2],
+                            oracle_core.kappa0(512, lay[m, 3], lay[m, 5], lay[m, 4], lay[m, 6], 0.0))
+         for m in range(8)]
+    FX = np.concatenate([f[0] for f in F])
+    FY = np.concatenate([f[1] for f in F])
+    eps = 1.5 / 511
+    idx = np.concatenate([[512 * m, 512 * m + 511] for m in range(8)])
+    for dtype, tol, npd, td in ((swim.SWIM_F32, 1e-5, np.float32, torch.float32),
+                                (swim.SWIM_F64, 1e-12, np.float64, torch.float64)):
+        # both sides take the same (rounded) positions and forces
+        arr = [a.astype(npd) for a in (X, Y, FX, FY)]
+        ux = torch.empty(4096, dtype=td, device="cuda")
+        uy = torch.empty_like(ux)
+        swim.swim_pair_velocity(paper, np.array([0, 4096]), [lay[0, 0]], [eps],
+                                *[torch.from_numpy(a).cuda() for a in arr], ux, uy)
+        torch.cuda.synchronize()
+        ox, oy = oracle_core.velocity_at(*[a.astype(np.float64) for a in arr], lay[0, 0], eps, idx)
+        got = np.r_[ux.cpu().double().numpy()[idx], uy.cpu().double().numpy()[idx]]
+        ref = np.r_[ox, oy]
+        print({"dtype": dtype, "max": rel_max(got, ref)})
+        assert rel_max(got, ref) <= tol, (dtype, rel_max(got, ref))
+    P = torch.from_numpy(lay).cuda()
+    dt = 2e-5 / 64
+    out = {}
+    for dtype, td in ((swim.SWIM_F64, torch.float64), (swim.SWIM_F32, torch.float32)):
+        P_t = P.to(torch.float64)
+        obs = torch.empty((8, 10, 2), dtype=td, device="cuda")
+        speed = torch.empty(8, dtype=td, device="cuda")
+        st = torch.empty(1, dtype=torch.int32, device="cuda")
+        swim.swim_forward(paper, [512], [8], P_t, 100, dt, 10, 1.5, obs, speed, st)
+        torch.cuda.synchronize()
+        assert st.item() == swim.SWIM_ST_OK, dtype
+        out[dtype] = obs.cpu().double().numpy()
+    o64, o32 = out[swim.SWIM_F64], out[swim.SWIM_F32]
+    x0 = lay[:, 7:9] + np.array([1.0, 0.0])
+    disp = np.linalg.norm(o64 - x0[:, None, :])
+    floor = np.linalg.norm(np.spacing(np.abs(o64).astype(np.float32)))
+    err = np.linalg.norm(o32 - o64)
+    print({"fp32_vs_fp64": err / disp})
+    assert err <= 1e-4 * disp + floor
