@@ -648,16 +648,15 @@ int forward_impl(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, co
 struct MlpAct {
     float* pre[4];
     float* H[4];
-    float *Y, *dY, *dA[2], *rowsq;
-    float* ws;         // split-K partial sums of the GEMMs
-    int64_t ws_floats;
+    float *Y, *dY, *dA[2], *sq;
+    MlpWs ws;  // split-K partial sums of the GEMMs
 };
 
 int mlp_act(swim_ctx* c, int64_t M, MlpAct* a)
 {
     const int64_t H = 256, O = 33;
     const int64_t ws = 1 << 20;  // partial sums: 16 slices of 256 x 256, or 4 of 1024 x 256
-    const int64_t total = 8 * M * H + 2 * M * O + 2 * M * H + M + ws;
+    const int64_t total = 8 * M * H + 2 * M * O + 2 * M * H + M * O + ws;
     TRY(ensure(c, B_MLP_ACT, (size_t)total * 4));
     float* p = (float*)c->buf[B_MLP_ACT].p;
     for (int l = 0; l < 4; ++l) a->pre[l] = p + l * M * H;
@@ -666,54 +665,64 @@ int mlp_act(swim_ctx* c, int64_t M, MlpAct* a)
     a->dY = a->Y + M * O;
     a->dA[0] = a->dY + M * O;
     a->dA[1] = a->dA[0] + M * H;
-    a->rowsq = a->dA[1] + M * H;
-    a->ws = a->rowsq + M;
-    a->ws_floats = ws;
+    a->sq = a->dA[1] + M * H;
+    a->ws.part = a->sq + M * O;
+    a->ws.part_floats = ws;
     return SWIM_OK;
 }
 
-int mlp_forward(const float* X, const float* P, int64_t M, const MlpAct& a, float* Y, hipStream_t st)
+// forward pass; with T (training), the output layer's epilogue also forms
+// the gradient of the squared error, dY = 2 (Y - T) / (M 33), and the
+// squared errors (a.dY, a.sq)
+int mlp_forward(const float* X, const float* P, int64_t M, const MlpAct& a, float* Y, hipStream_t st,
+                const float* T = nullptr)
 {
     const float* in = X;
     int64_t ldin = MLP_W[0];
     for (int l = 0; l < MLP_L; ++l) {
         const int K = MLP_W[l], N = MLP_W[l + 1];
         const float* W = P + mlp_offW(l);
-        const float* b = P + mlp_offb(l);
+        GemmEpi E;
+        E.bias = P + mlp_offb(l);
         if (l < MLP_L - 1) {
-            HIPCHK(launch_gemm_bf16(1, (int)M, N, K, in, ldin, 1, W, N, 1, a.pre[l], N, b, a.H[l], a.ws, a.ws_floats,
-                                    st));
+            E.aux = a.H[l];
+            HIPCHK(launch_gemm_bf16(1, (int)M, N, K, in, ldin, 1, W, N, 1, a.pre[l], N, E, a.ws, st));
             in = a.H[l];
             ldin = N;
+        } else if (T) {
+            E.aux = a.dY;
+            E.T = T;
+            E.sq = a.sq;
+            E.sc = 2.0f / ((float)M * (float)N);
+            HIPCHK(launch_gemm_bf16(4, (int)M, N, K, in, ldin, 1, W, N, 1, Y, N, E, a.ws, st));
         } else {
-            HIPCHK(launch_gemm_bf16(2, (int)M, N, K, in, ldin, 1, W, N, 1, Y, N, b, nullptr, a.ws, a.ws_floats, st));
+            HIPCHK(launch_gemm_bf16(2, (int)M, N, K, in, ldin, 1, W, N, 1, Y, N, E, a.ws, st));
         }
     }
     return SWIM_OK;
 }
 
-// gradients of the mean-squared error into G (layout of the parameters);
-// loss (device, optional) = mean over the M x 33 outputs
-int mlp_backward(const float* X, const float* T, const float* P, int64_t M, const MlpAct& a, float* G, float* loss,
-                 hipStream_t st)
+// gradients of the squared error into G (layout of the parameters), after
+// mlp_forward with the targets; loss (device, optional) = the sum of the
+// M x 33 squared errors
+int mlp_backward(const float* X, const float* P, int64_t M, const MlpAct& a, float* G, float* loss, hipStream_t st)
 {
     const int O = MLP_W[MLP_L];
-    HIPCHK(launch_mse_grad((int)M, O, a.Y, T, a.dY, a.rowsq, st));
-    if (loss) HIPCHK(launch_colsum((int)M, 1, a.rowsq, 1, loss, st));
+    if (loss) HIPCHK(launch_sum(M * O, a.sq, loss, st));
     const float* dA = a.dY;
     int cur = 0;
     for (int l = MLP_L - 1; l >= 0; --l) {
         const int K = MLP_W[l], N = MLP_W[l + 1];
         const float* Hin = l > 0 ? a.H[l - 1] : X;
         // dW_l = Hin^T dA  (K x N, summed over the M rows)
-        HIPCHK(launch_gemm_bf16(0, K, N, (int)M, Hin, 1, K, dA, N, 1, G + mlp_offW(l), N, nullptr, nullptr, a.ws,
-                                a.ws_floats, st));
+        HIPCHK(launch_gemm_bf16(0, K, N, (int)M, Hin, 1, K, dA, N, 1, G + mlp_offW(l), N, GemmEpi(), a.ws, st));
         HIPCHK(launch_colsum((int)M, N, dA, N, G + mlp_offb(l), st));
         if (l > 0) {
             // dA_{l-1} = (dA W_l^T) * gelu'(pre_{l-1})
             float* out = a.dA[cur];
-            HIPCHK(launch_gemm_bf16(3, (int)M, K, N, dA, N, 1, P + mlp_offW(l), 1, N, out, K, nullptr, a.pre[l - 1],
-                                    a.ws, a.ws_floats, st));
+            GemmEpi E;
+            E.aux = a.pre[l - 1];
+            HIPCHK(launch_gemm_bf16(3, (int)M, K, N, dA, N, 1, P + mlp_offW(l), 1, N, out, K, E, a.ws, st));
             dA = out;
             cur ^= 1;
         }
@@ -1546,8 +1555,8 @@ int surrogate_grad(swim_ctx* c, int64_t n, const float* X, const float* T, const
     hipStream_t st = pick(c, stream);
     MlpAct a;
     TRY(mlp_act(c, n, &a));
-    TRY(mlp_forward(X, params, n, a, a.Y, st));
-    TRY(mlp_backward(X, T, params, n, a, grads, loss, st));
+    TRY(mlp_forward(X, params, n, a, a.Y, st, T));
+    TRY(mlp_backward(X, params, n, a, grads, loss, st));
     return SWIM_OK;
 }
 
@@ -1574,8 +1583,8 @@ int surrogate_train(swim_ctx* c, int64_t n, const float* X, const float* T, cons
             ++t;
             HIPCHK(launch_gather_rows(batch, perm + (int64_t)e * n + s * batch, n, X, MLP_W[0], T, MLP_W[MLP_L], Xb, Tb,
                                       st));
-            TRY(mlp_forward(Xb, params, batch, a, a.Y, st));
-            TRY(mlp_backward(Xb, Tb, params, batch, a, G, loss_out ? loss_out + e * spe + s : nullptr, st));
+            TRY(mlp_forward(Xb, params, batch, a, a.Y, st, Tb));
+            TRY(mlp_backward(Xb, params, batch, a, G, loss_out ? loss_out + e * spe + s : nullptr, st));
             HIPCHK(launch_adam(MLP_NPARAM, params, G, adam_m, adam_v, lr, (float)b1, (float)b2,
                                (float)(1.0 - std::pow(b1, (double)t)), (float)(1.0 - std::pow(b2, (double)t)), 1e-8f, st));
         }

@@ -106,13 +106,25 @@ hipError_t launch_gauss_loglik(int dtype, int64_t n, int32_t n_obs, const void* 
                                const double* sigma, const int32_t* status, double* logl, hipStream_t st);
 
 // surrogate MLP (swim_mlp.hip)
-// ws (ws_floats floats, may be null): workspace of the split-K partial sums
+// operands of the GEMM epilogues (unused ones may be null)
+struct GemmEpi {
+    const float* bias = nullptr;  // [N]
+    float* aux = nullptr;         // GELU: H out; DGELU: pre-activations in; MSE: dY out
+    const float* T = nullptr;     // MSE: targets [M][N]
+    float* sq = nullptr;          // MSE: squared errors out [M][N]
+    float sc = 0.0f;              // MSE: 2 / (M N)
+};
+// workspace of the split-K partial sums
+struct MlpWs {
+    float* part = nullptr;
+    int64_t part_floats = 0;
+};
+// epi: 0 plain, 1 bias + GELU, 2 bias, 3 times GELU', 4 bias + MSE gradient
 hipError_t launch_gemm_bf16(int epi, int M, int N, int K, const float* A, int64_t sam, int64_t sak,
                             const float* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc,
-                            const float* bias, float* aux, float* ws, int64_t ws_floats, hipStream_t st);
+                            const GemmEpi& E, const MlpWs& ws, hipStream_t st);
 hipError_t launch_colsum(int M, int N, const float* A, int64_t lda, float* out, hipStream_t st);
-hipError_t launch_mse_grad(int M, int N, const float* Y, const float* T, float* dY, float* rowsq,
-                           hipStream_t st);
+hipError_t launch_sum(int64_t n, const float* v, float* out, hipStream_t st);
 hipError_t launch_gather_rows(int M, const int32_t* perm, int64_t nrows, const float* X, int nx,
                               const float* T, int nt, float* Xb, float* Tb, hipStream_t st);
 hipError_t launch_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,

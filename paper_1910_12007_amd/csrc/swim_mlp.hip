@@ -44,9 +44,21 @@ __device__ __forceinline__ float erf_as(float x)
     return copysignf(fmaf(-p, e, 1.0f), x);
 }
 
+// GELU(x) = (x/2)(1 + erf(x/sqrt 2)) with erf from 7.1.26 rearranged: with
+// a = |x|, z = a/sqrt 2 and erf(z) = 1 - P(t) exp(-z^2), t = 1/(1 + p z),
+// GELU(x) = max(x, 0) - (a/2) P(t) exp(-a^2/2) for either sign of x (no
+// copysign, no 1 + erf); the same function as (x/2)(1 + erf_as(x/sqrt 2)).
 __device__ __forceinline__ float gelu_f(float x)
 {
-    return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f));
+    const float a = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, a, 1.0f));
+    float p = fmaf(1.061405429f, t, -1.453152027f);
+    p = fmaf(p, t, 1.421413741f);
+    p = fmaf(p, t, -0.284496736f);
+    p = fmaf(p, t, 0.254829592f);
+    // exp(-a^2/2) / 2, the halving folded into the exponent
+    const float e = __builtin_amdgcn_exp2f(fmaf(a * a, -0.5f * 1.4426950408889634f, -1.0f));
+    return fmaf(-(a * t), p * e, fmaxf(x, 0.0f));
 }
 
 __device__ __forceinline__ float gelu_grad_f(float x)
@@ -62,22 +74,29 @@ __device__ __forceinline__ float gelu_grad_f(float x)
 //   MLP_EPI_GELU   pre = acc + bias[n] -> C;  H = gelu(pre) -> aux
 //   MLP_EPI_BIAS   C = acc + bias[n]
 //   MLP_EPI_DGELU  C = acc * gelu'(aux(m, n))   (aux = pre-activations)
+//   MLP_EPI_MSE    Y = acc + bias[n] -> C; with d = Y - T(m, n):
+//                  dY = sc d -> aux (sc = 2 / (M N)), d^2 -> sq  (ldc = N)
 // Workgroup tile 64 x 64 (4 waves of 32 x 32 = 2 x 2 MFMA tiles), k chunks of 32.
 constexpr int GT = 64, GK = 32, GPAD = 8;
 
-// epilogue of one output element (the split-K reduction applies it too)
+// epilogue of one output element (the split-K fixup applies it too)
 template <int EPI>
-__device__ __forceinline__ void gemm_epilogue(float v, int n, int64_t o, float* __restrict__ C,
-                                              const float* __restrict__ bias, float* __restrict__ aux)
+__device__ __forceinline__ void gemm_epilogue(float v, int n, int64_t o, float* __restrict__ C, const GemmEpi& E)
 {
     if (EPI == 1) {
-        v += bias[n];
+        v += E.bias[n];
         C[o] = v;
-        aux[o] = gelu_f(v);
+        E.aux[o] = gelu_f(v);
     } else if (EPI == 2) {
-        C[o] = v + bias[n];
+        C[o] = v + E.bias[n];
     } else if (EPI == 3) {
-        C[o] = v * gelu_grad_f(aux[o]);
+        C[o] = v * gelu_grad_f(E.aux[o]);
+    } else if (EPI == 4) {
+        v += E.bias[n];
+        C[o] = v;
+        const float d = v - E.T[o];
+        E.aux[o] = E.sc * d;
+        E.sq[o] = d * d;
     } else {
         C[o] = v;
     }
@@ -88,11 +107,14 @@ __device__ __forceinline__ void gemm_epilogue(float v, int n, int64_t o, float* 
 // part[z][M][N]; k_gemm_reduce adds the slices in order of z and applies the
 // epilogue (deterministic).  This fills the chip when the M x N tiles are
 // few (the weight gradients: 256 x 256 outputs summed over a batch of 1024).
+// (A last-arriving-workgroup reduction inside the GEMM was tried: its
+// device-scope fences, which write back the L2 of the XCD, made the GEMMs
+// 3-5x slower than the second launch.)
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const float* __restrict__ A, int64_t sam,
                                                    int64_t sak, const float* __restrict__ B, int64_t sbk, int64_t sbn,
-                                                   float* __restrict__ C, int64_t ldc, const float* __restrict__ bias,
-                                                   float* __restrict__ aux, float* __restrict__ part, int kper)
+                                                   float* __restrict__ C, int64_t ldc, GemmEpi E,
+                                                   float* __restrict__ part, int kper)
 {
     __shared__ uint16_t As[GT][GK + GPAD];   // [m][k]
     __shared__ uint16_t Bs[GT][GK + GPAD];   // [n][k]
@@ -110,22 +132,42 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const fl
     const bool a_k_fast = sak == 1, b_n_fast = sbn == 1 || sbk != 1;
     const int kbeg = part ? (int)blockIdx.z * kper * GK : 0;
     const int kend = part ? min(K, kbeg + kper * GK) : K;
-    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+    // the next chunk's operands are fetched into registers while the
+    // current chunk's MFMAs run
+    constexpr int PER = (GT * GK) / 256;
+    float ra[PER], rb[PER];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < (GT * GK) / 256; ++i) {
+        for (int i = 0; i < PER; ++i) {
             const int e = tid + 256 * i;
             const int r = a_k_fast ? e / GK : e % GT, kk = a_k_fast ? e % GK : e / GT;
             const int m = m0 + r, k = k0 + kk;
-            As[r][kk] = (m < M && k < K) ? f2bf(A[(int64_t)m * sam + (int64_t)k * sak]) : (uint16_t)0;
+            ra[i] = (m < M && k < K) ? A[(int64_t)m * sam + (int64_t)k * sak] : 0.0f;
         }
 #pragma unroll
-        for (int i = 0; i < (GT * GK) / 256; ++i) {
+        for (int i = 0; i < PER; ++i) {
             const int e = tid + 256 * i;
             const int kk = b_n_fast ? e / GT : e % GK, c = b_n_fast ? e % GT : e / GK;
             const int n = n0 + c, k = k0 + kk;
-            Bs[c][kk] = (n < N && k < K) ? f2bf(B[(int64_t)k * sbk + (int64_t)n * sbn]) : (uint16_t)0;
+            rb[i] = (n < N && k < K) ? B[(int64_t)k * sbk + (int64_t)n * sbn] : 0.0f;
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            const int r = a_k_fast ? e / GK : e % GT, kk = a_k_fast ? e % GK : e / GT;
+            As[r][kk] = f2bf(ra[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            const int kk = b_n_fast ? e / GT : e % GK, c = b_n_fast ? e % GT : e / GK;
+            Bs[c][kk] = f2bf(rb[i]);
         }
         __syncthreads();
+        if (k0 + GK < kend) fetch(k0 + GK);
 #pragma unroll
         for (int ks = 0; ks < GK; ks += 16) {
             // operand layout of the 16x16x16 MFMA: lane l holds row (l % 16)
@@ -134,10 +176,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const fl
             bf16x4_t av[2], bv[2];
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                const uint16_t* pa = &As[wm + 16 * t + (lane & 15)][kq];
-                const uint16_t* pb = &Bs[wn + 16 * t + (lane & 15)][kq];
-                av[t] = bf16x4_t{(short)pa[0], (short)pa[1], (short)pa[2], (short)pa[3]};
-                bv[t] = bf16x4_t{(short)pb[0], (short)pb[1], (short)pb[2], (short)pb[3]};
+                // 8-byte aligned: rows of GK + GPAD = 40 elements, kq % 4 == 0
+                av[t] = __builtin_bit_cast(bf16x4_t, *reinterpret_cast<const uint2*>(&As[wm + 16 * t + (lane & 15)][kq]));
+                bv[t] = __builtin_bit_cast(bf16x4_t, *reinterpret_cast<const uint2*>(&Bs[wn + 16 * t + (lane & 15)][kq]));
             }
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -160,57 +201,76 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const fl
                 if (part)
                     part[((int64_t)blockIdx.z * M + m) * N + n] = acc[a][b][r];
                 else
-                    gemm_epilogue<EPI>(acc[a][b][r], n, (int64_t)m * ldc + n, C, bias, aux);
+                    gemm_epilogue<EPI>(acc[a][b][r], n, (int64_t)m * ldc + n, C, E);
             }
 }
 
-// C(m, n) = sum over z of part[z][m][n], z ascending, then the epilogue
+// C(m, n) = sum over z of part[z][m][n], z ascending, then the epilogue.  The
+// S <= GEMM_MAX_SPLIT loads are issued before the sum (independent, not a
+// chain of dependent load latencies).
+constexpr int GEMM_MAX_SPLIT = 16;
 template <int EPI>
 __global__ void k_gemm_reduce(int M, int N, int S, const float* __restrict__ part, float* __restrict__ C, int64_t ldc,
-                              const float* __restrict__ bias, float* __restrict__ aux)
+                              GemmEpi E)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)M * N) return;
     const int m = (int)(e / N), n = (int)(e % N);
+    float p[GEMM_MAX_SPLIT];
+#pragma unroll
+    for (int z = 0; z < GEMM_MAX_SPLIT; ++z) p[z] = z < S ? part[(int64_t)z * M * N + e] : 0.0f;
     float v = 0.0f;
-    for (int z = 0; z < S; ++z) v += part[(int64_t)z * M * N + e];
-    gemm_epilogue<EPI>(v, n, (int64_t)m * ldc + n, C, bias, aux);
+#pragma unroll
+    for (int z = 0; z < GEMM_MAX_SPLIT; ++z)
+        if (z < S) v += p[z];
+    gemm_epilogue<EPI>(v, n, (int64_t)m * ldc + n, C, E);
 }
 
-// out[n] = sum_m A[m*lda + n]  (bias gradients): a workgroup sums 64
-// columns, 16 row groups each summing every 16th row, then the 16 partial
-// sums in a fixed order (deterministic)
-__global__ __launch_bounds__(1024) void k_colsum(int M, int N, const float* A, int64_t lda, float* out)
+// out[n] = sum_m A[m*lda + n]  (bias gradients): a workgroup of 1024
+// threads sums 8 columns, 128 row groups each summing every 128th row (8
+// rows for a batch of 1024, loads issued ahead of the adds), then the 128
+// partial sums of a column in a fixed tree (deterministic)
+__global__ __launch_bounds__(1024) void k_colsum(int M, int N, const float* __restrict__ A, int64_t lda,
+                                                 float* __restrict__ out)
 {
-    __shared__ float part[16][64];
-    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int n = blockIdx.x * 64 + c;
+    __shared__ float part[128][9];
+    const int c = threadIdx.x & 7, g = threadIdx.x >> 3;
+    const int n = blockIdx.x * 8 + c;
     float s = 0.f;
-    if (n < N)
-        for (int m = g; m < M; m += 16) s += A[(int64_t)m * lda + n];
+    if (n < N) {
+        int m = g;
+        for (; m + 128 * 7 < M; m += 128 * 8) {
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = A[(int64_t)(m + 128 * j) * lda + n];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += v[j];
+        }
+        for (; m < M; m += 128) s += A[(int64_t)m * lda + n];
+    }
     part[g][c] = s;
     __syncthreads();
-    if (g == 0 && n < N) {
-        float t = 0.f;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) t += part[q][c];
-        out[n] = t;
+    for (int w = 64; w >= 1; w >>= 1) {
+        if (g < w) part[g][c] += part[g + w][c];
+        __syncthreads();
     }
+    if (g == 0 && n < N) out[n] = part[0][c];
 }
 
-// dY = 2 (Y - T) / (M * N); per-row squared error (for the loss)
-__global__ void k_mse_grad(int M, int N, const float* Y, const float* T, float* dY, float* rowsq)
+// out[0] = sum of v[0..n): one workgroup of 1024 threads, each summing a
+// strided share, then a fixed tree (the training loss)
+__global__ __launch_bounds__(1024) void k_sum(int64_t n, const float* __restrict__ v, float* __restrict__ out)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    const float sc = 2.0f / ((float)M * (float)N);
-    float sq = 0.f;
-    for (int n = 0; n < N; ++n) {
-        const float d = Y[(int64_t)m * N + n] - T[(int64_t)m * N + n];
-        dY[(int64_t)m * N + n] = sc * d;
-        sq = fmaf(d, d, sq);
+    __shared__ float part[1024];
+    float s = 0.f;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) s += v[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
     }
-    if (rowsq) rowsq[m] = sq;
+    if (threadIdx.x == 0) out[0] = part[0];
 }
 
 // rows of X and T picked by perm[0..M) into the batch buffers; an index
@@ -310,34 +370,36 @@ __global__ void k_scatter(int64_t n, const uint8_t* keep, const int32_t* offs, i
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_gemm_bf16(int epi, int M, int N, int K, const float* A, int64_t sam, int64_t sak, const float* B,
-                            int64_t sbk, int64_t sbn, float* C, int64_t ldc, const float* bias, float* aux,
-                            float* ws, int64_t ws_floats, hipStream_t st)
+                            int64_t sbk, int64_t sbn, float* C, int64_t ldc, const GemmEpi& E, const MlpWs& ws,
+                            hipStream_t st)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
+    if (epi == 4 && ldc != N) return hipErrorInvalidValue;
     const int gx = (N + GT - 1) / GT, gy = (M + GT - 1) / GT, chunks = (K + GK - 1) / GK;
     // split K into S slices when the output tiles alone leave CUs idle
     int S = 1, kper = chunks;
-    if (ws && chunks >= 2 && gx * gy < 256) {
-        S = std::min(chunks, (256 + gx * gy - 1) / (gx * gy));
-        while (S > 1 && (int64_t)S * M * N > ws_floats) --S;
+    if (ws.part && chunks >= 2 && gx * gy < 256) {
+        S = std::min({chunks, (256 + gx * gy - 1) / (gx * gy), GEMM_MAX_SPLIT});
+        while (S > 1 && (int64_t)S * M * N > ws.part_floats) --S;
         kper = (chunks + S - 1) / S;
         S = (chunks + kper - 1) / kper;
     }
-    float* part = S > 1 ? ws : nullptr;
+    float* part = S > 1 ? ws.part : nullptr;
     const dim3 grid(gx, gy, S);
-#define SWIM_GEMM_CASE(E)                                                                                          \
-    case E:                                                                                                        \
-        hipLaunchKernelGGL(k_gemm_bf16<E>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, \
-                           aux, part, kper);                                                                       \
+#define SWIM_GEMM_CASE(EP)                                                                                         \
+    case EP:                                                                                                       \
+        hipLaunchKernelGGL(k_gemm_bf16<EP>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, E,  \
+                           part, kper);                                                                            \
         if (part)                                                                                                  \
-            hipLaunchKernelGGL(k_gemm_reduce<E>, dim3((unsigned)(((int64_t)M * N + 255) / 256)), dim3(256), 0, st, \
-                               M, N, S, part, C, ldc, bias, aux);                                                  \
+            hipLaunchKernelGGL(k_gemm_reduce<EP>, dim3((unsigned)(((int64_t)M * N + 255) / 256)), dim3(256), 0,    \
+                               st, M, N, S, part, C, ldc, E);                                                      \
         break;
     switch (epi) {
         SWIM_GEMM_CASE(0)
         SWIM_GEMM_CASE(1)
         SWIM_GEMM_CASE(2)
         SWIM_GEMM_CASE(3)
+        SWIM_GEMM_CASE(4)
     default: return hipErrorInvalidValue;
     }
 #undef SWIM_GEMM_CASE
@@ -346,13 +408,14 @@ hipError_t launch_gemm_bf16(int epi, int M, int N, int K, const float* A, int64_
 
 hipError_t launch_colsum(int M, int N, const float* A, int64_t lda, float* out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64), dim3(1024), 0, st, M, N, A, lda, out);
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_colsum, dim3((N + 7) / 8), dim3(1024), 0, st, M, N, A, lda, out);
     return hipGetLastError();
 }
 
-hipError_t launch_mse_grad(int M, int N, const float* Y, const float* T, float* dY, float* rowsq, hipStream_t st)
+hipError_t launch_sum(int64_t n, const float* v, float* out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mse_grad, dim3((M + 255) / 256), dim3(256), 0, st, M, N, Y, T, dY, rowsq);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, st, n, v, out);
     return hipGetLastError();
 }
 
@@ -614,20 +677,31 @@ hipError_t launch_flag_bounded(int64_t n, const float* T, int nt, int n_disp, fl
 }
 
 // ---------------------------------------------------------------------------
-// Fused inference: every workgroup carries a tile of MLP_RT rows through all
-// five layers.  Activations stay in LDS as bfloat16 (the rounding every GEMM
-// operand gets anyway), weights come from a bfloat16 copy packed per layer
-// as W^T [n][k] (k padded to a multiple of 16, n of the last layer to 48)
-// and pass through LDS in chunks of MLP_KC k, double-buffered: the next
-// chunk (of this layer or the next) is read into registers while the
-// current one feeds the MFMAs.  Each of the 4 waves owns 32
-// rows and all output columns; MFMA 16x16x16 bf16 with FP32 accumulation,
-// in the same k order as the layer-by-layer path.  MODE 0 writes the
-// outputs; MODE 1 computes the prescreen distance of every row.
+// Fused inference: every workgroup carries MLP_RT = 64 rows through all
+// five layers, one 16-row tile per wave, with the activations in
+// registers.  The product is formed transposed, C^T = W^T H^T, with
+// v_mfma_f32_16x16x32_bf16: the weights are the A operand (rows n), the
+// activations the B operand (columns = rows m of the batch).  A lane's four
+// results of output tile c are the outputs n = 16c + 4q + r (q = lane / 16,
+// r = 0..3) of row m = lane % 16; bias, GELU and the rounding to bfloat16
+// turn tiles 2p and 2p + 1 into the lane's eight operand values of the next
+// layer's k slice p, i.e. the k order within each 32-wide slice is
+//   slot 8q + j  <->  k = 4q + j (j < 4),  16 + 4q + (j - 4) (j >= 4),
+// and the packed weights (k_pack_w16) use the same order.  So activations
+// never touch LDS; the weights, a bfloat16 copy packed per layer as W^T
+// [n][k] (k in that slot order, padded to a multiple of 32, n of the last
+// layer to 48), pass through LDS in chunks of MLP_KC = 32 k,
+// double-buffered: the next chunk (of this layer or the next) is read into
+// registers while the current one feeds the MFMAs.  40 KB of LDS, 158
+// VGPRs (three waves per SIMD); FP32 accumulation over the slices in order.  MODE 0 writes the outputs;
+// MODE 1 computes the prescreen distance of every row.
 // ---------------------------------------------------------------------------
-constexpr int MLP_RT = 128, MLP_HP = 256 + 8, MLP_KC = 64, MLP_WP = MLP_KC + 8;
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+constexpr int TT = 1;  // 16-row tiles per wave (two: 256 registers and spills, no faster)
+constexpr int MLP_RT = 64 * TT, MLP_KC = 32, MLP_WP = MLP_KC + 8;
 constexpr int MLP_NL = 5;
-constexpr int mlp_kp(int l) { return l == 0 ? 16 : 256; }   // padded K
+constexpr int mlp_kp(int l) { return l == 0 ? 32 : 256; }   // padded K
 constexpr int mlp_np(int l) { return l == MLP_NL - 1 ? 48 : 256; }  // padded N
 constexpr int mlp_k(int l) { return l == 0 ? 5 : 256; }
 constexpr int mlp_n(int l) { return l == MLP_NL - 1 ? 33 : 256; }
@@ -644,8 +718,13 @@ constexpr int64_t mlp_offW_d(int l)
     for (int k = 0; k < l; ++k) o += (int64_t)mlp_k(k) * mlp_n(k) + mlp_n(k);
     return o;
 }
+// the k of operand slot s (0..31) of a 32-wide slice (see above)
+__host__ __device__ constexpr int mlp_slot_k(int s)
+{
+    return (s & 7) < 4 ? 4 * (s >> 3) + (s & 7) : 16 + 4 * (s >> 3) + (s & 7) - 4;
+}
 
-// bfloat16 copy of the weights, transposed and padded (zeros)
+// bfloat16 copy of the weights, transposed, k in slot order, padded (zeros)
 __global__ void k_pack_w16(const float* P, uint16_t* W16)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -653,60 +732,58 @@ __global__ void k_pack_w16(const float* P, uint16_t* W16)
     int l = 0;
     while (l + 1 < MLP_NL && e >= mlp_w16_off(l + 1)) ++l;
     const int64_t i = e - mlp_w16_off(l);
-    const int n = (int)(i / mlp_kp(l)), k = (int)(i % mlp_kp(l));
+    const int n = (int)(i / mlp_kp(l)), kk = (int)(i % mlp_kp(l));
+    const int k = (kk & ~31) + mlp_slot_k(kk & 31);
     const float v = (n < mlp_n(l) && k < mlp_k(l)) ? P[mlp_offW_d(l) + (int64_t)k * mlp_n(l) + n] : 0.0f;
     W16[e] = f2bf(v);
 }
 
-// weight chunk c of layer l (rows n < Np(l), k in [64c, 64c + kce)) as
-// per-thread 16-byte pieces: global -> registers, registers -> LDS
+// weight chunk c of layer l (rows n < Np(l), slots [32c, 32c + 32)) as
+// per-thread 16-byte pieces: global -> registers, registers -> LDS.  A row
+// is 4 pieces; 256 rows are 1024 pieces, 4 per thread (the last layer's 48
+// rows: the first 192 pieces).
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 struct WChunk {
-    u32x4_t v[8];
+    u32x4_t v[4];
 };
 __device__ __forceinline__ const uint16_t* mlp_wl(const uint16_t* W16, int l)
 {
-    return W16 + (l == 0 ? 0 : (l == MLP_NL - 1 ? mlp_w16_off(MLP_NL - 1) : mlp_w16_off(1) + (int64_t)(l - 1) * 65536));
+    return W16 + (l == 0 ? 0 : mlp_w16_off(1) + (int64_t)(l - 1) * 65536);
 }
 __device__ __forceinline__ int mlp_chunks(int l) { return l == 0 ? 1 : 256 / MLP_KC; }
-// One code path for every layer: each thread moves 8 pieces of 16 bytes;
-// the loads are clamped to a valid piece (so the prefetch is always fully
-// defined and stays in registers), only valid pieces are stored.
-__device__ __forceinline__ void wchunk_geom(int l, int& Kp, int& Np, int& per)
+// this thread's pieces of layer l's chunks: element offsets in the packed
+// layer (chunk 0; chunk c adds 32 c) and in the LDS buffer (-1: none)
+struct WAddr {
+    int src[4], dst[4];
+};
+__device__ __forceinline__ void wchunk_addr(int l, int tid, WAddr& a)
 {
-    Kp = l == 0 ? 16 : 256;
-    Np = l == MLP_NL - 1 ? 48 : 256;
-    per = (Kp < MLP_KC ? Kp : MLP_KC) / 8;
-}
-__device__ __forceinline__ void wchunk_load(const uint16_t* W16, int l, int c, int tid, WChunk& w)
-{
-    int Kp, Np, per;
-    wchunk_geom(l, Kp, Np, per);
-    const uint16_t* Wl = mlp_wl(W16, l);
-    const int last = Np * per - 1;
+    const int Kp = l == 0 ? 32 : 256, np4 = 4 * (l == MLP_NL - 1 ? 48 : 256);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int e = min(tid + 256 * q, last);
-        const int n = e / per, p = e - (e / per) * per;
-        w.v[q] = *reinterpret_cast<const u32x4_t*>(Wl + (int64_t)n * Kp + MLP_KC * c + 8 * p);
+    for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q, ec = min(e, np4 - 1);  // clamped: always a valid piece
+        a.src[q] = (ec >> 2) * Kp + 8 * (ec & 3);
+        a.dst[q] = e < np4 ? (e >> 2) * MLP_WP + 8 * (e & 3) : -1;
     }
 }
-__device__ __forceinline__ void wchunk_store(int l, int tid, const WChunk& w, uint16_t* Ws)
+__device__ __forceinline__ void wchunk_load(const uint16_t* Wl, const WAddr& a, int c, WChunk& w)
 {
-    int Kp, Np, per;
-    wchunk_geom(l, Kp, Np, per);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int e = tid + 256 * q;
-        if (e < Np * per) {
-            const int n = e / per, p = e - (e / per) * per;
-            *reinterpret_cast<u32x4_t*>(Ws + n * MLP_WP + 8 * p) = w.v[q];
-        }
-    }
+    for (int q = 0; q < 4; ++q) w.v[q] = *reinterpret_cast<const u32x4_t*>(Wl + a.src[q] + MLP_KC * c);
+}
+__device__ __forceinline__ void wchunk_store(const WAddr& a, const WChunk& w, uint16_t* Ws)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (a.dst[q] >= 0) *reinterpret_cast<u32x4_t*>(Ws + a.dst[q]) = w.v[q];
+}
+__device__ __forceinline__ uint32_t pack_bf2(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, bf16x2_t{(__bf16)a, (__bf16)b});
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_mlp_fused(int64_t M, const float* __restrict__ X,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_fused(int64_t M, const float* __restrict__ X,
                                                    const uint16_t* __restrict__ W16, const float* __restrict__ P,
                                                    float* __restrict__ Y, const float* __restrict__ out_mu,
                                                    const float* __restrict__ out_sd, const float* __restrict__ obs,
@@ -714,130 +791,129 @@ __global__ __launch_bounds__(256) void k_mlp_fused(int64_t M, const float* __res
                                                    uint8_t* __restrict__ keep)
 {
     extern __shared__ __align__(16) uint16_t mlp_smem[];
-    uint16_t* Hs = mlp_smem;                    // [MLP_RT][MLP_HP]
-    uint16_t* Wb = mlp_smem + MLP_RT * MLP_HP;  // [2][256][MLP_WP], double-buffered
+    uint16_t* Wb = mlp_smem;  // [2][256][MLP_WP], double-buffered
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * MLP_RT;
-    // inputs, k padded to 16
-    for (int e = tid; e < MLP_RT * 16; e += 256) {
-        const int r = e >> 4, k = e & 15;
-        const float v = (r0 + r < M && k < 5) ? X[(r0 + r) * 5 + k] : 0.0f;
-        Hs[r * MLP_HP + k] = f2bf(v);
+    const int q = lane >> 4;
+    // this lane's rows of the batch (one per row tile) and output slots
+    int64_t row[TT];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) row[t] = (int64_t)blockIdx.x * MLP_RT + 16 * TT * wave + 16 * t + (lane & 15);
+    // B operands of the current layer: 8 slices x 2 row tiles (layer 0: the
+    // five inputs in slice 0, slot order, zeros elsewhere)
+    u32x4_t hb[TT][8];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+        float xin[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = mlp_slot_k(8 * q + j);
+            xin[j] = (k < 5 && row[t] < M) ? X[row[t] * 5 + k] : 0.0f;
+        }
+        hb[t][0] = u32x4_t{pack_bf2(xin[0], xin[1]), pack_bf2(xin[2], xin[3]), pack_bf2(xin[4], xin[5]),
+                           pack_bf2(xin[6], xin[7])};
+#pragma unroll
+        for (int p = 1; p < 8; ++p) hb[t][p] = u32x4_t{0u, 0u, 0u, 0u};
     }
-    const int wr = 32 * wave;  // this wave's rows
-    const int rowq = 4 * (lane >> 4), col = lane & 15;
-    // the weight chunks of all layers form one sequence g = 0, 1, ...;
-    // chunk g lives in Wbuf[g & 1], chunk g + 1 is fetched while g is used
     WChunk nxt;
-    wchunk_load(W16, 0, 0, tid, nxt);
-    wchunk_store(0, tid, nxt, Wb);
+    WAddr wa_cur, wa_next;
+    wchunk_addr(0, tid, wa_cur);
+    wchunk_load(mlp_wl(W16, 0), wa_cur, 0, nxt);
+    wchunk_store(wa_cur, nxt, Wb);
     int g = 0;
 #pragma unroll 1
     for (int l = 0; l < MLP_NL; ++l) {
-        const int NT = l == MLP_NL - 1 ? 3 : 16;  // 16-wide column tiles
+        const int NT = l == MLP_NL - 1 ? 3 : 16;  // 16-row tiles of n
         const int nchunk = mlp_chunks(l);
-        const int kce = l == 0 ? 16 : MLP_KC;
-        f32x4_t acc[2][16];
+        const uint16_t* Wl = mlp_wl(W16, l);
+        const uint16_t* Wn = mlp_wl(W16, l + 1 < MLP_NL ? l + 1 : l);
+        if (l + 1 < MLP_NL) wchunk_addr(l + 1, tid, wa_next);
+        const float* bias = P + mlp_offW_d(l) + (int64_t)mlp_k(l) * mlp_n(l);
+        // hidden layers start from the bias (C^T[n][m] = b[n]), the last
+        // layer adds it to its 33 outputs
+        f32x4_t acc[TT][16];
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int c = 0; c < 16; ++c) {
+            const f32x4_t b0 = l < MLP_NL - 1 ? *reinterpret_cast<const f32x4_t*>(bias + 16 * c + 4 * q)
+                                              : f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int c = 0; c < 16; ++c) acc[t][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-        for (int ch = 0; ch < nchunk; ++ch, ++g) {
-            __syncthreads();  // chunk g stored; the previous user of Wbuf[(g + 1) & 1] done
-            // fetch the next chunk of the sequence (this layer's next, or the
-            // next layer's first)
-            const bool more = ch + 1 < nchunk || l + 1 < MLP_NL;
-            const int nl = ch + 1 < nchunk ? l : l + 1, nc = ch + 1 < nchunk ? ch + 1 : 0;
-            if (more) wchunk_load(W16, nl, nc, tid, nxt);
-            const uint16_t* Ws = Wb + (g & 1) * 256 * MLP_WP;
-            const int kc = MLP_KC * ch;
-            for (int ks = 0; ks < kce; ks += 16) {
-                const int kq = ks + 4 * (lane >> 4);
-                bf16x4_t av[2];
+            for (int t = 0; t < TT; ++t) acc[t][c] = b0;
+        }
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const uint2 v = *reinterpret_cast<const uint2*>(Hs + (wr + 16 * t + col) * MLP_HP + kc + kq);
-                    av[t] = __builtin_bit_cast(bf16x4_t, v);
-                }
+        for (int ch = 0; ch < 8; ++ch) {
+            if (ch < nchunk) {
+                // chunk g stored by every thread; the previous reader of
+                // Wbuf[(g + 1) & 1] done
+                __syncthreads();
+                const bool same = ch + 1 < nchunk, more = same || l + 1 < MLP_NL;
+                if (more) wchunk_load(same ? Wl : Wn, same ? wa_cur : wa_next, same ? ch + 1 : 0, nxt);
+                const uint16_t* Ws = Wb + (g & 1) * 256 * MLP_WP;
 #pragma unroll
                 for (int c = 0; c < 16; ++c) {
                     if (c < NT) {
-                        const uint2 v = *reinterpret_cast<const uint2*>(Ws + (16 * c + col) * MLP_WP + kq);
-                        const bf16x4_t bv = __builtin_bit_cast(bf16x4_t, v);
-                        acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[0], bv, acc[0][c], 0, 0, 0);
-                        acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[1], bv, acc[1][c], 0, 0, 0);
+                        const bf16x8_t wv = __builtin_bit_cast(
+                            bf16x8_t, *reinterpret_cast<const u32x4_t*>(Ws + (16 * c + (lane & 15)) * MLP_WP + 8 * q));
+#pragma unroll
+                        for (int t = 0; t < TT; ++t)
+                            acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                wv, __builtin_bit_cast(bf16x8_t, hb[t][ch]), acc[t][c], 0, 0, 0);
                     }
+                }
+                if (more) wchunk_store(same ? wa_cur : wa_next, nxt, Wb + ((g + 1) & 1) * 256 * MLP_WP);
+                ++g;
+            }
+        }
+        if (l + 1 < MLP_NL) wa_cur = wa_next;
+        if (l < MLP_NL - 1) {
+            // GELU, bfloat16: tiles 2p, 2p + 1 -> slice p of the next
+            // layer's operand
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {
+#pragma unroll
+                for (int t = 0; t < TT; ++t) {
+                    const f32x4_t a0 = acc[t][2 * p], a1 = acc[t][2 * p + 1];
+                    hb[t][p] = u32x4_t{pack_bf2(gelu_f(a0[0]), gelu_f(a0[1])), pack_bf2(gelu_f(a0[2]), gelu_f(a0[3])),
+                                       pack_bf2(gelu_f(a1[0]), gelu_f(a1[1])), pack_bf2(gelu_f(a1[2]), gelu_f(a1[3]))};
                 }
             }
-            if (more) wchunk_store(nl, tid, nxt, Wb + ((g + 1) & 1) * 256 * MLP_WP);
-        }
-        const float* bias = P + mlp_offW_d(l) + (int64_t)mlp_k(l) * mlp_n(l);
-        if (l < MLP_NL - 1) {
-            // bias, GELU, back into this wave's rows of the activations
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                for (int c = 0; c < 16; ++c) {
-                    const int n = 16 * c + col;
-                    const float bn = bias[n];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        Hs[(wr + 16 * t + rowq + r) * MLP_HP + n] = f2bf(gelu_f(acc[t][c][r] + bn));
-                }
         } else if (MODE == 0) {
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
+            for (int t = 0; t < TT; ++t)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const int n = 16 * c + col;
-                    if (n >= 33) continue;
-                    const float bn = bias[n];
+                for (int c = 0; c < 3; ++c)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int64_t row = r0 + wr + 16 * t + rowq + r;
-                        if (row < M) Y[row * 33 + n] = acc[t][c][r] + bn;
+                        const int n = 16 * c + 4 * q + r;
+                        if (n < 33 && row[t] < M) Y[row[t] * 33 + n] = acc[t][c][r] + bias[n];
                     }
-                }
         } else {
             // prescreen: d = sqrt(mean_{n < n_sum} (mu_n + sd_n y_n - obs_n)^2)
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                float sq[4] = {0.f, 0.f, 0.f, 0.f};
+            for (int t = 0; t < TT; ++t) {
+                float sq = 0.f;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const int n = 16 * c + col;
-                    if (n < n_sum) {
-                        const float bn = bias[n], mu = out_mu[n], sd = out_sd[n], ob = obs[n];
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const float dv = fmaf(sd, acc[t][c][r] + bn, mu) - ob;
-                            sq[r] = fmaf(dv, dv, sq[r]);
-                        }
-                    }
-                }
-                // sum over the 16 lanes that hold the same rows, fixed tree
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int o = 8; o >= 1; o >>= 1) sq[r] += __shfl_xor(sq[r], o, 16);
-                if (col == 0) {
+                for (int c = 0; c < 3; ++c)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int64_t row = r0 + wr + 16 * t + rowq + r;
-                        if (row < M) {
-                            const float d = sqrtf(sq[r] / (float)n_sum);
-                            if (dist) dist[row] = d;
-                            keep[row] = (d <= tol) ? 1 : 0;
+                        const int n = 16 * c + 4 * q + r;
+                        if (n < n_sum) {
+                            const float dv = fmaf(out_sd[n], acc[t][c][r] + bias[n], out_mu[n]) - obs[n];
+                            sq = fmaf(dv, dv, sq);
                         }
                     }
+                // the four lanes of row m (lane % 16 equal), fixed order
+                sq += __shfl_xor(sq, 16, 64);
+                sq += __shfl_xor(sq, 32, 64);
+                if (q == 0 && row[t] < M) {
+                    const float d = sqrtf(sq / (float)n_sum);
+                    if (dist) dist[row[t]] = d;
+                    keep[row[t]] = (d <= tol) ? 1 : 0;
                 }
             }
         }
     }
 }
 
-size_t mlp_fused_lds_bytes() { return (size_t)(MLP_RT * MLP_HP + 2 * 256 * MLP_WP) * sizeof(uint16_t); }
+size_t mlp_fused_lds_bytes() { return (size_t)(2 * 256 * MLP_WP) * sizeof(uint16_t); }
 int64_t mlp_w16_count() { return MLP_W16_TOTAL; }
 
 hipError_t launch_pack_w16(const float* P, uint16_t* W16, hipStream_t st)
@@ -852,15 +928,6 @@ hipError_t launch_mlp_fused(int mode, int64_t M, const float* X, const uint16_t*
 {
     if (M <= 0) return hipSuccess;
     const size_t lds = mlp_fused_lds_bytes();
-    static bool attr[2] = {false, false};
-    if (!attr[mode != 0]) {
-        hipError_t e = mode == 0 ? hipFuncSetAttribute((const void*)k_mlp_fused<0>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
-                                 : hipFuncSetAttribute((const void*)k_mlp_fused<1>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr[mode != 0] = true;
-    }
     const dim3 grid((unsigned)((M + MLP_RT - 1) / MLP_RT));
     if (mode == 0)
         hipLaunchKernelGGL(k_mlp_fused<0>, grid, dim3(256), lds, st, M, X, W16, P, Y, out_mu, out_sd, obs, n_sum, tol,
