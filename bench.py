@@ -2,9 +2,13 @@
 
 Workload ("batch"): 4096 ABC parameter sets drawn from the uniform prior
 alpha in [0, 10], S_b in [0.01, 1], S_s in [1e2, 1e4] (Philox seed 1); every
-swimmer has N = 128 points and runs 5000 forward-Euler steps of dt = 5e-5,
-its head observed every 100 steps; FP32; the paper's blob (eq. eqnblob, the
-library's default).  One bench step is one pass of the hot path over that
+swimmer has N = 128 points and runs to T = 0.25 in 10000 forward-Euler
+steps of dt = 2.5e-5, its head observed every 200 steps (the data's 50
+times); FP32; the paper's blob (eq. eqnblob, the library's default).  The
+workload as first stated takes 5000 steps of 5e-5: with the paper's blob
+the data's own parameters (2, 0.1, 1e3) are beyond forward Euler's
+stability bound there and blow up at step 40, so the step is halved over
+the same time.  One bench step is one pass of the hot path over that
 batch: the per-system set-up (constants and the FP32 kernel tables of the
 paper's blob), then preferred curvature, elastic forces, dense
 regularized-Brinkmanlet velocity sum, Euler update and observations for all
@@ -87,7 +91,7 @@ def cpu_baseline(steps_cpu):
     samples of the workloads (its paper-blob kernel integrates every pair at
     alpha > 0, about 1 ms per pair on one core):
       batch  one swimmer of the batched workload at the data's parameters
-             (alpha = 2), N = 128, the paper's blob, steps_cpu of its 5000
+             (alpha = 2), N = 128, the paper's blob, steps_cpu of its 10000
              steps, all threads: the reported value;
       single the single-swimmer workload on one core: N = 64, alpha = 1
              (quadrature) for 3 of its 2000 steps (extrapolated to 2000),
@@ -95,8 +99,8 @@ def cpu_baseline(steps_cpu):
       dense  one velocity evaluation of the dense workload's sample 0
              (8 x 512 points, its alpha), at 32 of its 4096 targets, all
              threads.
-    The batched workload's 64-particle subset (5000 steps each) would take
-    about 5e9 pair quadratures, days on these cores: the batch sample's rate
+    The batched workload's 64-particle subset (10000 steps each) would take
+    about 1e10 pair quadratures, days on these cores: the batch sample's rate
     stands for it."""
     from oracle import core
     from paper_1910_12007_amd import inputs
@@ -105,12 +109,12 @@ def cpu_baseline(steps_cpu):
     out = {"kind": "oracle", "cores": threads, "cpu_model": cpu_model(), "legs": {}}
     P = inputs.theta_rows(inputs.TRUE_THETA)
     t0 = time.perf_counter()
-    core.forward(P, 128, steps_cpu, 5e-5, 100)
+    core.forward(P, 128, steps_cpu, inputs.BATCH_DT, 100)
     sec = time.perf_counter() - t0
     out["value"] = 128 * 128 * steps_cpu / sec
     out["unit"] = "pair-evals/s"
     out["sample"] = (f"1 swimmer of the batched workload (alpha, S_b, S_s = 2, 0.1, 1e3), N=128, paper's blob, "
-                     f"{steps_cpu} of 5000 steps, FP64, {sec:.1f} s on {threads} threads")
+                     f"{steps_cpu} of {inputs.BATCH_STEPS} steps, FP64, {sec:.1f} s on {threads} threads")
     core.set_threads(1)
     try:
         single = {}
@@ -227,29 +231,32 @@ def dense_leg(ctx, stream, samples=64, steps=1000, dt_div=64):
     return out
 
 
-def per_sample_leg(ctx, stream, P_all, n=256, N=128, steps=5000, dt=5e-5):
+def per_sample_leg(ctx, stream, P_all, n=256, N=128, steps=None, dt=None):
     """The batched generation's first n draws as one fused persistent launch
     against one launch per sample (each a batch of one system), both on the
     library's path with inputs resident; HIP events on the same stream."""
     import torch
-    from paper_1910_12007_amd import swim
+    from paper_1910_12007_amd import inputs, swim
+    steps = steps or inputs.BATCH_STEPS
+    dt = dt or inputs.BATCH_DT
+    oe = inputs.BATCH_OBS_EVERY
     P = P_all[:n].contiguous()
-    obs = torch.empty((n, steps // 100, 2), dtype=torch.float32, device="cuda")
+    obs = torch.empty((n, steps // oe, 2), dtype=torch.float32, device="cuda")
     speed = torch.empty(n, dtype=torch.float32, device="cuda")
     status = torch.empty(n, dtype=torch.int32, device="cuda")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     graph_mode = swim.swim_get_option(ctx, swim.SWIM_OPT_GRAPH)
     swim.swim_set_option(ctx, swim.SWIM_OPT_GRAPH, 0)
     try:
-        swim.swim_forward(ctx, np.full(n, N, np.int32), None, P, steps, dt, 100, 1.5, obs, speed, status,
+        swim.swim_forward(ctx, np.full(n, N, np.int32), None, P, steps, dt, oe, 1.5, obs, speed, status,
                           stream=stream)
         ev[0].record(stream)
-        swim.swim_forward(ctx, np.full(n, N, np.int32), None, P, steps, dt, 100, 1.5, obs, speed, status,
+        swim.swim_forward(ctx, np.full(n, N, np.int32), None, P, steps, dt, oe, 1.5, obs, speed, status,
                           stream=stream)
         ev[1].record(stream)
         ev[2].record(stream)
         for i in range(n):
-            swim.swim_forward(ctx, np.full(1, N, np.int32), None, P[i:i + 1], steps, dt, 100, 1.5, obs[i:i + 1],
+            swim.swim_forward(ctx, np.full(1, N, np.int32), None, P[i:i + 1], steps, dt, oe, 1.5, obs[i:i + 1],
                               speed[i:i + 1], status[i:i + 1], stream=stream)
         ev[3].record(stream)
         torch.cuda.synchronize()
@@ -259,7 +266,7 @@ def per_sample_leg(ctx, stream, P_all, n=256, N=128, steps=5000, dt=5e-5):
     return {"draws": n, "fused_ms": fused, "per_sample_launches_ms": single, "speedup": single / fused}
 
 
-def pmc_leg(ctx, data, n=16384, steps=5000, dt=5e-5, quantiles=(0.5, 0.25, 0.1)):
+def pmc_leg(ctx, data, n=16384, steps=None, dt=None, quantiles=(0.5, 0.25, 0.1)):
     """Uneven batching with population Monte Carlo: n particles, each with
     its own filament size N ~ U{64, 96, ..., 512} (seed 2) and the batched
     workload's priors, steps and dt; three generations at the 50th, 25th and
@@ -270,6 +277,8 @@ def pmc_leg(ctx, data, n=16384, steps=5000, dt=5e-5, quantiles=(0.5, 0.25, 0.1))
     graph once the layout repeats."""
     import torch
     from paper_1910_12007_amd import inputs, swim, surrogate_abc
+    steps = steps or inputs.BATCH_STEPS
+    dt = dt or inputs.BATCH_DT
     N = inputs.uneven_sizes(n, seed=2)
     model = surrogate_abc.batch_model(steps=steps, dt=dt)
     theta0 = swim.abc_prior_draw(2, n, inputs.PRIOR_LO, inputs.PRIOR_HI)
@@ -315,7 +324,7 @@ def tmcmc_leg(ctx, data, n=2048, seed=7):
     wall = time.perf_counter() - t0
     th = r["theta"]
     truth = np.append(inputs.TRUE_THETA, 1e-3)
-    return {"workload": f"TMCMC, {n} samples per stage, N=128, 5000 steps dt=5e-05, FP32, "
+    return {"workload": f"TMCMC, {n} samples per stage, N=128, {model.steps} steps dt={model.dt}, FP32, "
                         "theta = (alpha, S_b, S_s, sigma), data of the batched workload",
             "stages": r["n_stages"], "q": [float(x) for x in r["q"]], "forward_runs": r["runs"],
             "seconds": wall, "forward_seconds": r["seconds"], "forward_runs_per_s": r["runs"] / r["seconds"],
@@ -548,7 +557,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--euler-steps", type=int, default=5000)
+    ap.add_argument("--euler-steps", type=int, default=0, help="0: the workload's 10000 steps")
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--wps", type=int, default=0, help="waves per system (0: library default)")
@@ -591,7 +600,11 @@ def main():
         print(json.dumps(dense_leg(ctx, stream, steps=args.dense_only, dt_div=args.dense_div)), flush=True)
         ctx.close()
         return
-    n, N, steps, dt, obs_every = args.n, 128, args.euler_steps, 5e-5, 100
+    n, N = args.n, 128
+    steps, dt, obs_every = inputs.BATCH_STEPS, inputs.BATCH_DT, inputs.BATCH_OBS_EVERY
+    if args.euler_steps:
+        steps = args.euler_steps
+        obs_every = min(obs_every, steps)
     n_obs = steps // obs_every
     theta = swim.abc_prior_draw(1, n, inputs.PRIOR_LO, inputs.PRIOR_HI)
     P = torch.from_numpy(inputs.theta_rows(theta)).to("cuda")

@@ -34,6 +34,11 @@ PARAM_FIELDS = ("alpha", "Sb", "Ss", "b", "omega", "k", "phase", "x0", "y0")
 PRIOR_LO = np.array([0.0, 0.01, 1e2])
 PRIOR_HI = np.array([10.0, 1.0, 1e4])
 TRUE_THETA = np.array([2.0, 0.1, 1e3])
+# the batched workload's time grid: T = 0.25 in 10000 forward-Euler steps of
+# 2.5e-5, the head every 200 steps (the synthetic data's 50 times).  Half the
+# step of the workload as first stated (5000 of 5e-5): with the paper's blob
+# the true parameters are beyond forward Euler's stability bound at 5e-5.
+BATCH_STEPS, BATCH_DT, BATCH_OBS_EVERY = 10000, 2.5e-5, 200
 
 UNEVEN_N_CHOICES = np.arange(64, 513, 32)
 

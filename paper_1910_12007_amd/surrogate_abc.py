@@ -6,14 +6,14 @@ only sequences the calls, times them and summarizes the accepted sets.
 The experiment:
 
 1. plain batched ABC on the batched generation's draws (4096 prior draws,
-   seed 1, N = 128, 5000 steps of dt = 5e-5): its 5th-percentile tolerance
-   ``tol`` over the completed runs;
+   seed 1, N = 128, 10000 steps of dt = 2.5e-5): its 5th-percentile
+   tolerance ``tol`` over the completed runs;
 2. training set: ``n_train_runs`` prior draws (seed 4) run on the forward
    model; the first ``train_cap`` completed ones whose head stays within
    1.5 beat amplitudes of its start give (alpha,
    ln S_b, ln S_s, b, omega) -> 16 head displacements and the mean speed
-   (with the paper's blob about 2.3 % of the draws qualify, so 65536
-   training runs take about 3M draws);
+   (about 8 % of the draws qualify, so 65536 training runs take about
+   0.8M draws);
 3. training: Adam (lr 1e-3, batch 1024, ``epochs`` epochs) on the GPU with
    the library's BF16 MFMA forward and backward kernels;
 4. prescreen ``n_prop`` fresh prior draws at ``factor * tol`` with the
@@ -47,7 +47,8 @@ SUM_IDX = np.arange(2, 50, 3, dtype=np.int32)
 MAX_DISP_PER_B = 1.5
 
 
-def batch_model(steps=5000, dt=5e-5, obs_every=100, dtype=swim.SWIM_F32):
+def batch_model(steps=inputs.BATCH_STEPS, dt=inputs.BATCH_DT, obs_every=inputs.BATCH_OBS_EVERY,
+                dtype=swim.SWIM_F32):
     m = swim.abc_model()
     for d in range(3):
         m.lo[d] = float(inputs.PRIOR_LO[d])
@@ -131,7 +132,7 @@ def posterior_summary(theta):
     return dict(mean=theta.mean(0), lo=np.quantile(theta, 0.05, axis=0), hi=np.quantile(theta, 0.95, axis=0))
 
 
-def run(ctx, data, N=128, n_c1=4096, n_train_runs=3_000_000, train_cap=65536, epochs=20, n_prop=1 << 20,
+def run(ctx, data, N=128, n_c1=4096, n_train_runs=1_000_000, train_cap=65536, epochs=20, n_prop=1 << 20,
         factor=2.0, prop_seed=5, model=None, keep_surrogate=False):
     """The whole comparison.  Plain ABC runs on the same n_prop proposals
     (same Philox seed) as the prescreen, so the surrogate's accepted set is

@@ -467,3 +467,73 @@ def test_dense_sample_as_benchmarked(paper, oracle_core):
     err = np.linalg.norm(o32 - o64)
     print({"fp32_vs_fp64": err / disp})
     assert err <= 1e-4 * disp + floor
+
+
+def test_batched_workload_as_benchmarked(paper):
+    """The batched workload in the launch configuration the benchmark times:
+    4096 prior draws (Philox seed 1), N = 128, the paper's blob, 10000 steps
+    of dt = 2.5e-5, head every 200 steps, FP32, default launch shapes, one
+    swim_forward call; then the ABC distance, tolerance and accept mask.
+    The tolerance and mask follow the oracle's definitions applied to the
+    GPU distances.  The oracle integrates every pair of the paper's blob
+    (~10 s per step of this system on one core), so the sampled runs, the
+    first completed run in draw order and the one closest to the data, are
+    held against the library's FP64 run of the same system over all 10000
+    steps (the FP64 path is pinned to the oracle above), at 1e-4 on the mean
+    speed, the ABC distance and the displacement series; the two earliest
+    blow-ups blow up in FP64 too."""
+    import os
+    from oracle import abc
+    n, N = 4096, 128
+    steps, dt, oe = inputs.BATCH_STEPS, inputs.BATCH_DT, inputs.BATCH_OBS_EVERY
+    n_obs = steps // oe
+    theta = swim.abc_prior_draw(1, n, inputs.PRIOR_LO, inputs.PRIOR_HI)
+    P = inputs.theta_rows(theta)
+    obs = torch.empty((n, n_obs, 2), dtype=torch.float32, device="cuda")
+    speed = torch.empty(n, dtype=torch.float32, device="cuda")
+    status = torch.empty(n, dtype=torch.int32, device="cuda")
+    done = torch.empty(n, dtype=torch.int32, device="cuda")
+    swim.swim_forward(paper, np.full(n, N, np.int32), None, torch.from_numpy(P).cuda(), steps, dt, oe, 1.5, obs,
+                      speed, status, done)
+    data = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "abc_data_batch.txt"))[:n_obs, :2]
+    dist = torch.empty(n, dtype=torch.float64, device="cuda")
+    tol = torch.empty(1, dtype=torch.float64, device="cuda")
+    acc = torch.empty(n, dtype=torch.uint8, device="cuda")
+    swim.abc_distance(paper, obs, torch.from_numpy(data).cuda(), status, dist)
+    swim.abc_select(paper, dist, 0.05, tol, acc)
+    torch.cuda.synchronize()
+    st, d, sd = status.cpu().numpy(), dist.cpu().numpy(), done.cpu().numpy()
+    assert tol.item() == abc.tolerance(d, 0.05)
+    assert np.array_equal(acc.cpu().numpy().astype(bool), abc.accept(d, tol.item()))
+    ok, bad = np.flatnonzero(st == 0), np.flatnonzero(st != 0)
+    assert 100 < ok.size < n
+    samples = [ok[0], ok[np.argmin(d[ok])]]
+    P2 = torch.from_numpy(P[samples]).cuda()
+    o64 = torch.empty((2, n_obs, 2), dtype=torch.float64, device="cuda")
+    s64 = torch.empty(2, dtype=torch.float64, device="cuda")
+    t64 = torch.empty(2, dtype=torch.int32, device="cuda")
+    swim.swim_forward(paper, [N, N], None, P2, steps, dt, oe, 1.5, o64, s64, t64)
+    torch.cuda.synchronize()
+    assert list(t64.cpu().numpy()) == [0, 0]
+    o32 = obs.cpu().double().numpy()
+    x0 = np.array([1.0, 0.0])
+    for k, i in enumerate(samples):
+        r, rs = o64[k].cpu().numpy(), s64[k].item()
+        dr = abc.distance(r[None], data)[0]
+        floor = np.linalg.norm(np.spacing(np.abs(r).astype(np.float32)))
+        err = np.linalg.norm(o32[i] - r)
+        print({"draw": int(i), "theta": theta[i], "series": err / np.linalg.norm(r - x0),
+               "speed": abs(speed[i].item() / rs - 1), "dist": abs(d[i] / dr - 1)})
+        assert abs(speed[i].item() / rs - 1) <= 1e-4
+        assert abs(d[i] / dr - 1) <= 1e-4
+        assert err <= 1e-4 * np.linalg.norm(r - x0) + floor
+    # the two earliest blow-ups blow up in FP64 too
+    early = bad[np.argsort(sd[bad], kind="stable")[:2]]
+    k = int(sd[early].max()) + 50
+    Pb = torch.from_numpy(P[early]).cuda()
+    ob = torch.empty((2, 1, 2), dtype=torch.float64, device="cuda")
+    sb = torch.empty(2, dtype=torch.float64, device="cuda")
+    tb = torch.empty(2, dtype=torch.int32, device="cuda")
+    swim.swim_forward(paper, [N, N], None, Pb, k, dt, k, 1.5, ob, sb, tb)
+    torch.cuda.synchronize()
+    assert np.all(tb.cpu().numpy() != 0), (theta[early], sd[early])

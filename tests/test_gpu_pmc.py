@@ -30,7 +30,7 @@ def test_pmc_generations(ctx):
     from oracle import abc
     n, steps = 1024, 1000
     N = inputs.uneven_sizes(n, seed=12)
-    model = surrogate_abc.batch_model(steps=steps, dt=5e-5)
+    model = surrogate_abc.batch_model(steps=steps, dt=5e-5, obs_every=100)
     data = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "abc_data_batch.txt"))[:steps // 100, :2]
     g0 = swim.abc_step(ctx, model, data, N, 3, 0, 0.5)
     assert np.array_equal(g0["theta"], abc.prior_draw(3, n, inputs.PRIOR_LO, inputs.PRIOR_HI))

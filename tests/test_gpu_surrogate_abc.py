@@ -44,7 +44,7 @@ def ctx():
 def test_dataset_matches_stepwise_calls(ctx):
     """Training rows = forward runs of the same prior draws, kept when they
     complete and stay within the displacement bound, in draw order."""
-    model = sa.batch_model(steps=600)
+    model = sa.batch_model(steps=600, dt=5e-5, obs_every=100)
     n_runs, N, n_obs = 1500, 128, 6
     sum_idx = np.arange(16) % n_obs
     cap = 2048
@@ -80,7 +80,7 @@ def test_dataset_matches_stepwise_calls(ctx):
 def test_prescreened_matches_stepwise_calls(ctx):
     """Survivors = proposals whose surrogate distance is <= factor * tol;
     their re-run distances equal plain ABC's on the same draws."""
-    model = sa.batch_model(steps=600)
+    model = sa.batch_model(steps=600, dt=5e-5, obs_every=100)
     n_obs = 6
     dat = data()[:n_obs]
     sum_idx = np.arange(16) % n_obs
