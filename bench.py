@@ -42,13 +42,13 @@ sys.path.insert(0, ROOT)
 # (4 FMA): 42 FLOP (FMA = 2) per distinct pair, 21 per ordered pair.  The
 # kernel is bound by VALU instruction issue, not FLOP: integer and float
 # operations share the issue slots.  rocprofv3's SQ_INSTS_VALU over the
-# launch gives 22.3 VALU lane-operations per ordered pair evaluation, all
+# launch gives 22.1 VALU lane-operations per ordered pair evaluation, all
 # work of the step included (the symmetric pair loop alone is 16.5 in the
 # ISA); the issue peak without packed FP32 is 256 CUs x 4 SIMDs x 16 lanes
 # per clock x 2.4 GHz = 39.3e12 lane-operations/s, i.e. 78.6 TFLOP/s of FMA
 # (the build keeps packed FP32 off).
 # (profiles/k_forward_batch_4096x128_counters.md)
-VALU_OPS_PER_PAIR = 22.3
+VALU_OPS_PER_PAIR = 22.1
 PAIR_LOOP_VALU_OPS = 16.5  # the symmetric pair loop alone (ISA), also the sperm kernel's
 FP32_FLOP_PER_PAIR = 21
 NONPACKED_FP32_PEAK_TFLOPS = 78.6
@@ -59,11 +59,11 @@ VALU_OPS_PER_PAIR_BIG = 39.9
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 # HBM bytes of one launch of that kernel on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch: 52369.6 and 3098.9) scaled by
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch: 52344.8 and 3213.0) scaled by
 # the same counters over a 256 MiB device copy (x2.0 and x1.0), for the
 # kernel as it stands (profiles/k_forward_batch_4096x128_counters.md); set it
 # to None whenever the kernel changes until the counters are taken again
-TRAFFIC_BYTES = 52369.6 * 1024 * 2.0 + 3098.9 * 1024 * 1.0
+TRAFFIC_BYTES = 52344.8 * 1024 * 2.0 + 3213.0 * 1024 * 1.0
 
 
 def load_data():
