@@ -813,8 +813,15 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
     for (int step = 0; step < r.steps; ++step) {
         // pair phase: this wave's share of the symmetric pair schedule
         {
+            // no pair lies beyond the FP32 table: every step starts from
+            // positions within the run bound |x|, |y| <= 1e3 (a step that
+            // leaves it ends the run), so r <= 2829; with eps >= 1.5/511
+            // (n <= 512, one filament's N at most 512) 1 + sigma r^2 <
+            // 1 + 4 (r/eps)^2 < 2^42, inside the table's 2^44 (the initial
+            // positions are the caller's: a run placed beyond the bound
+            // reads zeros for its far pairs in its first step and stops)
             T ax[TPL], ay[TPL];
-            pair_phase_sym<T, TPL, WPS>(C, L.tab, L.src, n, wave, lane, ax, ay);
+            pair_phase_sym<T, TPL, WPS, false>(C, L.tab, L.src, n, wave, lane, ax, ay);
 #pragma unroll
             for (int c = 0; c < TPL; ++c) {
                 if (c < nblk64) {
@@ -925,9 +932,16 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
     __syncthreads();
 }
 
+// FP32 systems of up to 128 points in 16-wave workgroups are held to 64
+// VGPRs (8 waves per SIMD): two systems then share a CU, so that one's
+// barriers and LDS latency overlap the other's pair phase (without the
+// bound the build takes 92 VGPRs and one system per CU; the spills the bound
+// costs lie outside the pair loop)
 template <typename T, int TPL, int WPS>
-__global__ __launch_bounds__(64 * WPS) void k_forward(Batch b, Run r, const int32_t* order, int32_t* queue, T* obs,
-                                                      T* speed, int32_t* status, int32_t* steps_done)
+__global__ __launch_bounds__(64 * WPS) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && TPL <= 2 && WPS == 16
+                                                                                 ? 8
+                                                                                 : 1))) void
+k_forward(Batch b, Run r, const int32_t* order, int32_t* queue, T* obs, T* speed, int32_t* status, int32_t* steps_done)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_item;

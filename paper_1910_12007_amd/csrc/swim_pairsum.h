@@ -88,10 +88,10 @@ __device__ __forceinline__ int src2_slot(int i) { return ((i >> 6) << 7) + (i & 
 
 // kernel functions of one pair at offset (dx, dy).  FP64: direct evaluation.
 // FP32 (positions scaled by rho): the table (FAR = false; a pair beyond it
-// gives zeros and sets far), or the direct evaluation of pairs beyond the
-// table only (FAR = true; zeros for the others).  H2 comes scaled to the
-// coordinates (H2 / sigma in FP32).
-template <typename T, bool FAR>
+// gives zeros and, with CHECK, sets far), or the direct evaluation of pairs
+// beyond the table only (FAR = true; zeros for the others).  H2 comes scaled
+// to the coordinates (H2 / sigma in FP32).
+template <typename T, bool FAR, bool CHECK = true>
 __device__ __forceinline__ void pair_kernel(const SysConst<T>& C, const char* et, T dx, T dy, T& Ht, T& H2,
                                             bool& far)
 {
@@ -101,7 +101,7 @@ __device__ __forceinline__ void pair_kernel(const SysConst<T>& C, const char* et
         const uint32_t bits = __builtin_bit_cast(uint32_t, fmaf(dx, dx, fmaf(dy, dy, 1.0f)));
         const uint32_t id = bits >> TAB_SHIFT;
         if constexpr (!FAR) {
-            far = far || id >= TAB_END;
+            if constexpr (CHECK) far = far || id >= TAB_END;
             tab_eval(*reinterpret_cast<const TabE*>(et + (min(id, TAB_END) << 5)), tab_u(bits), Ht, H2);
         } else {
             Ht = 0.0f;
@@ -116,7 +116,7 @@ __device__ __forceinline__ void pair_kernel(const SysConst<T>& C, const char* et
 
 // offsets [s_lo, s_hi) of block pair (a, b); adds the target sums to block
 // a's and the moving points' sums to block b's accumulators of this lane
-template <typename T, int TPL, bool FAR>
+template <typename T, int TPL, bool FAR, bool CHECK = true>
 __device__ __forceinline__ bool sym_offsets(const SysConst<T>& C, const char* et, const Src4<T>* src2, int a, int b,
                                             int s_lo, int s_hi, int lane, T (&accx)[TPL], T (&accy)[TPL])
 {
@@ -124,25 +124,32 @@ __device__ __forceinline__ bool sym_offsets(const SysConst<T>& C, const char* et
     const Src4<T>* sp = src2 + (b << 7) + lane;
     T ax = (T)0, ay = (T)0, bx = (T)0, by = (T)0;
     bool far = false;
-    const int s_full = (a == b) ? min(s_hi, 32) : s_hi;  // offsets every lane takes
-    for (int s = s_lo; s < s_full; ++s) {
-        const Src4<T> q = sp[s];
+    // offsets every lane takes (wave-uniform: a scalar loop counter), two
+    // per iteration (one address update for both loads)
+    const int s_full = __builtin_amdgcn_readfirstlane((a == b) ? min(s_hi, 32) : s_hi);
+    auto offset = [&](const Src4<T>& q) {
         const T dx = ti.x - q.x, dy = ti.y - q.y;
         T Ht, H2;
-        pair_kernel<T, FAR>(C, et, dx, dy, Ht, H2, far);
+        pair_kernel<T, FAR, CHECK>(C, et, dx, dy, Ht, H2, far);
         const T fdj = H2 * fma_t(q.fx, dx, q.fy * dy);
         ax = fma_t(Ht, q.fx, fma_t(fdj, dx, ax));
         ay = fma_t(Ht, q.fy, fma_t(fdj, dy, ay));
         const T fdi = H2 * fma_t(ti.fx, dx, ti.fy * dy);
         bx = lane_rot(fma_t(Ht, ti.fx, fma_t(fdi, dx, bx)));
         by = lane_rot(fma_t(Ht, ti.fy, fma_t(fdi, dy, by)));
+    };
+    int s = __builtin_amdgcn_readfirstlane(s_lo);
+    for (; s + 1 < s_full; s += 2) {
+        offset(sp[s]);
+        offset(sp[s + 1]);
     }
+    if (s < s_full) offset(sp[s]);
     if (s_full < s_hi) {
         // offset 32 within a block: lanes 32..63 repeat lanes 0..31's couples
         const Src4<T> q = sp[32];
         const T dx = ti.x - q.x, dy = ti.y - q.y;
         T Ht, H2;
-        pair_kernel<T, FAR>(C, et, dx, dy, Ht, H2, far);
+        pair_kernel<T, FAR, CHECK>(C, et, dx, dy, Ht, H2, far);
         Ht = lane < 32 ? Ht : (T)0;
         H2 = lane < 32 ? H2 : (T)0;
         const T fdj = H2 * fma_t(q.fx, dx, q.fy * dy);
@@ -171,8 +178,10 @@ __device__ __forceinline__ bool sym_offsets(const SysConst<T>& C, const char* et
 }
 
 // this wave's share of the pair sums of all n points: accx[c], accy[c] hold
-// the partial velocity of point 64c + lane
-template <typename T, int TPL, int WPS>
+// the partial velocity of point 64c + lane.  CHECK = false: the caller
+// guarantees that no FP32 pair lies beyond the table, which then is read
+// without the per-pair test (an index beyond it reads the zero entry)
+template <typename T, int TPL, int WPS, bool CHECK = true>
 __device__ __forceinline__ void pair_phase_sym(const SysConst<T>& C, const TabSys* tab, const Src4<T>* src2, int n,
                                                int wave, int lane, T (&accx)[TPL], T (&accy)[TPL])
 {
@@ -196,8 +205,8 @@ __device__ __forceinline__ void pair_phase_sym(const SysConst<T>& C, const TabSy
             const int lo = max(g0, g), hi = min(g1, g + len);
             if (lo < hi) {
                 const int s_lo = lo - g + base, s_hi = hi - g + base;
-                const bool far = sym_offsets<T, TPL, false>(C, et, src2, a, b, s_lo, s_hi, lane, accx, accy);
-                if constexpr (sizeof(T) == 4) {
+                const bool far = sym_offsets<T, TPL, false, CHECK>(C, et, src2, a, b, s_lo, s_hi, lane, accx, accy);
+                if constexpr (sizeof(T) == 4 && CHECK) {
                     if (__any(far)) sym_offsets<T, TPL, true>(C, et, src2, a, b, s_lo, s_hi, lane, accx, accy);
                 }
             }
