@@ -42,14 +42,14 @@ sys.path.insert(0, ROOT)
 # (4 FMA): 42 FLOP (FMA = 2) per distinct pair, 21 per ordered pair.  The
 # kernel is bound by VALU instruction issue, not FLOP: integer and float
 # operations share the issue slots.  rocprofv3's SQ_INSTS_VALU over the
-# launch gives 22.1 VALU lane-operations per ordered pair evaluation, all
-# work of the step included (the symmetric pair loop alone is 16.5 in the
+# launch gives 21.6 VALU lane-operations per ordered pair evaluation, all
+# work of the step included (the symmetric pair loop alone is 15.75 in the
 # ISA); the issue peak without packed FP32 is 256 CUs x 4 SIMDs x 16 lanes
 # per clock x 2.4 GHz = 39.3e12 lane-operations/s, i.e. 78.6 TFLOP/s of FMA
 # (the build keeps packed FP32 off).
 # (profiles/k_forward_batch_4096x128_counters.md)
-VALU_OPS_PER_PAIR = 22.1
-PAIR_LOOP_VALU_OPS = 16.5  # the symmetric pair loop alone (ISA), also the sperm kernel's
+VALU_OPS_PER_PAIR = 21.6
+PAIR_LOOP_VALU_OPS = 16.5  # the sperm kernel's symmetric pair loop alone (ISA)
 FP32_FLOP_PER_PAIR = 21
 NONPACKED_FP32_PEAK_TFLOPS = 78.6
 # the large-system kernel k_big_step<float, 1> (one target per lane, FP64
@@ -59,11 +59,13 @@ VALU_OPS_PER_PAIR_BIG = 39.9
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 # HBM bytes of one launch of that kernel on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch: 52344.8 and 3213.0) scaled by
-# the same counters over a 256 MiB device copy (x2.0 and x1.0), for the
-# kernel as it stands (profiles/k_forward_batch_4096x128_counters.md); set it
-# to None whenever the kernel changes until the counters are taken again
-TRAFFIC_BYTES = None  # the kernel changed: retake the counters
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch: 77677.8 and 190232.8) scaled
+# by the same counters over a 256 MiB device copy (x2.0 and x1.0), for the
+# kernel as it stands (profiles/k_forward_batch_4096x128_counters.md): the
+# 4096 kernel tables (104 MB) plus the write-back and re-read of the 92-byte
+# per-lane register spills of the 64-VGPR build; set it to None whenever the
+# kernel changes until the counters are taken again
+TRAFFIC_BYTES = (77677.8 * 2.00 + 190232.8 * 1.00) * 1024
 
 
 def load_data():
@@ -653,15 +655,21 @@ def main():
     # timing events recorded right before and after the persistent launch,
     # on the stream it runs on (SWIM_OPT_TIME_KERNEL; those calls launch
     # eagerly instead of replaying the captured graph)
+    # The set-up is the whole call less the launch, both taken on these
+    # same calls (the launch alone varies by a few percent between calls)
     swim.swim_set_option(ctx, swim.SWIM_OPT_TIME_KERNEL, 1)
-    kus = []
+    kus, calls = [], []
     for _ in range(max(3, args.steps)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
         swim.swim_forward(ctx, Ns, None, P, steps, dt, obs_every, 1.5, obs, speed, status, done, stream=stream)
+        b.record(stream)
         kus.append(swim.swim_get_option(ctx, swim.SWIM_OPT_KERNEL_US))
+        calls.append((a, b))
     swim.swim_set_option(ctx, swim.SWIM_OPT_TIME_KERNEL, 0)
     torch.cuda.synchronize()
     kernel_ms = float(np.mean(kus)) * 1e-3
-    setup_ms = fwd_ms - kernel_ms
+    setup_ms = float(np.mean([a.elapsed_time(b) for a, b in calls])) - kernel_ms
     tflops = FP32_FLOP_PER_PAIR * pairs / (kernel_ms * 1e-3) / 1e12
     issue = VALU_OPS_PER_PAIR * pairs / (kernel_ms * 1e-3) / 1e12
     out = {
