@@ -65,7 +65,7 @@ FP32_PEAK_TFLOPS = 157.3
 # 4096 kernel tables (104 MB) plus the write-back and re-read of the 92-byte
 # per-lane register spills of the 64-VGPR build; set it to None whenever the
 # kernel changes until the counters are taken again
-TRAFFIC_BYTES = (77677.8 * 2.00 + 190232.8 * 1.00) * 1024
+TRAFFIC_BYTES = None  # the kernel changed: retake the counters
 
 
 def load_data():
@@ -697,7 +697,7 @@ def main():
         "forward_call_ms": fwd_ms, "setup_ms": setup_ms,
         "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / FP32_PEAK_TFLOPS, "traffic": TRAFFIC_BYTES,
-                     "kernel": "k_forward<float,2,16> (persistent forward run)", "kernel_ms": kernel_ms,
+                     "kernel": "k_forward<float,2,8> (persistent forward run, the default launch shape of 128-point FP32 systems)", "kernel_ms": kernel_ms,
                      "kernel_ms_source": "HIP events around the persistent launch (SWIM_OPT_TIME_KERNEL), "
                                          f"mean of {len(kus)} calls",
                      "fp32_flop_per_pair": FP32_FLOP_PER_PAIR, "pair_evals_per_launch": pairs,

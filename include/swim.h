@@ -89,9 +89,10 @@ int swim_version(void);
 
 /* Launch options of a context (the autotuner sets the first two):
  *   SWIM_OPT_WPS     wavefronts that share one system in the persistent
- *                    kernel, splitting its pair work: 0 (automatic), 1, 2,
- *                    4, 8, 16 (reduced when the partial sums would not fit
- *                    LDS).  Systems above 256 points need at least 2: a
+ *                    kernel, splitting its pair work: 0 (automatic: the
+ *                    autotuned value, else 8 for FP32 systems of 65..128
+ *                    points and 16 otherwise), 1, 2, 4, 8, 16 (reduced
+ *                    when the partial sums would not fit LDS).  Systems above 256 points need at least 2: a
  *                    forward call with 1 and such a system fails with
  *                    SWIM_EINVAL (the automatic choice never takes 1 there);
  *   SWIM_OPT_BIG_TPL targets per lane of the large-system kernel:

@@ -427,7 +427,12 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
         q.tpl = bucket_span[k].first;
         q.start = bucket_span[k].second;
         q.count = (k + 1 < bucket_span.size() ? bucket_span[k + 1].second : (int64_t)order.size()) - q.start;
-        q.wps = c->opt_wps ? c->opt_wps : (c->tuned_wps[dtype][q.tpl] ? c->tuned_wps[dtype][q.tpl] : 16);
+        // untuned default: 16 waves, except FP32 systems of 65..128 points,
+        // which take 8 (16 offsets of the pair schedule per wave instead of 8
+        // halves the per-wave share of each step's fixed work; two systems
+        // per CU either way)
+        const int wps_default = (dtype == SWIM_F32 && q.tpl == 2) ? 8 : 16;
+        q.wps = c->opt_wps ? c->opt_wps : (c->tuned_wps[dtype][q.tpl] ? c->tuned_wps[dtype][q.tpl] : wps_default);
         // at most FWD_MAX_WINDOWS point windows per lane: fewer waves are not
         // built (their one-wave instantiations exceed 256 VGPRs and spill to
         // AGPRs), and an explicit request for them is refused; the wave

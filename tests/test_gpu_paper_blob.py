@@ -372,22 +372,26 @@ def test_batched_size_fp32_against_fp64(paper):
     blob at alpha > 0, 1000 steps: the FP32 run (tables from the node sweep)
     against the library's FP64 run of the same system (quadrature per pair;
     the FP64 cases above pin it to the oracle), at 1e-4 on the displacement
-    series and the mean speed.  The draws are the two completed runs with
-    the softest stretching springs among the batch's first 256 prior draws:
-    a completed run is not necessarily a stable one (with the paper's
-    stiffer near field, stiff-spring draws such as (9.3, 0.038, 3478) settle
-    into a bounded period-2 oscillation of forward Euler, in which FP32 and
-    FP64 drift apart by a few percent; such runs stray from the data and
-    carry no parity information)."""
+    series and the mean speed.  The draws are picked on the FP64 runs of the
+    batch's first 256 prior draws alone: of those that complete and swim at
+    a physical speed (mean head speed below one body length per unit time;
+    the gait drives about 0.4), the two with the softest stretching springs.
+    A completed run is not necessarily a stable one: with the paper's
+    stiffer near field, some draws settle into a bounded oscillation of
+    forward Euler (e.g. (7.92, 0.54, 179): mean speed 25, and whether it
+    leaves the position bound within 1000 steps depends on rounding), in
+    which the two precisions drift apart by a few percent and which carries
+    no parity information.  Picking on FP32 completion let the FP32 sum
+    order decide which draws the test compares."""
     N, steps, dt, oe = 128, 1000, 5e-5, 100
     theta = swim.abc_prior_draw(1, 256, inputs.PRIOR_LO, inputs.PRIOR_HI)
     Pa = torch.from_numpy(inputs.theta_rows(theta)).cuda()
-    ob = torch.empty((256, steps // oe, 2), dtype=torch.float32, device="cuda")
-    sp = torch.empty(256, dtype=torch.float32, device="cuda")
+    ob = torch.empty((256, steps // oe, 2), dtype=torch.float64, device="cuda")
+    sp = torch.empty(256, dtype=torch.float64, device="cuda")
     st = torch.empty(256, dtype=torch.int32, device="cuda")
     swim.swim_forward(paper, np.full(256, N, np.int32), None, Pa, steps, dt, oe, 1.5, ob, sp, st)
     torch.cuda.synchronize()
-    ok = np.flatnonzero(st.cpu().numpy() == 0)
+    ok = np.flatnonzero((st.cpu().numpy() == 0) & (sp.cpu().numpy() < 1.0))
     assert ok.size >= 2
     pick = list(ok[np.argsort(theta[ok, 2], kind="stable")[:2]])
     P = inputs.theta_rows(theta[pick])
