@@ -535,8 +535,18 @@ __global__ void k_forces(int64_t n_fil, const int64_t* fil_off, const int32_t* n
 }
 
 
-// LDS of the persistent kernel: [FP32 table][src2][part][bad], 16-byte
-// aligned sections
+// FP32 launch shapes whose table is held as the 64 KiB LDS index window
+// (one operation less per pair): those that already run at most two
+// systems per CU, where two windows and the rest of the layout fit the LDS
+__host__ __device__ constexpr bool fwd_window(int dtype, int tpl, int wps)
+{
+    return dtype == 0 && tpl <= 2 && wps == 8;
+}
+
+// LDS of the persistent kernel: [FP32 table][src2][part][bad, item], 16-byte
+// aligned sections.  The kernel has no static LDS, so the table (or its
+// index window) starts at LDS address 0 and a pair's entry address needs
+// no base
 struct FwdLdsLayout {
     size_t tab, src, part, bad, total;
 };
@@ -546,10 +556,10 @@ __host__ __device__ constexpr FwdLdsLayout fwd_lds_layout(int dtype, int tpl, in
     const size_t e = dtype == 0 ? sizeof(float) : sizeof(double), nmax = 64 * (size_t)tpl;
     FwdLdsLayout L{};
     L.tab = 0;
-    L.src = dtype == 0 ? fwd_align16(sizeof(TabSys)) : 0;
+    L.src = dtype == 0 ? fwd_align16(fwd_window(dtype, tpl, wps) ? TAB_WIN_BYTES : sizeof(TabSys)) : 0;
     L.part = fwd_align16(L.src + 2 * nmax * 4 * e);
     L.bad = fwd_align16(L.part + (size_t)wps * nmax * 2 * e);
-    L.total = fwd_align16(L.bad + 4 * (size_t)wps);
+    L.total = fwd_align16(L.bad + 4 * ((size_t)wps + 1));  // wave flags, then the queue item
     return L;
 }
 
@@ -598,7 +608,7 @@ __device__ __forceinline__ double lane_prev(double v)
 
 
 template <typename T> struct FwdLds {
-    TabSys* tab;   // FP32 kernel table (FP32 runs)
+    TabSys* tab;   // FP32 kernel table (FP32 runs; its index window where fwd_window)
     Src4<T>* src;  // [2 NMAX] positions (hi part) and forces, each block of 64 twice
     V2<T>* part;   // [WPS][NMAX] partial velocities
     int* bad;      // [WPS] wave flags: 1 non-finite position, 2 beyond the bound
@@ -697,7 +707,7 @@ __device__ __forceinline__ void lane_force(int fl, T xh, T yh, T xl, T yl, T ss2
 
 template <typename T, int TPL, int WPS>
 __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>& L, T* obs, T* speed,
-                           int32_t* status, int32_t* steps_done)
+                           int32_t* status, int32_t* steps_done, bool refuse)
 {
     constexpr bool COMP = sizeof(T) == 4;
     constexpr int NMAX = 64 * TPL, NT = 64 * WPS;
@@ -708,20 +718,28 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
     const int nsw = b.nswim[s];
     const int n = N * nsw;
     const int64_t f0 = b.sw_off[s];
-    if (status[s] == SWIM_ST_BADPARAM_) {
-        // parameters outside the kernel's domain: no run, NaN outputs
+    if (refuse || status[s] == SWIM_ST_BADPARAM_) {
+        // parameters outside the kernel's domain (or a launch that cannot
+        // run, refuse): no run, NaN outputs
         for (int m = tid; m < nsw; m += NT) {
             T* q = obs + (f0 + m) * (int64_t)r.n_obs * 2;
             for (int o = 0; o < 2 * r.n_obs; ++o) q[o] = (T)NAN;
             speed[f0 + m] = (T)NAN;
         }
-        if (tid == 0 && steps_done) steps_done[s] = 0;
+        if (tid == 0) {
+            if (steps_done) steps_done[s] = 0;
+            if (refuse) status[s] = SWIM_ST_BADPARAM_;
+        }
         __syncthreads();
         return;
     }
     const SysConst<T> C = ((const SysConst<T>*)b.sysc)[s];
     const double dsd = 1.0 / (double)(N - 1);
-    if constexpr (COMP) tab_load((const TabSys*)b.tab + s, L.tab, tid, NT);
+    constexpr bool WIN = fwd_window(COMP ? 0 : 1, TPL, WPS);
+    if constexpr (WIN)
+        tab_load_window((const TabSys*)b.tab + s, reinterpret_cast<unsigned char*>(L.tab), tid, NT);
+    else if constexpr (COMP)
+        tab_load((const TabSys*)b.tab + s, L.tab, tid, NT);
     const int nwin = (n + FWD_WIN - 1) / FWD_WIN;
     const int pw = min(WPS, nwin);     // waves with point work
     const bool pwave = wave < pw;      // uniform within a wave
@@ -821,7 +839,7 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
             // positions are the caller's: a run placed beyond the bound
             // reads zeros for its far pairs in its first step and stops)
             T ax[TPL], ay[TPL];
-            pair_phase_sym<T, TPL, WPS, false>(C, L.tab, L.src, n, wave, lane, ax, ay);
+            pair_phase_sym<T, TPL, WPS, false, WIN>(C, L.tab, L.src, n, wave, lane, ax, ay);
 #pragma unroll
             for (int c = 0; c < TPL; ++c) {
                 if (c < nblk64) {
@@ -944,13 +962,22 @@ __global__ __launch_bounds__(64 * WPS) __attribute__((amdgpu_waves_per_eu(sizeof
 k_forward(Batch b, Run r, const int32_t* order, int32_t* queue, T* obs, T* speed, int32_t* status, int32_t* steps_done)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_item;
     FwdLds<T> L;
     const FwdLdsLayout lay = fwd_lds_layout(sizeof(T) == 4 ? 0 : 1, TPL, WPS);
     L.tab = reinterpret_cast<TabSys*>(smem + lay.tab);
     L.src = reinterpret_cast<Src4<T>*>(smem + lay.src);
     L.part = reinterpret_cast<V2<T>*>(smem + lay.part);
     L.bad = reinterpret_cast<int*>(smem + lay.bad);
+    int& s_item = L.bad[WPS];
+    // the pair loop of the index-window layout addresses the table from LDS
+    // address 0, where the dynamic LDS starts while the kernel declares no
+    // static LDS; should it start elsewhere, every system is refused
+    // (status SWIM_ST_BADPARAM, NaN outputs) rather than run on wrong data
+    bool refuse = false;
+#if defined(__HIP_DEVICE_COMPILE__)
+    refuse = fwd_window(sizeof(T) == 4 ? 0 : 1, TPL, WPS) &&
+             (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) unsigned char*)smem != 0u;
+#endif
     // Work queue: thread 0 takes the next system; the item reaches every
     // thread through LDS and readfirstlane makes it an SGPR, so the loop exit
     // is a uniform scalar branch.  A workgroup takes at most n_sys items.
@@ -961,7 +988,7 @@ k_forward(Batch b, Run r, const int32_t* order, int32_t* queue, T* obs, T* speed
         __syncthreads();
         if (item >= b.n_sys) break;
         const int s = __builtin_amdgcn_readfirstlane(order[item]);
-        run_system<T, TPL, WPS>(b, r, s, L, obs, speed, status, steps_done);
+        run_system<T, TPL, WPS>(b, r, s, L, obs, speed, status, steps_done, refuse);
     }
 }
 

@@ -34,6 +34,33 @@ __device__ __forceinline__ void tab_load(const TabSys* g, TabSys* tab, int tid, 
     for (int i = tid; i < NV; i += nthreads) dst[i] = src[i];
 }
 
+// The FP32 table as a 64 KiB index window: the entry of index id (the bits
+// of v >> TAB_SHIFT, TAB_BIAS for v = 1) sits at byte (id << 5) mod 2^16,
+// so the address of a pair's entry is (bits >> (TAB_SHIFT - 5)) & 0xFFE0:
+// two operations, no bias and no clamp.  Entries 16.. of the table fill
+// bytes [0, 32 (TAB_N - 16)), entries 0..15 (v in [1, 2)) the top 512
+// bytes, and every other slot is zero: the indices of finite v beyond the
+// table (TAB_END .. 4079) land on zeros, as the zero entry TAB_N does for a
+// clamped index.  Non-finite v (4080..4095) alias entries 0..15; their
+// positions are non-finite already and end the run.
+constexpr uint32_t TAB_WIN_BYTES = 65536;
+static_assert(TAB_M == 4 && sizeof(TabE) == 32 && TAB_BIAS == 2032 && TAB_END <= 4080,
+              "the index window holds 2048 entries of v's octaves 0..127");
+__device__ __forceinline__ uint32_t tab_win_off(uint32_t bits) { return (bits >> (TAB_SHIFT - 5)) & 0xFFE0u; }
+
+// copy one system's FP32 kernel table from HBM into its LDS index window
+__device__ __forceinline__ void tab_load_window(const TabSys* g, unsigned char* win, int tid, int nthreads)
+{
+    const float4* src = reinterpret_cast<const float4*>(g->e);
+    float4* dst = reinterpret_cast<float4*>(win);
+    constexpr int NV = (int)(TAB_WIN_BYTES / sizeof(float4)), EV = (int)(sizeof(TabE) / sizeof(float4));
+    for (int i = tid; i < NV; i += nthreads) {
+        // slot id mod 2048 holds entry id - TAB_BIAS
+        const int ent = (i / EV - (int)TAB_BIAS) & 2047;
+        dst[i] = ent < TAB_N ? src[ent * EV + (i % EV)] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
 // error-free (hi, lo) += d  (TwoSum, then renormalize)
 template <typename T> __device__ __forceinline__ void acc2(T& hi, T& lo, T d)
 {
@@ -91,7 +118,7 @@ __device__ __forceinline__ int src2_slot(int i) { return ((i >> 6) << 7) + (i & 
 // gives zeros and, with CHECK, sets far), or the direct evaluation of pairs
 // beyond the table only (FAR = true; zeros for the others).  H2 comes scaled
 // to the coordinates (H2 / sigma in FP32).
-template <typename T, bool FAR, bool CHECK = true>
+template <typename T, bool FAR, bool CHECK = true, bool WRAP = false>
 __device__ __forceinline__ void pair_kernel(const SysConst<T>& C, const char* et, T dx, T dy, T& Ht, T& H2,
                                             bool& far)
 {
@@ -102,7 +129,18 @@ __device__ __forceinline__ void pair_kernel(const SysConst<T>& C, const char* et
         const uint32_t id = bits >> TAB_SHIFT;
         if constexpr (!FAR) {
             if constexpr (CHECK) far = far || id >= TAB_END;
-            tab_eval(*reinterpret_cast<const TabE*>(et + (min(id, TAB_END) << 5)), tab_u(bits), Ht, H2);
+            if constexpr (WRAP) {
+                // the index window at LDS address 0 (tab_load_window): the
+                // entry's address is its offset in the window (an LDS
+                // address, which only the device pass compiles)
+#if defined(__HIP_DEVICE_COMPILE__)
+                typedef const __attribute__((address_space(3))) TabE* LdsTabE;
+                const TabE e = *(LdsTabE)(uintptr_t)tab_win_off(bits);
+                tab_eval(e, tab_u(bits), Ht, H2);
+#endif
+            } else {
+                tab_eval(*reinterpret_cast<const TabE*>(et + (min(id, TAB_END) << 5)), tab_u(bits), Ht, H2);
+            }
         } else {
             Ht = 0.0f;
             H2 = 0.0f;
@@ -116,7 +154,7 @@ __device__ __forceinline__ void pair_kernel(const SysConst<T>& C, const char* et
 
 // offsets [s_lo, s_hi) of block pair (a, b); adds the target sums to block
 // a's and the moving points' sums to block b's accumulators of this lane
-template <typename T, int TPL, bool FAR, bool CHECK = true>
+template <typename T, int TPL, bool FAR, bool CHECK = true, bool WRAP = false>
 __device__ __forceinline__ bool sym_offsets(const SysConst<T>& C, const char* et, const Src4<T>* src2, int a, int b,
                                             int s_lo, int s_hi, int lane, T (&accx)[TPL], T (&accy)[TPL])
 {
@@ -133,7 +171,7 @@ __device__ __forceinline__ bool sym_offsets(const SysConst<T>& C, const char* et
     auto offset = [&](const Src4<T>& q) {
         const T dx = ti.x - q.x, dy = ti.y - q.y;
         T Ht, H2;
-        pair_kernel<T, FAR, CHECK>(C, et, dx, dy, Ht, H2, far);
+        pair_kernel<T, FAR, CHECK, WRAP>(C, et, dx, dy, Ht, H2, far);
         const T hx = H2 * dx, hy = H2 * dy;
         const T mxx = fma_t(hx, dx, Ht), myy = fma_t(hy, dy, Ht), mxy = hx * dy;
         ax = fma_t(mxx, q.fx, fma_t(mxy, q.fy, ax));
@@ -152,7 +190,7 @@ __device__ __forceinline__ bool sym_offsets(const SysConst<T>& C, const char* et
         const Src4<T> q = sp[32];
         const T dx = ti.x - q.x, dy = ti.y - q.y;
         T Ht, H2;
-        pair_kernel<T, FAR, CHECK>(C, et, dx, dy, Ht, H2, far);
+        pair_kernel<T, FAR, CHECK, WRAP>(C, et, dx, dy, Ht, H2, far);
         Ht = lane < 32 ? Ht : (T)0;
         H2 = lane < 32 ? H2 : (T)0;
         const T hx = H2 * dx, hy = H2 * dy;
@@ -183,15 +221,19 @@ __device__ __forceinline__ bool sym_offsets(const SysConst<T>& C, const char* et
 // this wave's share of the pair sums of all n points: accx[c], accy[c] hold
 // the partial velocity of point 64c + lane.  CHECK = false: the caller
 // guarantees that no FP32 pair lies beyond the table, which then is read
-// without the per-pair test (an index beyond it reads the zero entry)
-template <typename T, int TPL, int WPS, bool CHECK = true>
+// without the per-pair test (an index beyond it reads a zero entry).
+// WRAP: tab points at the table's LDS index window (tab_load_window)
+template <typename T, int TPL, int WPS, bool CHECK = true, bool WRAP = false>
 __device__ __forceinline__ void pair_phase_sym(const SysConst<T>& C, const TabSys* tab, const Src4<T>* src2, int n,
                                                int wave, int lane, T (&accx)[TPL], T (&accy)[TPL])
 {
 #pragma unroll
     for (int c = 0; c < TPL; ++c) accx[c] = accy[c] = (T)0;
     const char* et = nullptr;
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (WRAP) {
+        // tab is the table's LDS index window
+        et = reinterpret_cast<const char*>(tab);
+    } else if constexpr (sizeof(T) == 4) {
         // entry of index id at et + (id << 5) bytes: the bias goes into a
         // wave-uniform base (a register operand of the address arithmetic;
         // gfx9 address arithmetic takes no 32-bit literal)
@@ -208,7 +250,8 @@ __device__ __forceinline__ void pair_phase_sym(const SysConst<T>& C, const TabSy
             const int lo = max(g0, g), hi = min(g1, g + len);
             if (lo < hi) {
                 const int s_lo = lo - g + base, s_hi = hi - g + base;
-                const bool far = sym_offsets<T, TPL, false, CHECK>(C, et, src2, a, b, s_lo, s_hi, lane, accx, accy);
+                const bool far =
+                    sym_offsets<T, TPL, false, CHECK, WRAP>(C, et, src2, a, b, s_lo, s_hi, lane, accx, accy);
                 if constexpr (sizeof(T) == 4 && CHECK) {
                     if (__any(far)) sym_offsets<T, TPL, true>(C, et, src2, a, b, s_lo, s_hi, lane, accx, accy);
                 }
