@@ -52,10 +52,12 @@ VALU_OPS_PER_PAIR = 18.3
 PAIR_LOOP_VALU_OPS = 15.75  # the sperm kernel's symmetric pair loop alone (ISA, per ordered pair)
 FP32_FLOP_PER_PAIR = 21
 NONPACKED_FP32_PEAK_TFLOPS = 78.6
-# the large-system kernel k_big_step<float, 1> (one target per lane, FP64
-# accumulation): 39.9 VALU lane-operations per pair evaluation from
-# SQ_INSTS_VALU (profiles/k_big_step_dense_64x8x512_counters.md)
-VALU_OPS_PER_PAIR_BIG = 39.9
+# the FP32 large-system step, k_big_pairs (every pair once for both points,
+# FP64 accumulation) and k_big_update: 26.2 VALU lane-operations per ordered
+# pair evaluation from SQ_INSTS_VALU
+# (profiles/k_big_pairs_dense_64x8x512_counters.md; the one-sided
+# k_big_step<float, 1> it replaced took 39.9)
+VALU_OPS_PER_PAIR_BIG = 26.2
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 # HBM bytes of one launch of that kernel on this workload, from rocprofv3
@@ -194,7 +196,8 @@ def dense_leg(ctx, stream, samples=64, steps=1000, dt_div=64):
     larger), so the run uses a stable power-of-two fraction: dt / 64 (with
     the paper's blob 56 of 64 samples blow up within 50 steps at dt / 32,
     none in 1000 at dt / 48 or dt / 64); the work per step does not depend
-    on dt.  Runs on the per-step large-system kernel.
+    on dt.  Runs on the FP32 large-system step (per step: the tile-pair
+    kernel, every pair once for both points, then the update kernel).
     (The parity of one full-size velocity evaluation against the FP64
     oracle is a test: test_dense_sample_velocity_at_full_size.)"""
     import torch
@@ -221,7 +224,7 @@ def dense_leg(ctx, stream, samples=64, steps=1000, dt_div=64):
     d = done.cpu().numpy().astype(np.int64)
     pairs = float(np.sum(d * 4096 * 4096))
     out = {"workload": f"{samples} samples x 8 swimmers x N=512 (2x4 grid, spacing 1.5), {steps} Euler steps of "
-                       f"dt=2e-5/{dt_div} (stability), FP32, per-step large-system kernel",
+                       f"dt=2e-5/{dt_div} (stability), FP32, symmetric large-system step (k_big_pairs + k_big_update)",
            "ms": ms, "pair_evals_per_s": pairs / (ms * 1e-3), "swimmer_steps_per_s": float(np.sum(d)) * 8 / (ms * 1e-3),
            "runs_stopped": int(np.sum(status.cpu().numpy() != 0)),
            "fp32_tflops": FP32_FLOP_PER_PAIR * pairs / (ms * 1e-3) / 1e12,

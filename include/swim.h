@@ -95,8 +95,13 @@ int swim_version(void);
  *                    when the partial sums would not fit LDS).  Systems above 256 points need at least 2: a
  *                    forward call with 1 and such a system fails with
  *                    SWIM_EINVAL (the automatic choice never takes 1 there);
- *   SWIM_OPT_BIG_TPL targets per lane of the large-system kernel:
- *                    0 (automatic), 1, 2, 4;
+ *   SWIM_OPT_BIG_TPL the large-system step (systems above 512 points):
+ *                    0 (automatic: FP32 takes the symmetric step, every
+ *                    pair evaluated once for both points, in tile pairs of
+ *                    256 points with a partial-sum buffer reduced in a
+ *                    fixed order; FP64 the one-sided kernel at one target
+ *                    per lane), or 1, 2, 4: the one-sided kernel at that
+ *                    many targets per lane;
  *   SWIM_OPT_GRAPH   forward runs as a captured hipGraph: 0 never (eager
  *                    launches), 1 (default) capture when a call repeats the
  *                    previous call's layout (systems, sizes, run length,
@@ -163,12 +168,14 @@ int swim_get_option(swim_ctx *ctx, int32_t key, int32_t *value);
  *     (systems of up to 64*tpl points, tpl in {1,2,3,4,6,8}), the waves per
  *     system among 2, 4, 8, 16 (those whose partial sums fit the LDS), one
  *     bucket at a time with the others at their current choice;
- *   - if the batch has systems over 512 points, the targets per lane of
- *     the large-system kernel among 1, 2, 4.
+ *   - if the batch has systems over 512 points, the large-system step:
+ *     the one-sided kernel at 1, 2, 4 targets per lane and, for FP32, the
+ *     symmetric step (SWIM_OPT_BIG_TPL = 0).
  * The choices stay in the context (used by every later run whose
  * SWIM_OPT_WPS is 0; the large-system choice sets SWIM_OPT_BIG_TPL) and
  * are returned in chosen (host int32[9]: waves per system for tpl = 1..8,
- * 0 where not tuned, then the large-system targets per lane). */
+ * 0 where not tuned, then the large-system choice, SWIM_OPT_BIG_TPL's
+ * value). */
 int swim_autotune(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const int32_t *N,
                   const int32_t *n_swim, const double *params, int32_t probe_steps, double dt,
                   double eps_over_ds, int32_t *chosen);
@@ -263,9 +270,14 @@ int swim_elastic_forces(swim_ctx *ctx, int32_t dtype, int64_t n_fil, const int32
  * status   device int32[n_sys]: SWIM_ST_* per system.
  * steps_done device int32[n_sys] or NULL: forward-Euler steps computed per
  *          system (steps, or the step at which the run stopped, 0 if not run).
- * Systems of up to 512 points run in one persistent kernel (a wavefront per
- * system, work queue in longest-first order); larger systems run one launch
- * per step with the targets split over workgroups.  Asynchronous. */
+ * Systems of up to 512 points run in one persistent kernel (a workgroup per
+ * system, work queue in longest-first order); larger systems run the
+ * large-system step, launches per Euler step with the work split over
+ * workgroups (SWIM_OPT_BIG_TPL).  FP32 systems whose pairs could lie beyond
+ * the FP32 kernel table within the position bound (2829 (N-1) / eps_over_ds
+ * >= 2^22, i.e. eps_over_ds well below 1.5) take the large-system step at
+ * any size, since the persistent kernel does not test for such pairs.
+ * Asynchronous. */
 int swim_forward(swim_ctx *ctx, int32_t dtype, int64_t n_sys, const int32_t *N,
                  const int32_t *n_swim, const double *params, int32_t steps, double dt,
                  int32_t obs_every, double eps_over_ds, void *obs, void *speed, int32_t *status,

@@ -65,6 +65,7 @@ enum BufId {
     B_MLP_ACT, B_MLP_GRAD, B_MLP_BATCH, B_MLP_IDX, B_MLP_CNT,
     B_PS_THETA, B_PS_X, B_PS_KEEP, B_PS_IDX, B_PS_NK, B_PS_SUM, B_DS_T, B_TAB, B_DONE, B_W16, B_SIGMA, B_LOGL,
     B_SP_SW, B_SP_HEAD, B_SP_TAIL, B_SP_G, B_SP_SIG, B_WTAB,
+    B_BT_PSYS, B_BT_PT, B_BT_TSYS, B_BT_TT, B_BT_POFF, B_BT_PART,
     B_NBUF
 };
 
@@ -261,6 +262,19 @@ int choose_tpl(int pts)
     return -1;
 }
 
+// targets per lane of a forward system in the persistent kernel, or -1 for
+// the large-system step: systems above 512 points, and FP32 systems whose
+// pairs can lie beyond the FP32 kernel table after the first step (within
+// the position bound pairs are at most 2829 apart, and the table holds
+// v = 1 + (r / eps)^2 < 2^44, eps = eps_over_ds / (N - 1)): the persistent
+// kernel reads the table without testing for such pairs, the large-system
+// step evaluates them directly
+int forward_tpl(int32_t dtype, int N, int pts, double eps_over_ds)
+{
+    if (dtype == SWIM_F32 && 2829.0 * (double)(N - 1) / eps_over_ds >= 4194304.0) return -1;
+    return choose_tpl(pts);
+}
+
 // two U(0,1) doubles of the library's Philox4x32-10 stream (swim_philox.h)
 void uniforms2(uint64_t seed, uint32_t stream, uint64_t index, uint32_t draw, double* u)
 {
@@ -360,7 +374,7 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
         nsw[s] = nswim ? nswim[s] : 1;
         sw_off[s + 1] = sw_off[s] + nsw[s];
         pts[s] = N[s] * nsw[s];
-        const int tpl = choose_tpl(pts[s]);
+        const int tpl = forward_tpl(dtype, N[s], pts[s], run.eps_over_ds);
         if (tpl > 0) {
             bucket[tpl - 1].push_back((int32_t)s);
         } else {
@@ -380,17 +394,43 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
         bucket_span.push_back({t, (int64_t)order.size()});
         order.insert(order.end(), v.begin(), v.end());
     }
-    // large systems: target blocks of 256 * tpl_big points
+    // large systems: FP32 at the automatic choice takes the symmetric step
+    // (tile pairs, then tiles, of 256 points); otherwise target blocks of
+    // 256 * tpl_big points of the one-sided step
+    const bool big_sym = dtype == SWIM_F32 && c->opt_big_tpl == 0;
     const int tpl_big = c->opt_big_tpl ? c->opt_big_tpl : 1;
     std::vector<int64_t> blk_s, blk_f;
-    for (int64_t s : big_list)
-        for (int64_t f = 0; f < pts[s]; f += 256 * tpl_big) {
-            blk_s.push_back(s);
-            blk_f.push_back(f);
+    std::vector<int64_t> bp_sys, bt_sys, bt_poff;
+    std::vector<int32_t> bp_tile, bt_tile;
+    int64_t bt_slots = 0;
+    if (big_sym) {
+        bt_poff.assign(n_sys, 0);
+        for (int64_t s : big_list) {
+            const int nt = (pts[s] + BIG_TILE_POINTS - 1) / BIG_TILE_POINTS;
+            if (nt > 0xFFFF) return fail(SWIM_EINVAL, "system of %d points exceeds the large-system tiling", pts[s]);
+            bt_poff[s] = bt_slots;
+            bt_slots += (int64_t)nt * nt;
+            for (int ta = 0; ta < nt; ++ta) {
+                bt_sys.push_back(s);
+                bt_tile.push_back(ta);
+                for (int tb = ta; tb < nt; ++tb) {
+                    bp_sys.push_back(s);
+                    bp_tile.push_back(ta | (tb << 16));
+                }
+            }
         }
+    } else {
+        for (int64_t s : big_list)
+            for (int64_t f = 0; f < pts[s]; f += 256 * tpl_big) {
+                blk_s.push_back(s);
+                blk_f.push_back(f);
+            }
+    }
     const size_t es = dtype == SWIM_F32 ? 4 : 8;
     size_t total = (sw_off.size() + big_off.size() + big_list.size() + 2 * blk_s.size()) * 8 +
-                   (nsw.size() + order.size()) * 4 + n_sys * 4 + 64;
+                   (nsw.size() + order.size()) * 4 + n_sys * 4 + 64 +
+                   (bp_sys.size() + bt_sys.size() + bt_poff.size()) * 8 + (bp_tile.size() + bt_tile.size()) * 4 +
+                   6 * 256;
     TRY(begin_uploads(c, total));
     TRY(stage(c, sw_off.data(), sw_off.size() * 8, B_SWOFF, st));
     TRY(stage(c, big_off.data(), big_off.size() * 8, B_OFF, st));
@@ -400,6 +440,13 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     TRY(stage(c, big_list.data(), big_list.size() * 8, B_LIST, st));
     TRY(stage(c, blk_s.data(), blk_s.size() * 8, B_BLKS, st));
     TRY(stage(c, blk_f.data(), blk_f.size() * 8, B_BLKF, st));
+    if (big_sym) {
+        TRY(stage(c, bp_sys.data(), bp_sys.size() * 8, B_BT_PSYS, st));
+        TRY(stage(c, bp_tile.data(), bp_tile.size() * 4, B_BT_PT, st));
+        TRY(stage(c, bt_sys.data(), bt_sys.size() * 8, B_BT_TSYS, st));
+        TRY(stage(c, bt_tile.data(), bt_tile.size() * 4, B_BT_TT, st));
+        TRY(stage(c, bt_poff.data(), bt_poff.size() * 8, B_BT_POFF, st));
+    }
     TRY(end_uploads(c, st));
     void *sysc, *sysc64;
     TRY(sysconst_buffers(c, dtype, n_sys, &sysc, &sysc64));
@@ -487,9 +534,24 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
             S.yl[q] = base + (6 + q) * one;
         }
         S.head0 = base + 8 * one;
-        if (big_step_lds_bytes(dtype, max_big) > 160 * 1024)
-            return fail(SWIM_EINVAL, "system of %d points exceeds the LDS capacity", max_big);
-        HIPCHK(prepare_big_step(dtype, tpl_big, max_big));
+        if (big_sym) {
+            TRY(ensure(c, B_BT_PART, (size_t)bt_slots * BIG_TILE_POINTS * 2 * sizeof(double)));
+            HIPCHK(prepare_big_pairs());
+        } else {
+            if (big_step_lds_bytes(dtype, max_big) > 160 * 1024)
+                return fail(SWIM_EINVAL, "system of %d points exceeds the LDS capacity", max_big);
+            HIPCHK(prepare_big_step(dtype, tpl_big, max_big));
+        }
+    }
+    BigTiles bt_pairs{}, bt_tiles{};
+    if (big_sym) {
+        bt_pairs.sys = (const int64_t*)c->buf[B_BT_PSYS].p;
+        bt_pairs.tile = (const int32_t*)c->buf[B_BT_PT].p;
+        bt_pairs.poff = (const int64_t*)c->buf[B_BT_POFF].p;
+        bt_pairs.part = c->buf[B_BT_PART].p;
+        bt_tiles = bt_pairs;
+        bt_tiles.sys = (const int64_t*)c->buf[B_BT_TSYS].p;
+        bt_tiles.tile = (const int32_t*)c->buf[B_BT_TT].p;
     }
     // the launch sequence of the run (uploads above are not part of it)
     auto launch_all = [&]() -> hipError_t {
@@ -522,10 +584,18 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
             const hipStream_t st_big = lane_stream(big_lane % lanes);
             e = launch_big_init(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S, status, obs,
                                 run.n_obs, st_big);
-            for (int step = 0; step < run.steps && e == hipSuccess; ++step)
-                e = launch_big_step(dtype, tpl_big, (int64_t)blk_s.size(), (const int64_t*)c->buf[B_BLKS].p,
-                                    (const int64_t*)c->buf[B_BLKF].p, max_big, b, S, step, run, obs, status,
-                                    steps_done, st_big);
+            for (int step = 0; step < run.steps && e == hipSuccess; ++step) {
+                if (big_sym) {
+                    e = launch_big_pairs((int64_t)bp_sys.size(), bt_pairs, b, S, step, run, status, st_big);
+                    if (e == hipSuccess)
+                        e = launch_big_update((int64_t)bt_sys.size(), bt_tiles, b, S, step, run, obs, status,
+                                              steps_done, st_big);
+                } else {
+                    e = launch_big_step(dtype, tpl_big, (int64_t)blk_s.size(), (const int64_t*)c->buf[B_BLKS].p,
+                                        (const int64_t*)c->buf[B_BLKF].p, max_big, b, S, step, run, obs, status,
+                                        steps_done, st_big);
+                }
+            }
             if (e == hipSuccess)
                 e = launch_big_finish(dtype, (const int64_t*)c->buf[B_LIST].p, (int64_t)big_list.size(), b, S,
                                       run.steps & 1, run, speed, status, steps_done, st_big);
@@ -558,6 +628,7 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     h.add(run.stop_data);
     h.add(run.stop_ssq);
     h.add(tpl_big);
+    h.add(big_sym ? 1 : 0);
     h.add(c->opt_blob);
     for (const Bucket& q : bk) {
         h.add(q.tpl);
@@ -568,7 +639,9 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     h.add(big_lane);
     const void* ptrs[] = {params_dev, obs, speed, status, steps_done, sysc, sysc64, b.tab, c->buf[B_SWOFF].p,
                           c->buf[B_OFF].p, c->buf[B_NPT].p, c->buf[B_NSW].p, c->buf[B_ORDER].p, c->buf[B_LIST].p,
-                          c->buf[B_BLKS].p, c->buf[B_BLKF].p, c->buf[B_QUEUE].p, c->buf[B_BIG].p, st};
+                          c->buf[B_BLKS].p, c->buf[B_BLKF].p, c->buf[B_QUEUE].p, c->buf[B_BIG].p,
+                          c->buf[B_BT_PSYS].p, c->buf[B_BT_PT].p, c->buf[B_BT_TSYS].p, c->buf[B_BT_TT].p,
+                          c->buf[B_BT_POFF].p, c->buf[B_BT_PART].p, st};
     h.add_bytes(ptrs, sizeof(ptrs));
     const uint64_t key = h.v;
     ++c->graph_clock;
@@ -1909,7 +1982,7 @@ int swim_autotune(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     for (int64_t s = 0; s < n_sys; ++s) {
         const int nsw = n_swim ? n_swim[s] : 1;
         nfil += nsw;
-        const int tpl = choose_tpl(N[s] * nsw);
+        const int tpl = forward_tpl(dtype, N[s], N[s] * nsw, eps_over_ds);
         if (tpl > 0) has_tpl[tpl] = true;
         else has_big = true;
     }
@@ -1965,10 +2038,13 @@ int swim_autotune(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
         }
         c->tuned_wps[dtype][tpl] = best_w;
     }
-    int best_big = save_big ? save_big : 1;
+    // large systems: the one-sided kernel at 1, 2, 4 targets per lane and,
+    // for FP32, the symmetric tile-pair step (the automatic choice, 0)
+    int best_big = save_big;
     if (has_big && rc == SWIM_OK) {
         float best = 0.f;
-        for (int t : {1, 2, 4}) {
+        for (int t : {0, 1, 2, 4}) {
+            if (t == 0 && dtype != SWIM_F32) continue;
             c->opt_big_tpl = t;
             float ms = 0.f;
             rc = timed(&ms);

@@ -82,6 +82,21 @@ struct BigState {
     void* yl[2];
     void* head0;   // [n_filaments][2] T, initial head positions
 };
+// the symmetric FP32 large-system step: tile pairs (pairs kernel) or tiles
+// (update kernel) of BIG_T = 256 points, and the partial-sum slots
+struct BigTiles {
+    const int64_t* sys;   // [n_items] system
+    const int32_t* tile;  // [n_items] ta | tb << 16 (tile pairs, ta <= tb), or the tile
+    const int64_t* poff;  // [n_sys] first partial slot of a large system (nt * nt slots)
+    void* part;           // slots of 256 double pairs: slot poff + t * nt + q = tile t's sums over tile q
+};
+constexpr int BIG_TILE_POINTS = 256;
+size_t big_pair_lds_bytes();
+hipError_t prepare_big_pairs();
+hipError_t launch_big_pairs(int64_t n_pairs, const BigTiles& bt, const Batch& b, const BigState& s, int step,
+                            const Run& r, const int32_t* status, hipStream_t st);
+hipError_t launch_big_update(int64_t n_tiles, const BigTiles& bt, const Batch& b, const BigState& s, int step,
+                             const Run& r, void* obs, int32_t* status, int32_t* steps_done, hipStream_t st);
 hipError_t launch_big_init(int dtype, const int64_t* list, int64_t n_list, const Batch& b,
                            const BigState& s, int32_t* status, void* obs, int32_t n_obs,
                            hipStream_t st);

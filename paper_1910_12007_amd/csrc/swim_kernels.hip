@@ -833,11 +833,12 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
         {
             // no pair lies beyond the FP32 table: every step starts from
             // positions within the run bound |x|, |y| <= 1e3 (a step that
-            // leaves it ends the run), so r <= 2829; with eps >= 1.5/511
-            // (n <= 512, one filament's N at most 512) 1 + sigma r^2 <
-            // 1 + 4 (r/eps)^2 < 2^42, inside the table's 2^44 (the initial
-            // positions are the caller's: a run placed beyond the bound
-            // reads zeros for its far pairs in its first step and stops)
+            // leaves it ends the run), so r <= 2829, and the host sends the
+            // systems whose 2829 / eps reaches 2^22 (eps_over_ds well below
+            // its usual 1.5) to the large-system step, so that here
+            // 1 + (r/eps)^2 < 2^44, inside the table (the initial positions
+            // are the caller's: a run placed beyond the bound reads zeros
+            // for its far pairs in its first step and stops)
             T ax[TPL], ay[TPL];
             pair_phase_sym<T, TPL, WPS, false, WIN>(C, L.tab, L.src, n, wave, lane, ax, ay);
 #pragma unroll
@@ -1034,6 +1035,66 @@ __global__ void k_big_init(const int64_t* list, Batch b, BigState S, int32_t* st
     }
 }
 
+// source record of point i of a large system at time t: its position (hi
+// part) and elastic force, from the positions of the current buffer
+template <typename T>
+__device__ __forceinline__ Src4<T> big_source(const Batch& b, const T* xh, const T* yh, const T* xl, const T* yl,
+                                              int64_t f0, int N, int i, T t)
+{
+    constexpr bool COMP = sizeof(T) == 4;
+    const int m = i / N, p = i - m * N;
+    const FilP<T> q = load_filp<T>(b.params, f0 + m, N);
+    const int base = m * N;
+    auto seg = [&](int kk, T& dx, T& dy) {
+        const int a = base + kk, c = base + kk + 1;
+        dx = (xh[c] - xh[a]) + (COMP ? xl[c] - xl[a] : (T)0);
+        dy = (yh[c] - yh[a]) + (COMP ? yl[c] - yl[a] : (T)0);
+    };
+    T Fx, Fy;
+    point_force<T>(seg, p, q, t, Fx, Fy);
+    Src4<T> v;
+    v.x = xh[i];
+    v.y = yh[i];
+    v.fx = Fx;
+    v.fy = Fy;
+    return v;
+}
+
+// Euler step of point i of a large system from its velocity (ux, uy):
+// position (hi, lo) into buffer nxt, the bound check, the head sample
+template <typename T>
+__device__ __forceinline__ void big_update_point(const BigState& S, int step, const Run& r, int64_t s, int64_t p0,
+                                                 int64_t f0, int N, int64_t i, int nxt, T hx, T hy, T lx, T ly, T ux,
+                                                 T uy, T* obs, int32_t* status, int32_t* steps_done)
+{
+    constexpr bool COMP = sizeof(T) == 4;
+    const T dt = (T)r.dt;
+    if (COMP) {
+        acc2(hx, lx, dt * ux);
+        acc2(hy, ly, dt * uy);
+    } else {
+        hx = fma_t(dt, ux, hx);
+        hy = fma_t(dt, uy, hy);
+    }
+    ((T*)S.xh[nxt])[p0 + i] = hx;
+    ((T*)S.yh[nxt])[p0 + i] = hy;
+    ((T*)S.xl[nxt])[p0 + i] = lx;
+    ((T*)S.yl[nxt])[p0 + i] = ly;
+    if (bad_t(hx) || bad_t(hy)) {
+        atomicMax(&status[s], (isfinite(hx) && isfinite(hy)) ? 2 : 1);
+        if (steps_done) steps_done[s] = step + 1;
+    }
+    if (r.obs_every > 0 && (step + 1) % r.obs_every == 0) {
+        const int m = (int)(i / N), p = (int)(i - (int64_t)m * N);
+        if (p == N - 1) {
+            const int o = (step + 1) / r.obs_every - 1;
+            T* q = obs + ((f0 + m) * (int64_t)r.n_obs + o) * 2;
+            q[0] = hx + lx;
+            q[1] = hy + ly;
+        }
+    }
+}
+
 template <typename T, int TPL>
 __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const int64_t* blk_first, Batch b,
                                                   BigState S, int step, Run r, T* obs, int32_t* status,
@@ -1084,64 +1145,239 @@ __global__ __launch_bounds__(256) void k_big_step(const int64_t* blk_sys, const 
     for (int j0 = 0; j0 < n; j0 += BIG_TILE) {
         const int m_t = min(BIG_TILE, n - j0);
         if (j0 > 0) __syncthreads();  // the previous tile is consumed
-        for (int jj = tid; jj < m_t; jj += 256) {
-            const int i = j0 + jj;
-            const int m = i / N, p = i - m * N;
-            const FilP<T> q = load_filp<T>(b.params, f0 + m, N);
-            const int base = m * N;
-            auto seg = [&](int kk, T& dx, T& dy) {
-                const int a = base + kk, c = base + kk + 1;
-                dx = (xh[c] - xh[a]) + (COMP ? xl[c] - xl[a] : (T)0);
-                dy = (yh[c] - yh[a]) + (COMP ? yl[c] - yl[a] : (T)0);
-            };
-            T Fx, Fy;
-            point_force<T>(seg, p, q, t, Fx, Fy);
-            Src4<T> v;
-            v.x = xh[i];
-            v.y = yh[i];
-            v.fx = Fx;
-            v.fy = Fy;
-            src[jj] = v;
-        }
+        for (int jj = tid; jj < m_t; jj += 256) src[jj] = big_source<T>(b, xh, yh, xl, yl, f0, N, j0 + jj, t);
         __syncthreads();
         if constexpr (COMP)
             pair_accumulate_x<TPL>(C, tab, src, m_t, xi, yi, axd, ayd);
         else
             pair_accumulate<T, TPL>(C, src, m_t, xi, yi, ax, ay);
     }
-    const T dt = (T)r.dt;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         const int64_t i = first + tid + 256 * k;
         if (i >= n) continue;
-        T hx = xi[k], hy = yi[k], lx = xl[i], ly = yl[i];
         const T ux = COMP ? (T)axd[k] : ax[k];
         const T uy = COMP ? (T)ayd[k] : ay[k];
-        if (COMP) {
-            acc2(hx, lx, dt * ux);
-            acc2(hy, ly, dt * uy);
+        big_update_point<T>(S, step, r, s, p0, f0, N, i, nxt, xi[k], yi[k], xl[i], yl[i], ux, uy, obs, status,
+                            steps_done);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// large systems in FP32, symmetric: every pair of points is evaluated once
+// per step and serves both ends.  Points form tiles of BIG_T = 256 (four
+// blocks of 64); one workgroup of four waves takes one pair of tiles
+// (ta <= tb) of one system.  Wave w holds block w of tile ta as targets, one
+// point per lane, and runs over the blocks of tile tb (from block w on when
+// ta == tb) with the lane schedule of the small systems: at offset s lane l
+// pairs its target with point (l + s) mod 64 of the block, whose sums rotate
+// down one lane per offset.  Both ends accumulate in FP64 as in
+// pair_accumulate_x (the constant part of Ht in two floats, exact products).
+// The workgroup leaves tile ta's sums over tile tb and tile tb's over tile
+// ta in two slots of a partial-sum buffer (one slot when ta == tb); then
+// k_big_update adds a tile's slots in a fixed order and takes the Euler
+// step: deterministic, no atomics on the sums.
+// ---------------------------------------------------------------------------
+
+// offsets [s_lo, s_hi) of one block pair: ti is this lane's target (its
+// force in FP64: tfx, tfy), sp + lane + s the moving point at offset s (the
+// block stored twice).  Targets' sums add to (ax, ay); the moving points'
+// sums of this pass return in (bxo, byo), realigned to lane = point.  Offsets
+// from s_full on (the diagonal block's offset 32) count for lanes 0..31
+// only.  FAR: only the pairs beyond the table, evaluated directly.
+template <bool FAR>
+__device__ __forceinline__ bool big_sym_block(const SysConst<float>& C, const TabSys* tab, const Src4<float>& ti,
+                                              double tfx, double tfy, const Src4<float>* sp, int s_lo, int s_full,
+                                              int s_hi, int lane, double& ax, double& ay, double& bxo, double& byo)
+{
+    const float ts = C.ts;
+    double bx = 0.0, by = 0.0;
+    bool far = false;
+    auto offset = [&](const Src4<float>& q, bool live) {
+        const float dx = ti.x - q.x, dy = ti.y - q.y;
+        const float t = fmaf(dx, dx, dy * dy);
+        const uint32_t bits = tab_bits(t, ts);
+        const uint32_t id = bits >> TAB_SHIFT;
+        float h0, lo, H2;
+        if constexpr (!FAR) {
+            far = far || id >= TAB_END;
+            const uint32_t ic = min(id, TAB_END) - TAB_BIAS;
+            const TabE& e = tab->e[ic];
+            const float u = tab_u(bits);
+            h0 = e.h[0];
+            lo = tab->h0lo[ic] + u * fmaf(fmaf(e.h[3], u, e.h[2]), u, e.h[1]);
+            H2 = fmaf(fmaf(fmaf(e.g[3], u, e.g[2]), u, e.g[1]), u, e.g[0]) * ts;
         } else {
-            hx = fma_t(dt, ux, hx);
-            hy = fma_t(dt, uy, hy);
+            h0 = 0.0f;
+            lo = 0.0f;
+            H2 = 0.0f;
+            if (id >= TAB_END) kernel_eval<float>(C, t, h0, H2);
         }
-        ((T*)S.xh[nxt])[p0 + i] = hx;
-        ((T*)S.yh[nxt])[p0 + i] = hy;
-        ((T*)S.xl[nxt])[p0 + i] = lx;
-        ((T*)S.yl[nxt])[p0 + i] = ly;
-        if (bad_t(hx) || bad_t(hy)) {
-            atomicMax(&status[s], (isfinite(hx) && isfinite(hy)) ? 2 : 1);
-            if (steps_done) steps_done[s] = step + 1;
+        if (!live) {
+            h0 = 0.0f;
+            lo = 0.0f;
+            H2 = 0.0f;
         }
-        if (r.obs_every > 0 && (step + 1) % r.obs_every == 0) {
-            const int m = (int)(i / N), p = (int)(i - (int64_t)m * N);
-            if (p == N - 1) {
-                const int o = (step + 1) / r.obs_every - 1;
-                T* q = obs + ((f0 + m) * (int64_t)r.n_obs + o) * 2;
-                q[0] = hx + lx;
-                q[1] = hy + ly;
-            }
+        // h0 + lo is exact in FP64
+        const double hd = (double)h0 + (double)lo;
+        const double dxd = dx, dyd = dy, qfx = q.fx, qfy = q.fy;
+        const double fdj = (double)(H2 * fmaf(q.fx, dx, q.fy * dy));
+        const double fdi = (double)(H2 * fmaf(ti.fx, dx, ti.fy * dy));
+        ax = fma(hd, qfx, fma(fdj, dxd, ax));
+        ay = fma(hd, qfy, fma(fdj, dyd, ay));
+        bx = lane_rot(fma(hd, tfx, fma(fdi, dxd, bx)));
+        by = lane_rot(fma(hd, tfy, fma(fdi, dyd, by)));
+    };
+    const Src4<float>* spl = sp + lane;
+    int s = __builtin_amdgcn_readfirstlane(s_lo);
+    const int sf = __builtin_amdgcn_readfirstlane(s_full);
+    for (; s + 1 < sf; s += 2) {
+        offset(spl[s], true);
+        offset(spl[s + 1], true);
+    }
+    if (s < sf) offset(spl[s], true);
+    if (sf < s_hi) offset(spl[sf], lane < 32);
+    // lane l now holds the sums of point (l + s_hi) mod 64 of the block
+    const int from = (lane - s_hi) & 63;
+    bxo = __shfl(bx, from, 64);
+    byo = __shfl(by, from, 64);
+    return far;
+}
+
+constexpr int BIG_T = BIG_TILE_POINTS;  // points per tile of the symmetric large-system step
+
+// LDS of k_big_pairs: [table][tile ta, BIG_T][tile tb, each block twice][the
+// four waves' sums of tile tb's points]
+constexpr size_t BIG_PAIR_SRC = sizeof(TabSys);
+constexpr size_t BIG_PAIR_SRC2 = BIG_PAIR_SRC + BIG_T * sizeof(Src4<float>);
+constexpr size_t BIG_PAIR_PB = BIG_PAIR_SRC2 + 2 * BIG_T * sizeof(Src4<float>);
+constexpr size_t BIG_PAIR_LDS = BIG_PAIR_PB + 4 * BIG_T * sizeof(V2<double>);
+static_assert(sizeof(TabSys) % 16 == 0, "16-byte aligned LDS sections");
+
+__global__ __launch_bounds__(256) void k_big_pairs(BigTiles bt, Batch b, BigState S, int step, Run r,
+                                                    const int32_t* status)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    TabSys* tab = reinterpret_cast<TabSys*>(smem);
+    Src4<float>* sa = reinterpret_cast<Src4<float>*>(smem + BIG_PAIR_SRC);
+    Src4<float>* sb2 = reinterpret_cast<Src4<float>*>(smem + BIG_PAIR_SRC2);
+    V2<double>* pb = reinterpret_cast<V2<double>*>(smem + BIG_PAIR_PB);
+    __shared__ int s_status;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t s = bt.sys[blockIdx.x];
+    const int tt = bt.tile[blockIdx.x];
+    const int ta = tt & 0xffff, tb = tt >> 16;
+    // one read of the status per workgroup, broadcast (uniform exit)
+    if (tid == 0) s_status = status[s];
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_status) != 0) return;
+    tab_load((const TabSys*)b.tab + s, tab, tid, 256);
+    const int64_t p0 = b.pt_off[s];
+    const int N = b.npt[s];
+    const int n = N * b.nswim[s];
+    const int nt = (n + BIG_T - 1) / BIG_T;
+    const int64_t f0 = b.sw_off[s];
+    const int cur = step & 1;
+    const float* xh = (const float*)S.xh[cur] + p0;
+    const float* yh = (const float*)S.yh[cur] + p0;
+    const float* xl = (const float*)S.xl[cur] + p0;
+    const float* yl = (const float*)S.yl[cur] + p0;
+    const float t = (float)((double)step * r.dt);
+    const SysConst<float> C = ((const SysConst<float>*)b.sysc)[s];
+    const bool diag = ta == tb;
+    // sources of both tiles; points beyond n: at point n - 1, no force (they
+    // add nothing and their own sums are not used)
+    for (int jj = tid; jj < BIG_T; jj += 256) {
+        const int ib = tb * BIG_T + jj;
+        Src4<float> v = big_source<float>(b, xh, yh, xl, yl, f0, N, min(ib, n - 1), t);
+        if (ib >= n) v.fx = v.fy = 0.0f;
+        const int k = ((jj >> 6) << 7) + (jj & 63);
+        sb2[k] = v;
+        sb2[k + 64] = v;
+        if (!diag) {
+            const int ia = ta * BIG_T + jj;
+            Src4<float> u = big_source<float>(b, xh, yh, xl, yl, f0, N, min(ia, n - 1), t);
+            if (ia >= n) u.fx = u.fy = 0.0f;
+            sa[jj] = u;
         }
     }
+    for (int k = tid; k < 4 * BIG_T; k += 256) pb[k] = V2<double>{0.0, 0.0};
+    __syncthreads();
+    const Src4<float> ti = diag ? sb2[(w << 7) + lane] : sa[(w << 6) + lane];
+    const double tfx = ti.fx, tfy = ti.fy;
+    double ax = 0.0, ay = 0.0;
+    for (int bb = diag ? w : 0; bb < 4; ++bb) {
+        // the diagonal block: offsets 1..32, offset 32 for lanes 0..31
+        const bool dblk = diag && bb == w;
+        const int s_lo = dblk ? 1 : 0, s_full = dblk ? 32 : 64, s_hi = dblk ? 33 : 64;
+        const Src4<float>* sp = sb2 + (bb << 7);
+        double bx, by;
+        const bool far = big_sym_block<false>(C, tab, ti, tfx, tfy, sp, s_lo, s_full, s_hi, lane, ax, ay, bx, by);
+        if (__any(far)) {
+            double fx2, fy2;
+            big_sym_block<true>(C, tab, ti, tfx, tfy, sp, s_lo, s_full, s_hi, lane, ax, ay, fx2, fy2);
+            bx += fx2;
+            by += fy2;
+        }
+        pb[w * BIG_T + (bb << 6) + lane] = V2<double>{bx, by};
+    }
+    V2<double>* const pbuf = reinterpret_cast<V2<double>*>(bt.part);
+    V2<double>* part = pbuf + (bt.poff[s] + (int64_t)ta * nt + tb) * BIG_T;
+    if (diag) {
+        // this wave's targets are points of the same tile: their sums join
+        // the moving-point sums of their own block
+        V2<double>& e = pb[w * BIG_T + (w << 6) + lane];
+        e.x += ax;
+        e.y += ay;
+    } else {
+        part[(w << 6) + lane] = V2<double>{ax, ay};
+    }
+    __syncthreads();
+    // tile tb's sums over tile ta (the whole tile's when ta == tb): the four
+    // waves' slots in order
+    V2<double> u = pb[tid];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+        u.x += pb[q * BIG_T + tid].x;
+        u.y += pb[q * BIG_T + tid].y;
+    }
+    pbuf[(bt.poff[s] + (int64_t)tb * nt + ta) * BIG_T + tid] = u;
+}
+
+// the Euler step of the symmetric large-system path: one workgroup per tile,
+// a point's velocity the sum of its tile's slots in tile order
+__global__ __launch_bounds__(256) void k_big_update(BigTiles bt, Batch b, BigState S, int step, Run r, float* obs,
+                                                     int32_t* status, int32_t* steps_done)
+{
+    __shared__ int s_status;
+    const int tid = threadIdx.x;
+    const int64_t s = bt.sys[blockIdx.x];
+    const int tile = bt.tile[blockIdx.x];
+    if (tid == 0) s_status = status[s];
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_status) != 0) return;
+    const int64_t p0 = b.pt_off[s];
+    const int N = b.npt[s];
+    const int n = N * b.nswim[s];
+    const int nt = (n + BIG_T - 1) / BIG_T;
+    const int64_t f0 = b.sw_off[s];
+    const int cur = step & 1, nxt = cur ^ 1;
+    const int64_t i = (int64_t)tile * BIG_T + tid;
+    if (i >= n) return;
+    const V2<double>* src = reinterpret_cast<const V2<double>*>(bt.part) + (bt.poff[s] + (int64_t)tile * nt) * BIG_T + tid;
+    double ux = 0.0, uy = 0.0;
+    for (int q = 0; q < nt; ++q) {
+        const V2<double> v = src[(int64_t)q * BIG_T];
+        ux += v.x;
+        uy += v.y;
+    }
+    const float* xh = (const float*)S.xh[cur] + p0;
+    const float* yh = (const float*)S.yh[cur] + p0;
+    const float* xl = (const float*)S.xl[cur] + p0;
+    const float* yl = (const float*)S.yl[cur] + p0;
+    big_update_point<float>(S, step, r, s, p0, f0, N, i, nxt, xh[i], yh[i], xl[i], yl[i], (float)ux, (float)uy, obs,
+                            status, steps_done);
 }
 
 template <typename T>
@@ -1553,6 +1789,38 @@ hipError_t launch_big_step(int dtype, int tpl, int64_t nb, const int64_t* bs, co
         switch (tpl) { BIG_CASE(double, 1) BIG_CASE(double, 2) BIG_CASE(double, 4) default: return hipErrorInvalidValue; }
     }
 #undef BIG_CASE
+}
+
+size_t big_pair_lds_bytes() { return BIG_PAIR_LDS; }
+
+// raise k_big_pairs' dynamic-LDS limit (outside any stream capture)
+hipError_t prepare_big_pairs()
+{
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_big_pairs, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)BIG_PAIR_LDS);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_big_pairs(int64_t n_pairs, const BigTiles& bt, const Batch& b, const BigState& s, int step,
+                            const Run& r, const int32_t* status, hipStream_t st)
+{
+    if (n_pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_big_pairs, dim3((unsigned)n_pairs), dim3(256), BIG_PAIR_LDS, st, bt, b, s, step, r, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_big_update(int64_t n_tiles, const BigTiles& bt, const Batch& b, const BigState& s, int step,
+                             const Run& r, void* obs, int32_t* status, int32_t* steps_done, hipStream_t st)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_big_update, dim3((unsigned)n_tiles), dim3(256), 0, st, bt, b, s, step, r, (float*)obs,
+                       status, steps_done);
+    return hipGetLastError();
 }
 
 hipError_t launch_big_finish(int dtype, const int64_t* list, int64_t n_list, const Batch& b, const BigState& s,

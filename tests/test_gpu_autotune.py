@@ -38,7 +38,7 @@ def test_autotune_choices_and_tune_file(ctx, oracle_core, tmp_path):
     for t in (1, 4, 6, 8):
         assert ch["wps"][t] in (2, 4, 8, 16), (t, ch)
     assert ch["wps"][2] == 0 and ch["wps"][3] == 0
-    assert ch["big_tpl"] in (1, 2, 4)
+    assert ch["big_tpl"] in (0, 1, 2, 4)
     assert swim.swim_get_option(ctx, swim.SWIM_OPT_BIG_TPL) == ch["big_tpl"]
     f = tmp_path / "tune.txt"
     swim.swim_tune_save(ctx, f)

@@ -286,6 +286,79 @@ def test_large_system_over_several_tiles_matches_oracle(ctx, oracle_core, dtype,
             check_traj(obs[m], ref["obs"][m], np.array([P[m, 7] + 1.0, P[m, 8]]), tol, dtype, steps, 3.0)
 
 
+def _forward_eps(ctx, dtype, N, nsw, P, steps, dt, oe, eps_over_ds):
+    td = DT[dtype]
+    nfil = P.shape[0]
+    obs = torch.full((nfil, steps // oe, 2), float("nan"), dtype=td, device="cuda")
+    speed = torch.empty(nfil, dtype=td, device="cuda")
+    status = torch.empty(len(N), dtype=torch.int32, device="cuda")
+    swim.swim_forward(ctx, np.asarray(N, np.int32), nsw, dev(P, torch.float64), steps, dt, oe, eps_over_ds, obs,
+                      speed, status)
+    torch.cuda.synchronize()
+    return obs.cpu().double().numpy(), status.cpu().numpy()
+
+
+def test_large_system_symmetric_step_matches_one_sided(ctx):
+    """The FP32 large-system step at its automatic choice (every pair once for
+    both points, tile pairs of 256 points, partial sums reduced in a fixed
+    order) against the one-sided kernel (every ordered pair, one target per
+    lane): both accumulate in FP64 from the same FP32 table, so they differ
+    by FP64 rounding of differently ordered sums; 1e-6 of each head's
+    displacement.  Cases: 8 swimmers of N = 140 (1120 points, five tiles, the
+    last partly filled; 40 steps of 5e-5); 8 swimmers of N = 80 in two groups
+    at opposite corners of the position bound with eps = 0.05 ds, whose
+    cross pairs (r ~ 2800 > 2^22 eps) lie beyond the FP32 table and take the
+    direct pass (20 steps of 2e-6, stable at this eps on the oracle; the
+    FP32 run also against the FP64 one at 1e-4); and one N = 128 swimmer at
+    eps = 0.08 ds, which the host sends to the large-system step because its
+    pairs could leave the table (40 steps of 5e-7, against FP64 at 1e-4).
+    The far pairs' contributions are tiny here (each filament's forces sum
+    to zero), so these cases check that the direct pass and the routing run
+    and agree, not the far field's size.  The symmetric runs repeat bit for
+    bit."""
+    lay = inputs.dense_layout(n_samples=2, seed=5)
+    P1 = lay[1].copy()
+    P1[:, 0] = 0.7
+    P1[:, 7] -= 2.75
+    P1[:, 8] -= 0.75
+    P2 = inputs.dense_layout(n_samples=1, seed=5)[0].copy()
+    P2[:, 0] = 0.7
+    P2[:, 7] -= 2.75
+    P2[:, 8] -= 0.75
+    P2[:4, 7:9] -= 985.0
+    P2[4:, 7:9] += 985.0
+    P3 = inputs.param_rows(1, alpha=1.0)
+    try:
+        for Nn, nsw, P, steps, dt, oe, e in ((140, 8, P1, 40, 5e-5, 10, 1.5), (80, 8, P2, 20, 2e-6, 5, 0.05),
+                                             (128, 1, P3, 40, 5e-7, 10, 0.08)):
+            out = {}
+            x0 = P[:, 7:9] + np.array([1.0, 0.0])
+            for big in ((0, 1, 0) if nsw > 1 else (0,)):
+                swim.swim_set_option(ctx, swim.SWIM_OPT_BIG_TPL, big)
+                obs, st = _forward_eps(ctx, swim.SWIM_F32, [Nn], [nsw], P, steps, dt, oe, e)
+                assert list(st) == [0], (Nn, big, st)
+                if big in out:
+                    assert np.array_equal(obs, out[big]), "symmetric runs are not bit-reproducible"
+                out[big] = obs
+            if 1 in out:
+                for m in range(nsw):
+                    disp = np.linalg.norm(out[1][m] - x0[m])
+                    err = np.linalg.norm(out[0][m] - out[1][m])
+                    floor = np.linalg.norm(np.spacing(np.abs(out[1][m]).astype(np.float32)))
+                    assert err <= 1e-6 * disp + floor, (Nn, m, err, disp)
+            if e < 1.0:
+                o64, st = _forward_eps(ctx, swim.SWIM_F64, [Nn], [nsw], P, steps, dt, oe, e)
+                assert list(st) == [0]
+                for m in range(nsw):
+                    disp = np.linalg.norm(o64[m] - x0[m])
+                    err = np.linalg.norm(out[0][m] - o64[m])
+                    floor = np.linalg.norm(np.spacing(np.abs(o64[m]).astype(np.float32)))
+                    print({"N": Nn, "m": m, "fp32_vs_fp64": err / disp})
+                    assert err <= 1e-4 * disp + floor, (Nn, m, err, disp)
+    finally:
+        swim.swim_set_option(ctx, swim.SWIM_OPT_BIG_TPL, 0)
+
+
 def test_dense_sample_velocity_at_full_size(ctx, oracle_core):
     """One velocity evaluation of the large-N dense workload at its full size:
     sample 0 (8 swimmers x 512 points on the 2 x 4 grid, alpha from seed 3)
