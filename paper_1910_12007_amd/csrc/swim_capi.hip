@@ -639,10 +639,19 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     h.add(big_lane);
     const void* ptrs[] = {params_dev, obs, speed, status, steps_done, sysc, sysc64, b.tab, c->buf[B_SWOFF].p,
                           c->buf[B_OFF].p, c->buf[B_NPT].p, c->buf[B_NSW].p, c->buf[B_ORDER].p, c->buf[B_LIST].p,
-                          c->buf[B_BLKS].p, c->buf[B_BLKF].p, c->buf[B_QUEUE].p, c->buf[B_BIG].p,
-                          c->buf[B_BT_PSYS].p, c->buf[B_BT_PT].p, c->buf[B_BT_TSYS].p, c->buf[B_BT_TT].p,
-                          c->buf[B_BT_POFF].p, c->buf[B_BT_PART].p, st};
+                          c->buf[B_QUEUE].p, c->buf[B_BIG].p, st};
     h.add_bytes(ptrs, sizeof(ptrs));
+    // the large-system step's own lists: only those its launches read (the
+    // other path's buffers are shared with other calls, which may move them)
+    if (!big_list.empty()) {
+        const void* bptrs[] = {c->buf[B_BLKS].p, c->buf[B_BLKF].p};
+        const void* sptrs[] = {c->buf[B_BT_PSYS].p, c->buf[B_BT_PT].p, c->buf[B_BT_TSYS].p,
+                               c->buf[B_BT_TT].p,   c->buf[B_BT_POFF].p, c->buf[B_BT_PART].p};
+        if (big_sym)
+            h.add_bytes(sptrs, sizeof(sptrs));
+        else
+            h.add_bytes(bptrs, sizeof(bptrs));
+    }
     const uint64_t key = h.v;
     ++c->graph_clock;
     for (auto& g : c->graphs)
