@@ -827,6 +827,14 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
     __syncthreads();
     int st = 0, done = r.steps;
     const int nblk64 = (n + 63) >> 6;
+    // this wave's share of the pair schedule when it is one segment
+    int seg_a = 0, seg_b = 0, seg_lo = 0, seg_hi = 0;
+    bool one_seg = sym_one_segment<WPS>(n, wave, seg_a, seg_b, seg_lo, seg_hi);
+    one_seg = __builtin_amdgcn_readfirstlane(one_seg ? 1 : 0) != 0;
+    seg_a = __builtin_amdgcn_readfirstlane(seg_a);
+    seg_b = __builtin_amdgcn_readfirstlane(seg_b);
+    seg_lo = __builtin_amdgcn_readfirstlane(seg_lo);
+    seg_hi = __builtin_amdgcn_readfirstlane(seg_hi);
     int obs_left = r.obs_every, obs_k = 0;  // steps to the next sample, its index
     for (int step = 0; step < r.steps; ++step) {
         // pair phase: this wave's share of the symmetric pair schedule
@@ -840,7 +848,10 @@ __device__ void run_system(const Batch& b, const Run& r, int s, const FwdLds<T>&
             // are the caller's: a run placed beyond the bound reads zeros
             // for its far pairs in its first step and stops)
             T ax[TPL], ay[TPL];
-            pair_phase_sym<T, TPL, WPS, false, WIN>(C, L.tab, L.src, n, wave, lane, ax, ay);
+            if (one_seg)
+                pair_phase_seg<T, TPL, false, WIN>(C, L.tab, L.src, seg_a, seg_b, seg_lo, seg_hi, lane, ax, ay);
+            else
+                pair_phase_sym<T, TPL, WPS, false, WIN>(C, L.tab, L.src, n, wave, lane, ax, ay);
 #pragma unroll
             for (int c = 0; c < TPL; ++c) {
                 if (c < nblk64) {

@@ -261,6 +261,55 @@ __device__ __forceinline__ void pair_phase_sym(const SysConst<T>& C, const TabSy
     }
 }
 
+// The single block pair (a, b) and offset range [s_lo, s_hi) of this wave's
+// share of pair_phase_sym's schedule for n points, when the share lies in
+// one block pair (as for 128 points over 8 waves: 16 offsets each), else
+// false.  Step-invariant: a run finds it once.
+template <int WPS>
+__device__ __forceinline__ bool sym_one_segment(int n, int wave, int& sa, int& sb, int& s_lo, int& s_hi)
+{
+    const int B = (n + 63) >> 6;
+    const int S = 32 * B * B;
+    const int per = (S + WPS - 1) / WPS;
+    const int g0 = min(S, wave * per), g1 = min(S, g0 + per);
+    if (g0 >= g1) return false;
+    int g = 0;
+    for (int a = 0; a < B; ++a) {
+        for (int b = a; b < B; ++b) {
+            const int len = (a == b) ? 32 : 64, base = (a == b) ? 1 : 0;
+            if (g0 >= g && g1 <= g + len) {
+                sa = a;
+                sb = b;
+                s_lo = g0 - g + base;
+                s_hi = g1 - g + base;
+                return true;
+            }
+            g += len;
+        }
+    }
+    return false;
+}
+
+// pair_phase_sym for a wave whose share is the one segment found by
+// sym_one_segment (same sums, same order)
+template <typename T, int TPL, bool CHECK = true, bool WRAP = false>
+__device__ __forceinline__ void pair_phase_seg(const SysConst<T>& C, const TabSys* tab, const Src4<T>* src2, int a,
+                                               int b, int s_lo, int s_hi, int lane, T (&accx)[TPL], T (&accy)[TPL])
+{
+#pragma unroll
+    for (int c = 0; c < TPL; ++c) accx[c] = accy[c] = (T)0;
+    const char* et = nullptr;
+    if constexpr (WRAP) {
+        et = reinterpret_cast<const char*>(tab);
+    } else if constexpr (sizeof(T) == 4) {
+        et = reinterpret_cast<const char*>(tab->e) + opaque_uniform(-(int)(TAB_BIAS * sizeof(TabE)));
+    }
+    const bool far = sym_offsets<T, TPL, false, CHECK, WRAP>(C, et, src2, a, b, s_lo, s_hi, lane, accx, accy);
+    if constexpr (sizeof(T) == 4 && CHECK) {
+        if (__any(far)) sym_offsets<T, TPL, true>(C, et, src2, a, b, s_lo, s_hi, lane, accx, accy);
+    }
+}
+
 // sum over the 64 lanes of a wavefront (butterfly; lane j's result is
 // deterministic)
 template <typename T> __device__ __forceinline__ T wave_total(T v)
