@@ -42,13 +42,13 @@ sys.path.insert(0, ROOT)
 # (4 FMA): 42 FLOP (FMA = 2) per distinct pair, 21 per ordered pair.  The
 # kernel is bound by VALU instruction issue, not FLOP: integer and float
 # operations share the issue slots.  rocprofv3's SQ_INSTS_VALU over the
-# launch gives 18.3 VALU lane-operations per ordered pair evaluation, all
+# launch gives 17.8 VALU lane-operations per ordered pair evaluation, all
 # work of the step included (the symmetric pair loop alone is 14.75 in the
 # ISA); the issue peak without packed FP32 is 256 CUs x 4 SIMDs x 16 lanes
 # per clock x 2.4 GHz = 39.3e12 lane-operations/s, i.e. 78.6 TFLOP/s of FMA
 # (the build keeps packed FP32 off).
 # (profiles/k_forward_batch_4096x128_counters.md)
-VALU_OPS_PER_PAIR = 18.3
+VALU_OPS_PER_PAIR = 17.8
 PAIR_LOOP_VALU_OPS = 15.75  # the sperm kernel's symmetric pair loop alone (ISA, per ordered pair)
 FP32_FLOP_PER_PAIR = 21
 NONPACKED_FP32_PEAK_TFLOPS = 78.6
@@ -61,12 +61,12 @@ VALU_OPS_PER_PAIR_BIG = 26.2
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 # HBM bytes of one launch of that kernel on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch: 46308.3 and 2217.5) scaled by
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch: 46328.1 and 2224.0) scaled by
 # the same counters over a 256 MiB device copy (x2.0 and x1.0), for the
 # kernel as it stands (profiles/k_forward_batch_4096x128_counters.md): almost
 # all of it the 4096 kernel tables (22.5 KiB each) read once into LDS; set
 # it to None whenever the kernel changes until the counters are taken again
-TRAFFIC_BYTES = None  # the kernel changed: retake the counters
+TRAFFIC_BYTES = (46328.1 * 2.00 + 2224.0 * 1.00) * 1024
 
 
 def load_data():
