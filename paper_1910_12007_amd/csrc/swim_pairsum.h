@@ -341,12 +341,19 @@ __host__ __device__ constexpr bool tail_pays(int n)
 //    (tail l, tail j) for target tail l only.
 // Every ordered pair is taken once.  The full blocks' offsets are split
 // over the waves as in pair_phase_sym; tail point j goes to wave j mod WPS.
+// seg: this wave's share of the full blocks' schedule as found by
+// sym_one_segment for 64 Bf points (seg[0] != 0: a single segment a = seg[1],
+// b = seg[2], offsets [seg[3], seg[4])), or null
 template <typename T, int TPL, int WPS>
 __device__ __forceinline__ void pair_phase_tail(const SysConst<T>& C, const TabSys* tab, const Src4<T>* src2, int n,
-                                                int wave, int lane, T (&accx)[TPL], T (&accy)[TPL])
+                                                int wave, int lane, T (&accx)[TPL], T (&accy)[TPL],
+                                                const int* seg = nullptr)
 {
     const int Bf = n >> 6, r = n & 63;
-    pair_phase_sym<T, TPL, WPS>(C, tab, src2, 64 * Bf, wave, lane, accx, accy);
+    if (seg && seg[0])
+        pair_phase_seg<T, TPL>(C, tab, src2, seg[1], seg[2], seg[3], seg[4], lane, accx, accy);
+    else
+        pair_phase_sym<T, TPL, WPS>(C, tab, src2, 64 * Bf, wave, lane, accx, accy);
     const char* et = nullptr;
     if constexpr (sizeof(T) == 4)
         et = reinterpret_cast<const char*>(tab->e) + opaque_uniform(-(int)(TAB_BIAS * sizeof(TabE)));

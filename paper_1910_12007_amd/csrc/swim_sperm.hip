@@ -409,11 +409,26 @@ __device__ void sperm_system(const SpermShape& g, const SpermRun& r, int64_t s, 
     __syncthreads();
     int st = 0;
     int obs_left = r.obs_every, obs_k = 1;
+    // this wave's share of the symmetric schedule (of the full blocks when
+    // the tail schedule takes the rest), found once when it is one segment
+    const bool tail_sched = tail_pays(n);
+    int seg[5] = {0, 0, 0, 0, 0};
+    {
+        int a = 0, b = 0, lo = 0, hi = 0;
+        const bool one = sym_one_segment<WPS>(tail_sched ? 64 * (n >> 6) : n, wave, a, b, lo, hi);
+        seg[0] = __builtin_amdgcn_readfirstlane(one ? 1 : 0);
+        seg[1] = __builtin_amdgcn_readfirstlane(a);
+        seg[2] = __builtin_amdgcn_readfirstlane(b);
+        seg[3] = __builtin_amdgcn_readfirstlane(lo);
+        seg[4] = __builtin_amdgcn_readfirstlane(hi);
+    }
     for (int step = 0; step < r.steps; ++step) {
         {
             T ax[TPL], ay[TPL];
-            if (tail_pays(n))
-                pair_phase_tail<T, TPL, WPS>(C, tab, src, n, wave, lane, ax, ay);
+            if (tail_sched)
+                pair_phase_tail<T, TPL, WPS>(C, tab, src, n, wave, lane, ax, ay, seg);
+            else if (seg[0])
+                pair_phase_seg<T, TPL>(C, tab, src, seg[1], seg[2], seg[3], seg[4], lane, ax, ay);
             else
                 pair_phase_sym<T, TPL, WPS>(C, tab, src, n, wave, lane, ax, ay);
 #pragma unroll
