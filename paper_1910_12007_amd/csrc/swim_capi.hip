@@ -404,7 +404,11 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     std::vector<int32_t> bp_tile, bt_tile;
     int64_t bt_slots = 0;
     if (big_sym) {
+        // tile pairs: the off-diagonal ones (twice the work) first, so that
+        // the launch's tail holds the lighter diagonal ones
         bt_poff.assign(n_sys, 0);
+        std::vector<int64_t> dg_sys;
+        std::vector<int32_t> dg_tile;
         for (int64_t s : big_list) {
             const int nt = (pts[s] + BIG_TILE_POINTS - 1) / BIG_TILE_POINTS;
             if (nt > 0xFFFF) return fail(SWIM_EINVAL, "system of %d points exceeds the large-system tiling", pts[s]);
@@ -413,12 +417,16 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
             for (int ta = 0; ta < nt; ++ta) {
                 bt_sys.push_back(s);
                 bt_tile.push_back(ta);
-                for (int tb = ta; tb < nt; ++tb) {
+                dg_sys.push_back(s);
+                dg_tile.push_back(ta | (ta << 16));
+                for (int tb = ta + 1; tb < nt; ++tb) {
                     bp_sys.push_back(s);
                     bp_tile.push_back(ta | (tb << 16));
                 }
             }
         }
+        bp_sys.insert(bp_sys.end(), dg_sys.begin(), dg_sys.end());
+        bp_tile.insert(bp_tile.end(), dg_tile.begin(), dg_tile.end());
     } else {
         for (int64_t s : big_list)
             for (int64_t f = 0; f < pts[s]; f += 256 * tpl_big) {
