@@ -583,7 +583,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the swimmer batches are "
-              "independent, and this build measures the single-GPU share.", file=sys.stderr)
+              "independent, so the workload is measured as one GPU's share of it.", file=sys.stderr)
         sys.exit(2)
 
     import torch
