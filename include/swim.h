@@ -164,10 +164,17 @@ int swim_get_option(swim_ctx *ctx, int32_t key, int32_t *value);
 /* Autotuner of the launch shapes (synchronous).  Times forward runs of
  * probe_steps steps of the given batch (layout and parameter rows as for
  * swim_forward; params device) on the context's stream, eagerly:
- *   - for every size bucket of the persistent kernel present in the batch
- *     (systems of up to 64*tpl points, tpl in {1,2,3,4,6,8}), the waves per
- *     system among 2, 4, 8, 16 (those whose partial sums fit the LDS), one
- *     bucket at a time with the others at their current choice;
+ *   - for every size bucket of the persistent kernel the forward calls
+ *     launch for this batch (systems of up to 64*tpl points, tpl in
+ *     {1,2,3,4,6,8}, after the merging that swim_forward describes), the
+ *     waves per system among 2, 4, 8, 16 (those whose partial sums fit the
+ *     LDS), each bucket probed alone on its systems of the batch (the
+ *     buckets of a call run side by side, so the call's time does not see
+ *     a bucket off its longest path): the most waves whose probe is within
+ *     5 % of the fastest (a run's own speed grows with its waves, and the
+ *     longest runs bound a launch's time, which a short probe does not
+ *     show).  The probes copy params to the host and allocate a device
+ *     buffer of the same size;
  *   - if the batch has systems over 512 points, the large-system step:
  *     the one-sided kernel at 1, 2, 4 targets per lane and, for FP32, the
  *     symmetric step (SWIM_OPT_BIG_TPL = 0).
@@ -270,10 +277,15 @@ int swim_elastic_forces(swim_ctx *ctx, int32_t dtype, int64_t n_fil, const int32
  * status   device int32[n_sys]: SWIM_ST_* per system.
  * steps_done device int32[n_sys] or NULL: forward-Euler steps computed per
  *          system (steps, or the step at which the run stopped, 0 if not run).
- * Systems of up to 512 points run in one persistent kernel (a workgroup per
- * system, work queue in longest-first order); larger systems run the
- * large-system step, launches per Euler step with the work split over
- * workgroups (SWIM_OPT_BIG_TPL).  FP32 systems whose pairs could lie beyond
+ * Systems of up to 512 points run in the persistent kernel (a workgroup per
+ * system, work queue in longest-first order), one launch per size bucket
+ * (systems of up to 64*tpl points, tpl in {1,2,3,4,6,8}); larger systems
+ * run the large-system step, launches per Euler step with the work split
+ * over workgroups (SWIM_OPT_BIG_TPL).  The buckets and the large systems
+ * run side by side on the context's stream and up to three more; with more
+ * than four such parts, adjacent buckets closest in size merge (the smaller
+ * systems run in the larger bucket's launch) until four remain.  Waves of
+ * larger buckets issue at a higher priority where launches share a CU.  FP32 systems whose pairs could lie beyond
  * the FP32 kernel table within the position bound (2829 (N-1) / eps_over_ds
  * >= 2^22, i.e. eps_over_ds well below 1.5) take the large-system step at
  * any size, since the persistent kernel does not test for such pairs.

@@ -153,6 +153,10 @@ struct swim_ctx {
     bool timed = false;
     hipStream_t last_stream = nullptr;  // stream of the previous call (null: none yet)
     bool broken = false;
+    // the autotuner's probes of one launch bucket alone: the bucket each
+    // natural size bucket launches in, taken from the whole batch
+    bool forced_launch = false;
+    int force_launch_tpl[9] = {};
 };
 
 namespace {
@@ -275,6 +279,39 @@ int forward_tpl(int32_t dtype, int N, int pts, double eps_over_ds)
     return choose_tpl(pts);
 }
 
+// The targets per lane each size bucket launches with.  The buckets of one
+// call (plus the large systems, big) run side by side on at most lanes
+// streams.  With more parts than lanes, a lane would run two launches one
+// after the other, the second waiting for the first one's tail (its longest
+// run, one workgroup on part of a CU); instead, adjacent buckets merge until
+// the parts fit, the smaller bucket's systems running in the larger one's
+// kernel.  The pair merged is the one closest in size (the largest ratio of
+// the two targets per lane; the larger sizes on a tie), whose smaller
+// systems lose the least in the larger kernel.  present[t]: some system
+// takes t targets per lane (choose_tpl); launch[t]: the targets per lane it
+// runs with (0 where t is absent).
+void merge_buckets(const bool (&present)[9], bool big, int lanes, int (&launch)[9])
+{
+    std::vector<int> ts;
+    for (int t : TPL_CHOICES)
+        if (present[t]) ts.push_back(t);
+    while ((int)ts.size() + (big ? 1 : 0) > lanes && ts.size() > 1) {
+        size_t best = 0;
+        for (size_t i = 1; i + 1 < ts.size(); ++i)
+            if ((double)ts[i] / ts[i + 1] >= (double)ts[best] / ts[best + 1]) best = i;
+        ts.erase(ts.begin() + (long)best);
+    }
+    for (int t = 0; t <= 8; ++t) {
+        launch[t] = 0;
+        if (t == 0 || !present[t]) continue;
+        for (int u : ts)
+            if (u >= t) {
+                launch[t] = u;
+                break;
+            }
+    }
+}
+
 // two U(0,1) doubles of the library's Philox4x32-10 stream (swim_philox.h)
 void uniforms2(uint64_t seed, uint32_t stream, uint64_t index, uint32_t draw, double* u)
 {
@@ -370,11 +407,23 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     int64_t big_pts = 0;
     std::vector<std::vector<int32_t>> bucket(8);
     std::vector<int64_t> big_list;
+    std::vector<int8_t> tpl_of(n_sys);
+    bool present[9] = {}, any_big = false;
+    for (int64_t s = 0; s < n_sys; ++s) {
+        const int p = N[s] * (nswim ? nswim[s] : 1);
+        tpl_of[s] = (int8_t)forward_tpl(dtype, N[s], p, run.eps_over_ds);
+        if (tpl_of[s] > 0) present[tpl_of[s]] = true;
+        else any_big = true;
+    }
+    int launch_tpl[9];
+    merge_buckets(present, any_big, 1 + swim_ctx::N_AUX, launch_tpl);
+    if (c->forced_launch)
+        for (int t = 0; t <= 8; ++t) launch_tpl[t] = c->force_launch_tpl[t];
     for (int64_t s = 0; s < n_sys; ++s) {
         nsw[s] = nswim ? nswim[s] : 1;
         sw_off[s + 1] = sw_off[s] + nsw[s];
         pts[s] = N[s] * nsw[s];
-        const int tpl = forward_tpl(dtype, N[s], pts[s], run.eps_over_ds);
+        const int tpl = tpl_of[s] > 0 ? launch_tpl[tpl_of[s]] : -1;
         if (tpl > 0) {
             bucket[tpl - 1].push_back((int32_t)s);
         } else {
@@ -1994,15 +2043,20 @@ int swim_autotune(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     TRY(check_run(n_sys, N, n_swim, probe_steps, dt, probe_steps, eps_over_ds));
     hipStream_t st = c->stream;
     int64_t nfil = 0;
-    bool has_tpl[9] = {};
+    bool present[9] = {}, has_tpl[9] = {};
     bool has_big = false;
     for (int64_t s = 0; s < n_sys; ++s) {
         const int nsw = n_swim ? n_swim[s] : 1;
         nfil += nsw;
         const int tpl = forward_tpl(dtype, N[s], N[s] * nsw, eps_over_ds);
-        if (tpl > 0) has_tpl[tpl] = true;
+        if (tpl > 0) present[tpl] = true;
         else has_big = true;
     }
+    // the buckets the forward calls launch (merge_buckets)
+    int launch_tpl[9];
+    merge_buckets(present, has_big, 1 + swim_ctx::N_AUX, launch_tpl);
+    for (int t = 1; t <= 8; ++t)
+        if (launch_tpl[t] > 0) has_tpl[launch_tpl[t]] = true;
     const size_t es = dtype == SWIM_F32 ? 4 : 8;
     TRY(ensure(c, B_OBS, (size_t)nfil * 2 * es));
     TRY(ensure(c, B_SPEED, (size_t)nfil * es));
@@ -2013,21 +2067,29 @@ int swim_autotune(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
     r.obs_every = probe_steps;
     r.n_obs = 1;
     r.eps_over_ds = eps_over_ds;
+    // the batch's filament rows on the host, for the buckets' own probes
+    std::vector<double> hrows((size_t)nfil * SWIM_NPARAM);
+    HIPCHK(hipMemcpyAsync(hrows.data(), params, hrows.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double* sub_rows = nullptr;
+    HIPCHK(hipMalloc((void**)&sub_rows, hrows.size() * sizeof(double)));
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIPCHK(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipFree(sub_rows);
         return fail(SWIM_EHIP, "event creation failed");
     }
     const int save_graph = c->opt_graph, save_wps = c->opt_wps, save_big = c->opt_big_tpl;
     c->opt_graph = 0;
     c->opt_wps = 0;
     int rc = SWIM_OK;
-    auto timed = [&](float* ms) -> int {
-        // one untimed run first: first launches pay for code loading
+    // a forward run of n systems (sizes Ns, filaments nsws, rows P on the
+    // device), timed after one untimed run (first launches pay for code
+    // loading)
+    auto timed_on = [&](int64_t n, const int32_t* Ns, const int32_t* nsws, const double* P, float* ms) -> int {
         for (int rep = 0; rep < 2; ++rep) {
             if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) return fail(SWIM_EHIP, "event record failed");
-            TRY(forward_impl(c, dtype, n_sys, N, n_swim, params, r, c->buf[B_OBS].p, c->buf[B_SPEED].p,
+            TRY(forward_impl(c, dtype, n, Ns, nsws, P, r, c->buf[B_OBS].p, c->buf[B_SPEED].p,
                              (int32_t*)c->buf[B_STATUS].p, nullptr, st));
         }
         HIPCHK(hipEventRecord(e1, st));
@@ -2035,26 +2097,59 @@ int swim_autotune(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
         HIPCHK(hipEventElapsedTime(ms, e0, e1));
         return SWIM_OK;
     };
+    auto timed = [&](float* ms) -> int { return timed_on(n_sys, N, n_swim, params, ms); };
     // waves per system, one size bucket at a time (the others at their
-    // current choice), then targets per lane of the large-system kernel
+    // current choice), then targets per lane of the large-system kernel.
+    // The probe's time is the batch's throughput; a run's own speed grows
+    // with its waves, and a long run's time bounds its launch (a few long
+    // runs among many short ones, as in a generation whose draws mostly
+    // blow up), which a short probe does not show: the most waves within
+    // WPS_TIE of the fastest probe are taken.
+    // Each bucket is probed alone (its systems of the batch, launched as in
+    // the whole batch's calls): side by side with the others, a bucket off
+    // the call's longest path would not change the call's time.
+    constexpr float WPS_TIE = 1.05f;
     const int wps_cand[] = {2, 4, 8, 16};
+    c->forced_launch = true;
+    for (int t = 0; t <= 8; ++t) c->force_launch_tpl[t] = launch_tpl[t];
     for (int tpl = 1; tpl <= 8 && rc == SWIM_OK; ++tpl) {
         if (!has_tpl[tpl]) continue;
+        std::vector<int32_t> Ns, nsws;
+        std::vector<double> rows;
+        int64_t f = 0;
+        for (int64_t s = 0; s < n_sys; ++s) {
+            const int nsw = n_swim ? n_swim[s] : 1;
+            const int t0 = forward_tpl(dtype, N[s], N[s] * nsw, eps_over_ds);
+            if (t0 > 0 && launch_tpl[t0] == tpl) {
+                Ns.push_back(N[s]);
+                nsws.push_back(nsw);
+                rows.insert(rows.end(), hrows.begin() + f * SWIM_NPARAM, hrows.begin() + (f + nsw) * SWIM_NPARAM);
+            }
+            f += nsw;
+        }
+        if (hipMemcpyAsync(sub_rows, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice, st) !=
+            hipSuccess) {
+            rc = fail(SWIM_EHIP, "upload of a bucket's rows failed");
+            break;
+        }
+        float ms_w[4] = {};
         float best = 0.f;
-        int best_w = 16;
-        for (int w : wps_cand) {
+        for (int k = 0; k < 4; ++k) {
+            const int w = wps_cand[k];
             if (forward_lds_bytes(dtype, tpl, w) > 160 * 1024) continue;
             c->tuned_wps[dtype][tpl] = w;
-            float ms = 0.f;
-            rc = timed(&ms);
+            rc = timed_on((int64_t)Ns.size(), Ns.data(), nsws.data(), sub_rows, &ms_w[k]);
             if (rc != SWIM_OK) break;
-            if (best == 0.f || ms < best) {
-                best = ms;
-                best_w = w;
-            }
+            if (best == 0.f || ms_w[k] < best) best = ms_w[k];
         }
+        int best_w = 16;
+        for (int k = 0; k < 4; ++k)
+            if (ms_w[k] > 0.f && ms_w[k] <= WPS_TIE * best) best_w = wps_cand[k];
         c->tuned_wps[dtype][tpl] = best_w;
     }
+    c->forced_launch = false;
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(sub_rows);
     // large systems: the one-sided kernel at 1, 2, 4 targets per lane and,
     // for FP32, the symmetric tile-pair step (the automatic choice, 0)
     int best_big = save_big;

@@ -990,6 +990,13 @@ k_forward(Batch b, Run r, const int32_t* order, int32_t* queue, T* obs, T* speed
     refuse = fwd_window(sizeof(T) == 4 ? 0 : 1, TPL, WPS) &&
              (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) unsigned char*)smem != 0u;
 #endif
+    // Instruction-issue priority of this launch's waves against the other
+    // size buckets' launches that share its CUs: larger systems first.  A
+    // system's run costs ~N^2 per step, so in an uneven batch the largest
+    // runs that do not stop early set the call's length; a SIMD picks the
+    // highest-priority ready wave, and the smaller systems' waves take the
+    // slots those leave idle (barriers, LDS latency).
+    __builtin_amdgcn_s_setprio(TPL >= 6 ? 3 : TPL >= 4 ? 2 : TPL >= 2 ? 1 : 0);
     // Work queue: thread 0 takes the next system; the item reaches every
     // thread through LDS and readfirstlane makes it an SGPR, so the loop exit
     // is a uniform scalar branch.  A workgroup takes at most n_sys items.
