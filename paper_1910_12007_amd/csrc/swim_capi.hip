@@ -433,13 +433,20 @@ int forward_chunk(swim_ctx* c, int32_t dtype, int64_t n_sys, const int32_t* N, c
             max_big = std::max(max_big, pts[s]);
         }
     }
-    // longest-first order inside every bucket
+    // longest-first order inside every bucket; in a merged bucket, the
+    // systems merged in from smaller buckets first (each group longest-
+    // first): in a launch of their own they would have started at once,
+    // and behind the larger group they would start only once all of its
+    // systems are taken (in a generation whose large draws mostly blow up,
+    // the few long runs are then the last to start)
     std::vector<int32_t> order;
     std::vector<std::pair<int, int64_t>> bucket_span;  // (tpl, start)
     for (int t : TPL_CHOICES) {
         auto& v = bucket[t - 1];
         if (v.empty()) continue;
-        std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return pts[a] > pts[b]; });
+        std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) {
+            return tpl_of[a] != tpl_of[b] ? tpl_of[a] < tpl_of[b] : pts[a] > pts[b];
+        });
         bucket_span.push_back({t, (int64_t)order.size()});
         order.insert(order.end(), v.begin(), v.end());
     }
