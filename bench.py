@@ -61,12 +61,12 @@ VALU_OPS_PER_PAIR_BIG = 26.2
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 # HBM bytes of one launch of that kernel on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch: 46328.1 and 2224.0) scaled by
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch: 46324.6 and 2227.1) scaled by
 # the same counters over a 256 MiB device copy (x2.0 and x1.0), for the
 # kernel as it stands (profiles/k_forward_batch_4096x128_counters.md): almost
 # all of it the 4096 kernel tables (22.5 KiB each) read once into LDS; set
 # it to None whenever the kernel changes until the counters are taken again
-TRAFFIC_BYTES = (46328.1 * 2.00 + 2224.0 * 1.00) * 1024
+TRAFFIC_BYTES = (46324.6 * 2.00 + 2227.1 * 1.00) * 1024
 
 
 def load_data():
