@@ -709,6 +709,15 @@ int abc_prescreened(swim_ctx *ctx, const abc_model *model, int32_t N, const floa
 int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int32_t blob, int64_t n, const double *t,
                           double *h1t, double *h2, double *h1c);
 
+/* Launch plan of a swim_forward call (host only, no device work): for each
+ * system, the targets per lane of the persistent-kernel launch it runs in
+ * (1, 2, 3, 4, 6 or 8, after the merging of size buckets that swim_forward
+ * describes), or -1 for the large-system step.  Arguments as swim_forward's
+ * (N, n_swim host; n_swim may be NULL); tpl host int32[n_sys] (written).
+ * SWIM_EINVAL for a bad dtype or sizes outside swim_forward's limits. */
+int swim_forward_plan(int32_t dtype, int64_t n_sys, const int32_t *N, const int32_t *n_swim,
+                      double eps_over_ds, int32_t *tpl);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1602,6 +1602,31 @@ int abc_step(swim_ctx* c, const abc_model* m, const double* data, int32_t n_obs,
     return SWIM_OK;
 }
 
+int swim_forward_plan(int32_t dtype, int64_t n_sys, const int32_t* N, const int32_t* n_swim, double eps_over_ds,
+                      int32_t* tpl)
+{
+    TRY(check_dtype(dtype));
+    if (n_sys < 0 || (n_sys > 0 && (!N || !tpl))) return fail(SWIM_EINVAL, "bad swim_forward_plan arguments");
+    if (!(eps_over_ds > 0)) return fail(SWIM_EINVAL, "eps_over_ds must be > 0");
+    bool present[9] = {}, big = false;
+    for (int64_t s = 0; s < n_sys; ++s) {
+        const int nsw = n_swim ? n_swim[s] : 1;
+        if (N[s] < 3 || N[s] > 4096 || nsw < 1 || (int64_t)N[s] * nsw > 4096)
+            return fail(SWIM_EINVAL, "system %lld: N = %d with %d filaments is outside the limits", (long long)s, N[s], nsw);
+        const int t = forward_tpl(dtype, N[s], N[s] * nsw, eps_over_ds);
+        if (t > 0) present[t] = true;
+        else big = true;
+    }
+    int launch[9];
+    merge_buckets(present, big, 1 + swim_ctx::N_AUX, launch);
+    for (int64_t s = 0; s < n_sys; ++s) {
+        const int nsw = n_swim ? n_swim[s] : 1;
+        const int t = forward_tpl(dtype, N[s], N[s] * nsw, eps_over_ds);
+        tpl[s] = t > 0 ? launch[t] : -1;
+    }
+    return SWIM_OK;
+}
+
 int swim_kernel_eval_host(int32_t dtype, double alpha, double eps, int32_t blob, int64_t n, const double* t,
                           double* h1t, double* h2, double* h1c)
 {

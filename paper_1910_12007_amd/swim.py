@@ -69,6 +69,7 @@ SIGNATURES = {
                             _c.c_int64, _c.c_double, _DP, _DP, _U8P, _DP, _DP, _I32P]),
     "swim_kernel_eval_host": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_double, _c.c_int32, _c.c_int64, _DP, _DP, _DP,
                                          _DP]),
+    "swim_forward_plan": (_c.c_int, [_c.c_int32, _c.c_int64, _I32P, _I32P, _c.c_double, _I32P]),
     "tmcmc_loglik": (_c.c_int, [_P, _c.c_int32, _c.c_int64, _c.c_int32, _P, _P, _P, _P, _P, _P]),
     "tmcmc_run": (_c.c_int, [_P, _P, _P, _DP, _c.c_int32, _c.c_int32, _c.c_int64, _c.c_uint64, _DP, _DP, _DP, _I32P,
                              _DP, _I64P, _I64P, _DP]),
@@ -346,6 +347,18 @@ def tmcmc_run(ctx, model, lo, hi, data, N, n, seed, cv_target=1.0, cov_scale=0.2
     k = int(ns[0])
     return dict(theta=theta, logl=logl, q=q[:k + 1], n_stages=k, log_evidence=float(lev[0]), accepted=acc[:k],
                 runs=int(runs[0]), seconds=float(secs[0]))
+
+
+def swim_forward_plan(dtype, N, n_swim=None, eps_over_ds=1.5):
+    """Targets per lane of the launch each system runs in (-1: the
+    large-system step); host only."""
+    n_, n_p = _h(N, np.int32, _I32P)
+    s_p = None
+    if n_swim is not None:
+        s_, s_p = _h(n_swim, np.int32, _I32P)
+    out = np.empty(n_.size, dtype=np.int32)
+    _check(lib().swim_forward_plan(int(dtype), n_.size, n_p, s_p, float(eps_over_ds), out.ctypes.data_as(_I32P)))
+    return out
 
 
 def swim_kernel_eval_host(dtype, alpha, eps, t, blob=SWIM_BLOB_PAPER):

@@ -139,6 +139,33 @@ def test_host_kernel_rejects_out_of_domain():
         swim.swim_kernel_eval_host(swim.SWIM_F64, -1.0, 0.02, np.array([1.0]))
 
 
+def test_forward_plan_merges_size_buckets():
+    """The launch plan of swim_forward: systems bucketed by points per system
+    (up to 64 * tpl, tpl in 1, 2, 3, 4, 6, 8; above 512 points the
+    large-system step), and with more than four parts (buckets plus the
+    large systems) adjacent buckets merge, the pair with the largest ratio
+    of targets per lane first, the larger pair on a tie."""
+    F32, F64 = swim.SWIM_F32, swim.SWIM_F64
+    # four buckets side by side: no merge
+    assert list(swim.swim_forward_plan(F32, [64, 100, 150, 250])) == [1, 2, 3, 4]
+    # six buckets: 6 into 8 (3/4, tied with 3 and 4, the larger pair), then 3 into 4
+    assert list(swim.swim_forward_plan(F32, [64, 96, 160, 200, 320, 448, 512])) == [1, 2, 4, 4, 8, 8, 8]
+    # the large systems count as a part: four buckets and them, 3 into 4
+    assert list(swim.swim_forward_plan(F32, [64, 96, 160, 200, 600])) == [1, 2, 4, 4, -1]
+    # buckets 1, 2, 4, 6, 8: ratios 1/2, 1/2, 2/3, 3/4, so 6 into 8
+    assert list(swim.swim_forward_plan(F64, [64, 96, 200, 320, 500])) == [1, 2, 4, 8, 8]
+    # a system's points are N times its filaments
+    assert list(swim.swim_forward_plan(F32, [64, 64], [1, 3])) == [1, 3]
+    # FP32 systems whose pairs could leave the kernel table take the large-system step
+    assert swim.swim_forward_plan(F32, [128], eps_over_ds=0.05)[0] == -1
+    assert swim.swim_forward_plan(F64, [128], eps_over_ds=0.05)[0] == 2
+    assert swim.swim_forward_plan(F32, []).size == 0
+    for bad in (dict(dtype=F32, N=[2]), dict(dtype=7, N=[64]), dict(dtype=F32, N=[4097]),
+                dict(dtype=F32, N=[64], n_swim=[65])):
+        with pytest.raises(swim.SwimError):
+            swim.swim_forward_plan(bad["dtype"], bad["N"], bad.get("n_swim"))
+
+
 def test_prior_draw_bit_exact_with_oracle():
     from oracle import abc
     th = swim.abc_prior_draw(20191027, 5000, inputs.PRIOR_LO, inputs.PRIOR_HI)
